@@ -1,0 +1,756 @@
+// FP64 CPU oracle: pseudopotential multiphase lattice Boltzmann step with the multiphase
+// curved wetting boundary of Yao, Liu, Zhong & Wen, "Multiphase curved boundary condition in
+// lattice Boltzmann method" (arXiv 2203.04508).
+//
+// TEST INFRASTRUCTURE ONLY. Tests, the package smoke check and the CPU-baseline leg of the
+// benchmark load this library; the HIP product path never does, and the two share no code.
+//
+// It is written to be read against the paper: doubles, plain loops over nodes and directions,
+// each step of the method in its own function, no blocking and no fusion.
+//
+//   lattice            D2Q9 velocities in the column order of the moment matrix M (Sec. 2.1, eq. 2);
+//                      D3Q19 for the 3-D runs (not in the paper; listed below)
+//   equilibrium        eq. 14 with c_s^2 = 1/3
+//   forcing            exact difference method, eq. 13
+//   collision          eq. 4 with S = I/tau (single relaxation time), streaming eq. 5
+//   nonideal force     pseudopotential with an EOS-based effective mass (the model class named in
+//                      Sec. 1): psi = sqrt(2 (p_EOS - rho c_s^2) / G), F = -G psi(x) sum_i w^_i psi(x+e_i) e_i,
+//                      Carnahan-Starling p_EOS
+//   wall density       eq. 15 restricted to the first solid layer, times a wettability factor phi
+//   curved boundary    eq. 16 (0 <= q < 1/2), eq. 17 (1/2 <= q <= 1)       (Sec. 3.1)
+//   mass modification  eq. 18                                              (Sec. 3.2)
+//
+// Geometry is exact integer arithmetic in units of 2^-16 lattice spacings: node classification,
+// the fluid-solid link list and each link's q = q_fixed / 2^16 (first point of the link segment
+// that lies inside or on a shape).
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+namespace {
+
+constexpr int MAXQ = 19;
+constexpr int64_t ONE = 65536;  // one lattice spacing in fixed point
+
+struct Lat {
+    int dim = 2, Q = 9;
+    int e[MAXQ][3] = {};
+    double w[MAXQ] = {};    // lattice weights of eq. 14
+    double wf[MAXQ] = {};   // interaction-force stencil weights, sum_i wf_i e_i e_i^T = I
+    int opp[MAXQ] = {};
+};
+
+Lat make_lat(int dim) {
+    Lat L;
+    L.dim = dim;
+    if (dim == 2) {
+        // columns of M (eq. 2): rows j_x and j_y give the x and y components of e_i
+        static const int E[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
+                                    {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+        L.Q = 9;
+        for (int i = 0; i < 9; ++i) { L.e[i][0] = E[i][0]; L.e[i][1] = E[i][1]; L.e[i][2] = 0; }
+    } else {
+        // D3Q19: rest, the 6 axis vectors, the 12 edge vectors; opposite pairs sit side by side
+        static const int E[19][3] = {{0, 0, 0},
+            {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+            {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+            {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+            {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+        L.Q = 19;
+        for (int i = 0; i < 19; ++i) for (int k = 0; k < 3; ++k) L.e[i][k] = E[i][k];
+    }
+    for (int i = 0; i < L.Q; ++i) {
+        int n2 = L.e[i][0] * L.e[i][0] + L.e[i][1] * L.e[i][1] + L.e[i][2] * L.e[i][2];
+        if (dim == 2) {
+            L.w[i] = n2 == 0 ? 4.0 / 9.0 : (n2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+            L.wf[i] = n2 == 0 ? 0.0 : (n2 == 1 ? 1.0 / 3.0 : 1.0 / 12.0);
+        } else {
+            L.w[i] = n2 == 0 ? 1.0 / 3.0 : (n2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+            L.wf[i] = n2 == 0 ? 0.0 : (n2 == 1 ? 1.0 / 6.0 : 1.0 / 12.0);
+        }
+        for (int j = 0; j < L.Q; ++j)
+            if (L.e[j][0] == -L.e[i][0] && L.e[j][1] == -L.e[i][1] && L.e[j][2] == -L.e[i][2]) L.opp[i] = j;
+    }
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+typedef struct {
+    int32_t dim, nx, ny, nz;  // nz = 1 for dim 2
+    double tau;               // single relaxation time (S = I/tau in eq. 4)
+    double G;                 // interaction strength of the pseudopotential force (negative)
+    double eos_a, eos_b, eos_R, eos_T;  // Carnahan-Starling parameters and temperature
+} or_params;
+
+}  // extern "C"
+
+namespace {
+
+// ----------------------------------------------------------------------------------------
+// dual numbers with K tangent directions (forward-mode reference derivatives)
+// ----------------------------------------------------------------------------------------
+constexpr int KD = 4;
+struct Dual {
+    double v = 0;
+    double d[KD] = {};
+    Dual() = default;
+    Dual(double x) : v(x) {}
+};
+inline Dual operator+(const Dual& a, const Dual& b) { Dual r(a.v + b.v); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+inline Dual operator-(const Dual& a, const Dual& b) { Dual r(a.v - b.v); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+inline Dual operator-(const Dual& a) { Dual r(-a.v); for (int k = 0; k < KD; ++k) r.d[k] = -a.d[k]; return r; }
+inline Dual operator*(const Dual& a, const Dual& b) { Dual r(a.v * b.v); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+inline Dual operator/(const Dual& a, const Dual& b) { Dual r(a.v / b.v); for (int k = 0; k < KD; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v); return r; }
+inline Dual operator+(const Dual& a, double b) { return a + Dual(b); }
+inline Dual operator+(double a, const Dual& b) { return Dual(a) + b; }
+inline Dual operator-(const Dual& a, double b) { return a - Dual(b); }
+inline Dual operator-(double a, const Dual& b) { return Dual(a) - b; }
+inline Dual operator*(const Dual& a, double b) { Dual r(a.v * b); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] * b; return r; }
+inline Dual operator*(double a, const Dual& b) { return b * a; }
+inline Dual operator/(const Dual& a, double b) { Dual r(a.v / b); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] / b; return r; }
+inline Dual operator/(double a, const Dual& b) { return Dual(a) / b; }
+inline Dual& operator+=(Dual& a, const Dual& b) { a = a + b; return a; }
+inline Dual sqrt(const Dual& a) { double s = std::sqrt(a.v); Dual r(s); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] / (2.0 * s); return r; }
+inline double val(double x) { return x; }
+inline double val(const Dual& x) { return x.v; }
+inline bool finite(double x) { return std::isfinite(x); }
+inline bool finite(const Dual& x) { return std::isfinite(x.v); }
+
+// ----------------------------------------------------------------------------------------
+// thermodynamics: Carnahan-Starling EOS and the pseudopotential
+// ----------------------------------------------------------------------------------------
+template <class R>
+R p_eos(const or_params& P, R rho) {
+    R eta = rho * (P.eos_b / 4.0);
+    R one_m = 1.0 - eta;
+    return rho * (P.eos_R * P.eos_T) * (1.0 + eta + eta * eta - eta * eta * eta) / (one_m * one_m * one_m)
+           - P.eos_a * rho * rho;
+}
+
+// The pressure of the pseudopotential model is rho c_s^2 + G psi^2 / 2 (c = 1); equating it with
+// p_EOS fixes psi.  Returns false when rho <= 0 or the square root argument is negative.
+template <class R>
+bool psi_of(const or_params& P, R rho, R* psi) {
+    if (!(val(rho) > 0.0)) { *psi = R(0.0); return false; }
+    R arg = 2.0 * (p_eos(P, rho) - rho / 3.0) / P.G;
+    if (!(val(arg) >= 0.0)) { *psi = R(0.0); return false; }
+    using std::sqrt;
+    *psi = sqrt(arg);
+    return true;
+}
+
+// eq. 14: second-order equilibrium, c_s^2 = 1/3
+template <class R>
+void equilibrium(const Lat& L, R rho, const R u[3], R out[]) {
+    R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < L.Q; ++i) {
+        R eu = u[0] * double(L.e[i][0]) + u[1] * double(L.e[i][1]) + u[2] * double(L.e[i][2]);
+        out[i] = L.w[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+}
+
+// eq. 13: exact-difference forcing term F_i = f^eq(rho, u + dt F / rho) - f^eq(rho, u), dt = 1
+template <class R>
+void edm_terms(const Lat& L, R rho, const R u[3], const R F[3], R out[]) {
+    R a[MAXQ], b[MAXQ];
+    R us[3];
+    for (int k = 0; k < 3; ++k) us[k] = u[k] + F[k] / rho;
+    equilibrium(L, rho, us, a);
+    equilibrium(L, rho, u, b);
+    for (int i = 0; i < L.Q; ++i) out[i] = a[i] - b[i];
+}
+
+// eqs. 16 and 17 for one link; F_i is the eq. 13 term of direction i at x1 and time t.
+// x2_fluid selects the fallback when the second fluid node behind x1 is solid (q < 1/2 only):
+// the link is then treated by halfway bounce-back, the q = 1/2 case of the same scheme.
+template <class R>
+R curved_bc(double q, bool x2_fluid, R ft_i_x1, R ft_i_x2, R ft_ibar_x1, R F_i) {
+    if (q < 0.5) {
+        if (!x2_fluid) return ft_i_x1;
+        return (2.0 * q) * ft_i_x1 + (1.0 - 2.0 * q) * ft_i_x2 + (1.0 - 2.0 * q) * F_i;
+    }
+    return (1.0 / (2.0 * q)) * ft_i_x1 + ((2.0 * q - 1.0) / (2.0 * q)) * ft_ibar_x1
+           + ((2.0 * q - 1.0) / (2.0 * q)) * F_i;
+}
+
+// ----------------------------------------------------------------------------------------
+// grid helpers
+// ----------------------------------------------------------------------------------------
+struct Grid {
+    int dim, n[3];
+    int64_t N;
+    explicit Grid(const or_params& P) : dim(P.dim) {
+        n[0] = P.nx; n[1] = P.ny; n[2] = dim == 3 ? P.nz : 1;
+        N = int64_t(n[0]) * n[1] * n[2];
+    }
+    int64_t lin(int x, int y, int z) const { return x + int64_t(n[0]) * (y + int64_t(n[1]) * z); }
+    void coords(int64_t id, int c[3]) const {
+        c[0] = int(id % n[0]); c[1] = int((id / n[0]) % n[1]); c[2] = int(id / (int64_t(n[0]) * n[1]));
+    }
+    static int wrap(int a, int m) { a %= m; return a < 0 ? a + m : a; }
+    int64_t shift(int64_t id, const int d[3], int sign) const {
+        int c[3];
+        coords(id, c);
+        for (int k = 0; k < 3; ++k) c[k] = wrap(c[k] + sign * d[k], n[k]);
+        return lin(c[0], c[1], c[2]);
+    }
+};
+
+// ----------------------------------------------------------------------------------------
+// exact geometry in 2^-16 units
+// ----------------------------------------------------------------------------------------
+enum { SHAPE_BALL = 1, SHAPE_BAND_Y = 2 };
+enum { CLS_EQ16 = 0, CLS_HBB = 1, CLS_EQ17 = 2 };
+constexpr uint32_t NOHIT = 0xFFFFFFFFu;
+
+struct Shape {
+    int64_t kind, c[3], r, lo, hi, group;
+};
+
+Shape load_shape(const int64_t* s) {
+    Shape h;
+    h.kind = s[0]; h.c[0] = s[1]; h.c[1] = s[2]; h.c[2] = s[3]; h.r = s[4]; h.lo = s[5]; h.hi = s[6]; h.group = s[7];
+    return h;
+}
+
+// periodic minimum image of d on a ring of length Lf: result in [-Lf/2, Lf/2)
+int64_t min_image(int64_t d, int64_t Lf) {
+    d %= Lf;
+    if (d < 0) d += Lf;
+    if (d >= Lf / 2) d -= Lf;
+    return d;
+}
+
+int64_t pmod(int64_t a, int64_t m) { a %= m; return a < 0 ? a + m : a; }
+
+// strict interior test of the lattice node at integer coordinates c
+bool node_inside(const Grid& g, const Shape& s, const int c[3]) {
+    if (s.kind == SHAPE_BALL) {
+        __int128 acc = 0;
+        for (int k = 0; k < g.dim; ++k) {
+            int64_t d = min_image(int64_t(c[k]) * ONE - s.c[k], int64_t(g.n[k]) * ONE);
+            acc += (__int128)d * d;
+        }
+        return acc < (__int128)s.r * s.r;
+    }
+    int64_t Ly = int64_t(g.n[1]) * ONE;
+    return pmod(int64_t(c[1]) * ONE - s.lo, Ly) < s.hi - s.lo;
+}
+
+// First n in [0, 2^16] for which X1 + n e lies inside or on shape s; NOHIT if none.
+// For a ball the squared distance along the segment is the convex quadratic
+// f(n) = A n^2 + B n + C; its smaller root is estimated in double and then settled by exact
+// integer sign tests.
+uint32_t first_hit(const Grid& g, const Shape& s, const int c1[3], const int e[3]) {
+    if (s.kind == SHAPE_BALL) {
+        int64_t d[3] = {0, 0, 0};
+        for (int k = 0; k < g.dim; ++k) d[k] = min_image(int64_t(c1[k]) * ONE - s.c[k], int64_t(g.n[k]) * ONE);
+        __int128 A = 0, B = 0, C = -(__int128)s.r * s.r;
+        for (int k = 0; k < g.dim; ++k) {
+            A += e[k] * e[k];
+            B += (__int128)2 * d[k] * e[k];
+            C += (__int128)d[k] * d[k];
+        }
+        auto f = [&](int64_t n) { return A * n * n + B * n + C; };
+        if (f(0) <= 0) return 0;
+        if (B >= 0) return NOHIT;  // f increases on n >= 0
+        __int128 disc = B * B - 4 * A * C;
+        if (disc < 0) return NOHIT;
+        double root = (-double(B) - std::sqrt(double(disc))) / (2.0 * double(A));
+        int64_t n = int64_t(std::ceil(root));
+        if (n < 0) n = 0;
+        while (n > 0 && f(n - 1) <= 0) --n;
+        // step forward while still on the decreasing branch and outside
+        while (f(n) > 0 && 2 * A * n + B < 0) ++n;
+        if (f(n) > 0 || n > ONE) return NOHIT;
+        return uint32_t(n);
+    }
+    // periodic band along y: inside-or-on iff (Y - lo) mod Ly <= hi - lo
+    int64_t Ly = int64_t(g.n[1]) * ONE;
+    int64_t H = s.hi - s.lo;
+    int64_t r = pmod(int64_t(c1[1]) * ONE - s.lo, Ly);
+    if (r <= H) return 0;
+    int64_t n;
+    if (e[1] > 0) n = Ly - r;        // reaches the band's lower face (r wraps to 0)
+    else if (e[1] < 0) n = r - H;    // reaches the band's upper face
+    else return NOHIT;
+    return n <= ONE ? uint32_t(n) : NOHIT;
+}
+
+// lattice range of a ball's bounding box, widened by `pad` nodes
+void ball_box(const Shape& s, int k, int pad, int* lo, int* hi) {
+    int64_t a = s.c[k] - s.r, b = s.c[k] + s.r;
+    int64_t fa = a >= 0 ? a / ONE : -((-a + ONE - 1) / ONE);
+    int64_t fb = b >= 0 ? b / ONE : -((-b + ONE - 1) / ONE);
+    *lo = int(fa) - pad;
+    *hi = int(fb) + 1 + pad;
+}
+
+// ----------------------------------------------------------------------------------------
+// the simulation state
+// ----------------------------------------------------------------------------------------
+template <class R>
+struct Sim {
+    or_params P;
+    Lat L;
+    Grid g;
+    std::vector<uint8_t> solid;
+    std::vector<int64_t> link0;     // CSR: links of node x are link0[x] .. link0[x+1]-1
+    std::vector<int32_t> lk_dir;
+    std::vector<uint32_t> lk_q;
+    std::vector<int64_t> wall_of;   // wall index of a first-layer solid node, -1 otherwise
+    std::vector<int64_t> wall_nodes;
+    std::vector<R> phi;             // wettability factor per wall node
+    // state at time t
+    std::vector<R> ft;    // post-collision populations f~_i(x, t), SoA [Q][N]
+    std::vector<R> rho;   // rho(x, t)
+    std::vector<R> u;     // u(x, t) = j / rho, [3][N]
+    std::vector<R> F;     // nonideal force F(x, t), [3][N]
+    // work
+    std::vector<R> fn, psi;
+    R dm_last = R(0.0);
+    int64_t n_domain = 0;
+
+    explicit Sim(const or_params& p) : P(p), L(make_lat(p.dim)), g(p) {}
+
+    bool fluid(int64_t x) const { return solid[x] == 0; }
+
+    int64_t link_of(int64_t x, int dir) const {
+        for (int64_t l = link0[x]; l < link0[x + 1]; ++l) if (lk_dir[l] == dir) return l;
+        return -1;
+    }
+
+    // S1-S6: from pre-collision populations fpre at time t to the post-collision state
+    void collide(const std::vector<R>& fpre) {
+        const int64_t N = g.N;
+        const int Q = L.Q;
+        // S1: density and velocity
+#pragma omp parallel for schedule(static)
+        for (int64_t x = 0; x < N; ++x) {
+            if (!fluid(x)) continue;
+            R r = 0.0, j[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < Q; ++i) {
+                r += fpre[i * N + x];
+                for (int k = 0; k < 3; ++k) j[k] += fpre[i * N + x] * double(L.e[i][k]);
+            }
+            rho[x] = r;
+            for (int k = 0; k < 3; ++k) u[k * N + x] = j[k] / r;
+        }
+        // S2 + S3: pseudopotential on fluid nodes; wall nodes take psi of their virtual density
+        int64_t bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+        for (int64_t x = 0; x < N; ++x) {
+            if (fluid(x)) {
+                if (!psi_of(P, rho[x], &psi[x])) ++bad;
+            } else if (wall_of[x] >= 0) {
+                // eq. 15, first layer: lattice-weighted mean of the fluid neighbours' density
+                R num = 0.0;
+                double den = 0.0;
+                for (int i = 1; i < Q; ++i) {
+                    int64_t y = g.shift(x, L.e[i], +1);
+                    if (fluid(y)) { num += L.w[i] * rho[y]; den += L.w[i]; }
+                }
+                R rho_w = phi[wall_of[x]] * (num / den);
+                if (!psi_of(P, rho_w, &psi[x])) ++bad;
+            } else {
+                psi[x] = 0.0;
+            }
+        }
+        n_domain += bad;
+        // S4 - S6: force, exact-difference forcing term, single-relaxation-time collision
+#pragma omp parallel for schedule(static)
+        for (int64_t x = 0; x < N; ++x) {
+            if (!fluid(x)) continue;
+            R s[3] = {0.0, 0.0, 0.0};
+            for (int i = 1; i < Q; ++i) {
+                int64_t y = g.shift(x, L.e[i], +1);
+                for (int k = 0; k < 3; ++k) s[k] += L.wf[i] * psi[y] * double(L.e[i][k]);
+            }
+            R Fx[3], ux[3];
+            for (int k = 0; k < 3; ++k) { Fx[k] = -P.G * psi[x] * s[k]; F[k * N + x] = Fx[k]; ux[k] = u[k * N + x]; }
+            R feq[MAXQ], Fi[MAXQ];
+            equilibrium(L, rho[x], ux, feq);
+            edm_terms(L, rho[x], ux, Fx, Fi);
+            for (int i = 0; i < Q; ++i) {
+                R f = fpre[i * N + x];
+                ft[i * N + x] = f - (f - feq[i]) / P.tau + Fi[i];
+            }
+        }
+    }
+
+    // eq. 13 term of direction i at node x from the stored moments of time t
+    R force_term(int64_t x, int i) const {
+        const int64_t N = g.N;
+        R ux[3], Fx[3], Fi[MAXQ];
+        for (int k = 0; k < 3; ++k) { ux[k] = u[k * N + x]; Fx[k] = F[k * N + x]; }
+        edm_terms(L, rho[x], ux, Fx, Fi);
+        return Fi[i];
+    }
+
+    // S7-S9: streaming (eq. 5), curved boundary (eqs. 16-17), mass modification (eq. 18)
+    void stream_and_bounce() {
+        const int64_t N = g.N;
+        const int Q = L.Q;
+#pragma omp parallel for schedule(static)
+        for (int64_t x = 0; x < N; ++x) {
+            if (!fluid(x)) continue;
+            for (int i = 0; i < Q; ++i) {
+                int64_t src = g.shift(x, L.e[i], -1);
+                if (fluid(src)) {
+                    fn[i * N + x] = ft[i * N + src];
+                    continue;
+                }
+                // the population arriving along e_i left x along e_j (j = opposite of i) and met the wall
+                int j = L.opp[i];
+                int64_t l = link_of(x, j);
+                double q = double(lk_q[l]) / double(ONE);
+                int64_t x2 = g.shift(x, L.e[j], -1);
+                R ft_j_x2 = fluid(x2) ? ft[j * N + x2] : R(0.0);
+                fn[i * N + x] = curved_bc(q, fluid(x2), ft[j * N + x], ft_j_x2, ft[i * N + x], force_term(x, j));
+            }
+        }
+        // eq. 18: every boundary-fluid node keeps the outflow-inflow difference of its links in f_0
+        R total = 0.0;
+        for (int64_t x = 0; x < N; ++x) {
+            if (!fluid(x) || link0[x] == link0[x + 1]) continue;
+            R dm = 0.0;
+            for (int64_t l = link0[x]; l < link0[x + 1]; ++l) {
+                int j = lk_dir[l];
+                dm += ft[j * N + x] - fn[L.opp[j] * N + x];
+            }
+            fn[x] = fn[x] + dm;
+            total += dm;
+        }
+        dm_last = total;
+    }
+
+    void step() {
+        stream_and_bounce();
+        collide(fn);
+    }
+};
+
+template <class R>
+int build_sim(Sim<R>* S, const uint8_t* solid, const int64_t* lk_node, const int32_t* lk_dir,
+              const uint32_t* lk_q, int64_t nlinks) {
+    const Grid& g = S->g;
+    const Lat& L = S->L;
+    const int64_t N = g.N;
+    S->solid.assign(solid, solid + N);
+    S->link0.assign(N + 1, 0);
+    for (int64_t l = 0; l < nlinks; ++l) {
+        if (lk_node[l] < 0 || lk_node[l] >= N) return -1;
+        if (l > 0 && (lk_node[l] < lk_node[l - 1] || (lk_node[l] == lk_node[l - 1] && lk_dir[l] <= lk_dir[l - 1]))) return -1;
+        if (lk_dir[l] < 1 || lk_dir[l] >= L.Q || lk_q[l] > uint32_t(ONE)) return -1;
+        S->link0[lk_node[l] + 1]++;
+    }
+    for (int64_t x = 0; x < N; ++x) S->link0[x + 1] += S->link0[x];
+    S->lk_dir.assign(lk_dir, lk_dir + nlinks);
+    S->lk_q.assign(lk_q, lk_q + nlinks);
+    // every fluid-solid neighbour pair must be a link, and every link such a pair
+    for (int64_t x = 0; x < N; ++x) {
+        for (int i = 1; i < L.Q; ++i) {
+            bool need = S->fluid(x) && !S->fluid(g.shift(x, L.e[i], +1));
+            bool have = S->link_of(x, i) >= 0;
+            if (need != have) return -1;
+        }
+    }
+    S->wall_of.assign(N, -1);
+    S->wall_nodes.clear();
+    for (int64_t x = 0; x < N; ++x) {
+        if (S->fluid(x)) continue;
+        for (int i = 1; i < L.Q; ++i)
+            if (S->fluid(g.shift(x, L.e[i], +1))) { S->wall_of[x] = int64_t(S->wall_nodes.size()); S->wall_nodes.push_back(x); break; }
+    }
+    S->phi.assign(S->wall_nodes.size(), R(1.0));
+    S->ft.assign(size_t(L.Q) * N, R(0.0));
+    S->fn.assign(size_t(L.Q) * N, R(0.0));
+    S->rho.assign(N, R(0.0));
+    S->psi.assign(N, R(0.0));
+    S->u.assign(3 * N, R(0.0));
+    S->F.assign(3 * N, R(0.0));
+    return 0;
+}
+
+struct Handle {
+    int kind;  // 0 double, 1 dual
+    void* sim;
+};
+
+}  // namespace
+
+// ========================================================================================
+// C entry points (ctypes)
+// ========================================================================================
+extern "C" {
+
+// ---- lattice and pointwise pieces (used by the pins) ----
+int or_lattice(int dim, int32_t* e, double* w, double* wf, int32_t* opp) {
+    Lat L = make_lat(dim);
+    for (int i = 0; i < L.Q; ++i) {
+        for (int k = 0; k < 3; ++k) e[3 * i + k] = L.e[i][k];
+        w[i] = L.w[i]; wf[i] = L.wf[i]; opp[i] = L.opp[i];
+    }
+    return L.Q;
+}
+
+void or_equilibrium(int dim, double rho, const double* u, double* out) {
+    Lat L = make_lat(dim);
+    double uu[3] = {u[0], u[1], dim == 3 ? u[2] : 0.0};
+    equilibrium(L, rho, uu, out);
+}
+
+void or_edm_terms(int dim, double rho, const double* u, const double* F, double* out) {
+    Lat L = make_lat(dim);
+    double uu[3] = {u[0], u[1], dim == 3 ? u[2] : 0.0};
+    double FF[3] = {F[0], F[1], dim == 3 ? F[2] : 0.0};
+    edm_terms(L, rho, uu, FF, out);
+}
+
+double or_p_eos(const or_params* P, double rho) { return p_eos(*P, rho); }
+
+double or_psi(const or_params* P, double rho) {
+    double s;
+    return psi_of(*P, rho, &s) ? s : std::nan("");
+}
+
+double or_curved_bc(double q, int x2_fluid, double ft_i_x1, double ft_i_x2, double ft_ibar_x1, double F_i) {
+    return curved_bc(q, x2_fluid != 0, ft_i_x1, ft_i_x2, ft_ibar_x1, F_i);
+}
+
+// ---- geometry ----
+int or_classify(const or_params* P, const int64_t* shapes, int64_t nshape, uint8_t* solid) {
+    Grid g(*P);
+    std::memset(solid, 0, size_t(g.N));
+    for (int64_t s = 0; s < nshape; ++s) {
+        Shape h = load_shape(shapes + 8 * s);
+        if (h.kind == SHAPE_BALL) {
+            if (h.r <= 0) return -1;
+            for (int k = 0; k < g.dim; ++k) if (2 * h.r >= int64_t(g.n[k]) * ONE) return -1;
+            int lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+            for (int k = 0; k < g.dim; ++k) ball_box(h, k, 0, &lo[k], &hi[k]);
+            for (int z = lo[2]; z < hi[2]; ++z)
+                for (int y = lo[1]; y < hi[1]; ++y)
+                    for (int x = lo[0]; x < hi[0]; ++x) {
+                        int c[3] = {Grid::wrap(x, g.n[0]), Grid::wrap(y, g.n[1]), g.dim == 3 ? Grid::wrap(z, g.n[2]) : 0};
+                        if (node_inside(g, h, c)) solid[g.lin(c[0], c[1], c[2])] = 1;
+                    }
+        } else if (h.kind == SHAPE_BAND_Y) {
+            if (h.hi <= h.lo || h.hi - h.lo >= int64_t(g.n[1]) * ONE) return -1;
+            for (int64_t id = 0; id < g.N; ++id) {
+                int c[3];
+                g.coords(id, c);
+                if (node_inside(g, h, c)) solid[id] = 1;
+            }
+        } else {
+            return -1;
+        }
+    }
+    return 0;
+}
+
+int64_t or_count_links(const or_params* P, const uint8_t* solid) {
+    Grid g(*P);
+    Lat L = make_lat(P->dim);
+    int64_t n = 0;
+    for (int64_t x = 0; x < g.N; ++x) {
+        if (solid[x]) continue;
+        for (int i = 1; i < L.Q; ++i) if (solid[g.shift(x, L.e[i], +1)]) ++n;
+    }
+    return n;
+}
+
+// Links (x1, i) with x1 fluid and x1 + e_i solid, in (node, direction) order, with
+// q_fixed = the first n for which x1 + n e_i / 2^16 is inside or on any shape, and the class
+// used by the step: eq. 16 (q < 1/2, x2 = x1 - e_i fluid), halfway bounce-back (q < 1/2, x2 solid)
+// or eq. 17 (q >= 1/2).
+int or_fill_links(const or_params* P, const int64_t* shapes, int64_t nshape, const uint8_t* solid,
+                  int64_t* node, int32_t* dir, int32_t* cls, uint32_t* qfix, int64_t cap) {
+    Grid g(*P);
+    Lat L = make_lat(P->dim);
+    std::vector<int64_t> first(g.N + 1, 0);
+    int64_t n = 0;
+    for (int64_t x = 0; x < g.N; ++x) {
+        first[x] = n;
+        if (solid[x]) continue;
+        for (int i = 1; i < L.Q; ++i) {
+            if (!solid[g.shift(x, L.e[i], +1)]) continue;
+            if (n >= cap) return -2;
+            node[n] = x; dir[n] = i; qfix[n] = NOHIT;
+            ++n;
+        }
+    }
+    first[g.N] = n;
+    auto visit = [&](const Shape& h, int64_t x) {
+        if (solid[x] || first[x] == first[x + 1]) return;
+        int c[3];
+        g.coords(x, c);
+        for (int64_t l = first[x]; l < first[x + 1]; ++l) {
+            uint32_t hit = first_hit(g, h, c, L.e[dir[l]]);
+            if (hit < qfix[l]) qfix[l] = hit;
+        }
+    };
+    for (int64_t s = 0; s < nshape; ++s) {
+        Shape h = load_shape(shapes + 8 * s);
+        if (h.kind == SHAPE_BALL) {
+            int lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+            for (int k = 0; k < g.dim; ++k) ball_box(h, k, 1, &lo[k], &hi[k]);
+            for (int z = lo[2]; z < hi[2]; ++z)
+                for (int y = lo[1]; y < hi[1]; ++y)
+                    for (int x = lo[0]; x < hi[0]; ++x)
+                        visit(h, g.lin(Grid::wrap(x, g.n[0]), Grid::wrap(y, g.n[1]), g.dim == 3 ? Grid::wrap(z, g.n[2]) : 0));
+        } else {
+            for (int64_t x = 0; x < g.N; ++x) visit(h, x);
+        }
+    }
+    for (int64_t l = 0; l < n; ++l) {
+        if (qfix[l] == NOHIT) return -3;  // the solid neighbour lies in no shape: inconsistent input
+        if (qfix[l] >= uint32_t(ONE / 2)) cls[l] = CLS_EQ17;
+        else cls[l] = solid[g.shift(node[l], L.e[dir[l]], -1)] ? CLS_HBB : CLS_EQ16;
+    }
+    return 0;
+}
+
+int64_t or_wall_nodes(const or_params* P, const uint8_t* solid, int64_t* out, int64_t cap) {
+    Grid g(*P);
+    Lat L = make_lat(P->dim);
+    int64_t n = 0;
+    for (int64_t x = 0; x < g.N; ++x) {
+        if (!solid[x]) continue;
+        for (int i = 1; i < L.Q; ++i)
+            if (!solid[g.shift(x, L.e[i], +1)]) {
+                if (out && n < cap) out[n] = x;
+                ++n;
+                break;
+            }
+    }
+    return n;
+}
+
+// ---- simulation (double) ----
+void* or_sim_create(const or_params* P, const uint8_t* solid, const int64_t* lk_node, const int32_t* lk_dir,
+                    const uint32_t* lk_q, int64_t nlinks) {
+    if (P->dim != 2 && P->dim != 3) return nullptr;
+    if (!(P->tau > 0.5) || !(P->G < 0.0)) return nullptr;
+    auto* S = new Sim<double>(*P);
+    if (build_sim(S, solid, lk_node, lk_dir, lk_q, nlinks) != 0) { delete S; return nullptr; }
+    return S;
+}
+
+void or_sim_destroy(void* h) { delete static_cast<Sim<double>*>(h); }
+
+int64_t or_sim_n_wall(void* h) { return int64_t(static_cast<Sim<double>*>(h)->wall_nodes.size()); }
+
+int or_sim_set_phi(void* h, const double* phi) {
+    auto* S = static_cast<Sim<double>*>(h);
+    for (size_t w = 0; w < S->phi.size(); ++w) {
+        if (!(phi[w] > 0.0)) return -1;
+        S->phi[w] = phi[w];
+    }
+    return 0;
+}
+
+static int finish(Sim<double>* S) {
+    if (S->n_domain) return -4;
+    for (int64_t x = 0; x < S->g.N; ++x)
+        if (S->fluid(x))
+            for (int i = 0; i < S->L.Q; ++i)
+                if (!std::isfinite(S->ft[i * S->g.N + x])) return -5;
+    return 0;
+}
+
+// pre-collision populations f(x, t) (SoA [Q][N]; solid entries ignored) -> post-collision state at t
+int or_sim_set_f(void* h, const double* fpre) {
+    auto* S = static_cast<Sim<double>*>(h);
+    std::vector<double> f(fpre, fpre + size_t(S->L.Q) * S->g.N);
+    S->n_domain = 0;
+    S->collide(f);
+    return finish(S);
+}
+
+// f(x, 0) = f^eq(rho0, u0) (eq. 14), then the first collision
+int or_sim_init_eq(void* h, const double* rho0, const double* u0) {
+    auto* S = static_cast<Sim<double>*>(h);
+    const int64_t N = S->g.N;
+    std::vector<double> f(size_t(S->L.Q) * N, 0.0);
+    for (int64_t x = 0; x < N; ++x) {
+        if (!S->fluid(x)) continue;
+        double uu[3] = {0, 0, 0}, fe[MAXQ];
+        if (u0) for (int k = 0; k < S->g.dim; ++k) uu[k] = u0[k * N + x];
+        equilibrium(S->L, rho0[x], uu, fe);
+        for (int i = 0; i < S->L.Q; ++i) f[i * N + x] = fe[i];
+    }
+    S->n_domain = 0;
+    S->collide(f);
+    return finish(S);
+}
+
+int or_sim_step(void* h, int64_t nsteps, double* dm_hist) {
+    auto* S = static_cast<Sim<double>*>(h);
+    S->n_domain = 0;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        S->step();
+        if (dm_hist) dm_hist[t] = S->dm_last;
+        if (S->n_domain) return -4;
+    }
+    return finish(S);
+}
+
+void or_sim_get_f(void* h, double* f) {
+    auto* S = static_cast<Sim<double>*>(h);
+    std::memcpy(f, S->ft.data(), S->ft.size() * sizeof(double));
+}
+
+// rho(x, t) and the physical velocity v = u + F / (2 rho) (Sec. 2.2, after eq. 14), SoA [dim][N];
+// F (nullable) receives the nonideal force
+void or_sim_moments(void* h, double* rho, double* v, double* F) {
+    auto* S = static_cast<Sim<double>*>(h);
+    const int64_t N = S->g.N;
+    for (int64_t x = 0; x < N; ++x) {
+        bool fl = S->fluid(x);
+        rho[x] = fl ? S->rho[x] : 0.0;
+        for (int k = 0; k < S->g.dim; ++k) {
+            v[k * N + x] = fl ? S->u[k * N + x] + S->F[k * N + x] / (2.0 * S->rho[x]) : 0.0;
+            if (F) F[k * N + x] = fl ? S->F[k * N + x] : 0.0;
+        }
+    }
+}
+
+// total mass: sum over fluid nodes of the stored populations
+double or_sim_mass(void* h) {
+    auto* S = static_cast<Sim<double>*>(h);
+    double m = 0.0;
+    for (int64_t x = 0; x < S->g.N; ++x) {
+        if (!S->fluid(x)) continue;
+        for (int i = 0; i < S->L.Q; ++i) m += S->ft[i * S->g.N + x];
+    }
+    return m;
+}
+
+double or_sim_dm_last(void* h) { return static_cast<Sim<double>*>(h)->dm_last; }
+
+// wall nodes (ascending linear index) and their eq. 15 density rho_ave(s) at time t, before the
+// wettability factor
+int64_t or_sim_wall_rho(void* h, int64_t* nodes, double* rho_ave) {
+    auto* S = static_cast<Sim<double>*>(h);
+    const int64_t nw = int64_t(S->wall_nodes.size());
+    for (int64_t w = 0; w < nw; ++w) {
+        int64_t x = S->wall_nodes[w];
+        double num = 0.0, den = 0.0;
+        for (int i = 1; i < S->L.Q; ++i) {
+            int64_t y = S->g.shift(x, S->L.e[i], +1);
+            if (S->fluid(y)) { num += S->L.w[i] * S->rho[y]; den += S->L.w[i]; }
+        }
+        if (nodes) nodes[w] = x;
+        if (rho_ave) rho_ave[w] = num / den;
+    }
+    return nw;
+}
+
+}  // extern "C"
