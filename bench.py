@@ -1,0 +1,161 @@
+"""Throughput of the multiphase curved-boundary LBM step on one MI355X.
+
+A step is one pass of the whole hot path over the lattice: the fused kernel that pulls the
+populations, applies the curved-boundary links (eqs. 16-18), computes the pseudopotential force and
+collides. Inputs are resident in HBM before the timed region starts. Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline per step; fwd+adjoint MLUPS; relative mass drift"
+HBM_PEAK_GBS = 8000.0
+DTYPES = {"f64": "f64", "f32s": "f32", "f16s": "f32"}
+STORAGE_BYTES = {"f64": 8, "f32s": 4, "f16s": 2}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def setup_gpu(wl, precision, rho_ref):
+    from paper_2203_04508_amd import mcb
+
+    lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision, rho_ref=rho_ref)
+    nl, nb, nw = lat.set_geometry(wl.shapes)
+    from paper_2203_04508_amd import workloads as W
+
+    lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
+    lat.init_equilibrium(wl.rho0())
+    return lat, (nl, nb, nw)
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    from oracle import oracle
+    from paper_2203_04508_amd import workloads as W
+
+    P = oracle.make_params(wl.dim, *wl.dims, tau=wl.tau, T=wl.T)
+    sim, (solid, *_rest) = oracle.sim_from_shapes(P, wl.shapes)
+    sim.set_phi(W.phi_for_walls(wl, oracle.wall_nodes(P, solid)))
+    sim.init_eq(wl.rho0())
+    sim.step(1)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        sim.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or steps >= 1000:
+            break
+    return {
+        "value": wl.N * steps / el / 1e6,
+        "unit": "MLUPS",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{steps} steps of workload {wl.name} ({'x'.join(map(str, wl.dims[:wl.dim]))}) after set-up, FP64",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="f64", choices=list(DTYPES))
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the domain-decomposed "
+              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_04508_amd import workloads as W
+
+    wl = W.make(args.workload)
+    steps = args.steps if args.steps is not None else min(wl.steps, 2000)
+    rho_ref = wl.rho_v if args.precision != "f64" else 0.0
+    log(f"[bench] workload {wl.name} dims {wl.dims[:wl.dim]} precision {args.precision}: set-up")
+    lat, (nl, nb, nw) = setup_gpu(wl, args.precision, rho_ref)
+    M0 = lat.mass().M
+    log(f"[bench] links {nl} boundary nodes {nb} wall nodes {nw}; warmup {args.warmup}")
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"[bench] timed: {steps} steps")
+    lat.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, launches = lat.timing_report()
+    lat.timing(False)
+    rep = lat.mass()
+    drift = (rep.M - M0) / M0
+
+    Q = wl.Q
+    s = STORAGE_BYTES[args.precision]
+    bytes_per_node = 2 * Q * s + 1  # populations read once and written once, plus a one-byte node class
+    fused_ms = ms / max(1, launches)
+    achieved = wl.N * bytes_per_node / (fused_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{wl.name}_{args.precision}.json")
+    if os.path.exists(tfile):
+        traffic = json.load(open(tfile)).get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": wl.N * steps / el / 1e6,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPES[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name}: D2Q9 {wl.dims[0]}x{wl.dims[1]}" if wl.dim == 2 else f"{wl.name}: D3Q19 {wl.dims[0]}^3",
+            "storage": args.precision,
+            "rho_ref": rho_ref,
+            "links": nl, "boundary_nodes": nb, "wall_nodes": nw,
+            "T_over_Tc": wl.T_over_Tc, "tau": wl.tau,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_step2d" if wl.dim == 2 else "k_step3d",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": wl.N * bytes_per_node,
+            "kernel_ms": fused_ms,
+            "kernel_launches": launches,
+        },
+        "mass_drift": drift,
+        "mass_drift_steps": args.warmup + steps,
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

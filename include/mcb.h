@@ -1,0 +1,212 @@
+/*
+ * mcb.h -- C ABI of libmcb: one pseudopotential multiphase lattice Boltzmann time step with the
+ * multiphase curved wetting boundary of Yao, Liu, Zhong & Wen, "Multiphase curved boundary
+ * condition in lattice Boltzmann method" (arXiv 2203.04508), on AMD Instinct MI355X (gfx950).
+ *
+ * The step (Sec. 2-3 of the paper):
+ *   streaming, eq. 5, pull form; incoming populations across fluid-solid links from the curved
+ *   boundary condition, eq. 16 (0 <= q < 1/2) and eq. 17 (1/2 <= q <= 1), each carrying the
+ *   nonideal forcing term F_i(x1, t) of eq. 13; the interpolation-error mass modification of
+ *   eq. 18 added to the rest population of every boundary-fluid node; then density, velocity,
+ *   the EOS-based pseudopotential psi(rho) with first-layer wall densities from eq. 15 times a
+ *   wettability factor phi, the nearest-neighbour interaction force, and single-relaxation-time
+ *   collision (eq. 4 with S = I/tau) with exact-difference forcing (eqs. 13-14).
+ *
+ * Conventions
+ *   - Every function returns an mcb_status: 0 on success, a negative MCB_E* code otherwise.
+ *     Nothing throws across the ABI. mcb_last_error() returns a description of the last error of
+ *     a context (a pointer owned by the context, valid until its next call).
+ *   - Host arrays passed in are owned by the caller and copied before the call returns.
+ *   - Device memory is owned by the caller: mcb_required_sizes() gives the byte sizes of two
+ *     arenas (lattice, links) that the caller allocates (e.g. as torch tensors) and binds with
+ *     mcb_bind_buffers(). The library allocates no device memory. Arenas must stay alive and
+ *     bound while the context uses them; mcb_bind_buffers() may be called again (e.g. once the
+ *     link counts are known).
+ *   - Work is queued on the HIP stream given to mcb_bind_buffers(). mcb_step() and the geometry
+ *     FILL phase are asynchronous; faults detected on the device (non-finite populations, psi
+ *     domain errors) are reported by the next synchronising call: mcb_mass, mcb_moments,
+ *     mcb_get_f, mcb_sync.
+ *   - A context is used by one host thread at a time.
+ *   - Node linear index: x + nx * (y + ny * z). Population arrays on the host are SoA, [Q][N].
+ *   - D2Q9 velocity order is the column order of the moment matrix M (eq. 2):
+ *     (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+ *     D3Q19: rest, (+-1,0,0), (0,+-1,0), (0,0,+-1), then (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0)
+ *     (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1).
+ */
+#ifndef MCB_H
+#define MCB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mcb_status;
+
+enum {
+    MCB_OK = 0,
+    MCB_EINVAL = -1,   /* bad argument */
+    MCB_ESIZE = -2,    /* a buffer or capacity is too small */
+    MCB_EHIP = -3,     /* a HIP runtime call failed */
+    MCB_EDOMAIN = -4,  /* psi undefined: rho <= 0 or negative square-root argument */
+    MCB_ENAN = -5,     /* non-finite population */
+    MCB_ESTATE = -6,   /* call out of order */
+    MCB_ENOTSUP = -7   /* unsupported combination */
+};
+
+/* storage of the populations */
+enum {
+    MCB_F64 = 0,   /* FP64 storage and arithmetic */
+    MCB_F32S = 1,  /* shifted FP32 storage g_i = f_i - w_i rho_ref, FP32 arithmetic */
+    MCB_F16S = 2   /* shifted FP16 storage, FP32 arithmetic */
+};
+
+/* boundary scheme on fluid-solid links */
+enum {
+    MCB_BC_PRESENT = 0  /* eqs. 16-18 of the paper */
+};
+
+/* build_links phases */
+enum { MCB_COUNT = 0, MCB_FILL = 1 };
+
+/* shape kinds (units: 2^-16 lattice spacings) */
+enum { MCB_SHAPE_BALL = 1, MCB_SHAPE_BAND_Y = 2 };
+
+/* link classes */
+enum { MCB_CLS_EQ16 = 0, MCB_CLS_HBB = 1, MCB_CLS_EQ17 = 2 };
+
+typedef struct mcb_ctx mcb_ctx;
+
+typedef struct {
+    int32_t dim;            /* 2 (D2Q9) or 3 (D3Q19) */
+    int32_t nx, ny, nz;     /* periodic box, each in [3, 32768]; nz = 1 for dim 2; N < 2^31 */
+    double tau;             /* relaxation time, > 1/2 */
+    double G;               /* interaction strength of the pseudopotential force, < 0 */
+    double eos_a, eos_b, eos_R, eos_T;  /* Carnahan-Starling EOS parameters and temperature */
+    int32_t precision;      /* MCB_F64, MCB_F32S, MCB_F16S */
+    int32_t bc_mode;        /* MCB_BC_PRESENT */
+    double rho_ref;         /* shift of the stored populations (ignored for MCB_F64) */
+} mcb_params;
+
+/* A solid shape. kind MCB_SHAPE_BALL: centre (cx, cy, cz) and radius; a node is solid when it
+ * lies strictly inside. kind MCB_SHAPE_BAND_Y: the periodic band lo <= y < hi (x, z free).
+ * group is carried for the caller (e.g. a wettability table) and not used by the library. */
+typedef struct {
+    int64_t kind, cx, cy, cz, radius, lo, hi, group;
+} mcb_shape;
+
+/* One fluid-solid link (x1 fluid, x1 + e_dir solid). q = q_fixed / 2^16 is the first point of
+ * the segment x1 -> x1 + e_dir inside or on a shape (Sec. 3.1, Figs. 1-2); cls is
+ * MCB_CLS_EQ16 (q < 1/2, x2 = x1 - e_dir fluid), MCB_CLS_HBB (q < 1/2, x2 solid: halfway
+ * bounce-back) or MCB_CLS_EQ17 (q >= 1/2). Canonical order: node ascending, then dir. */
+typedef struct {
+    int64_t node;
+    int32_t dir, cls;
+    uint32_t q_fixed, pad;
+} mcb_link;
+
+typedef struct {
+    int64_t lattice_bytes;  /* populations (two lattices), node tags, scratch */
+    int64_t links_bytes;    /* boundary-node, link and wall-node tables */
+} mcb_sizes;
+
+typedef struct {
+    void* lattice;          /* device pointer, >= lattice_bytes, 256-byte aligned */
+    int64_t lattice_bytes;
+    void* links;            /* device pointer, >= links_bytes, 256-byte aligned; may be NULL
+                               before the link counts are known */
+    int64_t links_bytes;
+} mcb_buffers;
+
+typedef struct {
+    double M;        /* total mass: sum over fluid nodes of the populations (FP64 reduction) */
+    double J[3];     /* total post-collision momentum */
+    double dM_last;  /* sum of the eq. 18 corrections of the last step (the paper's Delta M) */
+    int64_t n_nan;   /* fluid nodes with a non-finite population */
+    int64_t n_domain;/* psi domain errors since the state was set */
+    int64_t t;       /* steps taken since the state was set */
+} mcb_mass_report;
+
+/* ---- context ---------------------------------------------------------------------------- */
+/* Validates params (MCB_EINVAL otherwise) and creates a context; no device work. */
+mcb_status mcb_create(const mcb_params* params, mcb_ctx** out);
+void mcb_destroy(mcb_ctx* ctx);
+const char* mcb_last_error(const mcb_ctx* ctx);
+
+/* Arena sizes for the given shape count and link/boundary-node/wall-node counts (pass zeros
+ * before the counts are known: links_bytes is then 0). */
+mcb_status mcb_required_sizes(const mcb_params* params, int64_t n_shapes, int64_t n_links,
+                              int64_t n_bnodes, int64_t n_wall, mcb_sizes* out);
+
+/* Binds caller-owned device arenas and the HIP stream (hipStream_t; NULL = default stream).
+ * The lattice arena must be sized for the shape count later passed to mcb_set_geometry. */
+mcb_status mcb_bind_buffers(mcb_ctx* ctx, const mcb_buffers* bufs, void* hip_stream);
+
+/* ---- geometry (the exact integer pass) -------------------------------------------------- */
+/* Copies the shape list to the device. Balls need 2 radius < box length on every axis. */
+mcb_status mcb_set_geometry(mcb_ctx* ctx, const mcb_shape* shapes, int64_t n);
+
+/* MCB_COUNT: classifies nodes on the device and returns the number of links, boundary-fluid
+ * nodes and wall nodes (synchronises). MCB_FILL (after binding a links arena of the size
+ * mcb_required_sizes gives for those counts): fills the link table with q and class, the
+ * boundary-node and wall-node tables, and sets every wall node's phi to 1. */
+mcb_status mcb_build_links(mcb_ctx* ctx, int32_t phase, int64_t* n_links, int64_t* n_bnodes,
+                           int64_t* n_wall);
+
+/* Copies the canonical link list to the host (cap entries available). */
+mcb_status mcb_get_links(mcb_ctx* ctx, mcb_link* host, int64_t cap);
+
+/* Wall nodes (solid nodes with a fluid neighbour), ascending linear index. */
+mcb_status mcb_get_wall_nodes(mcb_ctx* ctx, int64_t* host, int64_t cap);
+
+/* Test override of q: the (node, dir) sequence must equal the built list; q_fixed in [0, 2^16]
+ * is taken from each entry and the class recomputed. */
+mcb_status mcb_set_links(mcb_ctx* ctx, const mcb_link* links, int64_t n);
+
+/* ---- wettability -------------------------------------------------------------------------- */
+/* phi per wall node (ascending linear index), > 0: the virtual wall density is phi times the
+ * eq. 15 first-layer average of the fluid neighbours. */
+mcb_status mcb_set_wettability(mcb_ctx* ctx, const double* phi, int64_t n_wall);
+
+/* ---- state -------------------------------------------------------------------------------- */
+/* f(x, 0) = f^eq(rho, u) (eq. 14) on fluid nodes, then the first collision. rho: N doubles;
+ * u: dim x N doubles or NULL (rest). Values on solid nodes are ignored. Synchronises. */
+mcb_status mcb_init_equilibrium(mcb_ctx* ctx, const double* rho, const double* u);
+
+/* Pre-collision populations f(x, t) (Q x N doubles, solid entries ignored) followed by one
+ * collision: the state becomes the post-collision populations of time t. Synchronises. */
+mcb_status mcb_set_f(mcb_ctx* ctx, const double* f);
+
+/* Post-collision populations f~(x, t) of the current state (Q x N doubles; solid entries 0). */
+mcb_status mcb_get_f(mcb_ctx* ctx, double* f);
+
+/* ---- time stepping -------------------------------------------------------------------------- */
+/* n steps, asynchronous on the bound stream. */
+mcb_status mcb_step(mcb_ctx* ctx, int64_t n);
+
+/* ---- observables ---------------------------------------------------------------------------- */
+/* rho (N doubles) and the physical velocity v = u + F / (2 rho) (dim x N doubles; Sec. 2.2,
+ * after eq. 14) of the current state. Either pointer may be NULL. Solid entries 0. */
+mcb_status mcb_moments(mcb_ctx* ctx, double* rho, double* v);
+
+/* FP64 mass / momentum / Delta M report (deterministic two-pass reduction). */
+mcb_status mcb_mass(mcb_ctx* ctx, mcb_mass_report* out);
+
+/* Waits for the stream and reports device-detected faults. */
+mcb_status mcb_sync(mcb_ctx* ctx);
+
+/* ---- measurement ------------------------------------------------------------------------ */
+/* enable != 0 starts timing of mcb_step with HIP events recorded on the bound stream around every
+ * launch of the fused step kernel (totals reset); 0 stops it. */
+mcb_status mcb_timing(mcb_ctx* ctx, int32_t enable);
+
+/* Total milliseconds of the fused step kernel and the number of timed launches since timing was
+ * enabled (synchronises). */
+mcb_status mcb_timing_report(mcb_ctx* ctx, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCB_H */

@@ -29,6 +29,9 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -490,6 +493,14 @@ struct Handle {
 // ========================================================================================
 extern "C" {
 
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 // ---- lattice and pointwise pieces (used by the pins) ----
 int or_lattice(int dim, int32_t* e, double* w, double* wf, int32_t* opp) {
     Lat L = make_lat(dim);
@@ -722,15 +733,22 @@ void or_sim_moments(void* h, double* rho, double* v, double* F) {
     }
 }
 
-// total mass: sum over fluid nodes of the stored populations
+// total mass: sum over fluid nodes of the stored populations, with Neumaier's compensated
+// summation so that the sum itself is exact to a few ulps at any lattice size
 double or_sim_mass(void* h) {
     auto* S = static_cast<Sim<double>*>(h);
-    double m = 0.0;
+    double sum = 0.0, comp = 0.0;
     for (int64_t x = 0; x < S->g.N; ++x) {
         if (!S->fluid(x)) continue;
-        for (int i = 0; i < S->L.Q; ++i) m += S->ft[i * S->g.N + x];
+        for (int i = 0; i < S->L.Q; ++i) {
+            const double v = S->ft[i * S->g.N + x];
+            const double t = sum + v;
+            if (std::fabs(sum) >= std::fabs(v)) comp += (sum - t) + v;
+            else comp += (v - t) + sum;
+            sum = t;
+        }
     }
-    return m;
+    return sum + comp;
 }
 
 double or_sim_dm_last(void* h) { return static_cast<Sim<double>*>(h)->dm_last; }

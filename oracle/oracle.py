@@ -58,6 +58,7 @@ def lib():
         L = C.CDLL(LIB)
         P = C.POINTER(Params)
         vp = C.c_void_p
+        L.or_num_threads.restype = C.c_int
         L.or_lattice.argtypes = [C.c_int, vp, vp, vp, vp]
         L.or_lattice.restype = C.c_int
         L.or_equilibrium.argtypes = [C.c_int, C.c_double, vp, vp]
@@ -103,6 +104,10 @@ def lib():
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
 
 
 # ---------------------------------------------------------------------------- pointwise pieces

@@ -1,0 +1,532 @@
+// Host side of the C ABI declared in include/mcb.h: argument checks, arena layout, call order,
+// stream handling and error reporting.  Device work lives in geometry.hip, step2d.hip,
+// step3d.hip and monitor.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "mcb_internal.h"
+
+namespace mcb {
+
+int64_t storage_bytes(int precision) { return precision == MCB_F64 ? 8 : (precision == MCB_F32S ? 4 : 2); }
+int64_t compute_bytes(int precision) { return precision == MCB_F64 ? 8 : 4; }
+
+static int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64_t n_bnodes, int64_t n_wall) {
+    Layout L{};
+    const int Q = p.dim == 2 ? 9 : 19;
+    const int64_t N = int64_t(p.nx) * p.ny * (p.dim == 3 ? p.nz : 1);
+    const int64_t s = storage_bytes(p.precision), cb = compute_bytes(p.precision);
+    const int64_t nblk = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { const int64_t at = o; o = align256(o + bytes); return at; };
+    L.fa = take(Q * N * s);
+    L.fb = take(Q * N * s);
+    L.tag = take(4 * N);
+    L.solid = take(N);
+    L.scratch = take(8 * N * (2 + p.dim));
+    L.blocksums = take(8 * (3 * nblk + 3));
+    L.flags = take(4 * FLAG_COUNT);
+    L.partials = take(8 * MON_BLOCKS * MON_FIELDS);
+    L.result = take(8 * MON_FIELDS);
+    L.shapes = take(int64_t(sizeof(mcb_shape)) * (n_shapes > 0 ? n_shapes : 1));  // last: only it depends on n_shapes
+    L.lattice_bytes = o;
+    o = 0;
+    const int64_t nb = n_bnodes > 0 ? n_bnodes : 0, nl = n_links > 0 ? n_links : 0, nw = n_wall > 0 ? n_wall : 0;
+    L.bn_node = take(4 * nb);
+    L.bn_mask = take(4 * nb);
+    L.bn_link0 = take(4 * nb);
+    L.dm = take(8 * nb);
+    L.lk_qc = take(4 * nl);
+    L.lk_F = take(cb * nl);
+    L.wl_node = take(4 * nw);
+    L.wl_phi = take(8 * nw);
+    L.links_bytes = (nb + nl + nw) > 0 ? o : 0;
+    return L;
+}
+
+hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
+
+}  // namespace mcb
+
+using namespace mcb;
+
+namespace {
+
+mcb_status fail(mcb_ctx* c, mcb_status code, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return fail(c, MCB_EHIP, "%s: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+bool params_ok(const mcb_params* p, const char** why) {
+    if (!p) { *why = "null params"; return false; }
+    if (p->dim != 2 && p->dim != 3) { *why = "dim must be 2 or 3"; return false; }
+    const int nz = p->dim == 3 ? p->nz : 1;
+    if (p->nx < 3 || p->ny < 3 || p->nx > 32768 || p->ny > 32768 || (p->dim == 3 && (nz < 3 || nz > 32768))) {
+        *why = "box sizes must lie in [3, 32768]";
+        return false;
+    }
+    if (p->dim == 2 && p->nz != 1) { *why = "nz must be 1 in 2-D"; return false; }
+    if (int64_t(p->nx) * p->ny * nz >= (int64_t(1) << 31)) { *why = "N must be < 2^31"; return false; }
+    const int64_t sbytes = p->precision == MCB_F64 ? 8 : (p->precision == MCB_F32S ? 4 : 2);
+    if (int64_t(p->nx) * p->ny * nz * (p->dim == 2 ? 9 : 19) * sbytes > int64_t(0xFFFFFE00u)) {
+        *why = "one population lattice must stay below 4 GiB (32-bit buffer offsets)";
+        return false;
+    }
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) { *why = "tau must exceed 1/2"; return false; }
+    if (!(p->G < 0.0) || !std::isfinite(p->G)) { *why = "G must be negative"; return false; }
+    if (!std::isfinite(p->eos_a) || !std::isfinite(p->eos_b) || !std::isfinite(p->eos_R) || !std::isfinite(p->eos_T) ||
+        p->eos_b <= 0 || p->eos_R <= 0 || p->eos_T <= 0) {
+        *why = "bad EOS parameters";
+        return false;
+    }
+    if (p->precision < MCB_F64 || p->precision > MCB_F16S) { *why = "unknown precision"; return false; }
+    if (p->bc_mode != MCB_BC_PRESENT) { *why = "unknown bc_mode"; return false; }
+    if (p->precision != MCB_F64 && !(std::isfinite(p->rho_ref) && p->rho_ref >= 0.0)) { *why = "bad rho_ref"; return false; }
+    return true;
+}
+
+void* fcur(mcb_ctx* c) { return c->lat + (c->swapped ? c->L.fb : c->L.fa); }
+void* fnext(mcb_ctx* c) { return c->lat + (c->swapped ? c->L.fa : c->L.fb); }
+
+mcb_status check_flags(mcb_ctx* c, int64_t* n_domain_out) {
+    int32_t flags[FLAG_COUNT];
+    HIPCHK(hipMemcpyAsync(flags, c->lat + c->L.flags, sizeof flags, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (n_domain_out) *n_domain_out = flags[FLAG_DOMAIN] ? 1 : 0;
+    if (flags[FLAG_NOHIT]) return fail(c, MCB_EINVAL, "a link's solid neighbour lies in no shape");
+    if (flags[FLAG_DOMAIN]) return fail(c, MCB_EDOMAIN, "psi domain error: rho <= 0 or negative square-root argument");
+    return MCB_OK;
+}
+
+mcb_status clear_flags(mcb_ctx* c) {
+    HIPCHK(hipMemsetAsync(c->lat + c->L.flags, 0, 4 * FLAG_COUNT, c->stream));
+    return MCB_OK;
+}
+
+// host copy of the link tables, expanded to the canonical list
+mcb_status expand_links(mcb_ctx* c, std::vector<mcb_link>& out) {
+    const int64_t nb = c->n_bnodes, nl = c->n_links;
+    std::vector<int32_t> node(nb), link0(nb);
+    std::vector<uint32_t> mask(nb), qc(nl);
+    if (nb > 0) {
+        HIPCHK(hipMemcpyAsync(node.data(), c->lk + c->L.bn_node, 4 * nb, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(mask.data(), c->lk + c->L.bn_mask, 4 * nb, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(link0.data(), c->lk + c->L.bn_link0, 4 * nb, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (nl > 0) HIPCHK(hipMemcpyAsync(qc.data(), c->lk + c->L.lk_qc, 4 * nl, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    out.assign(nl, mcb_link{});
+    for (int64_t b = 0; b < nb; ++b) {
+        int64_t l = link0[b];
+        for (int j = 1; j < c->g.Q; ++j) {
+            if (!((mask[b] >> j) & 1u)) continue;
+            if (l >= nl) return fail(c, MCB_EINVAL, "corrupt link table");
+            out[l].node = node[b];
+            out[l].dir = j;
+            out[l].cls = int32_t(qc[l] >> CLS_SHIFT);
+            out[l].q_fixed = qc[l] & QMASK;
+            out[l].pad = 0;
+            ++l;
+        }
+    }
+    return MCB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcb_status mcb_create(const mcb_params* params, mcb_ctx** out) {
+    if (!out) return MCB_EINVAL;
+    *out = nullptr;
+    const char* why = nullptr;
+    if (!params_ok(params, &why)) return MCB_EINVAL;
+    auto* c = new (std::nothrow) mcb_ctx();
+    if (!c) return MCB_EINVAL;
+    c->p = *params;
+    if (c->p.dim == 2) c->p.nz = 1;
+    c->g.dim = c->p.dim;
+    c->g.nx = c->p.nx;
+    c->g.ny = c->p.ny;
+    c->g.nz = c->p.nz;
+    c->g.Q = c->p.dim == 2 ? 9 : 19;
+    c->g.N = int64_t(c->p.nx) * c->p.ny * c->p.nz;
+    c->L = make_layout(c->p, 0, 0, 0, 0);
+    *out = c;
+    return MCB_OK;
+}
+
+void mcb_destroy(mcb_ctx* c) {
+    if (!c) return;
+    if (c->ev_made)
+        for (int r = 0; r < mcb_ctx::RING; ++r)
+            for (int k = 0; k < 2; ++k) (void)hipEventDestroy(c->ev[r][k]);
+    delete c;
+}
+
+const char* mcb_last_error(const mcb_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+mcb_status mcb_required_sizes(const mcb_params* params, int64_t n_shapes, int64_t n_links, int64_t n_bnodes, int64_t n_wall,
+                              mcb_sizes* out) {
+    const char* why = nullptr;
+    if (!out || !params_ok(params, &why)) return MCB_EINVAL;
+    if (n_shapes < 0 || n_links < 0 || n_bnodes < 0 || n_wall < 0) return MCB_EINVAL;
+    mcb_params p = *params;
+    if (p.dim == 2) p.nz = 1;
+    const Layout L = make_layout(p, n_shapes, n_links, n_bnodes, n_wall);
+    out->lattice_bytes = L.lattice_bytes;
+    out->links_bytes = L.links_bytes;
+    return MCB_OK;
+}
+
+mcb_status mcb_bind_buffers(mcb_ctx* c, const mcb_buffers* b, void* stream) {
+    if (!c) return MCB_EINVAL;
+    if (!b || !b->lattice) return fail(c, MCB_EINVAL, "lattice arena missing");
+    if ((reinterpret_cast<uintptr_t>(b->lattice) & 255) || (b->links && (reinterpret_cast<uintptr_t>(b->links) & 255)))
+        return fail(c, MCB_EINVAL, "arenas must be 256-byte aligned");
+    const Layout L0 = make_layout(c->p, 0, 0, 0, 0);
+    if (b->lattice_bytes < L0.lattice_bytes)
+        return fail(c, MCB_ESIZE, "lattice arena %lld < %lld bytes", (long long)b->lattice_bytes, (long long)L0.lattice_bytes);
+    if (c->lat && c->lat != b->lattice && c->stage >= 2)
+        return fail(c, MCB_ESTATE, "the lattice arena cannot move once geometry is set");
+    c->lat = static_cast<char*>(b->lattice);
+    c->lat_bytes = b->lattice_bytes;
+    if (b->links) {
+        if (c->lk && c->lk != b->links && c->stage >= 4)
+            return fail(c, MCB_ESTATE, "the links arena cannot move once links are built");
+        c->lk = static_cast<char*>(b->links);
+        c->lk_bytes = b->links_bytes;
+    }
+    c->stream = static_cast<hipStream_t>(stream);
+    if (c->stage < 1) c->stage = 1;
+    // lattice offsets do not depend on the counts; refresh the link offsets if counts are known
+    c->L = make_layout(c->p, c->n_shapes, c->n_links > 0 ? c->n_links : 0, c->n_bnodes > 0 ? c->n_bnodes : 0,
+                       c->n_wall > 0 ? c->n_wall : 0);
+    return MCB_OK;
+}
+
+mcb_status mcb_set_geometry(mcb_ctx* c, const mcb_shape* shapes, int64_t n) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 1) return fail(c, MCB_ESTATE, "bind buffers first");
+    if (n < 0 || (n > 0 && !shapes)) return fail(c, MCB_EINVAL, "bad shape list");
+    const int64_t len[3] = {int64_t(c->p.nx) * ONE, int64_t(c->p.ny) * ONE, int64_t(c->p.nz) * ONE};
+    int nb = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        const mcb_shape& h = shapes[s];
+        if (h.kind == MCB_SHAPE_BALL) {
+            if (h.radius <= 0) return fail(c, MCB_EINVAL, "shape %lld: radius must be positive", (long long)s);
+            for (int k = 0; k < c->p.dim; ++k)
+                if (2 * h.radius >= len[k]) return fail(c, MCB_EINVAL, "shape %lld: diameter exceeds the box", (long long)s);
+            const int64_t cc[3] = {h.cx, h.cy, h.cz};
+            for (int k = 0; k < 3; ++k)
+                if (cc[k] < -(int64_t(1) << 40) || cc[k] > (int64_t(1) << 40))
+                    return fail(c, MCB_EINVAL, "shape %lld: centre out of range", (long long)s);
+        } else if (h.kind == MCB_SHAPE_BAND_Y) {
+            if (h.hi <= h.lo || h.hi - h.lo >= len[1]) return fail(c, MCB_EINVAL, "shape %lld: bad band", (long long)s);
+            if (nb >= MAX_BANDS) return fail(c, MCB_ENOTSUP, "at most %d bands", MAX_BANDS);
+            c->bands[nb++] = h;
+        } else {
+            return fail(c, MCB_EINVAL, "shape %lld: unknown kind", (long long)s);
+        }
+    }
+    const Layout L = make_layout(c->p, n, 0, 0, 0);
+    if (c->lat_bytes < L.lattice_bytes)
+        return fail(c, MCB_ESIZE, "lattice arena too small for %lld shapes", (long long)n);
+    c->n_bands = nb;
+    c->n_shapes = n;
+    c->L = L;
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(c->lat + c->L.shapes, shapes, sizeof(mcb_shape) * n, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    c->n_links = c->n_bnodes = c->n_wall = -1;
+    c->stage = 2;
+    return MCB_OK;
+}
+
+mcb_status mcb_build_links(mcb_ctx* c, int32_t phase, int64_t* n_links, int64_t* n_bnodes, int64_t* n_wall) {
+    if (!c) return MCB_EINVAL;
+    if (phase == MCB_COUNT) {
+        if (c->stage < 2) return fail(c, MCB_ESTATE, "set geometry first");
+        mcb_status st = clear_flags(c);
+        if (st) return st;
+        HIPCHK(geom_classify(c));
+        HIPCHK(geom_count(c));
+        const int64_t nblk = (c->g.N + SCAN_BLOCK - 1) / SCAN_BLOCK;
+        int64_t tot[3];
+        HIPCHK(hipMemcpyAsync(tot, c->lat + c->L.blocksums + 8 * 3 * nblk, sizeof tot, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (tot[0] >= (int64_t(1) << 31)) return fail(c, MCB_ENOTSUP, "too many links");
+        if (c->g.dim == 2 && tot[1] >= (int64_t(1) << 23)) return fail(c, MCB_ENOTSUP, "2-D tags hold at most 2^23 boundary nodes");
+        c->n_links = tot[0];
+        c->n_bnodes = tot[1];
+        c->n_wall = tot[2];
+        c->stage = 3;
+    } else if (phase == MCB_FILL) {
+        if (c->stage < 3) return fail(c, MCB_ESTATE, "run the COUNT phase first");
+        const Layout L = make_layout(c->p, c->n_shapes, c->n_links, c->n_bnodes, c->n_wall);
+        if (L.links_bytes > 0 && (!c->lk || c->lk_bytes < L.links_bytes))
+            return fail(c, MCB_ESIZE, "links arena too small: need %lld bytes", (long long)L.links_bytes);
+        c->L = L;
+        mcb_status st = clear_flags(c);
+        if (st) return st;
+        HIPCHK(geom_fill(c));
+        st = check_flags(c, nullptr);
+        if (st) return st;
+        c->stage = 4;
+        c->swapped = false;
+    } else {
+        return fail(c, MCB_EINVAL, "unknown phase");
+    }
+    if (n_links) *n_links = c->n_links;
+    if (n_bnodes) *n_bnodes = c->n_bnodes;
+    if (n_wall) *n_wall = c->n_wall;
+    return MCB_OK;
+}
+
+mcb_status mcb_get_links(mcb_ctx* c, mcb_link* host, int64_t cap) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
+    if (cap < c->n_links || (c->n_links > 0 && !host)) return fail(c, MCB_ESIZE, "capacity %lld < %lld links", (long long)cap, (long long)c->n_links);
+    std::vector<mcb_link> v;
+    mcb_status st = expand_links(c, v);
+    if (st) return st;
+    if (!v.empty()) std::memcpy(host, v.data(), v.size() * sizeof(mcb_link));
+    return MCB_OK;
+}
+
+mcb_status mcb_get_wall_nodes(mcb_ctx* c, int64_t* host, int64_t cap) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
+    if (cap < c->n_wall || (c->n_wall > 0 && !host)) return fail(c, MCB_ESIZE, "capacity too small");
+    std::vector<int32_t> w(c->n_wall);
+    if (c->n_wall > 0) {
+        HIPCHK(hipMemcpyAsync(w.data(), c->lk + c->L.wl_node, 4 * c->n_wall, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    for (int64_t i = 0; i < c->n_wall; ++i) host[i] = w[i];
+    return MCB_OK;
+}
+
+mcb_status mcb_set_links(mcb_ctx* c, const mcb_link* links, int64_t n) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
+    if (n != c->n_links || (n > 0 && !links)) return fail(c, MCB_EINVAL, "link count differs from the built list");
+    std::vector<mcb_link> cur;
+    mcb_status st = expand_links(c, cur);
+    if (st) return st;
+    std::vector<uint32_t> qc(n);
+    for (int64_t l = 0; l < n; ++l) {
+        if (links[l].node != cur[l].node || links[l].dir != cur[l].dir)
+            return fail(c, MCB_EINVAL, "link %lld: (node, dir) differs from the built list", (long long)l);
+        if (links[l].q_fixed > uint32_t(ONE)) return fail(c, MCB_EINVAL, "link %lld: q_fixed > 2^16", (long long)l);
+        qc[l] = links[l].q_fixed;
+    }
+    if (n > 0) HIPCHK(hipMemcpyAsync(c->lk + c->L.lk_qc, qc.data(), 4 * n, hipMemcpyHostToDevice, c->stream));
+    st = clear_flags(c);
+    if (st) return st;
+    HIPCHK(geom_reclass(c));
+    return check_flags(c, nullptr);
+}
+
+mcb_status mcb_set_wettability(mcb_ctx* c, const double* phi, int64_t n_wall) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
+    if (n_wall != c->n_wall || (n_wall > 0 && !phi)) return fail(c, MCB_EINVAL, "phi needs %lld entries", (long long)c->n_wall);
+    for (int64_t w = 0; w < n_wall; ++w)
+        if (!(phi[w] > 0.0) || !std::isfinite(phi[w])) return fail(c, MCB_EINVAL, "phi[%lld] must be positive", (long long)w);
+    if (n_wall > 0) {
+        HIPCHK(hipMemcpyAsync(c->lk + c->L.wl_phi, phi, 8 * n_wall, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return MCB_OK;
+}
+
+static mcb_status collide_from(mcb_ctx* c, void* fpre) {
+    // fpre holds pre-collision populations in storage format; the collision writes the other lattice
+    void* dst = (fpre == c->lat + c->L.fb) ? c->lat + c->L.fa : c->lat + c->L.fb;
+    HIPCHK(step_fused(c, fpre, dst, false));
+    c->swapped = dst == c->lat + c->L.fb;
+    c->t = 0;
+    c->stage = 5;
+    return check_flags(c, nullptr);
+}
+
+mcb_status mcb_init_equilibrium(mcb_ctx* c, const double* rho, const double* u) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
+    if (!rho) return fail(c, MCB_EINVAL, "rho missing");
+    double* srho = reinterpret_cast<double*>(c->lat + c->L.scratch);
+    double* su = srho + 2 * c->g.N;
+    mcb_status st = clear_flags(c);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(srho, rho, 8 * c->g.N, hipMemcpyHostToDevice, c->stream));
+    if (u) HIPCHK(hipMemcpyAsync(su, u, 8 * c->g.N * c->g.dim, hipMemcpyHostToDevice, c->stream));
+    void* tmp = c->lat + c->L.fb;
+    HIPCHK(init_feq(c, srho, u ? su : nullptr, tmp));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return collide_from(c, tmp);
+}
+
+mcb_status mcb_set_f(mcb_ctx* c, const double* f) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
+    if (!f) return fail(c, MCB_EINVAL, "f missing");
+    double* stage_buf = reinterpret_cast<double*>(c->lat + c->L.scratch);
+    mcb_status st = clear_flags(c);
+    if (st) return st;
+    char* tmp = c->lat + c->L.fb;
+    const int64_t s = storage_bytes(c->p.precision);
+    for (int i = 0; i < c->g.Q; ++i) {
+        HIPCHK(hipMemcpyAsync(stage_buf, f + i * c->g.N, 8 * c->g.N, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(convert_plane_in(c, stage_buf, tmp + i * c->g.N * s, i));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return collide_from(c, tmp);
+}
+
+mcb_status mcb_get_f(mcb_ctx* c, double* f) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
+    if (!f) return fail(c, MCB_EINVAL, "f missing");
+    double* stage_buf = reinterpret_cast<double*>(c->lat + c->L.scratch);
+    const char* cur = static_cast<const char*>(fcur(c));
+    const int64_t s = storage_bytes(c->p.precision);
+    for (int i = 0; i < c->g.Q; ++i) {
+        HIPCHK(convert_plane_out(c, cur + i * c->g.N * s, stage_buf, i));
+        HIPCHK(hipMemcpyAsync(f + i * c->g.N, stage_buf, 8 * c->g.N, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return check_flags(c, nullptr);
+}
+
+static mcb_status drain_slot(mcb_ctx* c, int r) {
+    if (!c->ev_pending[r]) return MCB_OK;
+    HIPCHK(hipEventSynchronize(c->ev[r][1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[r][0], c->ev[r][1]));
+    c->ms_tot += ms;
+    c->launches += 1;
+    c->ev_pending[r] = false;
+    return MCB_OK;
+}
+
+mcb_status mcb_step(mcb_ctx* c, int64_t n) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
+    if (n < 0) return fail(c, MCB_EINVAL, "negative step count");
+    for (int64_t k = 0; k < n; ++k) {
+        if (c->timing) {
+            const int r = c->ev_next;
+            c->ev_next = (r + 1) % mcb_ctx::RING;
+            mcb_status st = drain_slot(c, r);
+            if (st) return st;
+            HIPCHK(hipEventRecord(c->ev[r][0], c->stream));
+            HIPCHK(step_fused(c, fcur(c), fnext(c), true));
+            HIPCHK(hipEventRecord(c->ev[r][1], c->stream));
+            c->ev_pending[r] = true;
+        } else {
+            HIPCHK(step_fused(c, fcur(c), fnext(c), true));
+        }
+        c->swapped = !c->swapped;
+        ++c->t;
+    }
+    return MCB_OK;
+}
+
+mcb_status mcb_timing(mcb_ctx* c, int32_t enable) {
+    if (!c) return MCB_EINVAL;
+    if (enable) {
+        if (!c->ev_made) {
+            for (int r = 0; r < mcb_ctx::RING; ++r)
+                for (int k = 0; k < 2; ++k) HIPCHK(hipEventCreate(&c->ev[r][k]));
+            c->ev_made = true;
+        }
+        for (int r = 0; r < mcb_ctx::RING; ++r) c->ev_pending[r] = false;
+        c->ev_next = 0;
+        c->ms_tot = 0.0;
+        c->launches = 0;
+    }
+    c->timing = enable != 0;
+    return MCB_OK;
+}
+
+mcb_status mcb_timing_report(mcb_ctx* c, double* ms, int64_t* launches) {
+    if (!c) return MCB_EINVAL;
+    if (c->ev_made)
+        for (int r = 0; r < mcb_ctx::RING; ++r) {
+            mcb_status st = drain_slot(c, r);
+            if (st) return st;
+        }
+    if (ms) *ms = c->ms_tot;
+    if (launches) *launches = c->launches;
+    return MCB_OK;
+}
+
+mcb_status mcb_moments(mcb_ctx* c, double* rho, double* v) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
+    HIPCHK(moments_out(c, fcur(c), rho, v));
+    return check_flags(c, nullptr);
+}
+
+mcb_status mcb_mass(mcb_ctx* c, mcb_mass_report* out) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
+    if (!out) return fail(c, MCB_EINVAL, "report missing");
+    HIPCHK(monitor(c, fcur(c)));
+    double r[MON_FIELDS];
+    HIPCHK(hipMemcpyAsync(r, c->lat + c->L.result, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::memset(out, 0, sizeof *out);
+    out->M = r[0];
+    out->J[0] = r[1];
+    out->J[1] = r[2];
+    out->J[2] = r[3];
+    out->dM_last = c->t > 0 ? r[4] : 0.0;
+    out->n_nan = int64_t(r[5]);
+    out->t = c->t;
+    int64_t nd = 0;
+    mcb_status st = check_flags(c, &nd);
+    out->n_domain = nd;
+    if (st) return st;
+    if (out->n_nan > 0) return fail(c, MCB_ENAN, "%lld fluid nodes hold non-finite populations", (long long)out->n_nan);
+    return MCB_OK;
+}
+
+mcb_status mcb_sync(mcb_ctx* c) {
+    if (!c) return MCB_EINVAL;
+    if (!c->stream && !c->lat) return MCB_OK;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->stage < 1) return MCB_OK;
+    return check_flags(c, nullptr);
+}
+
+}  // extern "C"
+
+namespace mcb {
+hipError_t step2d(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
+hipError_t step3d(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
+
+hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
+    return c->g.dim == 2 ? step2d(c, fcur, fnext, pull) : step3d(c, fcur, fnext, pull);
+}
+}  // namespace mcb

@@ -1,0 +1,120 @@
+// Device helpers shared by the step, boundary and monitor kernels.
+#pragma once
+
+#include "mcb_internal.h"
+
+namespace mcb {
+
+// ---------------------------------------------------------------- storage conversions
+// 64-bit and 32-bit element indices (the 32-bit forms let the compiler address from a scalar base)
+template <class S, class C>
+__device__ inline C ld(const S* __restrict__ p, int64_t i);
+template <>
+__device__ inline double ld<double, double>(const double* __restrict__ p, int64_t i) { return p[i]; }
+template <>
+__device__ inline float ld<float, float>(const float* __restrict__ p, int64_t i) { return p[i]; }
+template <>
+__device__ inline float ld<__half, float>(const __half* __restrict__ p, int64_t i) { return __half2float(p[i]); }
+template <class S, class C>
+__device__ inline C ld(const S* __restrict__ p, uint32_t i) { return ld<S, C>(p, int64_t(i)); }
+
+template <class S, class C>
+__device__ inline void st(S* __restrict__ p, int64_t i, C v);
+template <>
+__device__ inline void st<double, double>(double* __restrict__ p, int64_t i, double v) { p[i] = v; }
+template <>
+__device__ inline void st<float, float>(float* __restrict__ p, int64_t i, float v) { p[i] = v; }
+template <>
+__device__ inline void st<__half, float>(__half* __restrict__ p, int64_t i, float v) { p[i] = __float2half_rn(v); }
+template <class S, class C>
+__device__ inline void st(S* __restrict__ p, uint32_t i, C v) { st<S, C>(p, int64_t(i), v); }
+
+// ---------------------------------------------------------------- bounds-checked buffer access
+// Raw buffer instructions address from a scalar 128-bit resource plus a 32-bit per-lane byte
+// offset; an offset at or beyond the resource size makes a load return 0 and drops a store.  A
+// lane that must not touch memory gets offset OOB, so loads and stores need no divergent branch
+// (and the compiler can keep track of how many memory operations are in flight).
+constexpr uint32_t OOB = 0xFFFFFF00u;
+constexpr uint32_t BUF_MAX = 0xFFFFFE00u;  // largest resource size used
+
+__device__ inline __amdgpu_buffer_rsrc_t make_res(const void* p, uint64_t bytes) {
+    const uint32_t n = bytes > BUF_MAX ? BUF_MAX : uint32_t(bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(n), 0x00020000);
+}
+
+template <class S>
+struct Buf;
+template <>
+struct Buf<double> {
+    static __device__ inline double ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    }
+};
+template <>
+struct Buf<float> {
+    static __device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+    static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+    }
+};
+template <>
+struct Buf<__half> {
+    static __device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)));
+    }
+    static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v)), r, off, 0, 0);
+    }
+};
+__device__ inline int32_t ld_i32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return int32_t(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// reciprocal: IEEE division in FP64, the hardware reciprocal (1 ulp) in FP32
+__device__ inline double rcp(double x) { return 1.0 / x; }
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double fsqrt(double x) { return sqrt(x); }
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// ---------------------------------------------------------------- thermodynamics
+template <class C>
+struct Eos {
+    C RT, a, b4, two_over_G;  // R T, a, b / 4, 2 / G
+};
+
+// Effective mass of the EOS-based pseudopotential: rho c_s^2 + G psi^2 / 2 = p_CS(rho), c = 1.
+// A non-positive density or a negative square-root argument sets *bad (and gives psi = 0).
+template <class C>
+__device__ inline C psi_val(C rho, const Eos<C>& e, bool* bad) {
+    const C eta = rho * e.b4;
+    const C om = C(1) - eta;
+    const C p = rho * e.RT * (C(1) + eta + eta * eta - eta * eta * eta) * rcp(om * om * om) - e.a * rho * rho;
+    const C arg = (p - rho * C(1.0 / 3.0)) * e.two_over_G;
+    const bool ok = (rho > C(0)) && (arg >= C(0));
+    *bad = *bad || !ok;
+    return ok ? fsqrt(arg) : C(0);
+}
+
+// As psi_val, raising the sticky domain flag directly (kernels outside the hot loop).
+template <class C>
+__device__ inline C psi_of(C rho, const Eos<C>& e, int32_t* flags) {
+    const C eta = rho * e.b4;
+    const C om = C(1) - eta;
+    const C p = rho * e.RT * (C(1) + eta + eta * eta - eta * eta * eta) * rcp(om * om * om) - e.a * rho * rho;
+    const C arg = (p - rho * C(1.0 / 3.0)) * e.two_over_G;
+    if (!(rho > C(0)) || !(arg >= C(0))) {
+        atomicOr(&flags[FLAG_DOMAIN], 1);
+        return C(0);
+    }
+    return fsqrt(arg);
+}
+
+__device__ inline int wrap1(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+}  // namespace mcb

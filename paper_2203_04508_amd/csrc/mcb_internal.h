@@ -1,0 +1,111 @@
+// Internal declarations of libmcb: context, arena layout, device lattice tables, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/mcb.h"
+
+namespace mcb {
+
+constexpr int64_t ONE = 65536;            // one lattice spacing in fixed point
+constexpr uint32_t NOHIT = 0xFFFFFFFFu;
+constexpr uint32_t QMASK = 0x1FFFFu;      // q_fixed in bits 0..16 of a packed link word
+constexpr int CLS_SHIFT = 30;             // link class in bits 30..31
+
+constexpr int STRIP = 256;                // 2-D step: lanes per workgroup (4 waves), one column each
+constexpr int STRIP_OUT = STRIP - 4;      // output columns per workgroup (two halo columns per side)
+constexpr int SCAN_BLOCK = 256;           // geometry scan granularity
+constexpr int MON_BLOCKS = 1024;          // monitor partial sums
+constexpr int MON_FIELDS = 8;             // M, Jx, Jy, Jz, dM, n_nan, spare, spare
+constexpr int MAX_BANDS = 8;
+
+// sticky device fault flags
+enum { FLAG_DOMAIN = 0, FLAG_NOHIT = 1, FLAG_COUNT = 16 };
+
+// ---------------------------------------------------------------- device lattice tables
+// D2Q9 in the column order of the moment matrix (eq. 2); D3Q19 rest / axes / edges.
+static __constant__ int c_ex[2][19] = {
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0}};
+static __constant__ int c_ey[2][19] = {
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1}};
+static __constant__ int c_ez[2][19] = {
+    {0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1}};
+static __constant__ int c_opp[2][19] = {
+    {0, 3, 4, 1, 2, 7, 8, 5, 6},
+    {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17}};
+
+struct GridDev {
+    int dim, nx, ny, nz, Q;
+    int64_t N;
+};
+
+// Byte offsets of the sub-buffers carved out of the two caller-owned arenas.
+struct Layout {
+    // lattice arena
+    int64_t fa, fb, tag, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
+    // links arena
+    int64_t bn_node, bn_mask, bn_link0, dm, lk_qc, lk_F, wl_node, wl_phi, links_bytes;
+};
+
+Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64_t n_bnodes, int64_t n_wall);
+int64_t storage_bytes(int precision);
+int64_t compute_bytes(int precision);
+
+}  // namespace mcb
+
+struct mcb_ctx {
+    mcb_params p{};
+    mcb::GridDev g{};
+    hipStream_t stream = nullptr;
+    char* lat = nullptr;
+    int64_t lat_bytes = 0;
+    char* lk = nullptr;
+    int64_t lk_bytes = 0;
+    int64_t n_shapes = 0, n_links = -1, n_bnodes = -1, n_wall = -1;
+    int64_t cap_shapes = 0;
+    int stage = 0;        // 0 created, 1 bound, 2 geometry set, 3 counted, 4 links filled, 5 state set
+    bool swapped = false; // current post-collision state lives in fb instead of fa
+    int64_t t = 0;
+    double dm_cum = 0.0;
+    int n_bands = 0;
+    mcb_shape bands[mcb::MAX_BANDS]{};
+    mcb::Layout L{};
+    std::string err;
+    // per-kernel event timing of mcb_step: a ring of event triples drained lazily
+    bool timing = false;
+    static constexpr int RING = 64;
+    hipEvent_t ev[RING][2]{};
+    bool ev_pending[RING]{};
+    int ev_next = 0;
+    bool ev_made = false;
+    double ms_tot = 0.0;
+    int64_t launches = 0;
+};
+
+namespace mcb {
+
+// ---------------------------------------------------------------- launchers (asynchronous)
+// geometry.hip
+hipError_t geom_classify(mcb_ctx* c);
+hipError_t geom_count(mcb_ctx* c);                // block sums + scan, totals at the end
+hipError_t geom_fill(mcb_ctx* c);                 // tags, boundary-node / wall tables, q, class
+hipError_t geom_reclass(mcb_ctx* c);              // class from the current q (after an override)
+
+// step2d.hip / step3d.hip
+hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
+hipError_t init_feq(mcb_ctx* c, const double* rho, const double* u, void* fout);
+
+// monitor.hip
+hipError_t monitor(mcb_ctx* c, const void* fcur);
+hipError_t moments_out(mcb_ctx* c, const void* fcur, double* rho, double* v);
+hipError_t convert_plane_in(mcb_ctx* c, const double* src, void* dst_plane, int dir);
+hipError_t convert_plane_out(mcb_ctx* c, const void* src_plane, double* dst, int dir);
+
+}  // namespace mcb

@@ -1,0 +1,295 @@
+// Observation and set-up kernels: equilibrium initialisation, the FP64 mass / momentum monitor
+// (deterministic two-pass wave64 reduction), the moment output v = u + F / (2 rho), and FP64
+// host-format conversions of the stored populations.
+#include "kernels_common.h"
+
+namespace mcb {
+namespace {
+
+template <class C>
+__device__ inline C wgt(int L, int i) {
+    if (L == 0) return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
+    return i == 0 ? C(1.0 / 3.0) : (i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0));
+}
+
+__device__ inline int64_t nb_index(const GridDev& g, int L, int64_t x, int i, int sign) {
+    const int cx = int(x % g.nx), cy = int((x / g.nx) % g.ny), cz = int(x / (int64_t(g.nx) * g.ny));
+    return wrap1(cx + sign * c_ex[L][i], g.nx) +
+           int64_t(g.nx) * (wrap1(cy + sign * c_ey[L][i], g.ny) + int64_t(g.ny) * wrap1(cz + sign * c_ez[L][i], g.nz));
+}
+
+// f(x, 0) = f^eq(rho, u) - w_i rho_ref on fluid nodes (eq. 14), zero elsewhere
+template <class S, class C>
+__global__ void k_init_feq(GridDev g, int L, const int32_t* __restrict__ tag, const double* __restrict__ rho,
+                           const double* __restrict__ u, C rho_ref, S* __restrict__ f) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        if (tag[x] < 0) {
+            for (int i = 0; i < g.Q; ++i) st<S, C>(f, i * g.N + x, C(0));
+            continue;
+        }
+        const C r = C(rho[x]);
+        C uv[3] = {C(0), C(0), C(0)};
+        if (u)
+            for (int k = 0; k < g.dim; ++k) uv[k] = C(u[k * g.N + x]);
+        const C uu = uv[0] * uv[0] + uv[1] * uv[1] + uv[2] * uv[2];
+        for (int i = 0; i < g.Q; ++i) {
+            const C eu = C(c_ex[L][i]) * uv[0] + C(c_ey[L][i]) * uv[1] + C(c_ez[L][i]) * uv[2];
+            const C w = wgt<C>(L, i);
+            const C geq = w * (r - rho_ref) + w * r * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
+            st<S, C>(f, i * g.N + x, geq);
+        }
+    }
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// pass 1: fixed grid of MON_BLOCKS workgroups, fixed node assignment -> deterministic partials
+template <class S, class C>
+__global__ __launch_bounds__(256) void k_mon_partial(GridDev g, int L, const S* __restrict__ f, const int32_t* __restrict__ tag,
+                                                     double rho_ref, const double* __restrict__ dm, int64_t nb,
+                                                     double* __restrict__ partials) {
+    double acc[MON_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += stride) {
+        if (tag[x] < 0) continue;
+        double m = 0, jx = 0, jy = 0, jz = 0;
+        for (int i = 0; i < g.Q; ++i) {
+            const double v = double(ld<S, C>(f, i * g.N + x));
+            m += v;
+            jx += v * c_ex[L][i];
+            jy += v * c_ey[L][i];
+            jz += v * c_ez[L][i];
+        }
+        m += rho_ref;
+        acc[0] += m;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[3] += jz;
+        if (!isfinite(m) || !isfinite(jx) || !isfinite(jy) || !isfinite(jz)) acc[5] += 1.0;
+    }
+    for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < nb; b += stride) acc[4] += dm[b];
+    __shared__ double red[MON_FIELDS][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < MON_FIELDS; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) red[k][wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < MON_FIELDS) {
+        const int k = threadIdx.x;
+        partials[blockIdx.x * MON_FIELDS + k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    }
+}
+
+// pass 2: one workgroup, fixed order
+__global__ __launch_bounds__(256) void k_mon_final(const double* __restrict__ partials, int nparts, double* __restrict__ out) {
+    __shared__ double red[MON_FIELDS][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < MON_FIELDS; ++k) {
+        double s = 0;
+        for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += partials[p * MON_FIELDS + k];
+        s = wave_sum(s);
+        if (lane == 0) red[k][wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < MON_FIELDS) {
+        const int k = threadIdx.x;
+        out[k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    }
+}
+
+// ---- moments: rho, psi (fluid and wall nodes), then v = (j - F / 2) / rho
+template <class S, class C>
+__global__ void k_rho_out(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag, double rho_ref,
+                          double* __restrict__ rho) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        if (tag[x] < 0) { rho[x] = 0.0; continue; }
+        double s = 0;
+        for (int i = 0; i < g.Q; ++i) s += double(ld<S, C>(f, i * g.N + x));
+        rho[x] = s + rho_ref;
+    }
+}
+
+__global__ void k_psi_out(GridDev g, int L, const int32_t* __restrict__ tag, const double* __restrict__ rho,
+                          const double* __restrict__ phi, Eos<double> eos, int32_t* flags, double* __restrict__ psi) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int tg = tag[x];
+        if (tg >= 0) { psi[x] = psi_of(rho[x], eos, flags); continue; }
+        if (tg == -1) { psi[x] = 0.0; continue; }
+        double num = 0, den = 0;
+        for (int i = 1; i < g.Q; ++i) {
+            const int64_t y = nb_index(g, L, x, i, +1);
+            if (tag[y] >= 0) {
+                num += wgt<double>(L, i) * rho[y];
+                den += wgt<double>(L, i);
+            }
+        }
+        psi[x] = psi_of(phi[-tg - 2] * (num / den), eos, flags);
+    }
+}
+
+template <class S, class C>
+__global__ void k_vel_out(GridDev g, int L, const S* __restrict__ f, const int32_t* __restrict__ tag,
+                          const double* __restrict__ rho, const double* __restrict__ psi, double G, double* __restrict__ v) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        if (tag[x] < 0) {
+            for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = 0.0;
+            continue;
+        }
+        double j[3] = {0, 0, 0}, s[3] = {0, 0, 0};
+        for (int i = 1; i < g.Q; ++i) {
+            const double fi = double(ld<S, C>(f, i * g.N + x));
+            const double ws = (L == 0) ? (i < 5 ? 1.0 / 3.0 : 1.0 / 12.0) : (i < 7 ? 1.0 / 6.0 : 1.0 / 12.0);
+            const double py = psi[nb_index(g, L, x, i, +1)];
+            const int e[3] = {c_ex[L][i], c_ey[L][i], c_ez[L][i]};
+            for (int k = 0; k < 3; ++k) {
+                j[k] += fi * e[k];
+                s[k] += ws * py * e[k];
+            }
+        }
+        for (int k = 0; k < g.dim; ++k) {
+            const double F = -G * psi[x] * s[k];
+            v[k * g.N + x] = (j[k] - 0.5 * F) / rho[x];
+        }
+    }
+}
+
+template <class S, class C>
+__global__ void k_plane_in(int64_t N, const double* __restrict__ src, S* __restrict__ dst, C shift) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x)
+        st<S, C>(dst, x, C(src[x]) - shift);
+}
+
+template <class S, class C>
+__global__ void k_plane_out(int64_t N, const S* __restrict__ src, const int32_t* __restrict__ tag, double* __restrict__ dst,
+                            double shift) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x)
+        dst[x] = tag[x] < 0 ? 0.0 : double(ld<S, C>(src, x)) + shift;
+}
+
+inline unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    return unsigned(b < 1 ? 1 : b);
+}
+
+inline double w_of(const mcb_ctx* c, int i) {
+    if (c->g.dim == 2) return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+template <class S, class C>
+hipError_t init_feq_t(mcb_ctx* c, const double* rho, const double* u, void* fout) {
+    const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
+    hipLaunchKernelGGL((k_init_feq<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, c->g.dim == 2 ? 0 : 1,
+                       reinterpret_cast<const int32_t*>(c->lat + c->L.tag), rho, u, C(rr), static_cast<S*>(fout));
+    return hipGetLastError();
+}
+
+template <class S, class C>
+hipError_t monitor_t(mcb_ctx* c, const void* fcur) {
+    const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
+    double* partials = reinterpret_cast<double*>(c->lat + c->L.partials);
+    hipLaunchKernelGGL((k_mon_partial<S, C>), dim3(MON_BLOCKS), dim3(256), 0, c->stream, c->g, c->g.dim == 2 ? 0 : 1,
+                       static_cast<const S*>(fcur), reinterpret_cast<const int32_t*>(c->lat + c->L.tag), rr,
+                       reinterpret_cast<const double*>(c->lk + c->L.dm), c->n_bnodes, partials);
+    hipLaunchKernelGGL(k_mon_final, dim3(1), dim3(256), 0, c->stream, partials, MON_BLOCKS,
+                       reinterpret_cast<double*>(c->lat + c->L.result));
+    return hipGetLastError();
+}
+
+template <class S, class C>
+hipError_t moments_t(mcb_ctx* c, const void* fcur, double* rho, double* v) {
+    const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
+    const int L = c->g.dim == 2 ? 0 : 1;
+    double* sr = reinterpret_cast<double*>(c->lat + c->L.scratch);
+    double* sp = sr + c->g.N;
+    double* sv = sp + c->g.N;
+    const int32_t* tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
+    Eos<double> eos{c->p.eos_R * c->p.eos_T, c->p.eos_a, c->p.eos_b / 4.0, 2.0 / c->p.G};
+    hipLaunchKernelGGL((k_rho_out<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, rr, sr);
+    hipLaunchKernelGGL(k_psi_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, L, tag, sr,
+                       reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos,
+                       reinterpret_cast<int32_t*>(c->lat + c->L.flags), sp);
+    hipLaunchKernelGGL((k_vel_out<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, L, static_cast<const S*>(fcur),
+                       tag, sr, sp, c->p.G, sv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (rho) {
+        e = hipMemcpyAsync(rho, sr, sizeof(double) * c->g.N, hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return e;
+    }
+    if (v) {
+        e = hipMemcpyAsync(v, sv, sizeof(double) * c->g.N * c->g.dim, hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(c->stream);
+}
+
+}  // namespace
+
+hipError_t init_feq(mcb_ctx* c, const double* rho, const double* u, void* fout) {
+    switch (c->p.precision) {
+        case MCB_F64: return init_feq_t<double, double>(c, rho, u, fout);
+        case MCB_F32S: return init_feq_t<float, float>(c, rho, u, fout);
+        default: return init_feq_t<__half, float>(c, rho, u, fout);
+    }
+}
+
+hipError_t monitor(mcb_ctx* c, const void* fcur) {
+    switch (c->p.precision) {
+        case MCB_F64: return monitor_t<double, double>(c, fcur);
+        case MCB_F32S: return monitor_t<float, float>(c, fcur);
+        default: return monitor_t<__half, float>(c, fcur);
+    }
+}
+
+hipError_t moments_out(mcb_ctx* c, const void* fcur, double* rho, double* v) {
+    switch (c->p.precision) {
+        case MCB_F64: return moments_t<double, double>(c, fcur, rho, v);
+        case MCB_F32S: return moments_t<float, float>(c, fcur, rho, v);
+        default: return moments_t<__half, float>(c, fcur, rho, v);
+    }
+}
+
+hipError_t convert_plane_in(mcb_ctx* c, const double* src, void* dst_plane, int dir) {
+    const double shift = c->p.precision == MCB_F64 ? 0.0 : w_of(c, dir) * c->p.rho_ref;
+    switch (c->p.precision) {
+        case MCB_F64:
+            hipLaunchKernelGGL((k_plane_in<double, double>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N, src,
+                               static_cast<double*>(dst_plane), shift);
+            break;
+        case MCB_F32S:
+            hipLaunchKernelGGL((k_plane_in<float, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N, src,
+                               static_cast<float*>(dst_plane), float(shift));
+            break;
+        default:
+            hipLaunchKernelGGL((k_plane_in<__half, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N, src,
+                               static_cast<__half*>(dst_plane), float(shift));
+    }
+    return hipGetLastError();
+}
+
+hipError_t convert_plane_out(mcb_ctx* c, const void* src_plane, double* dst, int dir) {
+    const double shift = c->p.precision == MCB_F64 ? 0.0 : w_of(c, dir) * c->p.rho_ref;
+    const int32_t* tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
+    switch (c->p.precision) {
+        case MCB_F64:
+            hipLaunchKernelGGL((k_plane_out<double, double>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N,
+                               static_cast<const double*>(src_plane), tag, dst, shift);
+            break;
+        case MCB_F32S:
+            hipLaunchKernelGGL((k_plane_out<float, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N,
+                               static_cast<const float*>(src_plane), tag, dst, shift);
+            break;
+        default:
+            hipLaunchKernelGGL((k_plane_out<__half, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N,
+                               static_cast<const __half*>(src_plane), tag, dst, shift);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mcb

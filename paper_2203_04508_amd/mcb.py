@@ -1,0 +1,332 @@
+"""Python binding of libmcb (``include/mcb.h``): one function per C entry point, same names,
+argument marshalling only.  Every step of the simulation runs in the HIP kernels of the library;
+torch provides the device arenas and the stream.
+
+:class:`Lattice` strings the calls together (create -> bind -> geometry -> links -> state ->
+step -> observe) and owns the torch tensors that back the device arenas.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcb.so")
+
+MCB_OK, MCB_EINVAL, MCB_ESIZE, MCB_EHIP, MCB_EDOMAIN, MCB_ENAN, MCB_ESTATE, MCB_ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
+MCB_F64, MCB_F32S, MCB_F16S = 0, 1, 2
+MCB_BC_PRESENT = 0
+MCB_COUNT, MCB_FILL = 0, 1
+PRECISIONS = {"f64": MCB_F64, "f32s": MCB_F32S, "f16s": MCB_F16S}
+STATUS_NAMES = {0: "MCB_OK", -1: "MCB_EINVAL", -2: "MCB_ESIZE", -3: "MCB_EHIP", -4: "MCB_EDOMAIN",
+                -5: "MCB_ENAN", -6: "MCB_ESTATE", -7: "MCB_ENOTSUP"}
+
+
+class mcb_params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("tau", C.c_double), ("G", C.c_double),
+                ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double), ("eos_T", C.c_double),
+                ("precision", C.c_int32), ("bc_mode", C.c_int32), ("rho_ref", C.c_double)]
+
+
+class mcb_shape(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("kind", "cx", "cy", "cz", "radius", "lo", "hi", "group")]
+
+
+class mcb_link(C.Structure):
+    _fields_ = [("node", C.c_int64), ("dir", C.c_int32), ("cls", C.c_int32), ("q_fixed", C.c_uint32), ("pad", C.c_uint32)]
+
+
+LINK_DTYPE = np.dtype([("node", np.int64), ("dir", np.int32), ("cls", np.int32), ("q_fixed", np.uint32), ("pad", np.uint32)])
+
+
+class mcb_sizes(C.Structure):
+    _fields_ = [("lattice_bytes", C.c_int64), ("links_bytes", C.c_int64)]
+
+
+class mcb_buffers(C.Structure):
+    _fields_ = [("lattice", C.c_void_p), ("lattice_bytes", C.c_int64), ("links", C.c_void_p), ("links_bytes", C.c_int64)]
+
+
+class mcb_mass_report(C.Structure):
+    _fields_ = [("M", C.c_double), ("J", C.c_double * 3), ("dM_last", C.c_double),
+                ("n_nan", C.c_int64), ("n_domain", C.c_int64), ("t", C.c_int64)]
+
+
+EXPORTS = [
+    "mcb_create", "mcb_destroy", "mcb_last_error", "mcb_required_sizes", "mcb_bind_buffers",
+    "mcb_set_geometry", "mcb_build_links", "mcb_get_links", "mcb_get_wall_nodes", "mcb_set_links",
+    "mcb_set_wettability", "mcb_init_equilibrium", "mcb_set_f", "mcb_get_f", "mcb_step",
+    "mcb_moments", "mcb_mass", "mcb_sync", "mcb_timing", "mcb_timing_report",
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmcb.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libmcb.so not found at {path}: build it with paper_2203_04508_amd/build.py")
+    L = C.CDLL(path)
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    P = C.POINTER
+    sig = {
+        "mcb_create": ([P(mcb_params), P(vp)], i32),
+        "mcb_destroy": ([vp], None),
+        "mcb_last_error": ([vp], C.c_char_p),
+        "mcb_required_sizes": ([P(mcb_params), i64, i64, i64, i64, P(mcb_sizes)], i32),
+        "mcb_bind_buffers": ([vp, P(mcb_buffers), vp], i32),
+        "mcb_set_geometry": ([vp, vp, i64], i32),
+        "mcb_build_links": ([vp, i32, P(i64), P(i64), P(i64)], i32),
+        "mcb_get_links": ([vp, vp, i64], i32),
+        "mcb_get_wall_nodes": ([vp, vp, i64], i32),
+        "mcb_set_links": ([vp, vp, i64], i32),
+        "mcb_set_wettability": ([vp, vp, i64], i32),
+        "mcb_init_equilibrium": ([vp, vp, vp], i32),
+        "mcb_set_f": ([vp, vp], i32),
+        "mcb_get_f": ([vp, vp], i32),
+        "mcb_step": ([vp, i64], i32),
+        "mcb_moments": ([vp, vp, vp], i32),
+        "mcb_mass": ([vp, P(mcb_mass_report)], i32),
+        "mcb_sync": ([vp], i32),
+        "mcb_timing": ([vp, i32], i32),
+        "mcb_timing_report": ([vp, P(C.c_double), P(i64)], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+class MCBError(RuntimeError):
+    def __init__(self, code, where, msg):
+        self.code = code
+        super().__init__(f"{where}: {STATUS_NAMES.get(code, code)}: {msg}")
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(ctx, code, where):
+    if code != MCB_OK:
+        msg = load().mcb_last_error(ctx) if ctx else b""
+        raise MCBError(code, where, (msg or b"").decode())
+
+
+# ---------------------------------------------------------------- one wrapper per entry point
+def mcb_create(params: mcb_params):
+    h = C.c_void_p()
+    code = load().mcb_create(C.byref(params), C.byref(h))
+    if code != MCB_OK:
+        raise MCBError(code, "mcb_create", "invalid parameters")
+    return h
+
+
+def mcb_destroy(ctx):
+    load().mcb_destroy(ctx)
+
+
+def mcb_last_error(ctx) -> str:
+    return (load().mcb_last_error(ctx) or b"").decode()
+
+
+def mcb_required_sizes(params: mcb_params, n_shapes=0, n_links=0, n_bnodes=0, n_wall=0) -> mcb_sizes:
+    out = mcb_sizes()
+    code = load().mcb_required_sizes(C.byref(params), n_shapes, n_links, n_bnodes, n_wall, C.byref(out))
+    if code != MCB_OK:
+        raise MCBError(code, "mcb_required_sizes", "invalid arguments")
+    return out
+
+
+def mcb_bind_buffers(ctx, lattice_ptr, lattice_bytes, links_ptr, links_bytes, stream_handle):
+    b = mcb_buffers(lattice_ptr, lattice_bytes, links_ptr, links_bytes)
+    _check(ctx, load().mcb_bind_buffers(ctx, C.byref(b), C.c_void_p(stream_handle)), "mcb_bind_buffers")
+
+
+def mcb_set_geometry(ctx, shapes: np.ndarray):
+    shapes = np.ascontiguousarray(shapes, np.int64).reshape(-1, 8)
+    _check(ctx, load().mcb_set_geometry(ctx, _ptr(shapes), len(shapes)), "mcb_set_geometry")
+
+
+def mcb_build_links(ctx, phase):
+    nl, nb, nw = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(ctx, load().mcb_build_links(ctx, phase, C.byref(nl), C.byref(nb), C.byref(nw)), "mcb_build_links")
+    return nl.value, nb.value, nw.value
+
+
+def mcb_get_links(ctx, n_links) -> np.ndarray:
+    out = np.zeros(n_links, LINK_DTYPE)
+    _check(ctx, load().mcb_get_links(ctx, _ptr(out), n_links), "mcb_get_links")
+    return out
+
+
+def mcb_get_wall_nodes(ctx, n_wall) -> np.ndarray:
+    out = np.zeros(n_wall, np.int64)
+    _check(ctx, load().mcb_get_wall_nodes(ctx, _ptr(out), n_wall), "mcb_get_wall_nodes")
+    return out
+
+
+def mcb_set_links(ctx, links: np.ndarray):
+    links = np.ascontiguousarray(links, LINK_DTYPE)
+    _check(ctx, load().mcb_set_links(ctx, _ptr(links), len(links)), "mcb_set_links")
+
+
+def mcb_set_wettability(ctx, phi: np.ndarray):
+    phi = np.ascontiguousarray(phi, np.float64)
+    _check(ctx, load().mcb_set_wettability(ctx, _ptr(phi), len(phi)), "mcb_set_wettability")
+
+
+def mcb_init_equilibrium(ctx, rho: np.ndarray, u: np.ndarray | None = None):
+    rho = np.ascontiguousarray(rho, np.float64)
+    u = None if u is None else np.ascontiguousarray(u, np.float64)
+    _check(ctx, load().mcb_init_equilibrium(ctx, _ptr(rho), _ptr(u)), "mcb_init_equilibrium")
+
+
+def mcb_set_f(ctx, f: np.ndarray):
+    f = np.ascontiguousarray(f, np.float64)
+    _check(ctx, load().mcb_set_f(ctx, _ptr(f)), "mcb_set_f")
+
+
+def mcb_get_f(ctx, Q, N) -> np.ndarray:
+    f = np.zeros((Q, N))
+    _check(ctx, load().mcb_get_f(ctx, _ptr(f)), "mcb_get_f")
+    return f
+
+
+def mcb_step(ctx, n):
+    _check(ctx, load().mcb_step(ctx, int(n)), "mcb_step")
+
+
+def mcb_moments(ctx, dim, N):
+    rho = np.zeros(N)
+    v = np.zeros((dim, N))
+    _check(ctx, load().mcb_moments(ctx, _ptr(rho), _ptr(v)), "mcb_moments")
+    return rho, v
+
+
+def mcb_mass(ctx) -> mcb_mass_report:
+    r = mcb_mass_report()
+    _check(ctx, load().mcb_mass(ctx, C.byref(r)), "mcb_mass")
+    return r
+
+
+def mcb_sync(ctx):
+    _check(ctx, load().mcb_sync(ctx), "mcb_sync")
+
+
+def mcb_timing(ctx, enable: bool):
+    _check(ctx, load().mcb_timing(ctx, 1 if enable else 0), "mcb_timing")
+
+
+def mcb_timing_report(ctx):
+    """(total ms of the fused step kernel, number of timed launches)"""
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(ctx, load().mcb_timing_report(ctx, C.byref(ms), C.byref(n)), "mcb_timing_report")
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------- convenience object
+class Lattice:
+    """A context plus the torch tensors backing its device arenas."""
+
+    def __init__(self, dim, dims, tau, T, precision="f64", rho_ref=0.0, G=-1.0, a=1.0, b=4.0, R=1.0,
+                 device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        nz = dims[2] if dim == 3 else 1
+        self.params = mcb_params(dim, dims[0], dims[1], nz, tau, G, a, b, R, T,
+                                 PRECISIONS[precision] if isinstance(precision, str) else precision,
+                                 MCB_BC_PRESENT, rho_ref)
+        self.dim = dim
+        self.Q = 9 if dim == 2 else 19
+        self.N = int(dims[0]) * int(dims[1]) * int(nz)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = mcb_create(self.params)
+        self.lat = None
+        self.lnk = None
+        self.n_links = self.n_bnodes = self.n_wall = 0
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            mcb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind(self):
+        lp = self.lat.data_ptr()
+        kp = self.lnk.data_ptr() if self.lnk is not None and self.lnk.numel() else None
+        mcb_bind_buffers(self.ctx, lp, self.lat.numel(), kp, 0 if kp is None else self.lnk.numel(),
+                         self.stream.cuda_stream)
+
+    def set_geometry(self, shapes):
+        torch = self.torch
+        shapes = np.ascontiguousarray(shapes, np.int64).reshape(-1, 8)
+        sz = mcb_required_sizes(self.params, len(shapes))
+        if self.lat is None or self.lat.numel() < sz.lattice_bytes:
+            self.lat = torch.empty(sz.lattice_bytes, dtype=torch.uint8, device=self.device)
+        self._bind()
+        mcb_set_geometry(self.ctx, shapes)
+        self.n_links, self.n_bnodes, self.n_wall = mcb_build_links(self.ctx, MCB_COUNT)
+        sz = mcb_required_sizes(self.params, len(shapes), self.n_links, self.n_bnodes, self.n_wall)
+        if sz.links_bytes > 0:
+            self.lnk = torch.empty(sz.links_bytes, dtype=torch.uint8, device=self.device)
+        self._bind()
+        mcb_build_links(self.ctx, MCB_FILL)
+        return self.n_links, self.n_bnodes, self.n_wall
+
+    def links(self):
+        return mcb_get_links(self.ctx, self.n_links)
+
+    def wall_nodes(self):
+        return mcb_get_wall_nodes(self.ctx, self.n_wall)
+
+    def set_links(self, links):
+        mcb_set_links(self.ctx, links)
+
+    def set_wettability(self, phi):
+        phi = np.ascontiguousarray(np.broadcast_to(np.asarray(phi, np.float64), (self.n_wall,)))
+        mcb_set_wettability(self.ctx, phi)
+
+    def init_equilibrium(self, rho, u=None):
+        mcb_init_equilibrium(self.ctx, np.asarray(rho, np.float64).reshape(-1),
+                             None if u is None else np.asarray(u, np.float64).reshape(-1))
+
+    def set_f(self, f):
+        mcb_set_f(self.ctx, np.asarray(f, np.float64).reshape(self.Q, self.N))
+
+    def get_f(self):
+        return mcb_get_f(self.ctx, self.Q, self.N)
+
+    def step(self, n=1):
+        mcb_step(self.ctx, n)
+
+    def moments(self):
+        return mcb_moments(self.ctx, self.dim, self.N)
+
+    def mass(self):
+        return mcb_mass(self.ctx)
+
+    def sync(self):
+        mcb_sync(self.ctx)
+
+    def timing(self, enable=True):
+        mcb_timing(self.ctx, enable)
+
+    def timing_report(self):
+        return mcb_timing_report(self.ctx)

@@ -13,7 +13,7 @@ Shape record, int64 x 8 (units of 2^-16 lattice spacings):
 Workloads (the paper's own runs use 500x300 to 600x1200 boxes, drop radii 50-100 and an
 interface width of 10, Sec. 4; these synthetic cases keep that structure at other sizes):
     c0  64^2 D2Q9, one off-lattice cylinder (r 12.3 at (32.4, 20.7)), one drop r 10 resting on it
-    c1  1024^2 D2Q9, 300 random circles r in U(8, 24), 40 drops r in U(15, 40)
+    c1  1024^2 D2Q9, 300 random circles r in U(8, 24), 40 drops r in U(15, 40), 0.6 T_c, tau 1
     c2  4096^2 D2Q9, the c1 generator scaled x4 in area: 4800 circles, 640 drops
     c3  512^2 D2Q9, a slab with 60 half-circles r in U(4, 12) on top, one drop r 40
     c4  256^3 D3Q19, 400 random spheres r in U(6, 14), 200 drops r in U(8, 16)
@@ -98,21 +98,39 @@ def _min_image(d, L):
     return d - L * np.round(d / L)
 
 
+DROP_CUTOFF = 12.0  # drop profiles are evaluated out to r0 + DROP_CUTOFF * W (tanh is 1 to 1e-20 there)
+
+
 def drop_field(dims, dim, drops, rho_v, rho_l, W):
     nx, ny, nz = dims
-    axes = [np.arange(nx, dtype=np.float64), np.arange(ny, dtype=np.float64), np.arange(nz, dtype=np.float64)]
-    excess = np.zeros((nz, ny, nx))
+    n = [nx, ny, nz]
+    excess = np.zeros(nx * ny * nz)
     for c, r0 in drops:
-        d2 = np.zeros((nz, ny, nx))
+        reach = r0 + DROP_CUTOFF * W
+        ax = []
+        for k in range(3):
+            if k < dim:
+                lo = int(np.floor(c[k] - reach))
+                hi = int(np.ceil(c[k] + reach)) + 1
+                idx = np.arange(lo, hi)
+                if hi - lo >= n[k]:
+                    idx = np.arange(n[k])
+                ax.append(idx)
+            else:
+                ax.append(np.arange(1))
+        d2 = np.zeros((len(ax[2]), len(ax[1]), len(ax[0])))
         for k in range(dim):
-            dk = _min_image(axes[k] - c[k], dims[k])
+            dk = _min_image(np.mod(ax[k], n[k]).astype(np.float64) - c[k], n[k])
             shape = [1, 1, 1]
-            shape[2 - k] = dims[k]
+            shape[2 - k] = len(ax[k])
             d2 = d2 + (dk**2).reshape(shape)
         r = np.sqrt(d2)
-        prof = 0.5 * (rho_v + rho_l) + 0.5 * (rho_v - rho_l) * np.tanh(2.0 * (r - r0) / W)
-        excess = np.maximum(excess, prof - rho_v)
-    return (rho_v + excess).reshape(-1)
+        prof = 0.5 * (rho_v + rho_l) + 0.5 * (rho_v - rho_l) * np.tanh(2.0 * (r - r0) / W) - rho_v
+        prof = np.where(r - r0 > DROP_CUTOFF * W, 0.0, prof)
+        zz, yy, xx = np.meshgrid(np.mod(ax[2], n[2]), np.mod(ax[1], n[1]), np.mod(ax[0], n[0]), indexing="ij")
+        lin = (xx + nx * (yy + ny * zz)).reshape(-1)
+        excess[lin] = np.maximum(excess[lin], prof.reshape(-1))  # lin has no repeats within one drop
+    return rho_v + excess
 
 
 def _rsa(rng, n, dims, dim, rlo, rhi, max_tries=2_000_000):
@@ -168,7 +186,8 @@ def make(name: str) -> Workload:
         shapes = np.array([ball(c, r, g) for g, (c, r) in enumerate(zip(cs, rs))], np.int64)
         drops = _drops(rng, 40 * scale * scale, (n, n, 1), 2, 15.0, 40.0)
         phi = rng.uniform(*PHI_RANGE, len(rs))
-        return Workload(name, 2, (n, n, 1), 0.8, 0.60, shapes, drops, phi, 10000 if name == "c1" else 5000)
+        # tau = 1: at 0.6 T_c (density ratio ~ 700 with this model) tau = 0.8 is unstable
+        return Workload(name, 2, (n, n, 1), 1.0, 0.60, shapes, drops, phi, 10000 if name == "c1" else 5000)
     if name == "c3":
         rng = np.random.Generator(np.random.PCG64(3))
         top = 10.35
@@ -194,26 +213,39 @@ def make(name: str) -> Workload:
 def wall_groups(wl: Workload, wall_nodes: np.ndarray) -> np.ndarray:
     """Group of each wall node: the group of the first shape (in list order) strictly containing it."""
     nx, ny, nz = wl.dims
+    n = [nx, ny, nz]
     wall_nodes = np.asarray(wall_nodes, np.int64)
+    windex = np.full(wl.N, -1, np.int64)
+    windex[wall_nodes] = np.arange(len(wall_nodes))
     grp = np.full(len(wall_nodes), -1, np.int64)
-    coords = [wall_nodes % nx, (wall_nodes // nx) % ny, wall_nodes // (nx * ny)]
     for s in wl.shapes:
         kind, c, r, lo, hi, g = int(s[0]), s[1:4], int(s[4]), int(s[5]), int(s[6]), int(s[7])
-        todo = grp < 0
-        if not todo.any():
-            break
         if kind == KIND_BALL:
-            acc = np.zeros(len(wall_nodes), np.int64)
+            ax = []
+            for k in range(3):
+                if k < wl.dim:
+                    a = (int(c[k]) - r) // ONE
+                    b = (int(c[k]) + r) // ONE + 1
+                    ax.append(np.mod(np.arange(a, b), n[k]))
+                else:
+                    ax.append(np.zeros(1, np.int64))
+            zz, yy, xx = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+            cs = [xx.reshape(-1), yy.reshape(-1), zz.reshape(-1)]
+            acc = np.zeros(len(cs[0]), np.int64)
             for k in range(wl.dim):
-                Lk = wl.dims[k] * ONE
-                d = (coords[k] * ONE - int(c[k])) % Lk
+                Lk = n[k] * ONE
+                d = (cs[k] * ONE - int(c[k])) % Lk
                 d = np.where(d >= Lk // 2, d - Lk, d)
                 acc += d * d
-            inside = acc < r * r
+            lin = cs[0] + nx * (cs[1] + ny * cs[2])
+            w = windex[lin[acc < r * r]]
         else:
             Ly = ny * ONE
-            inside = ((coords[1] * ONE - lo) % Ly) < (hi - lo)
-        grp[todo & inside] = g
+            y = (wall_nodes // nx) % ny
+            w = np.nonzero(((y * ONE - lo) % Ly) < (hi - lo))[0]
+        w = w[w >= 0]
+        w = w[grp[w] < 0]
+        grp[w] = g
     if (grp < 0).any():
         raise ValueError("a wall node lies in no shape")
     return grp

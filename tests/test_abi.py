@@ -1,0 +1,82 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry point that
+include/mcb.h declares, and its structs have the layouts the Python binding assumes.
+No compute calls are made here."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcb.h")
+LIB = os.path.join(ROOT, "paper_2203_04508_amd", "libmcb.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcb_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libmcb.so not built (run __graft_entry__.build())")
+    return C.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_2203_04508_amd import mcb
+    assert sorted(mcb.EXPORTS) == declared_functions()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    from paper_2203_04508_amd import mcb
+    src = tmp_path / "sz.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "mcb.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(mcb_params), sizeof(mcb_shape),"
+        " sizeof(mcb_link), sizeof(mcb_sizes), sizeof(mcb_buffers), sizeof(mcb_mass_report),"
+        " offsetof(mcb_params, rho_ref)); return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(mcb.mcb_params), C.sizeof(mcb.mcb_shape), C.sizeof(mcb.mcb_link), C.sizeof(mcb.mcb_sizes),
+            C.sizeof(mcb.mcb_buffers), C.sizeof(mcb.mcb_mass_report), mcb.mcb_params.rho_ref.offset]
+    assert got == want
+    assert mcb.LINK_DTYPE.itemsize == C.sizeof(mcb.mcb_link)
+
+
+def test_host_side_argument_checks(lib):
+    """Parameter validation and sizing run on the host only."""
+    from paper_2203_04508_amd import mcb
+    mcb.load(LIB)
+    good = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, 0, 0.0)
+    sz = mcb.mcb_required_sizes(good, 1)
+    assert sz.lattice_bytes >= 2 * 9 * 64 * 64 * 8 and sz.links_bytes == 0
+    sz2 = mcb.mcb_required_sizes(good, 1, 100, 40, 30)
+    assert sz2.links_bytes > 0
+    for bad in [dict(tau=0.5), dict(G=1.0), dict(nx=2), dict(dim=4), dict(precision=7), dict(nz=5)]:
+        p = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, 0, 0.0)
+        for k, v in bad.items():
+            setattr(p, k, v)
+        with pytest.raises(mcb.MCBError) as ei:
+            mcb.mcb_create(p)
+        assert ei.value.code == mcb.MCB_EINVAL
+    h = mcb.mcb_create(good)
+    # calls out of order are refused before any device work
+    with pytest.raises(mcb.MCBError) as ei:
+        mcb.mcb_step(h, 1)
+    assert ei.value.code == mcb.MCB_ESTATE
+    with pytest.raises(mcb.MCBError) as ei:
+        mcb.mcb_set_geometry(h, [[1, 0, 0, 0, 65536, 0, 0, 0]])
+    assert ei.value.code == mcb.MCB_ESTATE
+    mcb.mcb_destroy(h)
