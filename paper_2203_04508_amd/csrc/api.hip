@@ -42,7 +42,7 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.bn_link0 = take(4 * nb);
     L.dm = take(8 * nb);
     L.lk_qc = take(4 * nl);
-    L.lk_F = take(cb * nl);
+    L.lk_rec = take(2 * cb * nl);  // per link: signed interpolation coefficient, forcing term
     L.wl_node = take(4 * nw);
     L.wl_phi = take(8 * nw);
     L.links_bytes = (nb + nl + nw) > 0 ? o : 0;

@@ -313,10 +313,13 @@ __global__ void k_q_band(Bands b, GridDev g, int L, int64_t nb, const int32_t* _
     }
 }
 
-// class from q and the second fluid node; flags links no shape was found for
+// Class from q and the second fluid node, and the link record used by the step: the eq. 16-17
+// value is t + a (f~_j(x1) - t) with t = (f~_j(x2) or f~_opp(j)(x1)) + F_j, so the record holds
+// a = 2q (eq. 16), a = 1/(2q) stored negated to mark eq. 17, or a = 1 (bounce-back), next to the
+// forcing term F_j (zeroed here, written by every collision).  Flags links no shape was found for.
 __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict__ solid, const int32_t* __restrict__ bn_node,
                         const uint32_t* __restrict__ bn_mask, const int32_t* __restrict__ bn_link0, uint32_t* lk_qc,
-                        int32_t* flags) {
+                        void* rec, int rec_double, int32_t* flags) {
     for (int64_t bi = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; bi < nb; bi += int64_t(gridDim.x) * blockDim.x) {
         const int64_t x = bn_node[bi];
         const uint32_t mask = bn_mask[bi];
@@ -334,6 +337,15 @@ __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict_
             if (q >= uint32_t(ONE / 2)) cls = MCB_CLS_EQ17;
             else cls = solid[neighbour(g, c, L, i, -1)] ? MCB_CLS_HBB : MCB_CLS_EQ16;
             lk_qc[l] = q | (uint32_t(cls) << CLS_SHIFT);
+            const double q2 = double(q) * (2.0 / 65536.0);
+            const double a = cls == MCB_CLS_EQ16 ? q2 : (cls == MCB_CLS_EQ17 ? -1.0 / q2 : 1.0);
+            if (rec_double) {
+                static_cast<double*>(rec)[2 * l] = a;
+                static_cast<double*>(rec)[2 * l + 1] = 0.0;
+            } else {
+                static_cast<float*>(rec)[2 * l] = float(a);
+                static_cast<float*>(rec)[2 * l + 1] = 0.0f;
+            }
             ++l;
         }
     }
@@ -412,7 +424,8 @@ hipError_t geom_reclass(mcb_ctx* c) {
                        solid, reinterpret_cast<const int32_t*>(c->lk + c->L.bn_node),
                        reinterpret_cast<const uint32_t*>(c->lk + c->L.bn_mask),
                        reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0),
-                       reinterpret_cast<uint32_t*>(c->lk + c->L.lk_qc), flags);
+                       reinterpret_cast<uint32_t*>(c->lk + c->L.lk_qc), static_cast<void*>(c->lk + c->L.lk_rec),
+                       c->p.precision == MCB_F64 ? 1 : 0, flags);
     return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ struct Buf<double> {
     static __device__ inline double ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
     }
+    static __device__ inline double round(double v) { return v; }
     static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
@@ -59,6 +60,7 @@ struct Buf<float> {
     static __device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
     }
+    static __device__ inline float round(float v) { return v; }
     static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
     }
@@ -68,6 +70,7 @@ struct Buf<__half> {
     static __device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)));
     }
+    static __device__ inline float round(float v) { return __half2float(__float2half_rn(v)); }
     static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v)), r, off, 0, 0);
     }

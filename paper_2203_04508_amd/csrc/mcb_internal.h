@@ -16,8 +16,7 @@ constexpr uint32_t NOHIT = 0xFFFFFFFFu;
 constexpr uint32_t QMASK = 0x1FFFFu;      // q_fixed in bits 0..16 of a packed link word
 constexpr int CLS_SHIFT = 30;             // link class in bits 30..31
 
-constexpr int STRIP = 256;                // 2-D step: lanes per workgroup (4 waves), one column each
-constexpr int STRIP_OUT = STRIP - 4;      // output columns per workgroup (two halo columns per side)
+constexpr int STRIP_HALO = 4;             // 2-D step: halo lanes per strip (two columns on each side)
 constexpr int SCAN_BLOCK = 256;           // geometry scan granularity
 constexpr int MON_BLOCKS = 1024;          // monitor partial sums
 constexpr int MON_FIELDS = 8;             // M, Jx, Jy, Jz, dM, n_nan, spare, spare
@@ -51,7 +50,7 @@ struct Layout {
     // lattice arena
     int64_t fa, fb, tag, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
     // links arena
-    int64_t bn_node, bn_mask, bn_link0, dm, lk_qc, lk_F, wl_node, wl_phi, links_bytes;
+    int64_t bn_node, bn_mask, bn_link0, dm, lk_qc, lk_rec, wl_node, wl_phi, links_bytes;
 };
 
 Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64_t n_bnodes, int64_t n_wall);

@@ -3,11 +3,12 @@
 // the pseudopotential with first-layer wall densities (eq. 15), the interaction force, and the
 // single-relaxation-time collision with exact-difference forcing (eqs. 4, 13-14).
 //
-// Layout: a workgroup (4 waves, 256 lanes) owns a strip of 256 consecutive columns and a segment
-// of H rows, and marches up the segment one row per iteration.  Each iteration
-//   A  pulls the populations of the next row (own columns plus two halo columns on each side) and
-//      puts rho and the node tag into a 4-row LDS ring; a population arriving across a link is
-//      pulled as its bounce-back value, which already gives the node's density at t+1;
+// Layout: a workgroup of W lanes (one or four waves) covers W consecutive columns -- W - 4 output
+// columns and two halo columns on each side -- over a segment of H rows, and marches up the
+// segment one row per iteration.  Each iteration
+//   A  reduces the populations of the current row to rho and puts rho and the node tag into a
+//      4-row LDS ring; a population arriving across a link is pulled as its bounce-back value,
+//      which already gives the node's density at t+1;
 //   B  computes psi one row behind (wall nodes: eq. 15 average of their fluid neighbours times
 //      phi) into a second 4-row LDS ring;
 //   C  two rows behind, applies the link corrections of eqs. 16-18 at boundary nodes, evaluates the
@@ -15,7 +16,9 @@
 //      (kept in registers), then stores them.
 // Per node only the populations (read once, written once) and a 4-byte tag reach HBM; rho and psi
 // live in LDS.  Halo rows and columns are re-pulled by the neighbouring workgroup and hit in L2 or
-// the Infinity Cache.  Node tags are fetched one row ahead, so no load waits on another.
+// the Infinity Cache.  The populations of the next row and the tag of the row after it are in
+// flight while a row is processed; every global access is a bounds-checked buffer instruction, so
+// no load or store sits in a divergent branch and the wait counters stay exact.
 #include "kernels_common.h"
 
 namespace mcb {
@@ -27,12 +30,10 @@ struct Args2 {
     S* fb;                       // post-collision populations of time t+1
     const int32_t* tag;          // >0: (boundary index << 8) | link bits; 0 fluid; -1 solid; -2-w wall w
     const int32_t* bn_link0;     // first link of each boundary node
-    const uint32_t* lk_qc;       // q_fixed | class << 30, per link
-    C* lk_F;                     // eq. 13 term of the link direction: read at t, rewritten at t+1
+    C* lk_rec;                   // per link: {signed coefficient a, forcing term F_j}
     double* dm;                  // eq. 18 correction per boundary node (for the monitor)
     const double* phi;           // wettability factor per wall node
     int32_t* flags;
-    uint64_t f_bytes;            // bytes of one population lattice
     uint32_t n_bnodes, n_links, n_wall;
     int nx, ny, H, nsx, nblocks;
     C tau_inv, G, rho_ref;
@@ -46,52 +47,19 @@ __device__ inline C w9(int i) {
 }
 
 __device__ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-
-struct Res2 {
-    __amdgpu_buffer_rsrc_t fa, fb, tag, l0, qc, F, dm, phi;
-};
-
-// Issue the loads of the nine populations arriving at (c, r) (eq. 5).  A population whose upstream
-// node is solid travelled along a link (x, j) with j its opposite; it is taken as its bounce-back
-// value f~_j(x, t), which gives the node's density at t+1 exactly: eq. 18 returns to f_0 whatever the
-// curved-boundary value of eqs. 16-17 adds to or takes from that population, and that correction is
-// applied just before the collision.  PULL = false reads the node's own populations (the collision
-// that starts a run).  Solid nodes read nothing (their loads return 0).
-template <class S, class C, bool PULL>
-__device__ inline void pull_node(const Res2& R, int nx, int ny, int c, int r, int tg, C f[9]) {
-    const uint32_t n = uint32_t(nx) * uint32_t(ny);
-    const uint32_t x = uint32_t(r) * nx + c;
-    const bool solid = tg < 0;
-    constexpr uint32_t s = sizeof(S);
-    if (PULL) {
-        const uint32_t cm = c == 0 ? nx - 1 : c - 1, cp = c == nx - 1 ? 0 : c + 1;
-        const uint32_t o0 = uint32_t(r) * nx;
-        const uint32_t om = uint32_t(r == 0 ? ny - 1 : r - 1) * nx;
-        const uint32_t op = uint32_t(r == ny - 1 ? 0 : r + 1) * nx;
-        const uint32_t src[9] = {o0 + c, o0 + cm, om + c, o0 + cp, op + c, om + cm, om + cp, op + cp, op + cm};
-        const uint32_t m = tg > 0 ? uint32_t(tg) & 0xFFu : 0u;  // bit j-1: x + e_j is solid
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const bool bounce = i > 0 && ((m >> (kOpp[i] - 1)) & 1u);
-            const uint32_t e = bounce ? uint32_t(kOpp[i]) * n + x : uint32_t(i) * n + src[i];
-            f[i] = Buf<S>::ld(R.fa, solid ? OOB : e * s);
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = Buf<S>::ld(R.fa, solid ? OOB : (uint32_t(i) * n + x) * s);
-    }
-}
+__device__ constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 // Per-workgroup state of the row march.
-template <class S, class C>
+template <class S, class C, int W>
 struct March {
     Args2<S, C> a;
-    Res2 R;
-    C (*s_rho)[STRIP];
-    C (*s_psi)[STRIP];
-    int (*s_tag)[STRIP];
+    __amdgpu_buffer_rsrc_t fa, fb, tag, l0, rec, dm, phi;
+    C (*s_rho)[W];
+    C (*s_psi)[W];
+    int (*s_tag)[W];
     int t, cx, nx, ny, y0, iters;
-    uint32_t n;
+    uint32_t n, xcol_b[3];   // byte offsets of columns x-1, x, x+1 within a row
     bool out_col;
     // pipeline registers: tags and link starts of rows r-2, r-1, r; row r+1 and r+2 in flight
     int tgA, tgB, tgC, l0A, l0B, l0C;
@@ -99,50 +67,83 @@ struct March {
     bool bad;
 };
 
+// Issue the loads of the nine populations arriving at row r of this lane's column (eq. 5).  A
+// population whose upstream node is solid travelled along a link (x, j) with j its opposite; it is
+// taken as its bounce-back value f~_j(x, t), which gives the node's density at t+1 exactly: eq. 18
+// returns to f_0 whatever the curved-boundary value of eqs. 16-17 adds to or takes from that
+// population, and that correction is applied just before the collision.  PULL = false reads the
+// node's own populations (the collision that starts a run).  Solid lanes read whatever lies at
+// their (valid) offsets; their values are never used.
+template <class S, class C, int W, bool PULL>
+__device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, int tg, C f[9]) {
+    constexpr uint32_t s = sizeof(S);
+    const uint32_t ns = M.n * s, rows = uint32_t(M.nx) * s;
+    const uint32_t r0 = uint32_t(r) * rows;
+    const uint32_t rm = uint32_t(r == 0 ? M.ny - 1 : r - 1) * rows;
+    const uint32_t rp = uint32_t(r == M.ny - 1 ? 0 : r + 1) * rows;
+    uint32_t off[9];
+    if (PULL) {
+        // upstream node of direction i: x - e_i
+        const uint32_t rowof[3] = {rp, r0, rm};  // e_y = -1, 0, +1
+#pragma unroll
+        for (int i = 0; i < 9; ++i) off[i] = uint32_t(i) * ns + rowof[kEy[i] + 1] + M.xcol_b[1 - kEx[i]];
+        const uint32_t m = tg > 0 ? uint32_t(tg) & 0xFFu : 0u;  // bit j-1: x + e_j is solid
+        if (__any(m != 0u)) {
+            const uint32_t xo = r0 + M.xcol_b[1];
+#pragma unroll
+            for (int i = 1; i < 9; ++i)
+                if ((m >> (kOpp[i] - 1)) & 1u) off[i] = uint32_t(kOpp[i]) * ns + xo;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) off[i] = uint32_t(i) * ns + r0 + M.xcol_b[1];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = Buf<S>::ld(M.fa, off[i]);
+}
+
 // One row of the march (iteration k, row r = y0 - 2 + k).  fC holds the pulled populations of row
 // r, fB and fA those of rows r-1 and r-2; the populations of row r+1 are issued into fN.
-template <class S, class C, bool PULL>
-__device__ __forceinline__ void march_row(March<S, C>& M, int k, C (&fA)[9], C (&fB)[9], C (&fC)[9], C (&fN)[9]) {
+template <class S, class C, int W, bool PULL>
+__device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], C (&fB)[9], C (&fC)[9], C (&fN)[9]) {
     const Args2<S, C>& a = M.a;
-    const Res2& R = M.R;
     const int t = M.t, nx = M.nx, ny = M.ny;
-    const uint32_t n = M.n;
     constexpr uint32_t s = sizeof(S), sc = sizeof(C);
     const int slot = k & 3;
     M.tgA = M.tgB; M.tgB = M.tgC; M.tgC = M.tg_cur;
     M.l0A = M.l0B; M.l0B = M.l0C; M.l0C = M.l0_cur;
     const int tgA = M.tgA;
-    // ---- link data of row r-2 (collided this iteration), in one batch; lanes without the link
-    // read nothing, and waves without boundary nodes skip the address arithmetic
     const bool coll = k >= 4 && M.out_col && tgA >= 0;
-    const uint32_t mA = (PULL && coll && tgA > 0) ? uint32_t(tgA) & 0xFFu : 0u;
     const int yA = ((M.y0 - 4 + k) % ny + ny) % ny;
-    const uint32_t xA = uint32_t(yA) * nx + M.cx;
+    const uint32_t xAb = (uint32_t(yA) * nx) * s + M.xcol_b[1];  // byte offset of (x, yA) in a plane
+    // ---- link records of row r-2 (collided this iteration), one batch; lanes without the link
+    // read nothing, waves without boundary nodes skip the address arithmetic
+    const uint32_t mA = (PULL && coll && tgA > 0) ? uint32_t(tgA) & 0xFFu : 0u;
     const bool wave_links = PULL && __any(mA != 0u);
-    uint32_t oq[8], oF[8], oo[8];
+    uint32_t orec[8], olo[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) oq[j] = oF[j] = oo[j] = OOB;
+    for (int j = 0; j < 8; ++j) orec[j] = olo[j] = OOB;
     if (wave_links) {
 #pragma unroll
         for (int j = 1; j < 9; ++j) {
             const bool has = (mA >> (j - 1)) & 1u;
             const uint32_t li = uint32_t(M.l0A) + __popc(mA & ((1u << (j - 1)) - 1u));
-            oq[j - 1] = has ? li * 4u : OOB;
-            oF[j - 1] = has ? li * sc : OOB;
-            oo[j - 1] = has ? (uint32_t(kOpp[j]) * n + xA) * s : OOB;
+            orec[j - 1] = has ? li * (2 * sc) : OOB;
+            olo[j - 1] = has ? uint32_t(kOpp[j]) * (M.n * s) + xAb : OOB;
         }
     }
-    uint32_t lw[8];
-    C lF[8], lo[8];
+    C la[8], lF[8], lo[8];
+    if (PULL) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        lw[j] = PULL ? uint32_t(ld_i32(R.qc, oq[j])) : 0u;
-        lF[j] = PULL ? Buf<C>::ld(R.F, oF[j]) : C(0);
-        lo[j] = PULL ? Buf<S>::ld(R.fa, oo[j]) : C(0);
+        for (int j = 0; j < 8; ++j) {
+            la[j] = Buf<C>::ld(M.rec, orec[j]);
+            lF[j] = Buf<C>::ld(M.rec, orec[j] + sc);
+            lo[j] = Buf<S>::ld(M.fa, olo[j]);
+        }
     }
     // wettability factor of a wall node of row r-1 (psi below); other lanes read nothing
     const int tgm = M.s_tag[(k - 1) & 3][t];
-    const double phv = Buf<double>::ld(R.phi, (k >= 1 && tgm <= -2) ? uint32_t(-tgm - 2) * 8u : OOB);
+    const double phv = Buf<double>::ld(M.phi, (k >= 1 && tgm <= -2) ? uint32_t(-tgm - 2) * 8u : OOB);
     // memory operations retire in issue order: the loads used later in this iteration go out
     // before the prefetch of the next row, so waiting for them leaves the prefetch in flight
     __builtin_amdgcn_sched_barrier(0);
@@ -152,9 +153,9 @@ __device__ __forceinline__ void march_row(March<S, C>& M, int k, C (&fA)[9], C (
         M.rr = M.rr1;
         M.rr1 = M.rr == ny - 1 ? 0 : M.rr + 1;
         M.tg_cur = more ? M.tg_nxt : -1;
-        M.l0_cur = ld_i32(R.l0, M.tg_cur > 0 ? uint32_t(M.tg_cur >> 8) * 4u : OOB);
-        pull_node<S, C, PULL>(R, nx, ny, M.cx, M.rr, M.tg_cur, fN);
-        M.tg_nxt = ld_i32(R.tag, k + 2 < M.iters ? (uint32_t(M.rr1) * nx + M.cx) * 4u : OOB);
+        M.l0_cur = ld_i32(M.l0, M.tg_cur > 0 ? uint32_t(M.tg_cur >> 8) * 4u : OOB);
+        pull_row<S, C, W, PULL>(M, M.rr, M.tg_cur, fN);
+        M.tg_nxt = ld_i32(M.tag, k + 2 < M.iters ? uint32_t(M.rr1) * (nx * 4u) + M.xcol_b[1] / s * 4u : OOB);
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- A: density of row r
@@ -162,12 +163,12 @@ __device__ __forceinline__ void march_row(March<S, C>& M, int k, C (&fA)[9], C (
         C sr = C(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) sr += fC[i];
-        M.s_rho[slot][t] = sr + a.rho_ref;
+        M.s_rho[slot][t] = M.tgC >= 0 ? sr + a.rho_ref : C(0);
         M.s_tag[slot][t] = M.tgC;
     }
     __syncthreads();
     // ---- B: psi of row r - 1
-    if (k >= 2 && t >= 1 && t < STRIP - 1) {
+    if (k >= 2 && t >= 1 && t < W - 1) {
         const int s_mid = (k - 1) & 3, s_lo = (k - 2) & 3;
         const int tg = M.s_tag[s_mid][t];
         C rho_n;
@@ -201,34 +202,40 @@ __device__ __forceinline__ void march_row(March<S, C>& M, int k, C (&fA)[9], C (
     for (int i = 0; i < 9; ++i) out[i] = C(0);
 #pragma unroll
     for (int j = 0; j < 8; ++j) Fl[j] = C(0);
+    const uint32_t mk = (coll && tgA > 0) ? uint32_t(tgA) & 0xFFu : 0u;
+    const bool wave_mk = __any(mk != 0u);
     if (k >= 4) {
+        // the node's density at t+1 from the pulled values (eq. 18 keeps it through the link
+        // corrections); the collision hands all of it back, with f_0 taking the rounding
+        C rs_pull = C(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) rs_pull += fA[i];
         if (wave_links) {
-            // eqs. 16-17 on each link (x, j), from the bounce-back-pulled values:
-            //   f~_j(x, t) = fA[opp j], f~_j(x2, t) = fA[j] (x2 = x - e_j fluid), f~_opp(j)(x, t) = lo;
-            // eq. 18: f_0 takes back f~_j(x, t) - f_opp(j)(x, t+1).  Link j rewrites only fA[opp j];
-            // fA[j] is read only when x2 is fluid, so (x, opp j) is no link and fA[j] is still the
-            // pulled value.
+            // eqs. 16-17 on each link (x, j) as t + a (f~_j(x, t) - t), t = other + F_j(x, t):
+            //   eq. 16: a = 2q, other = f~_j(x2, t) = fA[j] (x2 = x - e_j fluid);
+            //   eq. 17: a = 1/(2q) (stored negated), other = f~_opp(j)(x, t) = lo;
+            //   bounce-back: a = 1.
+            // f~_j(x, t) = fA[opp j] (the bounce-back-pulled value).  Eq. 18: f_0 takes back
+            // f~_j(x, t) - f_opp(j)(x, t+1).  Link j rewrites only fA[opp j]; fA[j] is read only when
+            // x2 is fluid, so (x, opp j) is no link and fA[j] is still the pulled value.
             C dsum = C(0);
 #pragma unroll
             for (int j = 1; j < 9; ++j) {
                 const bool has = (mA >> (j - 1)) & 1u;
                 if (!__any(has)) continue;
-                const uint32_t w = lw[j - 1];
-                const int cls = int(w >> CLS_SHIFT);
-                const C q2 = C(w & QMASK) * C(2.0 / 65536.0);  // 2q
-                const C Fj = lF[j - 1];
+                const C sa = la[j - 1];
+                const bool eq17 = sa < C(0);
                 const C fj = fA[kOpp[j]];
-                const C f16 = q2 * fj + (C(1) - q2) * (fA[j] + Fj);
-                const C f17 = (fj + (q2 - C(1)) * (lo[j - 1] + Fj)) * rcp(has && cls == MCB_CLS_EQ17 ? q2 : C(1));
-                const C fin = cls == MCB_CLS_EQ16 ? f16 : (cls == MCB_CLS_EQ17 ? f17 : fj);
+                const C tt = (eq17 ? lo[j - 1] : fA[j]) + lF[j - 1];
+                const C fin = tt + (eq17 ? -sa : sa) * (fj - tt);
                 fA[kOpp[j]] = has ? fin : fj;
                 dsum += has ? fj - fin : C(0);
             }
             fA[0] += dsum;
-            Buf<double>::st(R.dm, mA ? uint32_t(tgA >> 8) * 8u : OOB, double(dsum));
+            Buf<double>::st(M.dm, mA ? uint32_t(tgA >> 8) * 8u : OOB, double(dsum));
         }
         const int sl = (k - 3) & 3, sm = (k - 2) & 3, sh = (k - 1) & 3;
-        const int tc = t < 1 ? 1 : (t > STRIP - 2 ? STRIP - 2 : t);
+        const int tc = t < 1 ? 1 : (t > W - 2 ? W - 2 : t);
         const C p0 = M.s_psi[sm][tc];
         const C pE = M.s_psi[sm][tc + 1], pW = M.s_psi[sm][tc - 1];
         const C pN = M.s_psi[sh][tc], pS = M.s_psi[sl][tc];
@@ -257,84 +264,99 @@ __device__ __forceinline__ void march_row(March<S, C>& M, int k, C (&fA)[9], C (
         const C duu15 = C(1.5) * (dux * sx2 + duy * sy2);
         const C c0 = -(ti * uu15 + duu15);
         const C trs = ti * rs;
-        // rest
-        out[0] = fA[0] * omc + C(4.0 / 9.0) * (trs + rho * c0);
-        // a pair of opposite directions with e.u = eu, e.du = ed, e.(2u + du) = es
-        auto pair = [&](int ip, int im, C w, C eu, C ed, C es, C& Fp, C& Fm) {
+        auto pair = [&](int ip, int im, C w, C eu, C ed, C es) {
             const C sym = ti * C(4.5) * eu * eu + C(4.5) * ed * es + c0;
             const C anti = C(3) * (ti * eu + ed);
             const C base = w * (trs + rho * sym);
             const C wra = w * rho * anti;
             out[ip] = fA[ip] * omc + base + wra;
             out[im] = fA[im] * omc + base - wra;
-            // forcing terms alone, for the link directions
-            const C fs = C(4.5) * ed * es - duu15;
-            const C fa = C(3) * ed;
-            Fp = w * rho * (fs + fa);
-            Fm = w * rho * (fs - fa);
         };
-        C F1, F3, F2, F4, F5, F7, F6, F8;
-        pair(1, 3, C(1.0 / 9.0), ux, dux, sx2, F1, F3);
-        pair(2, 4, C(1.0 / 9.0), uy, duy, sy2, F2, F4);
-        pair(5, 7, C(1.0 / 36.0), ux + uy, dux + duy, sx2 + sy2, F5, F7);
-        pair(6, 8, C(1.0 / 36.0), uy - ux, duy - dux, sy2 - sx2, F6, F8);
-        Fl[0] = F1; Fl[1] = F2; Fl[2] = F3; Fl[3] = F4; Fl[4] = F5; Fl[5] = F6; Fl[6] = F7; Fl[7] = F8;
-    }
+        pair(1, 3, C(1.0 / 9.0), ux, dux, sx2);
+        pair(2, 4, C(1.0 / 9.0), uy, duy, sy2);
+        pair(5, 7, C(1.0 / 36.0), ux + uy, dux + duy, sx2 + sy2);
+        pair(6, 8, C(1.0 / 36.0), uy - ux, duy - dux, sy2 - sx2);
+        // collision conserves mass (the equilibrium and the forcing term of eq. 13 have zero net
+        // mass): set f_0 to the density minus the other eight outputs as stored, so the rounding of
+        // the lattice weights and of the storage format cannot bias the total mass
+        C rest = C(0);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Buf<S>::st(R.fb, coll ? (uint32_t(i) * n + xA) * s : OOB, out[i]);
-    // the link directions keep their forcing term for eqs. 16-17 of the next step
-    const uint32_t mk = (coll && tgA > 0) ? uint32_t(tgA) & 0xFFu : 0u;
-    uint32_t oS[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) oS[j] = OOB;
-    if (__any(mk != 0u)) {
-#pragma unroll
-        for (int j = 1; j < 9; ++j) {
-            const bool has = (mk >> (j - 1)) & 1u;
-            oS[j - 1] = has ? (uint32_t(M.l0A) + __popc(mk & ((1u << (j - 1)) - 1u))) * sc : OOB;
+        for (int i = 1; i < 9; ++i) {
+            out[i] = Buf<S>::round(out[i]);
+            rest += out[i];
+        }
+        out[0] = rs_pull - rest;
+        if (wave_mk) {
+            // forcing terms (eq. 13) of the link directions, kept for eqs. 16-17 of the next step
+            auto fpair = [&](int jp, int jm, C w, C ed, C es) {
+                const C fs = C(4.5) * ed * es - duu15;
+                const C fa3 = C(3) * ed;
+                Fl[jp - 1] = w * rho * (fs + fa3);
+                Fl[jm - 1] = w * rho * (fs - fa3);
+            };
+            fpair(1, 3, C(1.0 / 9.0), dux, sx2);
+            fpair(2, 4, C(1.0 / 9.0), duy, sy2);
+            fpair(5, 7, C(1.0 / 36.0), dux + duy, sx2 + sy2);
+            fpair(6, 8, C(1.0 / 36.0), duy - dux, sy2 - sx2);
         }
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) Buf<C>::st(R.F, oS[j], Fl[j]);
+    for (int i = 0; i < 9; ++i) Buf<S>::st(M.fb, coll ? uint32_t(i) * (M.n * s) + xAb : OOB, out[i]);
+    uint32_t oS[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) oS[j] = OOB;
+    if (wave_mk) {
+#pragma unroll
+        for (int j = 1; j < 9; ++j) {
+            const bool has = (mk >> (j - 1)) & 1u;
+            oS[j - 1] = has ? (uint32_t(M.l0A) + __popc(mk & ((1u << (j - 1)) - 1u))) * (2 * sc) + sc : OOB;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Buf<C>::st(M.rec, oS[j], Fl[j]);
 }
 
-template <class S, class C, bool PULL>
-__global__ __launch_bounds__(STRIP) void k_step2d(Args2<S, C> a) {
+template <class S, class C, int W, bool PULL>
+__global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     // XCD-aware order: consecutive logical tiles go to the same XCD (one L2)
     const int bid = blockIdx.x;
     const int per = a.nblocks >> 3, rem = a.nblocks & 7;
     const int xcd = bid & 7, k8 = bid >> 3;
     const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k8;
     const int sx = logical % a.nsx, sy = logical / a.nsx;
-    __shared__ C s_rho[4][STRIP];
-    __shared__ C s_psi[4][STRIP];
-    __shared__ int s_tag[4][STRIP];
+    __shared__ C s_rho[4][W];
+    __shared__ C s_psi[4][W];
+    __shared__ int s_tag[4][W];
+    constexpr int OUT = W - STRIP_HALO;
+    constexpr uint32_t s = sizeof(S);
 
-    March<S, C> M;
+    March<S, C, W> M;
     M.a = a;
     // lane t covers column x0 - 2 + t; lanes 2 .. 2 + Wv - 1 own the strip's output columns and the
     // two lanes on either side are its halo (psi needs rho two columns out, through the wall nodes)
-    const int x0 = sx * STRIP_OUT;
+    const int x0 = sx * OUT;
     M.y0 = sy * a.H;
-    const int Wv = min(STRIP_OUT, a.nx - x0), Hv = min(a.H, a.ny - M.y0);
+    const int Wv = min(OUT, a.nx - x0), Hv = min(a.H, a.ny - M.y0);
     M.t = threadIdx.x;
     M.nx = a.nx;
     M.ny = a.ny;
     M.n = uint32_t(a.nx) * uint32_t(a.ny);
     M.cx = ((x0 - 2 + M.t) % a.nx + a.nx) % a.nx;
+    M.xcol_b[0] = uint32_t(M.cx == 0 ? a.nx - 1 : M.cx - 1) * s;
+    M.xcol_b[1] = uint32_t(M.cx) * s;
+    M.xcol_b[2] = uint32_t(M.cx == a.nx - 1 ? 0 : M.cx + 1) * s;
     M.out_col = M.t >= 2 && M.t < 2 + Wv;
     M.iters = Hv + 4;
     M.s_rho = s_rho;
     M.s_psi = s_psi;
     M.s_tag = s_tag;
-    M.R.fa = make_res(a.fa, a.f_bytes);
-    M.R.fb = make_res(a.fb, a.f_bytes);
-    M.R.tag = make_res(a.tag, uint64_t(M.n) * 4);
-    M.R.l0 = make_res(a.bn_link0, uint64_t(a.n_bnodes) * 4);
-    M.R.qc = make_res(a.lk_qc, uint64_t(a.n_links) * 4);
-    M.R.F = make_res(a.lk_F, uint64_t(a.n_links) * sizeof(C));
-    M.R.dm = make_res(a.dm, uint64_t(a.n_bnodes) * 8);
-    M.R.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
+    M.fa = make_res(a.fa, uint64_t(9) * M.n * s);
+    M.fb = make_res(a.fb, uint64_t(9) * M.n * s);
+    M.tag = make_res(a.tag, uint64_t(M.n) * 4);
+    M.l0 = make_res(a.bn_link0, uint64_t(a.n_bnodes) * 4);
+    M.rec = make_res(a.lk_rec, uint64_t(a.n_links) * 2 * sizeof(C));
+    M.dm = make_res(a.dm, uint64_t(a.n_bnodes) * 8);
+    M.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
     M.tgA = M.tgB = M.tgC = -1;
     M.l0A = M.l0B = M.l0C = 0;
     M.bad = false;
@@ -344,47 +366,47 @@ __global__ __launch_bounds__(STRIP) void k_step2d(Args2<S, C> a) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) f0[i] = f1[i] = f2[i] = C(0);
     M.rr = ((M.y0 - 2) % a.ny + a.ny) % a.ny;
-    M.tg_cur = ld_i32(M.R.tag, (uint32_t(M.rr) * a.nx + M.cx) * 4u);
+    M.tg_cur = ld_i32(M.tag, (uint32_t(M.rr) * a.nx + M.cx) * 4u);
     M.rr1 = M.rr == a.ny - 1 ? 0 : M.rr + 1;
-    M.tg_nxt = ld_i32(M.R.tag, (uint32_t(M.rr1) * a.nx + M.cx) * 4u);
-    M.l0_cur = ld_i32(M.R.l0, M.tg_cur > 0 ? uint32_t(M.tg_cur >> 8) * 4u : OOB);
-    pull_node<S, C, PULL>(M.R, a.nx, a.ny, M.cx, M.rr, M.tg_cur, f3);
+    M.tg_nxt = ld_i32(M.tag, (uint32_t(M.rr1) * a.nx + M.cx) * 4u);
+    M.l0_cur = ld_i32(M.l0, M.tg_cur > 0 ? uint32_t(M.tg_cur >> 8) * 4u : OOB);
+    pull_row<S, C, W, PULL>(M, M.rr, M.tg_cur, f3);
     int k = 0;
     for (; k + 4 <= M.iters; k += 4) {
-        march_row<S, C, PULL>(M, k + 0, f0, f1, f3, f2);
-        march_row<S, C, PULL>(M, k + 1, f1, f3, f2, f0);
-        march_row<S, C, PULL>(M, k + 2, f3, f2, f0, f1);
-        march_row<S, C, PULL>(M, k + 3, f2, f0, f1, f3);
+        march_row<S, C, W, PULL>(M, k + 0, f0, f1, f3, f2);
+        march_row<S, C, W, PULL>(M, k + 1, f1, f3, f2, f0);
+        march_row<S, C, W, PULL>(M, k + 2, f3, f2, f0, f1);
+        march_row<S, C, W, PULL>(M, k + 3, f2, f0, f1, f3);
     }
     const int left = M.iters - k;  // uniform
-    if (left > 0) march_row<S, C, PULL>(M, k + 0, f0, f1, f3, f2);
-    if (left > 1) march_row<S, C, PULL>(M, k + 1, f1, f3, f2, f0);
-    if (left > 2) march_row<S, C, PULL>(M, k + 2, f3, f2, f0, f1);
+    if (left > 0) march_row<S, C, W, PULL>(M, k + 0, f0, f1, f3, f2);
+    if (left > 1) march_row<S, C, W, PULL>(M, k + 1, f1, f3, f2, f0);
+    if (left > 2) march_row<S, C, W, PULL>(M, k + 2, f3, f2, f0, f1);
     if (M.bad) atomicOr(&a.flags[FLAG_DOMAIN], 1);
 }
 
-template <class S, class C>
-hipError_t launch_step2d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
+template <class S, class C, int W>
+hipError_t launch_w(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
     Args2<S, C> a;
     a.fa = static_cast<const S*>(fcur);
     a.fb = static_cast<S*>(fnext);
     a.tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
     a.bn_link0 = reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0);
-    a.lk_qc = reinterpret_cast<const uint32_t*>(c->lk + c->L.lk_qc);
-    a.lk_F = reinterpret_cast<C*>(c->lk + c->L.lk_F);
+    a.lk_rec = reinterpret_cast<C*>(c->lk + c->L.lk_rec);
     a.dm = reinterpret_cast<double*>(c->lk + c->L.dm);
     a.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
     a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
-    a.f_bytes = uint64_t(c->g.Q) * c->g.N * sizeof(S);
     a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
     a.n_links = uint32_t(c->n_links > 0 ? c->n_links : 0);
     a.n_wall = uint32_t(c->n_wall > 0 ? c->n_wall : 0);
     a.nx = c->p.nx;
     a.ny = c->p.ny;
-    a.nsx = (a.nx + STRIP_OUT - 1) / STRIP_OUT;
+    constexpr int OUT = W - STRIP_HALO;
+    a.nsx = (a.nx + OUT - 1) / OUT;
     // segment height: long segments amortise the four halo rows; short ones fill the chip
+    const int64_t target = W == 64 ? 8192 : 2048;
     int H = 64;
-    while (H > 8 && int64_t(a.nsx) * ((a.ny + H - 1) / H) < 2048) H >>= 1;
+    while (H > 8 && int64_t(a.nsx) * ((a.ny + H - 1) / H) < target) H >>= 1;
     a.H = H;
     a.nblocks = a.nsx * ((a.ny + H - 1) / H);
     a.tau_inv = C(1.0 / c->p.tau);
@@ -395,10 +417,17 @@ hipError_t launch_step2d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
     a.eos.b4 = C(c->p.eos_b / 4.0);
     a.eos.two_over_G = C(2.0 / c->p.G);
     if (pull)
-        hipLaunchKernelGGL((k_step2d<S, C, true>), dim3(a.nblocks), dim3(STRIP), 0, c->stream, a);
+        hipLaunchKernelGGL((k_step2d<S, C, W, true>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
     else
-        hipLaunchKernelGGL((k_step2d<S, C, false>), dim3(a.nblocks), dim3(STRIP), 0, c->stream, a);
+        hipLaunchKernelGGL((k_step2d<S, C, W, false>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
     return hipGetLastError();
+}
+
+template <class S, class C>
+hipError_t launch_step2d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
+    // one-wave strips keep small lattices busy; four-wave strips waste fewer halo lanes
+    if (c->g.N > (int64_t(1) << 21)) return launch_w<S, C, 256>(c, fcur, fnext, pull);
+    return launch_w<S, C, 64>(c, fcur, fnext, pull);
 }
 
 }  // namespace
