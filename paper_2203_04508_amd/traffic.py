@@ -1,0 +1,116 @@
+"""Measured HBM traffic of the fused step kernel, calibrated against a plain copy.
+
+Two phases:
+
+``python -m paper_2203_04508_amd.traffic run --workload c2 --precision f32s --steps 5``
+    sets up the workload, runs a few steps, then copies a 1 GiB torch tensor (a plain device copy
+    of known size: 1 GiB read, 1 GiB written).  Run it under rocprofv3 once with
+    ``--pmc FETCH_SIZE`` and once with ``--pmc WRITE_SIZE``.
+
+``python -m paper_2203_04508_amd.traffic summarize --fetch-db A.db --write-db B.db --workload c2 --precision f32s``
+    reads both databases, scales each counter of the step kernel by (known copy bytes / what the
+    same counter reads for the copy kernel), and writes ``profiles/traffic_<workload>_<precision>.json``
+    and a short text summary next to it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sqlite3
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30
+
+
+def run(args):
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2203_04508_amd import mcb, workloads as W
+
+    wl = W.make(args.workload)
+    rr = wl.rho_v if args.precision != "f64" else 0.0
+    lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=args.precision, rho_ref=rr)
+    lat.set_geometry(wl.shapes)
+    lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
+    lat.init_equilibrium(wl.rho0())
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"[traffic] {args.workload} {args.precision}: {args.steps} steps and one {COPY_BYTES} B copy done", flush=True)
+
+
+def _counter(db, counter):
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select kernel_name, dispatch_id, sum(value) from counters_collection where counter_name = ? "
+        "group by kernel_name, dispatch_id", (counter,)).fetchall()
+    con.close()
+    return rows
+
+
+def _per_dispatch(rows, match):
+    vals = [v for k, d, v in rows if match(k)]
+    return sum(vals) / len(vals) if vals else None, len(vals)
+
+
+def _largest(rows, match):
+    vals = [v for k, d, v in rows if match(k)]
+    return max(vals) if vals else None, len(vals)
+
+
+def summarize(args):
+    out = {"workload": args.workload, "precision": args.precision, "copy_bytes": COPY_BYTES}
+    lines = []
+    is_step = lambda k: "k_step2d" in k or "k_step3d" in k
+    # the device copy of COPY_BYTES is the largest copy dispatch of the run
+    is_copy = lambda k: "copybuffer" in k.lower()
+    for counter, db, key in (("FETCH_SIZE", args.fetch_db, "read"), ("WRITE_SIZE", args.write_db, "write")):
+        rows = _counter(db, counter)
+        step_kib, nstep = _per_dispatch(rows, lambda k: is_step(k) and "true" in k)
+        copy_kib, ncopy = _largest(rows, is_copy)
+        factor = COPY_BYTES / (copy_kib * 1024.0)
+        out[f"{key}_counter_kib_per_dispatch"] = step_kib
+        out[f"{key}_copy_counter_kib"] = copy_kib
+        out[f"{key}_scale"] = factor
+        out[f"{key}_bytes_per_launch"] = step_kib * 1024.0 * factor
+        lines.append(f"{counter}: step kernel {step_kib:.0f} KiB/dispatch over {nstep} dispatches; "
+                     f"the {COPY_BYTES} B copy reads {copy_kib:.0f} KiB on this counter -> scale {factor:.4f}; "
+                     f"calibrated {out[f'{key}_bytes_per_launch'] / 1e6:.1f} MB per launch")
+    out["bytes_per_launch"] = out["read_bytes_per_launch"] + out["write_bytes_per_launch"]
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    base = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}")
+    json.dump(out, open(base + ".json", "w"), indent=1)
+    with open(base + ".txt", "w") as fh:
+        fh.write(f"HBM traffic of the fused step kernel, workload {args.workload}, storage {args.precision}\n")
+        fh.write(f"commands: {args.commands}\n" if args.commands else "")
+        fh.write("\n".join(lines) + "\n")
+        fh.write(f"total calibrated bytes per launch: {out['bytes_per_launch'] / 1e6:.1f} MB\n")
+    print(open(base + ".txt").read())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--workload", default="c2")
+    r.add_argument("--precision", default="f32s")
+    r.add_argument("--steps", type=int, default=5)
+    s = sub.add_parser("summarize")
+    s.add_argument("--fetch-db", required=True)
+    s.add_argument("--write-db", required=True)
+    s.add_argument("--workload", default="c2")
+    s.add_argument("--precision", default="f32s")
+    s.add_argument("--commands", default="")
+    a = ap.parse_args()
+    run(a) if a.cmd == "run" else summarize(a)
+
+
+if __name__ == "__main__":
+    main()

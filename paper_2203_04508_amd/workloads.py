@@ -13,8 +13,8 @@ Shape record, int64 x 8 (units of 2^-16 lattice spacings):
 Workloads (the paper's own runs use 500x300 to 600x1200 boxes, drop radii 50-100 and an
 interface width of 10, Sec. 4; these synthetic cases keep that structure at other sizes):
     c0  64^2 D2Q9, one off-lattice cylinder (r 12.3 at (32.4, 20.7)), one drop r 10 resting on it
-    c1  1024^2 D2Q9, 300 random circles r in U(8, 24), 40 drops r in U(15, 40), 0.6 T_c, tau 1
-    c2  4096^2 D2Q9, the c1 generator scaled x4 in area: 4800 circles, 640 drops
+    c1  1024^2 D2Q9, 300 random circles r in U(8, 24), 40 drops r in U(15, 40), 0.7 T_c, tau 1
+    c2  4096^2 D2Q9, the c1 generator scaled x4 in area: 4800 circles, 640 drops, 0.7 T_c, tau 1
     c3  512^2 D2Q9, a slab with 60 half-circles r in U(4, 12) on top, one drop r 40
     c4  256^3 D3Q19, 400 random spheres r in U(6, 14), 200 drops r in U(8, 16)
 """
@@ -186,8 +186,10 @@ def make(name: str) -> Workload:
         shapes = np.array([ball(c, r, g) for g, (c, r) in enumerate(zip(cs, rs))], np.int64)
         drops = _drops(rng, 40 * scale * scale, (n, n, 1), 2, 15.0, 40.0)
         phi = rng.uniform(*PHI_RANGE, len(rs))
-        # tau = 1: at 0.6 T_c (density ratio ~ 700 with this model) tau = 0.8 is unstable
-        return Workload(name, 2, (n, n, 1), 1.0, 0.60, shapes, drops, phi, 10000 if name == "c1" else 5000)
+        # 0.7 T_c and tau = 1: with single-relaxation-time collision the pseudopotential runs at
+        # 0.6 or 0.65 T_c (density ratio ~700 / ~250) end in psi domain errors within a few
+        # thousand steps on these geometries; 0.7 T_c (ratio ~65, the c0 temperature) stays stable
+        return Workload(name, 2, (n, n, 1), 1.0, 0.70, shapes, drops, phi, 10000 if name == "c1" else 5000)
     if name == "c3":
         rng = np.random.Generator(np.random.PCG64(3))
         top = 10.35
