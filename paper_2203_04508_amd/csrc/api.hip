@@ -27,6 +27,7 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.fa = take(Q * N * s);
     L.fb = take(Q * N * s);
     L.tag = take(4 * N);
+    L.nmask = take(p.dim == 3 ? 4 * N : 0);  // 3-D: link bits of each boundary node (bit j-1: x + e_j solid)
     L.solid = take(N);
     L.scratch = take(8 * N * (2 + p.dim));
     L.blocksums = take(8 * (3 * nblk + 3));
@@ -42,7 +43,9 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.bn_link0 = take(4 * nb);
     L.dm = take(8 * nb);
     L.lk_qc = take(4 * nl);
-    L.lk_rec = take(2 * cb * nl);  // per link: signed interpolation coefficient, forcing term
+    // per link: signed interpolation coefficient and forcing term; 2-D in link order, 3-D in fixed
+    // slots (boundary node, direction)
+    L.lk_rec = take(p.dim == 2 ? 2 * cb * nl : 2 * cb * Q3_LINKS * nb);
     L.wl_node = take(4 * nw);
     L.wl_phi = take(8 * nw);
     L.links_bytes = (nb + nl + nw) > 0 ? o : 0;
@@ -276,6 +279,8 @@ mcb_status mcb_build_links(mcb_ctx* c, int32_t phase, int64_t* n_links, int64_t*
         HIPCHK(hipStreamSynchronize(c->stream));
         if (tot[0] >= (int64_t(1) << 31)) return fail(c, MCB_ENOTSUP, "too many links");
         if (c->g.dim == 2 && tot[1] >= (int64_t(1) << 23)) return fail(c, MCB_ENOTSUP, "2-D tags hold at most 2^23 boundary nodes");
+        if (c->g.dim == 3 && tot[1] * Q3_LINKS * 2 * compute_bytes(c->p.precision) > int64_t(0xFFFFFE00u))
+            return fail(c, MCB_ENOTSUP, "3-D link records exceed 4 GiB");
         c->n_links = tot[0];
         c->n_bnodes = tot[1];
         c->n_wall = tot[2];

@@ -175,6 +175,7 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t* bs, int64_t nblk) {
 
 struct FillOut {
     int32_t* tag;
+    uint32_t* nmask;  // 3-D only
     int32_t* bn_node;
     uint32_t* bn_mask;
     int32_t* bn_link0;
@@ -199,6 +200,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_fill(GridDev g, int L, const uin
         if (mask) {
             // 2-D: boundary index and the 8 link bits share the tag; 3-D: boundary index + 1
             o.tag[x] = g.dim == 2 ? int32_t((bpre << 8) | (mask >> 1)) : int32_t(bpre + 1);
+            if (g.dim == 3) o.nmask[x] = mask >> 1;
             o.bn_node[bpre] = int32_t(x);
             o.bn_mask[bpre] = mask;
             o.bn_link0[bpre] = int32_t(lpre);
@@ -207,12 +209,15 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_fill(GridDev g, int L, const uin
             for (int k = 0; k < nl; ++k) o.lk_qc[lpre + k] = NOHIT;
         } else {
             o.tag[x] = 0;
+            if (g.dim == 3) o.nmask[x] = 0u;
         }
     } else if ((v >> 40) & 1) {
+        if (g.dim == 3) o.nmask[x] = 0u;
         o.tag[x] = int32_t(-2 - wpre);
         o.wl_node[wpre] = int32_t(x);
         o.wl_phi[wpre] = 1.0;
     } else {
+        if (g.dim == 3) o.nmask[x] = 0u;
         o.tag[x] = -1;
     }
 }
@@ -339,12 +344,13 @@ __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict_
             lk_qc[l] = q | (uint32_t(cls) << CLS_SHIFT);
             const double q2 = double(q) * (2.0 / 65536.0);
             const double a = cls == MCB_CLS_EQ16 ? q2 : (cls == MCB_CLS_EQ17 ? -1.0 / q2 : 1.0);
+            const int64_t slot = g.dim == 2 ? l : bi * Q3_LINKS + (i - 1);
             if (rec_double) {
-                static_cast<double*>(rec)[2 * l] = a;
-                static_cast<double*>(rec)[2 * l + 1] = 0.0;
+                static_cast<double*>(rec)[2 * slot] = a;
+                static_cast<double*>(rec)[2 * slot + 1] = 0.0;
             } else {
-                static_cast<float*>(rec)[2 * l] = float(a);
-                static_cast<float*>(rec)[2 * l + 1] = 0.0f;
+                static_cast<float*>(rec)[2 * slot] = float(a);
+                static_cast<float*>(rec)[2 * slot + 1] = 0.0f;
             }
             ++l;
         }
@@ -391,6 +397,7 @@ hipError_t geom_fill(mcb_ctx* c) {
     const int64_t nblk = (c->g.N + SCAN_BLOCK - 1) / SCAN_BLOCK;
     FillOut o;
     o.tag = reinterpret_cast<int32_t*>(c->lat + c->L.tag);
+    o.nmask = reinterpret_cast<uint32_t*>(c->lat + c->L.nmask);
     o.bn_node = reinterpret_cast<int32_t*>(c->lk + c->L.bn_node);
     o.bn_mask = reinterpret_cast<uint32_t*>(c->lk + c->L.bn_mask);
     o.bn_link0 = reinterpret_cast<int32_t*>(c->lk + c->L.bn_link0);

@@ -16,7 +16,8 @@ constexpr uint32_t NOHIT = 0xFFFFFFFFu;
 constexpr uint32_t QMASK = 0x1FFFFu;      // q_fixed in bits 0..16 of a packed link word
 constexpr int CLS_SHIFT = 30;             // link class in bits 30..31
 
-constexpr int STRIP_HALO = 4;             // 2-D step: halo lanes per strip (two columns on each side)
+constexpr int STRIP_HALO = 4;            // 2-D step: halo lanes per strip (two columns on each side)
+constexpr int Q3_LINKS = 18;              // 3-D: fixed link-record slots per boundary node
 constexpr int SCAN_BLOCK = 256;           // geometry scan granularity
 constexpr int MON_BLOCKS = 1024;          // monitor partial sums
 constexpr int MON_FIELDS = 8;             // M, Jx, Jy, Jz, dM, n_nan, spare, spare
@@ -48,7 +49,7 @@ struct GridDev {
 // Byte offsets of the sub-buffers carved out of the two caller-owned arenas.
 struct Layout {
     // lattice arena
-    int64_t fa, fb, tag, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
+    int64_t fa, fb, tag, nmask, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
     // links arena
     int64_t bn_node, bn_mask, bn_link0, dm, lk_qc, lk_rec, wl_node, wl_phi, links_bytes;
 };

@@ -92,8 +92,6 @@ def _compare_geometry(mcb, dim, dims, shapes):
 
 @pytest.mark.parametrize("name,dim,dims,shapes", GEOM_CASES, ids=[c[0] for c in GEOM_CASES])
 def test_geometry_bitexact_small(mcb, name, dim, dims, shapes):
-    if dim == 3:
-        pytest.skip("D3Q19 step not built yet; geometry covered in 3-D once it is")
     banner(f"geometry {name}")
     _compare_geometry(mcb, dim, dims, np.array(shapes, np.int64))
 
