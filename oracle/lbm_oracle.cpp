@@ -120,6 +120,7 @@ inline Dual operator/(const Dual& a, double b) { Dual r(a.v / b); for (int k = 0
 inline Dual operator/(double a, const Dual& b) { return Dual(a) / b; }
 inline Dual& operator+=(Dual& a, const Dual& b) { a = a + b; return a; }
 inline Dual sqrt(const Dual& a) { double s = std::sqrt(a.v); Dual r(s); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] / (2.0 * s); return r; }
+inline Dual tanh(const Dual& a) { double t = std::tanh(a.v); Dual r(t); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] * (1.0 - t * t); return r; }
 inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
 inline bool finite(double x) { return std::isfinite(x); }
@@ -481,6 +482,40 @@ int build_sim(Sim<R>* S, const uint8_t* solid, const int64_t* lk_node, const int
     return 0;
 }
 
+// Observables of the differentiation growth, from the stored state f~(x, T) (density
+// rho(x) = sum_i f~_i(x, T) over fluid nodes):
+//   kind 0  centre of mass in x, sum_x X (rho - rho_v) / sum_x (rho - rho_v), X the node's x index;
+//           prm[0] = rho_v
+//   kind 1  smooth wetted length, sum over links (x1, j) of |e_j| (1 + tanh((rho(x1) - rho_mid) / delta)) / 2;
+//           prm[0] = rho_mid, prm[1] = delta
+//   kind 2  total mass, sum_x rho
+template <class R>
+R loss_of(const Sim<R>& S, int kind, const double* prm) {
+    const int64_t N = S.g.N;
+    const int Q = S.L.Q;
+    R a = 0.0, b = 0.0;
+    for (int64_t x = 0; x < N; ++x) {
+        if (!S.fluid(x)) continue;
+        R r = 0.0;
+        for (int i = 0; i < Q; ++i) r = r + S.ft[i * N + x];
+        if (kind == 0) {
+            const double X = double(x % S.g.n[0]);
+            a = a + X * (r - prm[0]);
+            b = b + (r - prm[0]);
+        } else if (kind == 1) {
+            using std::tanh;
+            for (int64_t l = S.link0[x]; l < S.link0[x + 1]; ++l) {
+                const int* e = S.L.e[S.lk_dir[l]];
+                const double len = std::sqrt(double(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]));
+                a = a + len * 0.5 * (1.0 + tanh((r - prm[0]) / prm[1]));
+            }
+        } else {
+            a = a + r;
+        }
+    }
+    return kind == 0 ? a / b : a;
+}
+
 struct Handle {
     int kind;  // 0 double, 1 dual
     void* sim;
@@ -752,6 +787,85 @@ double or_sim_mass(void* h) {
 }
 
 double or_sim_dm_last(void* h) { return static_cast<Sim<double>*>(h)->dm_last; }
+
+int or_sim_loss(void* h, int kind, const double* prm, double* out) {
+    if (kind < 0 || kind > 2) return -1;
+    *out = loss_of(*static_cast<Sim<double>*>(h), kind, prm);
+    return 0;
+}
+
+// ---- forward-mode derivatives: dual numbers carrying KD tangent directions ----
+// The wettability factors carry the tangents, every step propagates them exactly (to rounding),
+// and a loss returns its value and its KD directional derivatives: the reference gradient for
+// the hand-written reverse mode, obtained with no transposition at all.
+int or_dual_kd(void) { return KD; }
+
+void* or_dsim_create(const or_params* P, const uint8_t* solid, const int64_t* lk_node, const int32_t* lk_dir,
+                     const uint32_t* lk_q, int64_t nlinks) {
+    if (P->dim != 2 && P->dim != 3) return nullptr;
+    if (!(P->tau > 0.5) || !(P->G < 0.0)) return nullptr;
+    auto* S = new Sim<Dual>(*P);
+    if (build_sim(S, solid, lk_node, lk_dir, lk_q, nlinks) != 0) { delete S; return nullptr; }
+    return S;
+}
+
+void or_dsim_destroy(void* h) { delete static_cast<Sim<Dual>*>(h); }
+
+// phi[w] with tangents dphi[k * n_wall + w], k < KD (dphi nullable: no tangents)
+int or_dsim_set_phi(void* h, const double* phi, const double* dphi) {
+    auto* S = static_cast<Sim<Dual>*>(h);
+    const size_t nw = S->phi.size();
+    for (size_t w = 0; w < nw; ++w) {
+        if (!(phi[w] > 0.0)) return -1;
+        Dual v(phi[w]);
+        if (dphi) for (int k = 0; k < KD; ++k) v.d[k] = dphi[k * nw + w];
+        S->phi[w] = v;
+    }
+    return 0;
+}
+
+static int dfinish(Sim<Dual>* S) {
+    if (S->n_domain) return -4;
+    for (int64_t x = 0; x < S->g.N; ++x)
+        if (S->fluid(x))
+            for (int i = 0; i < S->L.Q; ++i)
+                if (!finite(S->ft[i * S->g.N + x])) return -5;
+    return 0;
+}
+
+int or_dsim_init_eq(void* h, const double* rho0) {
+    auto* S = static_cast<Sim<Dual>*>(h);
+    const int64_t N = S->g.N;
+    std::vector<Dual> f(size_t(S->L.Q) * N, Dual(0.0));
+    for (int64_t x = 0; x < N; ++x) {
+        if (!S->fluid(x)) continue;
+        Dual uu[3] = {0.0, 0.0, 0.0}, fe[MAXQ];
+        equilibrium(S->L, Dual(rho0[x]), uu, fe);
+        for (int i = 0; i < S->L.Q; ++i) f[i * N + x] = fe[i];
+    }
+    S->n_domain = 0;
+    S->collide(f);
+    return dfinish(S);
+}
+
+int or_dsim_step(void* h, int64_t nsteps) {
+    auto* S = static_cast<Sim<Dual>*>(h);
+    S->n_domain = 0;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        S->step();
+        if (S->n_domain) return -4;
+    }
+    return dfinish(S);
+}
+
+// out[0] = loss value, out[1 + k] = its derivative along tangent k
+int or_dsim_loss(void* h, int kind, const double* prm, double* out) {
+    if (kind < 0 || kind > 2) return -1;
+    Dual L = loss_of(*static_cast<Sim<Dual>*>(h), kind, prm);
+    out[0] = L.v;
+    for (int k = 0; k < KD; ++k) out[1 + k] = L.d[k];
+    return 0;
+}
 
 // wall nodes (ascending linear index) and their eq. 15 density rho_ave(s) at time t, before the
 // wettability factor

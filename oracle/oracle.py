@@ -98,6 +98,20 @@ def lib():
         L.or_sim_dm_last.restype = C.c_double
         L.or_sim_wall_rho.argtypes = [vp, vp, vp]
         L.or_sim_wall_rho.restype = C.c_int64
+        L.or_sim_loss.argtypes = [vp, C.c_int, vp, vp]
+        L.or_sim_loss.restype = C.c_int
+        L.or_dual_kd.restype = C.c_int
+        L.or_dsim_create.argtypes = [P, vp, vp, vp, vp, C.c_int64]
+        L.or_dsim_create.restype = vp
+        L.or_dsim_destroy.argtypes = [vp]
+        L.or_dsim_set_phi.argtypes = [vp, vp, vp]
+        L.or_dsim_set_phi.restype = C.c_int
+        L.or_dsim_init_eq.argtypes = [vp, vp]
+        L.or_dsim_init_eq.restype = C.c_int
+        L.or_dsim_step.argtypes = [vp, C.c_int64]
+        L.or_dsim_step.restype = C.c_int
+        L.or_dsim_loss.argtypes = [vp, C.c_int, vp, vp]
+        L.or_dsim_loss.restype = C.c_int
         _lib = L
     return _lib
 
@@ -279,3 +293,72 @@ def sim_from_shapes(params: Params, shapes):
     solid = classify(params, shapes)
     node, d, cls, q = links(params, shapes, solid)
     return Sim(params, solid, node, d, q), (solid, node, d, cls, q)
+
+
+# ---------------------------------------------------------------------------- losses and derivatives
+LOSS_COM_X, LOSS_WETTED_LENGTH, LOSS_TOTAL_MASS = 0, 1, 2
+
+
+def sim_loss(sim: Sim, kind: int, prm=(0.0, 1.0)) -> float:
+    """Loss of the stored state f~(T) (kinds: 0 centre of mass in x, 1 smooth wetted length,
+    2 total mass)."""
+    prm = np.ascontiguousarray(prm, np.float64)
+    out = np.zeros(1)
+    Sim._check(lib().or_sim_loss(sim.h, kind, _p(prm), _p(out)), "loss")
+    return float(out[0])
+
+
+def dual_kd() -> int:
+    return lib().or_dual_kd()
+
+
+class DualSim:
+    """The same simulation in forward-mode dual numbers: the wettability factors carry up to
+    KD tangent directions, and loss() returns the loss with its directional derivatives."""
+
+    def __init__(self, params: Params, solid, lk_node, lk_dir, lk_q):
+        self.params = params
+        self.N = params.nx * params.ny * (params.nz if params.dim == 3 else 1)
+        self._keep = [np.ascontiguousarray(solid, np.uint8), np.ascontiguousarray(lk_node, np.int64),
+                      np.ascontiguousarray(lk_dir, np.int32), np.ascontiguousarray(lk_q, np.uint32)]
+        s, n, d, q = self._keep
+        self.h = lib().or_dsim_create(C.byref(params), _p(s), _p(n), _p(d), _p(q), len(n))
+        if not self.h:
+            raise OracleError("or_dsim_create rejected the parameters or the link list")
+        self.kd = dual_kd()
+
+    def close(self):
+        if self.h:
+            lib().or_dsim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_phi(self, phi, directions=None):
+        """phi: (n_wall,); directions: up to KD tangent vectors, shape (m, n_wall)."""
+        phi = np.ascontiguousarray(phi, np.float64)
+        d = None
+        if directions is not None:
+            directions = np.atleast_2d(np.asarray(directions, np.float64))
+            assert directions.shape[0] <= self.kd and directions.shape[1] == len(phi)
+            d = np.zeros((self.kd, len(phi)))
+            d[: directions.shape[0]] = directions
+        Sim._check(lib().or_dsim_set_phi(self.h, _p(phi), _p(d) if d is not None else None), "set_phi")
+
+    def init_eq(self, rho0):
+        rho0 = np.ascontiguousarray(rho0, np.float64).reshape(-1)
+        Sim._check(lib().or_dsim_init_eq(self.h, _p(rho0)), "init_eq")
+
+    def step(self, n=1):
+        Sim._check(lib().or_dsim_step(self.h, n), "step")
+
+    def loss(self, kind: int, prm=(0.0, 1.0)):
+        """(value, array of KD directional derivatives)."""
+        prm = np.ascontiguousarray(prm, np.float64)
+        out = np.zeros(1 + self.kd)
+        Sim._check(lib().or_dsim_loss(self.h, kind, _p(prm), _p(out)), "loss")
+        return float(out[0]), out[1:].copy()
