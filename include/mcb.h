@@ -205,6 +205,41 @@ mcb_status mcb_timing(mcb_ctx* ctx, int32_t enable);
  * enabled (synchronises). */
 mcb_status mcb_timing_report(mcb_ctx* ctx, double* ms, int64_t* launches);
 
+/* ---- differentiation: reverse mode with checkpoints ---------------------------------------- */
+/* Gradient of a loss of the state after nsteps steps from the equilibrium start rho0 (the same
+ * start as mcb_init_equilibrium with u = 0) with respect to the wettability factor phi of every
+ * wall node, by the hand-written discrete adjoint of the step.  The forward pass stores the state
+ * every k steps; the reverse pass recomputes each k-step segment from its checkpoint with the
+ * fused step kernel and applies the transposed step backwards through it, then the transposed
+ * first collision.  The adjoint arithmetic is FP64 in every storage precision (for the shifted
+ * storages it is the adjoint of the FP64 step linearised at the stored states).
+ *
+ * Losses of the stored state f~(T), rho(x) = sum_i f~_i(x, T) on fluid nodes:
+ *   MCB_LOSS_COM_X           sum_x X (rho - prm[0]) / sum_x (rho - prm[0]), X the node's x index
+ *                            (prm[0] = rho_v: the centre of mass of the liquid)
+ *   MCB_LOSS_WETTED_LENGTH   sum over links (x1, j) of |e_j| (1 + tanh((rho(x1) - prm[0]) / prm[1])) / 2
+ *   MCB_LOSS_TOTAL_MASS      sum_x rho (its gradient is zero: eq. 18 conserves mass for any phi)
+ */
+enum { MCB_LOSS_COM_X = 0, MCB_LOSS_WETTED_LENGTH = 1, MCB_LOSS_TOTAL_MASS = 2 };
+
+/* Device bytes of the reverse-mode arena for nsteps >= 0 steps with a checkpoint every k >= 1
+ * steps (after mcb_build_links(FILL)). */
+mcb_status mcb_adj_required_bytes(mcb_ctx* ctx, int64_t nsteps, int64_t k, int64_t* bytes);
+
+/* Binds the caller-owned reverse-mode arena (device memory, at least the required bytes, 256-byte
+ * aligned); it must stay alive while mcb_adj_forward / mcb_adj_backward use it. */
+mcb_status mcb_adj_bind(mcb_ctx* ctx, void* device_buffer, int64_t bytes);
+
+/* Equilibrium start from rho0 (N doubles), nsteps steps with checkpoints, and the loss of the final
+ * state in *value.  The context's state is then that final state (t = nsteps).  Synchronises. */
+mcb_status mcb_adj_forward(mcb_ctx* ctx, const double* rho0, int64_t nsteps, int64_t k, int32_t loss_kind,
+                           const double* loss_prm, double* value);
+
+/* dphi[w] = dloss * d loss / d phi[w] (n_wall doubles, wall nodes in ascending linear index) for
+ * the last mcb_adj_forward; the state must not have been changed since (MCB_ESTATE otherwise).
+ * The context's state is left as it was.  Synchronises. */
+mcb_status mcb_adj_backward(mcb_ctx* ctx, double dloss, double* dphi);
+
 #ifdef __cplusplus
 }
 #endif

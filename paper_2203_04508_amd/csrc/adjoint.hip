@@ -1,0 +1,498 @@
+// Reverse mode of the step: the hand-written discrete adjoint of the map from the post-collision
+// state of time t to that of time t+1, and of the first collision from the equilibrium start.
+// Together with checkpointed recomputation of the forward states (api layer) it gives the exact
+// gradient (to rounding) of a loss of the final state with respect to the wettability factor phi
+// of every wall node.
+//
+// State.  The forward step reads, besides the populations g(t), the forcing term F_j(x, t) of
+// eq. 13 on every fluid-solid link (eqs. 16-17 use it one step later), so the state is the pair
+// (g, R) with R the per-link forcing terms; its adjoint is (lambda, lambda_R).
+//
+// Forward step, per fluid node x (f = g + w rho_ref in the shifted storages):
+//   streaming, eq. 5:     p_i(x) = f_i(x - e_i)                           (x - e_i fluid)
+//   link (x, j), i = opp j: p_i(x) = B_j = c1 f_j(x) + c2 o + c3 R_j(x)     (eqs. 16-17)
+//        eq. 16: c1 = 2q, c2 = c3 = 1 - 2q, o = f_j(x - e_j); bounce-back: c1 = 1, c2 = c3 = 0;
+//        eq. 17: c1 = 1/(2q), c2 = c3 = 1 - 1/(2q), o = f_opp(j)(x)
+//   eq. 18:               p_0(x) += sum_links (f_j(x) - B_j)
+//   collision, with E_i(rho, m) = w_i (rho + 3 e_i.m + (4.5 (e_i.m)^2 - 1.5 m.m) / rho), the
+//   equilibrium of eq. 14 written with the momentum m = rho u:
+//        g'_i = p_i (1 - 1/tau) + (1/tau - 1) E_i(rho, j) + E_i(rho, j + F),   R'_i = E_i(rho, j + F) - E_i(rho, j)
+//   rho = sum p, j = sum p e, F = -G psi(x) sum_k w^_k psi(x + e_k) e_k, psi = psi(rho) on fluid
+//   nodes and psi(phi_s rho_ave(s)) on wall nodes s, rho_ave the eq. 15 weighted mean of the
+//   fluid neighbours' densities.
+// The kernels below apply the transposes of these maps in reverse order; every scatter of the
+// forward map becomes a gather, so each output is written by exactly one thread and the result is
+// deterministic.
+#include "kernels_common.h"
+
+namespace mcb {
+namespace {
+
+template <class C>
+__device__ inline C wgt(int L, int i) {
+    if (L == 0) return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
+    return i == 0 ? C(1.0 / 3.0) : (i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0));
+}
+// interaction-force stencil weights, sum_i w^_i e_i e_i^T = I
+__device__ inline double wforce(int L, int i) {
+    if (L == 0) return i < 5 ? 1.0 / 3.0 : 1.0 / 12.0;
+    return i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
+}
+
+__device__ inline int64_t nbr(const GridDev& g, int L, int64_t x, int i, int sign) {
+    const int cx = int(x % g.nx), cy = int((x / g.nx) % g.ny), cz = int(x / (int64_t(g.nx) * g.ny));
+    return wrap1(cx + sign * c_ex[L][i], g.nx) +
+           int64_t(g.nx) * (wrap1(cy + sign * c_ey[L][i], g.ny) + int64_t(g.ny) * wrap1(cz + sign * c_ez[L][i], g.nz));
+}
+
+struct AdjDev {
+    GridDev g;
+    int L;                       // 0: D2Q9, 1: D3Q19
+    const int32_t* tag;          // node tags (see the step kernels)
+    const uint32_t* nmask;       // 3-D link bits
+    const int32_t* bn_link0;     // 2-D first link of each boundary node
+    const double* phi;           // wettability factor per wall node
+    double tau, G, RT, a, b4, rho_ref;
+};
+
+// link bits (bit j-1: x + e_j solid) of a fluid node, and the record slot of its link j
+__device__ inline uint32_t link_bits(const AdjDev& A, int64_t x, int tg) {
+    if (tg <= 0) return 0u;
+    return A.L == 0 ? uint32_t(tg) & 0xFFu : A.nmask[x];
+}
+__device__ inline int64_t link_slot(const AdjDev& A, int tg, uint32_t mask, int j) {
+    if (A.L == 0) return int64_t(A.bn_link0[tg >> 8]) + __popc(mask & ((1u << (j - 1)) - 1u));
+    return int64_t(tg - 1) * Q3_LINKS + (j - 1);
+}
+
+// Carnahan-Starling pressure and its derivative
+__device__ inline void p_eos(const AdjDev& A, double rho, double* p, double* dp) {
+    const double eta = rho * A.b4, om = 1.0 - eta;
+    const double h = 1.0 + eta + eta * eta - eta * eta * eta, dh = 1.0 + 2.0 * eta - 3.0 * eta * eta;
+    const double om3 = om * om * om;
+    *p = rho * A.RT * h / om3 - A.a * rho * rho;
+    *dp = A.RT * (h / om3 + rho * A.b4 * (dh / om3 + 3.0 * h / (om3 * om))) - 2.0 * A.a * rho;
+}
+// psi(rho) = sqrt(2 (p - rho/3) / G) and d psi / d rho
+__device__ inline void psi_d(const AdjDev& A, double rho, double* psi, double* dpsi) {
+    double p, dp;
+    p_eos(A, rho, &p, &dp);
+    const double arg = 2.0 * (p - rho / 3.0) / A.G;
+    const double s = arg > 0.0 ? sqrt(arg) : 0.0;
+    *psi = s;
+    *dpsi = s > 0.0 ? (dp - 1.0 / 3.0) / (A.G * s) : 0.0;
+}
+
+template <class S>
+__device__ inline double ldf(const S* g, const AdjDev& A, int i, int64_t x) {
+    return double(ld<S, float>(reinterpret_cast<const S*>(g), i * A.g.N + x)) + wgt<double>(A.L, i) * A.rho_ref;
+}
+template <>
+__device__ inline double ldf<double>(const double* g, const AdjDev& A, int i, int64_t x) {
+    return g[i * A.g.N + x] + wgt<double>(A.L, i) * A.rho_ref;
+}
+
+// ---- 1: pre-collision populations p and density of time t+1 (recomputed from (g, R) of time t);
+// pull = 0: p = f^eq(rho0, 0), the first collision's input
+template <class S, class RC>
+__global__ void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __restrict__ rec, int pull,
+                            const double* __restrict__ rho0, double* __restrict__ p, double* __restrict__ rho) {
+    const int Q = A.g.Q;
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < A.g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int tg = A.tag[x];
+        if (tg < 0) continue;
+        double v[19];
+        if (!pull) {
+            for (int i = 0; i < Q; ++i) v[i] = wgt<double>(A.L, i) * rho0[x];
+        } else {
+            for (int i = 0; i < Q; ++i) v[i] = ldf<S>(gt, A, i, nbr(A.g, A.L, x, i, -1));
+            const uint32_t m = link_bits(A, x, tg);
+            double dm = 0.0;
+            for (int j = 1; j < Q; ++j) {
+                if (!((m >> (j - 1)) & 1u)) continue;
+                const int64_t sl = link_slot(A, tg, m, j);
+                const double a = double(rec[2 * sl]), Fj = double(rec[2 * sl + 1]);
+                const double fj = ldf<S>(gt, A, j, x);
+                const double o = a < 0.0 ? ldf<S>(gt, A, c_opp[A.L][j], x)
+                                         : (A.tag[nbr(A.g, A.L, x, j, -1)] >= 0 ? ldf<S>(gt, A, j, nbr(A.g, A.L, x, j, -1)) : 0.0);
+                const double c1 = fabs(a), c2 = 1.0 - c1;
+                const double B = c1 * fj + c2 * (o + Fj);
+                v[c_opp[A.L][j]] = B;
+                dm += fj - B;
+            }
+            v[0] += dm;
+        }
+        double r = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            p[i * A.g.N + x] = v[i];
+            r += v[i];
+        }
+        rho[x] = r;
+    }
+}
+
+// ---- 2: psi, d psi / d rho; wall nodes also keep rho_ave and the weight sum of eq. 15
+__global__ void k_psi(AdjDev A, const double* __restrict__ rho, double* __restrict__ psi, double* __restrict__ dpsi,
+                      double* __restrict__ rave, double* __restrict__ den) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < A.g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int tg = A.tag[x];
+        double s = 0.0, ds = 0.0;
+        if (tg >= 0) {
+            psi_d(A, rho[x], &s, &ds);
+        } else if (tg <= -2) {
+            double num = 0.0, dn = 0.0;
+            for (int i = 1; i < A.g.Q; ++i) {
+                const int64_t y = nbr(A.g, A.L, x, i, +1);
+                if (A.tag[y] >= 0) {
+                    num += wgt<double>(A.L, i) * rho[y];
+                    dn += wgt<double>(A.L, i);
+                }
+            }
+            const double ra = num / dn;
+            psi_d(A, A.phi[-tg - 2] * ra, &s, &ds);
+            rave[x] = ra;
+            den[x] = dn;
+        }
+        psi[x] = s;
+        dpsi[x] = ds;
+    }
+}
+
+// ---- 3: transposed collision.  lam1 = adjoint of g'(t+1), lamR1 = adjoint of R(t+1) (per link
+// slot).  Gives pbar = adjoint of p through the direct and (rho, j) dependences, and Fbar.
+__global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double* __restrict__ rho,
+                            const double* __restrict__ psi, const double* __restrict__ lam1,
+                            const double* __restrict__ lamR1, double* __restrict__ pbar, double* __restrict__ Fbar,
+                            double* __restrict__ Fv) {
+    const int Q = A.g.Q, L = A.L;
+    const int64_t N = A.g.N;
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int tg = A.tag[x];
+        if (tg < 0) continue;
+        const double r = rho[x];
+        double j[3] = {0, 0, 0}, S[3] = {0, 0, 0};
+        for (int i = 0; i < Q; ++i) {
+            const double v = p[i * N + x];
+            j[0] += v * c_ex[L][i];
+            j[1] += v * c_ey[L][i];
+            j[2] += v * c_ez[L][i];
+        }
+        for (int k = 1; k < Q; ++k) {
+            const double w = wforce(L, k) * psi[nbr(A.g, L, x, k, +1)];
+            S[0] += w * c_ex[L][k];
+            S[1] += w * c_ey[L][k];
+            S[2] += w * c_ez[L][k];
+        }
+        const double gp = -A.G * psi[x];
+        const double F[3] = {gp * S[0], gp * S[1], gp * S[2]};
+        const double m1[3] = {j[0] + F[0], j[1] + F[1], j[2] + F[2]};
+        const double mm0 = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+        const double mm1 = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
+        const uint32_t msk = link_bits(A, x, tg);
+        double rb = 0.0, jb[3] = {0, 0, 0}, Fb[3] = {0, 0, 0};
+        const double ir = 1.0 / r, ir2 = ir * ir;
+        for (int i = 0; i < Q; ++i) {
+            const double ab = lam1[i * N + x];
+            double rr = 0.0;
+            if (i >= 1 && ((msk >> (i - 1)) & 1u)) rr = lamR1[link_slot(A, tg, msk, i)];
+            const double al = ab + rr;                         // on E_i(rho, j + F)
+            const double be = ab * (1.0 / A.tau - 1.0) - rr;   // on E_i(rho, j)
+            const double w = wgt<double>(L, i);
+            const double e[3] = {double(c_ex[L][i]), double(c_ey[L][i]), double(c_ez[L][i])};
+            const double em0 = e[0] * j[0] + e[1] * j[1] + e[2] * j[2];
+            const double em1 = e[0] * m1[0] + e[1] * m1[1] + e[2] * m1[2];
+            // d E / d rho and d E / d m at (rho, m)
+            rb += al * w * (1.0 - (4.5 * em1 * em1 - 1.5 * mm1) * ir2) + be * w * (1.0 - (4.5 * em0 * em0 - 1.5 * mm0) * ir2);
+            for (int k = 0; k < 3; ++k) {
+                const double d1 = al * w * (3.0 * e[k] + (9.0 * em1 * e[k] - 3.0 * m1[k]) * ir);
+                const double d0 = be * w * (3.0 * e[k] + (9.0 * em0 * e[k] - 3.0 * j[k]) * ir);
+                jb[k] += d1 + d0;
+                Fb[k] += d1;
+            }
+        }
+        for (int i = 0; i < Q; ++i)
+            pbar[i * N + x] = lam1[i * N + x] * (1.0 - 1.0 / A.tau) + rb + c_ex[L][i] * jb[0] + c_ey[L][i] * jb[1] + c_ez[L][i] * jb[2];
+        for (int k = 0; k < 3; ++k) {
+            Fbar[k * N + x] = Fb[k];
+            Fv[k * N + x] = F[k];
+        }
+    }
+}
+
+// ---- 4: transposed force stencil and psi.  Fluid y: rbar = psi'(rho) psibar; wall s:
+// rho_w-bar = psi'(rho_w) psibar, dphi += rho_w-bar rho_ave, qbar = rho_w-bar phi / den (to be
+// spread over the fluid neighbours with their lattice weights).
+__global__ void k_psi_T(AdjDev A, const double* __restrict__ psi, const double* __restrict__ dpsi,
+                        const double* __restrict__ rave, const double* __restrict__ den, const double* __restrict__ Fbar,
+                        double* __restrict__ rbar, double* __restrict__ qbar, double* __restrict__ dphi) {
+    const int Q = A.g.Q, L = A.L;
+    const int64_t N = A.g.N;
+    for (int64_t y = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; y < N; y += int64_t(gridDim.x) * blockDim.x) {
+        const int tg = A.tag[y];
+        if (tg == -1) continue;
+        double pb = 0.0;
+        if (tg >= 0) {
+            // own force: F(y) = -G psi(y) S(y)
+            double S[3] = {0, 0, 0};
+            for (int k = 1; k < Q; ++k) {
+                const double w = wforce(L, k) * psi[nbr(A.g, L, y, k, +1)];
+                S[0] += w * c_ex[L][k];
+                S[1] += w * c_ey[L][k];
+                S[2] += w * c_ez[L][k];
+            }
+            pb += -A.G * (Fbar[y] * S[0] + Fbar[N + y] * S[1] + Fbar[2 * N + y] * S[2]);
+        }
+        // the fluid neighbours x = y - e_k whose force uses psi(y) = psi(x + e_k)
+        for (int k = 1; k < Q; ++k) {
+            const int64_t x = nbr(A.g, L, y, k, -1);
+            if (A.tag[x] < 0) continue;
+            const double fe = Fbar[x] * c_ex[L][k] + Fbar[N + x] * c_ey[L][k] + Fbar[2 * N + x] * c_ez[L][k];
+            pb += -A.G * psi[x] * wforce(L, k) * fe;
+        }
+        if (tg >= 0) {
+            rbar[y] = dpsi[y] * pb;
+        } else {
+            const int w = -tg - 2;
+            const double rwb = dpsi[y] * pb;
+            dphi[w] += rwb * rave[y];
+            qbar[y] = rwb * A.phi[w] / den[y];
+        }
+    }
+}
+
+// ---- 5: density adjoint into pbar (rho = sum_i p_i)
+__global__ void k_rho_T(AdjDev A, const double* __restrict__ rbar, const double* __restrict__ qbar, double* __restrict__ pbar) {
+    const int Q = A.g.Q, L = A.L;
+    const int64_t N = A.g.N;
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x) {
+        if (A.tag[x] < 0) continue;
+        double rb = rbar[x];
+        // wall nodes s = x - e_k average rho(x) = rho(s + e_k) with weight w_k
+        for (int k = 1; k < Q; ++k) {
+            const int64_t s = nbr(A.g, L, x, k, -1);
+            if (A.tag[s] <= -2) rb += wgt<double>(L, k) * qbar[s];
+        }
+        for (int i = 0; i < Q; ++i) pbar[i * N + x] += rb;
+    }
+}
+
+// ---- 6: transposed streaming, boundary condition and eq. 18: lambda(t) and lambda_R(t).
+// With Bbar_j(x) = pbar_opp(j)(x) - pbar_0(x) the adjoint of a boundary value, f_i(y) is used by
+//   the pull into p_i(y + e_i) (y + e_i fluid);
+//   its own link (y, i): c1 Bbar_i(y) + pbar_0(y) (eq. 18 adds f_i(y) to p_0);
+//   eq. 16 of the link (y + e_i, i) as o = f_i(x - e_i): c2 Bbar_i(y + e_i);
+//   eq. 17 of the link (y, opp i) as o = f_i(y): c2 Bbar_opp(i)(y);
+// and R_j(y) by its own link only: c3 Bbar_j(y).
+template <class RC>
+__global__ void k_stream_T(AdjDev A, const RC* __restrict__ rec, const double* __restrict__ pbar, double* __restrict__ lam0,
+                           double* __restrict__ lamR0) {
+    const int Q = A.g.Q, L = A.L;
+    const int64_t N = A.g.N;
+    for (int64_t y = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; y < N; y += int64_t(gridDim.x) * blockDim.x) {
+        const int tg = A.tag[y];
+        if (tg < 0) {
+            for (int i = 0; i < Q; ++i) lam0[i * N + y] = 0.0;
+            continue;
+        }
+        const uint32_t m = link_bits(A, y, tg);
+        const double pb0 = pbar[y];
+        for (int i = 0; i < Q; ++i) {
+            double acc = 0.0;
+            if (i == 0) {
+                acc = pb0;
+            } else if ((m >> (i - 1)) & 1u) {
+                const int64_t sl = link_slot(A, tg, m, i);
+                const double c1 = fabs(double(rec[2 * sl]));
+                const double Bb = pbar[c_opp[L][i] * N + y] - pb0;
+                acc = c1 * Bb + pb0;
+                lamR0[sl] = (1.0 - c1) * Bb;
+            } else {
+                const int64_t x = nbr(A.g, L, y, i, +1);
+                acc = pbar[i * N + x];
+                const int tx = A.tag[x];
+                const uint32_t mx = link_bits(A, x, tx);
+                if ((mx >> (i - 1)) & 1u) {
+                    const double ax = double(rec[2 * link_slot(A, tx, mx, i)]);
+                    if (ax > 0.0) acc += (1.0 - ax) * (pbar[c_opp[L][i] * N + x] - pbar[x]);
+                }
+            }
+            const int io = c_opp[L][i];
+            if (i >= 1 && ((m >> (io - 1)) & 1u)) {
+                const double ao = double(rec[2 * link_slot(A, tg, m, io)]);
+                if (ao < 0.0) acc += (1.0 + ao) * (pbar[i * N + y] - pb0);
+            }
+            lam0[i * N + y] = acc;
+        }
+    }
+}
+
+// ---- loss of the final state: deterministic two-pass reduction, then its gradient
+__device__ inline double wave_sum(double v) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+template <class S>
+__device__ inline double node_rho(const AdjDev& A, const S* g, int64_t x) {
+    double r = 0.0;
+    for (int i = 0; i < A.g.Q; ++i) r += ldf<S>(g, A, i, x);
+    return r;
+}
+
+__device__ inline double link_len(int L, int j) {
+    const int n2 = c_ex[L][j] * c_ex[L][j] + c_ey[L][j] * c_ey[L][j] + c_ez[L][j] * c_ez[L][j];
+    return n2 == 1 ? 1.0 : (n2 == 2 ? 1.4142135623730951 : 1.7320508075688772);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_loss_partial(AdjDev A, const S* __restrict__ g, int kind, double p0, double p1,
+                                                      double* __restrict__ part) {
+    double a = 0.0, b = 0.0;
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < A.g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int tg = A.tag[x];
+        if (tg < 0) continue;
+        const double r = node_rho<S>(A, g, x);
+        if (kind == 0) {
+            a += double(x % A.g.nx) * (r - p0);
+            b += r - p0;
+        } else if (kind == 1) {
+            const uint32_t m = link_bits(A, x, tg);
+            for (int j = 1; j < A.g.Q; ++j)
+                if ((m >> (j - 1)) & 1u) a += link_len(A.L, j) * 0.5 * (1.0 + tanh((r - p0) / p1));
+        } else {
+            a += r;
+        }
+    }
+    __shared__ double sa[4], sb[4];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sa[0] + sa[1] + sa[2] + sa[3];
+        part[gridDim.x + blockIdx.x] = sb[0] + sb[1] + sb[2] + sb[3];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double sa[4], sb[4];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        a += part[k];
+        b += part[n + k];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = sa[0] + sa[1] + sa[2] + sa[3];
+        out[1] = sb[0] + sb[1] + sb[2] + sb[3];
+    }
+}
+
+// lambda(T) = dloss * d loss / d g(T) (every population of a node enters through its density);
+// lambda_R(T) = 0.  sums = {a, b} of the reduction (kind 0: loss = a / b).
+template <class S>
+__global__ void k_loss_grad(AdjDev A, const S* __restrict__ g, int kind, double p0, double p1, const double* __restrict__ sums,
+                            double dloss, double* __restrict__ lam) {
+    const int64_t N = A.g.N;
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int tg = A.tag[x];
+        double d = 0.0;
+        if (tg >= 0) {
+            if (kind == 0) {
+                d = (double(x % A.g.nx) - sums[0] / sums[1]) / sums[1];
+            } else if (kind == 1) {
+                const double th = tanh((node_rho<S>(A, g, x) - p0) / p1);
+                const uint32_t m = link_bits(A, x, tg);
+                for (int j = 1; j < A.g.Q; ++j)
+                    if ((m >> (j - 1)) & 1u) d += link_len(A.L, j) * 0.5 * (1.0 - th * th) / p1;
+            } else {
+                d = 1.0;
+            }
+        }
+        for (int i = 0; i < A.g.Q; ++i) lam[i * N + x] = dloss * d;
+    }
+}
+
+inline unsigned grid_for(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    return unsigned(b < 1 ? 1 : b);
+}
+
+AdjDev make_dev(const mcb_ctx* c) {
+    AdjDev A;
+    A.g = c->g;
+    A.L = c->g.dim == 2 ? 0 : 1;
+    A.tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
+    A.nmask = reinterpret_cast<const uint32_t*>(c->lat + c->L.nmask);
+    A.bn_link0 = reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0);
+    A.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
+    A.tau = c->p.tau;
+    A.G = c->p.G;
+    A.RT = c->p.eos_R * c->p.eos_T;
+    A.a = c->p.eos_a;
+    A.b4 = c->p.eos_b / 4.0;
+    A.rho_ref = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
+    return A;
+}
+
+template <class S, class RC>
+hipError_t adj_step_t(mcb_ctx* c, const AdjWork& w, const void* gt, const void* rec, int pull, const double* lam1,
+                      const double* lamR1, double* lam0, double* lamR0) {
+    const AdjDev A = make_dev(c);
+    const unsigned G = grid_for(c->g.N);
+    hipLaunchKernelGGL((k_recompute<S, RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt),
+                       static_cast<const RC*>(rec), pull, w.rho0, w.p, w.rho);
+    hipLaunchKernelGGL(k_psi, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.dpsi, w.rave, w.den);
+    hipLaunchKernelGGL(k_collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar, w.Fv);
+    hipLaunchKernelGGL(k_psi_T, dim3(G), dim3(256), 0, c->stream, A, w.psi, w.dpsi, w.rave, w.den, w.Fbar, w.rbar, w.qbar, w.dphi);
+    if (pull) {
+        hipLaunchKernelGGL(k_rho_T, dim3(G), dim3(256), 0, c->stream, A, w.rbar, w.qbar, w.pbar);
+        hipLaunchKernelGGL((k_stream_T<RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const RC*>(rec), w.pbar, lam0, lamR0);
+    }
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t adj_loss_t(mcb_ctx* c, const AdjWork& w, const void* g, int kind, const double* prm, double dloss, double* lam) {
+    const AdjDev A = make_dev(c);
+    hipLaunchKernelGGL((k_loss_partial<S>), dim3(MON_BLOCKS), dim3(256), 0, c->stream, A, static_cast<const S*>(g), kind, prm[0],
+                       prm[1], w.part);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, c->stream, w.part, MON_BLOCKS, w.sums);
+    if (lam)
+        hipLaunchKernelGGL((k_loss_grad<S>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, A, static_cast<const S*>(g), kind,
+                           prm[0], prm[1], w.sums, dloss, lam);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t adj_step(mcb_ctx* c, const AdjWork& w, const void* gt, const void* rec, int pull, const double* lam1,
+                    const double* lamR1, double* lam0, double* lamR0) {
+    switch (c->p.precision) {
+        case MCB_F64: return adj_step_t<double, double>(c, w, gt, rec, pull, lam1, lamR1, lam0, lamR0);
+        case MCB_F32S: return adj_step_t<float, float>(c, w, gt, rec, pull, lam1, lamR1, lam0, lamR0);
+        default: return adj_step_t<__half, float>(c, w, gt, rec, pull, lam1, lamR1, lam0, lamR0);
+    }
+}
+
+hipError_t adj_loss(mcb_ctx* c, const AdjWork& w, const void* g, int kind, const double* prm, double dloss, double* lam) {
+    switch (c->p.precision) {
+        case MCB_F64: return adj_loss_t<double>(c, w, g, kind, prm, dloss, lam);
+        case MCB_F32S: return adj_loss_t<float>(c, w, g, kind, prm, dloss, lam);
+        default: return adj_loss_t<__half>(c, w, g, kind, prm, dloss, lam);
+    }
+}
+
+}  // namespace mcb

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/mcb.h: argument checks, arena layout, call order,
 // stream handling and error reporting.  Device work lives in geometry.hip, step2d.hip,
 // step3d.hip and monitor.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -53,6 +54,46 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
 }
 
 hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
+
+AdjPlan adj_plan(const mcb_ctx* c, int64_t nsteps, int64_t k) {
+    AdjPlan a{};
+    const int64_t N = c->g.N, Q = c->g.Q;
+    const int64_t cb = compute_bytes(c->p.precision);
+    a.nsteps = nsteps;
+    a.k = k;
+    a.nck = nsteps == 0 ? 1 : (nsteps + k - 1) / k;
+    a.state_b = align256(Q * N * storage_bytes(c->p.precision));
+    a.nslots = c->g.dim == 2 ? c->n_links : Q3_LINKS * c->n_bnodes;
+    a.rec_b = align256(2 * cb * a.nslots);
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { const int64_t at = o; o = align256(o + bytes); return at; };
+    a.rho0 = take(8 * N);
+    a.ck = take(a.nck * a.state_b);
+    a.ck_rec = take(a.nck * a.rec_b);
+    a.seg = take((k - 1) * a.state_b);
+    a.seg_rec = take((k - 1) * a.rec_b);
+    a.final_rec = take(a.rec_b);
+    for (int b = 0; b < 2; ++b) {
+        a.lam[b] = take(8 * Q * N);
+        a.lamR[b] = take(8 * (a.nslots > 0 ? a.nslots : 1));
+    }
+    a.p = take(8 * Q * N);
+    a.pbar = take(8 * Q * N);
+    a.rho = take(8 * N);
+    a.psi = take(8 * N);
+    a.dpsi = take(8 * N);
+    a.rave = take(8 * N);
+    a.den = take(8 * N);
+    a.rbar = take(8 * N);
+    a.qbar = take(8 * N);
+    a.Fbar = take(8 * 3 * N);
+    a.Fv = take(8 * 3 * N);
+    a.dphi = take(8 * (c->n_wall > 0 ? c->n_wall : 1));
+    a.part = take(8 * 2 * MON_BLOCKS);
+    a.sums = take(8 * 2);
+    a.bytes = o;
+    return a;
+}
 
 }  // namespace mcb
 
@@ -455,6 +496,136 @@ mcb_status mcb_step(mcb_ctx* c, int64_t n) {
         ++c->t;
     }
     return MCB_OK;
+}
+
+static AdjWork adj_work(mcb_ctx* c) {
+    const AdjPlan& a = c->ap;
+    auto d = [&](int64_t off) { return reinterpret_cast<double*>(c->adj + off); };
+    AdjWork w;
+    w.rho0 = d(a.rho0);
+    w.p = d(a.p);
+    w.pbar = d(a.pbar);
+    w.rho = d(a.rho);
+    w.psi = d(a.psi);
+    w.dpsi = d(a.dpsi);
+    w.rave = d(a.rave);
+    w.den = d(a.den);
+    w.rbar = d(a.rbar);
+    w.qbar = d(a.qbar);
+    w.Fbar = d(a.Fbar);
+    w.Fv = d(a.Fv);
+    w.dphi = d(a.dphi);
+    w.part = d(a.part);
+    w.sums = d(a.sums);
+    return w;
+}
+
+mcb_status mcb_adj_required_bytes(mcb_ctx* c, int64_t nsteps, int64_t k, int64_t* bytes) {
+    if (!c || !bytes) return MCB_EINVAL;
+    if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
+    if (nsteps < 0 || k < 1) return fail(c, MCB_EINVAL, "need nsteps >= 0 and k >= 1");
+    *bytes = adj_plan(c, nsteps, k).bytes;
+    return MCB_OK;
+}
+
+mcb_status mcb_adj_bind(mcb_ctx* c, void* buf, int64_t bytes) {
+    if (!c) return MCB_EINVAL;
+    if (!buf || bytes <= 0 || (reinterpret_cast<uintptr_t>(buf) & 255)) return fail(c, MCB_EINVAL, "bad reverse-mode arena");
+    c->adj = static_cast<char*>(buf);
+    c->adj_bytes = bytes;
+    c->adj_ready = false;
+    return MCB_OK;
+}
+
+mcb_status mcb_adj_forward(mcb_ctx* c, const double* rho0, int64_t nsteps, int64_t k, int32_t kind, const double* prm,
+                           double* value) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
+    if (!rho0 || !prm || !value) return fail(c, MCB_EINVAL, "missing argument");
+    if (nsteps < 0 || k < 1) return fail(c, MCB_EINVAL, "need nsteps >= 0 and k >= 1");
+    if (kind < MCB_LOSS_COM_X || kind > MCB_LOSS_TOTAL_MASS) return fail(c, MCB_EINVAL, "unknown loss");
+    if (kind == MCB_LOSS_WETTED_LENGTH && !(prm[1] > 0.0)) return fail(c, MCB_EINVAL, "wetted length needs delta > 0");
+    const AdjPlan a = adj_plan(c, nsteps, k);
+    if (!c->adj || c->adj_bytes < a.bytes) return fail(c, MCB_ESIZE, "reverse-mode arena needs %lld bytes", (long long)a.bytes);
+    c->adj_ready = false;
+    c->ap = a;
+    mcb_status st = mcb_init_equilibrium(c, rho0, nullptr);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(c->adj + a.rho0, rho0, 8 * c->g.N, hipMemcpyHostToDevice, c->stream));
+    char* rec = c->lk + c->L.lk_rec;
+    const int64_t rec_used = 2 * compute_bytes(c->p.precision) * a.nslots;
+    for (int64_t t = 0;; ++t) {
+        if (t % k == 0 && t / k < a.nck) {
+            HIPCHK(hipMemcpyAsync(c->adj + a.ck + (t / k) * a.state_b, fcur(c), c->g.Q * c->g.N * storage_bytes(c->p.precision),
+                                  hipMemcpyDeviceToDevice, c->stream));
+            if (rec_used > 0)
+                HIPCHK(hipMemcpyAsync(c->adj + a.ck_rec + (t / k) * a.rec_b, rec, rec_used, hipMemcpyDeviceToDevice, c->stream));
+        }
+        if (t == nsteps) break;
+        HIPCHK(step_fused(c, fcur(c), fnext(c), true));
+        c->swapped = !c->swapped;
+        ++c->t;
+    }
+    if (rec_used > 0) HIPCHK(hipMemcpyAsync(c->adj + a.final_rec, rec, rec_used, hipMemcpyDeviceToDevice, c->stream));
+    const AdjWork w = adj_work(c);
+    HIPCHK(adj_loss(c, w, fcur(c), kind, prm, 0.0, nullptr));
+    double sums[2];
+    HIPCHK(hipMemcpyAsync(sums, w.sums, sizeof sums, hipMemcpyDeviceToHost, c->stream));
+    st = check_flags(c, nullptr);
+    if (st) return st;
+    *value = kind == MCB_LOSS_COM_X ? sums[0] / sums[1] : sums[0];
+    c->adj_kind = kind;
+    c->adj_prm[0] = prm[0];
+    c->adj_prm[1] = prm[1];
+    c->adj_t_end = c->t;
+    c->adj_ready = true;
+    return MCB_OK;
+}
+
+mcb_status mcb_adj_backward(mcb_ctx* c, double dloss, double* dphi) {
+    if (!c) return MCB_EINVAL;
+    if (!c->adj_ready || c->t != c->adj_t_end) return fail(c, MCB_ESTATE, "no matching mcb_adj_forward");
+    if (c->n_wall > 0 && !dphi) return fail(c, MCB_EINVAL, "dphi missing");
+    const AdjPlan& a = c->ap;
+    const AdjWork w = adj_work(c);
+    const int64_t rec_used = 2 * compute_bytes(c->p.precision) * a.nslots;
+    char* rec = c->lk + c->L.lk_rec;
+    auto lam = [&](int b) { return reinterpret_cast<double*>(c->adj + a.lam[b]); };
+    auto lamR = [&](int b) { return reinterpret_cast<double*>(c->adj + a.lamR[b]); };
+    mcb_status st = clear_flags(c);
+    if (st) return st;
+    HIPCHK(hipMemsetAsync(w.dphi, 0, 8 * (c->n_wall > 0 ? c->n_wall : 1), c->stream));
+    int cur = 0;
+    HIPCHK(hipMemsetAsync(lamR(cur), 0, 8 * (a.nslots > 0 ? a.nslots : 1), c->stream));
+    HIPCHK(adj_loss(c, w, fcur(c), c->adj_kind, c->adj_prm, dloss, lam(cur)));
+    for (int64_t sg = a.nck - 1; sg >= 0; --sg) {
+        const int64_t t0 = sg * a.k, t1 = std::min(a.nsteps, t0 + a.k);
+        if (t0 >= t1) continue;
+        char* ck = c->adj + a.ck + sg * a.state_b;
+        char* ckr = c->adj + a.ck_rec + sg * a.rec_b;
+        // recompute the states t0+1 .. t1-1 of the segment (the step kernel updates the forcing
+        // terms of the link records in place; each step's records are kept beside its state)
+        if (rec_used > 0) HIPCHK(hipMemcpyAsync(rec, ckr, rec_used, hipMemcpyDeviceToDevice, c->stream));
+        const char* prev = ck;
+        for (int64_t t = t0 + 1; t < t1; ++t) {
+            char* dst = c->adj + a.seg + (t - t0 - 1) * a.state_b;
+            HIPCHK(step_fused(c, prev, dst, true));
+            if (rec_used > 0)
+                HIPCHK(hipMemcpyAsync(c->adj + a.seg_rec + (t - t0 - 1) * a.rec_b, rec, rec_used, hipMemcpyDeviceToDevice, c->stream));
+            prev = dst;
+        }
+        for (int64_t t = t1 - 1; t >= t0; --t) {
+            const void* gt = t == t0 ? static_cast<const void*>(ck) : c->adj + a.seg + (t - t0 - 1) * a.state_b;
+            const void* rt = t == t0 ? static_cast<const void*>(ckr) : c->adj + a.seg_rec + (t - t0 - 1) * a.rec_b;
+            HIPCHK(adj_step(c, w, gt, rt, 1, lam(cur), lamR(cur), lam(1 - cur), lamR(1 - cur)));
+            cur = 1 - cur;
+        }
+    }
+    // the first collision, from f^eq(rho0, 0)
+    HIPCHK(adj_step(c, w, nullptr, nullptr, 0, lam(cur), lamR(cur), nullptr, nullptr));
+    if (c->n_wall > 0) HIPCHK(hipMemcpyAsync(dphi, w.dphi, 8 * c->n_wall, hipMemcpyDeviceToHost, c->stream));
+    if (rec_used > 0) HIPCHK(hipMemcpyAsync(rec, c->adj + a.final_rec, rec_used, hipMemcpyDeviceToDevice, c->stream));
+    return check_flags(c, nullptr);
 }
 
 mcb_status mcb_timing(mcb_ctx* c, int32_t enable) {

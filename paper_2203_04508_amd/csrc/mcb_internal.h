@@ -55,6 +55,20 @@ struct Layout {
 };
 
 Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64_t n_bnodes, int64_t n_wall);
+
+// Reverse-mode arena (caller-owned): byte offsets of checkpoints, the recomputed segment, the
+// adjoint states and the work arrays of the transposed step.
+struct AdjPlan {
+    int64_t nsteps, k, nck, state_b, rec_b, nslots;
+    int64_t rho0, ck, ck_rec, seg, seg_rec, final_rec, lam[2], lamR[2];
+    int64_t p, pbar, rho, psi, dpsi, rave, den, rbar, qbar, Fbar, Fv, dphi, part, sums, bytes;
+};
+
+// device pointers of the work arrays
+struct AdjWork {
+    const double* rho0;
+    double *p, *pbar, *rho, *psi, *dpsi, *rave, *den, *rbar, *qbar, *Fbar, *Fv, *dphi, *part, *sums;
+};
 int64_t storage_bytes(int precision);
 int64_t compute_bytes(int precision);
 
@@ -87,6 +101,14 @@ struct mcb_ctx {
     bool ev_made = false;
     double ms_tot = 0.0;
     int64_t launches = 0;
+    // reverse mode
+    char* adj = nullptr;
+    int64_t adj_bytes = 0;
+    mcb::AdjPlan ap{};
+    bool adj_ready = false;   // a forward pass with checkpoints has run and the state is its end
+    int64_t adj_t_end = -1;
+    int32_t adj_kind = 0;
+    double adj_prm[2]{};
 };
 
 namespace mcb {
@@ -101,6 +123,12 @@ hipError_t geom_reclass(mcb_ctx* c);              // class from the current q (a
 // step2d.hip / step3d.hip
 hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
 hipError_t init_feq(mcb_ctx* c, const double* rho, const double* u, void* fout);
+
+// adjoint.hip: one transposed step (pull = 0: the first collision from f^eq(rho0, 0)), and the
+// loss of a state with (lam != nullptr) its gradient lam = dloss * d loss / d g
+hipError_t adj_step(mcb_ctx* c, const AdjWork& w, const void* gt, const void* rec, int pull, const double* lam1,
+                    const double* lamR1, double* lam0, double* lamR0);
+hipError_t adj_loss(mcb_ctx* c, const AdjWork& w, const void* g, int kind, const double* prm, double dloss, double* lam);
 
 // monitor.hip
 hipError_t monitor(mcb_ctx* c, const void* fcur);

@@ -170,14 +170,7 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
     const bool wave_links = PULL && __any(mA != 0u);
     constexpr int NE = EARLY ? 18 : 1;
     C la[NE], lF[NE], lo[NE];
-    if (EARLY && PULL) {
-        if (wave_links) {
-            link_loads<S, C, 0, NE>(M, mA, tgA, xAb, la, lF, lo);
-        } else {
-#pragma unroll
-            for (int j = 0; j < NE; ++j) la[j] = lF[j] = lo[j] = C(0);
-        }
-    }
+    if (EARLY && PULL && wave_links) link_loads<S, C, 0, NE>(M, mA, tgA, xAb, la, lF, lo);
     // wettability factor of a wall node of plane r-1 (psi below); other lanes read nothing
     const int tgm = M.s_tag[(k - 1) & 3][t];
     const double phv = Buf<double>::ld(M.phi, (k >= 1 && tgm <= -2) ? uint32_t(-tgm - 2) * 8u : OOB);
@@ -344,8 +337,10 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
             fpair(17, 18, we, duy - duz, sy2 - sz2);
         }
     }
+    // a lane that does not store starts from OOB; the saturating add keeps it out of bounds
+    const uint32_t xst = coll ? xAb : OOB;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) Buf<S>::st(M.fb, coll ? uint32_t(i) * M.ns + xAb : OOB, out[i]);
+    for (int i = 0; i < 19; ++i) Buf<S>::st(M.fb, __builtin_elementwise_add_sat(xst, uint32_t(i) * M.ns), out[i]);
     if (wave_mk) {
         const uint32_t base = uint32_t(tgA - 1) * uint32_t(Q3_LINKS * 2 * sc) + sc;
 #pragma unroll

@@ -60,6 +60,7 @@ EXPORTS = [
     "mcb_set_geometry", "mcb_build_links", "mcb_get_links", "mcb_get_wall_nodes", "mcb_set_links",
     "mcb_set_wettability", "mcb_init_equilibrium", "mcb_set_f", "mcb_get_f", "mcb_step",
     "mcb_moments", "mcb_mass", "mcb_sync", "mcb_timing", "mcb_timing_report",
+    "mcb_adj_required_bytes", "mcb_adj_bind", "mcb_adj_forward", "mcb_adj_backward",
 ]
 
 _lib = None
@@ -96,6 +97,10 @@ def load(path: str = LIB_PATH):
         "mcb_sync": ([vp], i32),
         "mcb_timing": ([vp, i32], i32),
         "mcb_timing_report": ([vp, P(C.c_double), P(i64)], i32),
+        "mcb_adj_required_bytes": ([vp, i64, i64, P(i64)], i32),
+        "mcb_adj_bind": ([vp, vp, i64], i32),
+        "mcb_adj_forward": ([vp, vp, i64, i64, i32, vp, P(C.c_double)], i32),
+        "mcb_adj_backward": ([vp, C.c_double, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -234,6 +239,34 @@ def mcb_timing_report(ctx):
     return ms.value, n.value
 
 
+MCB_LOSS_COM_X, MCB_LOSS_WETTED_LENGTH, MCB_LOSS_TOTAL_MASS = 0, 1, 2
+
+
+def mcb_adj_required_bytes(ctx, nsteps, k) -> int:
+    b = C.c_int64()
+    _check(ctx, load().mcb_adj_required_bytes(ctx, int(nsteps), int(k), C.byref(b)), "mcb_adj_required_bytes")
+    return b.value
+
+
+def mcb_adj_bind(ctx, dev_ptr, nbytes):
+    _check(ctx, load().mcb_adj_bind(ctx, C.c_void_p(dev_ptr), int(nbytes)), "mcb_adj_bind")
+
+
+def mcb_adj_forward(ctx, rho0, nsteps, k, kind, prm) -> float:
+    rho0 = np.ascontiguousarray(rho0, np.float64).reshape(-1)
+    prm = np.ascontiguousarray(np.resize(np.asarray(prm, np.float64), 2))
+    v = C.c_double()
+    _check(ctx, load().mcb_adj_forward(ctx, _ptr(rho0), int(nsteps), int(k), int(kind), _ptr(prm), C.byref(v)),
+           "mcb_adj_forward")
+    return v.value
+
+
+def mcb_adj_backward(ctx, dloss, n_wall) -> np.ndarray:
+    d = np.zeros(max(n_wall, 1))
+    _check(ctx, load().mcb_adj_backward(ctx, float(dloss), _ptr(d)), "mcb_adj_backward")
+    return d[:n_wall]
+
+
 # ---------------------------------------------------------------- convenience object
 class Lattice:
     """A context plus the torch tensors backing its device arenas."""
@@ -330,3 +363,51 @@ class Lattice:
 
     def timing_report(self):
         return mcb_timing_report(self.ctx)
+
+    # ---- reverse mode
+    def adj_forward(self, rho0, nsteps, k, kind=MCB_LOSS_COM_X, prm=(0.0, 1.0)) -> float:
+        """Equilibrium start from rho0, nsteps steps with a checkpoint every k; returns the loss."""
+        need = mcb_adj_required_bytes(self.ctx, nsteps, k)
+        if getattr(self, "adj", None) is None or self.adj.numel() < need:
+            self.adj = None
+            self.adj = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        mcb_adj_bind(self.ctx, self.adj.data_ptr(), self.adj.numel())
+        return mcb_adj_forward(self.ctx, rho0, nsteps, k, kind, prm)
+
+    def adj_backward(self, dloss=1.0) -> np.ndarray:
+        """dloss * d loss / d phi per wall node, for the last adj_forward."""
+        return mcb_adj_backward(self.ctx, dloss, self.n_wall)
+
+
+def _wettability_loss_class():
+    import torch
+
+    class WettabilityLoss(torch.autograd.Function):
+        """loss(phi) of the state after nsteps steps from the equilibrium start rho0, with the
+        hand-written reverse mode of the step as its backward.
+
+        forward(phi, lattice, rho0, nsteps, k, kind, prm): phi is a float64 tensor with one
+        entry per wall node (any device); returns a 0-d float64 tensor on phi's device."""
+
+        @staticmethod
+        def forward(ctx, phi, lattice, rho0, nsteps, k, kind=MCB_LOSS_COM_X, prm=(0.0, 1.0)):
+            lattice.set_wettability(phi.detach().to("cpu", torch.float64).numpy())
+            val = lattice.adj_forward(rho0, nsteps, k, kind, prm)
+            ctx.lattice = lattice
+            ctx.phi_device = phi.device
+            return torch.tensor(val, dtype=torch.float64, device=phi.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            d = ctx.lattice.adj_backward(float(g))
+            return torch.from_numpy(d).to(ctx.phi_device), None, None, None, None, None, None
+
+    return WettabilityLoss
+
+
+def __getattr__(name):
+    if name == "WettabilityLoss":
+        cls = _wettability_loss_class()
+        globals()["WettabilityLoss"] = cls
+        return cls
+    raise AttributeError(name)

@@ -208,7 +208,10 @@ def make(name: str) -> Workload:
         shapes = np.array([ball(c, r, g) for g, (c, r) in enumerate(zip(cs, rs))], np.int64)
         drops = _drops(rng, 200, (256, 256, 256), 3, 8.0, 16.0)
         phi = rng.uniform(*PHI_RANGE, len(rs))
-        return Workload("c4", 3, (256, 256, 256), 0.8, 0.65, shapes, drops, phi, 2000)
+        # 0.7 T_c, tau = 1 and a tanh width of 4: at 0.65 T_c (either tau) or with the width-2
+        # profile of the 2-D cases, the sharp start of 200 drops among 400 spheres drives the
+        # liquid past the pseudopotential's density limit within a few hundred steps
+        return Workload("c4", 3, (256, 256, 256), 1.0, 0.70, shapes, drops, phi, 2000, interface_width=4.0)
     raise KeyError(name)
 
 
