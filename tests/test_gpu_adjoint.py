@@ -101,3 +101,73 @@ def test_state_is_restored_after_backward(mcb):
         out.append(lat.get_f())
         lat.close()
     assert np.array_equal(out[0], out[1])
+
+
+def test_c3_gradient_against_central_differences(mcb):
+    banner("c3 (512^2 rough wall, 2000 steps, k = 100): adjoint vs central differences on 20 entries")
+    wl = W.make("c3")
+    lat = mcb.Lattice(2, wl.dims, wl.tau, wl.T)
+    lat.set_geometry(wl.shapes)
+    walls = lat.wall_nodes()
+    phi = W.phi_for_walls(wl, walls)
+    rho0 = wl.rho0()
+    prm = (wl.rho_v, 1.0)
+    lat.set_wettability(phi)
+    L0 = lat.adj_forward(rho0, wl.steps, 100, 0, prm)
+    g = lat.adj_backward(1.0)
+    assert np.isfinite(g).all() and np.abs(g).max() > 0
+    # entries whose derivative is not negligible, so that a relative comparison means something
+    rng = np.random.default_rng(33)
+    cand = np.nonzero(np.abs(g) >= 1e-2 * np.abs(g).max())[0]
+    idx = rng.choice(cand, min(20, len(cand)), replace=False)
+    worst = 0.0
+    for w in idx:
+        h = 1e-6 * max(1.0, abs(phi[w]))
+        vals = []
+        for sgn in (1.0, -1.0):
+            ph = phi.copy()
+            ph[w] += sgn * h
+            lat.set_wettability(ph)
+            vals.append(lat.adj_forward(rho0, wl.steps, 100, 0, prm))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        worst = max(worst, abs(fd - g[w]) / abs(fd))
+    print(f"loss {L0:.6f}, {len(cand)} candidate entries, worst relative difference {worst:.2e}", flush=True)
+    assert worst < 1e-4, worst
+    # the total mass has no derivative with respect to phi
+    lat.set_wettability(phi)
+    M = lat.adj_forward(rho0, wl.steps, 100, 2, (0.0, 1.0))
+    gm = lat.adj_backward(1.0)
+    assert np.abs(gm).max() < 1e-12 * M, np.abs(gm).max()
+    lat.close()
+
+
+def test_shifted_fp32_gradient_close_to_fp64(mcb):
+    banner("c3 reverse mode over shifted-FP32 states vs FP64 states, 500 steps")
+    wl = W.make("c3")
+    grads = []
+    for prec in ("f64", "f32s"):
+        lat = mcb.Lattice(2, wl.dims, wl.tau, wl.T, precision=prec, rho_ref=wl.rho_v if prec != "f64" else 0.0)
+        lat.set_geometry(wl.shapes)
+        lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
+        lat.adj_forward(wl.rho0(), 500, 100, 0, (wl.rho_v, 1.0))
+        grads.append(lat.adj_backward(1.0))
+        lat.close()
+    # FP32 storage perturbs the linearisation point by ~1e-7 relative per step
+    assert np.abs(grads[1] - grads[0]).max() <= 1e-4 * np.abs(grads[0]).max()
+
+
+def test_wettability_loss_autograd(mcb):
+    banner("WettabilityLoss through torch.autograd")
+    import torch
+    dims, shapes, rho0 = small_case()
+    lat = mcb.Lattice(2, dims, 0.8, 0.7 * TC)
+    lat.set_geometry(shapes)
+    phi = torch.full((lat.n_wall,), 1.02, dtype=torch.float64, requires_grad=True)
+    loss = mcb.WettabilityLoss.apply(phi, lat, rho0, 40, 9, 0, (RV, 1.0))
+    loss.backward()
+    lat.set_wettability(phi.detach().numpy())
+    ref = lat.adj_forward(rho0, 40, 9, 0, (RV, 1.0))
+    gref = lat.adj_backward(1.0)
+    assert float(loss) == ref
+    assert np.array_equal(phi.grad.numpy(), gref)
+    lat.close()
