@@ -52,6 +52,7 @@ struct AdjDev {
     const uint32_t* nmask;       // 3-D link bits
     const int32_t* bn_link0;     // 2-D first link of each boundary node
     const double* phi;           // wettability factor per wall node
+    int64_t nslots;              // link-record slots; F of slot s is at nslots + s
     double tau, G, RT, a, b4, rho_ref;
 };
 
@@ -61,7 +62,8 @@ __device__ inline uint32_t link_bits(const AdjDev& A, int64_t x, int tg) {
     return A.L == 0 ? uint32_t(tg) & 0xFFu : A.nmask[x];
 }
 __device__ inline int64_t link_slot(const AdjDev& A, int tg, uint32_t mask, int j) {
-    if (A.L == 0) return int64_t(A.bn_link0[tg >> 8]) + __popc(mask & ((1u << (j - 1)) - 1u));
+    (void)mask;
+    if (A.L == 0) return int64_t(tg >> 8) * Q2_LINKS + (j - 1);
     return int64_t(tg - 1) * Q3_LINKS + (j - 1);
 }
 
@@ -111,7 +113,7 @@ __global__ void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __rest
             for (int j = 1; j < Q; ++j) {
                 if (!((m >> (j - 1)) & 1u)) continue;
                 const int64_t sl = link_slot(A, tg, m, j);
-                const double a = double(rec[2 * sl]), Fj = double(rec[2 * sl + 1]);
+                const double a = double(rec[sl]), Fj = double(rec[A.nslots + sl]);
                 const double fj = ldf<S>(gt, A, j, x);
                 const double o = a < 0.0 ? ldf<S>(gt, A, c_opp[A.L][j], x)
                                          : (A.tag[nbr(A.g, A.L, x, j, -1)] >= 0 ? ldf<S>(gt, A, j, nbr(A.g, A.L, x, j, -1)) : 0.0);
@@ -302,7 +304,7 @@ __global__ void k_stream_T(AdjDev A, const RC* __restrict__ rec, const double* _
                 acc = pb0;
             } else if ((m >> (i - 1)) & 1u) {
                 const int64_t sl = link_slot(A, tg, m, i);
-                const double c1 = fabs(double(rec[2 * sl]));
+                const double c1 = fabs(double(rec[sl]));
                 const double Bb = pbar[c_opp[L][i] * N + y] - pb0;
                 acc = c1 * Bb + pb0;
                 lamR0[sl] = (1.0 - c1) * Bb;
@@ -312,13 +314,13 @@ __global__ void k_stream_T(AdjDev A, const RC* __restrict__ rec, const double* _
                 const int tx = A.tag[x];
                 const uint32_t mx = link_bits(A, x, tx);
                 if ((mx >> (i - 1)) & 1u) {
-                    const double ax = double(rec[2 * link_slot(A, tx, mx, i)]);
+                    const double ax = double(rec[link_slot(A, tx, mx, i)]);
                     if (ax > 0.0) acc += (1.0 - ax) * (pbar[c_opp[L][i] * N + x] - pbar[x]);
                 }
             }
             const int io = c_opp[L][i];
             if (i >= 1 && ((m >> (io - 1)) & 1u)) {
-                const double ao = double(rec[2 * link_slot(A, tg, m, io)]);
+                const double ao = double(rec[link_slot(A, tg, m, io)]);
                 if (ao < 0.0) acc += (1.0 + ao) * (pbar[i * N + y] - pb0);
             }
             lam0[i * N + y] = acc;
@@ -438,6 +440,7 @@ AdjDev make_dev(const mcb_ctx* c) {
     A.nmask = reinterpret_cast<const uint32_t*>(c->lat + c->L.nmask);
     A.bn_link0 = reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0);
     A.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
+    A.nslots = c->L.rec_slots;
     A.tau = c->p.tau;
     A.G = c->p.G;
     A.RT = c->p.eos_R * c->p.eos_T;

@@ -44,9 +44,10 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.bn_link0 = take(4 * nb);
     L.dm = take(8 * nb);
     L.lk_qc = take(4 * nl);
-    // per link: signed interpolation coefficient and forcing term; 2-D in link order, 3-D in fixed
-    // slots (boundary node, direction)
-    L.lk_rec = take(p.dim == 2 ? 2 * cb * nl : 2 * cb * Q3_LINKS * nb);
+    // link records in fixed slots (boundary node, direction): the signed interpolation coefficient
+    // a of every slot, then the forcing terms F (planar, so a node's slots are contiguous)
+    L.rec_slots = (p.dim == 2 ? Q2_LINKS : Q3_LINKS) * nb;
+    L.lk_rec = take(2 * cb * L.rec_slots);
     L.wl_node = take(4 * nw);
     L.wl_phi = take(8 * nw);
     L.links_bytes = (nb + nl + nw) > 0 ? o : 0;
@@ -63,7 +64,7 @@ AdjPlan adj_plan(const mcb_ctx* c, int64_t nsteps, int64_t k) {
     a.k = k;
     a.nck = nsteps == 0 ? 1 : (nsteps + k - 1) / k;
     a.state_b = align256(Q * N * storage_bytes(c->p.precision));
-    a.nslots = c->g.dim == 2 ? c->n_links : Q3_LINKS * c->n_bnodes;
+    a.nslots = c->L.rec_slots;
     a.rec_b = align256(2 * cb * a.nslots);
     int64_t o = 0;
     auto take = [&](int64_t bytes) { const int64_t at = o; o = align256(o + bytes); return at; };
@@ -320,8 +321,8 @@ mcb_status mcb_build_links(mcb_ctx* c, int32_t phase, int64_t* n_links, int64_t*
         HIPCHK(hipStreamSynchronize(c->stream));
         if (tot[0] >= (int64_t(1) << 31)) return fail(c, MCB_ENOTSUP, "too many links");
         if (c->g.dim == 2 && tot[1] >= (int64_t(1) << 23)) return fail(c, MCB_ENOTSUP, "2-D tags hold at most 2^23 boundary nodes");
-        if (c->g.dim == 3 && tot[1] * Q3_LINKS * 2 * compute_bytes(c->p.precision) > int64_t(0xFFFFFE00u))
-            return fail(c, MCB_ENOTSUP, "3-D link records exceed 4 GiB");
+        if (tot[1] * (c->g.Q - 1) * 2 * compute_bytes(c->p.precision) > int64_t(0xFFFFFE00u))
+            return fail(c, MCB_ENOTSUP, "link records exceed 4 GiB");
         c->n_links = tot[0];
         c->n_bnodes = tot[1];
         c->n_wall = tot[2];

@@ -325,6 +325,8 @@ __global__ void k_q_band(Bands b, GridDev g, int L, int64_t nb, const int32_t* _
 __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict__ solid, const int32_t* __restrict__ bn_node,
                         const uint32_t* __restrict__ bn_mask, const int32_t* __restrict__ bn_link0, uint32_t* lk_qc,
                         void* rec, int rec_double, int32_t* flags) {
+    // records: a[slot] for all slots, then F[slot]; slot = boundary index * (Q - 1) + direction - 1
+    const int64_t QL = g.Q - 1, nslots = nb * QL;
     for (int64_t bi = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; bi < nb; bi += int64_t(gridDim.x) * blockDim.x) {
         const int64_t x = bn_node[bi];
         const uint32_t mask = bn_mask[bi];
@@ -332,27 +334,29 @@ __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict_
         coords(g, x, c);
         int l = bn_link0[bi];
         for (int i = 1; i < g.Q; ++i) {
-            if (!((mask >> i) & 1u)) continue;
-            uint32_t q = lk_qc[l] & (NOHIT >> 2);
-            if (q > uint32_t(ONE)) {
-                atomicOr(&flags[FLAG_NOHIT], 1);
-                q = uint32_t(ONE / 2);
+            double a = 1.0;  // slots of directions without a link: never used by the step
+            if ((mask >> i) & 1u) {
+                uint32_t q = lk_qc[l] & (NOHIT >> 2);
+                if (q > uint32_t(ONE)) {
+                    atomicOr(&flags[FLAG_NOHIT], 1);
+                    q = uint32_t(ONE / 2);
+                }
+                int cls;
+                if (q >= uint32_t(ONE / 2)) cls = MCB_CLS_EQ17;
+                else cls = solid[neighbour(g, c, L, i, -1)] ? MCB_CLS_HBB : MCB_CLS_EQ16;
+                lk_qc[l] = q | (uint32_t(cls) << CLS_SHIFT);
+                const double q2 = double(q) * (2.0 / 65536.0);
+                a = cls == MCB_CLS_EQ16 ? q2 : (cls == MCB_CLS_EQ17 ? -1.0 / q2 : 1.0);
+                ++l;
             }
-            int cls;
-            if (q >= uint32_t(ONE / 2)) cls = MCB_CLS_EQ17;
-            else cls = solid[neighbour(g, c, L, i, -1)] ? MCB_CLS_HBB : MCB_CLS_EQ16;
-            lk_qc[l] = q | (uint32_t(cls) << CLS_SHIFT);
-            const double q2 = double(q) * (2.0 / 65536.0);
-            const double a = cls == MCB_CLS_EQ16 ? q2 : (cls == MCB_CLS_EQ17 ? -1.0 / q2 : 1.0);
-            const int64_t slot = g.dim == 2 ? l : bi * Q3_LINKS + (i - 1);
+            const int64_t slot = bi * QL + (i - 1);
             if (rec_double) {
-                static_cast<double*>(rec)[2 * slot] = a;
-                static_cast<double*>(rec)[2 * slot + 1] = 0.0;
+                static_cast<double*>(rec)[slot] = a;
+                static_cast<double*>(rec)[nslots + slot] = 0.0;
             } else {
-                static_cast<float*>(rec)[2 * slot] = float(a);
-                static_cast<float*>(rec)[2 * slot + 1] = 0.0f;
+                static_cast<float*>(rec)[slot] = float(a);
+                static_cast<float*>(rec)[nslots + slot] = 0.0f;
             }
-            ++l;
         }
     }
 }

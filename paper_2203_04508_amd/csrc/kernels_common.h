@@ -42,12 +42,18 @@ __device__ inline __amdgpu_buffer_rsrc_t make_res(const void* p, uint64_t bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(n), 0x00020000);
 }
 
+// Loads may also take a wave-uniform part of the offset in soffset (an SGPR).  Only loads do: a
+// load whose lane offset is OOB can at worst read a valid word of the same buffer, which the
+// caller discards, whereas a store must be dropped for certain.
 template <class S>
 struct Buf;
 template <>
 struct Buf<double> {
     static __device__ inline double ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    static __device__ inline double ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
     }
     static __device__ inline double round(double v) { return v; }
     static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
@@ -60,6 +66,9 @@ struct Buf<float> {
     static __device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
     }
+    static __device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+    }
     static __device__ inline float round(float v) { return v; }
     static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
@@ -70,6 +79,9 @@ struct Buf<__half> {
     static __device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
         return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)));
     }
+    static __device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+        return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0)));
+    }
     static __device__ inline float round(float v) { return __half2float(__float2half_rn(v)); }
     static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v)), r, off, 0, 0);
@@ -78,6 +90,11 @@ struct Buf<__half> {
 __device__ inline int32_t ld_i32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return int32_t(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
+__device__ inline int32_t ld_i32(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return int32_t(__builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+}
+// unsigned saturating add: an OOB lane offset stays out of bounds for any in-bounds addend
+__device__ inline uint32_t sat_add(uint32_t a, uint32_t b) { return __builtin_elementwise_add_sat(a, b); }
 
 // reciprocal: IEEE division in FP64, the hardware reciprocal (1 ulp) in FP32
 __device__ inline double rcp(double x) { return 1.0 / x; }

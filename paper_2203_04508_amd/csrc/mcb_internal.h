@@ -17,7 +17,8 @@ constexpr uint32_t QMASK = 0x1FFFFu;      // q_fixed in bits 0..16 of a packed l
 constexpr int CLS_SHIFT = 30;             // link class in bits 30..31
 
 constexpr int STRIP_HALO = 4;            // 2-D step: halo lanes per strip (two columns on each side)
-constexpr int Q3_LINKS = 18;              // 3-D: fixed link-record slots per boundary node
+constexpr int Q2_LINKS = 8;               // fixed link-record slots per boundary node (one per direction)
+constexpr int Q3_LINKS = 18;
 constexpr int SCAN_BLOCK = 256;           // geometry scan granularity
 constexpr int MON_BLOCKS = 1024;          // monitor partial sums
 constexpr int MON_FIELDS = 8;             // M, Jx, Jy, Jz, dM, n_nan, spare, spare
@@ -52,6 +53,7 @@ struct Layout {
     int64_t fa, fb, tag, nmask, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
     // links arena
     int64_t bn_node, bn_mask, bn_link0, dm, lk_qc, lk_rec, wl_node, wl_phi, links_bytes;
+    int64_t rec_slots;  // link-record slots: (Q - 1) per boundary node; records are planar, [a][F]
 };
 
 Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64_t n_bnodes, int64_t n_wall);

@@ -15,7 +15,8 @@
 //      force stencil from the psi ring and collides the populations pulled two iterations earlier
 //      (kept in registers), then stores them.
 // Per node only the populations (read once, written once) and a 4-byte tag reach HBM; rho and psi
-// live in LDS.  Halo rows and columns are re-pulled by the neighbouring workgroup and hit in L2 or
+// live in LDS.  A boundary node's link records sit in eight fixed slots (one per direction), so
+// their addresses are the node's slot base plus constants.  Halo rows and columns are re-pulled by the neighbouring workgroup and hit in L2 or
 // the Infinity Cache.  The populations of the next row and the tag of the row after it are in
 // flight while a row is processed; every global access is a bounds-checked buffer instruction, so
 // no load or store sits in a divergent branch and the wait counters stay exact.
@@ -29,12 +30,11 @@ struct Args2 {
     const S* fa;                 // post-collision populations of time t, SoA [9][N]
     S* fb;                       // post-collision populations of time t+1
     const int32_t* tag;          // >0: (boundary index << 8) | link bits; 0 fluid; -1 solid; -2-w wall w
-    const int32_t* bn_link0;     // first link of each boundary node
-    C* lk_rec;                   // per link: {signed coefficient a, forcing term F_j}
+    C* lk_rec;                   // slot s = 8 b + j - 1: coefficient a at s, forcing term F_j at n_slots + s
     double* dm;                  // eq. 18 correction per boundary node (for the monitor)
     const double* phi;           // wettability factor per wall node
     int32_t* flags;
-    uint32_t n_bnodes, n_links, n_wall;
+    uint32_t n_bnodes, n_slots, n_wall;
     int nx, ny, H, nsx, nblocks;
     C tau_inv, G, rho_ref;
     Eos<C> eos;
@@ -54,16 +54,16 @@ __device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 template <class S, class C, int W>
 struct March {
     Args2<S, C> a;
-    __amdgpu_buffer_rsrc_t fa, fb, tag, l0, rec, dm, phi;
+    __amdgpu_buffer_rsrc_t fa, fb, tag, rec, dm, phi;
     C (*s_rho)[W];
     C (*s_psi)[W];
     int (*s_tag)[W];
     int t, cx, nx, ny, y0, iters;
-    uint32_t n, xcol_b[3];   // byte offsets of columns x-1, x, x+1 within a row
+    uint32_t n, ns, F0, xcol_b[3];   // nodes, bytes per population array, forcing-term offset, columns x-1, x, x+1
     bool out_col;
-    // pipeline registers: tags and link starts of rows r-2, r-1, r; row r+1 and r+2 in flight
-    int tgA, tgB, tgC, l0A, l0B, l0C;
-    int rr, rr1, tg_cur, tg_nxt, l0_cur;
+    // pipeline registers: tags of rows r-2, r-1, r; row r+1 and the tag of r+2 in flight
+    int tgA, tgB, tgC;
+    int rr, rr1, tg_cur, tg_nxt;
     bool bad;
 };
 
@@ -77,29 +77,35 @@ struct March {
 template <class S, class C, int W, bool PULL>
 __device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, int tg, C f[9]) {
     constexpr uint32_t s = sizeof(S);
-    const uint32_t ns = M.n * s, rows = uint32_t(M.nx) * s;
+    const uint32_t rows = uint32_t(M.nx) * s;
     const uint32_t r0 = uint32_t(r) * rows;
     const uint32_t rm = uint32_t(r == 0 ? M.ny - 1 : r - 1) * rows;
     const uint32_t rp = uint32_t(r == M.ny - 1 ? 0 : r + 1) * rows;
-    uint32_t off[9];
-    if (PULL) {
-        // upstream node of direction i: x - e_i
-        const uint32_t rowof[3] = {rp, r0, rm};  // e_y = -1, 0, +1
+    // lane part of the offset in vo, wave-uniform part in so: away from the walls the loads take the
+    // loop-invariant column offsets and no address arithmetic
+    uint32_t vo[9], so[9];
+    const uint32_t rowof[3] = {rp, r0, rm};  // upstream row of e_y = -1, 0, +1
+    const uint32_t m = (PULL && tg > 0) ? uint32_t(tg) & 0xFFu : 0u;  // bit j-1: x + e_j is solid
+    if (PULL && __any(m != 0u)) {
+        // upstream node of direction i: x - e_i, or across a link the node itself (bounce-back)
 #pragma unroll
-        for (int i = 0; i < 9; ++i) off[i] = uint32_t(i) * ns + rowof[kEy[i] + 1] + M.xcol_b[1 - kEx[i]];
-        const uint32_t m = tg > 0 ? uint32_t(tg) & 0xFFu : 0u;  // bit j-1: x + e_j is solid
-        if (__any(m != 0u)) {
-            const uint32_t xo = r0 + M.xcol_b[1];
-#pragma unroll
-            for (int i = 1; i < 9; ++i)
-                if ((m >> (kOpp[i] - 1)) & 1u) off[i] = uint32_t(kOpp[i]) * ns + xo;
+        for (int i = 0; i < 9; ++i) {
+            vo[i] = uint32_t(i) * M.ns + rowof[kEy[i] + 1] + M.xcol_b[1 - kEx[i]];
+            so[i] = 0;
         }
+        const uint32_t xo = r0 + M.xcol_b[1];
+#pragma unroll
+        for (int i = 1; i < 9; ++i)
+            if ((m >> (kOpp[i] - 1)) & 1u) vo[i] = uint32_t(kOpp[i]) * M.ns + xo;
     } else {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) off[i] = uint32_t(i) * ns + r0 + M.xcol_b[1];
+        for (int i = 0; i < 9; ++i) {
+            vo[i] = PULL ? M.xcol_b[1 - kEx[i]] : M.xcol_b[1];
+            so[i] = uint32_t(i) * M.ns + (PULL ? rowof[kEy[i] + 1] : r0);
+        }
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = Buf<S>::ld(M.fa, off[i]);
+    for (int i = 0; i < 9; ++i) f[i] = Buf<S>::ld(M.fa, vo[i], so[i]);
 }
 
 // One row of the march (iteration k, row r = y0 - 2 + k).  fC holds the pulled populations of row
@@ -111,34 +117,24 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     constexpr uint32_t s = sizeof(S), sc = sizeof(C);
     const int slot = k & 3;
     M.tgA = M.tgB; M.tgB = M.tgC; M.tgC = M.tg_cur;
-    M.l0A = M.l0B; M.l0B = M.l0C; M.l0C = M.l0_cur;
     const int tgA = M.tgA;
     const bool coll = k >= 4 && M.out_col && tgA >= 0;
     const int yA = ((M.y0 - 4 + k) % ny + ny) % ny;
     const uint32_t xAb = (uint32_t(yA) * nx) * s + M.xcol_b[1];  // byte offset of (x, yA) in a plane
-    // ---- link records of row r-2 (collided this iteration), one batch; lanes without the link
-    // read nothing, waves without boundary nodes skip the address arithmetic
+    // ---- link records of row r-2 (collided this iteration): all eight slots of a boundary node
+    // (the correction below uses those with a link), and f~_opp(j)(x, t) for eq. 17; other lanes
+    // read nothing.  The load count is the same in every wave, so the wait counters stay exact.
     const uint32_t mA = (PULL && coll && tgA > 0) ? uint32_t(tgA) & 0xFFu : 0u;
     const bool wave_links = PULL && __any(mA != 0u);
-    uint32_t orec[8], olo[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) orec[j] = olo[j] = OOB;
-    if (wave_links) {
-#pragma unroll
-        for (int j = 1; j < 9; ++j) {
-            const bool has = (mA >> (j - 1)) & 1u;
-            const uint32_t li = uint32_t(M.l0A) + __popc(mA & ((1u << (j - 1)) - 1u));
-            orec[j - 1] = has ? li * (2 * sc) : OOB;
-            olo[j - 1] = has ? uint32_t(kOpp[j]) * (M.n * s) + xAb : OOB;
-        }
-    }
     C la[8], lF[8], lo[8];
     if (PULL) {
+        const uint32_t base = mA ? uint32_t(tgA >> 8) * (8 * sc) : OOB;
+        const uint32_t own = mA ? xAb : OOB;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            la[j] = Buf<C>::ld(M.rec, orec[j]);
-            lF[j] = Buf<C>::ld(M.rec, orec[j] + sc);
-            lo[j] = Buf<S>::ld(M.fa, olo[j]);
+            la[j] = Buf<C>::ld(M.rec, base + uint32_t(j) * sc);
+            lF[j] = Buf<C>::ld(M.rec, base + uint32_t(j) * sc, M.F0);
+            lo[j] = Buf<S>::ld(M.fa, own, uint32_t(kOpp[j + 1]) * M.ns);
         }
     }
     // wettability factor of a wall node of row r-1 (psi below); other lanes read nothing
@@ -147,15 +143,14 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     // memory operations retire in issue order: the loads used later in this iteration go out
     // before the prefetch of the next row, so waiting for them leaves the prefetch in flight
     __builtin_amdgcn_sched_barrier(0);
-    // ---- row r+1 populations, row r+2 tag, row r+1 link start
+    // ---- row r+1 populations, row r+2 tag
     {
         const bool more = k + 1 < M.iters;
         M.rr = M.rr1;
         M.rr1 = M.rr == ny - 1 ? 0 : M.rr + 1;
         M.tg_cur = more ? M.tg_nxt : -1;
-        M.l0_cur = ld_i32(M.l0, M.tg_cur > 0 ? uint32_t(M.tg_cur >> 8) * 4u : OOB);
         pull_row<S, C, W, PULL>(M, M.rr, M.tg_cur, fN);
-        M.tg_nxt = ld_i32(M.tag, k + 2 < M.iters ? uint32_t(M.rr1) * (nx * 4u) + M.xcol_b[1] / s * 4u : OOB);
+        M.tg_nxt = ld_i32(M.tag, k + 2 < M.iters ? uint32_t(M.cx) * 4u : OOB, uint32_t(M.rr1) * (nx * 4u));
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- A: density of row r
@@ -196,20 +191,21 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     }
     __syncthreads();
     // ---- C: boundary links, force and collision of row r - 2; colliding lanes store
+    // (computed in every iteration: in the first four, which collide nothing, the results are
+    // discarded, and there is no branch around the stores)
     C out[9];
     C Fl[8];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) out[i] = C(0);
 #pragma unroll
     for (int j = 0; j < 8; ++j) Fl[j] = C(0);
     const uint32_t mk = (coll && tgA > 0) ? uint32_t(tgA) & 0xFFu : 0u;
     const bool wave_mk = __any(mk != 0u);
-    if (k >= 4) {
+    {
         // the node's density at t+1 from the pulled values (eq. 18 keeps it through the link
         // corrections); the collision hands all of it back, with f_0 taking the rounding
         C rs_pull = C(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) rs_pull += fA[i];
+        C dsum = C(0);
         if (wave_links) {
             // eqs. 16-17 on each link (x, j) as t + a (f~_j(x, t) - t), t = other + F_j(x, t):
             //   eq. 16: a = 2q, other = f~_j(x2, t) = fA[j] (x2 = x - e_j fluid);
@@ -218,7 +214,6 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
             // f~_j(x, t) = fA[opp j] (the bounce-back-pulled value).  Eq. 18: f_0 takes back
             // f~_j(x, t) - f_opp(j)(x, t+1).  Link j rewrites only fA[opp j]; fA[j] is read only when
             // x2 is fluid, so (x, opp j) is no link and fA[j] is still the pulled value.
-            C dsum = C(0);
 #pragma unroll
             for (int j = 1; j < 9; ++j) {
                 const bool has = (mA >> (j - 1)) & 1u;
@@ -232,8 +227,8 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
                 dsum += has ? fj - fin : C(0);
             }
             fA[0] += dsum;
-            Buf<double>::st(M.dm, mA ? uint32_t(tgA >> 8) * 8u : OOB, double(dsum));
         }
+        Buf<double>::st(M.dm, mA ? uint32_t(tgA >> 8) * 8u : OOB, double(dsum));
         const int sl = (k - 3) & 3, sm = (k - 2) & 3, sh = (k - 1) & 3;
         const int tc = t < 1 ? 1 : (t > W - 2 ? W - 2 : t);
         const C p0 = M.s_psi[sm][tc];
@@ -300,20 +295,14 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
             fpair(6, 8, C(1.0 / 36.0), duy - dux, sy2 - sx2);
         }
     }
+    // a lane that does not store starts from OOB; the saturating add keeps it out of bounds
+    const uint32_t xst = coll ? xAb : OOB;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Buf<S>::st(M.fb, coll ? uint32_t(i) * (M.n * s) + xAb : OOB, out[i]);
-    uint32_t oS[8];
+    for (int i = 0; i < 9; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), out[i]);
+    // forcing terms of all eight slots of a boundary node (slots without a link are never read)
+    const uint32_t fst = mk ? M.F0 + uint32_t(tgA >> 8) * (8 * sc) : OOB;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) oS[j] = OOB;
-    if (wave_mk) {
-#pragma unroll
-        for (int j = 1; j < 9; ++j) {
-            const bool has = (mk >> (j - 1)) & 1u;
-            oS[j - 1] = has ? (uint32_t(M.l0A) + __popc(mk & ((1u << (j - 1)) - 1u))) * (2 * sc) + sc : OOB;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) Buf<C>::st(M.rec, oS[j], Fl[j]);
+    for (int j = 0; j < 8; ++j) Buf<C>::st(M.rec, fst + uint32_t(j) * sc, Fl[j]);
 }
 
 template <class S, class C, int W, bool PULL>
@@ -353,12 +342,12 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     M.fa = make_res(a.fa, uint64_t(9) * M.n * s);
     M.fb = make_res(a.fb, uint64_t(9) * M.n * s);
     M.tag = make_res(a.tag, uint64_t(M.n) * 4);
-    M.l0 = make_res(a.bn_link0, uint64_t(a.n_bnodes) * 4);
-    M.rec = make_res(a.lk_rec, uint64_t(a.n_links) * 2 * sizeof(C));
+    M.rec = make_res(a.lk_rec, uint64_t(a.n_slots) * 2 * sizeof(C));
+    M.F0 = a.n_slots * uint32_t(sizeof(C));
+    M.ns = M.n * s;
     M.dm = make_res(a.dm, uint64_t(a.n_bnodes) * 8);
     M.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
     M.tgA = M.tgB = M.tgC = -1;
-    M.l0A = M.l0B = M.l0C = 0;
     M.bad = false;
     // row march: the populations of row r+1 and the tag of row r+2 are in flight while row r is
     // reduced to rho, row r-1 to psi and row r-2 collided; four register sets rotate
@@ -369,7 +358,6 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     M.tg_cur = ld_i32(M.tag, (uint32_t(M.rr) * a.nx + M.cx) * 4u);
     M.rr1 = M.rr == a.ny - 1 ? 0 : M.rr + 1;
     M.tg_nxt = ld_i32(M.tag, (uint32_t(M.rr1) * a.nx + M.cx) * 4u);
-    M.l0_cur = ld_i32(M.l0, M.tg_cur > 0 ? uint32_t(M.tg_cur >> 8) * 4u : OOB);
     pull_row<S, C, W, PULL>(M, M.rr, M.tg_cur, f3);
     int k = 0;
     for (; k + 4 <= M.iters; k += 4) {
@@ -391,13 +379,12 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
     a.fa = static_cast<const S*>(fcur);
     a.fb = static_cast<S*>(fnext);
     a.tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
-    a.bn_link0 = reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0);
     a.lk_rec = reinterpret_cast<C*>(c->lk + c->L.lk_rec);
     a.dm = reinterpret_cast<double*>(c->lk + c->L.dm);
     a.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
     a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
     a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
-    a.n_links = uint32_t(c->n_links > 0 ? c->n_links : 0);
+    a.n_slots = uint32_t(c->L.rec_slots);
     a.n_wall = uint32_t(c->n_wall > 0 ? c->n_wall : 0);
     a.nx = c->p.nx;
     a.ny = c->p.ny;

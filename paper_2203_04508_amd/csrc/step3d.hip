@@ -38,11 +38,11 @@ struct Args3 {
     S* fb;                       // post-collision populations of time t+1
     const int32_t* tag;          // >0: boundary index + 1; 0 fluid; -1 solid; -2-w wall w
     const uint32_t* nmask;       // bit j-1 set: x + e_j is solid (boundary nodes only, 0 elsewhere)
-    C* lk_rec;                   // slot 18 b + j - 1: {signed coefficient a, forcing term F_j}
+    C* lk_rec;                   // slot s = 18 b + j - 1: coefficient a at s, forcing term F_j at n_slots + s
     double* dm;                  // eq. 18 correction per boundary node (for the monitor)
     const double* phi;           // wettability factor per wall node
     int32_t* flags;
-    uint32_t n_bnodes, n_wall;
+    uint32_t n_bnodes, n_wall, n_slots;
     int nx, ny, nz, D, ntx, nty, nblocks;
     C tau_inv, G, rho_ref;
     Eos<C> eos;
@@ -61,6 +61,7 @@ struct March3 {
     uint32_t pb;       // bytes per z-plane of one population array
     uint32_t p4;       // bytes per z-plane of a 4-byte node array
     uint32_t own4;     // byte offset of this lane's column in a 4-byte node array plane
+    uint32_t F0;       // byte offset of the forcing terms in the link records
     uint32_t vxy[9];   // byte offsets of the columns (x + dx, y + dy), index 3 (dy + 1) + dx + 1
     bool out_col, inner;
     // tags and link bits of planes r-2, r-1, r (history) and r+1, r+2 (ahead)
@@ -106,20 +107,16 @@ template <class S, class C, int J0, int NB>
 __device__ __forceinline__ void link_loads(const March3<S, C>& M, uint32_t mA, int tgA, uint32_t xAb, C (&la)[NB],
                                            C (&lF)[NB], C (&lo)[NB]) {
     constexpr uint32_t sc = sizeof(C);
-    const uint32_t base = uint32_t(tgA - 1) * uint32_t(Q3_LINKS * 2 * sc);
-    uint32_t orec[NB], olo[NB];
+    // all slots of a boundary node are read (the step uses only those with a link); other lanes
+    // read nothing: the offsets below are OOB for them
+    const uint32_t base = mA ? uint32_t(tgA - 1) * uint32_t(Q3_LINKS * sc) : OOB;
+    const uint32_t own = mA ? xAb : OOB;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         const int d = J0 + j + 1;
-        const bool has = (mA >> (d - 1)) & 1u;
-        orec[j] = has ? base + uint32_t(d - 1) * (2 * sc) : OOB;
-        olo[j] = has ? uint32_t(kOpp3[d]) * M.ns + xAb : OOB;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        la[j] = Buf<C>::ld(M.rec, orec[j]);
-        lF[j] = Buf<C>::ld(M.rec, orec[j] + sc);
-        lo[j] = Buf<S>::ld(M.fa, olo[j]);
+        la[j] = Buf<C>::ld(M.rec, base + uint32_t(d - 1) * sc);
+        lF[j] = Buf<C>::ld(M.rec, base + uint32_t(d - 1) * sc, M.F0);
+        lo[j] = Buf<S>::ld(M.fa, own, uint32_t(kOpp3[d]) * M.ns);
     }
 }
 
@@ -342,12 +339,10 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
 #pragma unroll
     for (int i = 0; i < 19; ++i) Buf<S>::st(M.fb, __builtin_elementwise_add_sat(xst, uint32_t(i) * M.ns), out[i]);
     if (wave_mk) {
-        const uint32_t base = uint32_t(tgA - 1) * uint32_t(Q3_LINKS * 2 * sc) + sc;
+        // every slot of a boundary node (those without a link are never read)
+        const uint32_t base = mk ? M.F0 + uint32_t(tgA - 1) * uint32_t(Q3_LINKS * sc) : OOB;
 #pragma unroll
-        for (int j = 1; j < 19; ++j) {
-            const bool has = (mk >> (j - 1)) & 1u;
-            Buf<C>::st(M.rec, has ? base + uint32_t(j - 1) * (2 * sc) : OOB, Fl[j - 1]);
-        }
+        for (int j = 1; j < 19; ++j) Buf<C>::st(M.rec, base + uint32_t(j - 1) * sc, Fl[j - 1]);
     }
     (void)s;
 }
@@ -399,7 +394,8 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
     M.fb = make_res(a.fb, uint64_t(19) * M.ns);
     M.tag = make_res(a.tag, uint64_t(nxy) * a.nz * 4);
     M.msk = make_res(a.nmask, uint64_t(nxy) * a.nz * 4);
-    M.rec = make_res(a.lk_rec, uint64_t(a.n_bnodes) * Q3_LINKS * 2 * sizeof(C));
+    M.rec = make_res(a.lk_rec, uint64_t(a.n_slots) * 2 * sizeof(C));
+    M.F0 = a.n_slots * uint32_t(sizeof(C));
     M.dm = make_res(a.dm, uint64_t(a.n_bnodes) * 8);
     M.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
     M.tgA = M.tgB = M.tgC = -1;
@@ -443,6 +439,7 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
     a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
     a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
     a.n_wall = uint32_t(c->n_wall > 0 ? c->n_wall : 0);
+    a.n_slots = uint32_t(c->L.rec_slots);
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.nz = c->p.nz;
