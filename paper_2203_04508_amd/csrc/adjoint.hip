@@ -6,7 +6,9 @@
 //
 // State.  The forward step reads, besides the populations g(t), the forcing term F_j(x, t) of
 // eq. 13 on every fluid-solid link (eqs. 16-17 use it one step later), so the state is the pair
-// (g, R) with R the per-link forcing terms; its adjoint is (lambda, lambda_R).
+// (g, R) with R the per-link forcing terms; its adjoint is (lambda, lambda_R).  The step keeps
+// the force F(x, t) of each boundary node, from which R follows with the node's own populations
+// (see the boundary pass); the reverse sweep recomputes R the same way.
 //
 // Forward step, per fluid node x (f = g + w rho_ref in the shifted storages):
 //   streaming, eq. 5:     p_i(x) = f_i(x - e_i)                           (x - e_i fluid)
@@ -52,9 +54,12 @@ struct AdjDev {
     const uint32_t* nmask;       // 3-D link bits
     const int32_t* bn_link0;     // 2-D first link of each boundary node
     const double* phi;           // wettability factor per wall node
-    int64_t nslots;              // link-record slots; F of slot s is at nslots + s
+    int fs;                      // stride of the per-boundary-node force
     double tau, G, RT, a, b4, rho_ref;
 };
+
+// boundary index of a boundary node's tag
+__device__ inline int64_t bidx(const AdjDev& A, int tg) { return A.L == 0 ? int64_t(tg >> 8) : int64_t(tg - 1); }
 
 // link bits (bit j-1: x + e_j solid) of a fluid node, and the record slot of its link j
 __device__ inline uint32_t link_bits(const AdjDev& A, int64_t x, int tg) {
@@ -97,8 +102,8 @@ __device__ inline double ldf<double>(const double* g, const AdjDev& A, int i, in
 // ---- 1: pre-collision populations p and density of time t+1 (recomputed from (g, R) of time t);
 // pull = 0: p = f^eq(rho0, 0), the first collision's input
 template <class S, class RC>
-__global__ void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __restrict__ rec, int pull,
-                            const double* __restrict__ rho0, double* __restrict__ p, double* __restrict__ rho) {
+__global__ void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __restrict__ la, const RC* __restrict__ Fv,
+                            int pull, const double* __restrict__ rho0, double* __restrict__ p, double* __restrict__ rho) {
     const int Q = A.g.Q;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < A.g.N; x += int64_t(gridDim.x) * blockDim.x) {
         const int tg = A.tag[x];
@@ -110,10 +115,33 @@ __global__ void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __rest
             for (int i = 0; i < Q; ++i) v[i] = ldf<S>(gt, A, i, nbr(A.g, A.L, x, i, -1));
             const uint32_t m = link_bits(A, x, tg);
             double dm = 0.0;
+            // forcing terms of time t: rho and rho u + F from the node's own populations
+            double r0 = 0.0, m0[3] = {0, 0, 0}, F0[3] = {0, 0, 0};
+            if (m) {
+                for (int i = 0; i < Q; ++i) {
+                    const double fi = ldf<S>(gt, A, i, x);
+                    r0 += fi;
+                    m0[0] += fi * c_ex[A.L][i];
+                    m0[1] += fi * c_ey[A.L][i];
+                    m0[2] += fi * c_ez[A.L][i];
+                }
+                const int64_t b = bidx(A, tg);
+                for (int k = 0; k < A.g.dim; ++k) F0[k] = double(Fv[b * A.fs + k]);
+                for (int k = 0; k < 3; ++k) m0[k] -= F0[k];
+            }
             for (int j = 1; j < Q; ++j) {
                 if (!((m >> (j - 1)) & 1u)) continue;
                 const int64_t sl = link_slot(A, tg, m, j);
-                const double a = double(rec[sl]), Fj = double(rec[A.nslots + sl]);
+                const double a = double(la[sl]);
+                // R_j = E_j(rho, m + F) - E_j(rho, m), E the equilibrium in momentum form
+                const double w = wgt<double>(A.L, j);
+                const double e[3] = {double(c_ex[A.L][j]), double(c_ey[A.L][j]), double(c_ez[A.L][j])};
+                const double m1[3] = {m0[0] + F0[0], m0[1] + F0[1], m0[2] + F0[2]};
+                const double em0 = e[0] * m0[0] + e[1] * m0[1] + e[2] * m0[2];
+                const double em1 = e[0] * m1[0] + e[1] * m1[1] + e[2] * m1[2];
+                const double mm0 = m0[0] * m0[0] + m0[1] * m0[1] + m0[2] * m0[2];
+                const double mm1 = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
+                const double Fj = w * (3.0 * (em1 - em0) + (4.5 * (em1 * em1 - em0 * em0) - 1.5 * (mm1 - mm0)) / r0);
                 const double fj = ldf<S>(gt, A, j, x);
                 const double o = a < 0.0 ? ldf<S>(gt, A, c_opp[A.L][j], x)
                                          : (A.tag[nbr(A.g, A.L, x, j, -1)] >= 0 ? ldf<S>(gt, A, j, nbr(A.g, A.L, x, j, -1)) : 0.0);
@@ -288,6 +316,7 @@ __global__ void k_rho_T(AdjDev A, const double* __restrict__ rbar, const double*
 template <class RC>
 __global__ void k_stream_T(AdjDev A, const RC* __restrict__ rec, const double* __restrict__ pbar, double* __restrict__ lam0,
                            double* __restrict__ lamR0) {
+    // rec: the link coefficients a per slot
     const int Q = A.g.Q, L = A.L;
     const int64_t N = A.g.N;
     for (int64_t y = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; y < N; y += int64_t(gridDim.x) * blockDim.x) {
@@ -440,7 +469,7 @@ AdjDev make_dev(const mcb_ctx* c) {
     A.nmask = reinterpret_cast<const uint32_t*>(c->lat + c->L.nmask);
     A.bn_link0 = reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0);
     A.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
-    A.nslots = c->L.rec_slots;
+    A.fs = int(c->L.fv_stride);
     A.tau = c->p.tau;
     A.G = c->p.G;
     A.RT = c->p.eos_R * c->p.eos_T;
@@ -451,18 +480,19 @@ AdjDev make_dev(const mcb_ctx* c) {
 }
 
 template <class S, class RC>
-hipError_t adj_step_t(mcb_ctx* c, const AdjWork& w, const void* gt, const void* rec, int pull, const double* lam1,
+hipError_t adj_step_t(mcb_ctx* c, const AdjWork& w, const void* gt, const void* fv, int pull, const double* lam1,
                       const double* lamR1, double* lam0, double* lamR0) {
     const AdjDev A = make_dev(c);
     const unsigned G = grid_for(c->g.N);
-    hipLaunchKernelGGL((k_recompute<S, RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt),
-                       static_cast<const RC*>(rec), pull, w.rho0, w.p, w.rho);
+    const RC* rec = reinterpret_cast<const RC*>(c->lk + c->L.lk_a);
+    hipLaunchKernelGGL((k_recompute<S, RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt), rec,
+                       static_cast<const RC*>(fv), pull, w.rho0, w.p, w.rho);
     hipLaunchKernelGGL(k_psi, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.dpsi, w.rave, w.den);
     hipLaunchKernelGGL(k_collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar, w.Fv);
     hipLaunchKernelGGL(k_psi_T, dim3(G), dim3(256), 0, c->stream, A, w.psi, w.dpsi, w.rave, w.den, w.Fbar, w.rbar, w.qbar, w.dphi);
     if (pull) {
         hipLaunchKernelGGL(k_rho_T, dim3(G), dim3(256), 0, c->stream, A, w.rbar, w.qbar, w.pbar);
-        hipLaunchKernelGGL((k_stream_T<RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const RC*>(rec), w.pbar, lam0, lamR0);
+        hipLaunchKernelGGL((k_stream_T<RC>), dim3(G), dim3(256), 0, c->stream, A, rec, w.pbar, lam0, lamR0);
     }
     return hipGetLastError();
 }

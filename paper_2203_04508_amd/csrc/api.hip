@@ -44,10 +44,14 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.bn_link0 = take(4 * nb);
     L.dm = take(8 * nb);
     L.lk_qc = take(4 * nl);
-    // link records in fixed slots (boundary node, direction): the signed interpolation coefficient
-    // a of every slot, then the forcing terms F (planar, so a node's slots are contiguous)
+    // per boundary node: the signed interpolation coefficient a of each direction's link (fixed
+    // slots), the force F (for the forcing terms of eqs. 16-17 one step later) and the rest
+    // population with the eq. 18 correction
     L.rec_slots = (p.dim == 2 ? Q2_LINKS : Q3_LINKS) * nb;
-    L.lk_rec = take(2 * cb * L.rec_slots);
+    L.fv_stride = p.dim == 2 ? 2 : 4;
+    L.lk_a = take(cb * L.rec_slots);
+    L.lk_Fv = take(cb * L.fv_stride * nb);
+    L.lk_f0c = take(cb * nb);
     L.wl_node = take(4 * nw);
     L.wl_phi = take(8 * nw);
     L.links_bytes = (nb + nl + nw) > 0 ? o : 0;
@@ -65,7 +69,7 @@ AdjPlan adj_plan(const mcb_ctx* c, int64_t nsteps, int64_t k) {
     a.nck = nsteps == 0 ? 1 : (nsteps + k - 1) / k;
     a.state_b = align256(Q * N * storage_bytes(c->p.precision));
     a.nslots = c->L.rec_slots;
-    a.rec_b = align256(2 * cb * a.nslots);
+    a.rec_b = align256(cb * c->L.fv_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0));
     int64_t o = 0;
     auto take = [&](int64_t bytes) { const int64_t at = o; o = align256(o + bytes); return at; };
     a.rho0 = take(8 * N);
@@ -553,8 +557,8 @@ mcb_status mcb_adj_forward(mcb_ctx* c, const double* rho0, int64_t nsteps, int64
     mcb_status st = mcb_init_equilibrium(c, rho0, nullptr);
     if (st) return st;
     HIPCHK(hipMemcpyAsync(c->adj + a.rho0, rho0, 8 * c->g.N, hipMemcpyHostToDevice, c->stream));
-    char* rec = c->lk + c->L.lk_rec;
-    const int64_t rec_used = 2 * compute_bytes(c->p.precision) * a.nslots;
+    char* rec = c->lk + c->L.lk_Fv;
+    const int64_t rec_used = compute_bytes(c->p.precision) * c->L.fv_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0);
     for (int64_t t = 0;; ++t) {
         if (t % k == 0 && t / k < a.nck) {
             HIPCHK(hipMemcpyAsync(c->adj + a.ck + (t / k) * a.state_b, fcur(c), c->g.Q * c->g.N * storage_bytes(c->p.precision),
@@ -589,8 +593,8 @@ mcb_status mcb_adj_backward(mcb_ctx* c, double dloss, double* dphi) {
     if (c->n_wall > 0 && !dphi) return fail(c, MCB_EINVAL, "dphi missing");
     const AdjPlan& a = c->ap;
     const AdjWork w = adj_work(c);
-    const int64_t rec_used = 2 * compute_bytes(c->p.precision) * a.nslots;
-    char* rec = c->lk + c->L.lk_rec;
+    const int64_t rec_used = compute_bytes(c->p.precision) * c->L.fv_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0);
+    char* rec = c->lk + c->L.lk_Fv;
     auto lam = [&](int b) { return reinterpret_cast<double*>(c->adj + a.lam[b]); };
     auto lamR = [&](int b) { return reinterpret_cast<double*>(c->adj + a.lamR[b]); };
     mcb_status st = clear_flags(c);
@@ -704,6 +708,10 @@ hipError_t step2d(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
 hipError_t step3d(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
 
 hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
+    if (pull) {
+        const hipError_t e = boundary_pass(c, const_cast<void*>(fcur));
+        if (e != hipSuccess) return e;
+    }
     return c->g.dim == 2 ? step2d(c, fcur, fnext, pull) : step3d(c, fcur, fnext, pull);
 }
 }  // namespace mcb

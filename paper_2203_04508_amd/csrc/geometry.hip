@@ -324,9 +324,10 @@ __global__ void k_q_band(Bands b, GridDev g, int L, int64_t nb, const int32_t* _
 // forcing term F_j (zeroed here, written by every collision).  Flags links no shape was found for.
 __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict__ solid, const int32_t* __restrict__ bn_node,
                         const uint32_t* __restrict__ bn_mask, const int32_t* __restrict__ bn_link0, uint32_t* lk_qc,
-                        void* rec, int rec_double, int32_t* flags) {
-    // records: a[slot] for all slots, then F[slot]; slot = boundary index * (Q - 1) + direction - 1
-    const int64_t QL = g.Q - 1, nslots = nb * QL;
+                        void* rec, void* rec_fv, int fv_stride, int rec_double, int32_t* flags) {
+    // coefficient a per slot = boundary index * (Q - 1) + direction - 1; the force of each boundary
+    // node (rec_fv, fv_stride per node) starts at zero
+    const int64_t QL = g.Q - 1;
     for (int64_t bi = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; bi < nb; bi += int64_t(gridDim.x) * blockDim.x) {
         const int64_t x = bn_node[bi];
         const uint32_t mask = bn_mask[bi];
@@ -350,13 +351,12 @@ __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict_
                 ++l;
             }
             const int64_t slot = bi * QL + (i - 1);
-            if (rec_double) {
-                static_cast<double*>(rec)[slot] = a;
-                static_cast<double*>(rec)[nslots + slot] = 0.0;
-            } else {
-                static_cast<float*>(rec)[slot] = float(a);
-                static_cast<float*>(rec)[nslots + slot] = 0.0f;
-            }
+            if (rec_double) static_cast<double*>(rec)[slot] = a;
+            else static_cast<float*>(rec)[slot] = float(a);
+        }
+        for (int k = 0; k < fv_stride; ++k) {
+            if (rec_double) static_cast<double*>(rec_fv)[bi * fv_stride + k] = 0.0;
+            else static_cast<float*>(rec_fv)[bi * fv_stride + k] = 0.0f;
         }
     }
 }
@@ -435,8 +435,8 @@ hipError_t geom_reclass(mcb_ctx* c) {
                        solid, reinterpret_cast<const int32_t*>(c->lk + c->L.bn_node),
                        reinterpret_cast<const uint32_t*>(c->lk + c->L.bn_mask),
                        reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0),
-                       reinterpret_cast<uint32_t*>(c->lk + c->L.lk_qc), static_cast<void*>(c->lk + c->L.lk_rec),
-                       c->p.precision == MCB_F64 ? 1 : 0, flags);
+                       reinterpret_cast<uint32_t*>(c->lk + c->L.lk_qc), static_cast<void*>(c->lk + c->L.lk_a),
+                       static_cast<void*>(c->lk + c->L.lk_Fv), int(c->L.fv_stride), c->p.precision == MCB_F64 ? 1 : 0, flags);
     return hipGetLastError();
 }
 

@@ -52,8 +52,9 @@ struct Layout {
     // lattice arena
     int64_t fa, fb, tag, nmask, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
     // links arena
-    int64_t bn_node, bn_mask, bn_link0, dm, lk_qc, lk_rec, wl_node, wl_phi, links_bytes;
-    int64_t rec_slots;  // link-record slots: (Q - 1) per boundary node; records are planar, [a][F]
+    int64_t bn_node, bn_mask, bn_link0, dm, lk_qc, lk_a, lk_Fv, lk_f0c, wl_node, wl_phi, links_bytes;
+    int64_t rec_slots;  // link-coefficient slots: (Q - 1) per boundary node, one per direction
+    int64_t fv_stride;  // elements per boundary node in lk_Fv (2 in 2-D, 4 in 3-D)
 };
 
 Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64_t n_bnodes, int64_t n_wall);
@@ -122,7 +123,11 @@ hipError_t geom_count(mcb_ctx* c);                // block sums + scan, totals a
 hipError_t geom_fill(mcb_ctx* c);                 // tags, boundary-node / wall tables, q, class
 hipError_t geom_reclass(mcb_ctx* c);              // class from the current q (after an override)
 
-// step2d.hip / step3d.hip
+// boundary.hip: eqs. 16-18 for the step that starts from fcur (writes solid slots of fcur, the
+// corrected rest populations and Delta M per boundary node)
+hipError_t boundary_pass(mcb_ctx* c, void* fcur);
+
+// step2d.hip / step3d.hip (pull = true: boundary pass + bulk kernel)
 hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
 hipError_t init_feq(mcb_ctx* c, const double* rho, const double* u, void* fout);
 

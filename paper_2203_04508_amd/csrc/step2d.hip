@@ -1,25 +1,28 @@
-// D2Q9 hot path: one fused kernel per time step -- pull-streaming (eq. 5), the multiphase curved
-// boundary on every fluid-solid link (eqs. 16-17) with the mass modification (eq. 18), density,
-// the pseudopotential with first-layer wall densities (eq. 15), the interaction force, and the
-// single-relaxation-time collision with exact-difference forcing (eqs. 4, 13-14).
+// D2Q9 bulk of a time step: one fused kernel -- pull-streaming (eq. 5), density, the
+// pseudopotential with first-layer wall densities (eq. 15), the interaction force, and the
+// single-relaxation-time collision with exact-difference forcing (eqs. 4, 13-14).  The boundary
+// pass that runs before it has applied eqs. 16-18: the population entering a boundary node across
+// a link waits in the solid neighbour's slot for that direction, so the pull needs no special
+// case, and the node's rest population with the eq. 18 correction waits in f0c.
 //
 // Layout: a workgroup of W lanes (one or four waves) covers W consecutive columns -- W - 4 output
 // columns and two halo columns on each side -- over a segment of H rows, and marches up the
 // segment one row per iteration.  Each iteration
-//   A  reduces the populations of the current row to rho and puts rho and the node tag into a
-//      4-row LDS ring; a population arriving across a link is pulled as its bounce-back value,
-//      which already gives the node's density at t+1;
+//   A  reduces the populations pulled for the current row to rho and puts rho and the node tag
+//      into a 4-row LDS ring;
 //   B  computes psi one row behind (wall nodes: eq. 15 average of their fluid neighbours times
 //      phi) into a second 4-row LDS ring;
-//   C  two rows behind, applies the link corrections of eqs. 16-18 at boundary nodes, evaluates the
-//      force stencil from the psi ring and collides the populations pulled two iterations earlier
-//      (kept in registers), then stores them.
+//   C  two rows behind, evaluates the force stencil from the psi ring and collides the populations
+//      pulled two iterations earlier (kept in registers), then stores them; boundary nodes also
+//      store their force, from which the next boundary pass recomputes the forcing terms of eq. 13.
 // Per node only the populations (read once, written once) and a 4-byte tag reach HBM; rho and psi
-// live in LDS.  A boundary node's link records sit in eight fixed slots (one per direction), so
-// their addresses are the node's slot base plus constants.  Halo rows and columns are re-pulled by the neighbouring workgroup and hit in L2 or
-// the Infinity Cache.  The populations of the next row and the tag of the row after it are in
-// flight while a row is processed; every global access is a bounds-checked buffer instruction, so
-// no load or store sits in a divergent branch and the wait counters stay exact.
+// live in LDS.  Halo rows and columns are re-pulled by the neighbouring workgroup and hit in L2
+// or the Infinity Cache.  The populations of the next row and the tag of the row after it are in
+// flight while a row is processed, with the wettability factors of that row's wall nodes.  Every
+// global access is a bounds-checked buffer instruction
+// (no load or store sits in a divergent branch, so the wait counters stay exact), and the lane
+// part of a pull address is loop-invariant, the row part a wave-uniform scalar: each vector
+// memory instruction moves a full row of one population with no address arithmetic.
 #include "kernels_common.h"
 
 namespace mcb {
@@ -30,11 +33,11 @@ struct Args2 {
     const S* fa;                 // post-collision populations of time t, SoA [9][N]
     S* fb;                       // post-collision populations of time t+1
     const int32_t* tag;          // >0: (boundary index << 8) | link bits; 0 fluid; -1 solid; -2-w wall w
-    C* lk_rec;                   // slot s = 8 b + j - 1: coefficient a at s, forcing term F_j at n_slots + s
-    double* dm;                  // eq. 18 correction per boundary node (for the monitor)
+    const C* f0c;                // rest population with the eq. 18 correction, per boundary node
+    C* Fv;                       // force per boundary node (for the next boundary pass), stride 2
     const double* phi;           // wettability factor per wall node
     int32_t* flags;
-    uint32_t n_bnodes, n_slots, n_wall;
+    uint32_t n_bnodes, n_wall;
     int nx, ny, H, nsx, nblocks;
     C tau_inv, G, rho_ref;
     Eos<C> eos;
@@ -54,66 +57,50 @@ __device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 template <class S, class C, int W>
 struct March {
     Args2<S, C> a;
-    __amdgpu_buffer_rsrc_t fa, fb, tag, rec, dm, phi;
+    __amdgpu_buffer_rsrc_t fa, fb, tag, f0c, Fv, phi;
     C (*s_rho)[W];
     C (*s_psi)[W];
     int (*s_tag)[W];
-    int t, cx, nx, ny, y0, iters;
-    uint32_t n, ns, F0, xcol_b[3];   // nodes, bytes per population array, forcing-term offset, columns x-1, x, x+1
+    int t, p, nx, ny, y0, iters;   // lane, its column's position in the LDS rows
+    uint32_t n, ns, xcol_b[3];   // nodes, bytes per population array, columns x-1, x, x+1
+    uint32_t tag_b;              // byte offset of the column in the tag array (OOB for idle lanes)
     bool out_col;
     // pipeline registers: tags of rows r-2, r-1, r; row r+1 and the tag of r+2 in flight
     int tgA, tgB, tgC;
-    int rr, rr1, tg_cur, tg_nxt;
+    int rr, rr1, tg_cur, tg_nxt, tg_nxt2;  // rows r+1 (pulling), r+2, r+3 (in flight)
+    double phA, phB;  // wettability factors of rows r-1 and r (wall lanes; issued with their pull)
     bool bad;
 };
 
-// Issue the loads of the nine populations arriving at row r of this lane's column (eq. 5).  A
-// population whose upstream node is solid travelled along a link (x, j) with j its opposite; it is
-// taken as its bounce-back value f~_j(x, t), which gives the node's density at t+1 exactly: eq. 18
-// returns to f_0 whatever the curved-boundary value of eqs. 16-17 adds to or takes from that
-// population, and that correction is applied just before the collision.  PULL = false reads the
-// node's own populations (the collision that starts a run).  Solid lanes read whatever lies at
-// their (valid) offsets; their values are never used.
+// Issue the loads of the nine populations arriving at row r of this lane's column (eq. 5), from
+// x - e_i; PULL = false reads the node's own populations (the collision that starts a run).  A
+// boundary node takes its rest population from f0c.
 template <class S, class C, int W, bool PULL>
 __device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, int tg, C f[9]) {
-    constexpr uint32_t s = sizeof(S);
+    constexpr uint32_t s = sizeof(S), sc = sizeof(C);
     const uint32_t rows = uint32_t(M.nx) * s;
     const uint32_t r0 = uint32_t(r) * rows;
     const uint32_t rm = uint32_t(r == 0 ? M.ny - 1 : r - 1) * rows;
     const uint32_t rp = uint32_t(r == M.ny - 1 ? 0 : r + 1) * rows;
-    // lane part of the offset in vo, wave-uniform part in so: away from the walls the loads take the
-    // loop-invariant column offsets and no address arithmetic
-    uint32_t vo[9], so[9];
     const uint32_t rowof[3] = {rp, r0, rm};  // upstream row of e_y = -1, 0, +1
-    const uint32_t m = (PULL && tg > 0) ? uint32_t(tg) & 0xFFu : 0u;  // bit j-1: x + e_j is solid
-    if (PULL && __any(m != 0u)) {
-        // upstream node of direction i: x - e_i, or across a link the node itself (bounce-back)
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            vo[i] = uint32_t(i) * M.ns + rowof[kEy[i] + 1] + M.xcol_b[1 - kEx[i]];
-            so[i] = 0;
-        }
-        const uint32_t xo = r0 + M.xcol_b[1];
-#pragma unroll
-        for (int i = 1; i < 9; ++i)
-            if ((m >> (kOpp[i] - 1)) & 1u) vo[i] = uint32_t(kOpp[i]) * M.ns + xo;
-    } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            vo[i] = PULL ? M.xcol_b[1 - kEx[i]] : M.xcol_b[1];
-            so[i] = uint32_t(i) * M.ns + (PULL ? rowof[kEy[i] + 1] : r0);
-        }
+    for (int i = 0; i < 9; ++i) {
+        const uint32_t vo = PULL ? M.xcol_b[1 - kEx[i]] : M.xcol_b[1];
+        const uint32_t so = uint32_t(i) * M.ns + (PULL ? rowof[kEy[i] + 1] : r0);
+        f[i] = Buf<S>::ld(M.fa, vo, so);
     }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = Buf<S>::ld(M.fa, vo[i], so[i]);
+    if (PULL) {
+        const C c0 = Buf<C>::ld(M.f0c, tg > 0 ? uint32_t(tg >> 8) * sc : OOB);
+        f[0] = tg > 0 ? c0 : f[0];
+    }
 }
 
 // One row of the march (iteration k, row r = y0 - 2 + k).  fC holds the pulled populations of row
 // r, fB and fA those of rows r-1 and r-2; the populations of row r+1 are issued into fN.
-template <class S, class C, int W, bool PULL>
+template <class S, class C, int W, int OUT, bool PULL>
 __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], C (&fB)[9], C (&fC)[9], C (&fN)[9]) {
     const Args2<S, C>& a = M.a;
-    const int t = M.t, nx = M.nx, ny = M.ny;
+    const int t = M.p, nx = M.nx, ny = M.ny;  // LDS rows are indexed by column position
     constexpr uint32_t s = sizeof(S), sc = sizeof(C);
     const int slot = k & 3;
     M.tgA = M.tgB; M.tgB = M.tgC; M.tgC = M.tg_cur;
@@ -121,36 +108,24 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     const bool coll = k >= 4 && M.out_col && tgA >= 0;
     const int yA = ((M.y0 - 4 + k) % ny + ny) % ny;
     const uint32_t xAb = (uint32_t(yA) * nx) * s + M.xcol_b[1];  // byte offset of (x, yA) in a plane
-    // ---- link records of row r-2 (collided this iteration): all eight slots of a boundary node
-    // (the correction below uses those with a link), and f~_opp(j)(x, t) for eq. 17; other lanes
-    // read nothing.  The load count is the same in every wave, so the wait counters stay exact.
-    const uint32_t mA = (PULL && coll && tgA > 0) ? uint32_t(tgA) & 0xFFu : 0u;
-    const bool wave_links = PULL && __any(mA != 0u);
-    C la[8], lF[8], lo[8];
-    if (PULL) {
-        const uint32_t base = mA ? uint32_t(tgA >> 8) * (8 * sc) : OOB;
-        const uint32_t own = mA ? xAb : OOB;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            la[j] = Buf<C>::ld(M.rec, base + uint32_t(j) * sc);
-            lF[j] = Buf<C>::ld(M.rec, base + uint32_t(j) * sc, M.F0);
-            lo[j] = Buf<S>::ld(M.fa, own, uint32_t(kOpp[j + 1]) * M.ns);
-        }
-    }
-    // wettability factor of a wall node of row r-1 (psi below); other lanes read nothing
-    const int tgm = M.s_tag[(k - 1) & 3][t];
-    const double phv = Buf<double>::ld(M.phi, (k >= 1 && tgm <= -2) ? uint32_t(-tgm - 2) * 8u : OOB);
-    // memory operations retire in issue order: the loads used later in this iteration go out
-    // before the prefetch of the next row, so waiting for them leaves the prefetch in flight
+    // wettability factor of a wall node of row r-1 (psi below), loaded with that row's pull
+    const double phv = M.phA;
     __builtin_amdgcn_sched_barrier(0);
-    // ---- row r+1 populations, row r+2 tag
+    // ---- row r+1 populations and wettability factors, row r+3 tags.  The tags run three rows
+    // ahead of the pull: the row r+1 loads that depend on a tag then wait for nothing newer than
+    // row r-1, and the pulls of rows r and r+1 are in flight together.
     {
         const bool more = k + 1 < M.iters;
         M.rr = M.rr1;
         M.rr1 = M.rr == ny - 1 ? 0 : M.rr + 1;
+        const int r3 = M.rr1 == ny - 1 ? 0 : M.rr1 + 1;
         M.tg_cur = more ? M.tg_nxt : -1;
+        M.tg_nxt = M.tg_nxt2;
         pull_row<S, C, W, PULL>(M, M.rr, M.tg_cur, fN);
-        M.tg_nxt = ld_i32(M.tag, k + 2 < M.iters ? uint32_t(M.cx) * 4u : OOB, uint32_t(M.rr1) * (nx * 4u));
+        const double phN = Buf<double>::ld(M.phi, M.tg_cur <= -2 ? uint32_t(-M.tg_cur - 2) * 8u : OOB);
+        M.tg_nxt2 = ld_i32(M.tag, k + 3 < M.iters ? M.tag_b : OOB, uint32_t(r3) * (nx * 4u));
+        M.phA = M.phB;
+        M.phB = phN;
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- A: density of row r
@@ -163,7 +138,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     }
     __syncthreads();
     // ---- B: psi of row r - 1
-    if (k >= 2 && t >= 1 && t < W - 1) {
+    if (k >= 2 && t >= 1 && t <= OUT + 2) {
         const int s_mid = (k - 1) & 3, s_lo = (k - 2) & 3;
         const int tg = M.s_tag[s_mid][t];
         C rho_n;
@@ -190,47 +165,19 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         M.s_psi[s_mid][t] = tg == -1 ? C(0) : psi_val(rho_n, a.eos, &M.bad);
     }
     __syncthreads();
-    // ---- C: boundary links, force and collision of row r - 2; colliding lanes store
-    // (computed in every iteration: in the first four, which collide nothing, the results are
-    // discarded, and there is no branch around the stores)
+    // ---- C: force and collision of row r - 2; colliding lanes store (computed in every iteration:
+    // in the first four, which collide nothing, the results are discarded, and there is no branch
+    // around the stores)
     C out[9];
-    C Fl[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) Fl[j] = C(0);
-    const uint32_t mk = (coll && tgA > 0) ? uint32_t(tgA) & 0xFFu : 0u;
-    const bool wave_mk = __any(mk != 0u);
+    C Fx, Fy;
     {
-        // the node's density at t+1 from the pulled values (eq. 18 keeps it through the link
-        // corrections); the collision hands all of it back, with f_0 taking the rounding
+        // the node's density at t+1 from the pulled values; the collision hands all of it back,
+        // with f_0 taking the rounding
         C rs_pull = C(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) rs_pull += fA[i];
-        C dsum = C(0);
-        if (wave_links) {
-            // eqs. 16-17 on each link (x, j) as t + a (f~_j(x, t) - t), t = other + F_j(x, t):
-            //   eq. 16: a = 2q, other = f~_j(x2, t) = fA[j] (x2 = x - e_j fluid);
-            //   eq. 17: a = 1/(2q) (stored negated), other = f~_opp(j)(x, t) = lo;
-            //   bounce-back: a = 1.
-            // f~_j(x, t) = fA[opp j] (the bounce-back-pulled value).  Eq. 18: f_0 takes back
-            // f~_j(x, t) - f_opp(j)(x, t+1).  Link j rewrites only fA[opp j]; fA[j] is read only when
-            // x2 is fluid, so (x, opp j) is no link and fA[j] is still the pulled value.
-#pragma unroll
-            for (int j = 1; j < 9; ++j) {
-                const bool has = (mA >> (j - 1)) & 1u;
-                if (!__any(has)) continue;
-                const C sa = la[j - 1];
-                const bool eq17 = sa < C(0);
-                const C fj = fA[kOpp[j]];
-                const C tt = (eq17 ? lo[j - 1] : fA[j]) + lF[j - 1];
-                const C fin = tt + (eq17 ? -sa : sa) * (fj - tt);
-                fA[kOpp[j]] = has ? fin : fj;
-                dsum += has ? fj - fin : C(0);
-            }
-            fA[0] += dsum;
-        }
-        Buf<double>::st(M.dm, mA ? uint32_t(tgA >> 8) * 8u : OOB, double(dsum));
         const int sl = (k - 3) & 3, sm = (k - 2) & 3, sh = (k - 1) & 3;
-        const int tc = t < 1 ? 1 : (t > W - 2 ? W - 2 : t);
+        const int tc = t < 1 ? 1 : (t > OUT + 2 ? OUT + 2 : t);
         const C p0 = M.s_psi[sm][tc];
         const C pE = M.s_psi[sm][tc + 1], pW = M.s_psi[sm][tc - 1];
         const C pN = M.s_psi[sh][tc], pS = M.s_psi[sl][tc];
@@ -238,12 +185,10 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         const C pSW = M.s_psi[sl][tc - 1], pSE = M.s_psi[sl][tc + 1];
         // F = -G psi(x) sum_i w^_i psi(x + e_i) e_i, w^ = 1/3 (axes), 1/12 (diagonals)
         const C gp = -a.G * p0;
-        const C Fx = gp * (C(1.0 / 3.0) * (pE - pW) + C(1.0 / 12.0) * (pNE - pNW - pSW + pSE));
-        const C Fy = gp * (C(1.0 / 3.0) * (pN - pS) + C(1.0 / 12.0) * (pNE + pNW - pSW - pSE));
+        Fx = gp * (C(1.0 / 3.0) * (pE - pW) + C(1.0 / 12.0) * (pNE - pNW - pSW + pSE));
+        Fy = gp * (C(1.0 / 3.0) * (pN - pS) + C(1.0 / 12.0) * (pNE + pNW - pSW - pSE));
 
-        C rs = C(0);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) rs += fA[i];
+        const C rs = rs_pull;
         const C rho = rs + a.rho_ref;
         const C irho = rcp(coll ? rho : C(1));
         const C ux = (fA[1] - fA[3] + fA[5] - fA[6] - fA[7] + fA[8]) * irho;
@@ -281,31 +226,21 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
             rest += out[i];
         }
         out[0] = rs_pull - rest;
-        if (wave_mk) {
-            // forcing terms (eq. 13) of the link directions, kept for eqs. 16-17 of the next step
-            auto fpair = [&](int jp, int jm, C w, C ed, C es) {
-                const C fs = C(4.5) * ed * es - duu15;
-                const C fa3 = C(3) * ed;
-                Fl[jp - 1] = w * rho * (fs + fa3);
-                Fl[jm - 1] = w * rho * (fs - fa3);
-            };
-            fpair(1, 3, C(1.0 / 9.0), dux, sx2);
-            fpair(2, 4, C(1.0 / 9.0), duy, sy2);
-            fpair(5, 7, C(1.0 / 36.0), dux + duy, sx2 + sy2);
-            fpair(6, 8, C(1.0 / 36.0), duy - dux, sy2 - sx2);
-        }
     }
-    // a lane that does not store starts from OOB; the saturating add keeps it out of bounds
-    const uint32_t xst = coll ? xAb : OOB;
+    // Every output column stores, solid nodes included: their slots carry nothing the step reads
+    // (the boundary pass overwrites the ones the pull takes), and rows written without holes keep
+    // every cache line whole.  A lane that does not store starts from OOB; the saturating add
+    // keeps it out of bounds.
+    const uint32_t xst = (k >= 4 && M.out_col) ? xAb : OOB;
 #pragma unroll
     for (int i = 0; i < 9; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), out[i]);
-    // forcing terms of all eight slots of a boundary node (slots without a link are never read)
-    const uint32_t fst = mk ? M.F0 + uint32_t(tgA >> 8) * (8 * sc) : OOB;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) Buf<C>::st(M.rec, fst + uint32_t(j) * sc, Fl[j]);
+    // force of a boundary node, for the forcing terms of the next boundary pass
+    const uint32_t fst = (coll && tgA > 0) ? uint32_t(tgA >> 8) * (2 * sc) : OOB;
+    Buf<C>::st(M.Fv, fst, Fx);
+    Buf<C>::st(M.Fv, fst + sc, Fy);
 }
 
-template <class S, class C, int W, bool PULL>
+template <class S, class C, int W, int OUT, bool PULL>
 __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     // XCD-aware order: consecutive logical tiles go to the same XCD (one L2)
     const int bid = blockIdx.x;
@@ -316,25 +251,31 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     __shared__ C s_rho[4][W];
     __shared__ C s_psi[4][W];
     __shared__ int s_tag[4][W];
-    constexpr int OUT = W - STRIP_HALO;
     constexpr uint32_t s = sizeof(S);
 
     March<S, C, W> M;
     M.a = a;
-    // lane t covers column x0 - 2 + t; lanes 2 .. 2 + Wv - 1 own the strip's output columns and the
-    // two lanes on either side are its halo (psi needs rho two columns out, through the wall nodes)
+    // The strip's OUT output columns x0 .. x0 + OUT - 1 go to lanes 0 .. OUT - 1, so that every
+    // wave's loads and stores of a row start on a cache line when OUT is a multiple of the line
+    // (32 FP32 or 64 FP16 values); the two halo columns on either side (psi needs rho two columns
+    // out, through the wall nodes) go to lanes OUT .. OUT + 3, and further lanes idle.  The LDS
+    // rows are indexed by position p = column - (x0 - 2).
     const int x0 = sx * OUT;
     M.y0 = sy * a.H;
     const int Wv = min(OUT, a.nx - x0), Hv = min(a.H, a.ny - M.y0);
     M.t = threadIdx.x;
+    const int t = M.t;
+    M.p = t < OUT + 2 ? t + 2 : (t < OUT + 4 ? t - OUT - 2 : t);
+    const bool live = t < OUT + 4;
     M.nx = a.nx;
     M.ny = a.ny;
     M.n = uint32_t(a.nx) * uint32_t(a.ny);
-    M.cx = ((x0 - 2 + M.t) % a.nx + a.nx) % a.nx;
-    M.xcol_b[0] = uint32_t(M.cx == 0 ? a.nx - 1 : M.cx - 1) * s;
-    M.xcol_b[1] = uint32_t(M.cx) * s;
-    M.xcol_b[2] = uint32_t(M.cx == a.nx - 1 ? 0 : M.cx + 1) * s;
-    M.out_col = M.t >= 2 && M.t < 2 + Wv;
+    const int cx = ((x0 - 2 + M.p) % a.nx + a.nx) % a.nx;
+    M.xcol_b[0] = live ? uint32_t(cx == 0 ? a.nx - 1 : cx - 1) * s : OOB;
+    M.xcol_b[1] = live ? uint32_t(cx) * s : OOB;
+    M.xcol_b[2] = live ? uint32_t(cx == a.nx - 1 ? 0 : cx + 1) * s : OOB;
+    M.tag_b = live ? uint32_t(cx) * 4u : OOB;
+    M.out_col = t < Wv;
     M.iters = Hv + 4;
     M.s_rho = s_rho;
     M.s_psi = s_psi;
@@ -342,10 +283,9 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     M.fa = make_res(a.fa, uint64_t(9) * M.n * s);
     M.fb = make_res(a.fb, uint64_t(9) * M.n * s);
     M.tag = make_res(a.tag, uint64_t(M.n) * 4);
-    M.rec = make_res(a.lk_rec, uint64_t(a.n_slots) * 2 * sizeof(C));
-    M.F0 = a.n_slots * uint32_t(sizeof(C));
+    M.f0c = make_res(a.f0c, uint64_t(a.n_bnodes) * sizeof(C));
+    M.Fv = make_res(a.Fv, uint64_t(a.n_bnodes) * 2 * sizeof(C));
     M.ns = M.n * s;
-    M.dm = make_res(a.dm, uint64_t(a.n_bnodes) * 8);
     M.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
     M.tgA = M.tgB = M.tgC = -1;
     M.bad = false;
@@ -355,40 +295,41 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) f0[i] = f1[i] = f2[i] = C(0);
     M.rr = ((M.y0 - 2) % a.ny + a.ny) % a.ny;
-    M.tg_cur = ld_i32(M.tag, (uint32_t(M.rr) * a.nx + M.cx) * 4u);
+    M.tg_cur = ld_i32(M.tag, M.tag_b, uint32_t(M.rr) * (a.nx * 4u));
     M.rr1 = M.rr == a.ny - 1 ? 0 : M.rr + 1;
-    M.tg_nxt = ld_i32(M.tag, (uint32_t(M.rr1) * a.nx + M.cx) * 4u);
+    M.tg_nxt = ld_i32(M.tag, M.tag_b, uint32_t(M.rr1) * (a.nx * 4u));
+    M.tg_nxt2 = ld_i32(M.tag, M.tag_b, uint32_t(M.rr1 == a.ny - 1 ? 0 : M.rr1 + 1) * (a.nx * 4u));
     pull_row<S, C, W, PULL>(M, M.rr, M.tg_cur, f3);
+    M.phA = 0.0;
+    M.phB = Buf<double>::ld(M.phi, M.tg_cur <= -2 ? uint32_t(-M.tg_cur - 2) * 8u : OOB);
     int k = 0;
     for (; k + 4 <= M.iters; k += 4) {
-        march_row<S, C, W, PULL>(M, k + 0, f0, f1, f3, f2);
-        march_row<S, C, W, PULL>(M, k + 1, f1, f3, f2, f0);
-        march_row<S, C, W, PULL>(M, k + 2, f3, f2, f0, f1);
-        march_row<S, C, W, PULL>(M, k + 3, f2, f0, f1, f3);
+        march_row<S, C, W, OUT, PULL>(M, k + 0, f0, f1, f3, f2);
+        march_row<S, C, W, OUT, PULL>(M, k + 1, f1, f3, f2, f0);
+        march_row<S, C, W, OUT, PULL>(M, k + 2, f3, f2, f0, f1);
+        march_row<S, C, W, OUT, PULL>(M, k + 3, f2, f0, f1, f3);
     }
     const int left = M.iters - k;  // uniform
-    if (left > 0) march_row<S, C, W, PULL>(M, k + 0, f0, f1, f3, f2);
-    if (left > 1) march_row<S, C, W, PULL>(M, k + 1, f1, f3, f2, f0);
-    if (left > 2) march_row<S, C, W, PULL>(M, k + 2, f3, f2, f0, f1);
+    if (left > 0) march_row<S, C, W, OUT, PULL>(M, k + 0, f0, f1, f3, f2);
+    if (left > 1) march_row<S, C, W, OUT, PULL>(M, k + 1, f1, f3, f2, f0);
+    if (left > 2) march_row<S, C, W, OUT, PULL>(M, k + 2, f3, f2, f0, f1);
     if (M.bad) atomicOr(&a.flags[FLAG_DOMAIN], 1);
 }
 
-template <class S, class C, int W>
+template <class S, class C, int W, int OUT>
 hipError_t launch_w(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
     Args2<S, C> a;
     a.fa = static_cast<const S*>(fcur);
     a.fb = static_cast<S*>(fnext);
     a.tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
-    a.lk_rec = reinterpret_cast<C*>(c->lk + c->L.lk_rec);
-    a.dm = reinterpret_cast<double*>(c->lk + c->L.dm);
+    a.f0c = reinterpret_cast<const C*>(c->lk + c->L.lk_f0c);
+    a.Fv = reinterpret_cast<C*>(c->lk + c->L.lk_Fv);
     a.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
     a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
     a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
-    a.n_slots = uint32_t(c->L.rec_slots);
     a.n_wall = uint32_t(c->n_wall > 0 ? c->n_wall : 0);
     a.nx = c->p.nx;
     a.ny = c->p.ny;
-    constexpr int OUT = W - STRIP_HALO;
     a.nsx = (a.nx + OUT - 1) / OUT;
     // segment height: long segments amortise the four halo rows; short ones fill the chip
     const int64_t target = W == 64 ? 8192 : 2048;
@@ -404,17 +345,20 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
     a.eos.b4 = C(c->p.eos_b / 4.0);
     a.eos.two_over_G = C(2.0 / c->p.G);
     if (pull)
-        hipLaunchKernelGGL((k_step2d<S, C, W, true>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
+        hipLaunchKernelGGL((k_step2d<S, C, W, OUT, true>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
     else
-        hipLaunchKernelGGL((k_step2d<S, C, W, false>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
+        hipLaunchKernelGGL((k_step2d<S, C, W, OUT, false>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
     return hipGetLastError();
 }
 
 template <class S, class C>
 hipError_t launch_step2d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
-    // one-wave strips keep small lattices busy; four-wave strips waste fewer halo lanes
-    if (c->g.N > (int64_t(1) << 21)) return launch_w<S, C, 256>(c, fcur, fnext, pull);
-    return launch_w<S, C, 64>(c, fcur, fnext, pull);
+    // one-wave strips keep small lattices busy; on large lattices the strips are a whole number of
+    // cache lines wide (224 FP32 / FP64 columns, 448 FP16 columns), so that no line is shared
+    // between strips or written in parts
+    if (c->g.N <= (int64_t(1) << 21)) return launch_w<S, C, 64, 60>(c, fcur, fnext, pull);
+    if (sizeof(S) == 2) return launch_w<S, C, 512, 448>(c, fcur, fnext, pull);
+    return launch_w<S, C, 256, 224>(c, fcur, fnext, pull);
 }
 
 }  // namespace

@@ -1,23 +1,22 @@
-// D3Q19 hot path: the fused time step of the D2Q9 kernel carried to three dimensions --
-// pull-streaming (eq. 5), the multiphase curved boundary on every fluid-solid link (eqs. 16-17)
-// with the mass modification (eq. 18), density, the pseudopotential with first-layer wall
-// densities (eq. 15), the interaction force, and the single-relaxation-time collision with
-// exact-difference forcing (eqs. 4, 13-14).
+// D3Q19 bulk of a time step: the fused kernel of the D2Q9 path carried to three dimensions --
+// pull-streaming (eq. 5), density, the pseudopotential with first-layer wall densities (eq. 15),
+// the interaction force, and the single-relaxation-time collision with exact-difference forcing
+// (eqs. 4, 13-14).  The boundary pass before it has applied eqs. 16-18 (the incoming population of
+// every link waits in the solid neighbour's slot, the corrected rest population in f0c).
 //
 // Layout: a workgroup of 32 x 16 lanes covers a 32 x 16 column tile of the x-y plane -- 28 x 12
 // output columns and two halo columns on every side -- over a segment of D planes in z, and
-// marches along z one plane per iteration.  As in two dimensions, each iteration
+// marches along z one plane per iteration.  Each iteration
 //   A  reduces the populations pulled for plane r to rho and puts rho and the node tag into a
-//      4-plane LDS ring (a population arriving across a link is pulled as its bounce-back value,
-//      which already gives the node's density at t+1);
+//      4-plane LDS ring;
 //   B  computes psi of plane r-1 (wall nodes: eq. 15 average over their fluid neighbours, times
 //      phi) into a second 4-plane ring;
-//   C  applies the link corrections of eqs. 16-18 at the boundary nodes of plane r-2, evaluates
-//      the force stencil from the psi ring, collides the populations pulled two iterations earlier
-//      (kept in registers) and stores them.
-// The populations of plane r+1, the link bits of plane r+2 and the tags of plane r+3 are in flight
-// while plane r is processed.  Boundary nodes carry an 18-bit link mask in a node array of their
-// own and 18 fixed link-record slots, so a record address is (boundary index, direction).
+//   C  evaluates the force stencil for plane r-2 from the psi ring, collides the populations
+//      pulled two iterations earlier (kept in registers) and stores them; boundary nodes also
+//      store their force for the next boundary pass.
+// The populations of plane r+1 and the tags of plane r+3 are in flight while plane r is processed.
+// The lane part of every pull address is one of nine loop-invariant column offsets and the plane
+// part a wave-uniform scalar, so the loads need no address arithmetic.
 #include "kernels_common.h"
 
 namespace mcb {
@@ -30,19 +29,17 @@ constexpr int OX = TX - 4, OY = TY - 4;        // output columns of a tile
 __device__ constexpr int kEx3[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 __device__ constexpr int kEy3[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 __device__ constexpr int kEz3[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-__device__ constexpr int kOpp3[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
 
 template <class S, class C>
 struct Args3 {
     const S* fa;                 // post-collision populations of time t, SoA [19][N]
     S* fb;                       // post-collision populations of time t+1
     const int32_t* tag;          // >0: boundary index + 1; 0 fluid; -1 solid; -2-w wall w
-    const uint32_t* nmask;       // bit j-1 set: x + e_j is solid (boundary nodes only, 0 elsewhere)
-    C* lk_rec;                   // slot s = 18 b + j - 1: coefficient a at s, forcing term F_j at n_slots + s
-    double* dm;                  // eq. 18 correction per boundary node (for the monitor)
+    const C* f0c;                // rest population with the eq. 18 correction, per boundary node
+    C* Fv;                       // force per boundary node (for the next boundary pass), stride 4
     const double* phi;           // wettability factor per wall node
     int32_t* flags;
-    uint32_t n_bnodes, n_wall, n_slots;
+    uint32_t n_bnodes, n_wall;
     int nx, ny, nz, D, ntx, nty, nblocks;
     C tau_inv, G, rho_ref;
     Eos<C> eos;
@@ -52,7 +49,7 @@ struct Args3 {
 template <class S, class C>
 struct March3 {
     Args3<S, C> a;
-    __amdgpu_buffer_rsrc_t fa, fb, tag, msk, rec, dm, phi;
+    __amdgpu_buffer_rsrc_t fa, fb, tag, f0c, Fv, phi;
     C (*s_rho)[NT];
     C (*s_psi)[NT];
     int (*s_tag)[NT];
@@ -61,130 +58,95 @@ struct March3 {
     uint32_t pb;       // bytes per z-plane of one population array
     uint32_t p4;       // bytes per z-plane of a 4-byte node array
     uint32_t own4;     // byte offset of this lane's column in a 4-byte node array plane
-    uint32_t F0;       // byte offset of the forcing terms in the link records
     uint32_t vxy[9];   // byte offsets of the columns (x + dx, y + dy), index 3 (dy + 1) + dx + 1
     bool out_col, inner;
-    // tags and link bits of planes r-2, r-1, r (history) and r+1, r+2 (ahead)
-    int tgA, tgB, tgC, tg_r, tg_r1, tg_r2;
-    uint32_t mkA, mkB, mkC, mk_r, mk_r1;
+    int tgA, tgB, tgC, tg_r, tg_r1, tg_r2;  // tags of planes r-2, r-1, r (history) and r+1, r+2
+    double phA, phB;                 // wettability factors of planes r-1 and r (wall lanes)
     bool bad;
 };
 
 __device__ inline int zinc(int z, int nz) { return z == nz - 1 ? 0 : z + 1; }
 
-// Issue the loads of the nineteen populations arriving at plane z of this lane's column (eq. 5).
-// A population whose upstream node x - e_i is solid is taken as its bounce-back value
-// f~_opp(i)(x, t) (see the D2Q9 kernel: this gives the node's density at t+1, and eqs. 16-18 are
-// applied just before the collision).  PULL = false reads the node's own populations.
+// force of a boundary node: three components at a 4-element stride
+template <class C>
+__device__ inline void st_force(__amdgpu_buffer_rsrc_t r, uint32_t off, C Fx, C Fy, C Fz) {
+    Buf<C>::st(r, off, Fx);
+    Buf<C>::st(r, off + uint32_t(sizeof(C)), Fy);
+    Buf<C>::st(r, off + 2u * uint32_t(sizeof(C)), Fz);
+}
+template <>
+__device__ inline void st_force<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, float Fx, float Fy, float Fz) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 v;
+    v.x = __builtin_bit_cast(unsigned int, Fx);
+    v.y = __builtin_bit_cast(unsigned int, Fy);
+    v.z = __builtin_bit_cast(unsigned int, Fz);
+    v.w = 0u;
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+}
+
+// Issue the loads of the nineteen populations arriving at plane z of this lane's column (eq. 5),
+// from x - e_i; PULL = false reads the node's own populations.  A boundary node takes its rest
+// population from f0c.
 template <class S, class C, bool PULL>
-__device__ __forceinline__ void pull_plane(const March3<S, C>& M, int z, uint32_t mk, C f[19]) {
-    const uint32_t z0b = uint32_t(z) * M.pb;
-    uint32_t off[19];
-    if (PULL) {
-        const uint32_t zmb = uint32_t(z == 0 ? M.nz - 1 : z - 1) * M.pb;
-        const uint32_t zpb = uint32_t(z == M.nz - 1 ? 0 : z + 1) * M.pb;
-        const uint32_t zof[3] = {zpb, z0b, zmb};  // upstream plane for e_z = -1, 0, +1
-#pragma unroll
-        for (int i = 0; i < 19; ++i)
-            off[i] = uint32_t(i) * M.ns + zof[kEz3[i] + 1] + M.vxy[(1 - kEy3[i]) * 3 + (1 - kEx3[i])];
-        if (__any(mk != 0u)) {
-            const uint32_t xo = z0b + M.vxy[4];
-#pragma unroll
-            for (int i = 1; i < 19; ++i)
-                if ((mk >> (kOpp3[i] - 1)) & 1u) off[i] = uint32_t(kOpp3[i]) * M.ns + xo;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 19; ++i) off[i] = uint32_t(i) * M.ns + z0b + M.vxy[4];
-    }
-#pragma unroll
-    for (int i = 0; i < 19; ++i) f[i] = Buf<S>::ld(M.fa, off[i]);
-}
-
-// Loads for the links of directions J0+1 .. J0+NB of a boundary node: the record {a, F_j} and
-// f~_opp(j)(x, t) (eq. 17).  Lanes without the link read nothing.
-template <class S, class C, int J0, int NB>
-__device__ __forceinline__ void link_loads(const March3<S, C>& M, uint32_t mA, int tgA, uint32_t xAb, C (&la)[NB],
-                                           C (&lF)[NB], C (&lo)[NB]) {
+__device__ __forceinline__ void pull_plane(const March3<S, C>& M, int z, int tg, C f[19]) {
     constexpr uint32_t sc = sizeof(C);
-    // all slots of a boundary node are read (the step uses only those with a link); other lanes
-    // read nothing: the offsets below are OOB for them
-    const uint32_t base = mA ? uint32_t(tgA - 1) * uint32_t(Q3_LINKS * sc) : OOB;
-    const uint32_t own = mA ? xAb : OOB;
+    const uint32_t z0b = uint32_t(z) * M.pb;
+    const uint32_t zmb = uint32_t(z == 0 ? M.nz - 1 : z - 1) * M.pb;
+    const uint32_t zpb = uint32_t(z == M.nz - 1 ? 0 : z + 1) * M.pb;
+    const uint32_t zof[3] = {zpb, z0b, zmb};  // upstream plane for e_z = -1, 0, +1
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const int d = J0 + j + 1;
-        la[j] = Buf<C>::ld(M.rec, base + uint32_t(d - 1) * sc);
-        lF[j] = Buf<C>::ld(M.rec, base + uint32_t(d - 1) * sc, M.F0);
-        lo[j] = Buf<S>::ld(M.fa, own, uint32_t(kOpp3[d]) * M.ns);
+    for (int i = 0; i < 19; ++i) {
+        const uint32_t vo = PULL ? M.vxy[(1 - kEy3[i]) * 3 + (1 - kEx3[i])] : M.vxy[4];
+        const uint32_t so = uint32_t(i) * M.ns + (PULL ? zof[kEz3[i] + 1] : z0b);
+        f[i] = Buf<S>::ld(M.fa, vo, so);
     }
-}
-
-// Eqs. 16-17 on the links of directions J0+1 .. J0+NB as t + a (f~_j(x, t) - t), t = other + F_j:
-//   eq. 16: a = 2q, other = f~_j(x2, t), the value pulled from x2 = x - e_j (fluid);
-//   eq. 17: a = 1/(2q) (stored negated), other = f~_opp(j)(x, t);
-//   bounce-back: a = 1.
-// f~_j(x, t) is the bounce-back-pulled value in slot opp(j); the result replaces it, and dsum
-// gathers what eq. 18 hands to f_0.
-template <class C, int J0, int NB>
-__device__ __forceinline__ void link_apply(C (&f)[19], uint32_t mA, const C (&la)[NB], const C (&lF)[NB],
-                                           const C (&lo)[NB], C& dsum) {
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const int d = J0 + j + 1;
-        const bool has = (mA >> (d - 1)) & 1u;
-        if (!__any(has)) continue;
-        const C sa = la[j];
-        const bool eq17 = sa < C(0);
-        const C fj = f[kOpp3[d]];
-        const C tt = (eq17 ? lo[j] : f[d]) + lF[j];
-        const C fin = tt + (eq17 ? -sa : sa) * (fj - tt);
-        f[kOpp3[d]] = has ? fin : fj;
-        dsum += has ? fj - fin : C(0);
+    if (PULL) {
+        const C c0 = Buf<C>::ld(M.f0c, tg > 0 ? uint32_t(tg - 1) * sc : OOB);
+        f[0] = tg > 0 ? c0 : f[0];
     }
 }
 
 // One plane of the march (iteration k, plane r = z0 - 2 + k).  fC holds the pulled populations
-// of plane r, fB and fA those of planes r-1 and r-2; the populations of plane r+1 go to fN.
-// EARLY: the link loads of plane r-2 are issued before the prefetch; otherwise in three batches
-// inside phase C.  PF: plane r+1 is pulled into fN while plane r is processed; otherwise plane r is
-// pulled into fC at the start of the iteration.  FP64 takes neither, to stay within the register
-// file.
-template <class S, class C, bool PULL, bool EARLY, bool PF>
+// of plane r, fB and fA those of planes r-1 and r-2; the populations of plane r+1 go to fN (PF),
+// else plane r is pulled into fC at the start of the iteration.
+template <class S, class C, bool PULL, bool PF>
 __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19], C (&fB)[19], C (&fC)[19],
                                             C (&fN)[19]) {
     const Args3<S, C>& a = M.a;
     const int t = M.t;
-    constexpr uint32_t s = sizeof(S), sc = sizeof(C);
+    constexpr uint32_t sc = sizeof(C);
     const int slot = k & 3;
     M.tgA = M.tgB; M.tgB = M.tgC; M.tgC = M.tg_r;
-    M.mkA = M.mkB; M.mkB = M.mkC; M.mkC = M.mk_r;
     const int tgA = M.tgA;
     const bool coll = k >= 4 && M.out_col && tgA >= 0;
     const int zA = ((M.z0 - 4 + k) % M.nz + M.nz) % M.nz;
     const uint32_t xAb = uint32_t(zA) * M.pb + M.vxy[4];  // byte offset of (x, y, zA) in a population array
-    const uint32_t mA = (PULL && coll && tgA > 0) ? M.mkA : 0u;
-    const bool wave_links = PULL && __any(mA != 0u);
-    constexpr int NE = EARLY ? 18 : 1;
-    C la[NE], lF[NE], lo[NE];
-    if (EARLY && PULL && wave_links) link_loads<S, C, 0, NE>(M, mA, tgA, xAb, la, lF, lo);
-    // wettability factor of a wall node of plane r-1 (psi below); other lanes read nothing
-    const int tgm = M.s_tag[(k - 1) & 3][t];
-    const double phv = Buf<double>::ld(M.phi, (k >= 1 && tgm <= -2) ? uint32_t(-tgm - 2) * 8u : OOB);
+    // wettability factor of a wall node of plane r-1 (psi below), loaded with that plane's pull
+    const double phv = M.phA;
     __builtin_amdgcn_sched_barrier(0);
-    // ---- plane r+1 populations (PF, else plane r), plane r+3 tags, plane r+2 link bits
+    // ---- plane r+1 populations and wettability factors (PF, else plane r), tags of plane r+3.
+    // The tags run three planes ahead of the pull: the loads that depend on a tag then wait for
+    // nothing newer than plane r-1, and the pulls of planes r and r+1 are in flight together.
     {
         const int z1 = zinc(M.zc, M.nz), z2 = zinc(z1, M.nz), z3 = zinc(z2, M.nz);
+        const int tgp = PF ? M.tg_r1 : M.tg_r;
         if (PF)
-            pull_plane<S, C, PULL>(M, z1, M.mk_r1, fN);
+            pull_plane<S, C, PULL>(M, z1, tgp, fN);
         else
-            pull_plane<S, C, PULL>(M, M.zc, M.mk_r, fC);
-        const int tg3 = ld_i32(M.tag, uint32_t(z3) * M.p4 + M.own4);
-        const uint32_t mk2 = uint32_t(ld_i32(M.msk, M.tg_r2 > 0 ? uint32_t(z2) * M.p4 + M.own4 : OOB));
-        M.tg_r = M.tg_r1; M.mk_r = M.mk_r1;
-        M.tg_r1 = M.tg_r2; M.mk_r1 = mk2;
+            pull_plane<S, C, PULL>(M, M.zc, tgp, fC);
+        const double phN = Buf<double>::ld(M.phi, tgp <= -2 ? uint32_t(-tgp - 2) * 8u : OOB);
+        const int tg3 = ld_i32(M.tag, M.own4, uint32_t(z3) * M.p4);
+        M.tg_r = M.tg_r1;
+        M.tg_r1 = M.tg_r2;
         M.tg_r2 = tg3;
         M.zc = z1;
+        if (PF) {
+            M.phA = M.phB;
+            M.phB = phN;
+        } else {
+            M.phA = phN;  // plane r, used at the next iteration as plane r-1
+        }
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- A: density of plane r
@@ -222,37 +184,18 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
         M.s_psi[s_mid][t] = tg == -1 ? C(0) : psi_val(rho_n, a.eos, &M.bad);
     }
     __syncthreads();
-    // ---- C: boundary links, force and collision of plane r - 2; colliding lanes store
+    // ---- C: force and collision of plane r - 2; colliding lanes store.  Waves that hold no
+    // output column skip the arithmetic but still issue the (out-of-bounds) stores.
     C out[19];
-    C Fl[18];
+    C Fx = C(0), Fy = C(0), Fz = C(0);
 #pragma unroll
     for (int i = 0; i < 19; ++i) out[i] = C(0);
+    if (__any(coll)) {
+        // the node's density at t+1 from the pulled values; the collision hands all of it back,
+        // with f_0 taking the rounding
+        C rs = C(0);
 #pragma unroll
-    for (int j = 0; j < 18; ++j) Fl[j] = C(0);
-    const uint32_t mk = (coll && tgA > 0) ? M.mkA : 0u;
-    const bool wave_mk = __any(mk != 0u);
-    if (k >= 4 && __any(coll)) {
-        // the node's density at t+1 from the pulled values (eq. 18 keeps it through the link
-        // corrections); the collision hands all of it back, with f_0 taking the rounding
-        C rs_pull = C(0);
-#pragma unroll
-        for (int i = 0; i < 19; ++i) rs_pull += fA[i];
-        if (wave_links) {
-            C dsum = C(0);
-            if constexpr (EARLY) {
-                link_apply<C, 0, 18>(fA, mA, la, lF, lo, dsum);
-            } else {
-                C ba[6], bF[6], bo[6];
-                link_loads<S, C, 0, 6>(M, mA, tgA, xAb, ba, bF, bo);
-                link_apply<C, 0, 6>(fA, mA, ba, bF, bo, dsum);
-                link_loads<S, C, 6, 6>(M, mA, tgA, xAb, ba, bF, bo);
-                link_apply<C, 6, 6>(fA, mA, ba, bF, bo, dsum);
-                link_loads<S, C, 12, 6>(M, mA, tgA, xAb, ba, bF, bo);
-                link_apply<C, 12, 6>(fA, mA, ba, bF, bo, dsum);
-            }
-            fA[0] += dsum;
-            Buf<double>::st(M.dm, mA ? uint32_t(tgA - 1) * 8u : OOB, double(dsum));
-        }
+        for (int i = 0; i < 19; ++i) rs += fA[i];
         const int sl = (k - 3) & 3, sm = (k - 2) & 3, sh = (k - 1) & 3;
         const int lx = t % TX, ly = t / TX;
         const int tc = min(max(ly, 1), TY - 2) * TX + min(max(lx, 1), TX - 2);
@@ -265,13 +208,10 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
         const C exy1 = P(1, 1, 0) - P(-1, -1, 0), exy2 = P(1, -1, 0) - P(-1, 1, 0);
         const C exz1 = P(1, 0, 1) - P(-1, 0, -1), exz2 = P(1, 0, -1) - P(-1, 0, 1);
         const C eyz1 = P(0, 1, 1) - P(0, -1, -1), eyz2 = P(0, 1, -1) - P(0, -1, 1);
-        const C Fx = gp * (C(1.0 / 6.0) * (P(1, 0, 0) - P(-1, 0, 0)) + C(1.0 / 12.0) * (exy1 + exy2 + exz1 + exz2));
-        const C Fy = gp * (C(1.0 / 6.0) * (P(0, 1, 0) - P(0, -1, 0)) + C(1.0 / 12.0) * (exy1 - exy2 + eyz1 + eyz2));
-        const C Fz = gp * (C(1.0 / 6.0) * (P(0, 0, 1) - P(0, 0, -1)) + C(1.0 / 12.0) * (exz1 - exz2 + eyz1 - eyz2));
+        Fx = gp * (C(1.0 / 6.0) * (P(1, 0, 0) - P(-1, 0, 0)) + C(1.0 / 12.0) * (exy1 + exy2 + exz1 + exz2));
+        Fy = gp * (C(1.0 / 6.0) * (P(0, 1, 0) - P(0, -1, 0)) + C(1.0 / 12.0) * (exy1 - exy2 + eyz1 + eyz2));
+        Fz = gp * (C(1.0 / 6.0) * (P(0, 0, 1) - P(0, 0, -1)) + C(1.0 / 12.0) * (exz1 - exz2 + eyz1 - eyz2));
 
-        C rs = C(0);
-#pragma unroll
-        for (int i = 0; i < 19; ++i) rs += fA[i];
         const C rho = rs + a.rho_ref;
         const C irho = rcp(coll ? rho : C(1));
         const C jx = (fA[1] - fA[2]) + (fA[7] - fA[8]) + (fA[9] - fA[10]) + (fA[11] - fA[12]) + (fA[13] - fA[14]);
@@ -314,40 +254,20 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
             out[i] = Buf<S>::round(out[i]);
             rest += out[i];
         }
-        out[0] = rs_pull - rest;
-        if (wave_mk) {
-            // forcing terms (eq. 13) of the link directions, kept for eqs. 16-17 of the next step
-            auto fpair = [&](int jp, int jm, C w, C ed, C es) {
-                const C fs = C(4.5) * ed * es - duu15;
-                const C fa3 = C(3) * ed;
-                Fl[jp - 1] = w * rho * (fs + fa3);
-                Fl[jm - 1] = w * rho * (fs - fa3);
-            };
-            fpair(1, 2, wa, dux, sx2);
-            fpair(3, 4, wa, duy, sy2);
-            fpair(5, 6, wa, duz, sz2);
-            fpair(7, 8, we, dux + duy, sx2 + sy2);
-            fpair(9, 10, we, dux - duy, sx2 - sy2);
-            fpair(11, 12, we, dux + duz, sx2 + sz2);
-            fpair(13, 14, we, dux - duz, sx2 - sz2);
-            fpair(15, 16, we, duy + duz, sy2 + sz2);
-            fpair(17, 18, we, duy - duz, sy2 - sz2);
-        }
+        out[0] = rs - rest;
     }
-    // a lane that does not store starts from OOB; the saturating add keeps it out of bounds
-    const uint32_t xst = coll ? xAb : OOB;
+    // Every output column stores, solid nodes included: their slots carry nothing the step reads
+    // (the boundary pass overwrites the ones the pull takes), and rows written without holes keep
+    // every cache line whole.  A lane that does not store starts from OOB; the saturating add
+    // keeps it out of bounds.
+    const uint32_t xst = (k >= 4 && M.out_col) ? xAb : OOB;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) Buf<S>::st(M.fb, __builtin_elementwise_add_sat(xst, uint32_t(i) * M.ns), out[i]);
-    if (wave_mk) {
-        // every slot of a boundary node (those without a link are never read)
-        const uint32_t base = mk ? M.F0 + uint32_t(tgA - 1) * uint32_t(Q3_LINKS * sc) : OOB;
-#pragma unroll
-        for (int j = 1; j < 19; ++j) Buf<C>::st(M.rec, base + uint32_t(j - 1) * sc, Fl[j - 1]);
-    }
-    (void)s;
+    for (int i = 0; i < 19; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), out[i]);
+    // force of a boundary node, for the forcing terms of the next boundary pass
+    st_force<C>(M.Fv, (coll && tgA > 0) ? uint32_t(tgA - 1) * (4 * sc) : OOB, Fx, Fy, Fz);
 }
 
-template <class S, class C, bool PULL, bool EARLY, bool PF>
+template <class S, class C, bool PULL, bool PF>
 __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
     // XCD-aware order: consecutive logical tiles (neighbours in x) go to the same XCD (one L2)
     const int bid = blockIdx.x;
@@ -393,29 +313,28 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
     M.fa = make_res(a.fa, uint64_t(19) * M.ns);
     M.fb = make_res(a.fb, uint64_t(19) * M.ns);
     M.tag = make_res(a.tag, uint64_t(nxy) * a.nz * 4);
-    M.msk = make_res(a.nmask, uint64_t(nxy) * a.nz * 4);
-    M.rec = make_res(a.lk_rec, uint64_t(a.n_slots) * 2 * sizeof(C));
-    M.F0 = a.n_slots * uint32_t(sizeof(C));
-    M.dm = make_res(a.dm, uint64_t(a.n_bnodes) * 8);
+    M.f0c = make_res(a.f0c, uint64_t(a.n_bnodes) * sizeof(C));
+    M.Fv = make_res(a.Fv, uint64_t(a.n_bnodes) * 4 * sizeof(C));
     M.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
     M.tgA = M.tgB = M.tgC = -1;
-    M.mkA = M.mkB = M.mkC = 0u;
     M.bad = false;
-    // prologue: tags of planes r, r+1, r+2, link bits of r and r+1, populations of plane r (PF)
+    // prologue: tags of planes r and r+1, populations of plane r (PF)
     C fA[19], fB[19], fC[19], fN[19];
 #pragma unroll
     for (int i = 0; i < 19; ++i) fA[i] = fB[i] = fC[i] = fN[i] = C(0);
     M.zc = ((M.z0 - 2) % a.nz + a.nz) % a.nz;
-    const int z1 = zinc(M.zc, a.nz), z2 = zinc(z1, a.nz);
-    M.tg_r = ld_i32(M.tag, uint32_t(M.zc) * M.p4 + M.own4);
-    M.tg_r1 = ld_i32(M.tag, uint32_t(z1) * M.p4 + M.own4);
-    M.tg_r2 = ld_i32(M.tag, uint32_t(z2) * M.p4 + M.own4);
-    M.mk_r = uint32_t(ld_i32(M.msk, M.tg_r > 0 ? uint32_t(M.zc) * M.p4 + M.own4 : OOB));
-    M.mk_r1 = uint32_t(ld_i32(M.msk, M.tg_r1 > 0 ? uint32_t(z1) * M.p4 + M.own4 : OOB));
-    if (PF) pull_plane<S, C, PULL>(M, M.zc, M.mk_r, fC);
+    M.tg_r = ld_i32(M.tag, M.own4, uint32_t(M.zc) * M.p4);
+    M.tg_r1 = ld_i32(M.tag, M.own4, uint32_t(zinc(M.zc, a.nz)) * M.p4);
+    M.tg_r2 = ld_i32(M.tag, M.own4, uint32_t(zinc(zinc(M.zc, a.nz), a.nz)) * M.p4);
+    M.phA = 0.0;
+    M.phB = 0.0;
+    if (PF) {
+        pull_plane<S, C, PULL>(M, M.zc, M.tg_r, fC);
+        M.phB = Buf<double>::ld(M.phi, M.tg_r <= -2 ? uint32_t(-M.tg_r - 2) * 8u : OOB);
+    }
     // the register sets rotate by copies (an unrolled rotation costs the allocator far more)
     for (int k = 0; k < M.iters; ++k) {
-        march_plane<S, C, PULL, EARLY, PF>(M, k, fA, fB, fC, fN);
+        march_plane<S, C, PULL, PF>(M, k, fA, fB, fC, fN);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             fA[i] = fB[i];
@@ -432,14 +351,12 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
     a.fa = static_cast<const S*>(fcur);
     a.fb = static_cast<S*>(fnext);
     a.tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
-    a.nmask = reinterpret_cast<const uint32_t*>(c->lat + c->L.nmask);
-    a.lk_rec = reinterpret_cast<C*>(c->lk + c->L.lk_rec);
-    a.dm = reinterpret_cast<double*>(c->lk + c->L.dm);
+    a.f0c = reinterpret_cast<const C*>(c->lk + c->L.lk_f0c);
+    a.Fv = reinterpret_cast<C*>(c->lk + c->L.lk_Fv);
     a.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
     a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
     a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
     a.n_wall = uint32_t(c->n_wall > 0 ? c->n_wall : 0);
-    a.n_slots = uint32_t(c->L.rec_slots);
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.nz = c->p.nz;
@@ -457,11 +374,11 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
     a.eos.a = C(c->p.eos_a);
     a.eos.b4 = C(c->p.eos_b / 4.0);
     a.eos.two_over_G = C(2.0 / c->p.G);
-    constexpr bool FAST = sizeof(C) == 4;
+    constexpr bool PF = sizeof(C) == 4;
     if (pull)
-        hipLaunchKernelGGL((k_step3d<S, C, true, FAST, FAST>), dim3(a.nblocks), dim3(NT), 0, c->stream, a);
+        hipLaunchKernelGGL((k_step3d<S, C, true, PF>), dim3(a.nblocks), dim3(NT), 0, c->stream, a);
     else
-        hipLaunchKernelGGL((k_step3d<S, C, false, FAST, FAST>), dim3(a.nblocks), dim3(NT), 0, c->stream, a);
+        hipLaunchKernelGGL((k_step3d<S, C, false, PF>), dim3(a.nblocks), dim3(NT), 0, c->stream, a);
     return hipGetLastError();
 }
 

@@ -201,6 +201,36 @@ def test_c1_full_size_one_step_parity(mcb):
     assert rel_err(lat.get_f(), sim.get_f(), fluid) < 1e-11
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32s", 3e-6), ("f16s", 3e-3)])
+def test_wide_strip_path_parity(mcb, prec, tol):
+    """Lattices above 2^21 nodes take the cache-line-aligned wide strips (224 or 448 output
+    columns, ragged last strip); one oracle-checked run of three steps."""
+    banner(f"wide-strip path, 2100x1030, {prec}")
+    dims = (2100, 1030, 1)
+    rng = np.random.default_rng(77)
+    shapes = W.random_links_case(rng, dims, 2, 40, 6.0, 20.0)
+    rv, rl = W.MAXWELL[0.7]
+    drops = [((rng.uniform(0, dims[0]), rng.uniform(0, dims[1])), rng.uniform(15, 40)) for _ in range(12)]
+    rho = W.drop_field(dims, 2, drops, rv, rl, 2.0)
+    T = 0.7 * TC
+    P = oracle.make_params(2, *dims, tau=0.9, T=T)
+    sim, (solid, *_r) = oracle.sim_from_shapes(P, shapes)
+    phi = rng.uniform(0.9, 1.1, sim.n_wall)
+    sim.set_phi(phi)
+    lat = mcb.Lattice(2, dims, 0.9, T, precision=prec, rho_ref=0.0 if prec == "f64" else rv)
+    lat.set_geometry(shapes)
+    lat.set_wettability(phi)
+    sim.init_eq(rho)
+    lat.init_equilibrium(rho)
+    fluid = solid == 0
+    for k in range(1, 4):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < tol * (k + 1), (k, e)
+    lat.close()
+
+
 def test_half_q_gives_zero_compensation_on_gpu(mcb):
     banner("q = 1/2 everywhere: dM == 0 exactly")
     wl = W.make("c0")
