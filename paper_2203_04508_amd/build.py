@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcb.so")
-SOURCES = ["api.hip", "geometry.hip", "boundary.hip", "step2d.hip", "step3d.hip", "monitor.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "geometry.hip", "step2d.hip", "step3d.hip", "monitor.hip", "adjoint.hip"]
 ARCH = os.environ.get("MCB_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

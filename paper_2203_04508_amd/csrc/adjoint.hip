@@ -469,7 +469,7 @@ AdjDev make_dev(const mcb_ctx* c) {
     A.nmask = reinterpret_cast<const uint32_t*>(c->lat + c->L.nmask);
     A.bn_link0 = reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0);
     A.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
-    A.fs = int(c->L.fv_stride);
+    A.fs = int(c->L.rec_stride);
     A.tau = c->p.tau;
     A.G = c->p.G;
     A.RT = c->p.eos_R * c->p.eos_T;
@@ -485,8 +485,10 @@ hipError_t adj_step_t(mcb_ctx* c, const AdjWork& w, const void* gt, const void* 
     const AdjDev A = make_dev(c);
     const unsigned G = grid_for(c->g.N);
     const RC* rec = reinterpret_cast<const RC*>(c->lk + c->L.lk_a);
-    hipLaunchKernelGGL((k_recompute<S, RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt), rec,
-                       static_cast<const RC*>(fv), pull, w.rho0, w.p, w.rho);
+    // the force of each boundary node follows its Q populations in the boundary record of time t
+    const RC* Fv = fv ? static_cast<const RC*>(fv) + c->g.Q : nullptr;
+    hipLaunchKernelGGL((k_recompute<S, RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt), rec, Fv, pull,
+                       w.rho0, w.p, w.rho);
     hipLaunchKernelGGL(k_psi, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.dpsi, w.rave, w.den);
     hipLaunchKernelGGL(k_collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar, w.Fv);
     hipLaunchKernelGGL(k_psi_T, dim3(G), dim3(256), 0, c->stream, A, w.psi, w.dpsi, w.rave, w.den, w.Fbar, w.rbar, w.qbar, w.dphi);

@@ -42,23 +42,19 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.bn_node = take(4 * nb);
     L.bn_mask = take(4 * nb);
     L.bn_link0 = take(4 * nb);
-    L.dm = take(8 * nb);
     L.lk_qc = take(4 * nl);
     // per boundary node: the signed interpolation coefficient a of each direction's link (fixed
-    // slots), the force F (for the forcing terms of eqs. 16-17 one step later) and the rest
-    // population with the eq. 18 correction
+    // slots), and the boundary records of the two lattice buffers (records of fa, records of fb)
     L.rec_slots = (p.dim == 2 ? Q2_LINKS : Q3_LINKS) * nb;
-    L.fv_stride = p.dim == 2 ? 2 : 4;
+    L.rec_stride = p.dim == 2 ? REC2 : REC3;
     L.lk_a = take(cb * L.rec_slots);
-    L.lk_Fv = take(cb * L.fv_stride * nb);
-    L.lk_f0c = take(cb * nb);
+    L.rec[0] = take(cb * L.rec_stride * nb);
+    L.rec[1] = take(cb * L.rec_stride * nb);
     L.wl_node = take(4 * nw);
     L.wl_phi = take(8 * nw);
     L.links_bytes = (nb + nl + nw) > 0 ? o : 0;
     return L;
 }
-
-hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
 
 AdjPlan adj_plan(const mcb_ctx* c, int64_t nsteps, int64_t k) {
     AdjPlan a{};
@@ -69,7 +65,7 @@ AdjPlan adj_plan(const mcb_ctx* c, int64_t nsteps, int64_t k) {
     a.nck = nsteps == 0 ? 1 : (nsteps + k - 1) / k;
     a.state_b = align256(Q * N * storage_bytes(c->p.precision));
     a.nslots = c->L.rec_slots;
-    a.rec_b = align256(cb * c->L.fv_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0));
+    a.rec_b = align256(cb * c->L.rec_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0));
     int64_t o = 0;
     auto take = [&](int64_t bytes) { const int64_t at = o; o = align256(o + bytes); return at; };
     a.rho0 = take(8 * N);
@@ -77,7 +73,6 @@ AdjPlan adj_plan(const mcb_ctx* c, int64_t nsteps, int64_t k) {
     a.ck_rec = take(a.nck * a.rec_b);
     a.seg = take((k - 1) * a.state_b);
     a.seg_rec = take((k - 1) * a.rec_b);
-    a.final_rec = take(a.rec_b);
     for (int b = 0; b < 2; ++b) {
         a.lam[b] = take(8 * Q * N);
         a.lamR[b] = take(8 * (a.nslots > 0 ? a.nslots : 1));
@@ -154,6 +149,9 @@ bool params_ok(const mcb_params* p, const char** why) {
 
 void* fcur(mcb_ctx* c) { return c->lat + (c->swapped ? c->L.fb : c->L.fa); }
 void* fnext(mcb_ctx* c) { return c->lat + (c->swapped ? c->L.fa : c->L.fb); }
+// boundary records of the current and the next state (each lattice buffer has its own)
+void* rcur(mcb_ctx* c) { return c->lk + c->L.rec[c->swapped ? 1 : 0]; }
+void* rnext(mcb_ctx* c) { return c->lk + c->L.rec[c->swapped ? 0 : 1]; }
 
 mcb_status check_flags(mcb_ctx* c, int64_t* n_domain_out) {
     int32_t flags[FLAG_COUNT];
@@ -325,8 +323,8 @@ mcb_status mcb_build_links(mcb_ctx* c, int32_t phase, int64_t* n_links, int64_t*
         HIPCHK(hipStreamSynchronize(c->stream));
         if (tot[0] >= (int64_t(1) << 31)) return fail(c, MCB_ENOTSUP, "too many links");
         if (c->g.dim == 2 && tot[1] >= (int64_t(1) << 23)) return fail(c, MCB_ENOTSUP, "2-D tags hold at most 2^23 boundary nodes");
-        if (tot[1] * (c->g.Q - 1) * 2 * compute_bytes(c->p.precision) > int64_t(0xFFFFFE00u))
-            return fail(c, MCB_ENOTSUP, "link records exceed 4 GiB");
+        if (tot[1] * (c->g.dim == 2 ? REC2 : REC3) * compute_bytes(c->p.precision) > int64_t(0xFFFFFE00u))
+            return fail(c, MCB_ENOTSUP, "boundary records exceed 4 GiB");
         c->n_links = tot[0];
         c->n_bnodes = tot[1];
         c->n_wall = tot[2];
@@ -413,8 +411,9 @@ mcb_status mcb_set_wettability(mcb_ctx* c, const double* phi, int64_t n_wall) {
 
 static mcb_status collide_from(mcb_ctx* c, void* fpre) {
     // fpre holds pre-collision populations in storage format; the collision writes the other lattice
-    void* dst = (fpre == c->lat + c->L.fb) ? c->lat + c->L.fa : c->lat + c->L.fb;
-    HIPCHK(step_fused(c, fpre, dst, false));
+    const bool to_fb = fpre != c->lat + c->L.fb;
+    void* dst = to_fb ? c->lat + c->L.fb : c->lat + c->L.fa;
+    HIPCHK(step_fused(c, fpre, nullptr, dst, c->lk + c->L.rec[to_fb ? 1 : 0], false));
     c->swapped = dst == c->lat + c->L.fb;
     c->t = 0;
     c->stage = 5;
@@ -491,11 +490,11 @@ mcb_status mcb_step(mcb_ctx* c, int64_t n) {
             mcb_status st = drain_slot(c, r);
             if (st) return st;
             HIPCHK(hipEventRecord(c->ev[r][0], c->stream));
-            HIPCHK(step_fused(c, fcur(c), fnext(c), true));
+            HIPCHK(step_fused(c, fcur(c), rcur(c), fnext(c), rnext(c), true));
             HIPCHK(hipEventRecord(c->ev[r][1], c->stream));
             c->ev_pending[r] = true;
         } else {
-            HIPCHK(step_fused(c, fcur(c), fnext(c), true));
+            HIPCHK(step_fused(c, fcur(c), rcur(c), fnext(c), rnext(c), true));
         }
         c->swapped = !c->swapped;
         ++c->t;
@@ -557,21 +556,19 @@ mcb_status mcb_adj_forward(mcb_ctx* c, const double* rho0, int64_t nsteps, int64
     mcb_status st = mcb_init_equilibrium(c, rho0, nullptr);
     if (st) return st;
     HIPCHK(hipMemcpyAsync(c->adj + a.rho0, rho0, 8 * c->g.N, hipMemcpyHostToDevice, c->stream));
-    char* rec = c->lk + c->L.lk_Fv;
-    const int64_t rec_used = compute_bytes(c->p.precision) * c->L.fv_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0);
+    const int64_t rec_used = compute_bytes(c->p.precision) * c->L.rec_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0);
     for (int64_t t = 0;; ++t) {
         if (t % k == 0 && t / k < a.nck) {
             HIPCHK(hipMemcpyAsync(c->adj + a.ck + (t / k) * a.state_b, fcur(c), c->g.Q * c->g.N * storage_bytes(c->p.precision),
                                   hipMemcpyDeviceToDevice, c->stream));
             if (rec_used > 0)
-                HIPCHK(hipMemcpyAsync(c->adj + a.ck_rec + (t / k) * a.rec_b, rec, rec_used, hipMemcpyDeviceToDevice, c->stream));
+                HIPCHK(hipMemcpyAsync(c->adj + a.ck_rec + (t / k) * a.rec_b, rcur(c), rec_used, hipMemcpyDeviceToDevice, c->stream));
         }
         if (t == nsteps) break;
-        HIPCHK(step_fused(c, fcur(c), fnext(c), true));
+        HIPCHK(step_fused(c, fcur(c), rcur(c), fnext(c), rnext(c), true));
         c->swapped = !c->swapped;
         ++c->t;
     }
-    if (rec_used > 0) HIPCHK(hipMemcpyAsync(c->adj + a.final_rec, rec, rec_used, hipMemcpyDeviceToDevice, c->stream));
     const AdjWork w = adj_work(c);
     HIPCHK(adj_loss(c, w, fcur(c), kind, prm, 0.0, nullptr));
     double sums[2];
@@ -593,8 +590,6 @@ mcb_status mcb_adj_backward(mcb_ctx* c, double dloss, double* dphi) {
     if (c->n_wall > 0 && !dphi) return fail(c, MCB_EINVAL, "dphi missing");
     const AdjPlan& a = c->ap;
     const AdjWork w = adj_work(c);
-    const int64_t rec_used = compute_bytes(c->p.precision) * c->L.fv_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0);
-    char* rec = c->lk + c->L.lk_Fv;
     auto lam = [&](int b) { return reinterpret_cast<double*>(c->adj + a.lam[b]); };
     auto lamR = [&](int b) { return reinterpret_cast<double*>(c->adj + a.lamR[b]); };
     mcb_status st = clear_flags(c);
@@ -608,16 +603,15 @@ mcb_status mcb_adj_backward(mcb_ctx* c, double dloss, double* dphi) {
         if (t0 >= t1) continue;
         char* ck = c->adj + a.ck + sg * a.state_b;
         char* ckr = c->adj + a.ck_rec + sg * a.rec_b;
-        // recompute the states t0+1 .. t1-1 of the segment (the step kernel updates the forcing
-        // terms of the link records in place; each step's records are kept beside its state)
-        if (rec_used > 0) HIPCHK(hipMemcpyAsync(rec, ckr, rec_used, hipMemcpyDeviceToDevice, c->stream));
+        // recompute the states t0+1 .. t1-1 of the segment, each with its boundary records
         const char* prev = ck;
+        const char* prev_rec = ckr;
         for (int64_t t = t0 + 1; t < t1; ++t) {
             char* dst = c->adj + a.seg + (t - t0 - 1) * a.state_b;
-            HIPCHK(step_fused(c, prev, dst, true));
-            if (rec_used > 0)
-                HIPCHK(hipMemcpyAsync(c->adj + a.seg_rec + (t - t0 - 1) * a.rec_b, rec, rec_used, hipMemcpyDeviceToDevice, c->stream));
+            char* dst_rec = c->adj + a.seg_rec + (t - t0 - 1) * a.rec_b;
+            HIPCHK(step_fused(c, prev, prev_rec, dst, dst_rec, true));
             prev = dst;
+            prev_rec = dst_rec;
         }
         for (int64_t t = t1 - 1; t >= t0; --t) {
             const void* gt = t == t0 ? static_cast<const void*>(ck) : c->adj + a.seg + (t - t0 - 1) * a.state_b;
@@ -629,7 +623,6 @@ mcb_status mcb_adj_backward(mcb_ctx* c, double dloss, double* dphi) {
     // the first collision, from f^eq(rho0, 0)
     HIPCHK(adj_step(c, w, nullptr, nullptr, 0, lam(cur), lamR(cur), nullptr, nullptr));
     if (c->n_wall > 0) HIPCHK(hipMemcpyAsync(dphi, w.dphi, 8 * c->n_wall, hipMemcpyDeviceToHost, c->stream));
-    if (rec_used > 0) HIPCHK(hipMemcpyAsync(rec, c->adj + a.final_rec, rec_used, hipMemcpyDeviceToDevice, c->stream));
     return check_flags(c, nullptr);
 }
 
@@ -673,7 +666,7 @@ mcb_status mcb_mass(mcb_ctx* c, mcb_mass_report* out) {
     if (!c) return MCB_EINVAL;
     if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
     if (!out) return fail(c, MCB_EINVAL, "report missing");
-    HIPCHK(monitor(c, fcur(c)));
+    HIPCHK(monitor(c, fcur(c), rcur(c)));
     double r[MON_FIELDS];
     HIPCHK(hipMemcpyAsync(r, c->lat + c->L.result, sizeof r, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -704,14 +697,10 @@ mcb_status mcb_sync(mcb_ctx* c) {
 }  // extern "C"
 
 namespace mcb {
-hipError_t step2d(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
-hipError_t step3d(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
+hipError_t step2d(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull);
+hipError_t step3d(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull);
 
-hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
-    if (pull) {
-        const hipError_t e = boundary_pass(c, const_cast<void*>(fcur));
-        if (e != hipSuccess) return e;
-    }
-    return c->g.dim == 2 ? step2d(c, fcur, fnext, pull) : step3d(c, fcur, fnext, pull);
+hipError_t step_fused(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
+    return c->g.dim == 2 ? step2d(c, fcur, rcur, fnext, rnext, pull) : step3d(c, fcur, rcur, fnext, rnext, pull);
 }
 }  // namespace mcb

@@ -179,7 +179,6 @@ struct FillOut {
     int32_t* bn_node;
     uint32_t* bn_mask;
     int32_t* bn_link0;
-    double* dm;
     uint32_t* lk_qc;
     int32_t* wl_node;
     double* wl_phi;
@@ -204,7 +203,6 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_fill(GridDev g, int L, const uin
             o.bn_node[bpre] = int32_t(x);
             o.bn_mask[bpre] = mask;
             o.bn_link0[bpre] = int32_t(lpre);
-            o.dm[bpre] = 0.0;
             const int nl = __popc(mask);
             for (int k = 0; k < nl; ++k) o.lk_qc[lpre + k] = NOHIT;
         } else {
@@ -318,16 +316,15 @@ __global__ void k_q_band(Bands b, GridDev g, int L, int64_t nb, const int32_t* _
     }
 }
 
-// Class from q and the second fluid node, and the link record used by the step: the eq. 16-17
-// value is t + a (f~_j(x1) - t) with t = (f~_j(x2) or f~_opp(j)(x1)) + F_j, so the record holds
-// a = 2q (eq. 16), a = 1/(2q) stored negated to mark eq. 17, or a = 1 (bounce-back), next to the
-// forcing term F_j (zeroed here, written by every collision).  Flags links no shape was found for.
+// Class from q and the second fluid node, and the link coefficient used by the step: the eq. 16-17
+// value is t + a (f~_j(x1) - t) with t = (f~_j(x2) or f~_opp(j)(x1)) + F_j, so the slot holds
+// a = 2q (eq. 16), a = 1/(2q) stored negated to mark eq. 17, or a = 1 (bounce-back); slots of
+// directions without a link hold NO_LINK.  Flags links no shape was found for.
 __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict__ solid, const int32_t* __restrict__ bn_node,
                         const uint32_t* __restrict__ bn_mask, const int32_t* __restrict__ bn_link0, uint32_t* lk_qc,
-                        void* rec, void* rec_fv, int fv_stride, int rec_double, int32_t* flags) {
-    // coefficient a per slot = boundary index * (Q - 1) + direction - 1; the force of each boundary
-    // node (rec_fv, fv_stride per node) starts at zero
-    const int64_t QL = g.Q - 1;
+                        void* rec, int rec_double, int32_t* flags) {
+    // coefficient a per slot = boundary index * slots per node + direction - 1
+    const int64_t QL = g.dim == 2 ? Q2_LINKS : Q3_LINKS;
     for (int64_t bi = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; bi < nb; bi += int64_t(gridDim.x) * blockDim.x) {
         const int64_t x = bn_node[bi];
         const uint32_t mask = bn_mask[bi];
@@ -335,7 +332,7 @@ __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict_
         coords(g, x, c);
         int l = bn_link0[bi];
         for (int i = 1; i < g.Q; ++i) {
-            double a = 1.0;  // slots of directions without a link: never used by the step
+            double a = NO_LINK;
             if ((mask >> i) & 1u) {
                 uint32_t q = lk_qc[l] & (NOHIT >> 2);
                 if (q > uint32_t(ONE)) {
@@ -354,9 +351,9 @@ __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict_
             if (rec_double) static_cast<double*>(rec)[slot] = a;
             else static_cast<float*>(rec)[slot] = float(a);
         }
-        for (int k = 0; k < fv_stride; ++k) {
-            if (rec_double) static_cast<double*>(rec_fv)[bi * fv_stride + k] = 0.0;
-            else static_cast<float*>(rec_fv)[bi * fv_stride + k] = 0.0f;
+        for (int64_t i = g.Q - 1; i < QL; ++i) {
+            if (rec_double) static_cast<double*>(rec)[bi * QL + i] = NO_LINK;
+            else static_cast<float*>(rec)[bi * QL + i] = float(NO_LINK);
         }
     }
 }
@@ -405,7 +402,6 @@ hipError_t geom_fill(mcb_ctx* c) {
     o.bn_node = reinterpret_cast<int32_t*>(c->lk + c->L.bn_node);
     o.bn_mask = reinterpret_cast<uint32_t*>(c->lk + c->L.bn_mask);
     o.bn_link0 = reinterpret_cast<int32_t*>(c->lk + c->L.bn_link0);
-    o.dm = reinterpret_cast<double*>(c->lk + c->L.dm);
     o.lk_qc = reinterpret_cast<uint32_t*>(c->lk + c->L.lk_qc);
     o.wl_node = reinterpret_cast<int32_t*>(c->lk + c->L.wl_node);
     o.wl_phi = reinterpret_cast<double*>(c->lk + c->L.wl_phi);
@@ -436,8 +432,16 @@ hipError_t geom_reclass(mcb_ctx* c) {
                        reinterpret_cast<const uint32_t*>(c->lk + c->L.bn_mask),
                        reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0),
                        reinterpret_cast<uint32_t*>(c->lk + c->L.lk_qc), static_cast<void*>(c->lk + c->L.lk_a),
-                       static_cast<void*>(c->lk + c->L.lk_Fv), int(c->L.fv_stride), c->p.precision == MCB_F64 ? 1 : 0, flags);
-    return hipGetLastError();
+                       c->p.precision == MCB_F64 ? 1 : 0, flags);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // both buffers of boundary records start empty (the first collision writes them)
+    const size_t rb = size_t(compute_bytes(c->p.precision) * c->L.rec_stride * c->n_bnodes);
+    for (int b = 0; b < 2; ++b) {
+        const hipError_t e2 = hipMemsetAsync(c->lk + c->L.rec[b], 0, rb, c->stream);
+        if (e2 != hipSuccess) return e2;
+    }
+    return hipSuccess;
 }
 
 }  // namespace mcb

@@ -96,6 +96,51 @@ __device__ inline int32_t ld_i32(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_
 // unsigned saturating add: an OOB lane offset stays out of bounds for any in-bounds addend
 __device__ inline uint32_t sat_add(uint32_t a, uint32_t b) { return __builtin_elementwise_add_sat(a, b); }
 
+// NV consecutive values of type C at byte offset off (a multiple of 16, or OOB) with 16-byte buffer
+// loads and stores (8 and 4 bytes for a remainder).  A lane at OOB reads zeros and writes nothing.
+template <class C, int NV>
+__device__ inline void ld_vec(__amdgpu_buffer_rsrc_t r, uint32_t off, C (&v)[NV]) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    constexpr int B = NV * int(sizeof(C));
+    static_assert(B % 4 == 0, "whole words");
+    uint32_t w[B / 4];
+    int k = 0;
+#pragma unroll
+    for (; k + 16 <= B; k += 16) {
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off + uint32_t(k), 0, 0);
+        w[k / 4] = x[0]; w[k / 4 + 1] = x[1]; w[k / 4 + 2] = x[2]; w[k / 4 + 3] = x[3];
+    }
+    if (k + 8 <= B) {
+        const u32x2 x = __builtin_amdgcn_raw_buffer_load_b64(r, off + uint32_t(k), 0, 0);
+        w[k / 4] = x[0]; w[k / 4 + 1] = x[1];
+        k += 8;
+    }
+    if (k + 4 <= B) w[k / 4] = __builtin_amdgcn_raw_buffer_load_b32(r, off + uint32_t(k), 0, 0);
+    __builtin_memcpy(v, w, B);
+}
+template <class C, int NV>
+__device__ inline void st_vec(__amdgpu_buffer_rsrc_t r, uint32_t off, const C (&v)[NV]) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    constexpr int B = NV * int(sizeof(C));
+    static_assert(B % 4 == 0, "whole words");
+    uint32_t w[B / 4];
+    __builtin_memcpy(w, v, B);
+    int k = 0;
+#pragma unroll
+    for (; k + 16 <= B; k += 16) {
+        const u32x4 x = {w[k / 4], w[k / 4 + 1], w[k / 4 + 2], w[k / 4 + 3]};
+        __builtin_amdgcn_raw_buffer_store_b128(x, r, sat_add(off, uint32_t(k)), 0, 0);
+    }
+    if (k + 8 <= B) {
+        const u32x2 x = {w[k / 4], w[k / 4 + 1]};
+        __builtin_amdgcn_raw_buffer_store_b64(x, r, sat_add(off, uint32_t(k)), 0, 0);
+        k += 8;
+    }
+    if (k + 4 <= B) __builtin_amdgcn_raw_buffer_store_b32(w[k / 4], r, sat_add(off, uint32_t(k)), 0, 0);
+}
+
 // reciprocal: IEEE division in FP64, the hardware reciprocal (1 ulp) in FP32
 __device__ inline double rcp(double x) { return 1.0 / x; }
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }

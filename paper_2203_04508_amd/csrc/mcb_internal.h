@@ -17,8 +17,14 @@ constexpr uint32_t QMASK = 0x1FFFFu;      // q_fixed in bits 0..16 of a packed l
 constexpr int CLS_SHIFT = 30;             // link class in bits 30..31
 
 constexpr int STRIP_HALO = 4;            // 2-D step: halo lanes per strip (two columns on each side)
-constexpr int Q2_LINKS = 8;               // fixed link-record slots per boundary node (one per direction)
-constexpr int Q3_LINKS = 18;
+constexpr int Q2_LINKS = 8;               // link-coefficient slots per boundary node: one per direction,
+constexpr int Q3_LINKS = 20;              // 3-D: and two unused ones, so every node's slots start on 16 bytes
+// Boundary record of a boundary-fluid node, written by its collision and read by the pull of the
+// next step: the post-collision populations as stored (Q values), the force F (dim values), the
+// eq. 18 correction that the pull of the step applied, and padding to a multiple of 16 bytes.
+constexpr int REC2 = 12;                  // 9 + 2 + 1
+constexpr int REC3 = 24;                  // 19 + 3 + 1 + 1
+constexpr double NO_LINK = 2.0;           // coefficient of a direction without a link (|a| <= 1 on links)
 constexpr int SCAN_BLOCK = 256;           // geometry scan granularity
 constexpr int MON_BLOCKS = 1024;          // monitor partial sums
 constexpr int MON_FIELDS = 8;             // M, Jx, Jy, Jz, dM, n_nan, spare, spare
@@ -52,9 +58,9 @@ struct Layout {
     // lattice arena
     int64_t fa, fb, tag, nmask, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
     // links arena
-    int64_t bn_node, bn_mask, bn_link0, dm, lk_qc, lk_a, lk_Fv, lk_f0c, wl_node, wl_phi, links_bytes;
-    int64_t rec_slots;  // link-coefficient slots: (Q - 1) per boundary node, one per direction
-    int64_t fv_stride;  // elements per boundary node in lk_Fv (2 in 2-D, 4 in 3-D)
+    int64_t bn_node, bn_mask, bn_link0, lk_qc, lk_a, rec[2], wl_node, wl_phi, links_bytes;
+    int64_t rec_slots;   // link-coefficient slots: Q2_LINKS / Q3_LINKS per boundary node
+    int64_t rec_stride;  // compute-type values per boundary record (REC2 / REC3)
 };
 
 Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64_t n_bnodes, int64_t n_wall);
@@ -63,7 +69,7 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
 // adjoint states and the work arrays of the transposed step.
 struct AdjPlan {
     int64_t nsteps, k, nck, state_b, rec_b, nslots;
-    int64_t rho0, ck, ck_rec, seg, seg_rec, final_rec, lam[2], lamR[2];
+    int64_t rho0, ck, ck_rec, seg, seg_rec, lam[2], lamR[2];
     int64_t p, pbar, rho, psi, dpsi, rave, den, rbar, qbar, Fbar, Fv, dphi, part, sums, bytes;
 };
 
@@ -123,12 +129,9 @@ hipError_t geom_count(mcb_ctx* c);                // block sums + scan, totals a
 hipError_t geom_fill(mcb_ctx* c);                 // tags, boundary-node / wall tables, q, class
 hipError_t geom_reclass(mcb_ctx* c);              // class from the current q (after an override)
 
-// boundary.hip: eqs. 16-18 for the step that starts from fcur (writes solid slots of fcur, the
-// corrected rest populations and Delta M per boundary node)
-hipError_t boundary_pass(mcb_ctx* c, void* fcur);
-
-// step2d.hip / step3d.hip (pull = true: boundary pass + bulk kernel)
-hipError_t step_fused(mcb_ctx* c, const void* fcur, void* fnext, bool pull);
+// step2d.hip / step3d.hip: one time step from the state (fcur, rcur) to (fnext, rnext), where r are
+// the boundary records of the state (pull = false: collision of fcur in place of the pull)
+hipError_t step_fused(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull);
 hipError_t init_feq(mcb_ctx* c, const double* rho, const double* u, void* fout);
 
 // adjoint.hip: one transposed step (pull = 0: the first collision from f^eq(rho0, 0)), and the
@@ -138,7 +141,7 @@ hipError_t adj_step(mcb_ctx* c, const AdjWork& w, const void* gt, const void* re
 hipError_t adj_loss(mcb_ctx* c, const AdjWork& w, const void* g, int kind, const double* prm, double dloss, double* lam);
 
 // monitor.hip
-hipError_t monitor(mcb_ctx* c, const void* fcur);
+hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur);
 hipError_t moments_out(mcb_ctx* c, const void* fcur, double* rho, double* v);
 hipError_t convert_plane_in(mcb_ctx* c, const double* src, void* dst_plane, int dir);
 hipError_t convert_plane_out(mcb_ctx* c, const void* src_plane, double* dst, int dir);

@@ -49,8 +49,8 @@ __device__ inline double wave_sum(double v) {
 // pass 1: fixed grid of MON_BLOCKS workgroups, fixed node assignment -> deterministic partials
 template <class S, class C>
 __global__ __launch_bounds__(256) void k_mon_partial(GridDev g, int L, const S* __restrict__ f, const int32_t* __restrict__ tag,
-                                                     double rho_ref, const double* __restrict__ dm, int64_t nb,
-                                                     double* __restrict__ partials) {
+                                                     double rho_ref, const C* __restrict__ rec, int rec_stride,
+                                                     int64_t nb, double* __restrict__ partials) {
     double acc[MON_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += stride) {
@@ -70,7 +70,9 @@ __global__ __launch_bounds__(256) void k_mon_partial(GridDev g, int L, const S* 
         acc[3] += jz;
         if (!isfinite(m) || !isfinite(jx) || !isfinite(jy) || !isfinite(jz)) acc[5] += 1.0;
     }
-    for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < nb; b += stride) acc[4] += dm[b];
+    // eq. 18 corrections that the last step applied, from the boundary records of the state
+    const int ds = g.Q + g.dim;
+    for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < nb; b += stride) acc[4] += double(rec[b * rec_stride + ds]);
     __shared__ double red[MON_FIELDS][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int k = 0; k < MON_FIELDS; ++k) {
@@ -190,12 +192,12 @@ hipError_t init_feq_t(mcb_ctx* c, const double* rho, const double* u, void* fout
 }
 
 template <class S, class C>
-hipError_t monitor_t(mcb_ctx* c, const void* fcur) {
+hipError_t monitor_t(mcb_ctx* c, const void* fcur, const void* rcur) {
     const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
     double* partials = reinterpret_cast<double*>(c->lat + c->L.partials);
     hipLaunchKernelGGL((k_mon_partial<S, C>), dim3(MON_BLOCKS), dim3(256), 0, c->stream, c->g, c->g.dim == 2 ? 0 : 1,
                        static_cast<const S*>(fcur), reinterpret_cast<const int32_t*>(c->lat + c->L.tag), rr,
-                       reinterpret_cast<const double*>(c->lk + c->L.dm), c->n_bnodes, partials);
+                       static_cast<const C*>(rcur), int(c->L.rec_stride), c->n_bnodes > 0 ? c->n_bnodes : 0, partials);
     hipLaunchKernelGGL(k_mon_final, dim3(1), dim3(256), 0, c->stream, partials, MON_BLOCKS,
                        reinterpret_cast<double*>(c->lat + c->L.result));
     return hipGetLastError();
@@ -239,11 +241,11 @@ hipError_t init_feq(mcb_ctx* c, const double* rho, const double* u, void* fout) 
     }
 }
 
-hipError_t monitor(mcb_ctx* c, const void* fcur) {
+hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur) {
     switch (c->p.precision) {
-        case MCB_F64: return monitor_t<double, double>(c, fcur);
-        case MCB_F32S: return monitor_t<float, float>(c, fcur);
-        default: return monitor_t<__half, float>(c, fcur);
+        case MCB_F64: return monitor_t<double, double>(c, fcur, rcur);
+        case MCB_F32S: return monitor_t<float, float>(c, fcur, rcur);
+        default: return monitor_t<__half, float>(c, fcur, rcur);
     }
 }
 

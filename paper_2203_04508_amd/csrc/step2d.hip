@@ -1,9 +1,25 @@
 // D2Q9 bulk of a time step: one fused kernel -- pull-streaming (eq. 5), density, the
 // pseudopotential with first-layer wall densities (eq. 15), the interaction force, and the
-// single-relaxation-time collision with exact-difference forcing (eqs. 4, 13-14).  The boundary
-// pass that runs before it has applied eqs. 16-18: the population entering a boundary node across
-// a link waits in the solid neighbour's slot for that direction, so the pull needs no special
-// case, and the node's rest population with the eq. 18 correction waits in f0c.
+// single-relaxation-time collision with exact-difference forcing (eqs. 4, 13-14), and at
+// boundary-fluid nodes the curved boundary condition (eqs. 16-17) with the mass correction of
+// eq. 18.
+//
+// Boundary nodes.  For a link (x, j) (x fluid, x + e_j solid) the population entering x along
+// opp(j) at t+1 is
+//   f_in = c1 f~_j(x, t) + c2 (o + F_j(x, t)),
+//   eq. 16 (q < 1/2, x2 = x - e_j fluid): c1 = 2q,      c2 = 1 - 2q,       o = f~_j(x2, t)
+//   eq. 17 (q >= 1/2):                    c1 = 1/(2q),  c2 = 1 - 1/(2q),   o = f~_opp(j)(x, t)
+//   bounce-back (q < 1/2, x2 solid):      c1 = 1,       c2 = 0,
+// and eq. 18 adds sum_links (f~_j(x, t) - f_in) to the rest population of x.  The pull of x already
+// brings f~_j(x2, t) (population j arrives from x - e_j); what else the links need is the node's own
+// post-collision populations and its force F(x, t), from which the exact-difference forcing term
+// F_j (eq. 13) is recomputed: rho = sum_i f~_i (the collision keeps the mass) and rho u =
+// sum_i f~_i e_i - F (the forcing term adds F to the momentum).  The collision of every boundary
+// node writes these into a contiguous boundary record; the pull of the next step reads the record
+// with the node's link coefficients in a few wide loads and applies the links in registers,
+// replacing the populations pulled from solid nodes.  Records alternate between two buffers with
+// the lattice buffers, since halo lanes of neighbouring workgroups read a node's record of time t
+// while its owner writes that of t+1.
 //
 // Layout: a workgroup of W lanes (one or four waves) covers W consecutive columns -- W - 4 output
 // columns and two halo columns on each side -- over a segment of H rows, and marches up the
@@ -14,9 +30,9 @@
 //      phi) into a second 4-row LDS ring;
 //   C  two rows behind, evaluates the force stencil from the psi ring and collides the populations
 //      pulled two iterations earlier (kept in registers), then stores them; boundary nodes also
-//      store their force, from which the next boundary pass recomputes the forcing terms of eq. 13.
-// Per node only the populations (read once, written once) and a 4-byte tag reach HBM; rho and psi
-// live in LDS.  Halo rows and columns are re-pulled by the neighbouring workgroup and hit in L2
+//      store their boundary record.
+// Per bulk node only the populations (read once, written once) and a 4-byte tag reach HBM; rho and
+// psi live in LDS.  Halo rows and columns are re-pulled by the neighbouring workgroup and hit in L2
 // or the Infinity Cache.  The populations of the next row and the tag of the row after it are in
 // flight while a row is processed, with the wettability factors of that row's wall nodes.  Every
 // global access is a bounds-checked buffer instruction
@@ -33,8 +49,9 @@ struct Args2 {
     const S* fa;                 // post-collision populations of time t, SoA [9][N]
     S* fb;                       // post-collision populations of time t+1
     const int32_t* tag;          // >0: (boundary index << 8) | link bits; 0 fluid; -1 solid; -2-w wall w
-    const C* f0c;                // rest population with the eq. 18 correction, per boundary node
-    C* Fv;                       // force per boundary node (for the next boundary pass), stride 2
+    const C* rin;                // boundary records of time t, REC2 per boundary node
+    C* rout;                     // boundary records of time t+1
+    const C* la;                 // link coefficients, Q2_LINKS per boundary node (NO_LINK: none)
     const double* phi;           // wettability factor per wall node
     int32_t* flags;
     uint32_t n_bnodes, n_wall;
@@ -57,7 +74,7 @@ __device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 template <class S, class C, int W>
 struct March {
     Args2<S, C> a;
-    __amdgpu_buffer_rsrc_t fa, fb, tag, f0c, Fv, phi;
+    __amdgpu_buffer_rsrc_t fa, fb, tag, rin, rout, la, phi;
     C (*s_rho)[W];
     C (*s_psi)[W];
     int (*s_tag)[W];
@@ -69,15 +86,16 @@ struct March {
     int tgA, tgB, tgC;
     int rr, rr1, tg_cur, tg_nxt, tg_nxt2;  // rows r+1 (pulling), r+2, r+3 (in flight)
     double phA, phB;  // wettability factors of rows r-1 and r (wall lanes; issued with their pull)
+    C recN[REC2], aN[Q2_LINKS];  // boundary record and link coefficients of row r+1 (in flight)
+    C dsA, dsB, dsC;             // eq. 18 corrections applied to rows r-2, r-1, r
     bool bad;
 };
 
 // Issue the loads of the nine populations arriving at row r of this lane's column (eq. 5), from
-// x - e_i; PULL = false reads the node's own populations (the collision that starts a run).  A
-// boundary node takes its rest population from f0c.
+// x - e_i; PULL = false reads the node's own populations (the collision that starts a run).
 template <class S, class C, int W, bool PULL>
-__device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, int tg, C f[9]) {
-    constexpr uint32_t s = sizeof(S), sc = sizeof(C);
+__device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, C f[9]) {
+    constexpr uint32_t s = sizeof(S);
     const uint32_t rows = uint32_t(M.nx) * s;
     const uint32_t r0 = uint32_t(r) * rows;
     const uint32_t rm = uint32_t(r == 0 ? M.ny - 1 : r - 1) * rows;
@@ -89,10 +107,48 @@ __device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, int tg,
         const uint32_t so = uint32_t(i) * M.ns + (PULL ? rowof[kEy[i] + 1] : r0);
         f[i] = Buf<S>::ld(M.fa, vo, so);
     }
-    if (PULL) {
-        const C c0 = Buf<C>::ld(M.f0c, tg > 0 ? uint32_t(tg >> 8) * sc : OOB);
-        f[0] = tg > 0 ? c0 : f[0];
+}
+
+// Eqs. 16-18 at a boundary node (bnd) from its record of time t (rec) and link coefficients (ca):
+// replaces the populations pulled from solid neighbours by f_in and corrects the rest population;
+// returns the correction.  Lanes that are not boundary nodes keep f and return 0.
+template <class S, class C>
+__device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[REC2], const C (&ca)[Q2_LINKS], C (&f)[9], C rho_ref) {
+    C rs = C(0), jx = C(0), jy = C(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        rs += rec[i];
+        jx += C(kEx[i]) * rec[i];
+        jy += C(kEy[i]) * rec[i];
     }
+    const C rho = bnd ? rs + rho_ref : C(1);
+    const C irho = rcp(rho);
+    const C Fx = rec[9], Fy = rec[10];
+    const C ux = (jx - Fx) * irho, uy = (jy - Fy) * irho;
+    const C dux = Fx * irho, duy = Fy * irho;
+    const C sx = C(2) * ux + dux, sy = C(2) * uy + duy;
+    const C duu = C(1.5) * (dux * sx + duy * sy);
+    // each slot opp(j) is replaced at most once, and never one that a later eq. 16 link reads (its
+    // x2 = x - e_j is fluid, while a replaced slot was pulled from a solid node)
+    C ds = C(0);
+#pragma unroll
+    for (int j = 1; j < 9; ++j) {
+        const C a = ca[j - 1];
+        const bool lk = bnd && a < C(1.5);
+        const C c1 = a < C(0) ? -a : a, c2 = C(1) - c1;
+        // eq. 13 term of direction j: w rho [3 e.du + 4.5 (e.du)(e.(2u + du)) - 1.5 du.(2u + du)]
+        const C ed = C(kEx[j]) * dux + C(kEy[j]) * duy;
+        const C es = C(kEx[j]) * sx + C(kEy[j]) * sy;
+        const C Fj = w9<C>(j) * rho * (C(3) * ed + C(4.5) * ed * es - duu);
+        C o = a < C(0) ? rec[kOpp[j]] : f[j];
+        o = c2 != C(0) ? o : C(0);
+        // rounded to the storage format, as the value would be stored; eq. 18 takes it so
+        const C fin = Buf<S>::round(c1 * rec[j] + c2 * (o + Fj));
+        ds += lk ? rec[j] - fin : C(0);
+        f[kOpp[j]] = lk ? fin : f[kOpp[j]];
+    }
+    f[0] += ds;
+    return ds;
 }
 
 // One row of the march (iteration k, row r = y0 - 2 + k).  fC holds the pulled populations of row
@@ -104,6 +160,12 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     constexpr uint32_t s = sizeof(S), sc = sizeof(C);
     const int slot = k & 3;
     M.tgA = M.tgB; M.tgB = M.tgC; M.tgC = M.tg_cur;
+    M.dsA = M.dsB; M.dsB = M.dsC;
+    C recC[REC2], aC[Q2_LINKS];  // record and coefficients of row r (arrived with its pull)
+#pragma unroll
+    for (int i = 0; i < REC2; ++i) recC[i] = M.recN[i];
+#pragma unroll
+    for (int i = 0; i < Q2_LINKS; ++i) aC[i] = M.aN[i];
     const int tgA = M.tgA;
     const bool coll = k >= 4 && M.out_col && tgA >= 0;
     const int yA = ((M.y0 - 4 + k) % ny + ny) % ny;
@@ -121,20 +183,29 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         const int r3 = M.rr1 == ny - 1 ? 0 : M.rr1 + 1;
         M.tg_cur = more ? M.tg_nxt : -1;
         M.tg_nxt = M.tg_nxt2;
-        pull_row<S, C, W, PULL>(M, M.rr, M.tg_cur, fN);
+        pull_row<S, C, W, PULL>(M, M.rr, fN);
         const double phN = Buf<double>::ld(M.phi, M.tg_cur <= -2 ? uint32_t(-M.tg_cur - 2) * 8u : OOB);
         M.tg_nxt2 = ld_i32(M.tag, k + 3 < M.iters ? M.tag_b : OOB, uint32_t(r3) * (nx * 4u));
         M.phA = M.phB;
         M.phB = phN;
     }
     __builtin_amdgcn_sched_barrier(0);
-    // ---- A: density of row r
+    // ---- A: links (eqs. 16-18) and density of row r
     {
+        M.dsC = C(0);
+        if (PULL && __any(M.tgC > 0)) M.dsC = apply_links<S, C>(M.tgC > 0, recC, aC, fC, a.rho_ref);
         C sr = C(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) sr += fC[i];
         M.s_rho[slot][t] = M.tgC >= 0 ? sr + a.rho_ref : C(0);
         M.s_tag[slot][t] = M.tgC;
+    }
+    // boundary record and link coefficients of row r+1, issued once those of row r are used up (so
+    // the two sets never hold registers together), a whole iteration before they are needed
+    if (PULL) {
+        const uint32_t bi = uint32_t(M.tg_cur >> 8);
+        ld_vec(M.rin, M.tg_cur > 0 ? bi * (REC2 * sc) : OOB, M.recN);
+        ld_vec(M.la, M.tg_cur > 0 ? bi * (Q2_LINKS * sc) : OOB, M.aN);
     }
     __syncthreads();
     // ---- B: psi of row r - 1
@@ -227,17 +298,22 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         }
         out[0] = rs_pull - rest;
     }
-    // Every output column stores, solid nodes included: their slots carry nothing the step reads
-    // (the boundary pass overwrites the ones the pull takes), and rows written without holes keep
-    // every cache line whole.  A lane that does not store starts from OOB; the saturating add
-    // keeps it out of bounds.
+    // Every output column stores, solid nodes included (zeros: the pull replaces what it takes
+    // from them), so rows are written without holes and every cache line whole.  A lane that does
+    // not store starts from OOB; the saturating add keeps it out of bounds.
     const uint32_t xst = (k >= 4 && M.out_col) ? xAb : OOB;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), out[i]);
-    // force of a boundary node, for the forcing terms of the next boundary pass
-    const uint32_t fst = (coll && tgA > 0) ? uint32_t(tgA >> 8) * (2 * sc) : OOB;
-    Buf<C>::st(M.Fv, fst, Fx);
-    Buf<C>::st(M.Fv, fst + sc, Fy);
+    for (int i = 0; i < 9; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), coll ? out[i] : C(0));
+    // boundary record of time t+1: the populations as stored, the force, the eq. 18 correction
+    {
+        C rv[REC2];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) rv[i] = Buf<S>::round(out[i]);
+        rv[9] = Fx;
+        rv[10] = Fy;
+        rv[11] = M.dsA;
+        st_vec(M.rout, (coll && tgA > 0) ? uint32_t(tgA >> 8) * (REC2 * sc) : OOB, rv);
+    }
 }
 
 template <class S, class C, int W, int OUT, bool PULL>
@@ -251,7 +327,7 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     __shared__ C s_rho[4][W];
     __shared__ C s_psi[4][W];
     __shared__ int s_tag[4][W];
-    constexpr uint32_t s = sizeof(S);
+    constexpr uint32_t s = sizeof(S), sc = sizeof(C);
 
     March<S, C, W> M;
     M.a = a;
@@ -283,11 +359,13 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     M.fa = make_res(a.fa, uint64_t(9) * M.n * s);
     M.fb = make_res(a.fb, uint64_t(9) * M.n * s);
     M.tag = make_res(a.tag, uint64_t(M.n) * 4);
-    M.f0c = make_res(a.f0c, uint64_t(a.n_bnodes) * sizeof(C));
-    M.Fv = make_res(a.Fv, uint64_t(a.n_bnodes) * 2 * sizeof(C));
+    M.rin = make_res(a.rin, uint64_t(a.n_bnodes) * REC2 * sizeof(C));
+    M.rout = make_res(a.rout, uint64_t(a.n_bnodes) * REC2 * sizeof(C));
+    M.la = make_res(a.la, uint64_t(a.n_bnodes) * Q2_LINKS * sizeof(C));
     M.ns = M.n * s;
     M.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
     M.tgA = M.tgB = M.tgC = -1;
+    M.dsA = M.dsB = M.dsC = C(0);
     M.bad = false;
     // row march: the populations of row r+1 and the tag of row r+2 are in flight while row r is
     // reduced to rho, row r-1 to psi and row r-2 collided; four register sets rotate
@@ -299,7 +377,16 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     M.rr1 = M.rr == a.ny - 1 ? 0 : M.rr + 1;
     M.tg_nxt = ld_i32(M.tag, M.tag_b, uint32_t(M.rr1) * (a.nx * 4u));
     M.tg_nxt2 = ld_i32(M.tag, M.tag_b, uint32_t(M.rr1 == a.ny - 1 ? 0 : M.rr1 + 1) * (a.nx * 4u));
-    pull_row<S, C, W, PULL>(M, M.rr, M.tg_cur, f3);
+    pull_row<S, C, W, PULL>(M, M.rr, f3);
+#pragma unroll
+    for (int i = 0; i < REC2; ++i) M.recN[i] = C(0);
+#pragma unroll
+    for (int i = 0; i < Q2_LINKS; ++i) M.aN[i] = C(0);
+    if (PULL) {
+        const uint32_t bi = uint32_t(M.tg_cur >> 8);
+        ld_vec(M.rin, M.tg_cur > 0 ? bi * (REC2 * sc) : OOB, M.recN);
+        ld_vec(M.la, M.tg_cur > 0 ? bi * (Q2_LINKS * sc) : OOB, M.aN);
+    }
     M.phA = 0.0;
     M.phB = Buf<double>::ld(M.phi, M.tg_cur <= -2 ? uint32_t(-M.tg_cur - 2) * 8u : OOB);
     int k = 0;
@@ -317,13 +404,14 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
 }
 
 template <class S, class C, int W, int OUT>
-hipError_t launch_w(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
+hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
     Args2<S, C> a;
     a.fa = static_cast<const S*>(fcur);
     a.fb = static_cast<S*>(fnext);
     a.tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
-    a.f0c = reinterpret_cast<const C*>(c->lk + c->L.lk_f0c);
-    a.Fv = reinterpret_cast<C*>(c->lk + c->L.lk_Fv);
+    a.rin = static_cast<const C*>(rcur);
+    a.rout = static_cast<C*>(rnext);
+    a.la = reinterpret_cast<const C*>(c->lk + c->L.lk_a);
     a.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
     a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
     a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
@@ -352,22 +440,22 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
 }
 
 template <class S, class C>
-hipError_t launch_step2d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
+hipError_t launch_step2d(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
     // one-wave strips keep small lattices busy; on large lattices the strips are a whole number of
     // cache lines wide (224 FP32 / FP64 columns, 448 FP16 columns), so that no line is shared
     // between strips or written in parts
-    if (c->g.N <= (int64_t(1) << 21)) return launch_w<S, C, 64, 60>(c, fcur, fnext, pull);
-    if (sizeof(S) == 2) return launch_w<S, C, 512, 448>(c, fcur, fnext, pull);
-    return launch_w<S, C, 256, 224>(c, fcur, fnext, pull);
+    if (c->g.N <= (int64_t(1) << 21)) return launch_w<S, C, 64, 60>(c, fcur, rcur, fnext, rnext, pull);
+    if (sizeof(S) == 2) return launch_w<S, C, 512, 448>(c, fcur, rcur, fnext, rnext, pull);
+    return launch_w<S, C, 256, 224>(c, fcur, rcur, fnext, rnext, pull);
 }
 
 }  // namespace
 
-hipError_t step2d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
+hipError_t step2d(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
     switch (c->p.precision) {
-        case MCB_F64: return launch_step2d<double, double>(c, fcur, fnext, pull);
-        case MCB_F32S: return launch_step2d<float, float>(c, fcur, fnext, pull);
-        default: return launch_step2d<__half, float>(c, fcur, fnext, pull);
+        case MCB_F64: return launch_step2d<double, double>(c, fcur, rcur, fnext, rnext, pull);
+        case MCB_F32S: return launch_step2d<float, float>(c, fcur, rcur, fnext, rnext, pull);
+        default: return launch_step2d<__half, float>(c, fcur, rcur, fnext, rnext, pull);
     }
 }
 

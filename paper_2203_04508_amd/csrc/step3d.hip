@@ -1,8 +1,11 @@
 // D3Q19 bulk of a time step: the fused kernel of the D2Q9 path carried to three dimensions --
 // pull-streaming (eq. 5), density, the pseudopotential with first-layer wall densities (eq. 15),
 // the interaction force, and the single-relaxation-time collision with exact-difference forcing
-// (eqs. 4, 13-14).  The boundary pass before it has applied eqs. 16-18 (the incoming population of
-// every link waits in the solid neighbour's slot, the corrected rest population in f0c).
+// (eqs. 4, 13-14), with the curved boundary condition (eqs. 16-17) and the mass correction of
+// eq. 18 at boundary-fluid nodes.  As in two dimensions, the collision of a boundary node writes a
+// contiguous boundary record (post-collision populations as stored, force, eq. 18 correction), and
+// the pull of the next step reads it with the node's link coefficients in a few wide loads and
+// replaces the populations pulled from solid neighbours by the eq. 16-17 values.
 //
 // Layout: a workgroup of 32 x 16 lanes covers a 32 x 16 column tile of the x-y plane -- 28 x 12
 // output columns and two halo columns on every side -- over a segment of D planes in z, and
@@ -13,7 +16,7 @@
 //      phi) into a second 4-plane ring;
 //   C  evaluates the force stencil for plane r-2 from the psi ring, collides the populations
 //      pulled two iterations earlier (kept in registers) and stores them; boundary nodes also
-//      store their force for the next boundary pass.
+//      store their boundary record.
 // The populations of plane r+1 and the tags of plane r+3 are in flight while plane r is processed.
 // The lane part of every pull address is one of nine loop-invariant column offsets and the plane
 // part a wave-uniform scalar, so the loads need no address arithmetic.
@@ -35,8 +38,9 @@ struct Args3 {
     const S* fa;                 // post-collision populations of time t, SoA [19][N]
     S* fb;                       // post-collision populations of time t+1
     const int32_t* tag;          // >0: boundary index + 1; 0 fluid; -1 solid; -2-w wall w
-    const C* f0c;                // rest population with the eq. 18 correction, per boundary node
-    C* Fv;                       // force per boundary node (for the next boundary pass), stride 4
+    const C* rin;                // boundary records of time t, REC3 per boundary node
+    C* rout;                     // boundary records of time t+1
+    const C* la;                 // link coefficients, Q3_LINKS per boundary node (NO_LINK: none)
     const double* phi;           // wettability factor per wall node
     int32_t* flags;
     uint32_t n_bnodes, n_wall;
@@ -49,7 +53,7 @@ struct Args3 {
 template <class S, class C>
 struct March3 {
     Args3<S, C> a;
-    __amdgpu_buffer_rsrc_t fa, fb, tag, f0c, Fv, phi;
+    __amdgpu_buffer_rsrc_t fa, fb, tag, rin, rout, la, phi;
     C (*s_rho)[NT];
     C (*s_psi)[NT];
     int (*s_tag)[NT];
@@ -62,35 +66,17 @@ struct March3 {
     bool out_col, inner;
     int tgA, tgB, tgC, tg_r, tg_r1, tg_r2;  // tags of planes r-2, r-1, r (history) and r+1, r+2
     double phA, phB;                 // wettability factors of planes r-1 and r (wall lanes)
+    C recN[REC3], aN[Q3_LINKS];      // boundary record and link coefficients of plane r+1 (PF)
+    C dsA, dsB, dsC;                 // eq. 18 corrections applied to planes r-2, r-1, r
     bool bad;
 };
 
 __device__ inline int zinc(int z, int nz) { return z == nz - 1 ? 0 : z + 1; }
 
-// force of a boundary node: three components at a 4-element stride
-template <class C>
-__device__ inline void st_force(__amdgpu_buffer_rsrc_t r, uint32_t off, C Fx, C Fy, C Fz) {
-    Buf<C>::st(r, off, Fx);
-    Buf<C>::st(r, off + uint32_t(sizeof(C)), Fy);
-    Buf<C>::st(r, off + 2u * uint32_t(sizeof(C)), Fz);
-}
-template <>
-__device__ inline void st_force<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, float Fx, float Fy, float Fz) {
-    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-    u32x4 v;
-    v.x = __builtin_bit_cast(unsigned int, Fx);
-    v.y = __builtin_bit_cast(unsigned int, Fy);
-    v.z = __builtin_bit_cast(unsigned int, Fz);
-    v.w = 0u;
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
-}
-
 // Issue the loads of the nineteen populations arriving at plane z of this lane's column (eq. 5),
-// from x - e_i; PULL = false reads the node's own populations.  A boundary node takes its rest
-// population from f0c.
+// from x - e_i; PULL = false reads the node's own populations.
 template <class S, class C, bool PULL>
-__device__ __forceinline__ void pull_plane(const March3<S, C>& M, int z, int tg, C f[19]) {
-    constexpr uint32_t sc = sizeof(C);
+__device__ __forceinline__ void pull_plane(const March3<S, C>& M, int z, C f[19]) {
     const uint32_t z0b = uint32_t(z) * M.pb;
     const uint32_t zmb = uint32_t(z == 0 ? M.nz - 1 : z - 1) * M.pb;
     const uint32_t zpb = uint32_t(z == M.nz - 1 ? 0 : z + 1) * M.pb;
@@ -101,10 +87,84 @@ __device__ __forceinline__ void pull_plane(const March3<S, C>& M, int z, int tg,
         const uint32_t so = uint32_t(i) * M.ns + (PULL ? zof[kEz3[i] + 1] : z0b);
         f[i] = Buf<S>::ld(M.fa, vo, so);
     }
-    if (PULL) {
-        const C c0 = Buf<C>::ld(M.f0c, tg > 0 ? uint32_t(tg - 1) * sc : OOB);
-        f[0] = tg > 0 ? c0 : f[0];
+}
+
+// boundary record of time t and link coefficients of a boundary node (tg > 0; other lanes get zeros)
+template <class S, class C>
+__device__ __forceinline__ void ld_rec(const March3<S, C>& M, int tg, C (&rec)[REC3], C (&ca)[Q3_LINKS]) {
+    constexpr uint32_t sc = sizeof(C);
+    const uint32_t bi = uint32_t(tg - 1);
+    ld_vec(M.rin, tg > 0 ? bi * (REC3 * sc) : OOB, rec);
+    ld_vec(M.la, tg > 0 ? bi * (Q3_LINKS * sc) : OOB, ca);
+}
+
+// D3Q19 weights
+template <class C>
+__device__ inline C w19(int i) {
+    return i == 0 ? C(1.0 / 3.0) : (i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0));
+}
+
+// Eqs. 16-18 at a boundary node (bnd) from its record of time t (rec) and link coefficients (ca):
+// replaces the populations pulled from solid neighbours by f_in (see the two-dimensional kernel for
+// the three cases) and corrects the rest population; returns the correction.  Lanes that are not
+// boundary nodes keep f and return 0.  LOAD_A: ca is loaded here from la at byte offset aoff, in
+// two halves, each just before its directions (keeps the FP64 kernel within its registers).
+template <class S, class C, bool LOAD_A>
+__device__ __forceinline__ C apply_links3(bool bnd, const C (&rec)[REC3], C (&ca)[Q3_LINKS], C (&f)[19], C rho_ref,
+                                          __amdgpu_buffer_rsrc_t la, uint32_t aoff) {
+    C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        rs += rec[i];
+        jx += C(kEx3[i]) * rec[i];
+        jy += C(kEy3[i]) * rec[i];
+        jz += C(kEz3[i]) * rec[i];
     }
+    const C rho = bnd ? rs + rho_ref : C(1);
+    const C irho = rcp(rho);
+    const C Fx = rec[19], Fy = rec[20], Fz = rec[21];
+    const C ux = (jx - Fx) * irho, uy = (jy - Fy) * irho, uz = (jz - Fz) * irho;
+    const C dux = Fx * irho, duy = Fy * irho, duz = Fz * irho;
+    const C sx = C(2) * ux + dux, sy = C(2) * uy + duy, sz = C(2) * uz + duz;
+    const C duu = C(1.5) * (dux * sx + duy * sy + duz * sz);
+    // each slot opp(j) is replaced at most once, and never one that a later eq. 16 link reads (its
+    // x2 = x - e_j is fluid, while a replaced slot was pulled from a solid node)
+    C ds = C(0);
+    auto link = [&](int j) {
+        const C a = ca[j - 1];
+        const bool lk = bnd && a < C(1.5);
+        const C c1 = a < C(0) ? -a : a, c2 = C(1) - c1;
+        // eq. 13 term of direction j
+        const C ed = C(kEx3[j]) * dux + C(kEy3[j]) * duy + C(kEz3[j]) * duz;
+        const C es = C(kEx3[j]) * sx + C(kEy3[j]) * sy + C(kEz3[j]) * sz;
+        const C Fj = w19<C>(j) * rho * (C(3) * ed + C(4.5) * ed * es - duu);
+        const int jo = (j & 1) ? j + 1 : j - 1;  // opposite direction
+        C o = a < C(0) ? rec[jo] : f[j];
+        o = c2 != C(0) ? o : C(0);
+        const C fin = Buf<S>::round(c1 * rec[j] + c2 * (o + Fj));
+        ds += lk ? rec[j] - fin : C(0);
+        f[jo] = lk ? fin : f[jo];
+    };
+    constexpr int HALF = Q3_LINKS / 2;
+    if (LOAD_A) {
+        C h[HALF];
+        ld_vec(la, aoff, h);
+#pragma unroll
+        for (int i = 0; i < HALF; ++i) ca[i] = h[i];
+    }
+#pragma unroll
+    for (int j = 1; j <= HALF; ++j) link(j);
+    if (LOAD_A) {
+        __builtin_amdgcn_sched_barrier(0);
+        C h[HALF];
+        ld_vec(la, aoff + uint32_t(HALF * sizeof(C)), h);
+#pragma unroll
+        for (int i = 0; i < HALF; ++i) ca[HALF + i] = h[i];
+    }
+#pragma unroll
+    for (int j = HALF + 1; j < 19; ++j) link(j);
+    f[0] += ds;
+    return ds;
 }
 
 // One plane of the march (iteration k, plane r = z0 - 2 + k).  fC holds the pulled populations
@@ -118,7 +178,13 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
     constexpr uint32_t sc = sizeof(C);
     const int slot = k & 3;
     M.tgA = M.tgB; M.tgB = M.tgC; M.tgC = M.tg_r;
+    M.dsA = M.dsB; M.dsB = M.dsC;
     const int tgA = M.tgA;
+    C recC[REC3], aC[Q3_LINKS];  // record and coefficients of plane r
+#pragma unroll
+    for (int i = 0; i < REC3; ++i) recC[i] = M.recN[i];
+#pragma unroll
+    for (int i = 0; i < Q3_LINKS; ++i) aC[i] = M.aN[i];
     const bool coll = k >= 4 && M.out_col && tgA >= 0;
     const int zA = ((M.z0 - 4 + k) % M.nz + M.nz) % M.nz;
     const uint32_t xAb = uint32_t(zA) * M.pb + M.vxy[4];  // byte offset of (x, y, zA) in a population array
@@ -131,10 +197,11 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
     {
         const int z1 = zinc(M.zc, M.nz), z2 = zinc(z1, M.nz), z3 = zinc(z2, M.nz);
         const int tgp = PF ? M.tg_r1 : M.tg_r;
-        if (PF)
-            pull_plane<S, C, PULL>(M, z1, tgp, fN);
-        else
-            pull_plane<S, C, PULL>(M, M.zc, tgp, fC);
+        if (PF) {
+            pull_plane<S, C, PULL>(M, z1, fN);
+        } else {
+            pull_plane<S, C, PULL>(M, M.zc, fC);
+        }
         const double phN = Buf<double>::ld(M.phi, tgp <= -2 ? uint32_t(-tgp - 2) * 8u : OOB);
         const int tg3 = ld_i32(M.tag, M.own4, uint32_t(z3) * M.p4);
         M.tg_r = M.tg_r1;
@@ -149,14 +216,27 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
         }
     }
     __builtin_amdgcn_sched_barrier(0);
-    // ---- A: density of plane r
+    // ---- A: links (eqs. 16-18) and density of plane r
     {
+        M.dsC = C(0);
+        if (PULL && __any(M.tgC > 0)) {
+            // without the prefetch (FP64) the record and the coefficients are loaded here, when the
+            // plane's pull is in
+            const uint32_t bi = uint32_t(M.tgC - 1);
+            if (!PF) ld_vec(M.rin, M.tgC > 0 ? bi * (REC3 * sc) : OOB, recC);
+            M.dsC = apply_links3<S, C, !PF>(M.tgC > 0, recC, aC, fC, a.rho_ref, M.la,
+                                            M.tgC > 0 ? bi * (Q3_LINKS * sc) : OOB);
+        }
         C sr = C(0);
 #pragma unroll
         for (int i = 0; i < 19; ++i) sr += fC[i];
         M.s_rho[slot][t] = M.tgC >= 0 ? sr + a.rho_ref : C(0);
         M.s_tag[slot][t] = M.tgC;
     }
+    // PF: boundary record and link coefficients of plane r+1 (tag M.tg_r by now), issued once those
+    // of plane r are used up (so the two sets never hold registers together), a whole iteration
+    // before they are needed
+    if (PF && PULL) ld_rec(M, M.tg_r, M.recN, M.aN);
     __syncthreads();
     // ---- B: psi of plane r - 1
     if (k >= 2 && M.inner) {
@@ -256,15 +336,24 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
         }
         out[0] = rs - rest;
     }
-    // Every output column stores, solid nodes included: their slots carry nothing the step reads
-    // (the boundary pass overwrites the ones the pull takes), and rows written without holes keep
-    // every cache line whole.  A lane that does not store starts from OOB; the saturating add
-    // keeps it out of bounds.
+    // Every output column stores, solid nodes included (zeros: the pull replaces what it takes
+    // from them), so rows are written without holes.  A lane that does not store starts from OOB;
+    // the saturating add keeps it out of bounds.
     const uint32_t xst = (k >= 4 && M.out_col) ? xAb : OOB;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), out[i]);
-    // force of a boundary node, for the forcing terms of the next boundary pass
-    st_force<C>(M.Fv, (coll && tgA > 0) ? uint32_t(tgA - 1) * (4 * sc) : OOB, Fx, Fy, Fz);
+    for (int i = 0; i < 19; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), coll ? out[i] : C(0));
+    // boundary record of time t+1: the populations as stored, the force, the eq. 18 correction
+    {
+        C rv[REC3];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) rv[i] = Buf<S>::round(out[i]);
+        rv[19] = Fx;
+        rv[20] = Fy;
+        rv[21] = Fz;
+        rv[22] = M.dsA;
+        rv[23] = C(0);
+        st_vec(M.rout, (coll && tgA > 0) ? uint32_t(tgA - 1) * (REC3 * sc) : OOB, rv);
+    }
 }
 
 template <class S, class C, bool PULL, bool PF>
@@ -313,10 +402,16 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
     M.fa = make_res(a.fa, uint64_t(19) * M.ns);
     M.fb = make_res(a.fb, uint64_t(19) * M.ns);
     M.tag = make_res(a.tag, uint64_t(nxy) * a.nz * 4);
-    M.f0c = make_res(a.f0c, uint64_t(a.n_bnodes) * sizeof(C));
-    M.Fv = make_res(a.Fv, uint64_t(a.n_bnodes) * 4 * sizeof(C));
+    M.rin = make_res(a.rin, uint64_t(a.n_bnodes) * REC3 * sizeof(C));
+    M.rout = make_res(a.rout, uint64_t(a.n_bnodes) * REC3 * sizeof(C));
+    M.la = make_res(a.la, uint64_t(a.n_bnodes) * Q3_LINKS * sizeof(C));
     M.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
     M.tgA = M.tgB = M.tgC = -1;
+    M.dsA = M.dsB = M.dsC = C(0);
+#pragma unroll
+    for (int i = 0; i < REC3; ++i) M.recN[i] = C(0);
+#pragma unroll
+    for (int i = 0; i < Q3_LINKS; ++i) M.aN[i] = C(0);
     M.bad = false;
     // prologue: tags of planes r and r+1, populations of plane r (PF)
     C fA[19], fB[19], fC[19], fN[19];
@@ -329,7 +424,8 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
     M.phA = 0.0;
     M.phB = 0.0;
     if (PF) {
-        pull_plane<S, C, PULL>(M, M.zc, M.tg_r, fC);
+        pull_plane<S, C, PULL>(M, M.zc, fC);
+        if (PULL) ld_rec(M, M.tg_r, M.recN, M.aN);
         M.phB = Buf<double>::ld(M.phi, M.tg_r <= -2 ? uint32_t(-M.tg_r - 2) * 8u : OOB);
     }
     // the register sets rotate by copies (an unrolled rotation costs the allocator far more)
@@ -346,13 +442,14 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
 }
 
 template <class S, class C>
-hipError_t launch_step3d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
+hipError_t launch_step3d(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
     Args3<S, C> a;
     a.fa = static_cast<const S*>(fcur);
     a.fb = static_cast<S*>(fnext);
     a.tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
-    a.f0c = reinterpret_cast<const C*>(c->lk + c->L.lk_f0c);
-    a.Fv = reinterpret_cast<C*>(c->lk + c->L.lk_Fv);
+    a.rin = static_cast<const C*>(rcur);
+    a.rout = static_cast<C*>(rnext);
+    a.la = reinterpret_cast<const C*>(c->lk + c->L.lk_a);
     a.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
     a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
     a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
@@ -384,11 +481,11 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
 
 }  // namespace
 
-hipError_t step3d(mcb_ctx* c, const void* fcur, void* fnext, bool pull) {
+hipError_t step3d(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
     switch (c->p.precision) {
-        case MCB_F64: return launch_step3d<double, double>(c, fcur, fnext, pull);
-        case MCB_F32S: return launch_step3d<float, float>(c, fcur, fnext, pull);
-        default: return launch_step3d<__half, float>(c, fcur, fnext, pull);
+        case MCB_F64: return launch_step3d<double, double>(c, fcur, rcur, fnext, rnext, pull);
+        case MCB_F32S: return launch_step3d<float, float>(c, fcur, rcur, fnext, rnext, pull);
+        default: return launch_step3d<__half, float>(c, fcur, rcur, fnext, rnext, pull);
     }
 }
 
