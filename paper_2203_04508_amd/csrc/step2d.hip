@@ -201,8 +201,11 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         M.s_tag[slot][t] = M.tgC;
     }
     // boundary record and link coefficients of row r+1, issued once those of row r are used up (so
-    // the two sets never hold registers together), a whole iteration before they are needed
-    if (PULL) {
+    // the two sets never hold registers together), a whole iteration before they are needed; only
+    // by waves that hold a boundary node in that row (16-byte loads cost address cycles even for
+    // lanes out of bounds), so the registers keep stale values exactly where the next iteration
+    // does not read them
+    if (PULL && __any(M.tg_cur > 0)) {
         const uint32_t bi = uint32_t(M.tg_cur >> 8);
         ld_vec(M.rin, M.tg_cur > 0 ? bi * (REC2 * sc) : OOB, M.recN);
         ld_vec(M.la, M.tg_cur > 0 ? bi * (Q2_LINKS * sc) : OOB, M.aN);
@@ -312,7 +315,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         rv[9] = Fx;
         rv[10] = Fy;
         rv[11] = M.dsA;
-        st_vec(M.rout, (coll && tgA > 0) ? uint32_t(tgA >> 8) * (REC2 * sc) : OOB, rv);
+        if (__any(coll && tgA > 0)) st_vec(M.rout, (coll && tgA > 0) ? uint32_t(tgA >> 8) * (REC2 * sc) : OOB, rv);
     }
 }
 

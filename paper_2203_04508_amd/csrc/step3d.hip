@@ -236,7 +236,10 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
     // PF: boundary record and link coefficients of plane r+1 (tag M.tg_r by now), issued once those
     // of plane r are used up (so the two sets never hold registers together), a whole iteration
     // before they are needed
-    if (PF && PULL) ld_rec(M, M.tg_r, M.recN, M.aN);
+    // (only by waves that hold a boundary node in that plane: 16-byte loads cost address cycles even
+    // for lanes out of bounds; the registers keep stale values exactly where the next iteration does
+    // not read them)
+    if (PF && PULL && __any(M.tg_r > 0)) ld_rec(M, M.tg_r, M.recN, M.aN);
     __syncthreads();
     // ---- B: psi of plane r - 1
     if (k >= 2 && M.inner) {
@@ -352,7 +355,7 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
         rv[21] = Fz;
         rv[22] = M.dsA;
         rv[23] = C(0);
-        st_vec(M.rout, (coll && tgA > 0) ? uint32_t(tgA - 1) * (REC3 * sc) : OOB, rv);
+        if (__any(coll && tgA > 0)) st_vec(M.rout, (coll && tgA > 0) ? uint32_t(tgA - 1) * (REC3 * sc) : OOB, rv);
     }
 }
 
