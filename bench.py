@@ -4,11 +4,12 @@ A step is one pass of the whole hot path over the lattice: the fused kernel that
 populations, applies the curved-boundary links (eqs. 16-18), computes the pseudopotential force and
 collides. Inputs are resident in HBM before the timed region starts. Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--no-cpu] [--no-adjoint]
 
 Default: the 4096^2 D2Q9 workload (4800 circles, 640 drops) with shifted-FP32 storage, its 5000
 steps, as the throughput and HBM-roofline figures are quoted on it; the oracle is timed on a
-bounded sample of the same workload.
+bounded sample of the same workload.  The forward + reverse-mode figure is measured on the 512^2
+rough-wall workload (2000 steps, checkpoints every 100 steps), as the gradient is defined there.
 """
 from __future__ import annotations
 
@@ -45,6 +46,54 @@ def setup_gpu(wl, precision, rho_ref):
     return lat, (nl, nb, nw)
 
 
+def algorithmic_bytes(wl, precision, nb):
+    """Bytes one launch of the step kernel must move: each node's populations read once and written
+    once plus its 4-byte tag; each boundary node's record read and written once plus its link
+    coefficients (halo re-reads and partial cache lines are not counted)."""
+    from paper_2203_04508_amd import mcb
+
+    s = STORAGE_BYTES[precision]
+    cb = 8 if precision == "f64" else 4
+    rec, nlk = (mcb.REC2, mcb.Q2_LINKS) if wl.dim == 2 else (mcb.REC3, mcb.Q3_LINKS)
+    return wl.N * (2 * wl.Q * s + 4) + nb * (2 * rec + nlk) * cb
+
+
+def fwd_adjoint(precision):
+    """Forward with checkpoints + reverse mode on the 512^2 rough-wall workload: lattice updates of
+    the forward trajectory per second of the whole (forward + backward) time."""
+    import torch
+    from paper_2203_04508_amd import mcb, workloads as W
+
+    wl = W.make("c3")
+    rr = wl.rho_v if precision != "f64" else 0.0
+    lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision, rho_ref=rr)
+    lat.set_geometry(wl.shapes)
+    lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
+    rho0 = wl.rho0()
+    k = 100
+    lat.adj_forward(rho0, 200, k, mcb.LOSS_COM_X, (wl.rho_v, 1.0))  # warm-up (arena, code paths)
+    lat.adj_backward(1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = lat.adj_forward(rho0, wl.steps, k, mcb.LOSS_COM_X, (wl.rho_v, 1.0))
+    t1 = time.perf_counter()
+    g = lat.adj_backward(1.0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    lat.close()
+    return {
+        "workload": f"c3: D2Q9 {wl.dims[0]}x{wl.dims[1]} rough wall, {wl.steps} steps, checkpoint every {k}",
+        "precision": precision,
+        "loss": "centre-of-mass x of the drop",
+        "value": wl.N * wl.steps / (t2 - t0) / 1e6,
+        "unit": "MLUPS",
+        "forward_s": t1 - t0,
+        "backward_s": t2 - t1,
+        "loss_value": float(loss),
+        "grad_entries": int(len(g)),
+    }
+
+
 def cpu_baseline(wl, budget_s=12.0):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
     from oracle import oracle
@@ -79,6 +128,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="f32s", choices=list(DTYPES))
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -110,15 +160,20 @@ def main():
     rep = lat.mass()
     drift = (rep.M - M0) / M0
 
-    Q = wl.Q
-    s = STORAGE_BYTES[args.precision]
-    bytes_per_node = 2 * Q * s + 1  # populations read once and written once, plus a one-byte node class
+    from paper_2203_04508_amd.traffic import kernel_digest
+
+    alg = algorithmic_bytes(wl, args.precision, nb)
+    # one kernel launch per step; HIP events on the library's stream bracket each launch
     fused_ms = ms / max(1, launches)
-    achieved = wl.N * bytes_per_node / (fused_ms * 1e-3) / 1e9
+    achieved = alg / (fused_ms * 1e-3) / 1e9
+    # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), used only
+    # when they were taken on the kernel as it is now
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{wl.name}_{args.precision}.json")
     if os.path.exists(tfile):
-        traffic = json.load(open(tfile)).get("bytes_per_launch")
+        tj = json.load(open(tfile))
+        if tj.get("kernel_digest") == kernel_digest(wl.dim):
+            traffic = tj.get("bytes_per_launch")
 
     out = {
         "metric": METRIC,
@@ -148,13 +203,16 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes_per_launch": wl.N * bytes_per_node,
+            "algorithmic_bytes_per_launch": alg,
             "kernel_ms": fused_ms,
             "kernel_launches": launches,
         },
         "mass_drift": drift,
         "mass_drift_steps": args.warmup + steps,
     }
+    if not args.no_adjoint:
+        log("[bench] forward + reverse mode (c3)")
+        out["fwd_adjoint"] = fwd_adjoint(args.precision)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

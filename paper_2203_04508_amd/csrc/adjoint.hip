@@ -54,7 +54,7 @@ struct AdjDev {
     const uint32_t* nmask;       // 3-D link bits
     const int32_t* bn_link0;     // 2-D first link of each boundary node
     const double* phi;           // wettability factor per wall node
-    int fs;                      // stride of the per-boundary-node force
+    int fs;                      // stride of the boundary records
     double tau, G, RT, a, b4, rho_ref;
 };
 
@@ -126,7 +126,8 @@ __global__ void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __rest
                     m0[2] += fi * c_ez[A.L][i];
                 }
                 const int64_t b = bidx(A, tg);
-                for (int k = 0; k < A.g.dim; ++k) F0[k] = double(Fv[b * A.fs + k]);
+                // F = rho du from the forcing terms at the head of the boundary record
+                for (int k = 0; k < A.g.dim; ++k) F0[k] = double(Fv[b * A.fs]) * double(Fv[b * A.fs + 1 + k]);
                 for (int k = 0; k < 3; ++k) m0[k] -= F0[k];
             }
             for (int j = 1; j < Q; ++j) {
@@ -485,8 +486,8 @@ hipError_t adj_step_t(mcb_ctx* c, const AdjWork& w, const void* gt, const void* 
     const AdjDev A = make_dev(c);
     const unsigned G = grid_for(c->g.N);
     const RC* rec = reinterpret_cast<const RC*>(c->lk + c->L.lk_a);
-    // the force of each boundary node follows its Q populations in the boundary record of time t
-    const RC* Fv = fv ? static_cast<const RC*>(fv) + c->g.Q : nullptr;
+    // boundary records of time t: rho and du = F / rho lead each record
+    const RC* Fv = static_cast<const RC*>(fv);
     hipLaunchKernelGGL((k_recompute<S, RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt), rec, Fv, pull,
                        w.rho0, w.p, w.rho);
     hipLaunchKernelGGL(k_psi, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.dpsi, w.rave, w.den);

@@ -52,6 +52,7 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.rec[1] = take(cb * L.rec_stride * nb);
     L.wl_node = take(4 * nw);
     L.wl_phi = take(8 * nw);
+    L.wl_fac = take(8 * nw);  // compute type
     L.links_bytes = (nb + nl + nw) > 0 ? o : 0;
     return L;
 }
@@ -404,6 +405,7 @@ mcb_status mcb_set_wettability(mcb_ctx* c, const double* phi, int64_t n_wall) {
         if (!(phi[w] > 0.0) || !std::isfinite(phi[w])) return fail(c, MCB_EINVAL, "phi[%lld] must be positive", (long long)w);
     if (n_wall > 0) {
         HIPCHK(hipMemcpyAsync(c->lk + c->L.wl_phi, phi, 8 * n_wall, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(wall_factors(c));
         HIPCHK(hipStreamSynchronize(c->stream));
     }
     return MCB_OK;

@@ -358,6 +358,25 @@ __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict_
     }
 }
 
+// Eq. 15 gives a wall node the lattice-weighted mean density of its fluid neighbours times phi.  The
+// weights of the fluid neighbours are fixed by the geometry, so the step takes
+// fac = phi / sum_{fluid x + e_i} w_i and multiplies it by sum_i w_i rho(x + e_i), in which solid
+// neighbours count with rho = 0.
+template <class C>
+__global__ void k_wall_fac(GridDev g, int L, int64_t nw, const int32_t* __restrict__ wl_node, const uint8_t* __restrict__ solid,
+                           const double* __restrict__ phi, C* __restrict__ fac) {
+    for (int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; w < nw; w += int64_t(gridDim.x) * blockDim.x) {
+        int c[3];
+        coords(g, wl_node[w], c);
+        double den = 0.0;
+        for (int i = 1; i < g.Q; ++i) {
+            const double wi = L == 0 ? (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0) : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+            if (!solid[neighbour(g, c, L, i, +1)]) den += wi;
+        }
+        fac[w] = C(phi[w] / den);
+    }
+}
+
 inline int lat_index(const mcb_ctx* c) { return c->g.dim == 2 ? 0 : 1; }
 
 inline unsigned grid_for(int64_t n, int block) {
@@ -420,7 +439,23 @@ hipError_t geom_fill(mcb_ctx* c) {
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    e = wall_factors(c);
+    if (e != hipSuccess) return e;
     return geom_reclass(c);
+}
+
+hipError_t wall_factors(mcb_ctx* c) {
+    if (c->n_wall <= 0) return hipSuccess;
+    const uint8_t* solid = reinterpret_cast<const uint8_t*>(c->lat + c->L.solid);
+    const int32_t* wn = reinterpret_cast<const int32_t*>(c->lk + c->L.wl_node);
+    const double* phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
+    if (c->p.precision == MCB_F64)
+        hipLaunchKernelGGL(k_wall_fac<double>, dim3(grid_for(c->n_wall, 256)), dim3(256), 0, c->stream, c->g, lat_index(c),
+                           c->n_wall, wn, solid, phi, reinterpret_cast<double*>(c->lk + c->L.wl_fac));
+    else
+        hipLaunchKernelGGL(k_wall_fac<float>, dim3(grid_for(c->n_wall, 256)), dim3(256), 0, c->stream, c->g, lat_index(c),
+                           c->n_wall, wn, solid, phi, reinterpret_cast<float*>(c->lk + c->L.wl_fac));
+    return hipGetLastError();
 }
 
 hipError_t geom_reclass(mcb_ctx* c) {

@@ -20,10 +20,14 @@ constexpr int STRIP_HALO = 4;            // 2-D step: halo lanes per strip (two 
 constexpr int Q2_LINKS = 8;               // link-coefficient slots per boundary node: one per direction,
 constexpr int Q3_LINKS = 20;              // 3-D: and two unused ones, so every node's slots start on 16 bytes
 // Boundary record of a boundary-fluid node, written by its collision and read by the pull of the
-// next step: the post-collision populations as stored (Q values), the force F (dim values), the
-// eq. 18 correction that the pull of the step applied, and padding to a multiple of 16 bytes.
-constexpr int REC2 = 12;                  // 9 + 2 + 1
-constexpr int REC3 = 24;                  // 19 + 3 + 1 + 1
+// next step: the terms of its exact-difference forcing (rho, du = F / rho, s = 2u + du and
+// duu = 1.5 du.s, from which F_j of eq. 13 follows per direction), its post-collision populations as
+// stored in the order 1 .. Q-1, 0, and the eq. 18 correction that the pull of that step applied.  The
+// pull loads only the leading RF + Q - 1 values (a loaded value that is never used frees its
+// register while the load is in flight, and the next write to it must wait for the load).
+constexpr int REC2 = 16;                  // 6 + 8 + 1 + 1
+constexpr int REC3 = 28;                  // 8 + 18 + 1 + 1
+constexpr int RF2 = 6, RF3 = 8;           // offset of population 1
 constexpr double NO_LINK = 2.0;           // coefficient of a direction without a link (|a| <= 1 on links)
 constexpr int SCAN_BLOCK = 256;           // geometry scan granularity
 constexpr int MON_BLOCKS = 1024;          // monitor partial sums
@@ -58,7 +62,7 @@ struct Layout {
     // lattice arena
     int64_t fa, fb, tag, nmask, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
     // links arena
-    int64_t bn_node, bn_mask, bn_link0, lk_qc, lk_a, rec[2], wl_node, wl_phi, links_bytes;
+    int64_t bn_node, bn_mask, bn_link0, lk_qc, lk_a, rec[2], wl_node, wl_phi, wl_fac, links_bytes;
     int64_t rec_slots;   // link-coefficient slots: Q2_LINKS / Q3_LINKS per boundary node
     int64_t rec_stride;  // compute-type values per boundary record (REC2 / REC3)
 };
@@ -128,6 +132,7 @@ hipError_t geom_classify(mcb_ctx* c);
 hipError_t geom_count(mcb_ctx* c);                // block sums + scan, totals at the end
 hipError_t geom_fill(mcb_ctx* c);                 // tags, boundary-node / wall tables, q, class
 hipError_t geom_reclass(mcb_ctx* c);              // class from the current q (after an override)
+hipError_t wall_factors(mcb_ctx* c);              // phi / (eq. 15 weight of the fluid neighbours) per wall node
 
 // step2d.hip / step3d.hip: one time step from the state (fcur, rcur) to (fnext, rnext), where r are
 // the boundary records of the state (pull = false: collision of fcur in place of the pull)

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_mon_partial(GridDev g, int L, const S* 
         if (!isfinite(m) || !isfinite(jx) || !isfinite(jy) || !isfinite(jz)) acc[5] += 1.0;
     }
     // eq. 18 corrections that the last step applied, from the boundary records of the state
-    const int ds = g.Q + g.dim;
+    const int ds = rec_stride - 1;
     for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < nb; b += stride) acc[4] += double(rec[b * rec_stride + ds]);
     __shared__ double red[MON_FIELDS][4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;

@@ -12,14 +12,13 @@
 //   bounce-back (q < 1/2, x2 solid):      c1 = 1,       c2 = 0,
 // and eq. 18 adds sum_links (f~_j(x, t) - f_in) to the rest population of x.  The pull of x already
 // brings f~_j(x2, t) (population j arrives from x - e_j); what else the links need is the node's own
-// post-collision populations and its force F(x, t), from which the exact-difference forcing term
-// F_j (eq. 13) is recomputed: rho = sum_i f~_i (the collision keeps the mass) and rho u =
-// sum_i f~_i e_i - F (the forcing term adds F to the momentum).  The collision of every boundary
-// node writes these into a contiguous boundary record; the pull of the next step reads the record
-// with the node's link coefficients in a few wide loads and applies the links in registers,
-// replacing the populations pulled from solid nodes.  Records alternate between two buffers with
-// the lattice buffers, since halo lanes of neighbouring workgroups read a node's record of time t
-// while its owner writes that of t+1.
+// post-collision populations and the exact-difference forcing term F_j(x, t) of eq. 13.  The
+// collision of every boundary node writes its populations and the terms F_j is made of (rho,
+// du = F / rho, s = 2u + du, 1.5 du.s) into a contiguous boundary record; the pull of the next step
+// reads the record with the node's link coefficients in a few wide loads and applies the links in
+// registers, replacing the populations pulled from solid nodes.  Records alternate between two
+// buffers with the lattice buffers, since halo lanes of neighbouring workgroups read a node's
+// record of time t while its owner writes that of t+1.
 //
 // Layout: a workgroup of W lanes (one or four waves) covers W consecutive columns -- W - 4 output
 // columns and two halo columns on each side -- over a segment of H rows, and marches up the
@@ -52,7 +51,7 @@ struct Args2 {
     const C* rin;                // boundary records of time t, REC2 per boundary node
     C* rout;                     // boundary records of time t+1
     const C* la;                 // link coefficients, Q2_LINKS per boundary node (NO_LINK: none)
-    const double* phi;           // wettability factor per wall node
+    const C* fac;                // eq. 15 factor per wall node: phi / weight of its fluid neighbours
     int32_t* flags;
     uint32_t n_bnodes, n_wall;
     int nx, ny, H, nsx, nblocks;
@@ -74,7 +73,7 @@ __device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 template <class S, class C, int W>
 struct March {
     Args2<S, C> a;
-    __amdgpu_buffer_rsrc_t fa, fb, tag, rin, rout, la, phi;
+    __amdgpu_buffer_rsrc_t fa, fb, tag, rin, rout, la, fac;
     C (*s_rho)[W];
     C (*s_psi)[W];
     int (*s_tag)[W];
@@ -84,17 +83,19 @@ struct March {
     bool out_col;
     // pipeline registers: tags of rows r-2, r-1, r; row r+1 and the tag of r+2 in flight
     int tgA, tgB, tgC;
-    int rr, rr1, tg_cur, tg_nxt, tg_nxt2;  // rows r+1 (pulling), r+2, r+3 (in flight)
-    double phA, phB;  // wettability factors of rows r-1 and r (wall lanes; issued with their pull)
-    C recN[REC2], aN[Q2_LINKS];  // boundary record and link coefficients of row r+1 (in flight)
+    int rr, rr1, tg_cur, tg_nxt, tg_nxt2;  // rows r+1, r+2 and the tags of r+1, r+2, r+3 (in flight)
+    C phA, phB;       // eq. 15 factors of rows r-1 and r (wall lanes; issued with their pull)
+    C recN[RF2 + 8], aN[Q2_LINKS];  // boundary record (the part the pull uses) and link coefficients of
+                                    // row r+1 (in flight)
     C dsA, dsB, dsC;             // eq. 18 corrections applied to rows r-2, r-1, r
     bool bad;
 };
 
 // Issue the loads of the nine populations arriving at row r of this lane's column (eq. 5), from
 // x - e_i; PULL = false reads the node's own populations (the collision that starts a run).
+// on = false: loads nothing (zeros).
 template <class S, class C, int W, bool PULL>
-__device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, C f[9]) {
+__device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, bool on, C f[9]) {
     constexpr uint32_t s = sizeof(S);
     const uint32_t rows = uint32_t(M.nx) * s;
     const uint32_t r0 = uint32_t(r) * rows;
@@ -103,31 +104,28 @@ __device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, C f[9])
     const uint32_t rowof[3] = {rp, r0, rm};  // upstream row of e_y = -1, 0, +1
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const uint32_t vo = PULL ? M.xcol_b[1 - kEx[i]] : M.xcol_b[1];
+        const uint32_t vo = on ? (PULL ? M.xcol_b[1 - kEx[i]] : M.xcol_b[1]) : OOB;
         const uint32_t so = uint32_t(i) * M.ns + (PULL ? rowof[kEy[i] + 1] : r0);
         f[i] = Buf<S>::ld(M.fa, vo, so);
     }
 }
 
+// e.(x, y) for a lattice vector of components 0 and +-1, folded when the components are constants
+// (a product with 0 cannot be dropped under IEEE rules)
+template <class C>
+__device__ __forceinline__ C edot(int ex, int ey, C x, C y) {
+    const C tx = ex > 0 ? x : -x, ty = ey > 0 ? y : -y;
+    return ex == 0 ? ty : (ey == 0 ? tx : tx + ty);
+}
+
 // Eqs. 16-18 at a boundary node (bnd) from its record of time t (rec) and link coefficients (ca):
 // replaces the populations pulled from solid neighbours by f_in and corrects the rest population;
-// returns the correction.  Lanes that are not boundary nodes keep f and return 0.
+// returns the correction.  Lanes that are not boundary nodes keep f and return 0.  Directions in
+// which no lane of the wave has a link are skipped.
 template <class S, class C>
-__device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[REC2], const C (&ca)[Q2_LINKS], C (&f)[9], C rho_ref) {
-    C rs = C(0), jx = C(0), jy = C(0);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        rs += rec[i];
-        jx += C(kEx[i]) * rec[i];
-        jy += C(kEy[i]) * rec[i];
-    }
-    const C rho = bnd ? rs + rho_ref : C(1);
-    const C irho = rcp(rho);
-    const C Fx = rec[9], Fy = rec[10];
-    const C ux = (jx - Fx) * irho, uy = (jy - Fy) * irho;
-    const C dux = Fx * irho, duy = Fy * irho;
-    const C sx = C(2) * ux + dux, sy = C(2) * uy + duy;
-    const C duu = C(1.5) * (dux * sx + duy * sy);
+__device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[RF2 + 8], const C (&ca)[Q2_LINKS], C (&f)[9]) {
+    const C rho = rec[0], dux = rec[1], duy = rec[2], sx = rec[3], sy = rec[4], duu = rec[5];
+    const C* fo = rec + RF2 - 1;  // own post-collision populations 1 .. 8
     // each slot opp(j) is replaced at most once, and never one that a later eq. 16 link reads (its
     // x2 = x - e_j is fluid, while a replaced slot was pulled from a solid node)
     C ds = C(0);
@@ -135,47 +133,51 @@ __device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[REC2], const C
     for (int j = 1; j < 9; ++j) {
         const C a = ca[j - 1];
         const bool lk = bnd && a < C(1.5);
-        const C c1 = a < C(0) ? -a : a, c2 = C(1) - c1;
-        // eq. 13 term of direction j: w rho [3 e.du + 4.5 (e.du)(e.(2u + du)) - 1.5 du.(2u + du)]
-        const C ed = C(kEx[j]) * dux + C(kEy[j]) * duy;
-        const C es = C(kEx[j]) * sx + C(kEy[j]) * sy;
-        const C Fj = w9<C>(j) * rho * (C(3) * ed + C(4.5) * ed * es - duu);
-        C o = a < C(0) ? rec[kOpp[j]] : f[j];
-        o = c2 != C(0) ? o : C(0);
-        // rounded to the storage format, as the value would be stored; eq. 18 takes it so
-        const C fin = Buf<S>::round(c1 * rec[j] + c2 * (o + Fj));
-        ds += lk ? rec[j] - fin : C(0);
-        f[kOpp[j]] = lk ? fin : f[kOpp[j]];
+        if (__builtin_amdgcn_ballot_w64(lk)) {
+            const C c1 = a < C(0) ? -a : a, c2 = C(1) - c1;
+            // eq. 13 term of direction j: w rho [3 e.du + 4.5 (e.du)(e.s) - 1.5 du.s]
+            const C ed = edot<C>(kEx[j], kEy[j], dux, duy);
+            const C es = edot<C>(kEx[j], kEy[j], sx, sy);
+            const C Fj = w9<C>(j) * rho * (C(3) * ed + C(4.5) * ed * es - duu);
+            C o = a < C(0) ? fo[kOpp[j]] : f[j];
+            o = c2 != C(0) ? o : C(0);
+            // rounded to the storage format, as the value would be stored; eq. 18 takes it so
+            const C fin = Buf<S>::round(c1 * fo[j] + c2 * (o + Fj));
+            ds += lk ? fo[j] - fin : C(0);
+            f[kOpp[j]] = lk ? fin : f[kOpp[j]];
+        }
     }
     f[0] += ds;
     return ds;
 }
 
 // One row of the march (iteration k, row r = y0 - 2 + k).  fC holds the pulled populations of row
-// r, fB and fA those of rows r-1 and r-2; the populations of row r+1 are issued into fN.
+// r, fB and fA those of rows r-1 and r-2, fN those of row r+1 (in flight); the populations of row
+// r+2 are issued into fP.
 template <class S, class C, int W, int OUT, bool PULL>
-__device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], C (&fB)[9], C (&fC)[9], C (&fN)[9]) {
+__device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], C (&fB)[9], C (&fC)[9], C (&fN)[9],
+                                          C (&fP)[9]) {
     const Args2<S, C>& a = M.a;
     const int t = M.p, nx = M.nx, ny = M.ny;  // LDS rows are indexed by column position
     constexpr uint32_t s = sizeof(S), sc = sizeof(C);
     const int slot = k & 3;
     M.tgA = M.tgB; M.tgB = M.tgC; M.tgC = M.tg_cur;
     M.dsA = M.dsB; M.dsB = M.dsC;
-    C recC[REC2], aC[Q2_LINKS];  // record and coefficients of row r (arrived with its pull)
+    C recC[RF2 + 8], aC[Q2_LINKS];  // record and coefficients of row r (arrived with its pull)
 #pragma unroll
-    for (int i = 0; i < REC2; ++i) recC[i] = M.recN[i];
+    for (int i = 0; i < RF2 + 8; ++i) recC[i] = M.recN[i];
 #pragma unroll
     for (int i = 0; i < Q2_LINKS; ++i) aC[i] = M.aN[i];
     const int tgA = M.tgA;
     const bool coll = k >= 4 && M.out_col && tgA >= 0;
     const int yA = ((M.y0 - 4 + k) % ny + ny) % ny;
     const uint32_t xAb = (uint32_t(yA) * nx) * s + M.xcol_b[1];  // byte offset of (x, yA) in a plane
-    // wettability factor of a wall node of row r-1 (psi below), loaded with that row's pull
-    const double phv = M.phA;
+    // eq. 15 factor of a wall node of row r-1 (psi below), loaded with that row's pull
+    const C phv = M.phA;
     __builtin_amdgcn_sched_barrier(0);
-    // ---- row r+1 populations and wettability factors, row r+3 tags.  The tags run three rows
-    // ahead of the pull: the row r+1 loads that depend on a tag then wait for nothing newer than
-    // row r-1, and the pulls of rows r and r+1 are in flight together.
+    // ---- row r+2 populations, row r+1 wettability factors, row r+3 tags.  The pulls run two rows
+    // ahead (rows r+1 and r+2 are in flight together), the tags three: the loads that depend on a
+    // tag then wait for nothing newer than row r-1.  Rows past the segment are not pulled.
     {
         const bool more = k + 1 < M.iters;
         M.rr = M.rr1;
@@ -183,8 +185,8 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         const int r3 = M.rr1 == ny - 1 ? 0 : M.rr1 + 1;
         M.tg_cur = more ? M.tg_nxt : -1;
         M.tg_nxt = M.tg_nxt2;
-        pull_row<S, C, W, PULL>(M, M.rr, fN);
-        const double phN = Buf<double>::ld(M.phi, M.tg_cur <= -2 ? uint32_t(-M.tg_cur - 2) * 8u : OOB);
+        pull_row<S, C, W, PULL>(M, M.rr1, k + 2 < M.iters, fP);
+        const C phN = Buf<C>::ld(M.fac, M.tg_cur <= -2 ? uint32_t(-M.tg_cur - 2) * sc : OOB);
         M.tg_nxt2 = ld_i32(M.tag, k + 3 < M.iters ? M.tag_b : OOB, uint32_t(r3) * (nx * 4u));
         M.phA = M.phB;
         M.phB = phN;
@@ -193,7 +195,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     // ---- A: links (eqs. 16-18) and density of row r
     {
         M.dsC = C(0);
-        if (PULL && __any(M.tgC > 0)) M.dsC = apply_links<S, C>(M.tgC > 0, recC, aC, fC, a.rho_ref);
+        if (PULL && __any(M.tgC > 0)) M.dsC = apply_links<S, C>(M.tgC > 0, recC, aC, fC);
         C sr = C(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) sr += fC[i];
@@ -219,8 +221,9 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         if (tg >= -1) {
             rho_n = M.s_rho[s_mid][t];
         } else {
-            // wall node: eq. 15 over the first layer, lattice weights of the fluid neighbours
-            C num = C(0), den = C(0);
+            // wall node: eq. 15 over the first layer -- the weighted sum of the neighbours' density
+            // (solid neighbours hold 0 in the ring) times phi / (weight of the fluid neighbours)
+            C num = C(0);
             const int rows[3] = {s_lo, s_mid, slot};
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
@@ -228,13 +231,9 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
                 for (int dx = -1; dx <= 1; ++dx) {
                     if (dx == 0 && dy == 0) continue;
                     const C w = (dx == 0 || dy == 0) ? C(1.0 / 9.0) : C(1.0 / 36.0);
-                    const int sl = rows[dy + 1];
-                    if (M.s_tag[sl][t + dx] >= 0) {
-                        num += w * M.s_rho[sl][t + dx];
-                        den += w;
-                    }
+                    num += w * M.s_rho[rows[dy + 1]][t + dx];
                 }
-            rho_n = C(phv) * num / den;
+            rho_n = phv * num;
         }
         M.s_psi[s_mid][t] = tg == -1 ? C(0) : psi_val(rho_n, a.eos, &M.bad);
     }
@@ -243,7 +242,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     // in the first four, which collide nothing, the results are discarded, and there is no branch
     // around the stores)
     C out[9];
-    C Fx, Fy;
+    C rho, dux, duy, sx2, sy2, duu15;  // forcing terms, kept for the boundary record
     {
         // the node's density at t+1 from the pulled values; the collision hands all of it back,
         // with f_0 taking the rounding
@@ -259,23 +258,25 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         const C pSW = M.s_psi[sl][tc - 1], pSE = M.s_psi[sl][tc + 1];
         // F = -G psi(x) sum_i w^_i psi(x + e_i) e_i, w^ = 1/3 (axes), 1/12 (diagonals)
         const C gp = -a.G * p0;
-        Fx = gp * (C(1.0 / 3.0) * (pE - pW) + C(1.0 / 12.0) * (pNE - pNW - pSW + pSE));
-        Fy = gp * (C(1.0 / 3.0) * (pN - pS) + C(1.0 / 12.0) * (pNE + pNW - pSW - pSE));
+        const C Fx = gp * (C(1.0 / 3.0) * (pE - pW) + C(1.0 / 12.0) * (pNE - pNW - pSW + pSE));
+        const C Fy = gp * (C(1.0 / 3.0) * (pN - pS) + C(1.0 / 12.0) * (pNE + pNW - pSW - pSE));
 
         const C rs = rs_pull;
-        const C rho = rs + a.rho_ref;
+        rho = rs + a.rho_ref;
         const C irho = rcp(coll ? rho : C(1));
         const C ux = (fA[1] - fA[3] + fA[5] - fA[6] - fA[7] + fA[8]) * irho;
         const C uy = (fA[2] - fA[4] + fA[5] + fA[6] - fA[7] - fA[8]) * irho;
-        const C dux = Fx * irho, duy = Fy * irho;
+        dux = Fx * irho;
+        duy = Fy * irho;
         const C ti = a.tau_inv, omc = C(1) - ti;
         // per direction: out_i = f_i (1 - 1/tau) + w_i [rs/tau + rho (sym_i +- anti_i)] with
         //   sym  = (4.5 (e.u)^2 - 1.5 u^2) / tau + 4.5 (e.du)(e.(2u + du)) - 1.5 du.(2u + du)
         //   anti = 3 (e.u / tau + e.du)
         // (eq. 14 equilibrium, eq. 13 forcing term, eq. 4 with S = I / tau)
         const C uu15 = C(1.5) * (ux * ux + uy * uy);
-        const C sx2 = C(2) * ux + dux, sy2 = C(2) * uy + duy;
-        const C duu15 = C(1.5) * (dux * sx2 + duy * sy2);
+        sx2 = C(2) * ux + dux;
+        sy2 = C(2) * uy + duy;
+        duu15 = C(1.5) * (dux * sx2 + duy * sy2);
         const C c0 = -(ti * uu15 + duu15);
         const C trs = ti * rs;
         auto pair = [&](int ip, int im, C w, C eu, C ed, C es) {
@@ -307,14 +308,20 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     const uint32_t xst = (k >= 4 && M.out_col) ? xAb : OOB;
 #pragma unroll
     for (int i = 0; i < 9; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), coll ? out[i] : C(0));
-    // boundary record of time t+1: the populations as stored, the force, the eq. 18 correction
+    // boundary record of time t+1: the forcing terms, the populations as stored, the eq. 18
+    // correction
     {
         C rv[REC2];
+        rv[0] = rho;
+        rv[1] = dux;
+        rv[2] = duy;
+        rv[3] = sx2;
+        rv[4] = sy2;
+        rv[5] = duu15;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) rv[i] = Buf<S>::round(out[i]);
-        rv[9] = Fx;
-        rv[10] = Fy;
-        rv[11] = M.dsA;
+        for (int i = 1; i < 9; ++i) rv[RF2 + i - 1] = out[i];  // rounded to the storage format above
+        rv[RF2 + 8] = Buf<S>::round(out[0]);
+        rv[RF2 + 9] = M.dsA;
         if (__any(coll && tgA > 0)) st_vec(M.rout, (coll && tgA > 0) ? uint32_t(tgA >> 8) * (REC2 * sc) : OOB, rv);
     }
 }
@@ -366,23 +373,24 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     M.rout = make_res(a.rout, uint64_t(a.n_bnodes) * REC2 * sizeof(C));
     M.la = make_res(a.la, uint64_t(a.n_bnodes) * Q2_LINKS * sizeof(C));
     M.ns = M.n * s;
-    M.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
+    M.fac = make_res(a.fac, uint64_t(a.n_wall) * sizeof(C));
     M.tgA = M.tgB = M.tgC = -1;
     M.dsA = M.dsB = M.dsC = C(0);
     M.bad = false;
-    // row march: the populations of row r+1 and the tag of row r+2 are in flight while row r is
-    // reduced to rho, row r-1 to psi and row r-2 collided; four register sets rotate
-    C f0[9], f1[9], f2[9], f3[9];
+    // row march: the populations of rows r+1 and r+2 are in flight while row r is reduced to rho,
+    // row r-1 to psi and row r-2 collided; five register sets rotate
+    C f0[9], f1[9], f2[9], f3[9], f4[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f0[i] = f1[i] = f2[i] = C(0);
+    for (int i = 0; i < 9; ++i) f0[i] = f1[i] = f4[i] = C(0);
     M.rr = ((M.y0 - 2) % a.ny + a.ny) % a.ny;
     M.tg_cur = ld_i32(M.tag, M.tag_b, uint32_t(M.rr) * (a.nx * 4u));
     M.rr1 = M.rr == a.ny - 1 ? 0 : M.rr + 1;
     M.tg_nxt = ld_i32(M.tag, M.tag_b, uint32_t(M.rr1) * (a.nx * 4u));
     M.tg_nxt2 = ld_i32(M.tag, M.tag_b, uint32_t(M.rr1 == a.ny - 1 ? 0 : M.rr1 + 1) * (a.nx * 4u));
-    pull_row<S, C, W, PULL>(M, M.rr, f3);
+    pull_row<S, C, W, PULL>(M, M.rr, true, f2);
+    pull_row<S, C, W, PULL>(M, M.rr1, true, f3);
 #pragma unroll
-    for (int i = 0; i < REC2; ++i) M.recN[i] = C(0);
+    for (int i = 0; i < RF2 + 8; ++i) M.recN[i] = C(0);
 #pragma unroll
     for (int i = 0; i < Q2_LINKS; ++i) M.aN[i] = C(0);
     if (PULL) {
@@ -390,19 +398,21 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
         ld_vec(M.rin, M.tg_cur > 0 ? bi * (REC2 * sc) : OOB, M.recN);
         ld_vec(M.la, M.tg_cur > 0 ? bi * (Q2_LINKS * sc) : OOB, M.aN);
     }
-    M.phA = 0.0;
-    M.phB = Buf<double>::ld(M.phi, M.tg_cur <= -2 ? uint32_t(-M.tg_cur - 2) * 8u : OOB);
+    M.phA = C(0);
+    M.phB = Buf<C>::ld(M.fac, M.tg_cur <= -2 ? uint32_t(-M.tg_cur - 2) * sc : OOB);
     int k = 0;
-    for (; k + 4 <= M.iters; k += 4) {
-        march_row<S, C, W, OUT, PULL>(M, k + 0, f0, f1, f3, f2);
-        march_row<S, C, W, OUT, PULL>(M, k + 1, f1, f3, f2, f0);
-        march_row<S, C, W, OUT, PULL>(M, k + 2, f3, f2, f0, f1);
-        march_row<S, C, W, OUT, PULL>(M, k + 3, f2, f0, f1, f3);
+    for (; k + 5 <= M.iters; k += 5) {
+        march_row<S, C, W, OUT, PULL>(M, k + 0, f0, f1, f2, f3, f4);
+        march_row<S, C, W, OUT, PULL>(M, k + 1, f1, f2, f3, f4, f0);
+        march_row<S, C, W, OUT, PULL>(M, k + 2, f2, f3, f4, f0, f1);
+        march_row<S, C, W, OUT, PULL>(M, k + 3, f3, f4, f0, f1, f2);
+        march_row<S, C, W, OUT, PULL>(M, k + 4, f4, f0, f1, f2, f3);
     }
     const int left = M.iters - k;  // uniform
-    if (left > 0) march_row<S, C, W, OUT, PULL>(M, k + 0, f0, f1, f3, f2);
-    if (left > 1) march_row<S, C, W, OUT, PULL>(M, k + 1, f1, f3, f2, f0);
-    if (left > 2) march_row<S, C, W, OUT, PULL>(M, k + 2, f3, f2, f0, f1);
+    if (left > 0) march_row<S, C, W, OUT, PULL>(M, k + 0, f0, f1, f2, f3, f4);
+    if (left > 1) march_row<S, C, W, OUT, PULL>(M, k + 1, f1, f2, f3, f4, f0);
+    if (left > 2) march_row<S, C, W, OUT, PULL>(M, k + 2, f2, f3, f4, f0, f1);
+    if (left > 3) march_row<S, C, W, OUT, PULL>(M, k + 3, f3, f4, f0, f1, f2);
     if (M.bad) atomicOr(&a.flags[FLAG_DOMAIN], 1);
 }
 
@@ -415,7 +425,7 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
     a.rin = static_cast<const C*>(rcur);
     a.rout = static_cast<C*>(rnext);
     a.la = reinterpret_cast<const C*>(c->lk + c->L.lk_a);
-    a.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
+    a.fac = reinterpret_cast<const C*>(c->lk + c->L.wl_fac);
     a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
     a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
     a.n_wall = uint32_t(c->n_wall > 0 ? c->n_wall : 0);
@@ -445,10 +455,10 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
 template <class S, class C>
 hipError_t launch_step2d(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
     // one-wave strips keep small lattices busy; on large lattices the strips are a whole number of
-    // cache lines wide (224 FP32 / FP64 columns, 448 FP16 columns), so that no line is shared
+    // cache lines wide (224 FP32 / FP64 columns, 192 FP16 columns), so that no line is shared
     // between strips or written in parts
     if (c->g.N <= (int64_t(1) << 21)) return launch_w<S, C, 64, 60>(c, fcur, rcur, fnext, rnext, pull);
-    if (sizeof(S) == 2) return launch_w<S, C, 512, 448>(c, fcur, rcur, fnext, rnext, pull);
+    if (sizeof(S) == 2) return launch_w<S, C, 256, 192>(c, fcur, rcur, fnext, rnext, pull);
     return launch_w<S, C, 256, 224>(c, fcur, rcur, fnext, rnext, pull);
 }
 

@@ -3,9 +3,10 @@
 // the interaction force, and the single-relaxation-time collision with exact-difference forcing
 // (eqs. 4, 13-14), with the curved boundary condition (eqs. 16-17) and the mass correction of
 // eq. 18 at boundary-fluid nodes.  As in two dimensions, the collision of a boundary node writes a
-// contiguous boundary record (post-collision populations as stored, force, eq. 18 correction), and
-// the pull of the next step reads it with the node's link coefficients in a few wide loads and
-// replaces the populations pulled from solid neighbours by the eq. 16-17 values.
+// contiguous boundary record (the terms of its forcing, its post-collision populations as stored,
+// the eq. 18 correction), and the pull of the next step reads it with the node's link coefficients
+// in a few wide loads and replaces the populations pulled from solid neighbours by the eq. 16-17
+// values.
 //
 // Layout: a workgroup of 32 x 16 lanes covers a 32 x 16 column tile of the x-y plane -- 28 x 12
 // output columns and two halo columns on every side -- over a segment of D planes in z, and
@@ -41,7 +42,7 @@ struct Args3 {
     const C* rin;                // boundary records of time t, REC3 per boundary node
     C* rout;                     // boundary records of time t+1
     const C* la;                 // link coefficients, Q3_LINKS per boundary node (NO_LINK: none)
-    const double* phi;           // wettability factor per wall node
+    const C* fac;                // eq. 15 factor per wall node: phi / weight of its fluid neighbours
     int32_t* flags;
     uint32_t n_bnodes, n_wall;
     int nx, ny, nz, D, ntx, nty, nblocks;
@@ -53,7 +54,7 @@ struct Args3 {
 template <class S, class C>
 struct March3 {
     Args3<S, C> a;
-    __amdgpu_buffer_rsrc_t fa, fb, tag, rin, rout, la, phi;
+    __amdgpu_buffer_rsrc_t fa, fb, tag, rin, rout, la, fac;
     C (*s_rho)[NT];
     C (*s_psi)[NT];
     int (*s_tag)[NT];
@@ -65,8 +66,9 @@ struct March3 {
     uint32_t vxy[9];   // byte offsets of the columns (x + dx, y + dy), index 3 (dy + 1) + dx + 1
     bool out_col, inner;
     int tgA, tgB, tgC, tg_r, tg_r1, tg_r2;  // tags of planes r-2, r-1, r (history) and r+1, r+2
-    double phA, phB;                 // wettability factors of planes r-1 and r (wall lanes)
-    C recN[REC3], aN[Q3_LINKS];      // boundary record and link coefficients of plane r+1 (PF)
+    C phA, phB;                      // eq. 15 factors of planes r-1 and r (wall lanes)
+    C recN[RF3 + 18], aN[18];        // boundary record (the part the pull uses) and link coefficients
+                                     // of plane r+1 (PF)
     C dsA, dsB, dsC;                 // eq. 18 corrections applied to planes r-2, r-1, r
     bool bad;
 };
@@ -91,7 +93,7 @@ __device__ __forceinline__ void pull_plane(const March3<S, C>& M, int z, C f[19]
 
 // boundary record of time t and link coefficients of a boundary node (tg > 0; other lanes get zeros)
 template <class S, class C>
-__device__ __forceinline__ void ld_rec(const March3<S, C>& M, int tg, C (&rec)[REC3], C (&ca)[Q3_LINKS]) {
+__device__ __forceinline__ void ld_rec(const March3<S, C>& M, int tg, C (&rec)[RF3 + 18], C (&ca)[18]) {
     constexpr uint32_t sc = sizeof(C);
     const uint32_t bi = uint32_t(tg - 1);
     ld_vec(M.rin, tg > 0 ? bi * (REC3 * sc) : OOB, rec);
@@ -104,65 +106,70 @@ __device__ inline C w19(int i) {
     return i == 0 ? C(1.0 / 3.0) : (i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0));
 }
 
+// e.(x, y, z) for a lattice vector of components 0 and +-1, folded when the components are
+// constants (a product with 0 cannot be dropped under IEEE rules)
+template <class C>
+__device__ __forceinline__ C edot3(int ex, int ey, int ez, C x, C y, C z) {
+    const C tx = ex > 0 ? x : -x, ty = ey > 0 ? y : -y, tz = ez > 0 ? z : -z;
+    const C a = ex == 0 ? ty : (ey == 0 ? tx : tx + ty);  // D3Q19: at most two components are set
+    return ez == 0 ? a : ((ex == 0 && ey == 0) ? tz : a + tz);
+}
+
 // Eqs. 16-18 at a boundary node (bnd) from its record of time t (rec) and link coefficients (ca):
 // replaces the populations pulled from solid neighbours by f_in (see the two-dimensional kernel for
 // the three cases) and corrects the rest population; returns the correction.  Lanes that are not
-// boundary nodes keep f and return 0.  LOAD_A: ca is loaded here from la at byte offset aoff, in
-// two halves, each just before its directions (keeps the FP64 kernel within its registers).
-template <class S, class C, bool LOAD_A>
-__device__ __forceinline__ C apply_links3(bool bnd, const C (&rec)[REC3], C (&ca)[Q3_LINKS], C (&f)[19], C rho_ref,
-                                          __amdgpu_buffer_rsrc_t la, uint32_t aoff) {
-    C rs = C(0), jx = C(0), jy = C(0), jz = C(0);
+// boundary nodes keep f and return 0; directions in which no lane of the wave has a link are
+// skipped.  LOAD: rec and ca are loaded here, from rin at byte offset roff and la at aoff, in two
+// halves, each just before its directions (keeps the FP64 kernel within its registers).
+template <class S, class C, bool LOAD>
+__device__ __forceinline__ C apply_links3(bool bnd, C (&rec)[RF3 + 18], C (&ca)[18], C (&f)[19], __amdgpu_buffer_rsrc_t rin,
+                                          uint32_t roff, __amdgpu_buffer_rsrc_t la, uint32_t aoff) {
+    constexpr int H1 = RF3 + 8, A1 = 8;  // first half: forcing terms, f~_1..f~_8; directions 1..8
+    if (LOAD) {
+        C h[H1], g[A1];
+        ld_vec(rin, roff, h);
+        ld_vec(la, aoff, g);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        rs += rec[i];
-        jx += C(kEx3[i]) * rec[i];
-        jy += C(kEy3[i]) * rec[i];
-        jz += C(kEz3[i]) * rec[i];
+        for (int i = 0; i < H1; ++i) rec[i] = h[i];
+#pragma unroll
+        for (int i = 0; i < A1; ++i) ca[i] = g[i];
     }
-    const C rho = bnd ? rs + rho_ref : C(1);
-    const C irho = rcp(rho);
-    const C Fx = rec[19], Fy = rec[20], Fz = rec[21];
-    const C ux = (jx - Fx) * irho, uy = (jy - Fy) * irho, uz = (jz - Fz) * irho;
-    const C dux = Fx * irho, duy = Fy * irho, duz = Fz * irho;
-    const C sx = C(2) * ux + dux, sy = C(2) * uy + duy, sz = C(2) * uz + duz;
-    const C duu = C(1.5) * (dux * sx + duy * sy + duz * sz);
+    const C rho = rec[0], dux = rec[1], duy = rec[2], duz = rec[3];
+    const C sx = rec[4], sy = rec[5], sz = rec[6], duu = rec[7];
     // each slot opp(j) is replaced at most once, and never one that a later eq. 16 link reads (its
     // x2 = x - e_j is fluid, while a replaced slot was pulled from a solid node)
     C ds = C(0);
     auto link = [&](int j) {
         const C a = ca[j - 1];
         const bool lk = bnd && a < C(1.5);
-        const C c1 = a < C(0) ? -a : a, c2 = C(1) - c1;
-        // eq. 13 term of direction j
-        const C ed = C(kEx3[j]) * dux + C(kEy3[j]) * duy + C(kEz3[j]) * duz;
-        const C es = C(kEx3[j]) * sx + C(kEy3[j]) * sy + C(kEz3[j]) * sz;
-        const C Fj = w19<C>(j) * rho * (C(3) * ed + C(4.5) * ed * es - duu);
-        const int jo = (j & 1) ? j + 1 : j - 1;  // opposite direction
-        C o = a < C(0) ? rec[jo] : f[j];
-        o = c2 != C(0) ? o : C(0);
-        const C fin = Buf<S>::round(c1 * rec[j] + c2 * (o + Fj));
-        ds += lk ? rec[j] - fin : C(0);
-        f[jo] = lk ? fin : f[jo];
+        if (__builtin_amdgcn_ballot_w64(lk)) {
+            const C c1 = a < C(0) ? -a : a, c2 = C(1) - c1;
+            // eq. 13 term of direction j
+            const C ed = edot3<C>(kEx3[j], kEy3[j], kEz3[j], dux, duy, duz);
+            const C es = edot3<C>(kEx3[j], kEy3[j], kEz3[j], sx, sy, sz);
+            const C Fj = w19<C>(j) * rho * (C(3) * ed + C(4.5) * ed * es - duu);
+            const int jo = (j & 1) ? j + 1 : j - 1;  // opposite direction
+            C o = a < C(0) ? rec[RF3 + jo - 1] : f[j];
+            o = c2 != C(0) ? o : C(0);
+            const C fin = Buf<S>::round(c1 * rec[RF3 + j - 1] + c2 * (o + Fj));
+            ds += lk ? rec[RF3 + j - 1] - fin : C(0);
+            f[jo] = lk ? fin : f[jo];
+        }
     };
-    constexpr int HALF = Q3_LINKS / 2;
-    if (LOAD_A) {
-        C h[HALF];
-        ld_vec(la, aoff, h);
 #pragma unroll
-        for (int i = 0; i < HALF; ++i) ca[i] = h[i];
-    }
-#pragma unroll
-    for (int j = 1; j <= HALF; ++j) link(j);
-    if (LOAD_A) {
+    for (int j = 1; j <= A1; ++j) link(j);
+    if (LOAD) {
         __builtin_amdgcn_sched_barrier(0);
-        C h[HALF];
-        ld_vec(la, aoff + uint32_t(HALF * sizeof(C)), h);
+        C h[RF3 + 18 - H1], g[18 - A1];
+        ld_vec(rin, roff + uint32_t(H1 * sizeof(C)), h);
+        ld_vec(la, aoff + uint32_t(A1 * sizeof(C)), g);
 #pragma unroll
-        for (int i = 0; i < HALF; ++i) ca[HALF + i] = h[i];
+        for (int i = 0; i < RF3 + 18 - H1; ++i) rec[H1 + i] = h[i];
+#pragma unroll
+        for (int i = 0; i < 18 - A1; ++i) ca[A1 + i] = g[i];
     }
 #pragma unroll
-    for (int j = HALF + 1; j < 19; ++j) link(j);
+    for (int j = A1 + 1; j < 19; ++j) link(j);
     f[0] += ds;
     return ds;
 }
@@ -180,16 +187,16 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
     M.tgA = M.tgB; M.tgB = M.tgC; M.tgC = M.tg_r;
     M.dsA = M.dsB; M.dsB = M.dsC;
     const int tgA = M.tgA;
-    C recC[REC3], aC[Q3_LINKS];  // record and coefficients of plane r
+    C recC[RF3 + 18], aC[18];  // record and coefficients of plane r
 #pragma unroll
-    for (int i = 0; i < REC3; ++i) recC[i] = M.recN[i];
+    for (int i = 0; i < RF3 + 18; ++i) recC[i] = M.recN[i];
 #pragma unroll
-    for (int i = 0; i < Q3_LINKS; ++i) aC[i] = M.aN[i];
+    for (int i = 0; i < 18; ++i) aC[i] = M.aN[i];
     const bool coll = k >= 4 && M.out_col && tgA >= 0;
     const int zA = ((M.z0 - 4 + k) % M.nz + M.nz) % M.nz;
     const uint32_t xAb = uint32_t(zA) * M.pb + M.vxy[4];  // byte offset of (x, y, zA) in a population array
-    // wettability factor of a wall node of plane r-1 (psi below), loaded with that plane's pull
-    const double phv = M.phA;
+    // eq. 15 factor of a wall node of plane r-1 (psi below), loaded with that plane's pull
+    const C phv = M.phA;
     __builtin_amdgcn_sched_barrier(0);
     // ---- plane r+1 populations and wettability factors (PF, else plane r), tags of plane r+3.
     // The tags run three planes ahead of the pull: the loads that depend on a tag then wait for
@@ -202,7 +209,7 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
         } else {
             pull_plane<S, C, PULL>(M, M.zc, fC);
         }
-        const double phN = Buf<double>::ld(M.phi, tgp <= -2 ? uint32_t(-tgp - 2) * 8u : OOB);
+        const C phN = Buf<C>::ld(M.fac, tgp <= -2 ? uint32_t(-tgp - 2) * sc : OOB);
         const int tg3 = ld_i32(M.tag, M.own4, uint32_t(z3) * M.p4);
         M.tg_r = M.tg_r1;
         M.tg_r1 = M.tg_r2;
@@ -223,8 +230,7 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
             // without the prefetch (FP64) the record and the coefficients are loaded here, when the
             // plane's pull is in
             const uint32_t bi = uint32_t(M.tgC - 1);
-            if (!PF) ld_vec(M.rin, M.tgC > 0 ? bi * (REC3 * sc) : OOB, recC);
-            M.dsC = apply_links3<S, C, !PF>(M.tgC > 0, recC, aC, fC, a.rho_ref, M.la,
+            M.dsC = apply_links3<S, C, !PF>(M.tgC > 0, recC, aC, fC, M.rin, M.tgC > 0 ? bi * (REC3 * sc) : OOB, M.la,
                                             M.tgC > 0 ? bi * (Q3_LINKS * sc) : OOB);
         }
         C sr = C(0);
@@ -249,20 +255,16 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
         if (tg >= -1) {
             rho_n = M.s_rho[s_mid][t];
         } else {
-            // wall node: eq. 15 over the first layer, lattice weights of the fluid neighbours
-            C num = C(0), den = C(0);
+            // wall node: eq. 15 over the first layer -- the weighted sum of the neighbours' density
+            // (solid neighbours hold 0 in the ring) times phi / (weight of the fluid neighbours)
+            C num = C(0);
             const int pl[3] = {s_lo, s_mid, slot};
 #pragma unroll
             for (int i = 1; i < 19; ++i) {
                 const C w = i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0);
-                const int sl = pl[kEz3[i] + 1];
-                const int nb = t + kEx3[i] + TX * kEy3[i];
-                if (M.s_tag[sl][nb] >= 0) {
-                    num += w * M.s_rho[sl][nb];
-                    den += w;
-                }
+                num += w * M.s_rho[pl[kEz3[i] + 1]][t + kEx3[i] + TX * kEy3[i]];
             }
-            rho_n = C(phv) * num / den;
+            rho_n = phv * num;
         }
         M.s_psi[s_mid][t] = tg == -1 ? C(0) : psi_val(rho_n, a.eos, &M.bad);
     }
@@ -270,7 +272,8 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
     // ---- C: force and collision of plane r - 2; colliding lanes store.  Waves that hold no
     // output column skip the arithmetic but still issue the (out-of-bounds) stores.
     C out[19];
-    C Fx = C(0), Fy = C(0), Fz = C(0);
+    // forcing terms, kept for the boundary record
+    C rho = C(0), dux = C(0), duy = C(0), duz = C(0), sx2 = C(0), sy2 = C(0), sz2 = C(0), duu15 = C(0);
 #pragma unroll
     for (int i = 0; i < 19; ++i) out[i] = C(0);
     if (__any(coll)) {
@@ -291,25 +294,29 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
         const C exy1 = P(1, 1, 0) - P(-1, -1, 0), exy2 = P(1, -1, 0) - P(-1, 1, 0);
         const C exz1 = P(1, 0, 1) - P(-1, 0, -1), exz2 = P(1, 0, -1) - P(-1, 0, 1);
         const C eyz1 = P(0, 1, 1) - P(0, -1, -1), eyz2 = P(0, 1, -1) - P(0, -1, 1);
-        Fx = gp * (C(1.0 / 6.0) * (P(1, 0, 0) - P(-1, 0, 0)) + C(1.0 / 12.0) * (exy1 + exy2 + exz1 + exz2));
-        Fy = gp * (C(1.0 / 6.0) * (P(0, 1, 0) - P(0, -1, 0)) + C(1.0 / 12.0) * (exy1 - exy2 + eyz1 + eyz2));
-        Fz = gp * (C(1.0 / 6.0) * (P(0, 0, 1) - P(0, 0, -1)) + C(1.0 / 12.0) * (exz1 - exz2 + eyz1 - eyz2));
+        const C Fx = gp * (C(1.0 / 6.0) * (P(1, 0, 0) - P(-1, 0, 0)) + C(1.0 / 12.0) * (exy1 + exy2 + exz1 + exz2));
+        const C Fy = gp * (C(1.0 / 6.0) * (P(0, 1, 0) - P(0, -1, 0)) + C(1.0 / 12.0) * (exy1 - exy2 + eyz1 + eyz2));
+        const C Fz = gp * (C(1.0 / 6.0) * (P(0, 0, 1) - P(0, 0, -1)) + C(1.0 / 12.0) * (exz1 - exz2 + eyz1 - eyz2));
 
-        const C rho = rs + a.rho_ref;
+        rho = rs + a.rho_ref;
         const C irho = rcp(coll ? rho : C(1));
         const C jx = (fA[1] - fA[2]) + (fA[7] - fA[8]) + (fA[9] - fA[10]) + (fA[11] - fA[12]) + (fA[13] - fA[14]);
         const C jy = (fA[3] - fA[4]) + (fA[7] - fA[8]) - (fA[9] - fA[10]) + (fA[15] - fA[16]) + (fA[17] - fA[18]);
         const C jz = (fA[5] - fA[6]) + (fA[11] - fA[12]) - (fA[13] - fA[14]) + (fA[15] - fA[16]) - (fA[17] - fA[18]);
         const C ux = jx * irho, uy = jy * irho, uz = jz * irho;
-        const C dux = Fx * irho, duy = Fy * irho, duz = Fz * irho;
+        dux = Fx * irho;
+        duy = Fy * irho;
+        duz = Fz * irho;
         const C ti = a.tau_inv, omc = C(1) - ti;
         // per direction: out_i = f_i (1 - 1/tau) + w_i [rs/tau + rho (sym_i +- anti_i)] with
         //   sym  = (4.5 (e.u)^2 - 1.5 u^2) / tau + 4.5 (e.du)(e.(2u + du)) - 1.5 du.(2u + du)
         //   anti = 3 (e.u / tau + e.du)
         // (eq. 14 equilibrium, eq. 13 forcing term, eq. 4 with S = I / tau)
         const C uu15 = C(1.5) * (ux * ux + uy * uy + uz * uz);
-        const C sx2 = C(2) * ux + dux, sy2 = C(2) * uy + duy, sz2 = C(2) * uz + duz;
-        const C duu15 = C(1.5) * (dux * sx2 + duy * sy2 + duz * sz2);
+        sx2 = C(2) * ux + dux;
+        sy2 = C(2) * uy + duy;
+        sz2 = C(2) * uz + duz;
+        duu15 = C(1.5) * (dux * sx2 + duy * sy2 + duz * sz2);
         const C c0 = -(ti * uu15 + duu15);
         const C trs = ti * rs;
         auto pair = [&](int ip, int im, C w, C eu, C ed, C es) {
@@ -345,16 +352,22 @@ __device__ __forceinline__ void march_plane(March3<S, C>& M, int k, C (&fA)[19],
     const uint32_t xst = (k >= 4 && M.out_col) ? xAb : OOB;
 #pragma unroll
     for (int i = 0; i < 19; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), coll ? out[i] : C(0));
-    // boundary record of time t+1: the populations as stored, the force, the eq. 18 correction
+    // boundary record of time t+1: the forcing terms, the populations as stored, the eq. 18
+    // correction
     {
         C rv[REC3];
+        rv[0] = rho;
+        rv[1] = dux;
+        rv[2] = duy;
+        rv[3] = duz;
+        rv[4] = sx2;
+        rv[5] = sy2;
+        rv[6] = sz2;
+        rv[7] = duu15;
 #pragma unroll
-        for (int i = 0; i < 19; ++i) rv[i] = Buf<S>::round(out[i]);
-        rv[19] = Fx;
-        rv[20] = Fy;
-        rv[21] = Fz;
-        rv[22] = M.dsA;
-        rv[23] = C(0);
+        for (int i = 1; i < 19; ++i) rv[RF3 + i - 1] = out[i];  // rounded to the storage format above
+        rv[RF3 + 18] = Buf<S>::round(out[0]);
+        rv[RF3 + 19] = M.dsA;
         if (__any(coll && tgA > 0)) st_vec(M.rout, (coll && tgA > 0) ? uint32_t(tgA - 1) * (REC3 * sc) : OOB, rv);
     }
 }
@@ -408,13 +421,13 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
     M.rin = make_res(a.rin, uint64_t(a.n_bnodes) * REC3 * sizeof(C));
     M.rout = make_res(a.rout, uint64_t(a.n_bnodes) * REC3 * sizeof(C));
     M.la = make_res(a.la, uint64_t(a.n_bnodes) * Q3_LINKS * sizeof(C));
-    M.phi = make_res(a.phi, uint64_t(a.n_wall) * 8);
+    M.fac = make_res(a.fac, uint64_t(a.n_wall) * sizeof(C));
     M.tgA = M.tgB = M.tgC = -1;
     M.dsA = M.dsB = M.dsC = C(0);
 #pragma unroll
-    for (int i = 0; i < REC3; ++i) M.recN[i] = C(0);
+    for (int i = 0; i < RF3 + 18; ++i) M.recN[i] = C(0);
 #pragma unroll
-    for (int i = 0; i < Q3_LINKS; ++i) M.aN[i] = C(0);
+    for (int i = 0; i < 18; ++i) M.aN[i] = C(0);
     M.bad = false;
     // prologue: tags of planes r and r+1, populations of plane r (PF)
     C fA[19], fB[19], fC[19], fN[19];
@@ -424,12 +437,12 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
     M.tg_r = ld_i32(M.tag, M.own4, uint32_t(M.zc) * M.p4);
     M.tg_r1 = ld_i32(M.tag, M.own4, uint32_t(zinc(M.zc, a.nz)) * M.p4);
     M.tg_r2 = ld_i32(M.tag, M.own4, uint32_t(zinc(zinc(M.zc, a.nz), a.nz)) * M.p4);
-    M.phA = 0.0;
-    M.phB = 0.0;
+    M.phA = C(0);
+    M.phB = C(0);
     if (PF) {
         pull_plane<S, C, PULL>(M, M.zc, fC);
         if (PULL) ld_rec(M, M.tg_r, M.recN, M.aN);
-        M.phB = Buf<double>::ld(M.phi, M.tg_r <= -2 ? uint32_t(-M.tg_r - 2) * 8u : OOB);
+        M.phB = Buf<C>::ld(M.fac, M.tg_r <= -2 ? uint32_t(-M.tg_r - 2) * sizeof(C) : OOB);
     }
     // the register sets rotate by copies (an unrolled rotation costs the allocator far more)
     for (int k = 0; k < M.iters; ++k) {
@@ -453,7 +466,7 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, const void* rcur, void* f
     a.rin = static_cast<const C*>(rcur);
     a.rout = static_cast<C*>(rnext);
     a.la = reinterpret_cast<const C*>(c->lk + c->L.lk_a);
-    a.phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
+    a.fac = reinterpret_cast<const C*>(c->lk + c->L.wl_fac);
     a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
     a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
     a.n_wall = uint32_t(c->n_wall > 0 ? c->n_wall : 0);

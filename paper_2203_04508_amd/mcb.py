@@ -240,6 +240,12 @@ def mcb_timing_report(ctx):
 
 
 MCB_LOSS_COM_X, MCB_LOSS_WETTED_LENGTH, MCB_LOSS_TOTAL_MASS = 0, 1, 2
+LOSS_COM_X, LOSS_WETTED_LENGTH, LOSS_TOTAL_MASS = MCB_LOSS_COM_X, MCB_LOSS_WETTED_LENGTH, MCB_LOSS_TOTAL_MASS
+
+# Per-boundary-node storage of the step kernel (compute-type values), for traffic accounting: the
+# boundary record (forcing terms, populations, eq. 18 correction) and the link-coefficient slots.
+REC2, REC3 = 16, 28
+Q2_LINKS, Q3_LINKS = 8, 20
 
 
 def mcb_adj_required_bytes(ctx, nsteps, k) -> int:

@@ -15,6 +15,7 @@ Two phases:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sqlite3
@@ -22,6 +23,16 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def kernel_digest(dim: int) -> str:
+    """Hash of the sources the step kernel of a dimension is built from: counters taken on another
+    version of the kernel do not describe this one."""
+    h = hashlib.sha256()
+    for f in ("step2d.hip" if dim == 2 else "step3d.hip", "kernels_common.h", "mcb_internal.h"):
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def run(args):
@@ -66,7 +77,11 @@ def _largest(rows, match):
 
 
 def summarize(args):
-    out = {"workload": args.workload, "precision": args.precision, "copy_bytes": COPY_BYTES}
+    sys.path.insert(0, ROOT)
+    from paper_2203_04508_amd import workloads as W
+
+    out = {"workload": args.workload, "precision": args.precision, "copy_bytes": COPY_BYTES,
+           "kernel_digest": kernel_digest(W.make(args.workload).dim)}
     lines = []
     is_step = lambda k: "k_step2d" in k or "k_step3d" in k
     # the device copy of COPY_BYTES is the largest copy dispatch of the run
@@ -88,7 +103,8 @@ def summarize(args):
     base = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}")
     json.dump(out, open(base + ".json", "w"), indent=1)
     with open(base + ".txt", "w") as fh:
-        fh.write(f"HBM traffic of the fused step kernel, workload {args.workload}, storage {args.precision}\n")
+        fh.write(f"HBM traffic of the fused step kernel, workload {args.workload}, storage {args.precision} "
+                 f"(kernel sources {out['kernel_digest']})\n")
         fh.write(f"commands: {args.commands}\n" if args.commands else "")
         fh.write("\n".join(lines) + "\n")
         fh.write(f"total calibrated bytes per launch: {out['bytes_per_launch'] / 1e6:.1f} MB\n")
