@@ -7,8 +7,9 @@
 // State.  The forward step reads, besides the populations g(t), the forcing term F_j(x, t) of
 // eq. 13 on every fluid-solid link (eqs. 16-17 use it one step later), so the state is the pair
 // (g, R) with R the per-link forcing terms; its adjoint is (lambda, lambda_R).  The step keeps
-// the force F(x, t) of each boundary node, from which R follows with the node's own populations
-// (see the boundary pass); the reverse sweep recomputes R the same way.
+// the forcing terms of each boundary node in its boundary record (rho and du = F / rho among them);
+// the reverse sweep takes F = rho du from the record of each state and recomputes R from F and the
+// node's own populations.
 //
 // Forward step, per fluid node x (f = g + w rho_ref in the shifted storages):
 //   streaming, eq. 5:     p_i(x) = f_i(x - e_i)                           (x - e_i fluid)
