@@ -197,7 +197,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step2d" if wl.dim == 2 else "k_step3d",
+            "kernel": "k_step2d" if wl.dim == 2 else "k_rho3d + k_step3d (one step)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

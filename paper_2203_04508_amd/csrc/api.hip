@@ -29,6 +29,7 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.fb = take(Q * N * s);
     L.tag = take(4 * N);
     L.nmask = take(p.dim == 3 ? 4 * N : 0);  // 3-D: link bits of each boundary node (bit j-1: x + e_j solid)
+    L.rho3 = take(p.dim == 3 ? cb * N : 0);  // 3-D: density pass output of the step (compute type)
     L.solid = take(N);
     L.scratch = take(8 * N * (2 + p.dim));
     L.blocksums = take(8 * (3 * nblk + 3));
@@ -264,6 +265,11 @@ mcb_status mcb_bind_buffers(mcb_ctx* c, const mcb_buffers* b, void* stream) {
         c->lk_bytes = b->links_bytes;
     }
     c->stream = static_cast<hipStream_t>(stream);
+    {
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     if (c->stage < 1) c->stage = 1;
     // lattice offsets do not depend on the counts; refresh the link offsets if counts are known
     c->L = make_layout(c->p, c->n_shapes, c->n_links > 0 ? c->n_links : 0, c->n_bnodes > 0 ? c->n_bnodes : 0,

@@ -147,6 +147,22 @@ __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double fsqrt(double x) { return sqrt(x); }
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// ---------------------------------------------------------------- launch shape
+// Workgroups of a kernel that the device holds at once (occupancy per compute unit x units).  The
+// marching step kernels size their segments so that the whole grid is resident: every workgroup
+// starts together, neighbours march in step (their shared halo lines meet in L2), and no partial
+// last round leaves units idle.
+// occ caches the per-unit occupancy (a property of the kernel alone; 0 = not yet queried).
+template <class K>
+inline int resident_blocks(const mcb_ctx* c, K kernel, int threads, int* occ) {
+    if (*occ < 1) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kernel, threads, 0) != hipSuccess || o < 1) o = 1;
+        *occ = o;
+    }
+    return *occ * (c->n_cu > 0 ? c->n_cu : 1);
+}
+
 // ---------------------------------------------------------------- thermodynamics
 template <class C>
 struct Eos {

@@ -21,10 +21,12 @@ constexpr int Q2_LINKS = 8;               // link-coefficient slots per boundary
 constexpr int Q3_LINKS = 20;              // 3-D: and two unused ones, so every node's slots start on 16 bytes
 // Boundary record of a boundary-fluid node, written by its collision and read by the pull of the
 // next step: the terms of its exact-difference forcing (rho, du = F / rho, s = 2u + du and
-// duu = 1.5 du.s, from which F_j of eq. 13 follows per direction), its post-collision populations as
-// stored in the order 1 .. Q-1, 0, and the eq. 18 correction that the pull of that step applied.  The
-// pull loads only the leading RF + Q - 1 values (a loaded value that is never used frees its
-// register while the load is in flight, and the next write to it must wait for the load).
+// duu = 1.5 du.s, from which F_j of eq. 13 follows per direction), its post-collision populations
+// 1 .. Q-1 as stored, one slot (2-D: population 0 as stored; 3-D: the sum of the node's own
+// populations on its links, which the 3-D density pass adds), and the eq. 18 correction that the
+// pull of that step applied.  The pull loads only the leading RF + Q - 1 values (a loaded value
+// that is never used frees its register while the load is in flight, and the next write to it
+// must wait for the load).
 constexpr int REC2 = 16;                  // 6 + 8 + 1 + 1
 constexpr int REC3 = 28;                  // 8 + 18 + 1 + 1
 constexpr int RF2 = 6, RF3 = 8;           // offset of population 1
@@ -60,7 +62,7 @@ struct GridDev {
 // Byte offsets of the sub-buffers carved out of the two caller-owned arenas.
 struct Layout {
     // lattice arena
-    int64_t fa, fb, tag, nmask, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
+    int64_t fa, fb, tag, nmask, rho3, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
     // links arena
     int64_t bn_node, bn_mask, bn_link0, lk_qc, lk_a, rec[2], wl_node, wl_phi, wl_fac, links_bytes;
     int64_t rec_slots;   // link-coefficient slots: Q2_LINKS / Q3_LINKS per boundary node
@@ -91,6 +93,7 @@ struct mcb_ctx {
     mcb_params p{};
     mcb::GridDev g{};
     hipStream_t stream = nullptr;
+    int n_cu = 0;         // compute units of the device (sizes the step grids to whole rounds)
     char* lat = nullptr;
     int64_t lat_bytes = 0;
     char* lk = nullptr;

@@ -432,10 +432,21 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.nsx = (a.nx + OUT - 1) / OUT;
-    // segment height: long segments amortise the four halo rows; short ones fill the chip
-    const int64_t target = W == 64 ? 8192 : 2048;
-    int H = 64;
-    while (H > 8 && int64_t(a.nsx) * ((a.ny + H - 1) / H) < target) H >>= 1;
+    // segment height: long segments amortise the four halo rows; short ones fill the chip.  Wide
+    // strips: as many segments as the device holds at once (all workgroups resident together);
+    // one-wave strips (small lattices): enough workgroups to fill the chip several times over.
+    int H;
+    if (W == 64) {
+        H = 64;
+        while (H > 8 && int64_t(a.nsx) * ((a.ny + H - 1) / H) < 8192) H >>= 1;
+    } else {
+        static int occ[2] = {0, 0};
+        const int cap = pull ? resident_blocks(c, k_step2d<S, C, W, OUT, true>, W, &occ[1])
+                             : resident_blocks(c, k_step2d<S, C, W, OUT, false>, W, &occ[0]);
+        const int per = cap / a.nsx > 0 ? cap / a.nsx : 1;  // segments per strip
+        H = (a.ny + per - 1) / per;
+        if (H < 16) H = 16;
+    }
     a.H = H;
     a.nblocks = a.nsx * ((a.ny + H - 1) / H);
     a.tau_inv = C(1.0 / c->p.tau);

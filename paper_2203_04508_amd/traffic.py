@@ -76,38 +76,66 @@ def _largest(rows, match):
     return max(vals) if vals else None, len(vals)
 
 
+def _pull_kernel(name):
+    """The per-step kernels of the pulling step (not the collision that starts a run), by name:
+    k_step2d<S, C, W, OUT, PULL>, k_step3d<S, C, PULL, PF>, k_rho3d<S, C, PULL>."""
+    for k, idx in (("k_step2d<", 4), ("k_step3d<", 2), ("k_rho3d<", 2)):
+        if k in name:
+            args = name.split(k, 1)[1].split(">", 1)[0].split(",")
+            return len(args) > idx and args[idx].strip() == "true"
+    return False
+
+
+def _short(name):
+    for k in ("k_step2d", "k_step3d", "k_rho3d"):
+        if k in name:
+            return k
+    return name
+
+
 def summarize(args):
     sys.path.insert(0, ROOT)
     from paper_2203_04508_amd import workloads as W
 
     out = {"workload": args.workload, "precision": args.precision, "copy_bytes": COPY_BYTES,
-           "kernel_digest": kernel_digest(W.make(args.workload).dim)}
+           "kernel_digest": kernel_digest(W.make(args.workload).dim), "kernels": {}}
     lines = []
-    is_step = lambda k: "k_step2d" in k or "k_step3d" in k
     # the device copy of COPY_BYTES is the largest copy dispatch of the run
     is_copy = lambda k: "copybuffer" in k.lower()
     for counter, db, key in (("FETCH_SIZE", args.fetch_db, "read"), ("WRITE_SIZE", args.write_db, "write")):
         rows = _counter(db, counter)
-        step_kib, nstep = _per_dispatch(rows, lambda k: is_step(k) and "true" in k)
-        copy_kib, ncopy = _largest(rows, is_copy)
+        copy_kib, _ = _largest(rows, is_copy)
         factor = COPY_BYTES / (copy_kib * 1024.0)
-        out[f"{key}_counter_kib_per_dispatch"] = step_kib
         out[f"{key}_copy_counter_kib"] = copy_kib
         out[f"{key}_scale"] = factor
-        out[f"{key}_bytes_per_launch"] = step_kib * 1024.0 * factor
-        lines.append(f"{counter}: step kernel {step_kib:.0f} KiB/dispatch over {nstep} dispatches; "
-                     f"the {COPY_BYTES} B copy reads {copy_kib:.0f} KiB on this counter -> scale {factor:.4f}; "
-                     f"calibrated {out[f'{key}_bytes_per_launch'] / 1e6:.1f} MB per launch")
-    out["bytes_per_launch"] = out["read_bytes_per_launch"] + out["write_bytes_per_launch"]
+        names = sorted({k for k, d, v in rows if _pull_kernel(k)})
+        for name in names:
+            kib, n = _per_dispatch(rows, lambda k, name=name: k == name)
+            kk = out["kernels"].setdefault(_short(name), {"name": name})
+            kk[f"{key}_counter_kib_per_dispatch"] = kib
+            kk[f"{key}_bytes_per_launch"] = kib * 1024.0 * factor
+            lines.append(f"{counter}: {_short(name)} {kib:.0f} KiB/dispatch over {n} dispatches; "
+                         f"calibrated {kk[f'{key}_bytes_per_launch'] / 1e6:.1f} MB per launch")
+        lines.append(f"{counter}: the {COPY_BYTES} B copy reads {copy_kib:.0f} KiB on this counter -> scale {factor:.4f}")
+    step = 0.0
+    for kk in out["kernels"].values():
+        kk["bytes_per_launch"] = kk.get("read_bytes_per_launch", 0.0) + kk.get("write_bytes_per_launch", 0.0)
+        step += kk["bytes_per_launch"]
+    # the step kernel proper (the collision pass in three dimensions) is the one bench.py reports
+    main = out["kernels"].get("k_step2d") or out["kernels"].get("k_step3d")
+    out["bytes_per_launch"] = main["bytes_per_launch"] if main else None
+    out["bytes_per_step"] = step
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     base = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}")
     json.dump(out, open(base + ".json", "w"), indent=1)
     with open(base + ".txt", "w") as fh:
-        fh.write(f"HBM traffic of the fused step kernel, workload {args.workload}, storage {args.precision} "
+        fh.write(f"HBM traffic of the step kernels, workload {args.workload}, storage {args.precision} "
                  f"(kernel sources {out['kernel_digest']})\n")
         fh.write(f"commands: {args.commands}\n" if args.commands else "")
         fh.write("\n".join(lines) + "\n")
-        fh.write(f"total calibrated bytes per launch: {out['bytes_per_launch'] / 1e6:.1f} MB\n")
+        for k, kk in out["kernels"].items():
+            fh.write(f"{k}: {kk['bytes_per_launch'] / 1e6:.1f} MB per launch (read + write)\n")
+        fh.write(f"total calibrated bytes per step: {step / 1e6:.1f} MB\n")
     print(open(base + ".txt").read())
 
 
