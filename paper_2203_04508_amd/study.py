@@ -86,7 +86,8 @@ def main():
             ref = rho
         r["rho_l2_rel_vs_f64"] = float(np.linalg.norm(rho - ref) / np.linalg.norm(ref))
         rows.append(r)
-    out = {"workload": wl.name, "dims": list(wl.dims[:wl.dim]), "steps": steps, "runs": rows}
+    out = {"command": "python3 -m paper_2203_04508_amd.study " + " ".join(sys.argv[1:]),
+           "workload": wl.name, "dims": list(wl.dims[:wl.dim]), "steps": steps, "runs": rows}
     text = json.dumps(out, indent=1)
     print(text)
     if args.out:
