@@ -98,8 +98,19 @@ def fwd_adjoint(precision):
     }
 
 
-def cpu_baseline(wl, budget_s=12.0):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, budget_s=12.0, single_s=4.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload: all threads
+    OpenMP gives it, then one thread."""
     from oracle import oracle
     from paper_2203_04508_amd import workloads as W
 
@@ -108,19 +119,30 @@ def cpu_baseline(wl, budget_s=12.0):
     sim.set_phi(W.phi_for_walls(wl, oracle.wall_nodes(P, solid)))
     sim.init_eq(wl.rho0())
     sim.step(1)
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        sim.step(1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or steps >= 1000:
-            break
+
+    def timed(budget):
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            sim.step(1)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > budget or steps >= 1000:
+                return steps, el
+
+    threads = oracle.num_threads()
+    steps, el = timed(budget_s)
+    oracle.set_threads(1)
+    s1, e1 = timed(single_s)
+    oracle.set_threads(threads)
     return {
         "value": wl.N * steps / el / 1e6,
         "unit": "MLUPS",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": f"{steps} steps of workload {wl.name} ({'x'.join(map(str, wl.dims[:wl.dim]))}) after set-up, FP64",
+        "cpu_model": _cpu_model(),
+        "single_thread_value": wl.N * s1 / e1 / 1e6,
+        "single_thread_sample": f"{s1} steps, 1 thread",
     }
 
 

@@ -536,6 +536,16 @@ int or_num_threads(void) {
 #endif
 }
 
+// timing helper: the number of threads later parallel loops use (no effect on the arithmetic,
+// which is per node)
+void or_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 // ---- lattice and pointwise pieces (used by the pins) ----
 int or_lattice(int dim, int32_t* e, double* w, double* wf, int32_t* opp) {
     Lat L = make_lat(dim);

@@ -101,6 +101,8 @@ def lib():
         L.or_sim_loss.argtypes = [vp, C.c_int, vp, vp]
         L.or_sim_loss.restype = C.c_int
         L.or_dual_kd.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_set_threads.restype = None
         L.or_dsim_create.argtypes = [P, vp, vp, vp, vp, C.c_int64]
         L.or_dsim_create.restype = vp
         L.or_dsim_destroy.argtypes = [vp]
@@ -122,6 +124,11 @@ def _p(a: np.ndarray):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (timing only; results do not depend on it)."""
+    lib().or_set_threads(int(n))
 
 
 # ---------------------------------------------------------------------------- pointwise pieces
