@@ -55,7 +55,8 @@ def algorithmic_bytes(wl, precision, nb):
     s = STORAGE_BYTES[precision]
     cb = 8 if precision == "f64" else 4
     rec, nlk = (mcb.REC2, mcb.Q2_LINKS) if wl.dim == 2 else (mcb.REC3, mcb.Q3_LINKS)
-    return wl.N * (2 * wl.Q * s + 4) + nb * (2 * rec + nlk) * cb
+    planes = wl.Q + 1 if precision == "f16s" else wl.Q  # FP16 storage keeps population 0 in FP32
+    return wl.N * (2 * planes * s + 4) + nb * (2 * rec + nlk) * cb
 
 
 def fwd_adjoint(precision):

@@ -93,7 +93,7 @@ __device__ inline void psi_d(const AdjDev& A, double rho, double* psi, double* d
 
 template <class S>
 __device__ inline double ldf(const S* g, const AdjDev& A, int i, int64_t x) {
-    return double(ld<S, float>(reinterpret_cast<const S*>(g), i * A.g.N + x)) + wgt<double>(A.L, i) * A.rho_ref;
+    return double(ldp<S, float>(g, i, A.g.N, x)) + wgt<double>(A.L, i) * A.rho_ref;
 }
 template <>
 __device__ inline double ldf<double>(const double* g, const AdjDev& A, int i, int64_t x) {

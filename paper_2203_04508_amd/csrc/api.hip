@@ -13,6 +13,13 @@
 namespace mcb {
 
 int64_t storage_bytes(int precision) { return precision == MCB_F64 ? 8 : (precision == MCB_F32S ? 4 : 2); }
+int64_t state_bytes(int precision, int Q, int64_t N) {
+    return (precision == MCB_F16S ? Q + 1 : Q) * N * storage_bytes(precision);
+}
+int64_t plane_bytes_off(int precision, int i, int64_t N) {
+    const int64_t s = storage_bytes(precision);
+    return (precision == MCB_F16S && i > 0 ? i + 1 : i) * N * s;
+}
 int64_t compute_bytes(int precision) { return precision == MCB_F64 ? 8 : 4; }
 
 static int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
@@ -25,8 +32,8 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     const int64_t nblk = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
     int64_t o = 0;
     auto take = [&](int64_t bytes) { const int64_t at = o; o = align256(o + bytes); return at; };
-    L.fa = take(Q * N * s);
-    L.fb = take(Q * N * s);
+    L.fa = take(state_bytes(p.precision, Q, N));
+    L.fb = take(state_bytes(p.precision, Q, N));
     L.tag = take(4 * N);
     L.nmask = take(p.dim == 3 ? 4 * N : 0);  // 3-D: link bits of each boundary node (bit j-1: x + e_j solid)
     L.rho3 = take(p.dim == 3 ? cb * N : 0);  // 3-D: density pass output of the step (compute type)
@@ -65,7 +72,7 @@ AdjPlan adj_plan(const mcb_ctx* c, int64_t nsteps, int64_t k) {
     a.nsteps = nsteps;
     a.k = k;
     a.nck = nsteps == 0 ? 1 : (nsteps + k - 1) / k;
-    a.state_b = align256(Q * N * storage_bytes(c->p.precision));
+    a.state_b = align256(state_bytes(c->p.precision, int(Q), N));
     a.nslots = c->L.rec_slots;
     a.rec_b = align256(cb * c->L.rec_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0));
     int64_t o = 0;
@@ -452,10 +459,9 @@ mcb_status mcb_set_f(mcb_ctx* c, const double* f) {
     mcb_status st = clear_flags(c);
     if (st) return st;
     char* tmp = c->lat + c->L.fb;
-    const int64_t s = storage_bytes(c->p.precision);
     for (int i = 0; i < c->g.Q; ++i) {
         HIPCHK(hipMemcpyAsync(stage_buf, f + i * c->g.N, 8 * c->g.N, hipMemcpyHostToDevice, c->stream));
-        HIPCHK(convert_plane_in(c, stage_buf, tmp + i * c->g.N * s, i));
+        HIPCHK(convert_plane_in(c, stage_buf, tmp + plane_bytes_off(c->p.precision, i, c->g.N), i));
         HIPCHK(hipStreamSynchronize(c->stream));
     }
     return collide_from(c, tmp);
@@ -467,9 +473,8 @@ mcb_status mcb_get_f(mcb_ctx* c, double* f) {
     if (!f) return fail(c, MCB_EINVAL, "f missing");
     double* stage_buf = reinterpret_cast<double*>(c->lat + c->L.scratch);
     const char* cur = static_cast<const char*>(fcur(c));
-    const int64_t s = storage_bytes(c->p.precision);
     for (int i = 0; i < c->g.Q; ++i) {
-        HIPCHK(convert_plane_out(c, cur + i * c->g.N * s, stage_buf, i));
+        HIPCHK(convert_plane_out(c, cur + plane_bytes_off(c->p.precision, i, c->g.N), stage_buf, i));
         HIPCHK(hipMemcpyAsync(f + i * c->g.N, stage_buf, 8 * c->g.N, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
     }
@@ -567,7 +572,7 @@ mcb_status mcb_adj_forward(mcb_ctx* c, const double* rho0, int64_t nsteps, int64
     const int64_t rec_used = compute_bytes(c->p.precision) * c->L.rec_stride * (c->n_bnodes > 0 ? c->n_bnodes : 0);
     for (int64_t t = 0;; ++t) {
         if (t % k == 0 && t / k < a.nck) {
-            HIPCHK(hipMemcpyAsync(c->adj + a.ck + (t / k) * a.state_b, fcur(c), c->g.Q * c->g.N * storage_bytes(c->p.precision),
+            HIPCHK(hipMemcpyAsync(c->adj + a.ck + (t / k) * a.state_b, fcur(c), state_bytes(c->p.precision, c->g.Q, c->g.N),
                                   hipMemcpyDeviceToDevice, c->stream));
             if (rec_used > 0)
                 HIPCHK(hipMemcpyAsync(c->adj + a.ck_rec + (t / k) * a.rec_b, rcur(c), rec_used, hipMemcpyDeviceToDevice, c->stream));

@@ -3,6 +3,8 @@
 
 #include "mcb_internal.h"
 
+#include <type_traits>
+
 namespace mcb {
 
 // ---------------------------------------------------------------- storage conversions
@@ -28,6 +30,39 @@ template <>
 __device__ inline void st<__half, float>(__half* __restrict__ p, int64_t i, float v) { p[i] = __float2half_rn(v); }
 template <class S, class C>
 __device__ inline void st(S* __restrict__ p, uint32_t i, C v) { st<S, C>(p, int64_t(i), v); }
+
+// ---------------------------------------------------------------- mass balance of the collision
+// The collision gives a node back exactly the mass it pulled: f_0 = (sum of the pulled populations)
+// - (the other outputs as stored).  With FP32 storage both sums are formed in FP64 (nine FP32
+// values do not add exactly in FP32, and that rounding would stay in the node's mass); FP16 values
+// add exactly in FP32, FP64 in FP64.
+template <class S, class C>
+using MassAcc = typename std::conditional<std::is_same<S, float>::value, double, C>::type;
+
+// ---------------------------------------------------------------- population planes
+// Populations are stored as Q planes of N values (SoA).  With FP16 storage the rest population
+// (plane 0) is kept in FP32, in the space of the first two half planes: it holds about 4/9 of the
+// mass and takes the rounding of the mass-conserving collision, which in FP16 would bias the mass;
+// plane i >= 1 then starts at half plane i + 1.
+template <class S>
+constexpr bool kMixed = sizeof(S) == 2;
+template <class S>
+__host__ __device__ inline int64_t plane_off(int i, int64_t N) {  // in elements of S
+    return (kMixed<S> && i > 0) ? int64_t(i + 1) * N : int64_t(i) * N;
+}
+template <class S, class C>
+__device__ inline C ldp(const S* __restrict__ f, int i, int64_t N, int64_t x) {
+    if (kMixed<S> && i == 0) return C(reinterpret_cast<const float*>(f)[x]);
+    return ld<S, C>(f, plane_off<S>(i, N) + x);
+}
+template <class S, class C>
+__device__ inline void stp(S* __restrict__ f, int i, int64_t N, int64_t x, C v) {
+    if (kMixed<S> && i == 0) {
+        reinterpret_cast<float*>(f)[x] = float(v);
+        return;
+    }
+    st<S, C>(f, plane_off<S>(i, N) + x, v);
+}
 
 // ---------------------------------------------------------------- bounds-checked buffer access
 // Raw buffer instructions address from a scalar 128-bit resource plus a 32-bit per-lane byte

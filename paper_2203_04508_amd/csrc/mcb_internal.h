@@ -85,6 +85,10 @@ struct AdjWork {
     double *p, *pbar, *rho, *psi, *dpsi, *rave, *den, *rbar, *qbar, *Fbar, *Fv, *dphi, *part, *sums;
 };
 int64_t storage_bytes(int precision);
+// bytes of one population state (Q planes; FP16 storage keeps plane 0 in FP32) and the byte offset
+// of plane i in it
+int64_t state_bytes(int precision, int Q, int64_t N);
+int64_t plane_bytes_off(int precision, int i, int64_t N);
 int64_t compute_bytes(int precision);
 
 }  // namespace mcb

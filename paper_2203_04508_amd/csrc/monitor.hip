@@ -24,7 +24,7 @@ __global__ void k_init_feq(GridDev g, int L, const int32_t* __restrict__ tag, co
                            const double* __restrict__ u, C rho_ref, S* __restrict__ f) {
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
         if (tag[x] < 0) {
-            for (int i = 0; i < g.Q; ++i) st<S, C>(f, i * g.N + x, C(0));
+            for (int i = 0; i < g.Q; ++i) stp<S, C>(f, i, g.N, x, C(0));
             continue;
         }
         const C r = C(rho[x]);
@@ -36,7 +36,7 @@ __global__ void k_init_feq(GridDev g, int L, const int32_t* __restrict__ tag, co
             const C eu = C(c_ex[L][i]) * uv[0] + C(c_ey[L][i]) * uv[1] + C(c_ez[L][i]) * uv[2];
             const C w = wgt<C>(L, i);
             const C geq = w * (r - rho_ref) + w * r * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu);
-            st<S, C>(f, i * g.N + x, geq);
+            stp<S, C>(f, i, g.N, x, geq);
         }
     }
 }
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_mon_partial(GridDev g, int L, const S* 
         if (tag[x] < 0) continue;
         double m = 0, jx = 0, jy = 0, jz = 0;
         for (int i = 0; i < g.Q; ++i) {
-            const double v = double(ld<S, C>(f, i * g.N + x));
+            const double v = double(ldp<S, C>(f, i, g.N, x));
             m += v;
             jx += v * c_ex[L][i];
             jy += v * c_ey[L][i];
@@ -110,7 +110,7 @@ __global__ void k_rho_out(GridDev g, const S* __restrict__ f, const int32_t* __r
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
         if (tag[x] < 0) { rho[x] = 0.0; continue; }
         double s = 0;
-        for (int i = 0; i < g.Q; ++i) s += double(ld<S, C>(f, i * g.N + x));
+        for (int i = 0; i < g.Q; ++i) s += double(ldp<S, C>(f, i, g.N, x));
         rho[x] = s + rho_ref;
     }
 }
@@ -143,7 +143,7 @@ __global__ void k_vel_out(GridDev g, int L, const S* __restrict__ f, const int32
         }
         double j[3] = {0, 0, 0}, s[3] = {0, 0, 0};
         for (int i = 1; i < g.Q; ++i) {
-            const double fi = double(ld<S, C>(f, i * g.N + x));
+            const double fi = double(ldp<S, C>(f, i, g.N, x));
             const double ws = (L == 0) ? (i < 5 ? 1.0 / 3.0 : 1.0 / 12.0) : (i < 7 ? 1.0 / 6.0 : 1.0 / 12.0);
             const double py = psi[nb_index(g, L, x, i, +1)];
             const int e[3] = {c_ex[L][i], c_ey[L][i], c_ez[L][i]};
@@ -269,8 +269,13 @@ hipError_t convert_plane_in(mcb_ctx* c, const double* src, void* dst_plane, int 
                                static_cast<float*>(dst_plane), float(shift));
             break;
         default:
-            hipLaunchKernelGGL((k_plane_in<__half, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N, src,
-                               static_cast<__half*>(dst_plane), float(shift));
+            // FP16 storage keeps the rest population in FP32
+            if (dir == 0)
+                hipLaunchKernelGGL((k_plane_in<float, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N, src,
+                                   static_cast<float*>(dst_plane), float(shift));
+            else
+                hipLaunchKernelGGL((k_plane_in<__half, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N, src,
+                                   static_cast<__half*>(dst_plane), float(shift));
     }
     return hipGetLastError();
 }
@@ -288,8 +293,12 @@ hipError_t convert_plane_out(mcb_ctx* c, const void* src_plane, double* dst, int
                                static_cast<const float*>(src_plane), tag, dst, shift);
             break;
         default:
-            hipLaunchKernelGGL((k_plane_out<__half, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N,
-                               static_cast<const __half*>(src_plane), tag, dst, shift);
+            if (dir == 0)
+                hipLaunchKernelGGL((k_plane_out<float, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N,
+                                   static_cast<const float*>(src_plane), tag, dst, shift);
+            else
+                hipLaunchKernelGGL((k_plane_out<__half, float>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g.N,
+                                   static_cast<const __half*>(src_plane), tag, dst, shift);
     }
     return hipGetLastError();
 }

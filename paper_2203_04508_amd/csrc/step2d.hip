@@ -79,6 +79,7 @@ struct March {
     int (*s_tag)[W];
     int t, p, nx, ny, y0, iters;   // lane, its column's position in the LDS rows
     uint32_t n, ns, xcol_b[3];   // nodes, bytes per population array, columns x-1, x, x+1
+    uint32_t xcol0;              // FP16 storage: byte offset of column x in the FP32 rest-population plane
     uint32_t tag_b;              // byte offset of the column in the tag array (OOB for idle lanes)
     bool out_col;
     // pipeline registers: tags of rows r-2, r-1, r; row r+1 and the tag of r+2 in flight
@@ -104,8 +105,13 @@ __device__ __forceinline__ void pull_row(const March<S, C, W>& M, int r, bool on
     const uint32_t rowof[3] = {rp, r0, rm};  // upstream row of e_y = -1, 0, +1
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
+        if (kMixed<S> && i == 0) {
+            // FP16 storage: the rest population (own node) in FP32 at twice the half offsets
+            f[0] = Buf<float>::ld(M.fa, on ? M.xcol0 : OOB, r0 * 2u);
+            continue;
+        }
         const uint32_t vo = on ? (PULL ? M.xcol_b[1 - kEx[i]] : M.xcol_b[1]) : OOB;
-        const uint32_t so = uint32_t(i) * M.ns + (PULL ? rowof[kEy[i] + 1] : r0);
+        const uint32_t so = uint32_t(i + (kMixed<S> ? 1 : 0)) * M.ns + (PULL ? rowof[kEy[i] + 1] : r0);
         f[i] = Buf<S>::ld(M.fa, vo, so);
     }
 }
@@ -246,9 +252,10 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     {
         // the node's density at t+1 from the pulled values; the collision hands all of it back,
         // with f_0 taking the rounding
-        C rs_pull = C(0);
+        MassAcc<S, C> rs_acc = 0;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) rs_pull += fA[i];
+        for (int i = 0; i < 9; ++i) rs_acc += MassAcc<S, C>(fA[i]);
+        const C rs_pull = C(rs_acc);
         const int sl = (k - 3) & 3, sm = (k - 2) & 3, sh = (k - 1) & 3;
         const int tc = t < 1 ? 1 : (t > OUT + 2 ? OUT + 2 : t);
         const C p0 = M.s_psi[sm][tc];
@@ -294,20 +301,25 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         // collision conserves mass (the equilibrium and the forcing term of eq. 13 have zero net
         // mass): set f_0 to the density minus the other eight outputs as stored, so the rounding of
         // the lattice weights and of the storage format cannot bias the total mass
-        C rest = C(0);
+        MassAcc<S, C> rest = 0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             out[i] = Buf<S>::round(out[i]);
-            rest += out[i];
+            rest += MassAcc<S, C>(out[i]);
         }
-        out[0] = rs_pull - rest;
+        out[0] = C(rs_acc - rest);
     }
     // Every output column stores, solid nodes included (zeros: the pull replaces what it takes
     // from them), so rows are written without holes and every cache line whole.  A lane that does
     // not store starts from OOB; the saturating add keeps it out of bounds.
     const uint32_t xst = (k >= 4 && M.out_col) ? xAb : OOB;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), coll ? out[i] : C(0));
+    for (int i = 0; i < 9; ++i) {
+        if (kMixed<S> && i == 0)
+            Buf<float>::st(M.fb, xst == OOB ? OOB : xst * 2u, coll ? out[0] : C(0));
+        else
+            Buf<S>::st(M.fb, sat_add(xst, uint32_t(i + (kMixed<S> ? 1 : 0)) * M.ns), coll ? out[i] : C(0));
+    }
     // boundary record of time t+1: the forcing terms, the populations as stored, the eq. 18
     // correction
     {
@@ -320,7 +332,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         rv[5] = duu15;
 #pragma unroll
         for (int i = 1; i < 9; ++i) rv[RF2 + i - 1] = out[i];  // rounded to the storage format above
-        rv[RF2 + 8] = Buf<S>::round(out[0]);
+        rv[RF2 + 8] = kMixed<S> ? out[0] : Buf<S>::round(out[0]);
         rv[RF2 + 9] = M.dsA;
         if (__any(coll && tgA > 0)) st_vec(M.rout, (coll && tgA > 0) ? uint32_t(tgA >> 8) * (REC2 * sc) : OOB, rv);
     }
@@ -366,8 +378,9 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     M.s_rho = s_rho;
     M.s_psi = s_psi;
     M.s_tag = s_tag;
-    M.fa = make_res(a.fa, uint64_t(9) * M.n * s);
-    M.fb = make_res(a.fb, uint64_t(9) * M.n * s);
+    M.fa = make_res(a.fa, uint64_t(kMixed<S> ? 10 : 9) * M.n * s);
+    M.fb = make_res(a.fb, uint64_t(kMixed<S> ? 10 : 9) * M.n * s);
+    M.xcol0 = live ? uint32_t(cx) * 4u : OOB;
     M.tag = make_res(a.tag, uint64_t(M.n) * 4);
     M.rin = make_res(a.rin, uint64_t(a.n_bnodes) * REC2 * sizeof(C));
     M.rout = make_res(a.rout, uint64_t(a.n_bnodes) * REC2 * sizeof(C));

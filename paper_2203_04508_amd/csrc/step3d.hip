@@ -35,7 +35,7 @@ namespace {
 constexpr int TX = 32, TY = 8, NT = TX * TY;           // lanes (and output columns) of a tile
 constexpr int RX = TX + 4, RY = TY + 4, NR = RX * RY;  // density region: two columns out
 constexpr int PX = TX + 2, PY = TY + 2, NP = PX * PY;  // psi region: one column out
-static_assert(NR <= 2 * NT && NP <= 2 * NT, "two region entries per lane");
+constexpr int NRL = (NR + NT - 1) / NT, NPL = (NP + NT - 1) / NT;  // region entries per lane
 
 // D3Q19: rest, the six axis vectors, the twelve edge vectors; opposite pairs side by side
 __device__ constexpr int kEx3[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_rho3d(RhoArgs<S, C> a) {
     const int x = bx * 256 + int(threadIdx.x);
     const bool on = x < a.nx;
     const uint32_t nxy = uint32_t(a.nx) * uint32_t(a.ny), N = nxy * uint32_t(a.nz);
-    const __amdgpu_buffer_rsrc_t fa = make_res(a.fa, uint64_t(19) * N * s);
+    const __amdgpu_buffer_rsrc_t fa = make_res(a.fa, uint64_t(kMixed<S> ? 20 : 19) * N * s);
     const __amdgpu_buffer_rsrc_t tagr = make_res(a.tag, uint64_t(N) * 4);
     const uint32_t node = uint32_t(z) * nxy + uint32_t(y) * a.nx + uint32_t(x);
     const int tg = ld_i32(tagr, on ? node * 4u : OOB);
@@ -94,11 +94,13 @@ __global__ __launch_bounds__(256) void k_rho3d(RhoArgs<S, C> a) {
     const int zm = zdec(z, a.nz), zp = zinc(z, a.nz);
     const int xs[3] = {xp, x, xm}, ys[3] = {yp, y, ym}, zs[3] = {zp, z, zm};  // upstream of e = -1, 0, +1
     C rs = C(0);
+    // FP16 storage: the rest population (own node) in FP32, the others from half plane i + 1 on
+    if (kMixed<S>) rs += Buf<float>::ld(fa, on ? node * 4u : OOB);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
+    for (int i = kMixed<S> ? 1 : 0; i < 19; ++i) {
         const uint32_t src =
             PULL ? uint32_t(zs[kEz3[i] + 1]) * nxy + uint32_t(ys[kEy3[i] + 1]) * uint32_t(a.nx) + uint32_t(xs[kEx3[i] + 1]) : node;
-        rs += Buf<S>::ld(fa, on ? (uint32_t(i) * N + src) * s : OOB);
+        rs += Buf<S>::ld(fa, on ? (uint32_t(i + (kMixed<S> ? 1 : 0)) * N + src) * s : OOB);
     }
     if (PULL && on && tg > 0) {
         // boundary node: its own f~_j(x, t) on each link (the slot pulled from the solid node holds 0)
@@ -204,8 +206,9 @@ struct March3 {
     uint32_t p4, pc;    // bytes per z-plane of a 4-byte and of a compute-type node array
     uint32_t own4;      // byte offset of this lane's column in a 4-byte node array plane (OOB: none)
     uint32_t vxy[9];    // byte offsets of the columns (x + dx, y + dy), index 3 (dy + 1) + dx + 1
-    uint32_t ro[2];     // byte offsets of this lane's density-region columns (OOB: none)
-    int pj[2];          // LDS index (density region) of this lane's psi-region columns (-1: none)
+    uint32_t xcol0;     // FP16 storage: byte offset of the column in the FP32 rest-population plane
+    uint32_t ro[NRL];   // byte offsets of this lane's density-region columns (OOB: none)
+    int pj[NPL];        // LDS index (density region) of this lane's psi-region columns (-1: none)
     bool out_col;
 };
 
@@ -219,8 +222,13 @@ __device__ __forceinline__ void pull_plane(const March3<S, C>& M, int z, bool on
     const uint32_t zof[3] = {zpb, z0b, zmb};  // upstream plane for e_z = -1, 0, +1
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
+        if (kMixed<S> && i == 0) {
+            // FP16 storage: the rest population (own node) in FP32 at twice the half offsets
+            f[0] = Buf<float>::ld(M.fa, on ? M.xcol0 : OOB, z0b * 2u);
+            continue;
+        }
         const uint32_t vo = on ? (PULL ? M.vxy[(1 - kEy3[i]) * 3 + (1 - kEx3[i])] : M.vxy[4]) : OOB;
-        const uint32_t so = uint32_t(i) * M.ns + (PULL ? zof[kEz3[i] + 1] : z0b);
+        const uint32_t so = uint32_t(i + (kMixed<S> ? 1 : 0)) * M.ns + (PULL ? zof[kEz3[i] + 1] : z0b);
         f[i] = Buf<S>::ld(M.fa, vo, so);
     }
 }
@@ -270,16 +278,21 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
             M.vxy[(dy + 1) * 3 + dx + 1] =
                 M.out_col ? (uint32_t(wrap1(cy + dy, a.ny)) * a.nx + wrap1(cx + dx, a.nx)) * s : OOB;
     // density region (RX x RY columns from (x0 - 2, y0 - 2)) and psi region (PX x PY columns from
-    // (x0 - 1, y0 - 1)): up to two entries per lane, periodic
+    // (x0 - 1, y0 - 1)): NRL and NPL entries per lane, periodic
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NRL; ++h) {
         const int r = t + h * NT;
         M.ro[h] = r < NR ? (uint32_t(wrapn(y0 - 2 + r / RX, a.ny)) * a.nx + wrapn(x0 - 2 + r % RX, a.nx)) * sc : OOB;
+    }
+#pragma unroll
+    for (int h = 0; h < NPL; ++h) {
+        const int r = t + h * NT;
         M.pj[h] = r < NP ? (r / PX + 1) * RX + (r % PX + 1) : -1;
     }
     const int iters = Dv + 4;
-    M.fa = make_res(a.fa, uint64_t(19) * M.ns);
-    M.fb = make_res(a.fb, uint64_t(19) * M.ns);
+    M.fa = make_res(a.fa, uint64_t(kMixed<S> ? 20 : 19) * M.ns);
+    M.fb = make_res(a.fb, uint64_t(kMixed<S> ? 20 : 19) * M.ns);
+    M.xcol0 = M.out_col ? (uint32_t(cy) * a.nx + cx) * 4u : OOB;
     M.tag = make_res(a.tag, uint64_t(nxy) * a.nz * 4);
     M.nmask = make_res(a.nmask, uint64_t(nxy) * a.nz * 4);
     M.rho = make_res(a.rho, uint64_t(nxy) * a.nz * sc);
@@ -291,9 +304,9 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
     // Iteration k: density of plane q = z0 - 2 + k into the LDS ring, psi of plane q - 1, collision
     // of plane p = q - 2.  Ring slots follow k modulo 3: plane q in slot k % 3.
     int zq = wrapn(z0 - 2, a.nz);            // plane q of the current iteration
-    C rr[2];                                 // density region of plane q (in flight)
+    C rr[NRL];                               // density region of plane q (in flight)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) rr[h] = Buf<C>::ld(M.rho, M.ro[h], uint32_t(zq) * M.pc);
+    for (int h = 0; h < NRL; ++h) rr[h] = Buf<C>::ld(M.rho, M.ro[h], uint32_t(zq) * M.pc);
     C fC[19], fN[19];                        // populations of planes p (arrived) and p + 1 (in flight)
 #pragma unroll
     for (int i = 0; i < 19; ++i) fC[i] = fN[i] = C(0);
@@ -310,10 +323,10 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
         // ---- density of plane q to LDS; issue the density region of plane q + 1, the populations
         // of plane p + 1 = q - 1 and the tag of plane p + 2 = q
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < NRL; ++h)
             if (M.ro[h] != OOB) s_rho[s0][t + h * NT] = rr[h];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) rr[h] = Buf<C>::ld(M.rho, k + 1 < iters ? M.ro[h] : OOB, uint32_t(zq1) * M.pc);
+        for (int h = 0; h < NRL; ++h) rr[h] = Buf<C>::ld(M.rho, k + 1 < iters ? M.ro[h] : OOB, uint32_t(zq1) * M.pc);
         pull_plane<S, C, PULL>(M, zqm, k >= 3 && k < Dv + 3, fN);
         const int tgNN = ld_i32(M.tag, k >= 2 && k < Dv + 2 ? M.own4 : OOB, uint32_t(zq) * M.p4);
         __syncthreads();
@@ -321,7 +334,7 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
         // solid nodes 0)
         if (k >= 2) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < NPL; ++h) {
                 const int c = M.pj[h];
                 if (c >= 0) {
                     const C rc = s_rho[s1][c];
@@ -359,9 +372,10 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
             if (__any(coll)) {
                 // the node's density at t+1 from its pulled values; the collision hands all of it
                 // back, with f_0 taking the rounding
-                C rs = C(0);
+                MassAcc<S, C> rs_acc = 0;
 #pragma unroll
-                for (int i = 0; i < 19; ++i) rs += fC[i];
+                for (int i = 0; i < 19; ++i) rs_acc += MassAcc<S, C>(fC[i]);
+                const C rs = C(rs_acc);
                 const int pc = (ly + 1) * PX + (lx + 1);
                 auto P = [&](int dx, int dy, int dz) {
                     const int sp = dz < 0 ? s0 : (dz > 0 ? s1 : s2);  // planes p - 1, p + 1, p
@@ -416,19 +430,24 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
                 pair(15, 16, we, uy + uz, duy + duz, sy2 + sz2);
                 pair(17, 18, we, uy - uz, duy - duz, sy2 - sz2);
                 // the collision conserves mass: f_0 is the density minus the other outputs as stored
-                C rest = C(0);
+                MassAcc<S, C> rest = 0;
 #pragma unroll
                 for (int i = 1; i < 19; ++i) {
                     out[i] = Buf<S>::round(out[i]);
-                    rest += out[i];
+                    rest += MassAcc<S, C>(out[i]);
                 }
-                out[0] = rs - rest;
+                out[0] = C(rs_acc - rest);
             }
             // Every output column stores, solid nodes included (zeros: the density pass and the
             // links read 0 from them), so rows are written whole.
             const uint32_t xst = M.out_col ? uint32_t(zdec(zqm, a.nz)) * M.pb + M.vxy[4] : OOB;
 #pragma unroll
-            for (int i = 0; i < 19; ++i) Buf<S>::st(M.fb, sat_add(xst, uint32_t(i) * M.ns), coll ? out[i] : C(0));
+            for (int i = 0; i < 19; ++i) {
+                if (kMixed<S> && i == 0)
+                    Buf<float>::st(M.fb, xst == OOB ? OOB : xst * 2u, coll ? out[0] : C(0));
+                else
+                    Buf<S>::st(M.fb, sat_add(xst, uint32_t(i + (kMixed<S> ? 1 : 0)) * M.ns), coll ? out[i] : C(0));
+            }
             // boundary record of time t+1: the forcing terms, the populations as stored, the eq. 18
             // correction
             if (__any(coll && tgC > 0)) {

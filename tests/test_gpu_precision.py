@@ -94,7 +94,9 @@ def test_fp32_mass_drift_c1_10k_steps(mcb):
     assert abs(d) <= 1e-6, d
 
 
-def test_fp16_mass_drift_is_bounded(mcb):
-    banner("shifted FP16 mass drift, 1024^2, 1000 steps (reported, not a target)")
-    d = _drift(mcb, "c1", "f16s", 1000)
-    assert np.isfinite(d) and abs(d) < 1e-3, d
+def test_fp16_mass_drift_c1_10k_steps(mcb):
+    # FP16 storage keeps the rest population in FP32, which takes the rounding of the collision's
+    # mass balance, so the FP32 bound holds as well
+    banner("shifted FP16 mass drift, 1024^2, 10^4 steps")
+    d = _drift(mcb, "c1", "f16s", 10000)
+    assert abs(d) <= 1e-6, d
