@@ -19,6 +19,9 @@
 //   wall density       eq. 15 restricted to the first solid layer, times a wettability factor phi
 //   curved boundary    eq. 16 (0 <= q < 1/2), eq. 17 (1/2 <= q <= 1)       (Sec. 3.1)
 //   mass modification  eq. 18                                              (Sec. 3.2)
+//   comparison schemes the paper measures the present one against (Secs. 1, 4): linear
+//                      interpolation bounce-back (eqs. 16-17 without the forcing term, no eq. 18),
+//                      the same with eq. 18, and halfway bounce-back; all four coincide at q = 1/2
 //
 // Geometry is exact integer arithmetic in units of 2^-16 lattice spacings: node classification,
 // the fluid-solid link list and each link's q = q_fixed / 2^16 (first point of the link segment
@@ -320,6 +323,7 @@ struct Sim {
     std::vector<R> fn, psi;
     R dm_last = R(0.0);
     int64_t n_domain = 0;
+    int bc_mode = 0;  // 0 present scheme, 1 IBC, 2 MIBC, 3 halfway bounce-back
 
     explicit Sim(const or_params& p) : P(p), L(make_lat(p.dim)), g(p) {}
 
@@ -416,11 +420,22 @@ struct Sim {
                 double q = double(lk_q[l]) / double(ONE);
                 int64_t x2 = g.shift(x, L.e[j], -1);
                 R ft_j_x2 = fluid(x2) ? ft[j * N + x2] : R(0.0);
-                fn[i * N + x] = curved_bc(q, fluid(x2), ft[j * N + x], ft_j_x2, ft[i * N + x], force_term(x, j));
+                if (bc_mode == 3) {
+                    // halfway bounce-back: the wall sits midway whatever q is
+                    fn[i * N + x] = ft[j * N + x];
+                } else {
+                    // IBC and MIBC interpolate without the nonideal-force term
+                    const R Fj = bc_mode == 0 ? force_term(x, j) : R(0.0);
+                    fn[i * N + x] = curved_bc(q, fluid(x2), ft[j * N + x], ft_j_x2, ft[i * N + x], Fj);
+                }
             }
         }
-        // eq. 18: every boundary-fluid node keeps the outflow-inflow difference of its links in f_0
         R total = 0.0;
+        if (bc_mode == 1) {  // plain IBC: no mass modification
+            dm_last = total;
+            return;
+        }
+        // eq. 18: every boundary-fluid node keeps the outflow-inflow difference of its links in f_0
         for (int64_t x = 0; x < N; ++x) {
             if (!fluid(x) || link0[x] == link0[x + 1]) continue;
             R dm = 0.0;
@@ -700,6 +715,13 @@ void* or_sim_create(const or_params* P, const uint8_t* solid, const int64_t* lk_
 }
 
 void or_sim_destroy(void* h) { delete static_cast<Sim<double>*>(h); }
+
+// boundary scheme of later steps: 0 present (eqs. 16-18), 1 IBC, 2 MIBC, 3 halfway bounce-back
+int or_sim_set_bc_mode(void* h, int mode) {
+    if (mode < 0 || mode > 3) return -1;
+    static_cast<Sim<double>*>(h)->bc_mode = mode;
+    return 0;
+}
 
 int64_t or_sim_n_wall(void* h) { return int64_t(static_cast<Sim<double>*>(h)->wall_nodes.size()); }
 

@@ -80,6 +80,8 @@ def lib():
         L.or_sim_create.argtypes = [P, vp, vp, vp, vp, C.c_int64]
         L.or_sim_create.restype = vp
         L.or_sim_destroy.argtypes = [vp]
+        L.or_sim_set_bc_mode.argtypes = [vp, C.c_int]
+        L.or_sim_set_bc_mode.restype = C.c_int
         L.or_sim_n_wall.argtypes = [vp]
         L.or_sim_n_wall.restype = C.c_int64
         L.or_sim_set_phi.argtypes = [vp, vp]
@@ -207,6 +209,10 @@ def wall_nodes(params: Params, solid: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------- simulation
+# boundary schemes (Secs. 1, 3 and 4): the present one and the three the paper compares it with
+BC_PRESENT, BC_IBC, BC_MIBC, BC_HBBC = 0, 1, 2, 3
+
+
 class OracleError(RuntimeError):
     pass
 
@@ -247,6 +253,11 @@ class Sim:
             raise OracleError(f"{what}: non-finite population")
         if rc != 0:
             raise OracleError(f"{what}: error {rc}")
+
+    def set_bc_mode(self, mode: int):
+        """0 present scheme (eqs. 16-18), 1 IBC (eqs. 16-17 without the forcing term, no eq. 18),
+        2 MIBC (IBC with eq. 18), 3 halfway bounce-back."""
+        self._check(lib().or_sim_set_bc_mode(self.h, int(mode)), "set_bc_mode")
 
     def set_phi(self, phi):
         phi = np.ascontiguousarray(np.broadcast_to(np.asarray(phi, np.float64), (self.n_wall,)))
