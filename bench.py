@@ -4,7 +4,7 @@ A step is one pass of the whole hot path over the lattice: the fused kernel that
 populations, applies the curved-boundary links (eqs. 16-18), computes the pseudopotential force and
 collides. Inputs are resident in HBM before the timed region starts. Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--no-cpu] [--no-adjoint]
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--bc-mode present] [--no-cpu] [--no-adjoint]
 
 Default: the 4096^2 D2Q9 workload (4800 circles, 640 drops) with shifted-FP32 storage, its 5000
 steps, as the throughput and HBM-roofline figures are quoted on it; the oracle is timed on a
@@ -34,10 +34,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def setup_gpu(wl, precision, rho_ref):
+def setup_gpu(wl, precision, rho_ref, bc_mode="present"):
     from paper_2203_04508_amd import mcb
 
-    lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision, rho_ref=rho_ref)
+    lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision, rho_ref=rho_ref, bc_mode=bc_mode)
     nl, nb, nw = lat.set_geometry(wl.shapes)
     from paper_2203_04508_amd import workloads as W
 
@@ -154,6 +154,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="f32s", choices=list(DTYPES))
+    ap.add_argument("--bc-mode", default="present", choices=["present", "ibc", "mibc", "hbbc"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -170,7 +171,7 @@ def main():
     steps = args.steps if args.steps is not None else wl.steps
     rho_ref = wl.rho_v if args.precision != "f64" else 0.0
     log(f"[bench] workload {wl.name} dims {wl.dims[:wl.dim]} precision {args.precision}: set-up")
-    lat, (nl, nb, nw) = setup_gpu(wl, args.precision, rho_ref)
+    lat, (nl, nb, nw) = setup_gpu(wl, args.precision, rho_ref, args.bc_mode)
     M0 = lat.mass().M
     log(f"[bench] links {nl} boundary nodes {nb} wall nodes {nw}; warmup {args.warmup}")
     lat.step(args.warmup)
@@ -218,6 +219,7 @@ def main():
         "config": {
             "workload": f"{wl.name}: D2Q9 {wl.dims[0]}x{wl.dims[1]}" if wl.dim == 2 else f"{wl.name}: D3Q19 {wl.dims[0]}^3",
             "storage": args.precision,
+            "bc_mode": args.bc_mode,
             "rho_ref": rho_ref,
             "links": nl, "boundary_nodes": nb, "wall_nodes": nw,
             "T_over_Tc": wl.T_over_Tc, "tau": wl.tau,

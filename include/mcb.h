@@ -62,9 +62,14 @@ enum {
     MCB_F16S = 2   /* shifted FP16 storage, FP32 arithmetic */
 };
 
-/* boundary scheme on fluid-solid links */
+/* boundary scheme on fluid-solid links: the paper's (Sec. 3) and the three it is compared with
+ * (Secs. 1 and 4).  All four coincide at q = 1/2. */
 enum {
-    MCB_BC_PRESENT = 0  /* eqs. 16-18 of the paper */
+    MCB_BC_PRESENT = 0, /* eqs. 16-18: interpolation with the forcing term, plus mass modification */
+    MCB_BC_IBC = 1,     /* eqs. 16-17 without the forcing term, no eq. 18 (2-D only: MCB_ENOTSUP
+                           from mcb_create for dim 3, whose density pass relies on eq. 18) */
+    MCB_BC_MIBC = 2,    /* eqs. 16-17 without the forcing term, with eq. 18 */
+    MCB_BC_HBBC = 3     /* halfway bounce-back on every link (q ignored; eq. 18 terms are zero) */
 };
 
 /* build_links phases */
@@ -85,7 +90,7 @@ typedef struct {
     double G;               /* interaction strength of the pseudopotential force, < 0 */
     double eos_a, eos_b, eos_R, eos_T;  /* Carnahan-Starling EOS parameters and temperature */
     int32_t precision;      /* MCB_F64, MCB_F32S, MCB_F16S */
-    int32_t bc_mode;        /* MCB_BC_PRESENT */
+    int32_t bc_mode;        /* MCB_BC_PRESENT, MCB_BC_IBC, MCB_BC_MIBC, MCB_BC_HBBC */
     double rho_ref;         /* shift of the stored populations (ignored for MCB_F64) */
 } mcb_params;
 
@@ -129,7 +134,8 @@ typedef struct {
 } mcb_mass_report;
 
 /* ---- context ---------------------------------------------------------------------------- */
-/* Validates params (MCB_EINVAL otherwise) and creates a context; no device work. */
+/* Validates params (MCB_EINVAL otherwise; MCB_ENOTSUP for MCB_BC_IBC in 3-D) and creates a
+ * context; no device work. */
 mcb_status mcb_create(const mcb_params* params, mcb_ctx** out);
 void mcb_destroy(mcb_ctx* ctx);
 const char* mcb_last_error(const mcb_ctx* ctx);
@@ -223,7 +229,8 @@ mcb_status mcb_timing_report(mcb_ctx* ctx, double* ms, int64_t* launches);
 enum { MCB_LOSS_COM_X = 0, MCB_LOSS_WETTED_LENGTH = 1, MCB_LOSS_TOTAL_MASS = 2 };
 
 /* Device bytes of the reverse-mode arena for nsteps >= 0 steps with a checkpoint every k >= 1
- * steps (after mcb_build_links(FILL)). */
+ * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_BC_PRESENT only: the adjoint
+ * calls return MCB_ENOTSUP for the other schemes. */
 mcb_status mcb_adj_required_bytes(mcb_ctx* ctx, int64_t nsteps, int64_t k, int64_t* bytes);
 
 /* Binds the caller-owned reverse-mode arena (device memory, at least the required bytes, 256-byte

@@ -322,7 +322,7 @@ __global__ void k_q_band(Bands b, GridDev g, int L, int64_t nb, const int32_t* _
 // directions without a link hold NO_LINK.  Flags links no shape was found for.
 __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict__ solid, const int32_t* __restrict__ bn_node,
                         const uint32_t* __restrict__ bn_mask, const int32_t* __restrict__ bn_link0, uint32_t* lk_qc,
-                        void* rec, int rec_double, int32_t* flags) {
+                        void* rec, int rec_double, int halfway, int32_t* flags) {
     // coefficient a per slot = boundary index * slots per node + direction - 1
     const int64_t QL = g.dim == 2 ? Q2_LINKS : Q3_LINKS;
     for (int64_t bi = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; bi < nb; bi += int64_t(gridDim.x) * blockDim.x) {
@@ -345,6 +345,7 @@ __global__ void k_class(GridDev g, int L, int64_t nb, const uint8_t* __restrict_
                 lk_qc[l] = q | (uint32_t(cls) << CLS_SHIFT);
                 const double q2 = double(q) * (2.0 / 65536.0);
                 a = cls == MCB_CLS_EQ16 ? q2 : (cls == MCB_CLS_EQ17 ? -1.0 / q2 : 1.0);
+                if (halfway) a = 1.0;  // halfway bounce-back on every link, whatever q
                 ++l;
             }
             const int64_t slot = bi * QL + (i - 1);
@@ -467,7 +468,7 @@ hipError_t geom_reclass(mcb_ctx* c) {
                        reinterpret_cast<const uint32_t*>(c->lk + c->L.bn_mask),
                        reinterpret_cast<const int32_t*>(c->lk + c->L.bn_link0),
                        reinterpret_cast<uint32_t*>(c->lk + c->L.lk_qc), static_cast<void*>(c->lk + c->L.lk_a),
-                       c->p.precision == MCB_F64 ? 1 : 0, flags);
+                       c->p.precision == MCB_F64 ? 1 : 0, c->p.bc_mode == MCB_BC_HBBC ? 1 : 0, flags);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // both buffers of boundary records start empty (the first collision writes them)

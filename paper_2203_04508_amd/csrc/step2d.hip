@@ -56,6 +56,7 @@ struct Args2 {
     uint32_t n_bnodes, n_wall;
     int nx, ny, H, nsx, nblocks;
     C tau_inv, G, rho_ref;
+    C kF, k18;                   // boundary scheme: weight of the forcing term, of eq. 18 (0 or 1)
     Eos<C> eos;
 };
 
@@ -127,10 +128,13 @@ __device__ __forceinline__ C edot(int ex, int ey, C x, C y) {
 // Eqs. 16-18 at a boundary node (bnd) from its record of time t (rec) and link coefficients (ca):
 // replaces the populations pulled from solid neighbours by f_in and corrects the rest population;
 // returns the correction.  Lanes that are not boundary nodes keep f and return 0.  Directions in
-// which no lane of the wave has a link are skipped.
+// which no lane of the wave has a link are skipped.  kF and k18 select the scheme: 1 and 1 the
+// present one, 0 and 0 linear interpolation bounce-back (no forcing term, no eq. 18), 0 and 1 the
+// same with eq. 18; halfway bounce-back is a = 1 on every link.
 template <class S, class C>
-__device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[RF2 + 8], const C (&ca)[Q2_LINKS], C (&f)[9]) {
-    const C rho = rec[0], dux = rec[1], duy = rec[2], sx = rec[3], sy = rec[4], duu = rec[5];
+__device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[RF2 + 8], const C (&ca)[Q2_LINKS], C (&f)[9], C kF,
+                                         C k18) {
+    const C rho = rec[0] * kF, dux = rec[1], duy = rec[2], sx = rec[3], sy = rec[4], duu = rec[5];
     const C* fo = rec + RF2 - 1;  // own post-collision populations 1 .. 8
     // each slot opp(j) is replaced at most once, and never one that a later eq. 16 link reads (its
     // x2 = x - e_j is fluid, while a replaced slot was pulled from a solid node)
@@ -153,6 +157,7 @@ __device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[RF2 + 8], cons
             f[kOpp[j]] = lk ? fin : f[kOpp[j]];
         }
     }
+    ds *= k18;
     f[0] += ds;
     return ds;
 }
@@ -201,7 +206,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     // ---- A: links (eqs. 16-18) and density of row r
     {
         M.dsC = C(0);
-        if (PULL && __any(M.tgC > 0)) M.dsC = apply_links<S, C>(M.tgC > 0, recC, aC, fC);
+        if (PULL && __any(M.tgC > 0)) M.dsC = apply_links<S, C>(M.tgC > 0, recC, aC, fC, a.kF, a.k18);
         C sr = C(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) sr += fC[i];
@@ -465,6 +470,8 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
     a.tau_inv = C(1.0 / c->p.tau);
     a.G = C(c->p.G);
     a.rho_ref = c->p.precision == MCB_F64 ? C(0) : C(c->p.rho_ref);
+    a.kF = c->p.bc_mode == MCB_BC_PRESENT ? C(1) : C(0);
+    a.k18 = c->p.bc_mode == MCB_BC_IBC ? C(0) : C(1);
     a.eos.RT = C(c->p.eos_R * c->p.eos_T);
     a.eos.a = C(c->p.eos_a);
     a.eos.b4 = C(c->p.eos_b / 4.0);

@@ -133,6 +133,7 @@ struct Args3 {
     uint32_t n_bnodes;
     int nx, ny, nz, D, ntx, nty, nblocks;
     C tau_inv, G, rho_ref;
+    C kF;                        // boundary scheme: weight of the forcing term (eq. 18 always applies)
     Eos<C> eos;
 };
 
@@ -142,10 +143,11 @@ struct Args3 {
 // population; returns the correction.  Lanes that are not boundary nodes keep f and return 0;
 // directions in which no lane of the wave has a link are skipped.  LOAD: rec and ca are loaded
 // here, from rin at byte offset roff and la at aoff, in two halves, each just before its directions
-// (keeps the FP64 kernel within its registers).
+// (keeps the FP64 kernel within its registers).  kF = 0 drops the forcing term (MIBC); halfway
+// bounce-back is a = 1 on every link.  Eq. 18 always applies: the density pass relies on it.
 template <class S, class C, bool LOAD>
 __device__ __forceinline__ C apply_links3(bool bnd, C (&rec)[RF3 + 18], C (&ca)[18], C (&f)[19], __amdgpu_buffer_rsrc_t rin,
-                                          uint32_t roff, __amdgpu_buffer_rsrc_t la, uint32_t aoff) {
+                                          uint32_t roff, __amdgpu_buffer_rsrc_t la, uint32_t aoff, C kF) {
     constexpr int H1 = RF3 + 8, A1 = 8;  // first half: forcing terms, f~_1..f~_8; directions 1..8
     if (LOAD) {
         C h[H1], g[A1];
@@ -156,7 +158,7 @@ __device__ __forceinline__ C apply_links3(bool bnd, C (&rec)[RF3 + 18], C (&ca)[
 #pragma unroll
         for (int i = 0; i < A1; ++i) ca[i] = g[i];
     }
-    const C rho = rec[0], dux = rec[1], duy = rec[2], duz = rec[3];
+    const C rho = rec[0] * kF, dux = rec[1], duy = rec[2], duz = rec[3];
     const C sx = rec[4], sy = rec[5], sz = rec[6], duu = rec[7];
     // each slot opp(j) is replaced at most once, and never one that a later eq. 16 link reads (its
     // x2 = x - e_j is fluid, while a replaced slot was pulled from a solid node)
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
                 // without the prefetch (FP64) the record and the coefficients are loaded here
                 const uint32_t bi = uint32_t(tgC - 1);
                 dsC = apply_links3<S, C, !PF>(tgC > 0, recC, aC, fC, M.rin, tgC > 0 ? bi * (REC3 * sc) : OOB, M.la,
-                                              tgC > 0 ? bi * (Q3_LINKS * sc) : OOB);
+                                              tgC > 0 ? bi * (Q3_LINKS * sc) : OOB, a.kF);
             }
             C out[19];
             C rho = C(0), dux = C(0), duy = C(0), duz = C(0), sx2 = C(0), sy2 = C(0), sz2 = C(0), duu15 = C(0);
@@ -549,6 +551,7 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, const void* rcur, void* f
     a.tau_inv = C(1.0 / c->p.tau);
     a.G = C(c->p.G);
     a.rho_ref = c->p.precision == MCB_F64 ? C(0) : C(c->p.rho_ref);
+    a.kF = c->p.bc_mode == MCB_BC_PRESENT ? C(1) : C(0);
     a.eos.RT = C(c->p.eos_R * c->p.eos_T);
     a.eos.a = C(c->p.eos_a);
     a.eos.b4 = C(c->p.eos_b / 4.0);

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libmcb.so")
 
 MCB_OK, MCB_EINVAL, MCB_ESIZE, MCB_EHIP, MCB_EDOMAIN, MCB_ENAN, MCB_ESTATE, MCB_ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 MCB_F64, MCB_F32S, MCB_F16S = 0, 1, 2
-MCB_BC_PRESENT = 0
+MCB_BC_PRESENT, MCB_BC_IBC, MCB_BC_MIBC, MCB_BC_HBBC = 0, 1, 2, 3
+BC_MODES = {"present": MCB_BC_PRESENT, "ibc": MCB_BC_IBC, "mibc": MCB_BC_MIBC, "hbbc": MCB_BC_HBBC}
 MCB_COUNT, MCB_FILL = 0, 1
 PRECISIONS = {"f64": MCB_F64, "f32s": MCB_F32S, "f16s": MCB_F16S}
 STATUS_NAMES = {0: "MCB_OK", -1: "MCB_EINVAL", -2: "MCB_ESIZE", -3: "MCB_EHIP", -4: "MCB_EDOMAIN",
@@ -131,7 +132,7 @@ def mcb_create(params: mcb_params):
     h = C.c_void_p()
     code = load().mcb_create(C.byref(params), C.byref(h))
     if code != MCB_OK:
-        raise MCBError(code, "mcb_create", "invalid parameters")
+        raise MCBError(code, "mcb_create", "unsupported combination" if code == -7 else "invalid parameters")
     return h
 
 
@@ -278,7 +279,7 @@ class Lattice:
     """A context plus the torch tensors backing its device arenas."""
 
     def __init__(self, dim, dims, tau, T, precision="f64", rho_ref=0.0, G=-1.0, a=1.0, b=4.0, R=1.0,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, bc_mode="present"):
         import torch
 
         self.torch = torch
@@ -286,7 +287,7 @@ class Lattice:
         nz = dims[2] if dim == 3 else 1
         self.params = mcb_params(dim, dims[0], dims[1], nz, tau, G, a, b, R, T,
                                  PRECISIONS[precision] if isinstance(precision, str) else precision,
-                                 MCB_BC_PRESENT, rho_ref)
+                                 BC_MODES[bc_mode] if isinstance(bc_mode, str) else bc_mode, rho_ref)
         self.dim = dim
         self.Q = 9 if dim == 2 else 19
         self.N = int(dims[0]) * int(dims[1]) * int(nz)

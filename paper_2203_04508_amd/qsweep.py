@@ -1,0 +1,243 @@
+"""Sessile drop on a flat wetting substrate, swept over the wall distance q, for the present boundary
+scheme and the three the paper compares it with (IBC, MIBC, halfway bounce-back); the setting of
+Secs. 4.1, 4.3 and 4.4 (Figs. 3, 7 and 9) with this library's pseudopotential model.
+
+Geometry: a periodic 500 x 300 box (FP64 storage); the substrate is the band of solid rows below
+y_w = y1 - q, with y1 = 11 the first fluid row, so every link from row y1 into the wall has the same
+q (axis and diagonal links alike).  The band's underside, at the top of the periodic box, sits at
+q = 1/2, where all four schemes coincide.  A drop of radius 50 is centred on the wall line.
+
+Wettability: the factor phi of the eq. 15 wall density is calibrated at q = 1/2 (where the schemes
+agree) to the two contact angles of the paper, 60 and 120 degrees, by bisection on the equilibrium
+angle.  The angle comes from a circle fitted to the drop's interface (rho = (rho_l + rho_v) / 2,
+interpolated along rows, rows at least 4 above the wall), cos(theta) = (y_w - y_c) / R.
+
+Reported per angle, scheme and q: M/M0 - 1 and the eq. 18 total Delta M of the step at sample times;
+the final contact angle; the largest speed over the fluid at the end (the spurious currents of
+Sec. 4.4); the step at which a run stopped on a psi domain error, if it did.
+
+    python -m paper_2203_04508_amd.qsweep [--steps 20000] [--out profiles/qsweep_flat.json]
+    python -m paper_2203_04508_amd.qsweep --summarize profiles/qsweep_flat.json   (text table)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+NX, NY, Y1, R0 = 500, 300, 11, 50.0
+T_OVER_TC, TAU = 0.70, 1.0
+
+
+def setup(q):
+    from paper_2203_04508_amd import workloads as W
+
+    yw = Y1 - q
+    shapes = np.array([W.band_y(-0.5, yw, 0)], np.int64)
+    rv, rl = W.MAXWELL[T_OVER_TC]
+    rho0 = W.drop_field((NX, NY, 1), 2, [((NX / 2.0, yw), R0)], rv, rl, 2.0)
+    # the half of the drop below the wall line would wrap to the top of the periodic box, against
+    # the band's underside: vapour there
+    rho0.reshape(NY, NX)[NY // 2:] = rv
+    return shapes, rho0, yw, rv, rl
+
+
+def interface_points(rho, yw, rv, rl):
+    """(x, y) where rho crosses (rho_l + rho_v) / 2 along rows at least 4 above the wall."""
+    rm = 0.5 * (rv + rl)
+    g = rho.reshape(NY, NX)
+    pts = []
+    for y in range(int(math.ceil(yw + 4.0)), NY):
+        row = g[y]
+        liq = row > rm
+        if not liq.any():
+            continue
+        d = np.nonzero(np.diff(liq.astype(np.int8)))[0]  # crossings between x and x + 1
+        for x in d:
+            a, b = row[x], row[x + 1]
+            pts.append((x + (rm - a) / (b - a), float(y)))
+    return np.array(pts)
+
+
+def contact_angle(rho, yw, rv, rl):
+    """Degrees, from an algebraic (Kasa) circle fit to the interface; nan without a drop."""
+    p = interface_points(rho, yw, rv, rl)
+    if len(p) < 8:
+        return float("nan")
+    x, y = p[:, 0], p[:, 1]
+    A = np.stack([x, y, np.ones_like(x)], 1)
+    c, *_ = np.linalg.lstsq(A, x * x + y * y, rcond=None)
+    xc, yc = c[0] / 2.0, c[1] / 2.0
+    R = math.sqrt(c[2] + xc * xc + yc * yc)
+    cth = (yw - yc) / R
+    return math.degrees(math.acos(max(-1.0, min(1.0, cth))))
+
+
+def make_lattice(mode, q, phi):
+    from paper_2203_04508_amd import mcb, workloads as W
+
+    shapes, rho0, yw, rv, rl = setup(q)
+    lat = mcb.Lattice(2, (NX, NY, 1), TAU, T_OVER_TC * W.CS_TC, precision="f64", bc_mode=mode)
+    try:
+        lat.set_geometry(shapes)
+        lat.set_wettability(phi)
+        lat.init_equilibrium(rho0)
+    except mcb.MCBError:
+        lat.close()
+        raise
+    return lat, yw, rv, rl
+
+
+def equilibrium_angle(phi, steps):
+    """Contact angle after steps steps of the present scheme at q = 1/2; nan if the run stops on a
+    psi domain error (phi too large for the equation of state)."""
+    from paper_2203_04508_amd import mcb
+
+    lat = None
+    try:
+        lat, yw, rv, rl = make_lattice("present", 0.5, phi)
+        lat.step(steps)
+        rho, _ = lat.moments()
+        return contact_angle(rho, yw, rv, rl)
+    except mcb.MCBError:
+        return float("nan")
+    finally:
+        if lat is not None:
+            lat.close()
+
+
+def calibrate(target, steps, lo=0.50, hi=1.45, iters=10):
+    """phi in [lo, hi] with the equilibrium angle at target degrees (the angle falls as phi rises;
+    a domain error counts as too wetting)."""
+    log = []
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        th = equilibrium_angle(mid, steps)
+        log.append((mid, th))
+        print(f"[qsweep] calibrate {target}: phi {mid:.5f} -> {th:.2f} deg", file=sys.stderr, flush=True)
+        if not np.isfinite(th) or th < target:
+            hi = mid
+        else:
+            lo = mid
+    return 0.5 * (lo + hi), log
+
+
+def run(mode, q, phi, steps, every):
+    from paper_2203_04508_amd import mcb
+
+    lat, yw, rv, rl = make_lattice(mode, q, phi)
+    M0 = lat.mass().M
+    ts, m, dm = [0], [0.0], [0.0]
+    failed = None
+    t = n = 0
+    try:
+        while t < steps:
+            n = min(every, steps - t)
+            lat.step(n)
+            t += n
+            rep = lat.mass()
+            ts.append(t)
+            m.append((rep.M - M0) / M0)
+            dm.append(rep.dM_last)
+    except mcb.MCBError as e:
+        failed = {"step_before": t + n, "error": str(e)}
+    out = {"mode": mode, "q": q, "t": ts, "drift": m, "dM_last": dm, "failed": failed}
+    if failed is None:
+        rho, v = lat.moments()
+        fluid = rho > 0
+        out["theta_end"] = contact_angle(rho, yw, rv, rl)
+        out["max_speed_end"] = float(np.sqrt((v[:, fluid] ** 2).sum(0)).max())
+    lat.close()
+    return out
+
+
+def _round(x, sig=6):
+    if isinstance(x, float):
+        return float(f"{x:.{sig}g}")
+    if isinstance(x, list):
+        return [_round(v, sig) for v in x]
+    if isinstance(x, dict):
+        return {k: _round(v, sig) for k, v in x.items()}
+    return x
+
+
+def summarize(res) -> str:
+    """Per angle: for each q, M/M0 at the end (or the step a run stopped before), the final contact
+    angle and the final largest speed, per scheme; and the largest |Delta M| sampled after the
+    first quarter of the run for MIBC and the present scheme."""
+    lines = [f"flat-substrate q-sweep, {res['box'][0]}x{res['box'][1]} D2Q9 FP64, drop r {res['drop_radius']}, "
+             f"{res['steps']} steps, T/Tc {res['T_over_Tc']}, tau {res['tau']}", f"command: {res['command']}"]
+    for a in res["angles"]:
+        th05 = a["theta_present_q05"]
+        lines.append("")
+        lines.append(f"target {a['target_deg']:.0f} deg: phi {a['phi']:.5f}, equilibrium angle at q = 1/2 {th05:.1f} deg")
+        runs = {(r["mode"], r["q"]): r for r in a["runs"]}
+        hb = next(r for r in a["runs"] if r["mode"] == "hbbc")
+        lines.append(f"halfway bounce-back (q-independent): M/M0-1 {hb['drift'][-1]:+.1e}, theta {hb['theta_end']:.1f}, "
+                     f"max|v| {hb['max_speed_end']:.2e}")
+        lines.append("  q   | present: M/M0-1   theta  max|v|  | IBC: M/M0 (theta)        | MIBC: M/M0-1  theta  max|v|  "
+                     "| max|dM| late: MIBC   present")
+        for q in sorted({r["q"] for r in a["runs"] if r["mode"] == "present"}):
+            p, i, m = runs[("present", q)], runs[("ibc", q)], runs[("mibc", q)]
+            k0 = len(p["t"]) // 4
+
+            def late(r):
+                return max(abs(v) for v in r["dM_last"][k0:]) if len(r["dM_last"]) > k0 else float("nan")
+
+            ibc = (f"{1 + i['drift'][-1]:.3f} ({i['theta_end']:.0f})" if i["failed"] is None
+                   else f"stop < {i['failed']['step_before']} ({1 + i['drift'][-1]:.3f})")
+            lines.append(f"  {q:.1f} | {p['drift'][-1]:+.1e}  {p['theta_end']:6.1f}  {p['max_speed_end']:.2e} | "
+                         f"{ibc:24s} | {m['drift'][-1]:+.1e}  {m['theta_end']:6.1f}  {m['max_speed_end']:.2e} | "
+                         f"{late(m):.2e}  {late(p):.2e}")
+    return "\n".join(lines) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--summarize", default=None, help="print the text table of a stored result")
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--every", type=int, default=1000)
+    ap.add_argument("--calib-steps", type=int, default=10000)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    if args.summarize:
+        print(summarize(json.load(open(args.summarize))), end="")
+        return
+    sys.path.insert(0, ROOT)
+    t0 = time.time()
+    qs = [round(0.1 * k, 1) for k in range(10)]
+    res = {"command": "python3 -m paper_2203_04508_amd.qsweep " + " ".join(sys.argv[1:]),
+           "box": [NX, NY], "first_fluid_row": Y1, "drop_radius": R0, "T_over_Tc": T_OVER_TC, "tau": TAU,
+           "precision": "f64", "steps": args.steps, "angles": []}
+    for target in (60.0, 120.0):
+        phi, log = calibrate(target, args.calib_steps)
+        ang = {"target_deg": target, "phi": phi, "calibration": [[p, th] for p, th in log],
+               "theta_present_q05": equilibrium_angle(phi, args.calib_steps), "runs": []}
+        for mode in ("present", "ibc", "mibc", "hbbc"):
+            for q in (qs if mode != "hbbc" else [0.3]):  # halfway bounce-back does not see q
+                r = run(mode, q, phi, args.steps, args.every)
+                ang["runs"].append(r)
+                f = r["failed"]
+                print(f"[qsweep] {target:.0f} deg {mode:7s} q={q:.1f}: M/M0-1 {r['drift'][-1]:+.3e}"
+                      + (f" stopped: {f['error']}" if f else f", theta {r['theta_end']:.1f}, max|v| {r['max_speed_end']:.2e}"),
+                      file=sys.stderr, flush=True)
+        res["angles"].append(ang)
+    res["wall_seconds"] = time.time() - t0
+    res = _round(res)
+    text = json.dumps(res, separators=(",", ":"))
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(text + "\n")
+    print(json.dumps({"angles": [{"target": a["target_deg"], "phi": a["phi"],
+                                  "final_drift": {f"{r['mode']}@{r['q']}": r["drift"][-1] for r in a["runs"]}}
+                                 for a in res["angles"]]}, indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -64,13 +64,24 @@ def test_host_side_argument_checks(lib):
     assert sz.lattice_bytes >= 2 * 9 * 64 * 64 * 8 and sz.links_bytes == 0
     sz2 = mcb.mcb_required_sizes(good, 1, 100, 40, 30)
     assert sz2.links_bytes > 0
-    for bad in [dict(tau=0.5), dict(G=1.0), dict(nx=2), dict(dim=4), dict(precision=7), dict(nz=5)]:
+    for bad in [dict(tau=0.5), dict(G=1.0), dict(nx=2), dict(dim=4), dict(precision=7), dict(nz=5),
+                dict(bc_mode=4), dict(bc_mode=-1)]:
         p = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, 0, 0.0)
         for k, v in bad.items():
             setattr(p, k, v)
         with pytest.raises(mcb.MCBError) as ei:
             mcb.mcb_create(p)
         assert ei.value.code == mcb.MCB_EINVAL
+    # every boundary scheme in 2-D; IBC in 3-D is an unsupported combination
+    for mode in (mcb.MCB_BC_PRESENT, mcb.MCB_BC_IBC, mcb.MCB_BC_MIBC, mcb.MCB_BC_HBBC):
+        p = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, mode, 0.0)
+        mcb.mcb_destroy(mcb.mcb_create(p))
+    p3 = mcb.mcb_params(3, 16, 16, 16, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, mcb.MCB_BC_IBC, 0.0)
+    with pytest.raises(mcb.MCBError) as ei:
+        mcb.mcb_create(p3)
+    assert ei.value.code == mcb.MCB_ENOTSUP
+    p3.bc_mode = mcb.MCB_BC_MIBC
+    mcb.mcb_destroy(mcb.mcb_create(p3))
     h = mcb.mcb_create(good)
     # calls out of order are refused before any device work
     with pytest.raises(mcb.MCBError) as ei:

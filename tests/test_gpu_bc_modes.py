@@ -1,0 +1,188 @@
+"""GPU parity of the comparison boundary schemes (linear interpolation bounce-back IBC, MIBC = IBC
+with eq. 18, halfway bounce-back HBBC; Secs. 1, 3 and 4 of arXiv 2203.04508) against the FP64
+oracle run in the same scheme, through the C ABI.
+
+Bars as for the present scheme: FP64 populations within 1e-12 relative per step (k steps: k 1e-12),
+1e-9 after 1000 steps; the eq. 18 total of the last step within 1e-12; FP32 / FP16 storage within
+the shifted-storage bars of the present scheme.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2203_04508_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TC = W.CS_TC
+MODES = {"ibc": oracle.BC_IBC, "mibc": oracle.BC_MIBC, "hbbc": oracle.BC_HBBC}
+
+
+def banner(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mcb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_04508_amd import mcb as m
+    m.load()
+    return m
+
+
+def rel_err(a, b, fluid):
+    worst = 0.0
+    for i in range(a.shape[0]):
+        d = np.abs(a[i, fluid] - b[i, fluid]).max()
+        s = np.abs(b[i, fluid]).max()
+        worst = max(worst, d / s)
+    return worst
+
+
+def build_pair(mcb, dim, dims, tau, T, shapes, mode, phi, q_override=None, precision="f64", rho_ref=0.0):
+    P = oracle.make_params(dim, *dims, tau=tau, T=T)
+    solid = oracle.classify(P, shapes)
+    node, d, cls, q = oracle.links(P, shapes, solid)
+    lat = mcb.Lattice(dim, dims, tau, T, precision=precision, rho_ref=rho_ref, bc_mode=mode)
+    nl, nb, nw = lat.set_geometry(shapes)
+    assert nl == len(node)
+    got = lat.links()
+    # the link list reports the geometry whatever the scheme
+    assert np.array_equal(got["q_fixed"], q) and np.array_equal(got["cls"], cls)
+    if q_override is not None:
+        q = q_override(q).astype(np.uint32)
+        got["q_fixed"] = q
+        lat.set_links(got)
+    sim = oracle.Sim(P, solid, node, d, q)
+    sim.set_bc_mode(MODES[mode])
+    phi = np.broadcast_to(np.asarray(phi, np.float64), (nw,)).copy()
+    sim.set_phi(phi)
+    lat.set_wettability(phi)
+    return sim, lat, solid == 0
+
+
+def random_state(rng, rho_field, dim):
+    N = len(rho_field)
+    u = rng.uniform(-0.02, 0.02, (N, dim))
+    f = np.stack([oracle.equilibrium(dim, rho_field[x], u[x]) for x in range(N)], axis=1)
+    return f * (1.0 + 0.01 * rng.standard_normal(f.shape))
+
+
+CASES2 = [("300x70-ragged", (300, 70, 1), 21, None), ("37x29-random-q", (37, 29, 1), 22, "random")]
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("name,dims,seed,qmode", CASES2, ids=[c[0] for c in CASES2])
+def test_step_parity_by_scheme_2d(mcb, mode, name, dims, seed, qmode):
+    banner(f"D2Q9 {mode} step parity {name}")
+    rng = np.random.default_rng(seed)
+    shapes = W.random_links_case(rng, dims, 2, max(3, dims[0] * dims[1] // 900), 2.0, 6.0)
+    rv, rl = W.MAXWELL[0.7]
+    drops = [((rng.uniform(0, dims[0]), rng.uniform(0, dims[1])), rng.uniform(4, 9)) for _ in range(3)]
+    rho = W.drop_field(dims, 2, drops, rv, rl, 2.0)
+    qo = (lambda q: rng.integers(0, 65537, len(q))) if qmode == "random" else None
+    sim, lat, fluid = build_pair(mcb, 2, dims, 0.8, 0.7 * TC, shapes, mode, rng.uniform(0.85, 1.15), qo)
+    f0 = random_state(rng, rho, 2)
+    sim.set_f(f0)
+    lat.set_f(f0)
+    for k in range(1, 21):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < 1e-12 * k, (k, e)
+    rep = lat.mass()
+    assert abs(rep.dM_last - sim.dm_last()) < 1e-12 * max(1.0, abs(sim.dm_last()))
+    if mode != "mibc":
+        assert rep.dM_last == 0.0  # IBC applies no correction; halfway bounce-back's terms cancel
+    lat.close()
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_c0_1000_steps_by_scheme(mcb, mode):
+    banner(f"c0 {mode}, 1000 steps")
+    wl = W.make("c0")
+    P = oracle.make_params(2, *wl.dims, tau=wl.tau, T=wl.T)
+    solid = oracle.classify(P, wl.shapes)
+    phi = W.phi_for_walls(wl, oracle.wall_nodes(P, solid))
+    sim, lat, fluid = build_pair(mcb, 2, wl.dims, wl.tau, wl.T, wl.shapes, mode, phi)
+    rho0 = wl.rho0()
+    sim.init_eq(rho0)
+    lat.init_equilibrium(rho0)
+    M0 = lat.mass().M
+    sim.step(1000)
+    lat.step(1000)
+    e = rel_err(lat.get_f(), sim.get_f(), fluid)
+    assert e < 1e-9, e
+    M1 = lat.mass().M
+    assert abs(M1 - sim.mass()) / M0 < 1e-12
+    if mode == "ibc":
+        assert abs(M1 - M0) / M0 > 1e-6  # the scheme the paper shows to leak or gain mass
+    else:
+        assert abs(M1 - M0) / M0 < 1e-12
+    lat.close()
+
+
+@pytest.mark.parametrize("mode,prec,tol", [("ibc", "f32s", 3e-6), ("mibc", "f32s", 3e-6), ("hbbc", "f32s", 3e-6),
+                                           ("mibc", "f16s", 3e-3)])
+def test_c1_shifted_storage_by_scheme(mcb, mode, prec, tol):
+    """1024^2 (300 off-lattice circles, 40 drops), three steps in reduced-precision storage."""
+    banner(f"c1 {mode} {prec}, 3 steps")
+    wl = W.make("c1")
+    P = oracle.make_params(2, *wl.dims, tau=wl.tau, T=wl.T)
+    solid = oracle.classify(P, wl.shapes)
+    phi = W.phi_for_walls(wl, oracle.wall_nodes(P, solid))
+    sim, lat, fluid = build_pair(mcb, 2, wl.dims, wl.tau, wl.T, wl.shapes, mode, phi, precision=prec,
+                                 rho_ref=wl.rho_v)
+    rho0 = wl.rho0()
+    sim.init_eq(rho0)
+    lat.init_equilibrium(rho0)
+    for k in range(1, 4):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < tol * (k + 1), (k, e)
+    lat.close()
+
+
+@pytest.mark.parametrize("mode", ["mibc", "hbbc"])
+def test_step_parity_by_scheme_3d(mcb, mode):
+    banner(f"D3Q19 {mode} step parity 31x27x19 random q")
+    dims = (31, 27, 19)
+    rng = np.random.default_rng(31)
+    shapes = W.random_links_case(rng, dims, 3, 4, 1.5, 4.5)
+    rv, rl = W.MAXWELL[0.7]
+    drops = [(tuple(rng.uniform(0, n) for n in dims), rng.uniform(2.5, 5.0)) for _ in range(3)]
+    rho = W.drop_field(dims, 3, drops, rv, rl, 4.0)
+    qo = lambda q: rng.integers(0, 65537, len(q))
+    sim, lat, fluid = build_pair(mcb, 3, dims, 0.8, 0.7 * TC, shapes, mode, rng.uniform(0.85, 1.15), qo)
+    f0 = random_state(rng, rho, 3)
+    sim.set_f(f0)
+    lat.set_f(f0)
+    for k in range(1, 11):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < 1e-12 * k, (k, e)
+    rep = lat.mass()
+    assert abs(rep.dM_last - sim.dm_last()) < 1e-12 * max(1.0, abs(sim.dm_last()))
+    lat.close()
+
+
+def test_unsupported_combinations_rejected(mcb):
+    banner("IBC in 3-D and reverse mode of a comparison scheme: MCB_ENOTSUP")
+    with pytest.raises(mcb.MCBError) as ei:
+        mcb.Lattice(3, (8, 8, 8), 1.0, 0.7 * TC, bc_mode="ibc")
+    assert ei.value.code == -7
+    wl = W.make("c0")
+    lat = mcb.Lattice(2, wl.dims, wl.tau, wl.T, bc_mode="mibc")
+    lat.set_geometry(wl.shapes)
+    lat.set_wettability(1.0)
+    with pytest.raises(mcb.MCBError) as ei:
+        lat.adj_forward(wl.rho0(), 10, 5)
+    assert ei.value.code == -7
+    lat.close()
