@@ -12,7 +12,9 @@
 //                      D3Q19 for the 3-D runs (not in the paper; listed below)
 //   equilibrium        eq. 14 with c_s^2 = 1/3
 //   forcing            exact difference method, eq. 13
-//   collision          eq. 4 with S = I/tau (single relaxation time), streaming eq. 5
+//   collision          eq. 4 with S = I/tau (single relaxation time), or in 2-D the paper's
+//                      multiple-relaxation-time form: eqs. 1-4 with the moment matrix of eq. 2, the
+//                      listed moment equilibria and S of eq. 3; streaming eq. 5
 //   nonideal force     pseudopotential with an EOS-based effective mass (the model class named in
 //                      Sec. 1): psi = sqrt(2 (p_EOS - rho c_s^2) / G), F = -G psi(x) sum_i w^_i psi(x+e_i) e_i,
 //                      Carnahan-Starling p_EOS
@@ -159,6 +161,67 @@ void equilibrium(const Lat& L, R rho, const R u[3], R out[]) {
     for (int i = 0; i < L.Q; ++i) {
         R eu = u[0] * double(L.e[i][0]) + u[1] * double(L.e[i][1]) + u[2] * double(L.e[i][2]);
         out[i] = L.w[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+}
+
+// eq. 2: D2Q9 moment matrix; rows rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy, columns the
+// velocities in the order of make_lat
+const double MRT_M[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+
+// inverse of an n x n matrix by Gauss-Jordan elimination with partial pivoting
+void invert(int n, const double* A, double* Ainv) {
+    std::vector<double> a(A, A + n * n), b(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) b[i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r) if (std::fabs(a[r * n + c]) > std::fabs(a[piv * n + c])) piv = r;
+        for (int k = 0; k < n; ++k) { std::swap(a[c * n + k], a[piv * n + k]); std::swap(b[c * n + k], b[piv * n + k]); }
+        const double d = a[c * n + c];
+        for (int k = 0; k < n; ++k) { a[c * n + k] /= d; b[c * n + k] /= d; }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double m = a[r * n + c];
+            for (int k = 0; k < n; ++k) { a[r * n + k] -= m * a[c * n + k]; b[r * n + k] -= m * b[c * n + k]; }
+        }
+    }
+    for (int i = 0; i < n * n; ++i) Ainv[i] = b[i];
+}
+
+// the multiple-relaxation-time collision of eqs. 1-4 (D2Q9): the relaxation rates of eq. 3 and M^-1
+struct Mrt {
+    bool on = false;
+    double s[9] = {};
+    double Minv[9][9] = {};
+};
+
+// eq. 1-4 for one node: f~ = f - M^-1 S (m - m_eq) with m = M f and the equilibria of Sec. 2.1
+// (q_y^eq read as -j_y, like q_x^eq); the eq. 13 term is added by the caller
+template <class R>
+void mrt_relax(const Mrt& T, const R f[9], R out[9]) {
+    R m[9];
+    for (int k = 0; k < 9; ++k) {
+        m[k] = 0.0;
+        for (int i = 0; i < 9; ++i) m[k] += MRT_M[k][i] * f[i];
+    }
+    const R rho = m[0], jx = m[3], jy = m[5];
+    const R jj = (jx * jx + jy * jy) / rho;
+    const R meq[9] = {rho, -2.0 * rho + 3.0 * jj, rho - 3.0 * jj, jx, -jx, jy, -jy,
+                      (jx * jx - jy * jy) / rho, jx * jy / rho};
+    R d[9];
+    for (int k = 0; k < 9; ++k) d[k] = T.s[k] * (m[k] - meq[k]);
+    for (int i = 0; i < 9; ++i) {
+        R c = 0.0;
+        for (int k = 0; k < 9; ++k) c += T.Minv[i][k] * d[k];
+        out[i] = f[i] - c;
     }
 }
 
@@ -324,6 +387,7 @@ struct Sim {
     R dm_last = R(0.0);
     int64_t n_domain = 0;
     int bc_mode = 0;  // 0 present scheme, 1 IBC, 2 MIBC, 3 halfway bounce-back
+    Mrt mrt;          // multiple-relaxation-time collision (2-D) when mrt.on
 
     explicit Sim(const or_params& p) : P(p), L(make_lat(p.dim)), g(p) {}
 
@@ -383,8 +447,15 @@ struct Sim {
             R Fx[3], ux[3];
             for (int k = 0; k < 3; ++k) { Fx[k] = -P.G * psi[x] * s[k]; F[k * N + x] = Fx[k]; ux[k] = u[k * N + x]; }
             R feq[MAXQ], Fi[MAXQ];
-            equilibrium(L, rho[x], ux, feq);
             edm_terms(L, rho[x], ux, Fx, Fi);
+            if (mrt.on) {
+                R f[9], o[9];
+                for (int i = 0; i < 9; ++i) f[i] = fpre[i * N + x];
+                mrt_relax(mrt, f, o);
+                for (int i = 0; i < 9; ++i) ft[i * N + x] = o[i] + Fi[i];
+                continue;
+            }
+            equilibrium(L, rho[x], ux, feq);
             for (int i = 0; i < Q; ++i) {
                 R f = fpre[i * N + x];
                 ft[i * N + x] = f - (f - feq[i]) / P.tau + Fi[i];
@@ -715,6 +786,21 @@ void* or_sim_create(const or_params* P, const uint8_t* solid, const int64_t* lk_
 }
 
 void or_sim_destroy(void* h) { delete static_cast<Sim<double>*>(h); }
+
+// multiple-relaxation-time collision for later collisions (D2Q9 only): S of eq. 3 with the given
+// s_e, s_epsilon, s_q, and s_nu = 1/tau; each rate in (0, 2)
+int or_sim_set_mrt(void* h, double se, double seps, double sq) {
+    auto* S = static_cast<Sim<double>*>(h);
+    if (S->L.Q != 9) return -1;
+    for (double r : {se, seps, sq})
+        if (!(r > 0.0 && r < 2.0)) return -1;
+    const double snu = 1.0 / S->P.tau;
+    const double rates[9] = {1.0, se, seps, 1.0, sq, 1.0, sq, snu, snu};
+    for (int k = 0; k < 9; ++k) S->mrt.s[k] = rates[k];
+    invert(9, &MRT_M[0][0], &S->mrt.Minv[0][0]);
+    S->mrt.on = true;
+    return 0;
+}
 
 // boundary scheme of later steps: 0 present (eqs. 16-18), 1 IBC, 2 MIBC, 3 halfway bounce-back
 int or_sim_set_bc_mode(void* h, int mode) {

@@ -80,6 +80,8 @@ def lib():
         L.or_sim_create.argtypes = [P, vp, vp, vp, vp, C.c_int64]
         L.or_sim_create.restype = vp
         L.or_sim_destroy.argtypes = [vp]
+        L.or_sim_set_mrt.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+        L.or_sim_set_mrt.restype = C.c_int
         L.or_sim_set_bc_mode.argtypes = [vp, C.c_int]
         L.or_sim_set_bc_mode.restype = C.c_int
         L.or_sim_n_wall.argtypes = [vp]
@@ -253,6 +255,11 @@ class Sim:
             raise OracleError(f"{what}: non-finite population")
         if rc != 0:
             raise OracleError(f"{what}: error {rc}")
+
+    def set_mrt(self, se=1.64, seps=1.54, sq=1.7):
+        """Multiple-relaxation-time collision (D2Q9, eqs. 1-4) for the collisions that follow, with
+        S = diag(1, se, seps, 1, sq, 1, sq, 1/tau, 1/tau); the defaults are the rates of eq. 3."""
+        self._check(lib().or_sim_set_mrt(self.h, se, seps, sq), "set_mrt")
 
     def set_bc_mode(self, mode: int):
         """0 present scheme (eqs. 16-18), 1 IBC (eqs. 16-17 without the forcing term, no eq. 18),
