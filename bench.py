@@ -4,7 +4,7 @@ A step is one pass of the whole hot path over the lattice: the fused kernel that
 populations, applies the curved-boundary links (eqs. 16-18), computes the pseudopotential force and
 collides. Inputs are resident in HBM before the timed region starts. Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--bc-mode present] [--no-cpu] [--no-adjoint]
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--bc-mode present] [--collision bgk] [--no-cpu] [--no-adjoint]
 
 Default: the 4096^2 D2Q9 workload (4800 circles, 640 drops) with shifted-FP32 storage, its 5000
 steps, as the throughput and HBM-roofline figures are quoted on it; the oracle is timed on a
@@ -34,10 +34,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def setup_gpu(wl, precision, rho_ref, bc_mode="present"):
+def setup_gpu(wl, precision, rho_ref, bc_mode="present", collision="bgk"):
     from paper_2203_04508_amd import mcb
 
-    lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision, rho_ref=rho_ref, bc_mode=bc_mode)
+    lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision, rho_ref=rho_ref, bc_mode=bc_mode,
+                      collision=collision)
     nl, nb, nw = lat.set_geometry(wl.shapes)
     from paper_2203_04508_amd import workloads as W
 
@@ -109,15 +110,18 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(wl, budget_s=12.0, single_s=4.0):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload: all threads
-    OpenMP gives it, then one thread."""
+def cpu_baseline(wl, budget_s=12.0, single_s=4.0, bc_mode="present", collision="bgk"):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload (same boundary
+    scheme and collision): all threads OpenMP gives it, then one thread."""
     from oracle import oracle
     from paper_2203_04508_amd import workloads as W
 
     P = oracle.make_params(wl.dim, *wl.dims, tau=wl.tau, T=wl.T)
     sim, (solid, *_rest) = oracle.sim_from_shapes(P, wl.shapes)
     sim.set_phi(W.phi_for_walls(wl, oracle.wall_nodes(P, solid)))
+    sim.set_bc_mode({"present": 0, "ibc": 1, "mibc": 2, "hbbc": 3}[bc_mode])
+    if collision == "mrt":
+        sim.set_mrt()
     sim.init_eq(wl.rho0())
     sim.step(1)
 
@@ -155,6 +159,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="f32s", choices=list(DTYPES))
     ap.add_argument("--bc-mode", default="present", choices=["present", "ibc", "mibc", "hbbc"])
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -171,7 +176,7 @@ def main():
     steps = args.steps if args.steps is not None else wl.steps
     rho_ref = wl.rho_v if args.precision != "f64" else 0.0
     log(f"[bench] workload {wl.name} dims {wl.dims[:wl.dim]} precision {args.precision}: set-up")
-    lat, (nl, nb, nw) = setup_gpu(wl, args.precision, rho_ref, args.bc_mode)
+    lat, (nl, nb, nw) = setup_gpu(wl, args.precision, rho_ref, args.bc_mode, args.collision)
     M0 = lat.mass().M
     log(f"[bench] links {nl} boundary nodes {nb} wall nodes {nw}; warmup {args.warmup}")
     lat.step(args.warmup)
@@ -220,6 +225,7 @@ def main():
             "workload": f"{wl.name}: D2Q9 {wl.dims[0]}x{wl.dims[1]}" if wl.dim == 2 else f"{wl.name}: D3Q19 {wl.dims[0]}^3",
             "storage": args.precision,
             "bc_mode": args.bc_mode,
+            "collision": args.collision,
             "rho_ref": rho_ref,
             "links": nl, "boundary_nodes": nb, "wall_nodes": nw,
             "T_over_Tc": wl.T_over_Tc, "tau": wl.tau,
@@ -244,7 +250,7 @@ def main():
         out["fwd_adjoint"] = fwd_adjoint(args.precision)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, bc_mode=args.bc_mode, collision=args.collision)
     print(json.dumps(out), flush=True)
 
 

@@ -72,6 +72,13 @@ enum {
     MCB_BC_HBBC = 3     /* halfway bounce-back on every link (q ignored; eq. 18 terms are zero) */
 };
 
+/* collision operator */
+enum {
+    MCB_COLL_BGK = 0,  /* eq. 4 with S = I/tau (single relaxation time) */
+    MCB_COLL_MRT = 1   /* eqs. 1-4: moment matrix of eq. 2, S = diag(1, s_e, s_eps, 1, s_q, 1, s_q,
+                          1/tau, 1/tau) of eq. 3; D2Q9 only (MCB_ENOTSUP from mcb_create for dim 3) */
+};
+
 /* build_links phases */
 enum { MCB_COUNT = 0, MCB_FILL = 1 };
 
@@ -92,6 +99,10 @@ typedef struct {
     int32_t precision;      /* MCB_F64, MCB_F32S, MCB_F16S */
     int32_t bc_mode;        /* MCB_BC_PRESENT, MCB_BC_IBC, MCB_BC_MIBC, MCB_BC_HBBC */
     double rho_ref;         /* shift of the stored populations (ignored for MCB_F64) */
+    int32_t collision;      /* MCB_COLL_BGK (0, the default of a zeroed struct) or MCB_COLL_MRT */
+    int32_t reserved;       /* 0 */
+    double s_e, s_eps, s_q; /* MRT rates of the energy, energy-square and heat-flux moments, each in
+                               (0, 2) for MCB_COLL_MRT (the paper's: 1.64, 1.54, 1.7); ignored for BGK */
 } mcb_params;
 
 /* A solid shape. kind MCB_SHAPE_BALL: centre (cx, cy, cz) and radius; a node is solid when it
@@ -134,7 +145,7 @@ typedef struct {
 } mcb_mass_report;
 
 /* ---- context ---------------------------------------------------------------------------- */
-/* Validates params (MCB_EINVAL otherwise; MCB_ENOTSUP for MCB_BC_IBC in 3-D) and creates a
+/* Validates params (MCB_EINVAL otherwise; MCB_ENOTSUP for MCB_BC_IBC or MCB_COLL_MRT in 3-D) and creates a
  * context; no device work. */
 mcb_status mcb_create(const mcb_params* params, mcb_ctx** out);
 void mcb_destroy(mcb_ctx* ctx);
@@ -229,8 +240,8 @@ mcb_status mcb_timing_report(mcb_ctx* ctx, double* ms, int64_t* launches);
 enum { MCB_LOSS_COM_X = 0, MCB_LOSS_WETTED_LENGTH = 1, MCB_LOSS_TOTAL_MASS = 2 };
 
 /* Device bytes of the reverse-mode arena for nsteps >= 0 steps with a checkpoint every k >= 1
- * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_BC_PRESENT only: the adjoint
- * calls return MCB_ENOTSUP for the other schemes. */
+ * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_BC_PRESENT with MCB_COLL_BGK
+ * only: the adjoint calls return MCB_ENOTSUP for the other schemes and for MRT. */
 mcb_status mcb_adj_required_bytes(mcb_ctx* ctx, int64_t nsteps, int64_t k, int64_t* bytes);
 
 /* Binds the caller-owned reverse-mode arena (device memory, at least the required bytes, 256-byte

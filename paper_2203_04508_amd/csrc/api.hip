@@ -153,6 +153,10 @@ bool params_ok(const mcb_params* p, const char** why) {
     if (p->precision < MCB_F64 || p->precision > MCB_F16S) { *why = "unknown precision"; return false; }
     if (p->bc_mode < MCB_BC_PRESENT || p->bc_mode > MCB_BC_HBBC) { *why = "unknown bc_mode"; return false; }
     if (p->precision != MCB_F64 && !(std::isfinite(p->rho_ref) && p->rho_ref >= 0.0)) { *why = "bad rho_ref"; return false; }
+    if (p->collision != MCB_COLL_BGK && p->collision != MCB_COLL_MRT) { *why = "unknown collision"; return false; }
+    if (p->collision == MCB_COLL_MRT)
+        for (double r : {p->s_e, p->s_eps, p->s_q})
+            if (!(r > 0.0 && r < 2.0)) { *why = "MRT rates must lie in (0, 2)"; return false; }
     return true;
 }
 
@@ -217,6 +221,8 @@ mcb_status mcb_create(const mcb_params* params, mcb_ctx** out) {
     if (!params_ok(params, &why)) return MCB_EINVAL;
     // the 3-D density pass takes the boundary nodes' density from the eq. 18 balance
     if (params->dim == 3 && params->bc_mode == MCB_BC_IBC) return MCB_ENOTSUP;
+    // the paper gives the moment basis of D2Q9 only
+    if (params->dim == 3 && params->collision == MCB_COLL_MRT) return MCB_ENOTSUP;
     auto* c = new (std::nothrow) mcb_ctx();
     if (!c) return MCB_EINVAL;
     c->p = *params;
@@ -544,6 +550,7 @@ mcb_status mcb_adj_required_bytes(mcb_ctx* c, int64_t nsteps, int64_t k, int64_t
     if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
     if (nsteps < 0 || k < 1) return fail(c, MCB_EINVAL, "need nsteps >= 0 and k >= 1");
     if (c->p.bc_mode != MCB_BC_PRESENT) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the present scheme only");
+    if (c->p.collision != MCB_COLL_BGK) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the BGK collision only");
     *bytes = adj_plan(c, nsteps, k).bytes;
     return MCB_OK;
 }
@@ -565,6 +572,7 @@ mcb_status mcb_adj_forward(mcb_ctx* c, const double* rho0, int64_t nsteps, int64
     if (nsteps < 0 || k < 1) return fail(c, MCB_EINVAL, "need nsteps >= 0 and k >= 1");
     if (kind < MCB_LOSS_COM_X || kind > MCB_LOSS_TOTAL_MASS) return fail(c, MCB_EINVAL, "unknown loss");
     if (c->p.bc_mode != MCB_BC_PRESENT) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the present scheme only");
+    if (c->p.collision != MCB_COLL_BGK) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the BGK collision only");
     if (kind == MCB_LOSS_WETTED_LENGTH && !(prm[1] > 0.0)) return fail(c, MCB_EINVAL, "wetted length needs delta > 0");
     const AdjPlan a = adj_plan(c, nsteps, k);
     if (!c->adj || c->adj_bytes < a.bytes) return fail(c, MCB_ESIZE, "reverse-mode arena needs %lld bytes", (long long)a.bytes);

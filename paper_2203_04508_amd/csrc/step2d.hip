@@ -57,6 +57,7 @@ struct Args2 {
     int nx, ny, H, nsx, nblocks;
     C tau_inv, G, rho_ref;
     C kF, k18;                   // boundary scheme: weight of the forcing term, of eq. 18 (0 or 1)
+    C s_e, s_eps, s_q;           // rates of the multiple-relaxation-time collision (eq. 3)
     Eos<C> eos;
 };
 
@@ -165,7 +166,7 @@ __device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[RF2 + 8], cons
 // One row of the march (iteration k, row r = y0 - 2 + k).  fC holds the pulled populations of row
 // r, fB and fA those of rows r-1 and r-2, fN those of row r+1 (in flight); the populations of row
 // r+2 are issued into fP.
-template <class S, class C, int W, int OUT, bool PULL>
+template <class S, class C, int W, int OUT, bool PULL, bool MRT>
 __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], C (&fB)[9], C (&fC)[9], C (&fN)[9],
                                           C (&fP)[9]) {
     const Args2<S, C>& a = M.a;
@@ -276,8 +277,9 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         const C rs = rs_pull;
         rho = rs + a.rho_ref;
         const C irho = rcp(coll ? rho : C(1));
-        const C ux = (fA[1] - fA[3] + fA[5] - fA[6] - fA[7] + fA[8]) * irho;
-        const C uy = (fA[2] - fA[4] + fA[5] + fA[6] - fA[7] - fA[8]) * irho;
+        const C jx = fA[1] - fA[3] + fA[5] - fA[6] - fA[7] + fA[8];
+        const C jy = fA[2] - fA[4] + fA[5] + fA[6] - fA[7] - fA[8];
+        const C ux = jx * irho, uy = jy * irho;
         dux = Fx * irho;
         duy = Fy * irho;
         const C ti = a.tau_inv, omc = C(1) - ti;
@@ -299,10 +301,38 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
             out[ip] = fA[ip] * omc + base + wra;
             out[im] = fA[im] * omc + base - wra;
         };
-        pair(1, 3, C(1.0 / 9.0), ux, dux, sx2);
-        pair(2, 4, C(1.0 / 9.0), uy, duy, sy2);
-        pair(5, 7, C(1.0 / 36.0), ux + uy, dux + duy, sx2 + sy2);
-        pair(6, 8, C(1.0 / 36.0), uy - ux, duy - dux, sy2 - sx2);
+        if constexpr (!MRT) {
+            pair(1, 3, C(1.0 / 9.0), ux, dux, sx2);
+            pair(2, 4, C(1.0 / 9.0), uy, duy, sy2);
+            pair(5, 7, C(1.0 / 36.0), ux + uy, dux + duy, sx2 + sy2);
+            pair(6, 8, C(1.0 / 36.0), uy - ux, duy - dux, sy2 - sx2);
+        } else {
+            // eqs. 1-4 with the moment matrix of eq. 2: the six non-conserved moments of the stored
+            // populations (the shift w_i rho_ref has moments rho_ref, -2 rho_ref, rho_ref, 0, ...,
+            // folded in through rs), relaxed at the eq. 3 rates toward the Sec. 2.1 equilibria
+            // (q^eq = -j); M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+            const C s14 = fA[1] + fA[2] + fA[3] + fA[4], s58 = fA[5] + fA[6] + fA[7] + fA[8];
+            const C jj = rho * (ux * ux + uy * uy);
+            const C de = a.s_e * (C(-4) * fA[0] - s14 + C(2) * s58 + C(2) * rs - C(3) * jj) * C(1.0 / 36.0);
+            const C dp = a.s_eps * (C(4) * fA[0] - C(2) * s14 + s58 - rs + C(3) * jj) * C(1.0 / 36.0);
+            const C dx = a.s_q * (C(-2) * (fA[1] - fA[3]) + (fA[5] - fA[6] - fA[7] + fA[8]) + jx) * C(1.0 / 12.0);
+            const C dy = a.s_q * (C(-2) * (fA[2] - fA[4]) + (fA[5] + fA[6] - fA[7] - fA[8]) + jy) * C(1.0 / 12.0);
+            const C dxx = ti * (fA[1] - fA[2] + fA[3] - fA[4] - rho * (ux * ux - uy * uy)) * C(0.25);
+            const C dxy = ti * (fA[5] - fA[6] + fA[7] - fA[8] - rho * ux * uy) * C(0.25);
+            // out = f - M^-1 S (m - m_eq) + F_i, F_i the eq. 13 term, by opposite pairs
+            auto mpair = [&](int ip, int im, C w, C ed, C es, C sym, C anti) {
+                const C wr = w * rho;
+                const C fs = wr * (C(4.5) * ed * es - duu15) + sym;
+                const C fa = wr * C(3) * ed + anti;
+                out[ip] = fA[ip] + fs + fa;
+                out[im] = fA[im] + fs - fa;
+            };
+            const C e1 = de + C(2) * dp, e2 = C(2) * de + dp;
+            mpair(1, 3, C(1.0 / 9.0), dux, sx2, e1 - dxx, C(2) * dx);
+            mpair(2, 4, C(1.0 / 9.0), duy, sy2, e1 + dxx, C(2) * dy);
+            mpair(5, 7, C(1.0 / 36.0), dux + duy, sx2 + sy2, -(e2 + dxy), -(dx + dy));
+            mpair(6, 8, C(1.0 / 36.0), duy - dux, sy2 - sx2, -(e2 - dxy), -(dy - dx));
+        }
         // collision conserves mass (the equilibrium and the forcing term of eq. 13 have zero net
         // mass): set f_0 to the density minus the other eight outputs as stored, so the rounding of
         // the lattice weights and of the storage format cannot bias the total mass
@@ -343,7 +373,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     }
 }
 
-template <class S, class C, int W, int OUT, bool PULL>
+template <class S, class C, int W, int OUT, bool PULL, bool MRT>
 __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     // XCD-aware order: consecutive logical tiles go to the same XCD (one L2)
     const int bid = blockIdx.x;
@@ -420,22 +450,23 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     M.phB = Buf<C>::ld(M.fac, M.tg_cur <= -2 ? uint32_t(-M.tg_cur - 2) * sc : OOB);
     int k = 0;
     for (; k + 5 <= M.iters; k += 5) {
-        march_row<S, C, W, OUT, PULL>(M, k + 0, f0, f1, f2, f3, f4);
-        march_row<S, C, W, OUT, PULL>(M, k + 1, f1, f2, f3, f4, f0);
-        march_row<S, C, W, OUT, PULL>(M, k + 2, f2, f3, f4, f0, f1);
-        march_row<S, C, W, OUT, PULL>(M, k + 3, f3, f4, f0, f1, f2);
-        march_row<S, C, W, OUT, PULL>(M, k + 4, f4, f0, f1, f2, f3);
+        march_row<S, C, W, OUT, PULL, MRT>(M, k + 0, f0, f1, f2, f3, f4);
+        march_row<S, C, W, OUT, PULL, MRT>(M, k + 1, f1, f2, f3, f4, f0);
+        march_row<S, C, W, OUT, PULL, MRT>(M, k + 2, f2, f3, f4, f0, f1);
+        march_row<S, C, W, OUT, PULL, MRT>(M, k + 3, f3, f4, f0, f1, f2);
+        march_row<S, C, W, OUT, PULL, MRT>(M, k + 4, f4, f0, f1, f2, f3);
     }
     const int left = M.iters - k;  // uniform
-    if (left > 0) march_row<S, C, W, OUT, PULL>(M, k + 0, f0, f1, f2, f3, f4);
-    if (left > 1) march_row<S, C, W, OUT, PULL>(M, k + 1, f1, f2, f3, f4, f0);
-    if (left > 2) march_row<S, C, W, OUT, PULL>(M, k + 2, f2, f3, f4, f0, f1);
-    if (left > 3) march_row<S, C, W, OUT, PULL>(M, k + 3, f3, f4, f0, f1, f2);
+    if (left > 0) march_row<S, C, W, OUT, PULL, MRT>(M, k + 0, f0, f1, f2, f3, f4);
+    if (left > 1) march_row<S, C, W, OUT, PULL, MRT>(M, k + 1, f1, f2, f3, f4, f0);
+    if (left > 2) march_row<S, C, W, OUT, PULL, MRT>(M, k + 2, f2, f3, f4, f0, f1);
+    if (left > 3) march_row<S, C, W, OUT, PULL, MRT>(M, k + 3, f3, f4, f0, f1, f2);
     if (M.bad) atomicOr(&a.flags[FLAG_DOMAIN], 1);
 }
 
 template <class S, class C, int W, int OUT>
 hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
+    const bool mrt = c->p.collision == MCB_COLL_MRT;
     Args2<S, C> a;
     a.fa = static_cast<const S*>(fcur);
     a.fb = static_cast<S*>(fnext);
@@ -458,9 +489,11 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
         H = 64;
         while (H > 8 && int64_t(a.nsx) * ((a.ny + H - 1) / H) < 8192) H >>= 1;
     } else {
-        static int occ[2] = {0, 0};
-        const int cap = pull ? resident_blocks(c, k_step2d<S, C, W, OUT, true>, W, &occ[1])
-                             : resident_blocks(c, k_step2d<S, C, W, OUT, false>, W, &occ[0]);
+        static int occ[4] = {0, 0, 0, 0};
+        const int cap = pull ? (mrt ? resident_blocks(c, k_step2d<S, C, W, OUT, true, true>, W, &occ[3])
+                                    : resident_blocks(c, k_step2d<S, C, W, OUT, true, false>, W, &occ[1]))
+                             : (mrt ? resident_blocks(c, k_step2d<S, C, W, OUT, false, true>, W, &occ[2])
+                                    : resident_blocks(c, k_step2d<S, C, W, OUT, false, false>, W, &occ[0]));
         const int per = cap / a.nsx > 0 ? cap / a.nsx : 1;  // segments per strip
         H = (a.ny + per - 1) / per;
         if (H < 16) H = 16;
@@ -472,14 +505,21 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
     a.rho_ref = c->p.precision == MCB_F64 ? C(0) : C(c->p.rho_ref);
     a.kF = c->p.bc_mode == MCB_BC_PRESENT ? C(1) : C(0);
     a.k18 = c->p.bc_mode == MCB_BC_IBC ? C(0) : C(1);
+    a.s_e = C(c->p.s_e);
+    a.s_eps = C(c->p.s_eps);
+    a.s_q = C(c->p.s_q);
     a.eos.RT = C(c->p.eos_R * c->p.eos_T);
     a.eos.a = C(c->p.eos_a);
     a.eos.b4 = C(c->p.eos_b / 4.0);
     a.eos.two_over_G = C(2.0 / c->p.G);
-    if (pull)
-        hipLaunchKernelGGL((k_step2d<S, C, W, OUT, true>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
+    if (pull && !mrt)
+        hipLaunchKernelGGL((k_step2d<S, C, W, OUT, true, false>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
+    else if (pull)
+        hipLaunchKernelGGL((k_step2d<S, C, W, OUT, true, true>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
+    else if (!mrt)
+        hipLaunchKernelGGL((k_step2d<S, C, W, OUT, false, false>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
     else
-        hipLaunchKernelGGL((k_step2d<S, C, W, OUT, false>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
+        hipLaunchKernelGGL((k_step2d<S, C, W, OUT, false, true>), dim3(a.nblocks), dim3(W), 0, c->stream, a);
     return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libmcb.so")
 MCB_OK, MCB_EINVAL, MCB_ESIZE, MCB_EHIP, MCB_EDOMAIN, MCB_ENAN, MCB_ESTATE, MCB_ENOTSUP = 0, -1, -2, -3, -4, -5, -6, -7
 MCB_F64, MCB_F32S, MCB_F16S = 0, 1, 2
 MCB_BC_PRESENT, MCB_BC_IBC, MCB_BC_MIBC, MCB_BC_HBBC = 0, 1, 2, 3
+MCB_COLL_BGK, MCB_COLL_MRT = 0, 1
+MRT_RATES_PAPER = (1.64, 1.54, 1.7)  # s_e, s_epsilon, s_q of eq. 3
 BC_MODES = {"present": MCB_BC_PRESENT, "ibc": MCB_BC_IBC, "mibc": MCB_BC_MIBC, "hbbc": MCB_BC_HBBC}
 MCB_COUNT, MCB_FILL = 0, 1
 PRECISIONS = {"f64": MCB_F64, "f32s": MCB_F32S, "f16s": MCB_F16S}
@@ -29,7 +31,9 @@ class mcb_params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("tau", C.c_double), ("G", C.c_double),
                 ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double), ("eos_T", C.c_double),
-                ("precision", C.c_int32), ("bc_mode", C.c_int32), ("rho_ref", C.c_double)]
+                ("precision", C.c_int32), ("bc_mode", C.c_int32), ("rho_ref", C.c_double),
+                ("collision", C.c_int32), ("reserved", C.c_int32),
+                ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double)]
 
 
 class mcb_shape(C.Structure):
@@ -279,7 +283,7 @@ class Lattice:
     """A context plus the torch tensors backing its device arenas."""
 
     def __init__(self, dim, dims, tau, T, precision="f64", rho_ref=0.0, G=-1.0, a=1.0, b=4.0, R=1.0,
-                 device="cuda:0", stream=None, bc_mode="present"):
+                 device="cuda:0", stream=None, bc_mode="present", collision="bgk", mrt_rates=MRT_RATES_PAPER):
         import torch
 
         self.torch = torch
@@ -287,7 +291,8 @@ class Lattice:
         nz = dims[2] if dim == 3 else 1
         self.params = mcb_params(dim, dims[0], dims[1], nz, tau, G, a, b, R, T,
                                  PRECISIONS[precision] if isinstance(precision, str) else precision,
-                                 BC_MODES[bc_mode] if isinstance(bc_mode, str) else bc_mode, rho_ref)
+                                 BC_MODES[bc_mode] if isinstance(bc_mode, str) else bc_mode, rho_ref,
+                                 {"bgk": MCB_COLL_BGK, "mrt": MCB_COLL_MRT}[collision], 0, *mrt_rates)
         self.dim = dim
         self.Q = 9 if dim == 2 else 19
         self.N = int(dims[0]) * int(dims[1]) * int(nz)

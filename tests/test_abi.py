@@ -45,12 +45,12 @@ def test_struct_layouts_match_header(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "mcb.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(mcb_params), sizeof(mcb_shape),"
         " sizeof(mcb_link), sizeof(mcb_sizes), sizeof(mcb_buffers), sizeof(mcb_mass_report),"
-        " offsetof(mcb_params, rho_ref)); return 0;}\n")
+        " offsetof(mcb_params, s_q)); return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(mcb.mcb_params), C.sizeof(mcb.mcb_shape), C.sizeof(mcb.mcb_link), C.sizeof(mcb.mcb_sizes),
-            C.sizeof(mcb.mcb_buffers), C.sizeof(mcb.mcb_mass_report), mcb.mcb_params.rho_ref.offset]
+            C.sizeof(mcb.mcb_buffers), C.sizeof(mcb.mcb_mass_report), mcb.mcb_params.s_q.offset]
     assert got == want
     assert mcb.LINK_DTYPE.itemsize == C.sizeof(mcb.mcb_link)
 
@@ -82,6 +82,21 @@ def test_host_side_argument_checks(lib):
     assert ei.value.code == mcb.MCB_ENOTSUP
     p3.bc_mode = mcb.MCB_BC_MIBC
     mcb.mcb_destroy(mcb.mcb_create(p3))
+    # MRT: D2Q9 only, rates in (0, 2)
+    pm = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, 0, 0.0, mcb.MCB_COLL_MRT, 0,
+                        *mcb.MRT_RATES_PAPER)
+    mcb.mcb_destroy(mcb.mcb_create(pm))
+    for k, v in (("s_e", 2.0), ("s_q", 0.0), ("collision", 2)):
+        bad = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, 0, 0.0, mcb.MCB_COLL_MRT, 0,
+                             *mcb.MRT_RATES_PAPER)
+        setattr(bad, k, v)
+        with pytest.raises(mcb.MCBError) as ei:
+            mcb.mcb_create(bad)
+        assert ei.value.code == mcb.MCB_EINVAL
+    p3.bc_mode, p3.collision, p3.s_e, p3.s_eps, p3.s_q = 0, mcb.MCB_COLL_MRT, 1.64, 1.54, 1.7
+    with pytest.raises(mcb.MCBError) as ei:
+        mcb.mcb_create(p3)
+    assert ei.value.code == mcb.MCB_ENOTSUP
     h = mcb.mcb_create(good)
     # calls out of order are refused before any device work
     with pytest.raises(mcb.MCBError) as ei:
