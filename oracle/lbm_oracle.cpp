@@ -15,6 +15,8 @@
 //   collision          eq. 4 with S = I/tau (single relaxation time), or in 2-D the paper's
 //                      multiple-relaxation-time form: eqs. 1-4 with the moment matrix of eq. 2, the
 //                      listed moment equilibria and S of eq. 3; streaming eq. 5
+//   body force         optional uniform acceleration g: F = F_nonideal + rho g (the drop-impact
+//                      runs of Sec. 4.5 use gravity); it enters eq. 13 and eqs. 16-17 with the rest
 //   nonideal force     pseudopotential with an EOS-based effective mass (the model class named in
 //                      Sec. 1): psi = sqrt(2 (p_EOS - rho c_s^2) / G), F = -G psi(x) sum_i w^_i psi(x+e_i) e_i,
 //                      Carnahan-Starling p_EOS
@@ -388,6 +390,7 @@ struct Sim {
     int64_t n_domain = 0;
     int bc_mode = 0;  // 0 present scheme, 1 IBC, 2 MIBC, 3 halfway bounce-back
     Mrt mrt;          // multiple-relaxation-time collision (2-D) when mrt.on
+    double grav[3] = {0.0, 0.0, 0.0};  // body acceleration
 
     explicit Sim(const or_params& p) : P(p), L(make_lat(p.dim)), g(p) {}
 
@@ -445,7 +448,11 @@ struct Sim {
                 for (int k = 0; k < 3; ++k) s[k] += L.wf[i] * psi[y] * double(L.e[i][k]);
             }
             R Fx[3], ux[3];
-            for (int k = 0; k < 3; ++k) { Fx[k] = -P.G * psi[x] * s[k]; F[k * N + x] = Fx[k]; ux[k] = u[k * N + x]; }
+            for (int k = 0; k < 3; ++k) {
+                Fx[k] = -P.G * psi[x] * s[k] + rho[x] * grav[k];
+                F[k * N + x] = Fx[k];
+                ux[k] = u[k * N + x];
+            }
             R feq[MAXQ], Fi[MAXQ];
             edm_terms(L, rho[x], ux, Fx, Fi);
             if (mrt.on) {
@@ -799,6 +806,17 @@ int or_sim_set_mrt(void* h, double se, double seps, double sq) {
     for (int k = 0; k < 9; ++k) S->mrt.s[k] = rates[k];
     invert(9, &MRT_M[0][0], &S->mrt.Minv[0][0]);
     S->mrt.on = true;
+    return 0;
+}
+
+// uniform body acceleration for later collisions (components beyond the lattice's dimension are 0)
+int or_sim_set_gravity(void* h, double gx, double gy, double gz) {
+    auto* S = static_cast<Sim<double>*>(h);
+    if (!std::isfinite(gx) || !std::isfinite(gy) || !std::isfinite(gz)) return -1;
+    if (S->L.dim == 2 && gz != 0.0) return -1;
+    S->grav[0] = gx;
+    S->grav[1] = gy;
+    S->grav[2] = gz;
     return 0;
 }
 

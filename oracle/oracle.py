@@ -80,6 +80,8 @@ def lib():
         L.or_sim_create.argtypes = [P, vp, vp, vp, vp, C.c_int64]
         L.or_sim_create.restype = vp
         L.or_sim_destroy.argtypes = [vp]
+        L.or_sim_set_gravity.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+        L.or_sim_set_gravity.restype = C.c_int
         L.or_sim_set_mrt.argtypes = [vp, C.c_double, C.c_double, C.c_double]
         L.or_sim_set_mrt.restype = C.c_int
         L.or_sim_set_bc_mode.argtypes = [vp, C.c_int]
@@ -255,6 +257,11 @@ class Sim:
             raise OracleError(f"{what}: non-finite population")
         if rc != 0:
             raise OracleError(f"{what}: error {rc}")
+
+    def set_gravity(self, g):
+        """Uniform body acceleration (2 or 3 components) added to the force of later collisions."""
+        g = list(g) + [0.0] * (3 - len(g))
+        self._check(lib().or_sim_set_gravity(self.h, *map(float, g)), "set_gravity")
 
     def set_mrt(self, se=1.64, seps=1.54, sq=1.7):
         """Multiple-relaxation-time collision (D2Q9, eqs. 1-4) for the collisions that follow, with
