@@ -103,6 +103,9 @@ typedef struct {
     int32_t reserved;       /* 0 */
     double s_e, s_eps, s_q; /* MRT rates of the energy, energy-square and heat-flux moments, each in
                                (0, 2) for MCB_COLL_MRT (the paper's: 1.64, 1.54, 1.7); ignored for BGK */
+    double gravity[3];      /* uniform body acceleration g (lattice units): the force of eq. 13 and of
+                               eqs. 16-17 becomes F_nonideal + rho g (Sec. 4.5 runs with gravity);
+                               finite; gravity[2] = 0 for dim 2; zero = no body force */
 } mcb_params;
 
 /* A solid shape. kind MCB_SHAPE_BALL: centre (cx, cy, cz) and radius; a node is solid when it
@@ -207,6 +210,12 @@ mcb_status mcb_step(mcb_ctx* ctx, int64_t n);
  * after eq. 14) of the current state. Either pointer may be NULL. Solid entries 0. */
 mcb_status mcb_moments(mcb_ctx* ctx, double* rho, double* v);
 
+/* Largest physical speed |v| over the fluid nodes of the current state (the spurious-current measure
+ * of Sec. 4.4) in *vmax, and in *node the smallest linear index of a fluid node attaining it (-1 and
+ * 0 without fluid nodes).  FP64, computed on the device, deterministic; non-finite speeds are
+ * skipped (mcb_mass counts them).  Either pointer may be NULL.  Synchronises. */
+mcb_status mcb_max_speed(mcb_ctx* ctx, double* vmax, int64_t* node);
+
 /* FP64 mass / momentum / Delta M report (deterministic two-pass reduction). */
 mcb_status mcb_mass(mcb_ctx* ctx, mcb_mass_report* out);
 
@@ -240,8 +249,8 @@ mcb_status mcb_timing_report(mcb_ctx* ctx, double* ms, int64_t* launches);
 enum { MCB_LOSS_COM_X = 0, MCB_LOSS_WETTED_LENGTH = 1, MCB_LOSS_TOTAL_MASS = 2 };
 
 /* Device bytes of the reverse-mode arena for nsteps >= 0 steps with a checkpoint every k >= 1
- * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_BC_PRESENT with MCB_COLL_BGK
- * only: the adjoint calls return MCB_ENOTSUP for the other schemes and for MRT. */
+ * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_BC_PRESENT with MCB_COLL_BGK and
+ * no body force: the adjoint calls return MCB_ENOTSUP for the other schemes, MRT and gravity. */
 mcb_status mcb_adj_required_bytes(mcb_ctx* ctx, int64_t nsteps, int64_t k, int64_t* bytes);
 
 /* Binds the caller-owned reverse-mode arena (device memory, at least the required bytes, 256-byte

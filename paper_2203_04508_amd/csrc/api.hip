@@ -154,6 +154,9 @@ bool params_ok(const mcb_params* p, const char** why) {
     if (p->bc_mode < MCB_BC_PRESENT || p->bc_mode > MCB_BC_HBBC) { *why = "unknown bc_mode"; return false; }
     if (p->precision != MCB_F64 && !(std::isfinite(p->rho_ref) && p->rho_ref >= 0.0)) { *why = "bad rho_ref"; return false; }
     if (p->collision != MCB_COLL_BGK && p->collision != MCB_COLL_MRT) { *why = "unknown collision"; return false; }
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(p->gravity[k])) { *why = "gravity must be finite"; return false; }
+    if (p->dim == 2 && p->gravity[2] != 0.0) { *why = "gravity[2] must be 0 in 2-D"; return false; }
     if (p->collision == MCB_COLL_MRT)
         for (double r : {p->s_e, p->s_eps, p->s_q})
             if (!(r > 0.0 && r < 2.0)) { *why = "MRT rates must lie in (0, 2)"; return false; }
@@ -551,6 +554,8 @@ mcb_status mcb_adj_required_bytes(mcb_ctx* c, int64_t nsteps, int64_t k, int64_t
     if (nsteps < 0 || k < 1) return fail(c, MCB_EINVAL, "need nsteps >= 0 and k >= 1");
     if (c->p.bc_mode != MCB_BC_PRESENT) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the present scheme only");
     if (c->p.collision != MCB_COLL_BGK) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the BGK collision only");
+    if (c->p.gravity[0] != 0.0 || c->p.gravity[1] != 0.0 || c->p.gravity[2] != 0.0)
+        return fail(c, MCB_ENOTSUP, "reverse mode without a body force only");
     *bytes = adj_plan(c, nsteps, k).bytes;
     return MCB_OK;
 }
@@ -573,6 +578,8 @@ mcb_status mcb_adj_forward(mcb_ctx* c, const double* rho0, int64_t nsteps, int64
     if (kind < MCB_LOSS_COM_X || kind > MCB_LOSS_TOTAL_MASS) return fail(c, MCB_EINVAL, "unknown loss");
     if (c->p.bc_mode != MCB_BC_PRESENT) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the present scheme only");
     if (c->p.collision != MCB_COLL_BGK) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the BGK collision only");
+    if (c->p.gravity[0] != 0.0 || c->p.gravity[1] != 0.0 || c->p.gravity[2] != 0.0)
+        return fail(c, MCB_ENOTSUP, "reverse mode without a body force only");
     if (kind == MCB_LOSS_WETTED_LENGTH && !(prm[1] > 0.0)) return fail(c, MCB_EINVAL, "wetted length needs delta > 0");
     const AdjPlan a = adj_plan(c, nsteps, k);
     if (!c->adj || c->adj_bytes < a.bytes) return fail(c, MCB_ESIZE, "reverse-mode arena needs %lld bytes", (long long)a.bytes);
@@ -684,6 +691,19 @@ mcb_status mcb_moments(mcb_ctx* c, double* rho, double* v) {
     if (!c) return MCB_EINVAL;
     if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
     HIPCHK(moments_out(c, fcur(c), rho, v));
+    return check_flags(c, nullptr);
+}
+
+mcb_status mcb_max_speed(mcb_ctx* c, double* vmax, int64_t* node) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
+    HIPCHK(max_speed(c, fcur(c)));
+    double r[2];
+    HIPCHK(hipMemcpyAsync(r, reinterpret_cast<double*>(c->lat + c->L.result) + MON_SPEED, sizeof r, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (vmax) *vmax = r[1] < 0.0 ? 0.0 : r[0];
+    if (node) *node = int64_t(r[1]);
     return check_flags(c, nullptr);
 }
 

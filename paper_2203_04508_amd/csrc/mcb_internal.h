@@ -33,7 +33,8 @@ constexpr int RF2 = 6, RF3 = 8;           // offset of population 1
 constexpr double NO_LINK = 2.0;           // coefficient of a direction without a link (|a| <= 1 on links)
 constexpr int SCAN_BLOCK = 256;           // geometry scan granularity
 constexpr int MON_BLOCKS = 1024;          // monitor partial sums
-constexpr int MON_FIELDS = 8;             // M, Jx, Jy, Jz, dM, n_nan, spare, spare
+constexpr int MON_FIELDS = 8;             // M, Jx, Jy, Jz, dM, n_nan, then the max-speed pair
+constexpr int MON_SPEED = 6;              // result slots of the largest speed and its node
 constexpr int MAX_BANDS = 8;
 
 // sticky device fault flags
@@ -155,6 +156,7 @@ hipError_t adj_loss(mcb_ctx* c, const AdjWork& w, const void* g, int kind, const
 // monitor.hip
 hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur);
 hipError_t moments_out(mcb_ctx* c, const void* fcur, double* rho, double* v);
+hipError_t max_speed(mcb_ctx* c, const void* fcur);  // result slots MON_SPEED, MON_SPEED + 1
 hipError_t convert_plane_in(mcb_ctx* c, const double* src, void* dst_plane, int dir);
 hipError_t convert_plane_out(mcb_ctx* c, const void* src_plane, double* dst, int dir);
 

@@ -135,7 +135,8 @@ __global__ void k_psi_out(GridDev g, int L, const int32_t* __restrict__ tag, con
 
 template <class S, class C>
 __global__ void k_vel_out(GridDev g, int L, const S* __restrict__ f, const int32_t* __restrict__ tag,
-                          const double* __restrict__ rho, const double* __restrict__ psi, double G, double* __restrict__ v) {
+                          const double* __restrict__ rho, const double* __restrict__ psi, double G, double gx, double gy,
+                          double gz, double* __restrict__ v) {
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
         if (tag[x] < 0) {
             for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = 0.0;
@@ -152,8 +153,9 @@ __global__ void k_vel_out(GridDev g, int L, const S* __restrict__ f, const int32
                 s[k] += ws * py * e[k];
             }
         }
+        const double gk[3] = {gx, gy, gz};
         for (int k = 0; k < g.dim; ++k) {
-            const double F = -G * psi[x] * s[k];
+            const double F = -G * psi[x] * s[k] + rho[x] * gk[k];
             v[k * g.N + x] = (j[k] - 0.5 * F) / rho[x];
         }
     }
@@ -203,8 +205,59 @@ hipError_t monitor_t(mcb_ctx* c, const void* fcur, const void* rcur) {
     return hipGetLastError();
 }
 
+// largest |v| over the fluid nodes and the smallest node index attaining it; fixed grid and fixed
+// combination order, so the result does not depend on timing
+__device__ inline void speed_pick(double& best, double& at, double b, double i) {
+    if (b > best || (b == best && i >= 0.0 && (at < 0.0 || i < at))) {
+        best = b;
+        at = i;
+    }
+}
+
+__device__ inline void speed_block(double& best, double& at) {
+    for (int d = 32; d >= 1; d >>= 1) speed_pick(best, at, __shfl_xor(best, d, 64), __shfl_xor(at, d, 64));
+    __shared__ double sb[4], sa[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        sb[wv] = best;
+        sa[wv] = at;
+    }
+    __syncthreads();
+    best = sb[0];
+    at = sa[0];
+    for (int w = 1; w < 4; ++w) speed_pick(best, at, sb[w], sa[w]);
+}
+
+__global__ __launch_bounds__(256) void k_speed_partial(GridDev g, const int32_t* __restrict__ tag, const double* __restrict__ v,
+                                                       double* __restrict__ part) {
+    double best = -1.0, at = -1.0;
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        if (tag[x] < 0) continue;
+        double s2 = 0.0;
+        for (int k = 0; k < g.dim; ++k) s2 += v[k * g.N + x] * v[k * g.N + x];
+        speed_pick(best, at, sqrt(s2), double(x));
+    }
+    speed_block(best, at);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = best;
+        part[2 * blockIdx.x + 1] = at;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_speed_final(const double* __restrict__ part, int nparts, double* __restrict__ out) {
+    double best = -1.0, at = -1.0;
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) speed_pick(best, at, part[2 * p], part[2 * p + 1]);
+    speed_block(best, at);
+    if (threadIdx.x == 0) {
+        out[0] = best;
+        out[1] = at;
+    }
+}
+
+// rho, psi and the physical velocity of the state into the scratch arena: rho at scratch, psi
+// after it, v (dim planes) after that
 template <class S, class C>
-hipError_t moments_t(mcb_ctx* c, const void* fcur, double* rho, double* v) {
+hipError_t moments_dev(mcb_ctx* c, const void* fcur) {
     const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
     const int L = c->g.dim == 2 ? 0 : 1;
     double* sr = reinterpret_cast<double*>(c->lat + c->L.scratch);
@@ -217,8 +270,28 @@ hipError_t moments_t(mcb_ctx* c, const void* fcur, double* rho, double* v) {
                        reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos,
                        reinterpret_cast<int32_t*>(c->lat + c->L.flags), sp);
     hipLaunchKernelGGL((k_vel_out<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, L, static_cast<const S*>(fcur),
-                       tag, sr, sp, c->p.G, sv);
-    hipError_t e = hipGetLastError();
+                       tag, sr, sp, c->p.G, c->p.gravity[0], c->p.gravity[1], c->p.gravity[2], sv);
+    return hipGetLastError();
+}
+
+template <class S, class C>
+hipError_t max_speed_t(mcb_ctx* c, const void* fcur) {
+    hipError_t e = moments_dev<S, C>(c, fcur);
+    if (e != hipSuccess) return e;
+    const double* sv = reinterpret_cast<const double*>(c->lat + c->L.scratch) + 2 * c->g.N;
+    double* part = reinterpret_cast<double*>(c->lat + c->L.partials);
+    hipLaunchKernelGGL(k_speed_partial, dim3(MON_BLOCKS), dim3(256), 0, c->stream, c->g,
+                       reinterpret_cast<const int32_t*>(c->lat + c->L.tag), sv, part);
+    hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(256), 0, c->stream, part, MON_BLOCKS,
+                       reinterpret_cast<double*>(c->lat + c->L.result) + MON_SPEED);
+    return hipGetLastError();
+}
+
+template <class S, class C>
+hipError_t moments_t(mcb_ctx* c, const void* fcur, double* rho, double* v) {
+    double* sr = reinterpret_cast<double*>(c->lat + c->L.scratch);
+    double* sv = sr + 2 * c->g.N;
+    hipError_t e = moments_dev<S, C>(c, fcur);
     if (e != hipSuccess) return e;
     if (rho) {
         e = hipMemcpyAsync(rho, sr, sizeof(double) * c->g.N, hipMemcpyDeviceToHost, c->stream);
@@ -246,6 +319,14 @@ hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur) {
         case MCB_F64: return monitor_t<double, double>(c, fcur, rcur);
         case MCB_F32S: return monitor_t<float, float>(c, fcur, rcur);
         default: return monitor_t<__half, float>(c, fcur, rcur);
+    }
+}
+
+hipError_t max_speed(mcb_ctx* c, const void* fcur) {
+    switch (c->p.precision) {
+        case MCB_F64: return max_speed_t<double, double>(c, fcur);
+        case MCB_F32S: return max_speed_t<float, float>(c, fcur);
+        default: return max_speed_t<__half, float>(c, fcur);
     }
 }
 

@@ -58,6 +58,7 @@ struct Args2 {
     C tau_inv, G, rho_ref;
     C kF, k18;                   // boundary scheme: weight of the forcing term, of eq. 18 (0 or 1)
     C s_e, s_eps, s_q;           // rates of the multiple-relaxation-time collision (eq. 3)
+    C gx, gy;                    // body acceleration: F = F_nonideal + rho g, so du = F / rho gains g
     Eos<C> eos;
 };
 
@@ -280,8 +281,8 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         const C jx = fA[1] - fA[3] + fA[5] - fA[6] - fA[7] + fA[8];
         const C jy = fA[2] - fA[4] + fA[5] + fA[6] - fA[7] - fA[8];
         const C ux = jx * irho, uy = jy * irho;
-        dux = Fx * irho;
-        duy = Fy * irho;
+        dux = Fx * irho + a.gx;
+        duy = Fy * irho + a.gy;
         const C ti = a.tau_inv, omc = C(1) - ti;
         // per direction: out_i = f_i (1 - 1/tau) + w_i [rs/tau + rho (sym_i +- anti_i)] with
         //   sym  = (4.5 (e.u)^2 - 1.5 u^2) / tau + 4.5 (e.du)(e.(2u + du)) - 1.5 du.(2u + du)
@@ -508,6 +509,8 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
     a.s_e = C(c->p.s_e);
     a.s_eps = C(c->p.s_eps);
     a.s_q = C(c->p.s_q);
+    a.gx = C(c->p.gravity[0]);
+    a.gy = C(c->p.gravity[1]);
     a.eos.RT = C(c->p.eos_R * c->p.eos_T);
     a.eos.a = C(c->p.eos_a);
     a.eos.b4 = C(c->p.eos_b / 4.0);

@@ -134,6 +134,7 @@ struct Args3 {
     int nx, ny, nz, D, ntx, nty, nblocks;
     C tau_inv, G, rho_ref;
     C kF;                        // boundary scheme: weight of the forcing term (eq. 18 always applies)
+    C gx, gy, gz;                // body acceleration: F = F_nonideal + rho g, so du = F / rho gains g
     Eos<C> eos;
 };
 
@@ -398,9 +399,9 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
                 const C jy = (fC[3] - fC[4]) + (fC[7] - fC[8]) - (fC[9] - fC[10]) + (fC[15] - fC[16]) + (fC[17] - fC[18]);
                 const C jz = (fC[5] - fC[6]) + (fC[11] - fC[12]) - (fC[13] - fC[14]) + (fC[15] - fC[16]) - (fC[17] - fC[18]);
                 const C ux = jx * irho, uy = jy * irho, uz = jz * irho;
-                dux = Fx * irho;
-                duy = Fy * irho;
-                duz = Fz * irho;
+                dux = Fx * irho + a.gx;
+                duy = Fy * irho + a.gy;
+                duz = Fz * irho + a.gz;
                 const C ti = a.tau_inv, omc = C(1) - ti;
                 // per direction: out_i = f_i (1 - 1/tau) + w_i [rs/tau + rho (sym_i +- anti_i)] with
                 //   sym  = (4.5 (e.u)^2 - 1.5 u^2) / tau + 4.5 (e.du)(e.(2u + du)) - 1.5 du.(2u + du)
@@ -552,6 +553,9 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, const void* rcur, void* f
     a.G = C(c->p.G);
     a.rho_ref = c->p.precision == MCB_F64 ? C(0) : C(c->p.rho_ref);
     a.kF = c->p.bc_mode == MCB_BC_PRESENT ? C(1) : C(0);
+    a.gx = C(c->p.gravity[0]);
+    a.gy = C(c->p.gravity[1]);
+    a.gz = C(c->p.gravity[2]);
     a.eos.RT = C(c->p.eos_R * c->p.eos_T);
     a.eos.a = C(c->p.eos_a);
     a.eos.b4 = C(c->p.eos_b / 4.0);

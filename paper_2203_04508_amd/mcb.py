@@ -33,7 +33,7 @@ class mcb_params(C.Structure):
                 ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double), ("eos_T", C.c_double),
                 ("precision", C.c_int32), ("bc_mode", C.c_int32), ("rho_ref", C.c_double),
                 ("collision", C.c_int32), ("reserved", C.c_int32),
-                ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double)]
+                ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double), ("gravity", C.c_double * 3)]
 
 
 class mcb_shape(C.Structure):
@@ -64,7 +64,7 @@ EXPORTS = [
     "mcb_create", "mcb_destroy", "mcb_last_error", "mcb_required_sizes", "mcb_bind_buffers",
     "mcb_set_geometry", "mcb_build_links", "mcb_get_links", "mcb_get_wall_nodes", "mcb_set_links",
     "mcb_set_wettability", "mcb_init_equilibrium", "mcb_set_f", "mcb_get_f", "mcb_step",
-    "mcb_moments", "mcb_mass", "mcb_sync", "mcb_timing", "mcb_timing_report",
+    "mcb_moments", "mcb_max_speed", "mcb_mass", "mcb_sync", "mcb_timing", "mcb_timing_report",
     "mcb_adj_required_bytes", "mcb_adj_bind", "mcb_adj_forward", "mcb_adj_backward",
 ]
 
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
         "mcb_get_f": ([vp, vp], i32),
         "mcb_step": ([vp, i64], i32),
         "mcb_moments": ([vp, vp, vp], i32),
+        "mcb_max_speed": ([vp, vp, vp], i32),
         "mcb_mass": ([vp, P(mcb_mass_report)], i32),
         "mcb_sync": ([vp], i32),
         "mcb_timing": ([vp, i32], i32),
@@ -222,6 +223,14 @@ def mcb_moments(ctx, dim, N):
     return rho, v
 
 
+def mcb_max_speed(ctx):
+    """(largest |v| over the fluid nodes, smallest node index attaining it)."""
+    v = C.c_double()
+    n = C.c_int64()
+    _check(ctx, load().mcb_max_speed(ctx, C.byref(v), C.byref(n)), "mcb_max_speed")
+    return v.value, n.value
+
+
 def mcb_mass(ctx) -> mcb_mass_report:
     r = mcb_mass_report()
     _check(ctx, load().mcb_mass(ctx, C.byref(r)), "mcb_mass")
@@ -283,7 +292,8 @@ class Lattice:
     """A context plus the torch tensors backing its device arenas."""
 
     def __init__(self, dim, dims, tau, T, precision="f64", rho_ref=0.0, G=-1.0, a=1.0, b=4.0, R=1.0,
-                 device="cuda:0", stream=None, bc_mode="present", collision="bgk", mrt_rates=MRT_RATES_PAPER):
+                 device="cuda:0", stream=None, bc_mode="present", collision="bgk", mrt_rates=MRT_RATES_PAPER,
+                 gravity=(0.0, 0.0, 0.0)):
         import torch
 
         self.torch = torch
@@ -292,7 +302,8 @@ class Lattice:
         self.params = mcb_params(dim, dims[0], dims[1], nz, tau, G, a, b, R, T,
                                  PRECISIONS[precision] if isinstance(precision, str) else precision,
                                  BC_MODES[bc_mode] if isinstance(bc_mode, str) else bc_mode, rho_ref,
-                                 {"bgk": MCB_COLL_BGK, "mrt": MCB_COLL_MRT}[collision], 0, *mrt_rates)
+                                 {"bgk": MCB_COLL_BGK, "mrt": MCB_COLL_MRT}[collision], 0, *mrt_rates,
+                                 (C.c_double * 3)(*(list(gravity) + [0.0] * (3 - len(gravity)))))
         self.dim = dim
         self.Q = 9 if dim == 2 else 19
         self.N = int(dims[0]) * int(dims[1]) * int(nz)
@@ -366,6 +377,9 @@ class Lattice:
 
     def mass(self):
         return mcb_mass(self.ctx)
+
+    def max_speed(self):
+        return mcb_max_speed(self.ctx)
 
     def sync(self):
         mcb_sync(self.ctx)

@@ -149,10 +149,9 @@ def run(mode, q, phi, steps, every):
         failed = {"step_before": t + n, "error": str(e)}
     out = {"mode": mode, "q": q, "t": ts, "drift": m, "dM_last": dm, "failed": failed}
     if failed is None:
-        rho, v = lat.moments()
-        fluid = rho > 0
+        rho, _ = lat.moments()
         out["theta_end"] = contact_angle(rho, yw, rv, rl)
-        out["max_speed_end"] = float(np.sqrt((v[:, fluid] ** 2).sum(0)).max())
+        out["max_speed_end"] = lat.max_speed()[0]
     lat.close()
     return out
 

@@ -45,12 +45,12 @@ def test_struct_layouts_match_header(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "mcb.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(mcb_params), sizeof(mcb_shape),"
         " sizeof(mcb_link), sizeof(mcb_sizes), sizeof(mcb_buffers), sizeof(mcb_mass_report),"
-        " offsetof(mcb_params, s_q)); return 0;}\n")
+        " offsetof(mcb_params, gravity)); return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(mcb.mcb_params), C.sizeof(mcb.mcb_shape), C.sizeof(mcb.mcb_link), C.sizeof(mcb.mcb_sizes),
-            C.sizeof(mcb.mcb_buffers), C.sizeof(mcb.mcb_mass_report), mcb.mcb_params.s_q.offset]
+            C.sizeof(mcb.mcb_buffers), C.sizeof(mcb.mcb_mass_report), mcb.mcb_params.gravity.offset]
     assert got == want
     assert mcb.LINK_DTYPE.itemsize == C.sizeof(mcb.mcb_link)
 
@@ -90,6 +90,13 @@ def test_host_side_argument_checks(lib):
         bad = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, 0, 0.0, mcb.MCB_COLL_MRT, 0,
                              *mcb.MRT_RATES_PAPER)
         setattr(bad, k, v)
+        with pytest.raises(mcb.MCBError) as ei:
+            mcb.mcb_create(bad)
+        assert ei.value.code == mcb.MCB_EINVAL
+    # gravity: finite, no z component in 2-D
+    for gz in ((0.0, 0.0, 1e-5), (float("nan"), 0.0, 0.0)):
+        bad = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, 0, 0.0)
+        bad.gravity[:] = gz
         with pytest.raises(mcb.MCBError) as ei:
             mcb.mcb_create(bad)
         assert ei.value.code == mcb.MCB_EINVAL

@@ -1,0 +1,170 @@
+"""GPU parity of the body force (F = F_nonideal + rho g, Sec. 4.5 of arXiv 2203.04508 runs with
+gravity) and of the largest-speed monitor (the spurious-current measure of Sec. 4.4) against the
+FP64 oracle, through the C ABI.
+
+Bars: FP64 populations within 1e-12 relative per step; the gravity-driven channel within 1% of
+the analytic parabola and within 1e-9 of the oracle after 12000 steps; the largest speed within
+1e-12 relative (FP64, same node) or 2e-3 (shifted FP32) of the oracle's velocity field, and equal
+to the largest speed of the GPU's own velocity output.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2203_04508_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TC = W.CS_TC
+
+
+def banner(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mcb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_04508_amd import mcb as m
+    m.load()
+    return m
+
+
+def rel_err(a, b, fluid):
+    worst = 0.0
+    for i in range(a.shape[0]):
+        d = np.abs(a[i, fluid] - b[i, fluid]).max()
+        s = np.abs(b[i, fluid]).max()
+        worst = max(worst, d / s)
+    return worst
+
+
+def build_pair(mcb, dim, dims, tau, T, shapes, phi, g, q_override=None, precision="f64", rho_ref=0.0, collision="bgk"):
+    P = oracle.make_params(dim, *dims, tau=tau, T=T)
+    solid = oracle.classify(P, shapes)
+    node, d, cls, q = oracle.links(P, shapes, solid)
+    lat = mcb.Lattice(dim, dims, tau, T, precision=precision, rho_ref=rho_ref, collision=collision, gravity=g)
+    nl, nb, nw = lat.set_geometry(shapes)
+    assert nl == len(node)
+    if q_override is not None:
+        q = q_override(q).astype(np.uint32)
+        got = lat.links()
+        got["q_fixed"] = q
+        lat.set_links(got)
+    sim = oracle.Sim(P, solid, node, d, q)
+    sim.set_gravity(g)
+    if collision == "mrt":
+        sim.set_mrt()
+    phi = np.broadcast_to(np.asarray(phi, np.float64), (nw,)).copy()
+    sim.set_phi(phi)
+    lat.set_wettability(phi)
+    return sim, lat, solid == 0
+
+
+def random_state(rng, rho_field, dim):
+    N = len(rho_field)
+    u = rng.uniform(-0.02, 0.02, (N, dim))
+    f = np.stack([oracle.equilibrium(dim, rho_field[x], u[x]) for x in range(N)], axis=1)
+    return f * (1.0 + 0.01 * rng.standard_normal(f.shape))
+
+
+def oracle_max_speed(sim, fluid):
+    _, v, _ = sim.moments()
+    s = np.sqrt((v ** 2).sum(0))
+    s[~fluid] = -1.0
+    return s.max(), int(np.argmax(s))
+
+
+CASES = [("2d-37x29-random-q", 2, (37, 29, 1), (3e-5, -5e-5), "bgk"),
+         ("2d-300x70-mrt", 2, (300, 70, 1), (0.0, -4e-5), "mrt"),
+         ("3d-31x27x19-random-q", 3, (31, 27, 19), (1e-5, -3e-5, 2e-5), "bgk")]
+
+
+@pytest.mark.parametrize("name,dim,dims,g,coll", CASES, ids=[c[0] for c in CASES])
+def test_gravity_step_parity_and_max_speed(mcb, name, dim, dims, g, coll):
+    banner(f"gravity parity {name}")
+    rng = np.random.default_rng(51 + dim)
+    nballs = max(3, int(np.prod(dims)) // (900 if dim == 2 else 2500))
+    shapes = W.random_links_case(rng, dims, dim, nballs, 2.0 if dim == 2 else 1.5, 6.0 if dim == 2 else 4.5)
+    rv, rl = W.MAXWELL[0.7]
+    drops = [(tuple(rng.uniform(0, n) for n in dims[:dim]), rng.uniform(3, 6)) for _ in range(3)]
+    rho = W.drop_field(dims, dim, drops, rv, rl, 2.0 if dim == 2 else 4.0)
+    qo = lambda q: rng.integers(0, 65537, len(q))
+    sim, lat, fluid = build_pair(mcb, dim, dims, 0.8, 0.7 * TC, shapes, rng.uniform(0.85, 1.15), g, qo, collision=coll)
+    f0 = random_state(rng, rho, dim)
+    sim.set_f(f0)
+    lat.set_f(f0)
+    for k in range(1, 11):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < 1e-12 * k, (k, e)
+    vo, no = oracle_max_speed(sim, fluid)
+    vg, ng = lat.max_speed()
+    assert abs(vg - vo) <= 1e-12 * vo and ng == no, (vg, vo, ng, no)
+    lat.close()
+
+
+def test_gravity_driven_channel_on_gpu(mcb):
+    """Walls at y = 1.3 (q = 0.7) and 22.2 (q = 0.2), uniform liquid, g along x, tau = 0.8."""
+    banner("gravity-driven channel, 12000 steps")
+    nx, ny, ylo, yhi, g, tau = 4, 32, 1.3, 22.2, 1e-6, 0.8
+    shapes = np.array([W.band_y(yhi, ny + ylo, 0)], np.int64)
+    sim, lat, fluid = build_pair(mcb, 2, (nx, ny, 1), tau, 0.7 * TC, shapes, 1.0, (g, 0.0))
+    rho0 = np.full(nx * ny, W.MAXWELL[0.70][1])
+    sim.init_eq(rho0)
+    lat.init_equilibrium(rho0)
+    sim.step(12000)
+    lat.step(12000)
+    assert rel_err(lat.get_f(), sim.get_f(), fluid) < 1e-9
+    _, v = lat.moments()
+    rows = np.arange(2, 23)
+    y = np.arange(ny)
+    want = g / (2 * (tau - 0.5) / 3) * (y - ylo) * (yhi - y)
+    ux = v[0].reshape(ny, nx)[:, 0]
+    assert np.abs(ux[rows] - want[rows]).max() / want[rows].max() < 1e-2
+    vmax, node = lat.max_speed()
+    assert abs(vmax - np.abs(v[0]).max()) <= 1e-15 + 1e-12 * vmax
+    lat.close()
+
+
+def test_max_speed_c1_fp32(mcb):
+    banner("largest speed c1, shifted FP32, 200 steps")
+    wl = W.make("c1")
+    P = oracle.make_params(2, *wl.dims, tau=wl.tau, T=wl.T)
+    solid = oracle.classify(P, wl.shapes)
+    phi = W.phi_for_walls(wl, oracle.wall_nodes(P, solid))
+    sim, lat, fluid = build_pair(mcb, 2, wl.dims, wl.tau, wl.T, wl.shapes, phi, (0.0, 0.0), precision="f32s",
+                                 rho_ref=wl.rho_v)
+    rho0 = wl.rho0()
+    sim.init_eq(rho0)
+    lat.init_equilibrium(rho0)
+    sim.step(200)
+    lat.step(200)
+    vo, no = oracle_max_speed(sim, fluid)
+    vg, ng = lat.max_speed()
+    # FP32 storage moves the velocity field (a small difference of populations) by ~1e-4 relative
+    assert abs(vg - vo) <= 2e-3 * vo, (vg, vo)
+    # and the reduction agrees exactly with the GPU's own velocity field
+    _, v = lat.moments()
+    s = np.sqrt((v ** 2).sum(0))
+    s[~fluid] = -1.0
+    assert vg == s.max() and ng == int(np.argmax(s))
+    lat.close()
+
+
+def test_gravity_reverse_mode_unsupported(mcb):
+    banner("reverse mode with gravity: MCB_ENOTSUP")
+    wl = W.make("c0")
+    lat = mcb.Lattice(2, wl.dims, wl.tau, wl.T, gravity=(0.0, -1e-5))
+    lat.set_geometry(wl.shapes)
+    lat.set_wettability(1.0)
+    with pytest.raises(mcb.MCBError) as ei:
+        lat.adj_forward(wl.rho0(), 10, 5)
+    assert ei.value.code == -7
+    lat.close()
