@@ -21,6 +21,10 @@
 //                      Sec. 1): psi = sqrt(2 (p_EOS - rho c_s^2) / G), F = -G psi(x) sum_i w^_i psi(x+e_i) e_i,
 //                      Carnahan-Starling p_EOS
 //   wall density       eq. 15 restricted to the first solid layer, times a wettability factor phi
+//   chemical-potential model (2-D, the paper's own, Sec. 2.2-2.3): Peng-Robinson EOS (eq. 10),
+//                      mu = k^2 mu_PR(rho) - kappa lap(rho) (eqs. 11-12), F = -rho grad mu + grad rho / 3
+//                      (eq. 9) with fourth-order central differences, densities on two solid layers
+//                      by eq. 15 and an assigned chemical potential on them (the wettability)
 //   curved boundary    eq. 16 (0 <= q < 1/2), eq. 17 (1/2 <= q <= 1)       (Sec. 3.1)
 //   mass modification  eq. 18                                              (Sec. 3.2)
 //   comparison schemes the paper measures the present one against (Secs. 1, 4): linear
@@ -36,6 +40,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <type_traits>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -164,6 +169,77 @@ void equilibrium(const Lat& L, R rho, const R u[3], R out[]) {
         R eu = u[0] * double(L.e[i][0]) + u[1] * double(L.e[i][1]) + u[2] * double(L.e[i][2]);
         out[i] = L.w[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
     }
+}
+
+// ---- Peng-Robinson equation of state and its chemical potential (eqs. 10-11)
+struct PR {
+    double a = 2.0 / 49.0, b = 2.0 / 21.0, R = 1.0, T = 0.0, omega = 0.344;
+    double alpha = 1.0;  // alpha(T), set by pr_set
+};
+
+// critical temperature of eq. 10 (the inflection point of p(rho) with zero slope, alpha = 1):
+// T_c = (0.0778 / 0.45724) a / (b R) to the precision of the classical constants; here solved
+// exactly from the two conditions (bisection on b rho_c in (0, 1), then T_c from p' = 0)
+inline double pr_p_dimless(double x, double t) {  // p b^2 / a at b rho = x, reduced R T b / a = t
+    return t * x / (1.0 - x) - x * x / (1.0 + 2.0 * x - x * x);
+}
+inline void pr_critical(double a, double b, double R, double* Tc, double* rhoc) {
+    // t(x) with dp/dx = 0, then the x where d2p/dx2 = 0 along that curve (numerical derivatives
+    // of the closed form, bisection on the sign of the second derivative)
+    auto t_of = [](double x) {
+        // dp/dx = t / (1 - x)^2 - (2x (1 + 2x - x^2) - x^2 (2 - 2x)) / (1 + 2x - x^2)^2 = 0
+        const double d = 1.0 + 2.0 * x - x * x;
+        return (1.0 - x) * (1.0 - x) * (2.0 * x * d - x * x * (2.0 - 2.0 * x)) / (d * d);
+    };
+    auto d2 = [&](double x) {
+        const double t = t_of(x), h = 1e-4;
+        return pr_p_dimless(x + h, t) - 2.0 * pr_p_dimless(x, t) + pr_p_dimless(x - h, t);
+    };
+    double lo = 0.05, hi = 0.6;
+    for (int it = 0; it < 200; ++it) {
+        const double m = 0.5 * (lo + hi);
+        if ((d2(lo) > 0) == (d2(m) > 0)) lo = m; else hi = m;
+    }
+    const double x = 0.5 * (lo + hi);
+    *rhoc = x / b;
+    *Tc = t_of(x) * a / (b * R);
+}
+
+inline void pr_set(PR& E) {
+    double Tc, rc;
+    pr_critical(E.a, E.b, E.R, &Tc, &rc);
+    const double m = 0.37464 + 1.54226 * E.omega - 0.26992 * E.omega * E.omega;
+    const double s = 1.0 + m * (1.0 - std::sqrt(E.T / Tc));
+    E.alpha = s * s;
+}
+
+inline double pr_p(const PR& E, double r) {  // eq. 10
+    const double br = E.b * r;
+    return r * E.R * E.T / (1.0 - br) - E.a * E.alpha * r * r / (1.0 + 2.0 * br - br * br);
+}
+
+// eq. 11 without the gradient term; false outside 0 < rho < 1/b
+inline bool pr_mu(const PR& E, double r, double* mu) {
+    const double br = E.b * r;
+    if (!(r > 0.0) || !(br < 1.0)) return false;
+    const double s2 = std::sqrt(2.0), aa = E.a * E.alpha;
+    *mu = E.R * E.T * std::log(r / (1.0 - br)) - aa / (2.0 * s2 * E.b) * std::log((s2 - 1.0 + br) / (s2 + 1.0 - br)) +
+          E.R * E.T / (1.0 - br) - aa * r / (1.0 + 2.0 * br - br * br);
+    return true;
+}
+
+// the chemical-potential model's settings (Sec. 2.2, eq. 12): mesh scaling k, gradient coefficient
+struct ChemPot {
+    bool on = false;
+    PR eos;
+    double k = 1.0, kappa = 0.0;
+};
+
+// fourth-order central differences along an axis: derivative and second derivative from the values
+// at offsets -2 .. +2
+inline double d1_4(double m2, double m1, double p1, double p2) { return (8.0 * (p1 - m1) - (p2 - m2)) / 12.0; }
+inline double d2_4(double m2, double m1, double c, double p1, double p2) {
+    return (16.0 * (p1 + m1) - (p2 + m2) - 30.0 * c) / 12.0;
 }
 
 // eq. 2: D2Q9 moment matrix; rows rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy, columns the
@@ -391,6 +467,10 @@ struct Sim {
     int bc_mode = 0;  // 0 present scheme, 1 IBC, 2 MIBC, 3 halfway bounce-back
     Mrt mrt;          // multiple-relaxation-time collision (2-D) when mrt.on
     double grav[3] = {0.0, 0.0, 0.0};  // body acceleration
+    ChemPot cp;                         // chemical-potential model when cp.on (2-D)
+    std::vector<int8_t> layer;          // solid layer of each node: 0 fluid, 1, 2 (eq. 15), 3 deeper
+    std::vector<double> mu_s;           // assigned chemical potential per first-layer wall node
+    std::vector<R> mu;                  // chemical potential field (fluid nodes and solid layers 1-2)
 
     explicit Sim(const or_params& p) : P(p), L(make_lat(p.dim)), g(p) {}
 
@@ -416,6 +496,13 @@ struct Sim {
             }
             rho[x] = r;
             for (int k = 0; k < 3; ++k) u[k * N + x] = j[k] / r;
+        }
+        if constexpr (std::is_same<R, double>::value) {
+            if (cp.on) {
+                chempot_force();
+                collide_with_force(fpre);
+                return;
+            }
         }
         // S2 + S3: pseudopotential on fluid nodes; wall nodes take psi of their virtual density
         int64_t bad = 0;
@@ -466,6 +553,99 @@ struct Sim {
             for (int i = 0; i < Q; ++i) {
                 R f = fpre[i * N + x];
                 ft[i * N + x] = f - (f - feq[i]) / P.tau + Fi[i];
+            }
+        }
+    }
+
+    // S5 - S6 with the force F(x, t) already in F: exact-difference forcing term and collision
+    void collide_with_force(const std::vector<R>& fpre) {
+        const int64_t N = g.N;
+        const int Q = L.Q;
+#pragma omp parallel for schedule(static)
+        for (int64_t x = 0; x < N; ++x) {
+            if (!fluid(x)) continue;
+            R Fx[3], ux[3];
+            for (int k = 0; k < 3; ++k) { Fx[k] = F[k * N + x]; ux[k] = u[k * N + x]; }
+            R feq[MAXQ], Fi[MAXQ];
+            edm_terms(L, rho[x], ux, Fx, Fi);
+            if (mrt.on) {
+                R f[9], o[9];
+                for (int i = 0; i < 9; ++i) f[i] = fpre[i * N + x];
+                mrt_relax(mrt, f, o);
+                for (int i = 0; i < 9; ++i) ft[i * N + x] = o[i] + Fi[i];
+                continue;
+            }
+            equilibrium(L, rho[x], ux, feq);
+            for (int i = 0; i < Q; ++i) {
+                R f = fpre[i * N + x];
+                ft[i * N + x] = f - (f - feq[i]) / P.tau + Fi[i];
+            }
+        }
+    }
+
+    // value of field v at x + m e_k (axis k)
+    R at_axis(const std::vector<R>& v, int64_t x, int k, int m) const {
+        int d[3] = {0, 0, 0};
+        d[k] = m;
+        return v[g.shift(x, d, +1)];
+    }
+
+    // Secs. 2.2-2.3: densities on the two solid layers (eq. 15), the chemical potential (eq. 12) on
+    // fluid nodes and the assigned one on the layers, the nonideal force (eq. 9) with fourth-order
+    // central differences, plus the body force
+    void chempot_force() {
+        const int64_t N = g.N;
+        const int Q = L.Q;
+        for (int lay = 1; lay <= 2; ++lay) {
+#pragma omp parallel for schedule(static)
+            for (int64_t x = 0; x < N; ++x) {
+                if (layer[x] != lay) continue;
+                R num = 0.0;
+                double den = 0.0;
+                for (int i = 1; i < Q; ++i) {
+                    const int64_t y = g.shift(x, L.e[i], +1);
+                    if (layer[y] == lay - 1) { num += L.w[i] * rho[y]; den += L.w[i]; }
+                }
+                rho[x] = num / den;
+            }
+        }
+        const double k2 = cp.k * cp.k;
+        int64_t bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+        for (int64_t x = 0; x < N; ++x) {
+            if (layer[x] == 0) {
+                double m0 = 0.0;
+                if (!pr_mu(cp.eos, rho[x], &m0)) ++bad;
+                R lap = 0.0;
+                for (int k = 0; k < g.dim; ++k)
+                    lap += d2_4(at_axis(rho, x, k, -2), at_axis(rho, x, k, -1), rho[x], at_axis(rho, x, k, 1), at_axis(rho, x, k, 2));
+                mu[x] = k2 * m0 - cp.kappa * lap;
+            } else if (layer[x] == 1) {
+                mu[x] = mu_s[wall_of[x]];
+            } else if (layer[x] == 2) {
+                // the assigned potential of the first-layer neighbours, weighted as in eq. 15
+                double num = 0.0, den = 0.0;
+                for (int i = 1; i < Q; ++i) {
+                    const int64_t y = g.shift(x, L.e[i], +1);
+                    if (layer[y] == 1) { num += L.w[i] * mu_s[wall_of[y]]; den += L.w[i]; }
+                }
+                mu[x] = num / den;
+            } else {
+                mu[x] = 0.0;
+            }
+        }
+        n_domain += bad;
+#pragma omp parallel for schedule(static)
+        for (int64_t x = 0; x < N; ++x) {
+            if (!fluid(x)) continue;
+            for (int k = 0; k < 3; ++k) {
+                R Fk = rho[x] * grav[k];
+                if (k < g.dim) {
+                    const R gm = d1_4(at_axis(mu, x, k, -2), at_axis(mu, x, k, -1), at_axis(mu, x, k, 1), at_axis(mu, x, k, 2));
+                    const R gr = d1_4(at_axis(rho, x, k, -2), at_axis(rho, x, k, -1), at_axis(rho, x, k, 1), at_axis(rho, x, k, 2));
+                    Fk += -rho[x] * gm + gr / 3.0;
+                }
+                F[k * N + x] = Fk;
             }
         }
     }
@@ -566,6 +746,16 @@ int build_sim(Sim<R>* S, const uint8_t* solid, const int64_t* lk_node, const int
             if (S->fluid(g.shift(x, L.e[i], +1))) { S->wall_of[x] = int64_t(S->wall_nodes.size()); S->wall_nodes.push_back(x); break; }
     }
     S->phi.assign(S->wall_nodes.size(), R(1.0));
+    // solid layers for eq. 15: 1 = a fluid neighbour, 2 = a layer-1 neighbour, 3 = deeper
+    S->layer.assign(N, 0);
+    for (int64_t x = 0; x < N; ++x) if (!S->fluid(x)) S->layer[x] = S->wall_of[x] >= 0 ? 1 : 3;
+    for (int64_t x = 0; x < N; ++x) {
+        if (S->layer[x] != 3) continue;
+        for (int i = 1; i < L.Q; ++i)
+            if (S->layer[g.shift(x, L.e[i], +1)] == 1) { S->layer[x] = 2; break; }
+    }
+    S->mu_s.assign(S->wall_nodes.size(), 0.0);
+    S->mu.assign(N, R(0.0));
     S->ft.assign(size_t(L.Q) * N, R(0.0));
     S->fn.assign(size_t(L.Q) * N, R(0.0));
     S->rho.assign(N, R(0.0));
@@ -808,6 +998,63 @@ int or_sim_set_mrt(void* h, double se, double seps, double sq) {
     S->mrt.on = true;
     return 0;
 }
+
+// the chemical-potential model (2-D) for later collisions: PR parameters a, b, R, temperature T,
+// acentric factor omega, mesh scaling k and gradient coefficient kappa (eqs. 9-12)
+int or_sim_set_chempot(void* h, double a, double b, double R, double T, double omega, double k, double kappa) {
+    auto* S = static_cast<Sim<double>*>(h);
+    if (S->L.dim != 2) return -1;
+    if (!(a > 0.0 && b > 0.0 && R > 0.0 && T > 0.0 && k > 0.0 && kappa >= 0.0) || !std::isfinite(omega)) return -1;
+    S->cp.eos.a = a;
+    S->cp.eos.b = b;
+    S->cp.eos.R = R;
+    S->cp.eos.T = T;
+    S->cp.eos.omega = omega;
+    pr_set(S->cp.eos);
+    S->cp.k = k;
+    S->cp.kappa = kappa;
+    S->cp.on = true;
+    return 0;
+}
+
+// assigned chemical potential of each first-layer wall node (the wettability, Sec. 2.3)
+int or_sim_set_mu_wall(void* h, const double* mu_s) {
+    auto* S = static_cast<Sim<double>*>(h);
+    for (size_t w = 0; w < S->mu_s.size(); ++w) {
+        if (!std::isfinite(mu_s[w])) return -1;
+        S->mu_s[w] = mu_s[w];
+    }
+    return 0;
+}
+
+// density and chemical potential of every node as the last collision saw them (fluid nodes and
+// the two solid layers; deeper solid nodes 0), chemical-potential model only
+int or_sim_cp_fields(void* h, double* rho, double* mu) {
+    auto* S = static_cast<Sim<double>*>(h);
+    if (!S->cp.on) return -1;
+    for (int64_t x = 0; x < S->g.N; ++x) {
+        rho[x] = S->layer[x] <= 2 ? S->rho[x] : 0.0;
+        mu[x] = S->layer[x] <= 2 ? S->mu[x] : 0.0;
+    }
+    return 0;
+}
+
+// eqs. 10-11 and the critical point of eq. 10, for tests
+double or_pr_p(double a, double b, double R, double T, double omega, double rho) {
+    PR E;
+    E.a = a; E.b = b; E.R = R; E.T = T; E.omega = omega;
+    pr_set(E);
+    return pr_p(E, rho);
+}
+double or_pr_mu(double a, double b, double R, double T, double omega, double rho) {
+    PR E;
+    E.a = a; E.b = b; E.R = R; E.T = T; E.omega = omega;
+    pr_set(E);
+    double m = std::nan("");
+    pr_mu(E, rho, &m);
+    return m;
+}
+void or_pr_critical(double a, double b, double R, double* Tc, double* rhoc) { pr_critical(a, b, R, Tc, rhoc); }
 
 // uniform body acceleration for later collisions (components beyond the lattice's dimension are 0)
 int or_sim_set_gravity(void* h, double gx, double gy, double gz) {

@@ -80,6 +80,18 @@ def lib():
         L.or_sim_create.argtypes = [P, vp, vp, vp, vp, C.c_int64]
         L.or_sim_create.restype = vp
         L.or_sim_destroy.argtypes = [vp]
+        L.or_sim_set_chempot.argtypes = [vp] + [C.c_double] * 7
+        L.or_sim_set_chempot.restype = C.c_int
+        L.or_sim_set_mu_wall.argtypes = [vp, vp]
+        L.or_sim_set_mu_wall.restype = C.c_int
+        L.or_sim_cp_fields.argtypes = [vp, vp, vp]
+        L.or_sim_cp_fields.restype = C.c_int
+        L.or_pr_p.argtypes = [C.c_double] * 6
+        L.or_pr_p.restype = C.c_double
+        L.or_pr_mu.argtypes = [C.c_double] * 6
+        L.or_pr_mu.restype = C.c_double
+        L.or_pr_critical.argtypes = [C.c_double] * 3 + [vp, vp]
+        L.or_pr_critical.restype = None
         L.or_sim_set_gravity.argtypes = [vp, C.c_double, C.c_double, C.c_double]
         L.or_sim_set_gravity.restype = C.c_int
         L.or_sim_set_mrt.argtypes = [vp, C.c_double, C.c_double, C.c_double]
@@ -175,6 +187,25 @@ def psi(params: Params, rho: float) -> float:
     return lib().or_psi(C.byref(params), float(rho))
 
 
+PR_PAPER = dict(a=2.0 / 49.0, b=2.0 / 21.0, R=1.0, omega=0.344)
+
+
+def pr_p(rho, T, a=2.0 / 49.0, b=2.0 / 21.0, R=1.0, omega=0.344) -> float:
+    """eq. 10 with alpha(T) of Sec. 2.2"""
+    return lib().or_pr_p(a, b, R, T, omega, rho)
+
+
+def pr_mu(rho, T, a=2.0 / 49.0, b=2.0 / 21.0, R=1.0, omega=0.344) -> float:
+    """eq. 11 without the gradient term (nan outside 0 < rho < 1/b)"""
+    return lib().or_pr_mu(a, b, R, T, omega, rho)
+
+
+def pr_critical(a=2.0 / 49.0, b=2.0 / 21.0, R=1.0):
+    Tc, rc = C.c_double(), C.c_double()
+    lib().or_pr_critical(a, b, R, C.byref(Tc), C.byref(rc))
+    return Tc.value, rc.value
+
+
 def curved_bc(q, x2_fluid, ft_i_x1, ft_i_x2, ft_ibar_x1, F_i) -> float:
     return lib().or_curved_bc(float(q), int(bool(x2_fluid)), float(ft_i_x1), float(ft_i_x2),
                               float(ft_ibar_x1), float(F_i))
@@ -257,6 +288,22 @@ class Sim:
             raise OracleError(f"{what}: non-finite population")
         if rc != 0:
             raise OracleError(f"{what}: error {rc}")
+
+    def set_chempot(self, T, k=1.0, kappa=0.0, a=2.0 / 49.0, b=2.0 / 21.0, R=1.0, omega=0.344):
+        """The chemical-potential model (2-D, eqs. 9-12) with the Peng-Robinson EOS for the collisions
+        that follow; defaults are the paper's a, b, R and the acentric factor of water."""
+        self._check(lib().or_sim_set_chempot(self.h, a, b, R, T, omega, k, kappa), "set_chempot")
+
+    def set_mu_wall(self, mu_s):
+        """Assigned chemical potential per first-layer wall node (the wettability, Sec. 2.3)."""
+        mu_s = np.ascontiguousarray(np.broadcast_to(np.asarray(mu_s, np.float64), (self.n_wall,)))
+        self._check(lib().or_sim_set_mu_wall(self.h, _p(mu_s)), "set_mu_wall")
+
+    def cp_fields(self):
+        """(rho, mu) on fluid nodes and the two solid layers as the last collision used them."""
+        rho, mu = np.zeros(self.N), np.zeros(self.N)
+        self._check(lib().or_sim_cp_fields(self.h, _p(rho), _p(mu)), "cp_fields")
+        return rho, mu
 
     def set_gravity(self, g):
         """Uniform body acceleration (2 or 3 components) added to the force of later collisions."""

@@ -1,0 +1,139 @@
+"""Pins of the oracle's chemical-potential multiphase model (Secs. 2.2-2.3 of arXiv 2203.04508):
+the Peng-Robinson EOS (eq. 10) and its chemical potential (eq. 11) against thermodynamics computed
+independently from the pressure alone; the nonideal force (eqs. 9, 12) against its closed form on
+a smooth density wave; the two-layer wall densities (eq. 15) and assigned chemical potential; a
+flat interface coexisting at the Maxwell densities (the model's thermodynamic consistency); mass
+conservation with curved walls (eq. 18)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle, thermo
+from paper_2203_04508_amd import workloads as W
+
+RC, TC = thermo.critical_point_pr()
+CP = dict(k=0.2, kappa=0.01)  # mesh scaling and gradient coefficient of the tests
+
+
+def test_critical_point_of_eq10():
+    Tc, rc = oracle.pr_critical()
+    assert abs(Tc / TC - 1) < 1e-9 and abs(rc / RC - 1) < 1e-7
+    # the classical Peng-Robinson constants: b rho_c = 0.25308, Z_c = 0.30740
+    assert abs(thermo.PR_B * RC - 0.253077) < 2e-6
+    assert abs(1.0 / (RC * TC) * thermo.p_pr(RC, TC) - 0.307401) < 2e-6
+
+
+@pytest.mark.parametrize("Tr", [0.9, 0.8, 0.7, 0.6])
+def test_eq11_equal_at_maxwell_coexistence(Tr):
+    """Equal-area coexistence from eq. 10 alone gives equal eq. 11 potentials."""
+    T = Tr * TC
+    rv, rl = thermo.maxwell_pr(T)
+    mu_v, mu_l = oracle.pr_mu(rv, T), oracle.pr_mu(rl, T)
+    assert abs(mu_v - mu_l) < 1e-12 * max(1.0, abs(mu_l))
+    assert abs(oracle.pr_p(rv, T) - thermo.p_pr(rv, T)) < 1e-15
+
+
+@pytest.mark.parametrize("rho", [0.05, 0.4, 2.6, 6.0, 9.5])
+def test_eq7_identity_dp_equals_rho_dmu(rho):
+    """p = rho psi' - psi with psi' = mu (eqs. 7-8) implies dp/drho = rho dmu/drho."""
+    T = 0.75 * TC
+    h = 1e-5 * rho
+    dp = (thermo.p_pr(rho + h, T) - thermo.p_pr(rho - h, T)) / (2 * h)
+    dmu = (oracle.pr_mu(rho + h, T) - oracle.pr_mu(rho - h, T)) / (2 * h)
+    assert abs(dp - rho * dmu) < 1e-7 * max(abs(dp), 1e-3)
+
+
+def _periodic(nx, ny, T, **cp):
+    P = oracle.make_params(2, nx, ny, 1, tau=1.0, T=0.05)
+    e0 = np.zeros(0, np.int64)
+    sim = oracle.Sim(P, np.zeros(nx * ny, np.uint8), e0, e0.astype(np.int32), e0.astype(np.uint32))
+    sim.set_chempot(T, **cp)
+    return sim
+
+
+def test_force_on_a_density_wave_matches_closed_form():
+    """rho = r0 + A sin(q x): mu' = k^2 p'(rho)/rho rho' - kappa rho''' (eq. 12 with eq. 7), so
+    F_x = -k^2 p'(rho) rho' + kappa rho rho''' + rho'/3 (eq. 9); the fourth-order differences agree
+    to O((q dx)^4)."""
+    L, r0, A = 64, 2.0, 0.2
+    T = 0.8 * TC
+    k, kappa = 0.6, 0.3
+    sim = _periodic(L, 4, T, k=k, kappa=kappa)
+    x = np.tile(np.arange(L), 4)
+    q = 2 * math.pi / L
+    rho = r0 + A * np.sin(q * x)
+    sim.init_eq(rho)
+    _, _, F = sim.moments()
+    h = 1e-6
+    dp = (np.array([thermo.p_pr(r + h, T) for r in rho]) - np.array([thermo.p_pr(r - h, T) for r in rho])) / (2 * h)
+    r1, r3 = A * q * np.cos(q * x), -A * q**3 * np.cos(q * x)
+    want = -k * k * dp * r1 + kappa * rho * r3 + r1 / 3.0
+    assert np.abs(F[0] - want).max() < 2e-3 * np.abs(want).max()
+    assert np.abs(F[1]).max() < 1e-15
+
+
+def test_uniform_density_has_no_force():
+    sim = _periodic(16, 12, 0.8 * TC, **CP)
+    sim.init_eq(np.full(16 * 12, 3.0))
+    _, _, F = sim.moments()
+    assert np.abs(F).max() == 0.0
+
+
+def test_wall_layers_eq15_and_assigned_potential():
+    """Flat substrate (solid rows 0-9 of the band up to 9.7): layer 1 is row 9, layer 2 row 8;
+    layer 1 = (4 rho(x) + rho(x-1) + rho(x+1))/6 of the first fluid row (eq. 15 weights), layer 2
+    the same of layer 1; both carry the assigned chemical potential."""
+    nx, ny = 24, 30
+    T = 0.8 * TC
+    P = oracle.make_params(2, nx, ny, 1, tau=1.0, T=0.05)
+    shapes = np.array([W.band_y(-0.5, 9.7, 0)], np.int64)
+    sim, (solid, *_r) = oracle.sim_from_shapes(P, shapes)
+    sim.set_chempot(T, **CP)
+    sim.set_mu_wall(-0.0123)
+    rng = np.random.default_rng(5)
+    rho0 = rng.uniform(0.5, 3.0, nx * ny)
+    sim.init_eq(rho0)
+    rho, mu = sim.cp_fields()
+    g, m = rho.reshape(ny, nx), mu.reshape(ny, nx)
+    avg = lambda row: (4 * row + np.roll(row, 1) + np.roll(row, -1)) / 6.0
+    assert np.allclose(g[9], avg(g[10]), rtol=1e-14, atol=0)
+    assert np.allclose(g[8], avg(g[9]), rtol=1e-14, atol=0)
+    # rows 0-1 are the band's underside (row 0 touches fluid row 29 through the periodic wrap)
+    assert np.allclose(g[0], avg(g[-1]), rtol=1e-14, atol=0)
+    assert np.all(g[2:8] == 0.0) and np.all(m[2:8] == 0.0)
+    assert np.all(m[8:10] == -0.0123) and np.all(m[0:2] == -0.0123)
+
+
+def test_flat_interface_coexists_at_maxwell_densities():
+    """A liquid slab at T_r = 0.8 relaxes to the Maxwell densities of eq. 10 (liquid within 0.1%,
+    vapour within 1%): the model is thermodynamically consistent, unlike the pseudopotential."""
+    Tr, ny, nx = 0.8, 200, 4
+    rv, rl = thermo.maxwell_pr(Tr * TC)
+    sim = _periodic(nx, ny, Tr * TC, **CP)
+    y = np.repeat(np.arange(ny), nx)
+    sim.init_eq(0.5 * (rl + rv) - 0.5 * (rl - rv) * np.tanh(2 * (np.abs(y - ny / 2) - ny / 4) / 6.0))
+    sim.step(30000)
+    rho, v, _ = sim.moments()
+    g = rho.reshape(ny, nx)[:, 0]
+    assert abs(g[ny // 2] / rl - 1) < 1e-3
+    assert abs(g[2] / rv - 1) < 1e-2
+    assert np.abs(v).max() < 1e-4
+
+
+def test_mass_conserved_with_curved_walls():
+    """c0's cylinder with a drop at T_r = 0.8, a wetting potential on the wall: eq. 18 keeps the
+    mass to rounding."""
+    wl = W.make("c0")
+    Tr = 0.8
+    rv, rl = thermo.maxwell_pr(Tr * TC)
+    P = oracle.make_params(2, *wl.dims, tau=1.0, T=0.05)
+    sim, (solid, *_r) = oracle.sim_from_shapes(P, wl.shapes)
+    sim.set_chempot(Tr * TC, **CP)
+    sim.set_mu_wall(0.0)
+    rho0 = W.drop_field(wl.dims, 2, wl.drops, rv, rl, 6.0)
+    sim.init_eq(rho0)
+    M0 = sim.mass()
+    dm = sim.step(1000, record_dm=True)
+    assert abs(sim.mass() - M0) / M0 < 1e-12
+    assert np.abs(dm).max() > 0.0
