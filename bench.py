@@ -4,7 +4,7 @@ A step is one pass of the whole hot path over the lattice: the fused kernel that
 populations, applies the curved-boundary links (eqs. 16-18), computes the pseudopotential force and
 collides. Inputs are resident in HBM before the timed region starts. Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--bc-mode present] [--collision bgk] [--no-cpu] [--no-adjoint]
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--bc-mode present] [--collision bgk] [--model pseudo] [--no-cpu] [--no-adjoint]
 
 Default: the 4096^2 D2Q9 workload (4800 circles, 640 drops) with shifted-FP32 storage, its 5000
 steps, as the throughput and HBM-roofline figures are quoted on it; the oracle is timed on a
@@ -34,14 +34,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def setup_gpu(wl, precision, rho_ref, bc_mode="present", collision="bgk"):
+def setup_gpu(wl, precision, rho_ref, bc_mode="present", collision="bgk", model="pseudo"):
     from paper_2203_04508_amd import mcb
+    from paper_2203_04508_amd import workloads as W
 
+    if model == "chempot":
+        # the paper's chemical-potential model on the same geometry: Peng-Robinson at 0.8 T_c
+        lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, 0.8 * W.PR_TC, precision=precision, rho_ref=rho_ref,
+                          bc_mode=bc_mode, collision=collision, model="chempot", cp_k=W.CP_K, cp_kappa=W.CP_KAPPA)
+        nl, nb, nw = lat.set_geometry(wl.shapes)
+        rho0, mu_s, _ = W.chempot_inputs(wl, lat.wall_nodes())
+        lat.set_wettability(mu_s)
+        lat.init_equilibrium(rho0)
+        return lat, (nl, nb, nw)
     lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision, rho_ref=rho_ref, bc_mode=bc_mode,
                       collision=collision)
     nl, nb, nw = lat.set_geometry(wl.shapes)
-    from paper_2203_04508_amd import workloads as W
-
     lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
     lat.init_equilibrium(wl.rho0())
     return lat, (nl, nb, nw)
@@ -110,7 +118,7 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(wl, budget_s=12.0, single_s=4.0, bc_mode="present", collision="bgk"):
+def cpu_baseline(wl, budget_s=12.0, single_s=4.0, bc_mode="present", collision="bgk", model="pseudo"):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload (same boundary
     scheme and collision): all threads OpenMP gives it, then one thread."""
     from oracle import oracle
@@ -118,11 +126,17 @@ def cpu_baseline(wl, budget_s=12.0, single_s=4.0, bc_mode="present", collision="
 
     P = oracle.make_params(wl.dim, *wl.dims, tau=wl.tau, T=wl.T)
     sim, (solid, *_rest) = oracle.sim_from_shapes(P, wl.shapes)
-    sim.set_phi(W.phi_for_walls(wl, oracle.wall_nodes(P, solid)))
     sim.set_bc_mode({"present": 0, "ibc": 1, "mibc": 2, "hbbc": 3}[bc_mode])
     if collision == "mrt":
         sim.set_mrt()
-    sim.init_eq(wl.rho0())
+    if model == "chempot":
+        sim.set_chempot(0.8 * W.PR_TC, k=W.CP_K, kappa=W.CP_KAPPA)
+        rho0, mu_s, _ = W.chempot_inputs(wl, oracle.wall_nodes(P, solid))
+        sim.set_mu_wall(mu_s)
+    else:
+        sim.set_phi(W.phi_for_walls(wl, oracle.wall_nodes(P, solid)))
+        rho0 = wl.rho0()
+    sim.init_eq(rho0)
     sim.step(1)
 
     def timed(budget):
@@ -160,6 +174,7 @@ def main():
     ap.add_argument("--precision", default="f32s", choices=list(DTYPES))
     ap.add_argument("--bc-mode", default="present", choices=["present", "ibc", "mibc", "hbbc"])
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
+    ap.add_argument("--model", default="pseudo", choices=["pseudo", "chempot"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -174,9 +189,9 @@ def main():
 
     wl = W.make(args.workload)
     steps = args.steps if args.steps is not None else wl.steps
-    rho_ref = wl.rho_v if args.precision != "f64" else 0.0
+    rho_ref = (W.PR_MAXWELL[0.80][0] if args.model == "chempot" else wl.rho_v) if args.precision != "f64" else 0.0
     log(f"[bench] workload {wl.name} dims {wl.dims[:wl.dim]} precision {args.precision}: set-up")
-    lat, (nl, nb, nw) = setup_gpu(wl, args.precision, rho_ref, args.bc_mode, args.collision)
+    lat, (nl, nb, nw) = setup_gpu(wl, args.precision, rho_ref, args.bc_mode, args.collision, args.model)
     M0 = lat.mass().M
     log(f"[bench] links {nl} boundary nodes {nb} wall nodes {nw}; warmup {args.warmup}")
     lat.step(args.warmup)
@@ -203,7 +218,7 @@ def main():
     # when they were taken on the kernel as it is now
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{wl.name}_{args.precision}.json")
-    if os.path.exists(tfile):
+    if os.path.exists(tfile) and args.model == "pseudo" and args.collision == "bgk":
         tj = json.load(open(tfile))
         if tj.get("kernel_digest") == kernel_digest(wl.dim):
             traffic = tj.get("bytes_per_launch")
@@ -226,13 +241,15 @@ def main():
             "storage": args.precision,
             "bc_mode": args.bc_mode,
             "collision": args.collision,
+            "model": args.model,
             "rho_ref": rho_ref,
             "links": nl, "boundary_nodes": nb, "wall_nodes": nw,
             "T_over_Tc": wl.T_over_Tc, "tau": wl.tau,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_step2d" if wl.dim == 2 else "k_rho3d + k_step3d (one step)",
+            "kernel": ("k_cp_rho + 2 k_cp_layer + k_cp_mu + k_cp_step (one step)" if args.model == "chempot"
+                       else "k_step2d" if wl.dim == 2 else "k_rho3d + k_step3d (one step)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -250,7 +267,7 @@ def main():
         out["fwd_adjoint"] = fwd_adjoint(args.precision)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, bc_mode=args.bc_mode, collision=args.collision)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, bc_mode=args.bc_mode, collision=args.collision, model=args.model)
     print(json.dumps(out), flush=True)
 
 

@@ -79,6 +79,18 @@ enum {
                           1/tau, 1/tau) of eq. 3; D2Q9 only (MCB_ENOTSUP from mcb_create for dim 3) */
 };
 
+/* multiphase model */
+enum {
+    MCB_MODEL_PSEUDO = 0,  /* pseudopotential, psi from the Carnahan-Starling EOS; wettability phi scales
+                              the first-layer wall density of eq. 15 */
+    MCB_MODEL_CHEMPOT = 1  /* the paper's chemical-potential model (Secs. 2.2-2.3), D2Q9 only: Peng-Robinson
+                              EOS (eq. 10; eos_a, eos_b, eos_R, eos_T are its a, b, R, T; G is ignored),
+                              mu = k^2 mu_PR(rho) - kappa lap(rho) (eqs. 11-12), F = -rho grad mu +
+                              grad(rho)/3 (eq. 9) by fourth-order central differences, densities on two solid
+                              layers by eq. 15; the wettability values are the assigned chemical potential of
+                              each wall node (both layers take it) */
+};
+
 /* build_links phases */
 enum { MCB_COUNT = 0, MCB_FILL = 1 };
 
@@ -106,6 +118,10 @@ typedef struct {
     double gravity[3];      /* uniform body acceleration g (lattice units): the force of eq. 13 and of
                                eqs. 16-17 becomes F_nonideal + rho g (Sec. 4.5 runs with gravity);
                                finite; gravity[2] = 0 for dim 2; zero = no body force */
+    int32_t model;          /* MCB_MODEL_PSEUDO (0) or MCB_MODEL_CHEMPOT (dim 2 only, else MCB_ENOTSUP) */
+    int32_t reserved2;      /* 0 */
+    double pr_omega;        /* MCB_MODEL_CHEMPOT: acentric factor of alpha(T) (water: 0.344) */
+    double cp_k, cp_kappa;  /* MCB_MODEL_CHEMPOT: mesh scaling k > 0 and gradient coefficient kappa >= 0 (eq. 12) */
 } mcb_params;
 
 /* A solid shape. kind MCB_SHAPE_BALL: centre (cx, cy, cz) and radius; a node is solid when it
@@ -148,7 +164,7 @@ typedef struct {
 } mcb_mass_report;
 
 /* ---- context ---------------------------------------------------------------------------- */
-/* Validates params (MCB_EINVAL otherwise; MCB_ENOTSUP for MCB_BC_IBC or MCB_COLL_MRT in 3-D) and creates a
+/* Validates params (MCB_EINVAL otherwise; MCB_ENOTSUP for MCB_BC_IBC, MCB_COLL_MRT or MCB_MODEL_CHEMPOT in 3-D) and creates a
  * context; no device work. */
 mcb_status mcb_create(const mcb_params* params, mcb_ctx** out);
 void mcb_destroy(mcb_ctx* ctx);
@@ -249,8 +265,8 @@ mcb_status mcb_timing_report(mcb_ctx* ctx, double* ms, int64_t* launches);
 enum { MCB_LOSS_COM_X = 0, MCB_LOSS_WETTED_LENGTH = 1, MCB_LOSS_TOTAL_MASS = 2 };
 
 /* Device bytes of the reverse-mode arena for nsteps >= 0 steps with a checkpoint every k >= 1
- * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_BC_PRESENT with MCB_COLL_BGK and
- * no body force: the adjoint calls return MCB_ENOTSUP for the other schemes, MRT and gravity. */
+ * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_MODEL_PSEUDO with MCB_BC_PRESENT,
+ * MCB_COLL_BGK and no body force: the adjoint calls return MCB_ENOTSUP otherwise. */
 mcb_status mcb_adj_required_bytes(mcb_ctx* ctx, int64_t nsteps, int64_t k, int64_t* bytes);
 
 /* Binds the caller-owned reverse-mode arena (device memory, at least the required bytes, 256-byte

@@ -177,32 +177,16 @@ struct PR {
     double alpha = 1.0;  // alpha(T), set by pr_set
 };
 
-// critical temperature of eq. 10 (the inflection point of p(rho) with zero slope, alpha = 1):
-// T_c = (0.0778 / 0.45724) a / (b R) to the precision of the classical constants; here solved
-// exactly from the two conditions (bisection on b rho_c in (0, 1), then T_c from p' = 0)
-inline double pr_p_dimless(double x, double t) {  // p b^2 / a at b rho = x, reduced R T b / a = t
-    return t * x / (1.0 - x) - x * x / (1.0 + 2.0 * x - x * x);
-}
+// critical point of eq. 10 (alpha = 1): with x = b rho, dp/drho = 0 gives
+//   R T b / a = (1 - x)^2 (2x + 2x^2) / (1 + 2x - x^2)^2,
+// and d2p/drho2 = 0 along it reduces to x^3 + x^2 + x - 1/3 = 0, whose real root (Cardano) is
+//   x_c = (-1 + cbrt(8 + 6 sqrt 2) + cbrt(8 - 6 sqrt 2)) / 3 = 0.25307...
 inline void pr_critical(double a, double b, double R, double* Tc, double* rhoc) {
-    // t(x) with dp/dx = 0, then the x where d2p/dx2 = 0 along that curve (numerical derivatives
-    // of the closed form, bisection on the sign of the second derivative)
-    auto t_of = [](double x) {
-        // dp/dx = t / (1 - x)^2 - (2x (1 + 2x - x^2) - x^2 (2 - 2x)) / (1 + 2x - x^2)^2 = 0
-        const double d = 1.0 + 2.0 * x - x * x;
-        return (1.0 - x) * (1.0 - x) * (2.0 * x * d - x * x * (2.0 - 2.0 * x)) / (d * d);
-    };
-    auto d2 = [&](double x) {
-        const double t = t_of(x), h = 1e-4;
-        return pr_p_dimless(x + h, t) - 2.0 * pr_p_dimless(x, t) + pr_p_dimless(x - h, t);
-    };
-    double lo = 0.05, hi = 0.6;
-    for (int it = 0; it < 200; ++it) {
-        const double m = 0.5 * (lo + hi);
-        if ((d2(lo) > 0) == (d2(m) > 0)) lo = m; else hi = m;
-    }
-    const double x = 0.5 * (lo + hi);
+    const double s2 = std::sqrt(2.0);
+    const double x = (-1.0 + std::cbrt(8.0 + 6.0 * s2) + std::cbrt(8.0 - 6.0 * s2)) / 3.0;
+    const double d = 1.0 + 2.0 * x - x * x;
     *rhoc = x / b;
-    *Tc = t_of(x) * a / (b * R);
+    *Tc = (1.0 - x) * (1.0 - x) * (2.0 * x + 2.0 * x * x) / (d * d) * a / (b * R);
 }
 
 inline void pr_set(PR& E) {

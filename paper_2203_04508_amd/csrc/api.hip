@@ -37,6 +37,12 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.tag = take(4 * N);
     L.nmask = take(p.dim == 3 ? 4 * N : 0);  // 3-D: link bits of each boundary node (bit j-1: x + e_j solid)
     L.rho3 = take(p.dim == 3 ? cb * N : 0);  // 3-D: density pass output of the step (compute type)
+    const bool cp = p.model == MCB_MODEL_CHEMPOT;
+    L.cp_rho = take(cp ? cb * N : 0);        // chemical-potential model: density and chemical potential
+    L.cp_mu = take(cp ? cb * N : 0);         // fields of the step (compute type), solid layer of each node
+    L.cp_layer = take(cp ? N : 0);
+    L.cp_l2 = take(cp ? 4 * N : 0);          // indices of the second-layer nodes, and their count
+    L.cp_l2n = take(cp ? 8 : 0);
     L.solid = take(N);
     L.scratch = take(8 * N * (2 + p.dim));
     L.blocksums = take(8 * (3 * nblk + 3));
@@ -144,7 +150,14 @@ bool params_ok(const mcb_params* p, const char** why) {
         return false;
     }
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) { *why = "tau must exceed 1/2"; return false; }
-    if (!(p->G < 0.0) || !std::isfinite(p->G)) { *why = "G must be negative"; return false; }
+    if (p->model != MCB_MODEL_PSEUDO && p->model != MCB_MODEL_CHEMPOT) { *why = "unknown model"; return false; }
+    if (p->model == MCB_MODEL_PSEUDO && (!(p->G < 0.0) || !std::isfinite(p->G))) { *why = "G must be negative"; return false; }
+    if (p->model == MCB_MODEL_CHEMPOT &&
+        (!(p->cp_k > 0.0) || !std::isfinite(p->cp_k) || !(p->cp_kappa >= 0.0) || !std::isfinite(p->cp_kappa) ||
+         !std::isfinite(p->pr_omega) || !(p->eos_a > 0.0))) {
+        *why = "bad chemical-potential parameters";
+        return false;
+    }
     if (!std::isfinite(p->eos_a) || !std::isfinite(p->eos_b) || !std::isfinite(p->eos_R) || !std::isfinite(p->eos_T) ||
         p->eos_b <= 0 || p->eos_R <= 0 || p->eos_T <= 0) {
         *why = "bad EOS parameters";
@@ -224,8 +237,8 @@ mcb_status mcb_create(const mcb_params* params, mcb_ctx** out) {
     if (!params_ok(params, &why)) return MCB_EINVAL;
     // the 3-D density pass takes the boundary nodes' density from the eq. 18 balance
     if (params->dim == 3 && params->bc_mode == MCB_BC_IBC) return MCB_ENOTSUP;
-    // the paper gives the moment basis of D2Q9 only
-    if (params->dim == 3 && params->collision == MCB_COLL_MRT) return MCB_ENOTSUP;
+    // the paper gives the moment basis of D2Q9 only; the chemical-potential path is two-dimensional
+    if (params->dim == 3 && (params->collision == MCB_COLL_MRT || params->model == MCB_MODEL_CHEMPOT)) return MCB_ENOTSUP;
     auto* c = new (std::nothrow) mcb_ctx();
     if (!c) return MCB_EINVAL;
     c->p = *params;
@@ -425,8 +438,10 @@ mcb_status mcb_set_wettability(mcb_ctx* c, const double* phi, int64_t n_wall) {
     if (!c) return MCB_EINVAL;
     if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
     if (n_wall != c->n_wall || (n_wall > 0 && !phi)) return fail(c, MCB_EINVAL, "phi needs %lld entries", (long long)c->n_wall);
+    const bool cp = c->p.model == MCB_MODEL_CHEMPOT;  // values are assigned chemical potentials
     for (int64_t w = 0; w < n_wall; ++w)
-        if (!(phi[w] > 0.0) || !std::isfinite(phi[w])) return fail(c, MCB_EINVAL, "phi[%lld] must be positive", (long long)w);
+        if (!std::isfinite(phi[w]) || (!cp && !(phi[w] > 0.0)))
+            return fail(c, MCB_EINVAL, "phi[%lld] must be %s", (long long)w, cp ? "finite" : "positive");
     if (n_wall > 0) {
         HIPCHK(hipMemcpyAsync(c->lk + c->L.wl_phi, phi, 8 * n_wall, hipMemcpyHostToDevice, c->stream));
         HIPCHK(wall_factors(c));
@@ -556,6 +571,7 @@ mcb_status mcb_adj_required_bytes(mcb_ctx* c, int64_t nsteps, int64_t k, int64_t
     if (c->p.collision != MCB_COLL_BGK) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the BGK collision only");
     if (c->p.gravity[0] != 0.0 || c->p.gravity[1] != 0.0 || c->p.gravity[2] != 0.0)
         return fail(c, MCB_ENOTSUP, "reverse mode without a body force only");
+    if (c->p.model != MCB_MODEL_PSEUDO) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the pseudopotential model only");
     *bytes = adj_plan(c, nsteps, k).bytes;
     return MCB_OK;
 }
@@ -580,6 +596,7 @@ mcb_status mcb_adj_forward(mcb_ctx* c, const double* rho0, int64_t nsteps, int64
     if (c->p.collision != MCB_COLL_BGK) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the BGK collision only");
     if (c->p.gravity[0] != 0.0 || c->p.gravity[1] != 0.0 || c->p.gravity[2] != 0.0)
         return fail(c, MCB_ENOTSUP, "reverse mode without a body force only");
+    if (c->p.model != MCB_MODEL_PSEUDO) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the pseudopotential model only");
     if (kind == MCB_LOSS_WETTED_LENGTH && !(prm[1] > 0.0)) return fail(c, MCB_EINVAL, "wetted length needs delta > 0");
     const AdjPlan a = adj_plan(c, nsteps, k);
     if (!c->adj || c->adj_bytes < a.bytes) return fail(c, MCB_ESIZE, "reverse-mode arena needs %lld bytes", (long long)a.bytes);

@@ -386,6 +386,29 @@ inline unsigned grid_for(int64_t n, int block) {
     return unsigned(b < 1 ? 1 : b);
 }
 
+// indices of the second-layer nodes (any order: each is computed on its own)
+__global__ void k_cp_l2_list(int64_t N, const int8_t* __restrict__ layer, int32_t* __restrict__ list,
+                             unsigned long long* __restrict__ count) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x)
+        if (layer[x] == 2) list[atomicAdd(count, 1ull)] = int32_t(x);
+}
+
+// solid layers of eq. 15 for the chemical-potential model: 0 fluid, 1 a wall node (a fluid
+// neighbour), 2 a solid node with a wall-node neighbour, 3 deeper
+__global__ void k_cp_layers(GridDev g, int L, const int32_t* __restrict__ tag, int8_t* __restrict__ layer) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t tg = tag[x];
+        int8_t v = tg >= 0 ? 0 : (tg <= -2 ? 1 : 3);
+        if (v == 3) {
+            int c[3];
+            coords(g, x, c);
+            for (int i = 1; i < g.Q; ++i)
+                if (tag[neighbour(g, c, L, i, +1)] <= -2) { v = 2; break; }
+        }
+        layer[x] = v;
+    }
+}
+
 }  // namespace
 
 hipError_t geom_classify(mcb_ctx* c) {
@@ -438,7 +461,21 @@ hipError_t geom_fill(mcb_ctx* c) {
         hipLaunchKernelGGL(k_q_band, dim3(grid_for(c->n_bnodes, 256)), dim3(256), 0, c->stream, b, c->g, L, c->n_bnodes,
                            o.bn_node, o.bn_mask, o.bn_link0, o.lk_qc);
     }
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    if (c->p.model == MCB_MODEL_CHEMPOT) {
+        int8_t* layer = reinterpret_cast<int8_t*>(c->lat + c->L.cp_layer);
+        unsigned long long* cnt = reinterpret_cast<unsigned long long*>(c->lat + c->L.cp_l2n);
+        hipLaunchKernelGGL(k_cp_layers, dim3(grid_for(c->g.N, 256)), dim3(256), 0, c->stream, c->g, L, o.tag, layer);
+        if ((e = hipMemsetAsync(cnt, 0, 8, c->stream)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cp_l2_list, dim3(grid_for(c->g.N, 256)), dim3(256), 0, c->stream, c->g.N, layer,
+                           reinterpret_cast<int32_t*>(c->lat + c->L.cp_l2), cnt);
+        // the second-layer count sizes a launch of every step: read it once here
+        unsigned long long n = 0;
+        if ((e = hipMemcpyAsync(&n, cnt, 8, hipMemcpyDeviceToHost, c->stream)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+        c->n_l2 = int64_t(n);
+    }
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = wall_factors(c);
     if (e != hipSuccess) return e;

@@ -63,7 +63,7 @@ struct GridDev {
 // Byte offsets of the sub-buffers carved out of the two caller-owned arenas.
 struct Layout {
     // lattice arena
-    int64_t fa, fb, tag, nmask, rho3, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
+    int64_t fa, fb, tag, nmask, rho3, cp_rho, cp_mu, cp_layer, cp_l2, cp_l2n, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
     // links arena
     int64_t bn_node, bn_mask, bn_link0, lk_qc, lk_a, rec[2], wl_node, wl_phi, wl_fac, links_bytes;
     int64_t rec_slots;   // link-coefficient slots: Q2_LINKS / Q3_LINKS per boundary node
@@ -104,6 +104,7 @@ struct mcb_ctx {
     char* lk = nullptr;
     int64_t lk_bytes = 0;
     int64_t n_shapes = 0, n_links = -1, n_bnodes = -1, n_wall = -1;
+    int64_t n_l2 = 0;  // chemical-potential model: nodes of the second solid layer
     int64_t cap_shapes = 0;
     int stage = 0;        // 0 created, 1 bound, 2 geometry set, 3 counted, 4 links filled, 5 state set
     bool swapped = false; // current post-collision state lives in fb instead of fa

@@ -161,6 +161,38 @@ __global__ void k_vel_out(GridDev g, int L, const S* __restrict__ f, const int32
     }
 }
 
+// chemical-potential model: v = (j - F / 2) / rho with F = -rho grad mu + grad(rho) / 3 + rho g from
+// the density and chemical-potential fields of the last collision (fourth-order differences)
+template <class S, class C>
+__global__ void k_vel_cp(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag, const double* __restrict__ rho,
+                         const C* __restrict__ fr, const C* __restrict__ fm, double gx, double gy, double* __restrict__ v) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        if (tag[x] < 0) {
+            v[x] = 0.0;
+            v[g.N + x] = 0.0;
+            continue;
+        }
+        double jx = 0, jy = 0;
+        for (int i = 1; i < 9; ++i) {
+            const double fi = double(ldp<S, C>(f, i, g.N, x));
+            jx += fi * c_ex[0][i];
+            jy += fi * c_ey[0][i];
+        }
+        const int cx = int(x % g.nx), cy = int(x / g.nx);
+        auto at = [&](const C* a, int dx, int dy) {
+            return double(a[int64_t(wrap1(cy + dy, g.ny)) * g.nx + wrap1(cx + dx, g.nx)]);
+        };
+        auto d1 = [](double m2, double m1, double p1, double p2) { return (8.0 * (p1 - m1) - (p2 - m2)) / 12.0; };
+        const double r = double(fr[x]);
+        const double Fx = -r * d1(at(fm, -2, 0), at(fm, -1, 0), at(fm, 1, 0), at(fm, 2, 0)) +
+                          d1(at(fr, -2, 0), at(fr, -1, 0), at(fr, 1, 0), at(fr, 2, 0)) / 3.0 + r * gx;
+        const double Fy = -r * d1(at(fm, 0, -2), at(fm, 0, -1), at(fm, 0, 1), at(fm, 0, 2)) +
+                          d1(at(fr, 0, -2), at(fr, 0, -1), at(fr, 0, 1), at(fr, 0, 2)) / 3.0 + r * gy;
+        v[x] = (jx - 0.5 * Fx) / rho[x];
+        v[g.N + x] = (jy - 0.5 * Fy) / rho[x];
+    }
+}
+
 template <class S, class C>
 __global__ void k_plane_in(int64_t N, const double* __restrict__ src, S* __restrict__ dst, C shift) {
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x)
@@ -266,6 +298,12 @@ hipError_t moments_dev(mcb_ctx* c, const void* fcur) {
     const int32_t* tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
     Eos<double> eos{c->p.eos_R * c->p.eos_T, c->p.eos_a, c->p.eos_b / 4.0, 2.0 / c->p.G};
     hipLaunchKernelGGL((k_rho_out<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, rr, sr);
+    if (c->p.model == MCB_MODEL_CHEMPOT) {
+        hipLaunchKernelGGL((k_vel_cp<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag,
+                           sr, reinterpret_cast<const C*>(c->lat + c->L.cp_rho), reinterpret_cast<const C*>(c->lat + c->L.cp_mu),
+                           c->p.gravity[0], c->p.gravity[1], sv);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_psi_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, L, tag, sr,
                        reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos,
                        reinterpret_cast<int32_t*>(c->lat + c->L.flags), sp);

@@ -164,6 +164,85 @@ __device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[RF2 + 8], cons
     return ds;
 }
 
+// Collision of one node (eq. 4, or eqs. 1-4 when MRT; eq. 13 forcing, eq. 14 equilibrium) from its
+// pulled populations fA (stored format: shifted by w_i rho_ref), their sum rs_acc and the force
+// (Fx, Fy) without the body force.  Writes the post-collision populations rounded to the storage
+// format, f_0 taking the rounding so that the node keeps its mass exactly, and the forcing terms
+// the boundary record carries.  coll = false (lanes that collide nothing) keeps the arithmetic finite.
+template <class S, class C, bool MRT>
+__device__ __forceinline__ void collide9(const Args2<S, C>& a, bool coll, const C (&fA)[9], MassAcc<S, C> rs_acc, C Fx, C Fy,
+                                         C (&out)[9], C& rho, C& dux, C& duy, C& sx2, C& sy2, C& duu15) {
+    const C rs = C(rs_acc);
+    rho = rs + a.rho_ref;
+    const C irho = rcp(coll ? rho : C(1));
+    const C jx = fA[1] - fA[3] + fA[5] - fA[6] - fA[7] + fA[8];
+    const C jy = fA[2] - fA[4] + fA[5] + fA[6] - fA[7] - fA[8];
+    const C ux = jx * irho, uy = jy * irho;
+    dux = Fx * irho + a.gx;
+    duy = Fy * irho + a.gy;
+    const C ti = a.tau_inv, omc = C(1) - ti;
+    // per direction: out_i = f_i (1 - 1/tau) + w_i [rs/tau + rho (sym_i +- anti_i)] with
+    //   sym  = (4.5 (e.u)^2 - 1.5 u^2) / tau + 4.5 (e.du)(e.(2u + du)) - 1.5 du.(2u + du)
+    //   anti = 3 (e.u / tau + e.du)
+    // (eq. 14 equilibrium, eq. 13 forcing term, eq. 4 with S = I / tau)
+    const C uu15 = C(1.5) * (ux * ux + uy * uy);
+    sx2 = C(2) * ux + dux;
+    sy2 = C(2) * uy + duy;
+    duu15 = C(1.5) * (dux * sx2 + duy * sy2);
+    const C c0 = -(ti * uu15 + duu15);
+    const C trs = ti * rs;
+    auto pair = [&](int ip, int im, C w, C eu, C ed, C es) {
+        const C sym = ti * C(4.5) * eu * eu + C(4.5) * ed * es + c0;
+        const C anti = C(3) * (ti * eu + ed);
+        const C base = w * (trs + rho * sym);
+        const C wra = w * rho * anti;
+        out[ip] = fA[ip] * omc + base + wra;
+        out[im] = fA[im] * omc + base - wra;
+    };
+    if constexpr (!MRT) {
+        pair(1, 3, C(1.0 / 9.0), ux, dux, sx2);
+        pair(2, 4, C(1.0 / 9.0), uy, duy, sy2);
+        pair(5, 7, C(1.0 / 36.0), ux + uy, dux + duy, sx2 + sy2);
+        pair(6, 8, C(1.0 / 36.0), uy - ux, duy - dux, sy2 - sx2);
+    } else {
+        // eqs. 1-4 with the moment matrix of eq. 2: the six non-conserved moments of the stored
+        // populations (the shift w_i rho_ref has moments rho_ref, -2 rho_ref, rho_ref, 0, ...,
+        // folded in through rs), relaxed at the eq. 3 rates toward the Sec. 2.1 equilibria
+        // (q^eq = -j); M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+        const C s14 = fA[1] + fA[2] + fA[3] + fA[4], s58 = fA[5] + fA[6] + fA[7] + fA[8];
+        const C jj = rho * (ux * ux + uy * uy);
+        const C de = a.s_e * (C(-4) * fA[0] - s14 + C(2) * s58 + C(2) * rs - C(3) * jj) * C(1.0 / 36.0);
+        const C dp = a.s_eps * (C(4) * fA[0] - C(2) * s14 + s58 - rs + C(3) * jj) * C(1.0 / 36.0);
+        const C dx = a.s_q * (C(-2) * (fA[1] - fA[3]) + (fA[5] - fA[6] - fA[7] + fA[8]) + jx) * C(1.0 / 12.0);
+        const C dy = a.s_q * (C(-2) * (fA[2] - fA[4]) + (fA[5] + fA[6] - fA[7] - fA[8]) + jy) * C(1.0 / 12.0);
+        const C dxx = ti * (fA[1] - fA[2] + fA[3] - fA[4] - rho * (ux * ux - uy * uy)) * C(0.25);
+        const C dxy = ti * (fA[5] - fA[6] + fA[7] - fA[8] - rho * ux * uy) * C(0.25);
+        // out = f - M^-1 S (m - m_eq) + F_i, F_i the eq. 13 term, by opposite pairs
+        auto mpair = [&](int ip, int im, C w, C ed, C es, C sym, C anti) {
+            const C wr = w * rho;
+            const C fs = wr * (C(4.5) * ed * es - duu15) + sym;
+            const C fa = wr * C(3) * ed + anti;
+            out[ip] = fA[ip] + fs + fa;
+            out[im] = fA[im] + fs - fa;
+        };
+        const C e1 = de + C(2) * dp, e2 = C(2) * de + dp;
+        mpair(1, 3, C(1.0 / 9.0), dux, sx2, e1 - dxx, C(2) * dx);
+        mpair(2, 4, C(1.0 / 9.0), duy, sy2, e1 + dxx, C(2) * dy);
+        mpair(5, 7, C(1.0 / 36.0), dux + duy, sx2 + sy2, -(e2 + dxy), -(dx + dy));
+        mpair(6, 8, C(1.0 / 36.0), duy - dux, sy2 - sx2, -(e2 - dxy), -(dy - dx));
+    }
+    // collision conserves mass (the equilibrium and the forcing term of eq. 13 have zero net
+    // mass): set f_0 to the density minus the other eight outputs as stored, so the rounding of
+    // the lattice weights and of the storage format cannot bias the total mass
+    MassAcc<S, C> rest = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        out[i] = Buf<S>::round(out[i]);
+        rest += MassAcc<S, C>(out[i]);
+    }
+    out[0] = C(rs_acc - rest);
+}
+
 // One row of the march (iteration k, row r = y0 - 2 + k).  fC holds the pulled populations of row
 // r, fB and fA those of rows r-1 and r-2, fN those of row r+1 (in flight); the populations of row
 // r+2 are issued into fP.
@@ -262,7 +341,6 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         MassAcc<S, C> rs_acc = 0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) rs_acc += MassAcc<S, C>(fA[i]);
-        const C rs_pull = C(rs_acc);
         const int sl = (k - 3) & 3, sm = (k - 2) & 3, sh = (k - 1) & 3;
         const int tc = t < 1 ? 1 : (t > OUT + 2 ? OUT + 2 : t);
         const C p0 = M.s_psi[sm][tc];
@@ -275,75 +353,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         const C Fx = gp * (C(1.0 / 3.0) * (pE - pW) + C(1.0 / 12.0) * (pNE - pNW - pSW + pSE));
         const C Fy = gp * (C(1.0 / 3.0) * (pN - pS) + C(1.0 / 12.0) * (pNE + pNW - pSW - pSE));
 
-        const C rs = rs_pull;
-        rho = rs + a.rho_ref;
-        const C irho = rcp(coll ? rho : C(1));
-        const C jx = fA[1] - fA[3] + fA[5] - fA[6] - fA[7] + fA[8];
-        const C jy = fA[2] - fA[4] + fA[5] + fA[6] - fA[7] - fA[8];
-        const C ux = jx * irho, uy = jy * irho;
-        dux = Fx * irho + a.gx;
-        duy = Fy * irho + a.gy;
-        const C ti = a.tau_inv, omc = C(1) - ti;
-        // per direction: out_i = f_i (1 - 1/tau) + w_i [rs/tau + rho (sym_i +- anti_i)] with
-        //   sym  = (4.5 (e.u)^2 - 1.5 u^2) / tau + 4.5 (e.du)(e.(2u + du)) - 1.5 du.(2u + du)
-        //   anti = 3 (e.u / tau + e.du)
-        // (eq. 14 equilibrium, eq. 13 forcing term, eq. 4 with S = I / tau)
-        const C uu15 = C(1.5) * (ux * ux + uy * uy);
-        sx2 = C(2) * ux + dux;
-        sy2 = C(2) * uy + duy;
-        duu15 = C(1.5) * (dux * sx2 + duy * sy2);
-        const C c0 = -(ti * uu15 + duu15);
-        const C trs = ti * rs;
-        auto pair = [&](int ip, int im, C w, C eu, C ed, C es) {
-            const C sym = ti * C(4.5) * eu * eu + C(4.5) * ed * es + c0;
-            const C anti = C(3) * (ti * eu + ed);
-            const C base = w * (trs + rho * sym);
-            const C wra = w * rho * anti;
-            out[ip] = fA[ip] * omc + base + wra;
-            out[im] = fA[im] * omc + base - wra;
-        };
-        if constexpr (!MRT) {
-            pair(1, 3, C(1.0 / 9.0), ux, dux, sx2);
-            pair(2, 4, C(1.0 / 9.0), uy, duy, sy2);
-            pair(5, 7, C(1.0 / 36.0), ux + uy, dux + duy, sx2 + sy2);
-            pair(6, 8, C(1.0 / 36.0), uy - ux, duy - dux, sy2 - sx2);
-        } else {
-            // eqs. 1-4 with the moment matrix of eq. 2: the six non-conserved moments of the stored
-            // populations (the shift w_i rho_ref has moments rho_ref, -2 rho_ref, rho_ref, 0, ...,
-            // folded in through rs), relaxed at the eq. 3 rates toward the Sec. 2.1 equilibria
-            // (q^eq = -j); M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-            const C s14 = fA[1] + fA[2] + fA[3] + fA[4], s58 = fA[5] + fA[6] + fA[7] + fA[8];
-            const C jj = rho * (ux * ux + uy * uy);
-            const C de = a.s_e * (C(-4) * fA[0] - s14 + C(2) * s58 + C(2) * rs - C(3) * jj) * C(1.0 / 36.0);
-            const C dp = a.s_eps * (C(4) * fA[0] - C(2) * s14 + s58 - rs + C(3) * jj) * C(1.0 / 36.0);
-            const C dx = a.s_q * (C(-2) * (fA[1] - fA[3]) + (fA[5] - fA[6] - fA[7] + fA[8]) + jx) * C(1.0 / 12.0);
-            const C dy = a.s_q * (C(-2) * (fA[2] - fA[4]) + (fA[5] + fA[6] - fA[7] - fA[8]) + jy) * C(1.0 / 12.0);
-            const C dxx = ti * (fA[1] - fA[2] + fA[3] - fA[4] - rho * (ux * ux - uy * uy)) * C(0.25);
-            const C dxy = ti * (fA[5] - fA[6] + fA[7] - fA[8] - rho * ux * uy) * C(0.25);
-            // out = f - M^-1 S (m - m_eq) + F_i, F_i the eq. 13 term, by opposite pairs
-            auto mpair = [&](int ip, int im, C w, C ed, C es, C sym, C anti) {
-                const C wr = w * rho;
-                const C fs = wr * (C(4.5) * ed * es - duu15) + sym;
-                const C fa = wr * C(3) * ed + anti;
-                out[ip] = fA[ip] + fs + fa;
-                out[im] = fA[im] + fs - fa;
-            };
-            const C e1 = de + C(2) * dp, e2 = C(2) * de + dp;
-            mpair(1, 3, C(1.0 / 9.0), dux, sx2, e1 - dxx, C(2) * dx);
-            mpair(2, 4, C(1.0 / 9.0), duy, sy2, e1 + dxx, C(2) * dy);
-            mpair(5, 7, C(1.0 / 36.0), dux + duy, sx2 + sy2, -(e2 + dxy), -(dx + dy));
-            mpair(6, 8, C(1.0 / 36.0), duy - dux, sy2 - sx2, -(e2 - dxy), -(dy - dx));
-        }
-        // collision conserves mass (the equilibrium and the forcing term of eq. 13 have zero net
-        // mass): set f_0 to the density minus the other eight outputs as stored, so the rounding of
-        // the lattice weights and of the storage format cannot bias the total mass
-        MassAcc<S, C> rest = 0;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            out[i] = Buf<S>::round(out[i]);
-            rest += MassAcc<S, C>(out[i]);
-        }
-        out[0] = C(rs_acc - rest);
+        collide9<S, C, MRT>(a, coll, fA, rs_acc, Fx, Fy, out, rho, dux, duy, sx2, sy2, duu15);
     }
     // Every output column stores, solid nodes included (zeros: the pull replaces what it takes
     // from them), so rows are written without holes and every cache line whole.  A lane that does
@@ -536,9 +546,292 @@ hipError_t launch_step2d(mcb_ctx* c, const void* fcur, const void* rcur, void* f
     return launch_w<S, C, 256, 224>(c, fcur, rcur, fnext, rnext, pull);
 }
 
+// ---------------------------------------------------------------- chemical-potential model (2-D)
+// The paper's multiphase model (Secs. 2.2-2.3): the force needs the density and the chemical
+// potential two nodes away on each axis, and the chemical potential itself the density two nodes
+// away, so a step runs as passes over the lattice: density (pull + eqs. 16-18), the two solid
+// layers of eq. 15, the chemical potential (eq. 12), then pull + force (eq. 9) + collision.
+template <class S, class C>
+struct ArgsCP {
+    Args2<S, C> a;
+    C* rho;                 // density of the step: fluid nodes and solid layers 1-2
+    C* mu;                  // chemical potential of the step: fluid nodes and solid layers 1-2
+    const int8_t* layer;    // 0 fluid, 1 wall node, 2 second solid layer, 3 deeper
+    const double* mus;      // assigned chemical potential per wall node
+    C k2, kappa;            // eq. 12: k^2 and kappa
+    C RT, b, c_log, aal;    // eq. 11: R T, b, a alpha / (2 sqrt 2 b), a alpha
+};
+
+// pulled populations of node (cx, cy) (PULL; otherwise its own stored ones), with eqs. 16-18 at
+// boundary nodes; ds = the eq. 18 correction.  Solid nodes hold zeros, which the links replace.
+template <class S, class C, bool PULL>
+__device__ __forceinline__ int pull_node(const Args2<S, C>& a, int64_t N, int cx, int cy, C (&f)[9], C& ds) {
+    const int tg = a.tag[int64_t(cy) * a.nx + cx];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int sx = PULL ? wrap1(cx - kEx[i], a.nx) : cx, sy = PULL ? wrap1(cy - kEy[i], a.ny) : cy;
+        f[i] = ldp<S, C>(a.fa, i, N, int64_t(sy) * a.nx + sx);
+    }
+    ds = C(0);
+    if (PULL) {
+        const bool bnd = tg > 0;
+        if (__any(bnd)) {
+            C rec[RF2 + 8], ca[Q2_LINKS];
+            const int64_t bi = bnd ? int64_t(tg >> 8) : 0;
+#pragma unroll
+            for (int k = 0; k < RF2 + 8; ++k) rec[k] = bnd ? a.rin[bi * REC2 + k] : C(0);
+#pragma unroll
+            for (int k = 0; k < Q2_LINKS; ++k) ca[k] = bnd ? a.la[bi * Q2_LINKS + k] : C(NO_LINK);
+            ds = apply_links<S, C>(bnd, rec, ca, f, a.kF, a.k18);
+        }
+    }
+    return tg;
+}
+
+// the passes over the lattice give each workgroup 256 columns of one row (blockIdx.x) of row blockIdx.y
+template <class S, class C, bool PULL>
+__global__ __launch_bounds__(256) void k_cp_rho(ArgsCP<S, C> p) {
+    const Args2<S, C>& a = p.a;
+    const int cx = blockIdx.x * 256 + threadIdx.x, cy = blockIdx.y;
+    if (cx >= a.nx) return;
+    const int64_t N = int64_t(a.nx) * a.ny, x = int64_t(cy) * a.nx + cx;
+    C f[9], ds;
+    const int tg = pull_node<S, C, PULL>(a, N, cx, cy, f, ds);
+    MassAcc<S, C> rs = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) rs += MassAcc<S, C>(f[i]);
+    p.rho[x] = tg >= 0 ? C(rs) + a.rho_ref : C(0);
+}
+
+// eq. 15 for one solid layer (its n nodes in list): the lattice-weighted mean over the neighbours
+// in the layer above
+template <class S, class C>
+__global__ __launch_bounds__(256) void k_cp_layer(ArgsCP<S, C> p, const int32_t* __restrict__ list, int64_t n, int lay) {
+    const int nx = p.a.nx, ny = p.a.ny;
+    for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < n; j += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t x = list[j];
+        const int cx = int(x % nx), cy = int(x / nx);
+        C num = C(0), den = C(0);
+        for (int i = 1; i < 9; ++i) {
+            const int64_t y = int64_t(wrap1(cy + kEy[i], ny)) * nx + wrap1(cx + kEx[i], nx);
+            if (p.layer[y] == lay - 1) {
+                num += w9<C>(i) * p.rho[y];
+                den += w9<C>(i);
+            }
+        }
+        p.rho[x] = num / den;
+    }
+}
+
+// 32-bit element offsets of the periodic cross stencil around (cx, cy): rows cy - 2 .. cy + 2 (times
+// nx) and columns cx - 2 .. cx + 2 (N < 2^31)
+struct Cross {
+    uint32_t row[5], col[5];
+};
+__device__ __forceinline__ Cross cross_of(int cx, int cy, int nx, int ny) {
+    Cross k;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        k.row[d] = uint32_t(wrap1(cy + d - 2, ny)) * uint32_t(nx);
+        k.col[d] = uint32_t(wrap1(cx + d - 2, nx));
+    }
+    return k;
+}
+
+// fourth-order central differences along an axis from the values at offsets -2 .. +2
+template <class C>
+__device__ __forceinline__ C cd1(C m2, C m1, C p1, C p2) {
+    return (C(8) * (p1 - m1) - (p2 - m2)) / C(12);
+}
+template <class C>
+__device__ __forceinline__ C cd2(C m2, C m1, C c, C p1, C p2) {
+    return (C(16) * (p1 + m1) - (p2 + m2) - C(30) * c) / C(12);
+}
+
+// chemical potential: eq. 12 on fluid nodes (Peng-Robinson mu of eq. 11), the assigned value on
+// wall nodes, on the second layer the eq. 15 mean of its wall-node neighbours' assigned values
+template <class S, class C>
+__global__ __launch_bounds__(256) void k_cp_mu(ArgsCP<S, C> p) {
+    const int nx = p.a.nx, ny = p.a.ny;
+    const C s2 = C(1.4142135623730951);
+    const int cx = blockIdx.x * 256 + threadIdx.x, cy = blockIdx.y;
+    if (cx >= nx) return;
+    const int64_t x = int64_t(cy) * nx + cx;
+    const int lay = p.layer[x];
+    const Cross k = cross_of(cx, cy, nx, ny);
+    auto at = [&](const C* v, int dx, int dy) { return v[k.row[dy + 2] + k.col[dx + 2]]; };
+    // the stencil's loads first, independent of the node's kind, so that they are all in flight at once
+    const C r = p.rho[x];
+    const C xm2 = at(p.rho, -2, 0), xm1 = at(p.rho, -1, 0), xp1 = at(p.rho, 1, 0), xp2 = at(p.rho, 2, 0);
+    const C ym2 = at(p.rho, 0, -2), ym1 = at(p.rho, 0, -1), yp1 = at(p.rho, 0, 1), yp2 = at(p.rho, 0, 2);
+    C m = C(0);
+    if (lay == 0) {
+        const C br = p.b * r;
+        if (!(r > C(0)) || !(br < C(1))) atomicOr(&p.a.flags[FLAG_DOMAIN], 1);
+        const C m0 = p.RT * log(r / (C(1) - br)) - p.c_log * log((s2 - C(1) + br) / (s2 + C(1) - br)) +
+                     p.RT / (C(1) - br) - p.aal * r / (C(1) + C(2) * br - br * br);
+        C lap = C(0);
+        lap += cd2(xm2, xm1, r, xp1, xp2);
+        lap += cd2(ym2, ym1, r, yp1, yp2);
+        m = p.k2 * m0 - p.kappa * lap;
+    } else if (lay == 1) {
+        m = C(p.mus[-p.a.tag[x] - 2]);
+    } else if (lay == 2) {
+        C num = C(0), den = C(0);
+        for (int i = 1; i < 9; ++i) {
+            const int64_t y = int64_t(wrap1(cy + kEy[i], ny)) * nx + wrap1(cx + kEx[i], nx);
+            if (p.layer[y] == 1) {
+                num += w9<C>(i) * C(p.mus[-p.a.tag[y] - 2]);
+                den += w9<C>(i);
+            }
+        }
+        m = num / den;
+    }
+    p.mu[x] = m;
+}
+
+// pull, eq. 9 force from the fields, collision, store (solid nodes store zeros), boundary record
+template <class S, class C, bool PULL, bool MRT>
+__global__ __launch_bounds__(256) void k_cp_step(ArgsCP<S, C> p) {
+    const Args2<S, C>& a = p.a;
+    const int nx = a.nx, ny = a.ny;
+    const int64_t N = int64_t(nx) * ny;
+    const int cx = blockIdx.x * 256 + threadIdx.x, cy = blockIdx.y;
+    if (cx >= nx) return;
+    {
+        const int64_t x = int64_t(cy) * nx + cx;
+        // the field stencils first, so that their loads are in flight with the pull
+        const Cross k = cross_of(cx, cy, nx, ny);
+        auto at = [&](const C* v, int dx, int dy) { return v[k.row[dy + 2] + k.col[dx + 2]]; };
+        const C r = p.rho[x];
+        const C mxm2 = at(p.mu, -2, 0), mxm1 = at(p.mu, -1, 0), mxp1 = at(p.mu, 1, 0), mxp2 = at(p.mu, 2, 0);
+        const C mym2 = at(p.mu, 0, -2), mym1 = at(p.mu, 0, -1), myp1 = at(p.mu, 0, 1), myp2 = at(p.mu, 0, 2);
+        const C rxm2 = at(p.rho, -2, 0), rxm1 = at(p.rho, -1, 0), rxp1 = at(p.rho, 1, 0), rxp2 = at(p.rho, 2, 0);
+        const C rym2 = at(p.rho, 0, -2), rym1 = at(p.rho, 0, -1), ryp1 = at(p.rho, 0, 1), ryp2 = at(p.rho, 0, 2);
+        C f[9], ds;
+        const int tg = pull_node<S, C, PULL>(a, N, cx, cy, f, ds);
+        const bool coll = tg >= 0;
+        MassAcc<S, C> rs = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) rs += MassAcc<S, C>(f[i]);
+        const C Fx = -r * cd1(mxm2, mxm1, mxp1, mxp2) + cd1(rxm2, rxm1, rxp1, rxp2) / C(3);
+        const C Fy = -r * cd1(mym2, mym1, myp1, myp2) + cd1(rym2, rym1, ryp1, ryp2) / C(3);
+        C out[9];
+        C rho, dux, duy, sx2, sy2, duu15;
+        collide9<S, C, MRT>(a, coll, f, rs, coll ? Fx : C(0), coll ? Fy : C(0), out, rho, dux, duy, sx2, sy2, duu15);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) stp<S, C>(a.fb, i, N, x, coll ? out[i] : C(0));
+        if (coll && tg > 0) {
+            C rv[REC2];
+            rv[0] = rho;
+            rv[1] = dux;
+            rv[2] = duy;
+            rv[3] = sx2;
+            rv[4] = sy2;
+            rv[5] = duu15;
+#pragma unroll
+            for (int i = 1; i < 9; ++i) rv[RF2 + i - 1] = out[i];
+            rv[RF2 + 8] = kMixed<S> ? out[0] : Buf<S>::round(out[0]);
+            rv[RF2 + 9] = ds;
+            C* dst = a.rout + int64_t(tg >> 8) * REC2;
+#pragma unroll
+            for (int k = 0; k < REC2; ++k) dst[k] = rv[k];
+        }
+    }
+}
+
+inline unsigned cp_grid(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    return unsigned(b < 1 ? 1 : b);
+}
+
+// Peng-Robinson critical temperature (alpha = 1): x = b rho_c is the real root of
+// x^3 + x^2 + x - 1/3 = 0 (d2p/drho2 = 0 on the curve dp/drho = 0), then
+// R T_c b / a = (1 - x)^2 (2x + 2x^2) / (1 + 2x - x^2)^2
+double pr_tc(double a, double b, double R) {
+    const double r2 = std::sqrt(2.0);
+    const double x = (std::cbrt(8.0 + 6.0 * r2) + std::cbrt(8.0 - 6.0 * r2) - 1.0) / 3.0;
+    const double q = 1.0 + 2.0 * x - x * x;
+    return a / (b * R) * (1.0 - x) * (1.0 - x) * 2.0 * x * (1.0 + x) / (q * q);
+}
+
+template <class S, class C>
+hipError_t launch_cp(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
+    ArgsCP<S, C> p;
+    Args2<S, C>& a = p.a;
+    a.fa = static_cast<const S*>(fcur);
+    a.fb = static_cast<S*>(fnext);
+    a.tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
+    a.rin = static_cast<const C*>(rcur);
+    a.rout = static_cast<C*>(rnext);
+    a.la = reinterpret_cast<const C*>(c->lk + c->L.lk_a);
+    a.fac = nullptr;
+    a.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
+    a.n_bnodes = uint32_t(c->n_bnodes > 0 ? c->n_bnodes : 0);
+    a.n_wall = uint32_t(c->n_wall > 0 ? c->n_wall : 0);
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.H = a.nsx = a.nblocks = 0;
+    a.tau_inv = C(1.0 / c->p.tau);
+    a.G = C(0);
+    a.rho_ref = c->p.precision == MCB_F64 ? C(0) : C(c->p.rho_ref);
+    a.kF = c->p.bc_mode == MCB_BC_PRESENT ? C(1) : C(0);
+    a.k18 = c->p.bc_mode == MCB_BC_IBC ? C(0) : C(1);
+    a.s_e = C(c->p.s_e);
+    a.s_eps = C(c->p.s_eps);
+    a.s_q = C(c->p.s_q);
+    a.gx = C(c->p.gravity[0]);
+    a.gy = C(c->p.gravity[1]);
+    a.eos = Eos<C>{};
+    p.rho = reinterpret_cast<C*>(c->lat + c->L.cp_rho);
+    p.mu = reinterpret_cast<C*>(c->lat + c->L.cp_mu);
+    p.layer = reinterpret_cast<const int8_t*>(c->lat + c->L.cp_layer);
+    p.mus = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
+    const double T = c->p.eos_T, Tc = pr_tc(c->p.eos_a, c->p.eos_b, c->p.eos_R);
+    const double om = c->p.pr_omega, mm = 0.37464 + 1.54226 * om - 0.26992 * om * om;
+    const double sa = 1.0 + mm * (1.0 - std::sqrt(T / Tc));
+    const double aal = c->p.eos_a * sa * sa;
+    p.k2 = C(c->p.cp_k * c->p.cp_k);
+    p.kappa = C(c->p.cp_kappa);
+    p.RT = C(c->p.eos_R * T);
+    p.b = C(c->p.eos_b);
+    p.c_log = C(aal / (2.0 * std::sqrt(2.0) * c->p.eos_b));
+    p.aal = C(aal);
+    const dim3 grid(unsigned((c->p.nx + 255) / 256), unsigned(c->p.ny)), blk(256);
+    if (pull)
+        hipLaunchKernelGGL((k_cp_rho<S, C, true>), grid, blk, 0, c->stream, p);
+    else
+        hipLaunchKernelGGL((k_cp_rho<S, C, false>), grid, blk, 0, c->stream, p);
+    if (c->n_wall > 0)
+        hipLaunchKernelGGL((k_cp_layer<S, C>), dim3(cp_grid(c->n_wall)), blk, 0, c->stream, p,
+                           reinterpret_cast<const int32_t*>(c->lk + c->L.wl_node), c->n_wall, 1);
+    if (c->n_l2 > 0)
+        hipLaunchKernelGGL((k_cp_layer<S, C>), dim3(cp_grid(c->n_l2)), blk, 0, c->stream, p,
+                           reinterpret_cast<const int32_t*>(c->lat + c->L.cp_l2), c->n_l2, 2);
+    hipLaunchKernelGGL((k_cp_mu<S, C>), grid, blk, 0, c->stream, p);
+    const bool mrt = c->p.collision == MCB_COLL_MRT;
+    if (pull && mrt)
+        hipLaunchKernelGGL((k_cp_step<S, C, true, true>), grid, blk, 0, c->stream, p);
+    else if (pull)
+        hipLaunchKernelGGL((k_cp_step<S, C, true, false>), grid, blk, 0, c->stream, p);
+    else if (mrt)
+        hipLaunchKernelGGL((k_cp_step<S, C, false, true>), grid, blk, 0, c->stream, p);
+    else
+        hipLaunchKernelGGL((k_cp_step<S, C, false, false>), grid, blk, 0, c->stream, p);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t step2d(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
+    if (c->p.model == MCB_MODEL_CHEMPOT) {
+        switch (c->p.precision) {
+            case MCB_F64: return launch_cp<double, double>(c, fcur, rcur, fnext, rnext, pull);
+            case MCB_F32S: return launch_cp<float, float>(c, fcur, rcur, fnext, rnext, pull);
+            default: return launch_cp<__half, float>(c, fcur, rcur, fnext, rnext, pull);
+        }
+    }
     switch (c->p.precision) {
         case MCB_F64: return launch_step2d<double, double>(c, fcur, rcur, fnext, rnext, pull);
         case MCB_F32S: return launch_step2d<float, float>(c, fcur, rcur, fnext, rnext, pull);

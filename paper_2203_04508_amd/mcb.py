@@ -19,6 +19,8 @@ MCB_OK, MCB_EINVAL, MCB_ESIZE, MCB_EHIP, MCB_EDOMAIN, MCB_ENAN, MCB_ESTATE, MCB_
 MCB_F64, MCB_F32S, MCB_F16S = 0, 1, 2
 MCB_BC_PRESENT, MCB_BC_IBC, MCB_BC_MIBC, MCB_BC_HBBC = 0, 1, 2, 3
 MCB_COLL_BGK, MCB_COLL_MRT = 0, 1
+MCB_MODEL_PSEUDO, MCB_MODEL_CHEMPOT = 0, 1
+PR_PAPER = dict(a=2.0 / 49.0, b=2.0 / 21.0, R=1.0, omega=0.344)  # Sec. 2.2: a, b, R, water's omega
 MRT_RATES_PAPER = (1.64, 1.54, 1.7)  # s_e, s_epsilon, s_q of eq. 3
 BC_MODES = {"present": MCB_BC_PRESENT, "ibc": MCB_BC_IBC, "mibc": MCB_BC_MIBC, "hbbc": MCB_BC_HBBC}
 MCB_COUNT, MCB_FILL = 0, 1
@@ -33,7 +35,9 @@ class mcb_params(C.Structure):
                 ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double), ("eos_T", C.c_double),
                 ("precision", C.c_int32), ("bc_mode", C.c_int32), ("rho_ref", C.c_double),
                 ("collision", C.c_int32), ("reserved", C.c_int32),
-                ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double), ("gravity", C.c_double * 3)]
+                ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double), ("gravity", C.c_double * 3),
+                ("model", C.c_int32), ("reserved2", C.c_int32), ("pr_omega", C.c_double),
+                ("cp_k", C.c_double), ("cp_kappa", C.c_double)]
 
 
 class mcb_shape(C.Structure):
@@ -291,19 +295,28 @@ def mcb_adj_backward(ctx, dloss, n_wall) -> np.ndarray:
 class Lattice:
     """A context plus the torch tensors backing its device arenas."""
 
-    def __init__(self, dim, dims, tau, T, precision="f64", rho_ref=0.0, G=-1.0, a=1.0, b=4.0, R=1.0,
+    def __init__(self, dim, dims, tau, T, precision="f64", rho_ref=0.0, G=-1.0, a=None, b=None, R=1.0,
                  device="cuda:0", stream=None, bc_mode="present", collision="bgk", mrt_rates=MRT_RATES_PAPER,
-                 gravity=(0.0, 0.0, 0.0)):
+                 gravity=(0.0, 0.0, 0.0), model="pseudo", cp_k=1.0, cp_kappa=0.0, pr_omega=PR_PAPER["omega"]):
+        """model "pseudo": pseudopotential with the Carnahan-Starling EOS (a, b default 1, 4);
+        model "chempot": the chemical-potential model with the Peng-Robinson EOS (a, b default to the
+        paper's 2/49, 2/21), mesh scaling cp_k and gradient coefficient cp_kappa."""
         import torch
 
         self.torch = torch
         self.device = torch.device(device)
         nz = dims[2] if dim == 3 else 1
+        cp = model == "chempot"
+        if a is None:
+            a = PR_PAPER["a"] if cp else 1.0
+        if b is None:
+            b = PR_PAPER["b"] if cp else 4.0
         self.params = mcb_params(dim, dims[0], dims[1], nz, tau, G, a, b, R, T,
                                  PRECISIONS[precision] if isinstance(precision, str) else precision,
                                  BC_MODES[bc_mode] if isinstance(bc_mode, str) else bc_mode, rho_ref,
                                  {"bgk": MCB_COLL_BGK, "mrt": MCB_COLL_MRT}[collision], 0, *mrt_rates,
-                                 (C.c_double * 3)(*(list(gravity) + [0.0] * (3 - len(gravity)))))
+                                 (C.c_double * 3)(*(list(gravity) + [0.0] * (3 - len(gravity)))),
+                                 MCB_MODEL_CHEMPOT if cp else MCB_MODEL_PSEUDO, 0, pr_omega, cp_k, cp_kappa)
         self.dim = dim
         self.Q = 9 if dim == 2 else 19
         self.N = int(dims[0]) * int(dims[1]) * int(nz)

@@ -7,16 +7,20 @@ y_w = y1 - q, with y1 = 11 the first fluid row, so every link from row y1 into t
 q (axis and diagonal links alike).  The band's underside, at the top of the periodic box, sits at
 q = 1/2, where all four schemes coincide.  A drop of radius 50 is centred on the wall line.
 
-Wettability: the factor phi of the eq. 15 wall density is calibrated at q = 1/2 (where the schemes
-agree) to the two contact angles of the paper, 60 and 120 degrees, by bisection on the equilibrium
-angle.  The angle comes from a circle fitted to the drop's interface (rho = (rho_l + rho_v) / 2,
+Two multiphase models: "pseudo" (this library's pseudopotential, BGK, tau = 1, Carnahan-Starling at
+0.7 T_c, wettability the factor phi of the eq. 15 wall density) and "chempot" (the paper's own:
+chemical-potential model with the Peng-Robinson EOS at 0.8 T_c, MRT collision with the rates of
+eq. 3 and tau = 0.8, wettability the assigned wall chemical potential mu_s of Sec. 2.3).
+
+Wettability (phi or mu_s) is calibrated at q = 1/2 (where the schemes agree) to the two contact
+angles of the paper, 60 and 120 degrees, by bisection on the equilibrium angle.  The angle comes from a circle fitted to the drop's interface (rho = (rho_l + rho_v) / 2,
 interpolated along rows, rows at least 4 above the wall), cos(theta) = (y_w - y_c) / R.
 
 Reported per angle, scheme and q: M/M0 - 1 and the eq. 18 total Delta M of the step at sample times;
 the final contact angle; the largest speed over the fluid at the end (the spurious currents of
 Sec. 4.4); the step at which a run stopped on a psi domain error, if it did.
 
-    python -m paper_2203_04508_amd.qsweep [--steps 20000] [--out profiles/qsweep_flat.json]
+    python -m paper_2203_04508_amd.qsweep [--model pseudo|chempot] [--steps 20000] [--out profiles/qsweep_flat.json]
     python -m paper_2203_04508_amd.qsweep --summarize profiles/qsweep_flat.json   (text table)
 """
 from __future__ import annotations
@@ -32,7 +36,20 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 NX, NY, Y1, R0 = 500, 300, 11, 50.0
-T_OVER_TC, TAU = 0.70, 1.0
+# per model: reduced temperature, tau, collision, interface width of the initial profile, and the
+# wettability search interval (the angle falls with phi, rises with mu_s)
+MODELS = {
+    "pseudo": dict(T_over_Tc=0.70, tau=1.0, collision="bgk", width=2.0, lo=0.50, hi=1.45, rising=False),
+    "chempot": dict(T_over_Tc=0.80, tau=0.8, collision="mrt", width=6.0, lo=-0.06, hi=0.06, rising=True),
+}
+MODEL = "pseudo"
+
+
+def _densities():
+    from paper_2203_04508_amd import workloads as W
+
+    m = MODELS[MODEL]
+    return W.PR_MAXWELL[m["T_over_Tc"]] if MODEL == "chempot" else W.MAXWELL[m["T_over_Tc"]]
 
 
 def setup(q):
@@ -40,8 +57,8 @@ def setup(q):
 
     yw = Y1 - q
     shapes = np.array([W.band_y(-0.5, yw, 0)], np.int64)
-    rv, rl = W.MAXWELL[T_OVER_TC]
-    rho0 = W.drop_field((NX, NY, 1), 2, [((NX / 2.0, yw), R0)], rv, rl, 2.0)
+    rv, rl = _densities()
+    rho0 = W.drop_field((NX, NY, 1), 2, [((NX / 2.0, yw), R0)], rv, rl, MODELS[MODEL]["width"])
     # the half of the drop below the wall line would wrap to the top of the periodic box, against
     # the band's underside: vapour there
     rho0.reshape(NY, NX)[NY // 2:] = rv
@@ -83,7 +100,15 @@ def make_lattice(mode, q, phi):
     from paper_2203_04508_amd import mcb, workloads as W
 
     shapes, rho0, yw, rv, rl = setup(q)
-    lat = mcb.Lattice(2, (NX, NY, 1), TAU, T_OVER_TC * W.CS_TC, precision="f64", bc_mode=mode)
+    m = MODELS[MODEL]
+    if MODEL == "chempot":
+        # the wettability argument is mu_s relative to the bulk potential at coexistence
+        phi = W.CP_K * W.CP_K * W.MU_PR_COEX[m["T_over_Tc"]] + phi
+        lat = mcb.Lattice(2, (NX, NY, 1), m["tau"], m["T_over_Tc"] * W.PR_TC, precision="f64", bc_mode=mode,
+                          collision=m["collision"], model="chempot", cp_k=W.CP_K, cp_kappa=W.CP_KAPPA)
+    else:
+        lat = mcb.Lattice(2, (NX, NY, 1), m["tau"], m["T_over_Tc"] * W.CS_TC, precision="f64", bc_mode=mode,
+                          collision=m["collision"])
     try:
         lat.set_geometry(shapes)
         lat.set_wettability(phi)
@@ -112,16 +137,20 @@ def equilibrium_angle(phi, steps):
             lat.close()
 
 
-def calibrate(target, steps, lo=0.50, hi=1.45, iters=10):
-    """phi in [lo, hi] with the equilibrium angle at target degrees (the angle falls as phi rises;
-    a domain error counts as too wetting)."""
+def calibrate(target, steps, iters=10):
+    """The wettability value in the model's interval with the equilibrium angle at target degrees
+    (pseudo: phi, the angle falls as it rises, a domain error counts as too wetting; chempot: mu_s
+    minus the bulk coexistence potential, the angle rises with it)."""
+    m = MODELS[MODEL]
+    lo, hi = m["lo"], m["hi"]
     log = []
     for _ in range(iters):
         mid = 0.5 * (lo + hi)
         th = equilibrium_angle(mid, steps)
         log.append((mid, th))
-        print(f"[qsweep] calibrate {target}: phi {mid:.5f} -> {th:.2f} deg", file=sys.stderr, flush=True)
-        if not np.isfinite(th) or th < target:
+        print(f"[qsweep] calibrate {target}: wettability {mid:.5f} -> {th:.2f} deg", file=sys.stderr, flush=True)
+        too_wetting = not np.isfinite(th) or th < target
+        if too_wetting != m["rising"]:
             hi = mid
         else:
             lo = mid
@@ -170,12 +199,13 @@ def summarize(res) -> str:
     """Per angle: for each q, M/M0 at the end (or the step a run stopped before), the final contact
     angle and the final largest speed, per scheme; and the largest |Delta M| sampled after the
     first quarter of the run for MIBC and the present scheme."""
-    lines = [f"flat-substrate q-sweep, {res['box'][0]}x{res['box'][1]} D2Q9 FP64, drop r {res['drop_radius']}, "
-             f"{res['steps']} steps, T/Tc {res['T_over_Tc']}, tau {res['tau']}", f"command: {res['command']}"]
+    lines = [f"flat-substrate q-sweep, model {res.get('model', 'pseudo')}, {res['box'][0]}x{res['box'][1]} D2Q9 FP64, "
+             f"drop r {res['drop_radius']}, {res['steps']} steps, T/Tc {res['T_over_Tc']}, tau {res['tau']}",
+             f"command: {res['command']}"]
     for a in res["angles"]:
         th05 = a["theta_present_q05"]
         lines.append("")
-        lines.append(f"target {a['target_deg']:.0f} deg: phi {a['phi']:.5f}, equilibrium angle at q = 1/2 {th05:.1f} deg")
+        lines.append(f"target {a['target_deg']:.0f} deg: wettability {a['phi']:.5f}, equilibrium angle at q = 1/2 {th05:.1f} deg")
         runs = {(r["mode"], r["q"]): r for r in a["runs"]}
         hb = next(r for r in a["runs"] if r["mode"] == "hbbc")
         lines.append(f"halfway bounce-back (q-independent): M/M0-1 {hb['drift'][-1]:+.1e}, theta {hb['theta_end']:.1f}, "
@@ -200,6 +230,7 @@ def summarize(res) -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--summarize", default=None, help="print the text table of a stored result")
+    ap.add_argument("--model", default="pseudo", choices=list(MODELS))
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--every", type=int, default=1000)
     ap.add_argument("--calib-steps", type=int, default=10000)
@@ -209,10 +240,13 @@ def main():
         print(summarize(json.load(open(args.summarize))), end="")
         return
     sys.path.insert(0, ROOT)
+    global MODEL
+    MODEL = args.model
     t0 = time.time()
     qs = [round(0.1 * k, 1) for k in range(10)]
     res = {"command": "python3 -m paper_2203_04508_amd.qsweep " + " ".join(sys.argv[1:]),
-           "box": [NX, NY], "first_fluid_row": Y1, "drop_radius": R0, "T_over_Tc": T_OVER_TC, "tau": TAU,
+           "model": MODEL, "box": [NX, NY], "first_fluid_row": Y1, "drop_radius": R0,
+           "T_over_Tc": MODELS[MODEL]["T_over_Tc"], "tau": MODELS[MODEL]["tau"], "collision": MODELS[MODEL]["collision"],
            "precision": "f64", "steps": args.steps, "angles": []}
     for target in (60.0, 120.0):
         phi, log = calibrate(target, args.calib_steps)

@@ -36,6 +36,14 @@ MAXWELL = {
     0.60: (3.08145853870e-3, 0.406204139769006),
 }
 
+# Peng-Robinson with the paper's a = 2/49, b = 2/21, R = 1, omega = 0.344 (Sec. 2.2): critical
+# temperature and the Maxwell coexistence densities at 0.8 T_c (tests recompute both from the EOS),
+# and the chemical-potential model settings the workloads use with it: mesh scaling k, gradient
+# coefficient kappa, interface width of the initial profile
+PR_TC = 0.07291903717300727
+PR_MAXWELL = {0.80: (0.19707941281764169, 7.204048715994298)}
+CP_K, CP_KAPPA, CP_WIDTH = 0.2, 0.01, 6.0
+
 KIND_BALL = 1
 KIND_BAND_Y = 2
 
@@ -262,6 +270,21 @@ def phi_for_walls(wl: Workload, wall_nodes: np.ndarray) -> np.ndarray:
         rng = np.random.Generator(np.random.PCG64(wl.extra["phi_seed"] + 1000))
         return rng.uniform(*PHI_RANGE, len(wall_nodes))
     return wl.phi_group[wall_groups(wl, wall_nodes)].astype(np.float64)
+
+
+def chempot_inputs(wl: Workload, wall_nodes: np.ndarray, T_over_Tc: float = 0.80):
+    """Inputs of a workload's geometry for the chemical-potential model: the drops at the Peng-
+    Robinson coexistence densities (tanh width CP_WIDTH), and per wall node an assigned chemical
+    potential: the bulk value of eq. 12 at coexistence, k^2 mu_PR(rho_v), scaled by the workload's
+    wettability factor (the same draw as phi_for_walls)."""
+    rv, rl = PR_MAXWELL[T_over_Tc]
+    rho0 = drop_field(wl.dims, wl.dim, wl.drops, rv, rl, CP_WIDTH)
+    mu_coex = CP_K * CP_K * MU_PR_COEX[T_over_Tc]
+    return rho0, mu_coex * phi_for_walls(wl, wall_nodes), rv
+
+
+# eq. 11 without the gradient term at the coexistence densities above (equal for both phases)
+MU_PR_COEX = {0.80: 0.2657526990499132}
 
 
 def random_links_case(rng, dims, dim, n_balls, rlo, rhi):

@@ -45,12 +45,12 @@ def test_struct_layouts_match_header(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "mcb.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(mcb_params), sizeof(mcb_shape),"
         " sizeof(mcb_link), sizeof(mcb_sizes), sizeof(mcb_buffers), sizeof(mcb_mass_report),"
-        " offsetof(mcb_params, gravity)); return 0;}\n")
+        " offsetof(mcb_params, cp_kappa)); return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(mcb.mcb_params), C.sizeof(mcb.mcb_shape), C.sizeof(mcb.mcb_link), C.sizeof(mcb.mcb_sizes),
-            C.sizeof(mcb.mcb_buffers), C.sizeof(mcb.mcb_mass_report), mcb.mcb_params.gravity.offset]
+            C.sizeof(mcb.mcb_buffers), C.sizeof(mcb.mcb_mass_report), mcb.mcb_params.cp_kappa.offset]
     assert got == want
     assert mcb.LINK_DTYPE.itemsize == C.sizeof(mcb.mcb_link)
 
@@ -100,6 +100,22 @@ def test_host_side_argument_checks(lib):
         with pytest.raises(mcb.MCBError) as ei:
             mcb.mcb_create(bad)
         assert ei.value.code == mcb.MCB_EINVAL
+    # chemical-potential model: D2Q9 only, k > 0, kappa >= 0; G is not used
+    pc = mcb.mcb_params(2, 64, 64, 1, 1.0, 0.0, 2 / 49, 2 / 21, 1.0, 0.058, mcb.MCB_F64, 0, 0.0)
+    pc.model, pc.pr_omega, pc.cp_k, pc.cp_kappa = mcb.MCB_MODEL_CHEMPOT, 0.344, 0.2, 0.01
+    mcb.mcb_destroy(mcb.mcb_create(pc))
+    for k, v in (("cp_k", 0.0), ("cp_kappa", -1.0), ("model", 2)):
+        bad = mcb.mcb_params(2, 64, 64, 1, 1.0, 0.0, 2 / 49, 2 / 21, 1.0, 0.058, mcb.MCB_F64, 0, 0.0)
+        bad.model, bad.pr_omega, bad.cp_k, bad.cp_kappa = mcb.MCB_MODEL_CHEMPOT, 0.344, 0.2, 0.01
+        setattr(bad, k, v)
+        with pytest.raises(mcb.MCBError) as ei:
+            mcb.mcb_create(bad)
+        assert ei.value.code == mcb.MCB_EINVAL
+    pc3 = mcb.mcb_params(3, 16, 16, 16, 1.0, 0.0, 2 / 49, 2 / 21, 1.0, 0.058, mcb.MCB_F64, 0, 0.0)
+    pc3.model, pc3.pr_omega, pc3.cp_k, pc3.cp_kappa = mcb.MCB_MODEL_CHEMPOT, 0.344, 0.2, 0.01
+    with pytest.raises(mcb.MCBError) as ei:
+        mcb.mcb_create(pc3)
+    assert ei.value.code == mcb.MCB_ENOTSUP
     p3.bc_mode, p3.collision, p3.s_e, p3.s_eps, p3.s_q = 0, mcb.MCB_COLL_MRT, 1.64, 1.54, 1.7
     with pytest.raises(mcb.MCBError) as ei:
         mcb.mcb_create(p3)

@@ -1,0 +1,165 @@
+"""GPU parity of the chemical-potential multiphase model (Secs. 2.2-2.3 of arXiv 2203.04508: Peng-
+Robinson EOS, eqs. 9-12, two-layer eq. 15, assigned wall chemical potential) against the FP64
+oracle, through the C ABI.
+
+Bars: FP64 populations within 1e-12 relative per step (k steps: k 1e-12) and 1e-9 after 1000
+steps, mass to 1e-12; FP32 storage within 2e-5 per step; the velocity output and the largest speed
+within 1e-10 (FP64) of the oracle's.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle, thermo
+from paper_2203_04508_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RC, TC = thermo.critical_point_pr()
+TR, K, KAPPA = 0.8, 0.2, 0.01
+T = TR * TC
+RV, RL = thermo.maxwell_pr(T)
+MU_COEX = K * K * oracle.pr_mu(RV, T)  # eq. 12 bulk potential at coexistence
+
+
+def banner(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mcb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_04508_amd import mcb as m
+    m.load()
+    return m
+
+
+def rel_err(a, b, fluid):
+    worst = 0.0
+    for i in range(a.shape[0]):
+        d = np.abs(a[i, fluid] - b[i, fluid]).max()
+        s = np.abs(b[i, fluid]).max()
+        worst = max(worst, d / s)
+    return worst
+
+
+def build_pair(mcb, dims, tau, shapes, mu_s, q_override=None, precision="f64", rho_ref=0.0, collision="bgk",
+               bc_mode="present", g=(0.0, 0.0)):
+    P = oracle.make_params(2, *dims, tau=tau, T=0.05)
+    solid = oracle.classify(P, shapes)
+    node, d, cls, q = oracle.links(P, shapes, solid)
+    lat = mcb.Lattice(2, dims, tau, T, precision=precision, rho_ref=rho_ref, collision=collision, bc_mode=bc_mode,
+                      gravity=g, model="chempot", cp_k=K, cp_kappa=KAPPA)
+    nl, nb, nw = lat.set_geometry(shapes)
+    assert nl == len(node)
+    if q_override is not None:
+        q = q_override(q).astype(np.uint32)
+        got = lat.links()
+        got["q_fixed"] = q
+        lat.set_links(got)
+    sim = oracle.Sim(P, solid, node, d, q)
+    sim.set_chempot(T, k=K, kappa=KAPPA)
+    sim.set_bc_mode({"present": 0, "ibc": 1, "mibc": 2, "hbbc": 3}[bc_mode])
+    sim.set_gravity(g)
+    if collision == "mrt":
+        sim.set_mrt()
+    mu_s = np.broadcast_to(np.asarray(mu_s, np.float64), (nw,)).copy()
+    sim.set_mu_wall(mu_s)
+    lat.set_wettability(mu_s)
+    return sim, lat, solid == 0
+
+
+def random_state(rng, rho_field):
+    N = len(rho_field)
+    u = rng.uniform(-0.01, 0.01, (N, 2))
+    f = np.stack([oracle.equilibrium(2, rho_field[x], u[x]) for x in range(N)], axis=1)
+    return f * (1.0 + 0.005 * rng.standard_normal(f.shape))
+
+
+CASES = [("300x70-ragged", (300, 70, 1), 61, None, "bgk", "present"),
+         ("37x29-random-q", (37, 29, 1), 62, "random", "bgk", "present"),
+         ("300x70-mrt-mibc", (300, 70, 1), 63, None, "mrt", "mibc")]
+
+
+@pytest.mark.parametrize("name,dims,seed,qmode,coll,mode", CASES, ids=[c[0] for c in CASES])
+def test_chempot_step_parity_small(mcb, name, dims, seed, qmode, coll, mode):
+    banner(f"chemical-potential step parity {name}")
+    rng = np.random.default_rng(seed)
+    shapes = W.random_links_case(rng, dims, 2, max(3, dims[0] * dims[1] // 900), 2.0, 6.0)
+    drops = [((rng.uniform(0, dims[0]), rng.uniform(0, dims[1])), rng.uniform(5, 9)) for _ in range(3)]
+    rho = W.drop_field(dims, 2, drops, RV, RL, 6.0)
+    qo = (lambda q: rng.integers(0, 65537, len(q))) if qmode == "random" else None
+    sim, lat, fluid = build_pair(mcb, dims, 0.8, shapes, MU_COEX * rng.uniform(0.9, 1.1), qo, collision=coll,
+                                 bc_mode=mode)
+    f0 = random_state(rng, rho)
+    sim.set_f(f0)
+    lat.set_f(f0)
+    assert rel_err(lat.get_f(), sim.get_f(), fluid) < 1e-13
+    for k in range(1, 21):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < 1e-12 * k, (k, e)
+    rep = lat.mass()
+    assert abs(rep.dM_last - sim.dm_last()) < 1e-12 * max(1.0, abs(sim.dm_last()))
+    # velocity output (the eq. 9 force from the fields) and the largest speed
+    _, v_o, _ = sim.moments()
+    _, v_g = lat.moments()
+    assert np.abs(v_g - v_o)[:, fluid].max() < 1e-10 * np.abs(v_o).max()
+    s = np.sqrt((v_o ** 2).sum(0))
+    s[~fluid] = -1.0
+    vg, ng = lat.max_speed()
+    assert abs(vg - s.max()) <= 1e-10 * s.max()
+    lat.close()
+
+
+def test_chempot_c0_1000_steps_and_mass(mcb):
+    banner("c0 chemical-potential model, 1000 steps")
+    wl = W.make("c0")
+    rho0 = W.drop_field(wl.dims, 2, wl.drops, RV, RL, 6.0)
+    sim, lat, fluid = build_pair(mcb, wl.dims, 1.0, wl.shapes, MU_COEX)
+    sim.init_eq(rho0)
+    lat.init_equilibrium(rho0)
+    assert rel_err(lat.get_f(), sim.get_f(), fluid) < 1e-13
+    M0 = lat.mass().M
+    sim.step(1000)
+    lat.step(1000)
+    e = rel_err(lat.get_f(), sim.get_f(), fluid)
+    assert e < 1e-9, e
+    assert abs(lat.mass().M - M0) / M0 < 1e-12
+    lat.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("f32s", 2e-5)])
+def test_chempot_c1_fp32(mcb, prec, tol):
+    banner(f"c1 chemical-potential model {prec}, 3 steps")
+    wl = W.make("c1")
+    rho0 = W.drop_field(wl.dims, 2, wl.drops, RV, RL, 6.0)
+    sim, lat, fluid = build_pair(mcb, wl.dims, 1.0, wl.shapes, MU_COEX, precision=prec, rho_ref=RV)
+    sim.init_eq(rho0)
+    lat.init_equilibrium(rho0)
+    for k in range(1, 4):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < tol * (k + 1), (k, e)
+    lat.close()
+
+
+def test_chempot_unsupported(mcb):
+    banner("chemical-potential model: 3-D and reverse mode are MCB_ENOTSUP")
+    with pytest.raises(mcb.MCBError) as ei:
+        mcb.Lattice(3, (8, 8, 8), 1.0, T, model="chempot", cp_k=K, cp_kappa=KAPPA)
+    assert ei.value.code == -7
+    wl = W.make("c0")
+    lat = mcb.Lattice(2, wl.dims, 1.0, T, model="chempot", cp_k=K, cp_kappa=KAPPA)
+    lat.set_geometry(wl.shapes)
+    lat.set_wettability(MU_COEX)
+    with pytest.raises(mcb.MCBError) as ei:
+        lat.adj_forward(W.drop_field(wl.dims, 2, wl.drops, RV, RL, 6.0), 10, 5)
+    assert ei.value.code == -7
+    lat.close()

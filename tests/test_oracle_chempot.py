@@ -137,3 +137,11 @@ def test_mass_conserved_with_curved_walls():
     dm = sim.step(1000, record_dm=True)
     assert abs(sim.mass() - M0) / M0 < 1e-12
     assert np.abs(dm).max() > 0.0
+
+
+def test_workload_constants_recomputed():
+    """The Peng-Robinson constants the input generator carries are the EOS's own."""
+    assert abs(W.PR_TC / TC - 1) < 1e-13
+    rv, rl = thermo.maxwell_pr(0.8 * TC)
+    assert abs(W.PR_MAXWELL[0.80][0] / rv - 1) < 1e-9 and abs(W.PR_MAXWELL[0.80][1] / rl - 1) < 1e-9
+    assert abs(W.MU_PR_COEX[0.80] - oracle.pr_mu(rv, 0.8 * TC)) < 1e-12
