@@ -22,6 +22,10 @@ Sec. 4.4); the step at which a run stopped on a psi domain error, if it did.
 
     python -m paper_2203_04508_amd.qsweep [--model pseudo|chempot] [--steps 20000] [--out profiles/qsweep_flat.json]
     python -m paper_2203_04508_amd.qsweep --summarize profiles/qsweep_flat.json   (text table)
+
+With --geometry curved, the setting of Sec. 4.2 (Figs. 5-6): a 500 x 600 box, a cylinder of radius
+100 (off-lattice centre, so q varies along the wall) and a drop of radius 70 centred on its top;
+the wettability is the flat substrate's calibration, each scheme runs --steps steps.
 """
 from __future__ import annotations
 
@@ -185,6 +189,82 @@ def run(mode, q, phi, steps, every):
     return out
 
 
+CNX, CNY, RCYL, RDROP = 500, 600, 100.0, 70.0
+CYL = (250.3, 200.7)
+
+
+def curved_lattice(mode, w):
+    """The Sec. 4.2 geometry with wettability w (as in make_lattice), initial state set."""
+    from paper_2203_04508_amd import mcb, workloads as W
+
+    m = MODELS[MODEL]
+    rv, rl = _densities()
+    shapes = np.array([W.ball(CYL, RCYL, 0)], np.int64)
+    rho0 = W.drop_field((CNX, CNY, 1), 2, [((CYL[0], CYL[1] + RCYL), RDROP)], rv, rl, m["width"])
+    if MODEL == "chempot":
+        w = W.CP_K * W.CP_K * W.MU_PR_COEX[m["T_over_Tc"]] + w
+        lat = mcb.Lattice(2, (CNX, CNY, 1), m["tau"], m["T_over_Tc"] * W.PR_TC, precision="f64", bc_mode=mode,
+                          collision=m["collision"], model="chempot", cp_k=W.CP_K, cp_kappa=W.CP_KAPPA)
+    else:
+        lat = mcb.Lattice(2, (CNX, CNY, 1), m["tau"], m["T_over_Tc"] * W.CS_TC, precision="f64", bc_mode=mode,
+                          collision=m["collision"])
+    try:
+        lat.set_geometry(shapes)
+        lat.set_wettability(w)
+        lat.init_equilibrium(rho0)
+    except mcb.MCBError:
+        lat.close()
+        raise
+    return lat, rv, rl
+
+
+def run_curved(mode, w, steps, every):
+    from paper_2203_04508_amd import mcb
+
+    lat, rv, rl = curved_lattice(mode, w)
+    M0 = lat.mass().M
+    ts, m, dm = [0], [0.0], [0.0]
+    failed = None
+    t = n = 0
+    try:
+        while t < steps:
+            n = min(every, steps - t)
+            lat.step(n)
+            t += n
+            rep = lat.mass()
+            ts.append(t)
+            m.append((rep.M - M0) / M0)
+            dm.append(rep.dM_last)
+    except mcb.MCBError as e:
+        failed = {"step_before": t + n, "error": str(e)}
+    out = {"mode": mode, "t": ts, "drift": m, "dM_last": dm, "failed": failed}
+    if failed is None:
+        rho, _ = lat.moments()
+        out["liquid_nodes_end"] = int((rho > 0.5 * (rv + rl)).sum())
+        out["max_speed_end"] = lat.max_speed()[0]
+    lat.close()
+    return out
+
+
+def summarize_curved(res) -> str:
+    lines = [f"curved-substrate runs, model {res['model']}, {res['box'][0]}x{res['box'][1]} D2Q9 FP64, cylinder r "
+             f"{res['cylinder_radius']}, drop r {res['drop_radius']}, {res['steps']} steps, T/Tc {res['T_over_Tc']}, "
+             f"tau {res['tau']}", f"command: {res['command']}"]
+    for a in res["angles"]:
+        lines.append("")
+        lines.append(f"target {a['target_deg']:.0f} deg (flat calibration, wettability {a['phi']:.5f})")
+        lines.append("  scheme   M/M0-1 at steps " + " ".join(f"{t:>9d}" for t in a["runs"][0]["t"][1::max(1, len(a['runs'][0]['t']) // 5)]) +
+                     "   liquid nodes   max|v|    max|dM| last quarter")
+        for r in a["runs"]:
+            idx = list(range(1, len(r["t"]), max(1, len(a['runs'][0]['t']) // 5)))
+            vals = " ".join(f"{r['drift'][k]:+9.2e}" if k < len(r["drift"]) else f"{'-':>9s}" for k in idx)
+            k0 = 3 * len(r["dM_last"]) // 4
+            tail = (f"   {r['liquid_nodes_end']:10d}   {r['max_speed_end']:.2e}" if r["failed"] is None
+                    else f"   stopped before step {r['failed']['step_before']}")
+            lines.append(f"  {r['mode']:7s}  {vals}{tail}   {max(abs(v) for v in r['dM_last'][k0:]):.2e}")
+    return "\n".join(lines) + "\n"
+
+
 def _round(x, sig=6):
     if isinstance(x, float):
         return float(f"{x:.{sig}g}")
@@ -231,18 +311,43 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--summarize", default=None, help="print the text table of a stored result")
     ap.add_argument("--model", default="pseudo", choices=list(MODELS))
+    ap.add_argument("--geometry", default="flat", choices=["flat", "curved"])
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--every", type=int, default=1000)
     ap.add_argument("--calib-steps", type=int, default=10000)
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     if args.summarize:
-        print(summarize(json.load(open(args.summarize))), end="")
+        res = json.load(open(args.summarize))
+        print((summarize_curved(res) if res.get("geometry") == "curved" else summarize(res)), end="")
         return
     sys.path.insert(0, ROOT)
     global MODEL
     MODEL = args.model
     t0 = time.time()
+    if args.geometry == "curved":
+        res = {"command": "python3 -m paper_2203_04508_amd.qsweep " + " ".join(sys.argv[1:]), "geometry": "curved",
+               "model": MODEL, "box": [CNX, CNY], "cylinder_radius": RCYL, "cylinder_centre": list(CYL),
+               "drop_radius": RDROP, "T_over_Tc": MODELS[MODEL]["T_over_Tc"], "tau": MODELS[MODEL]["tau"],
+               "collision": MODELS[MODEL]["collision"], "precision": "f64", "steps": args.steps, "angles": []}
+        for target in (60.0, 120.0):
+            w, log = calibrate(target, args.calib_steps)
+            ang = {"target_deg": target, "phi": w, "runs": []}
+            for mode in ("present", "ibc", "mibc", "hbbc"):
+                r = run_curved(mode, w, args.steps, args.every)
+                ang["runs"].append(r)
+                f = r["failed"]
+                print(f"[qsweep] curved {target:.0f} deg {mode:7s}: M/M0-1 {r['drift'][-1]:+.3e}"
+                      + (f" stopped: {f['error']}" if f else f", liquid nodes {r['liquid_nodes_end']}, max|v| {r['max_speed_end']:.2e}"),
+                      file=sys.stderr, flush=True)
+            res["angles"].append(ang)
+        res["wall_seconds"] = time.time() - t0
+        res = _round(res)
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(json.dumps(res, separators=(",", ":")) + "\n")
+        print(summarize_curved(res), end="")
+        return
     qs = [round(0.1 * k, 1) for k in range(10)]
     res = {"command": "python3 -m paper_2203_04508_amd.qsweep " + " ".join(sys.argv[1:]),
            "model": MODEL, "box": [NX, NY], "first_fluid_row": Y1, "drop_radius": R0,
