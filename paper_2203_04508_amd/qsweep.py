@@ -25,7 +25,9 @@ Sec. 4.4); the step at which a run stopped on a psi domain error, if it did.
 
 With --geometry curved, the setting of Sec. 4.2 (Figs. 5-6): a 500 x 600 box, a cylinder of radius
 100 (off-lattice centre, so q varies along the wall) and a drop of radius 70 centred on its top;
-the wettability is the flat substrate's calibration, each scheme runs --steps steps.
+the wettability is the flat substrate's calibration, each scheme runs --steps steps.  With
+--geometry curved-angles, the spurious currents of Sec. 4.4 (Fig. 10) on that geometry: contact
+angles 50 to 170 degrees (--angles), the present scheme against MIBC, the largest speed at the end.
 """
 from __future__ import annotations
 
@@ -265,6 +267,21 @@ def summarize_curved(res) -> str:
     return "\n".join(lines) + "\n"
 
 
+def summarize_angles(res) -> str:
+    lines = [f"spurious currents on the curved substrate, model {res['model']}, {res['box'][0]}x{res['box'][1]}, "
+             f"cylinder r {res['cylinder_radius']}, drop r {res['drop_radius']}, {res['steps']} steps",
+             f"command: {res['command']}", "",
+             "  target  flat-calibrated  | max|v| present   max|v| MIBC   ratio | M/M0-1 present   MIBC"]
+    for r in res["rows"]:
+        p, m = r["present"], r["mibc"]
+        vp, vm = p["max_speed_end"], m["max_speed_end"]
+        ratio = f"{vm / vp:6.1f}" if vp and vm else "     -"
+        fmt = lambda v: f"{v:.2e}" if v is not None else "stopped "
+        lines.append(f"  {r['target_deg']:6.0f}  {r['theta_flat']:15.1f}  |   {fmt(vp)}        {fmt(vm)}   {ratio} |"
+                     f" {p['drift']:+.1e}       {m['drift']:+.1e}")
+    return "\n".join(lines) + "\n"
+
+
 def _round(x, sig=6):
     if isinstance(x, float):
         return float(f"{x:.{sig}g}")
@@ -311,7 +328,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--summarize", default=None, help="print the text table of a stored result")
     ap.add_argument("--model", default="pseudo", choices=list(MODELS))
-    ap.add_argument("--geometry", default="flat", choices=["flat", "curved"])
+    ap.add_argument("--geometry", default="flat", choices=["flat", "curved", "curved-angles"])
+    ap.add_argument("--angles", default="50,70,90,110,130,150,170")
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--every", type=int, default=1000)
     ap.add_argument("--calib-steps", type=int, default=10000)
@@ -319,12 +337,36 @@ def main():
     args = ap.parse_args()
     if args.summarize:
         res = json.load(open(args.summarize))
-        print((summarize_curved(res) if res.get("geometry") == "curved" else summarize(res)), end="")
+        g = res.get("geometry")
+        print((summarize_curved(res) if g == "curved" else summarize_angles(res) if g == "curved-angles"
+               else summarize(res)), end="")
         return
     sys.path.insert(0, ROOT)
     global MODEL
     MODEL = args.model
     t0 = time.time()
+    if args.geometry == "curved-angles":
+        res = {"command": "python3 -m paper_2203_04508_amd.qsweep " + " ".join(sys.argv[1:]), "geometry": "curved-angles",
+               "model": MODEL, "box": [CNX, CNY], "cylinder_radius": RCYL, "drop_radius": RDROP,
+               "T_over_Tc": MODELS[MODEL]["T_over_Tc"], "tau": MODELS[MODEL]["tau"], "steps": args.steps, "rows": []}
+        for target in [float(a) for a in args.angles.split(",")]:
+            w, log = calibrate(target, args.calib_steps)
+            th = equilibrium_angle(w, args.calib_steps)
+            row = {"target_deg": target, "phi": w, "theta_flat": th}
+            for mode in ("present", "mibc"):
+                r = run_curved(mode, w, args.steps, args.steps)
+                row[mode] = {"drift": r["drift"][-1], "max_speed_end": r.get("max_speed_end"),
+                             "failed": r["failed"]}
+            print(f"[qsweep] curved angle {target:.0f} (flat {th:.1f}): present {row['present']['max_speed_end']}, "
+                  f"mibc {row['mibc']['max_speed_end']}", file=sys.stderr, flush=True)
+            res["rows"].append(row)
+        res["wall_seconds"] = time.time() - t0
+        res = _round(res)
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(json.dumps(res, separators=(",", ":")) + "\n")
+        print(summarize_angles(res), end="")
+        return
     if args.geometry == "curved":
         res = {"command": "python3 -m paper_2203_04508_amd.qsweep " + " ".join(sys.argv[1:]), "geometry": "curved",
                "model": MODEL, "box": [CNX, CNY], "cylinder_radius": RCYL, "cylinder_centre": list(CYL),
