@@ -134,7 +134,35 @@ def test_chempot_c0_1000_steps_and_mass(mcb):
     lat.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("f32s", 2e-5)])
+@pytest.mark.parametrize("dims,walls", [((5, 4, 1), False), ((3, 7, 1), False), ((13, 11, 1), True)])
+def test_chempot_tiny_lattices_wrap(mcb, dims, walls):
+    """Lattices of 3-13 nodes a side: the two-node stencils wrap through most of the box."""
+    banner(f"chemical-potential tiny lattice {dims} walls={walls}")
+    rng = np.random.default_rng(71 + dims[0])
+    shapes = W.random_links_case(rng, dims, 2, 1, 1.5, 2.5) if walls else np.zeros((0, 8), np.int64)
+    rho = rng.uniform(0.5 * RV + 0.5 * RL - 1.0, 0.5 * RV + 0.5 * RL + 1.0, int(np.prod(dims)))
+    if walls:
+        sim, lat, fluid = build_pair(mcb, dims, 0.9, shapes, MU_COEX)
+    else:
+        P = oracle.make_params(2, *dims, tau=0.9, T=0.05)
+        e0 = np.zeros(0, np.int64)
+        sim = oracle.Sim(P, np.zeros(len(rho), np.uint8), e0, e0.astype(np.int32), e0.astype(np.uint32))
+        sim.set_chempot(T, k=K, kappa=KAPPA)
+        lat = mcb.Lattice(2, dims, 0.9, T, model="chempot", cp_k=K, cp_kappa=KAPPA)
+        lat.set_geometry(np.zeros((0, 8), np.int64))
+        fluid = np.ones(len(rho), bool)
+    f0 = random_state(rng, rho)
+    sim.set_f(f0)
+    lat.set_f(f0)
+    for k in range(1, 11):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < 1e-12 * k, (k, e)
+    lat.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("f32s", 2e-5), ("f16s", 3e-3)])
 def test_chempot_c1_fp32(mcb, prec, tol):
     banner(f"c1 chemical-potential model {prec}, 3 steps")
     wl = W.make("c1")
