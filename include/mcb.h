@@ -265,8 +265,9 @@ mcb_status mcb_timing_report(mcb_ctx* ctx, double* ms, int64_t* launches);
 enum { MCB_LOSS_COM_X = 0, MCB_LOSS_WETTED_LENGTH = 1, MCB_LOSS_TOTAL_MASS = 2 };
 
 /* Device bytes of the reverse-mode arena for nsteps >= 0 steps with a checkpoint every k >= 1
- * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_MODEL_PSEUDO with MCB_BC_PRESENT,
- * MCB_COLL_BGK and no body force: the adjoint calls return MCB_ENOTSUP otherwise. */
+ * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_MODEL_PSEUDO with every boundary
+ * scheme, both collisions and the body force; the adjoint calls return MCB_ENOTSUP for
+ * MCB_MODEL_CHEMPOT. */
 mcb_status mcb_adj_required_bytes(mcb_ctx* ctx, int64_t nsteps, int64_t k, int64_t* bytes);
 
 /* Binds the caller-owned reverse-mode arena (device memory, at least the required bytes, 256-byte

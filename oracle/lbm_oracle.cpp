@@ -970,8 +970,9 @@ void or_sim_destroy(void* h) { delete static_cast<Sim<double>*>(h); }
 
 // multiple-relaxation-time collision for later collisions (D2Q9 only): S of eq. 3 with the given
 // s_e, s_epsilon, s_q, and s_nu = 1/tau; each rate in (0, 2)
-int or_sim_set_mrt(void* h, double se, double seps, double sq) {
-    auto* S = static_cast<Sim<double>*>(h);
+extern "C++" {
+template <class R>
+static int set_mrt(Sim<R>* S, double se, double seps, double sq) {
     if (S->L.Q != 9) return -1;
     for (double r : {se, seps, sq})
         if (!(r > 0.0 && r < 2.0)) return -1;
@@ -982,6 +983,8 @@ int or_sim_set_mrt(void* h, double se, double seps, double sq) {
     S->mrt.on = true;
     return 0;
 }
+}  // extern "C++"
+int or_sim_set_mrt(void* h, double se, double seps, double sq) { return set_mrt(static_cast<Sim<double>*>(h), se, seps, sq); }
 
 // the chemical-potential model (2-D) for later collisions: PR parameters a, b, R, temperature T,
 // acentric factor omega, mesh scaling k and gradient coefficient kappa (eqs. 9-12)
@@ -1041,8 +1044,9 @@ double or_pr_mu(double a, double b, double R, double T, double omega, double rho
 void or_pr_critical(double a, double b, double R, double* Tc, double* rhoc) { pr_critical(a, b, R, Tc, rhoc); }
 
 // uniform body acceleration for later collisions (components beyond the lattice's dimension are 0)
-int or_sim_set_gravity(void* h, double gx, double gy, double gz) {
-    auto* S = static_cast<Sim<double>*>(h);
+extern "C++" {
+template <class R>
+static int set_gravity(Sim<R>* S, double gx, double gy, double gz) {
     if (!std::isfinite(gx) || !std::isfinite(gy) || !std::isfinite(gz)) return -1;
     if (S->L.dim == 2 && gz != 0.0) return -1;
     S->grav[0] = gx;
@@ -1050,6 +1054,8 @@ int or_sim_set_gravity(void* h, double gx, double gy, double gz) {
     S->grav[2] = gz;
     return 0;
 }
+}  // extern "C++"
+int or_sim_set_gravity(void* h, double gx, double gy, double gz) { return set_gravity(static_cast<Sim<double>*>(h), gx, gy, gz); }
 
 // boundary scheme of later steps: 0 present (eqs. 16-18), 1 IBC, 2 MIBC, 3 halfway bounce-back
 int or_sim_set_bc_mode(void* h, int mode) {
@@ -1197,6 +1203,17 @@ static int dfinish(Sim<Dual>* S) {
         if (S->fluid(x))
             for (int i = 0; i < S->L.Q; ++i)
                 if (!finite(S->ft[i * S->g.N + x])) return -5;
+    return 0;
+}
+
+// the collision, body force and boundary scheme of the dual-number simulation (as or_sim_set_*)
+int or_dsim_set_mrt(void* h, double se, double seps, double sq) { return set_mrt(static_cast<Sim<Dual>*>(h), se, seps, sq); }
+int or_dsim_set_gravity(void* h, double gx, double gy, double gz) {
+    return set_gravity(static_cast<Sim<Dual>*>(h), gx, gy, gz);
+}
+int or_dsim_set_bc_mode(void* h, int mode) {
+    if (mode < 0 || mode > 3) return -1;
+    static_cast<Sim<Dual>*>(h)->bc_mode = mode;
     return 0;
 }
 

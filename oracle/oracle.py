@@ -126,6 +126,12 @@ def lib():
         L.or_dsim_destroy.argtypes = [vp]
         L.or_dsim_set_phi.argtypes = [vp, vp, vp]
         L.or_dsim_set_phi.restype = C.c_int
+        L.or_dsim_set_mrt.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+        L.or_dsim_set_mrt.restype = C.c_int
+        L.or_dsim_set_gravity.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+        L.or_dsim_set_gravity.restype = C.c_int
+        L.or_dsim_set_bc_mode.argtypes = [vp, C.c_int]
+        L.or_dsim_set_bc_mode.restype = C.c_int
         L.or_dsim_init_eq.argtypes = [vp, vp]
         L.or_dsim_init_eq.restype = C.c_int
         L.or_dsim_step.argtypes = [vp, C.c_int64]
@@ -427,6 +433,16 @@ class DualSim:
             d = np.zeros((self.kd, len(phi)))
             d[: directions.shape[0]] = directions
         Sim._check(lib().or_dsim_set_phi(self.h, _p(phi), _p(d) if d is not None else None), "set_phi")
+
+    def set_mrt(self, se=1.64, seps=1.54, sq=1.7):
+        Sim._check(lib().or_dsim_set_mrt(self.h, se, seps, sq), "set_mrt")
+
+    def set_gravity(self, g):
+        g = list(g) + [0.0] * (3 - len(g))
+        Sim._check(lib().or_dsim_set_gravity(self.h, *map(float, g)), "set_gravity")
+
+    def set_bc_mode(self, mode: int):
+        Sim._check(lib().or_dsim_set_bc_mode(self.h, int(mode)), "set_bc_mode")
 
     def init_eq(self, rho0):
         rho0 = np.ascontiguousarray(rho0, np.float64).reshape(-1)

@@ -17,12 +17,14 @@
 //        eq. 16: c1 = 2q, c2 = c3 = 1 - 2q, o = f_j(x - e_j); bounce-back: c1 = 1, c2 = c3 = 0;
 //        eq. 17: c1 = 1/(2q), c2 = c3 = 1 - 1/(2q), o = f_opp(j)(x)
 //   eq. 18:               p_0(x) += sum_links (f_j(x) - B_j)
+//   the comparison schemes weight the forcing term R by kF and the eq. 18 sum by k18 (0 or 1)
 //   collision, with E_i(rho, m) = w_i (rho + 3 e_i.m + (4.5 (e_i.m)^2 - 1.5 m.m) / rho), the
-//   equilibrium of eq. 14 written with the momentum m = rho u:
-//        g'_i = p_i (1 - 1/tau) + (1/tau - 1) E_i(rho, j) + E_i(rho, j + F),   R'_i = E_i(rho, j + F) - E_i(rho, j)
-//   rho = sum p, j = sum p e, F = -G psi(x) sum_k w^_k psi(x + e_k) e_k, psi = psi(rho) on fluid
-//   nodes and psi(phi_s rho_ave(s)) on wall nodes s, rho_ave the eq. 15 weighted mean of the
-//   fluid neighbours' densities.
+//   equilibrium of eq. 14 written with the momentum m = rho u, and K = M^-1 S M (eqs. 1-4; BGK:
+//   K = I / tau):
+//        g' = (I - K) p + (K - I) E(rho, j) + E(rho, j + F),   R'_i = E_i(rho, j + F) - E_i(rho, j)
+//   (the MRT equilibria are M E(rho, j)), rho = sum p, j = sum p e, F = -G psi(x) sum_k w^_k
+//   psi(x + e_k) e_k + rho g, psi = psi(rho) on fluid nodes and psi(phi_s rho_ave(s)) on wall
+//   nodes s, rho_ave the eq. 15 weighted mean of the fluid neighbours' densities.
 // The kernels below apply the transposes of these maps in reverse order; every scatter of the
 // forward map becomes a gather, so each output is written by exactly one thread and the result is
 // deterministic.
@@ -57,7 +59,19 @@ struct AdjDev {
     const double* phi;           // wettability factor per wall node
     int fs;                      // stride of the boundary records
     double tau, G, RT, a, b4, rho_ref;
+    double kF, k18;              // boundary scheme: weights of the forcing term and of eq. 18
+    double grav[3];              // body acceleration
+    int mrt;                     // 1: K = M^-1 S M with msc[k] = s_k / |row k of M|^2 (D2Q9)
+    double msc[9];
 };
+
+// D2Q9 moment matrix of eq. 2 (rows rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy); its rows are
+// orthogonal, so M^-1 = M^T diag(1 / |row k|^2)
+__device__ constexpr int kM2[9][9] = {{1, 1, 1, 1, 1, 1, 1, 1, 1},     {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+                                      {4, -2, -2, -2, -2, 1, 1, 1, 1},  {0, 1, 0, -1, 0, 1, -1, -1, 1},
+                                      {0, -2, 0, 2, 0, 1, -1, -1, 1},   {0, 0, 1, 0, -1, 1, 1, -1, -1},
+                                      {0, 0, -2, 0, 2, 1, 1, -1, -1},   {0, 1, -1, 1, -1, 0, 0, 0, 0},
+                                      {0, 0, 0, 0, 0, 1, -1, 1, -1}};
 
 // boundary index of a boundary node's tag
 __device__ inline int64_t bidx(const AdjDev& A, int tg) { return A.L == 0 ? int64_t(tg >> 8) : int64_t(tg - 1); }
@@ -148,11 +162,11 @@ __global__ void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __rest
                 const double o = a < 0.0 ? ldf<S>(gt, A, c_opp[A.L][j], x)
                                          : (A.tag[nbr(A.g, A.L, x, j, -1)] >= 0 ? ldf<S>(gt, A, j, nbr(A.g, A.L, x, j, -1)) : 0.0);
                 const double c1 = fabs(a), c2 = 1.0 - c1;
-                const double B = c1 * fj + c2 * (o + Fj);
+                const double B = c1 * fj + c2 * (o + A.kF * Fj);
                 v[c_opp[A.L][j]] = B;
                 dm += fj - B;
             }
-            v[0] += dm;
+            v[0] += A.k18 * dm;
         }
         double r = 0.0;
         for (int i = 0; i < Q; ++i) {
@@ -216,7 +230,25 @@ __global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double
             S[2] += w * c_ez[L][k];
         }
         const double gp = -A.G * psi[x];
-        const double F[3] = {gp * S[0], gp * S[1], gp * S[2]};
+        const double F[3] = {gp * S[0] + r * A.grav[0], gp * S[1] + r * A.grav[1], gp * S[2] + r * A.grav[2]};
+        // lt = (I - K)^T lambda: the adjoint of the direct dependence on p
+        double lt[19];
+        for (int i = 0; i < Q; ++i) lt[i] = lam1[i * N + x];
+        if (A.mrt) {
+            double mu[9];
+            for (int k = 0; k < 9; ++k) {
+                double v = 0.0;
+                for (int i = 0; i < 9; ++i) v += kM2[k][i] * lt[i];
+                mu[k] = A.msc[k] * v;
+            }
+            for (int i = 0; i < 9; ++i) {
+                double v = 0.0;
+                for (int k = 0; k < 9; ++k) v += kM2[k][i] * mu[k];
+                lt[i] -= v;
+            }
+        } else {
+            for (int i = 0; i < Q; ++i) lt[i] *= 1.0 - 1.0 / A.tau;
+        }
         const double m1[3] = {j[0] + F[0], j[1] + F[1], j[2] + F[2]};
         const double mm0 = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
         const double mm1 = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
@@ -227,8 +259,9 @@ __global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double
             const double ab = lam1[i * N + x];
             double rr = 0.0;
             if (i >= 1 && ((msk >> (i - 1)) & 1u)) rr = lamR1[link_slot(A, tg, msk, i)];
-            const double al = ab + rr;                         // on E_i(rho, j + F)
-            const double be = ab * (1.0 / A.tau - 1.0) - rr;   // on E_i(rho, j)
+            const double al = ab + rr;   // on E_i(rho, j + F)
+            const double be = -lt[i] - rr;  // on E_i(rho, j): (K - I)^T lambda
+            (void)ab;
             const double w = wgt<double>(L, i);
             const double e[3] = {double(c_ex[L][i]), double(c_ey[L][i]), double(c_ez[L][i])};
             const double em0 = e[0] * j[0] + e[1] * j[1] + e[2] * j[2];
@@ -242,8 +275,10 @@ __global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double
                 Fb[k] += d1;
             }
         }
+        // the body force depends on rho: F = ... + rho g
+        rb += Fb[0] * A.grav[0] + Fb[1] * A.grav[1] + Fb[2] * A.grav[2];
         for (int i = 0; i < Q; ++i)
-            pbar[i * N + x] = lam1[i * N + x] * (1.0 - 1.0 / A.tau) + rb + c_ex[L][i] * jb[0] + c_ey[L][i] * jb[1] + c_ez[L][i] * jb[2];
+            pbar[i * N + x] = lt[i] + rb + c_ex[L][i] * jb[0] + c_ey[L][i] * jb[1] + c_ez[L][i] * jb[2];
         for (int k = 0; k < 3; ++k) {
             Fbar[k * N + x] = Fb[k];
             Fv[k * N + x] = F[k];
@@ -328,7 +363,7 @@ __global__ void k_stream_T(AdjDev A, const RC* __restrict__ rec, const double* _
             continue;
         }
         const uint32_t m = link_bits(A, y, tg);
-        const double pb0 = pbar[y];
+        const double pb0 = pbar[y], pz = A.k18 * pb0;  // eq. 18 carries the adjoint of p_0 (if applied)
         for (int i = 0; i < Q; ++i) {
             double acc = 0.0;
             if (i == 0) {
@@ -336,9 +371,9 @@ __global__ void k_stream_T(AdjDev A, const RC* __restrict__ rec, const double* _
             } else if ((m >> (i - 1)) & 1u) {
                 const int64_t sl = link_slot(A, tg, m, i);
                 const double c1 = fabs(double(rec[sl]));
-                const double Bb = pbar[c_opp[L][i] * N + y] - pb0;
-                acc = c1 * Bb + pb0;
-                lamR0[sl] = (1.0 - c1) * Bb;
+                const double Bb = pbar[c_opp[L][i] * N + y] - pz;
+                acc = c1 * Bb + pz;
+                lamR0[sl] = A.kF * (1.0 - c1) * Bb;
             } else {
                 const int64_t x = nbr(A.g, L, y, i, +1);
                 acc = pbar[i * N + x];
@@ -346,13 +381,13 @@ __global__ void k_stream_T(AdjDev A, const RC* __restrict__ rec, const double* _
                 const uint32_t mx = link_bits(A, x, tx);
                 if ((mx >> (i - 1)) & 1u) {
                     const double ax = double(rec[link_slot(A, tx, mx, i)]);
-                    if (ax > 0.0) acc += (1.0 - ax) * (pbar[c_opp[L][i] * N + x] - pbar[x]);
+                    if (ax > 0.0) acc += (1.0 - ax) * (pbar[c_opp[L][i] * N + x] - A.k18 * pbar[x]);
                 }
             }
             const int io = c_opp[L][i];
             if (i >= 1 && ((m >> (io - 1)) & 1u)) {
                 const double ao = double(rec[link_slot(A, tg, m, io)]);
-                if (ao < 0.0) acc += (1.0 + ao) * (pbar[i * N + y] - pb0);
+                if (ao < 0.0) acc += (1.0 + ao) * (pbar[i * N + y] - pz);
             }
             lam0[i * N + y] = acc;
         }
@@ -478,6 +513,14 @@ AdjDev make_dev(const mcb_ctx* c) {
     A.a = c->p.eos_a;
     A.b4 = c->p.eos_b / 4.0;
     A.rho_ref = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
+    A.kF = c->p.bc_mode == MCB_BC_PRESENT ? 1.0 : 0.0;
+    A.k18 = c->p.bc_mode == MCB_BC_IBC ? 0.0 : 1.0;
+    for (int k = 0; k < 3; ++k) A.grav[k] = c->p.gravity[k];
+    A.mrt = c->p.collision == MCB_COLL_MRT ? 1 : 0;
+    const double sn = 1.0 / c->p.tau;
+    const double rate[9] = {1.0, c->p.s_e, c->p.s_eps, 1.0, c->p.s_q, 1.0, c->p.s_q, sn, sn};
+    const double norm[9] = {9.0, 36.0, 36.0, 6.0, 12.0, 6.0, 12.0, 4.0, 4.0};
+    for (int k = 0; k < 9; ++k) A.msc[k] = rate[k] / norm[k];
     return A;
 }
 

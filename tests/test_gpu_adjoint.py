@@ -83,6 +83,47 @@ def test_adjoint_matches_dual_numbers(mcb, nsteps, k, kind):
     lat.close()
 
 
+CONFIGS = [("mrt", dict(collision="mrt"), {}), ("gravity", dict(gravity=(2e-5, -4e-5)), {}),
+           ("mibc", dict(bc_mode="mibc"), {}), ("ibc", dict(bc_mode="ibc"), {}), ("hbbc", dict(bc_mode="hbbc"), {}),
+           ("mrt-gravity-mibc", dict(collision="mrt", gravity=(0.0, -3e-5), bc_mode="mibc"), {})]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("name,opts,_", CONFIGS, ids=[c[0] for c in CONFIGS])
+def test_adjoint_other_collisions_forces_and_schemes(mcb, name, opts, _, kind):
+    """Reverse mode with the MRT collision, a body force and the comparison boundary schemes against
+    the oracle's dual numbers run with the same settings (20 steps, checkpoint every 7)."""
+    banner(f"adjoint vs oracle duals, {name}, loss {kind}")
+    dims, shapes, rho0 = small_case()
+    prm = LOSSES[kind][1]
+    P = oracle.make_params(2, *dims, tau=0.8, T=0.7 * TC)
+    solid = oracle.classify(P, shapes)
+    node, d, cls, q = oracle.links(P, shapes, solid)
+    walls = oracle.wall_nodes(P, solid)
+    rng = np.random.default_rng(300 + kind + len(name))
+    phi = rng.uniform(0.9, 1.1, len(walls))
+    dirs = rng.standard_normal((4, len(walls)))
+    ds = oracle.DualSim(P, solid, node, d, q)
+    ds.set_phi(phi, dirs)
+    if opts.get("collision") == "mrt":
+        ds.set_mrt()
+    if "gravity" in opts:
+        ds.set_gravity(opts["gravity"])
+    ds.set_bc_mode({"present": 0, "ibc": 1, "mibc": 2, "hbbc": 3}[opts.get("bc_mode", "present")])
+    ds.init_eq(rho0)
+    ds.step(20)
+    L_o, dL_o = ds.loss(kind, prm)
+    lat = mcb.Lattice(2, dims, 0.8, 0.7 * TC, **opts)
+    lat.set_geometry(shapes)
+    lat.set_wettability(phi)
+    L_g = lat.adj_forward(rho0, 20, 7, kind, prm)
+    assert abs(L_g - L_o) <= 1e-12 * max(1.0, abs(L_o)), (L_g, L_o)
+    dL_g = dirs @ lat.adj_backward(1.0)
+    scale = max(np.abs(dL_o).max(), 1e-300)
+    assert np.abs(dL_g - dL_o).max() <= 1e-8 * scale + 1e-14, (dL_g, dL_o)
+    lat.close()
+
+
 def test_state_is_restored_after_backward(mcb):
     banner("forward + backward leave the state as a plain run's")
     dims, shapes, rho0 = small_case()

@@ -174,15 +174,7 @@ def test_step_parity_by_scheme_3d(mcb, mode):
 
 
 def test_unsupported_combinations_rejected(mcb):
-    banner("IBC in 3-D and reverse mode of a comparison scheme: MCB_ENOTSUP")
+    banner("IBC in 3-D: MCB_ENOTSUP")
     with pytest.raises(mcb.MCBError) as ei:
         mcb.Lattice(3, (8, 8, 8), 1.0, 0.7 * TC, bc_mode="ibc")
     assert ei.value.code == -7
-    wl = W.make("c0")
-    lat = mcb.Lattice(2, wl.dims, wl.tau, wl.T, bc_mode="mibc")
-    lat.set_geometry(wl.shapes)
-    lat.set_wettability(1.0)
-    with pytest.raises(mcb.MCBError) as ei:
-        lat.adj_forward(wl.rho0(), 10, 5)
-    assert ei.value.code == -7
-    lat.close()

@@ -156,15 +156,3 @@ def test_max_speed_c1_fp32(mcb):
     s[~fluid] = -1.0
     assert vg == s.max() and ng == int(np.argmax(s))
     lat.close()
-
-
-def test_gravity_reverse_mode_unsupported(mcb):
-    banner("reverse mode with gravity: MCB_ENOTSUP")
-    wl = W.make("c0")
-    lat = mcb.Lattice(2, wl.dims, wl.tau, wl.T, gravity=(0.0, -1e-5))
-    lat.set_geometry(wl.shapes)
-    lat.set_wettability(1.0)
-    with pytest.raises(mcb.MCBError) as ei:
-        lat.adj_forward(wl.rho0(), 10, 5)
-    assert ei.value.code == -7
-    lat.close()

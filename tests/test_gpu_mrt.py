@@ -158,15 +158,7 @@ def test_mrt_fp32_mass_drift_c1(mcb):
 
 
 def test_mrt_unsupported_combinations(mcb):
-    banner("MRT in 3-D and MRT reverse mode: MCB_ENOTSUP")
+    banner("MRT in 3-D: MCB_ENOTSUP")
     with pytest.raises(mcb.MCBError) as ei:
         mcb.Lattice(3, (8, 8, 8), 1.0, 0.7 * TC, collision="mrt")
     assert ei.value.code == -7
-    wl = W.make("c0")
-    lat = mcb.Lattice(2, wl.dims, wl.tau, wl.T, collision="mrt")
-    lat.set_geometry(wl.shapes)
-    lat.set_wettability(1.0)
-    with pytest.raises(mcb.MCBError) as ei:
-        lat.adj_forward(wl.rho0(), 10, 5)
-    assert ei.value.code == -7
-    lat.close()
