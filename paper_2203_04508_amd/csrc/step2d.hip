@@ -641,11 +641,11 @@ __device__ __forceinline__ Cross cross_of(int cx, int cy, int nx, int ny) {
 // fourth-order central differences along an axis from the values at offsets -2 .. +2
 template <class C>
 __device__ __forceinline__ C cd1(C m2, C m1, C p1, C p2) {
-    return (C(8) * (p1 - m1) - (p2 - m2)) / C(12);
+    return (C(8) * (p1 - m1) - (p2 - m2)) * C(1.0 / 12.0);
 }
 template <class C>
 __device__ __forceinline__ C cd2(C m2, C m1, C c, C p1, C p2) {
-    return (C(16) * (p1 + m1) - (p2 + m2) - C(30) * c) / C(12);
+    return (C(16) * (p1 + m1) - (p2 + m2) - C(30) * c) * C(1.0 / 12.0);
 }
 
 // chemical potential: eq. 12 on fluid nodes (Peng-Robinson mu of eq. 11), the assigned value on
@@ -668,8 +668,9 @@ __global__ __launch_bounds__(256) void k_cp_mu(ArgsCP<S, C> p) {
     if (lay == 0) {
         const C br = p.b * r;
         if (!(r > C(0)) || !(br < C(1))) atomicOr(&p.a.flags[FLAG_DOMAIN], 1);
-        const C m0 = p.RT * log(r / (C(1) - br)) - p.c_log * log((s2 - C(1) + br) / (s2 + C(1) - br)) +
-                     p.RT / (C(1) - br) - p.aal * r / (C(1) + C(2) * br - br * br);
+        const C iq = rcp(C(1) - br);
+        const C m0 = p.RT * log(r * iq) - p.c_log * log((s2 - C(1) + br) * rcp(s2 + C(1) - br)) +
+                     p.RT * iq - p.aal * r * rcp(C(1) + C(2) * br - br * br);
         C lap = C(0);
         lap += cd2(xm2, xm1, r, xp1, xp2);
         lap += cd2(ym2, ym1, r, yp1, yp2);
