@@ -715,24 +715,33 @@ int build_sim(Sim<R>* S, const uint8_t* solid, const int64_t* lk_node, const int
     S->lk_dir.assign(lk_dir, lk_dir + nlinks);
     S->lk_q.assign(lk_q, lk_q + nlinks);
     // every fluid-solid neighbour pair must be a link, and every link such a pair
+    int64_t mismatch = 0;
+#pragma omp parallel for schedule(static) reduction(+ : mismatch)
     for (int64_t x = 0; x < N; ++x) {
         for (int i = 1; i < L.Q; ++i) {
             bool need = S->fluid(x) && !S->fluid(g.shift(x, L.e[i], +1));
             bool have = S->link_of(x, i) >= 0;
-            if (need != have) return -1;
+            if (need != have) ++mismatch;
         }
     }
-    S->wall_of.assign(N, -1);
-    S->wall_nodes.clear();
+    if (mismatch) return -1;
+    // first-layer wall nodes (a fluid neighbour), numbered in ascending linear index
+    std::vector<uint8_t> is_wall(N, 0);
+#pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < N; ++x) {
         if (S->fluid(x)) continue;
         for (int i = 1; i < L.Q; ++i)
-            if (S->fluid(g.shift(x, L.e[i], +1))) { S->wall_of[x] = int64_t(S->wall_nodes.size()); S->wall_nodes.push_back(x); break; }
+            if (S->fluid(g.shift(x, L.e[i], +1))) { is_wall[x] = 1; break; }
     }
+    S->wall_of.assign(N, -1);
+    S->wall_nodes.clear();
+    for (int64_t x = 0; x < N; ++x)
+        if (is_wall[x]) { S->wall_of[x] = int64_t(S->wall_nodes.size()); S->wall_nodes.push_back(x); }
     S->phi.assign(S->wall_nodes.size(), R(1.0));
     // solid layers for eq. 15: 1 = a fluid neighbour, 2 = a layer-1 neighbour, 3 = deeper
     S->layer.assign(N, 0);
     for (int64_t x = 0; x < N; ++x) if (!S->fluid(x)) S->layer[x] = S->wall_of[x] >= 0 ? 1 : 3;
+#pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < N; ++x) {
         if (S->layer[x] != 3) continue;
         for (int i = 1; i < L.Q; ++i)
@@ -1098,6 +1107,7 @@ int or_sim_init_eq(void* h, const double* rho0, const double* u0) {
     auto* S = static_cast<Sim<double>*>(h);
     const int64_t N = S->g.N;
     std::vector<double> f(size_t(S->L.Q) * N, 0.0);
+#pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < N; ++x) {
         if (!S->fluid(x)) continue;
         double uu[3] = {0, 0, 0}, fe[MAXQ];
