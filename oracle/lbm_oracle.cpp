@@ -132,6 +132,7 @@ inline Dual operator/(const Dual& a, double b) { Dual r(a.v / b); for (int k = 0
 inline Dual operator/(double a, const Dual& b) { return Dual(a) / b; }
 inline Dual& operator+=(Dual& a, const Dual& b) { a = a + b; return a; }
 inline Dual sqrt(const Dual& a) { double s = std::sqrt(a.v); Dual r(s); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] / (2.0 * s); return r; }
+inline Dual log(const Dual& a) { Dual r(std::log(a.v)); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] / a.v; return r; }
 inline Dual tanh(const Dual& a) { double t = std::tanh(a.v); Dual r(t); for (int k = 0; k < KD; ++k) r.d[k] = a.d[k] * (1.0 - t * t); return r; }
 inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
@@ -203,11 +204,13 @@ inline double pr_p(const PR& E, double r) {  // eq. 10
 }
 
 // eq. 11 without the gradient term; false outside 0 < rho < 1/b
-inline bool pr_mu(const PR& E, double r, double* mu) {
-    const double br = E.b * r;
-    if (!(r > 0.0) || !(br < 1.0)) return false;
+template <class R>
+inline bool pr_mu(const PR& E, R r, R* mu) {
+    using std::log;
+    const R br = E.b * r;
+    if (!(val(r) > 0.0) || !(val(br) < 1.0)) return false;
     const double s2 = std::sqrt(2.0), aa = E.a * E.alpha;
-    *mu = E.R * E.T * std::log(r / (1.0 - br)) - aa / (2.0 * s2 * E.b) * std::log((s2 - 1.0 + br) / (s2 + 1.0 - br)) +
+    *mu = E.R * E.T * log(r / (1.0 - br)) - aa / (2.0 * s2 * E.b) * log((s2 - 1.0 + br) / (s2 + 1.0 - br)) +
           E.R * E.T / (1.0 - br) - aa * r / (1.0 + 2.0 * br - br * br);
     return true;
 }
@@ -221,8 +224,10 @@ struct ChemPot {
 
 // fourth-order central differences along an axis: derivative and second derivative from the values
 // at offsets -2 .. +2
-inline double d1_4(double m2, double m1, double p1, double p2) { return (8.0 * (p1 - m1) - (p2 - m2)) / 12.0; }
-inline double d2_4(double m2, double m1, double c, double p1, double p2) {
+template <class R>
+inline R d1_4(R m2, R m1, R p1, R p2) { return (8.0 * (p1 - m1) - (p2 - m2)) / 12.0; }
+template <class R>
+inline R d2_4(R m2, R m1, R c, R p1, R p2) {
     return (16.0 * (p1 + m1) - (p2 + m2) - 30.0 * c) / 12.0;
 }
 
@@ -453,7 +458,7 @@ struct Sim {
     double grav[3] = {0.0, 0.0, 0.0};  // body acceleration
     ChemPot cp;                         // chemical-potential model when cp.on (2-D)
     std::vector<int8_t> layer;          // solid layer of each node: 0 fluid, 1, 2 (eq. 15), 3 deeper
-    std::vector<double> mu_s;           // assigned chemical potential per first-layer wall node
+    std::vector<R> mu_s;                // assigned chemical potential per first-layer wall node
     std::vector<R> mu;                  // chemical potential field (fluid nodes and solid layers 1-2)
 
     explicit Sim(const or_params& p) : P(p), L(make_lat(p.dim)), g(p) {}
@@ -481,12 +486,10 @@ struct Sim {
             rho[x] = r;
             for (int k = 0; k < 3; ++k) u[k * N + x] = j[k] / r;
         }
-        if constexpr (std::is_same<R, double>::value) {
-            if (cp.on) {
-                chempot_force();
-                collide_with_force(fpre);
-                return;
-            }
+        if (cp.on) {
+            chempot_force();
+            collide_with_force(fpre);
+            return;
         }
         // S2 + S3: pseudopotential on fluid nodes; wall nodes take psi of their virtual density
         int64_t bad = 0;
@@ -598,7 +601,7 @@ struct Sim {
 #pragma omp parallel for schedule(static) reduction(+ : bad)
         for (int64_t x = 0; x < N; ++x) {
             if (layer[x] == 0) {
-                double m0 = 0.0;
+                R m0 = 0.0;
                 if (!pr_mu(cp.eos, rho[x], &m0)) ++bad;
                 R lap = 0.0;
                 for (int k = 0; k < g.dim; ++k)
@@ -608,7 +611,8 @@ struct Sim {
                 mu[x] = mu_s[wall_of[x]];
             } else if (layer[x] == 2) {
                 // the assigned potential of the first-layer neighbours, weighted as in eq. 15
-                double num = 0.0, den = 0.0;
+                R num = 0.0;
+                double den = 0.0;
                 for (int i = 1; i < Q; ++i) {
                     const int64_t y = g.shift(x, L.e[i], +1);
                     if (layer[y] == 1) { num += L.w[i] * mu_s[wall_of[y]]; den += L.w[i]; }
@@ -747,7 +751,7 @@ int build_sim(Sim<R>* S, const uint8_t* solid, const int64_t* lk_node, const int
         for (int i = 1; i < L.Q; ++i)
             if (S->layer[g.shift(x, L.e[i], +1)] == 1) { S->layer[x] = 2; break; }
     }
-    S->mu_s.assign(S->wall_nodes.size(), 0.0);
+    S->mu_s.assign(S->wall_nodes.size(), R(0.0));
     S->mu.assign(N, R(0.0));
     S->ft.assign(size_t(L.Q) * N, R(0.0));
     S->fn.assign(size_t(L.Q) * N, R(0.0));
@@ -997,8 +1001,9 @@ int or_sim_set_mrt(void* h, double se, double seps, double sq) { return set_mrt(
 
 // the chemical-potential model (2-D) for later collisions: PR parameters a, b, R, temperature T,
 // acentric factor omega, mesh scaling k and gradient coefficient kappa (eqs. 9-12)
-int or_sim_set_chempot(void* h, double a, double b, double R, double T, double omega, double k, double kappa) {
-    auto* S = static_cast<Sim<double>*>(h);
+extern "C++" {
+template <class RR>
+static int set_chempot(Sim<RR>* S, double a, double b, double R, double T, double omega, double k, double kappa) {
     if (S->L.dim != 2) return -1;
     if (!(a > 0.0 && b > 0.0 && R > 0.0 && T > 0.0 && k > 0.0 && kappa >= 0.0) || !std::isfinite(omega)) return -1;
     S->cp.eos.a = a;
@@ -1010,6 +1015,25 @@ int or_sim_set_chempot(void* h, double a, double b, double R, double T, double o
     S->cp.k = k;
     S->cp.kappa = kappa;
     S->cp.on = true;
+    return 0;
+}
+}  // extern "C++"
+int or_sim_set_chempot(void* h, double a, double b, double R, double T, double omega, double k, double kappa) {
+    return set_chempot(static_cast<Sim<double>*>(h), a, b, R, T, omega, k, kappa);
+}
+int or_dsim_set_chempot(void* h, double a, double b, double R, double T, double omega, double k, double kappa) {
+    return set_chempot(static_cast<Sim<Dual>*>(h), a, b, R, T, omega, k, kappa);
+}
+// assigned wall chemical potentials of the dual-number simulation, with tangents dmu[k * n_wall + w]
+int or_dsim_set_mu_wall(void* h, const double* mu_s, const double* dmu) {
+    auto* S = static_cast<Sim<Dual>*>(h);
+    const size_t nw = S->mu_s.size();
+    for (size_t w = 0; w < nw; ++w) {
+        if (!std::isfinite(mu_s[w])) return -1;
+        Dual v(mu_s[w]);
+        if (dmu) for (int k = 0; k < KD; ++k) v.d[k] = dmu[k * nw + w];
+        S->mu_s[w] = v;
+    }
     return 0;
 }
 

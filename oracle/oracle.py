@@ -126,6 +126,10 @@ def lib():
         L.or_dsim_destroy.argtypes = [vp]
         L.or_dsim_set_phi.argtypes = [vp, vp, vp]
         L.or_dsim_set_phi.restype = C.c_int
+        L.or_dsim_set_chempot.argtypes = [vp] + [C.c_double] * 7
+        L.or_dsim_set_chempot.restype = C.c_int
+        L.or_dsim_set_mu_wall.argtypes = [vp, vp, vp]
+        L.or_dsim_set_mu_wall.restype = C.c_int
         L.or_dsim_set_mrt.argtypes = [vp, C.c_double, C.c_double, C.c_double]
         L.or_dsim_set_mrt.restype = C.c_int
         L.or_dsim_set_gravity.argtypes = [vp, C.c_double, C.c_double, C.c_double]
@@ -436,6 +440,22 @@ class DualSim:
 
     def set_mrt(self, se=1.64, seps=1.54, sq=1.7):
         Sim._check(lib().or_dsim_set_mrt(self.h, se, seps, sq), "set_mrt")
+
+    def set_chempot(self, T, k=1.0, kappa=0.0, a=2.0 / 49.0, b=2.0 / 21.0, R=1.0, omega=0.344):
+        Sim._check(lib().or_dsim_set_chempot(self.h, a, b, R, T, omega, k, kappa), "set_chempot")
+
+    def set_mu_wall(self, mu_s, directions=None):
+        """mu_s: (n_wall,) assigned wall chemical potentials; directions: up to KD tangent vectors,
+        shape (m, n_wall)."""
+        mu_s = np.ascontiguousarray(mu_s, np.float64)
+        nw = len(mu_s)
+        d = None
+        if directions is not None:
+            d = np.zeros((dual_kd(), nw))
+            dd = np.asarray(directions, np.float64).reshape(-1, nw)
+            d[: len(dd)] = dd
+            d = np.ascontiguousarray(d)
+        Sim._check(lib().or_dsim_set_mu_wall(self.h, _p(mu_s), _p(d) if d is not None else None), "set_mu_wall")
 
     def set_gravity(self, g):
         g = list(g) + [0.0] * (3 - len(g))
