@@ -265,9 +265,8 @@ mcb_status mcb_timing_report(mcb_ctx* ctx, double* ms, int64_t* launches);
 enum { MCB_LOSS_COM_X = 0, MCB_LOSS_WETTED_LENGTH = 1, MCB_LOSS_TOTAL_MASS = 2 };
 
 /* Device bytes of the reverse-mode arena for nsteps >= 0 steps with a checkpoint every k >= 1
- * steps (after mcb_build_links(FILL)).  Reverse mode covers MCB_MODEL_PSEUDO with every boundary
- * scheme, both collisions and the body force; the adjoint calls return MCB_ENOTSUP for
- * MCB_MODEL_CHEMPOT. */
+ * steps (after mcb_build_links(FILL)).  Reverse mode covers both models (2-D for the chemical-potential
+ * one), every boundary scheme, both collisions and the body force. */
 mcb_status mcb_adj_required_bytes(mcb_ctx* ctx, int64_t nsteps, int64_t k, int64_t* bytes);
 
 /* Binds the caller-owned reverse-mode arena (device memory, at least the required bytes, 256-byte
@@ -279,7 +278,8 @@ mcb_status mcb_adj_bind(mcb_ctx* ctx, void* device_buffer, int64_t bytes);
 mcb_status mcb_adj_forward(mcb_ctx* ctx, const double* rho0, int64_t nsteps, int64_t k, int32_t loss_kind,
                            const double* loss_prm, double* value);
 
-/* dphi[w] = dloss * d loss / d phi[w] (n_wall doubles, wall nodes in ascending linear index) for
+/* dphi[w] = dloss * d loss / d phi[w] (n_wall doubles, wall nodes in ascending linear index; phi is the
+ * wettability value of mcb_set_wettability: the factor, or the assigned chemical potential) for
  * the last mcb_adj_forward; the state must not have been changed since (MCB_ESTATE otherwise).
  * The context's state is left as it was.  Synchronises. */
 mcb_status mcb_adj_backward(mcb_ctx* ctx, double dloss, double* dphi);

@@ -1,8 +1,9 @@
 // Reverse mode of the step: the hand-written discrete adjoint of the map from the post-collision
 // state of time t to that of time t+1, and of the first collision from the equilibrium start.
 // Together with checkpointed recomputation of the forward states (api layer) it gives the exact
-// gradient (to rounding) of a loss of the final state with respect to the wettability factor phi
-// of every wall node.
+// gradient (to rounding) of a loss of the final state with respect to the wettability of every wall
+// node: the factor phi (pseudopotential model) or the assigned chemical potential (chemical-potential
+// model, whose transposes follow the pseudopotential ones below).
 //
 // State.  The forward step reads, besides the populations g(t), the forcing term F_j(x, t) of
 // eq. 13 on every fluid-solid link (eqs. 16-17 use it one step later), so the state is the pair
@@ -63,6 +64,10 @@ struct AdjDev {
     double grav[3];              // body acceleration
     int mrt;                     // 1: K = M^-1 S M with msc[k] = s_k / |row k of M|^2 (D2Q9)
     double msc[9];
+    // chemical-potential model (D2Q9): solid layers, eq. 12 and the Peng-Robinson potential
+    int cp;
+    const int8_t* layer;
+    double k2, kappa, pRT, pb, pclog, paal;
 };
 
 // D2Q9 moment matrix of eq. 2 (rows rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy); its rows are
@@ -209,7 +214,7 @@ __global__ void k_psi(AdjDev A, const double* __restrict__ rho, double* __restri
 __global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double* __restrict__ rho,
                             const double* __restrict__ psi, const double* __restrict__ lam1,
                             const double* __restrict__ lamR1, double* __restrict__ pbar, double* __restrict__ Fbar,
-                            double* __restrict__ Fv) {
+                            double* __restrict__ Fv, const double* __restrict__ Fin) {
     const int Q = A.g.Q, L = A.L;
     const int64_t N = A.g.N;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x) {
@@ -223,14 +228,18 @@ __global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double
             j[1] += v * c_ey[L][i];
             j[2] += v * c_ez[L][i];
         }
-        for (int k = 1; k < Q; ++k) {
-            const double w = wforce(L, k) * psi[nbr(A.g, L, x, k, +1)];
-            S[0] += w * c_ex[L][k];
-            S[1] += w * c_ey[L][k];
-            S[2] += w * c_ez[L][k];
+        if (!Fin) {
+            for (int k = 1; k < Q; ++k) {
+                const double w = wforce(L, k) * psi[nbr(A.g, L, x, k, +1)];
+                S[0] += w * c_ex[L][k];
+                S[1] += w * c_ey[L][k];
+                S[2] += w * c_ez[L][k];
+            }
         }
-        const double gp = -A.G * psi[x];
-        const double F[3] = {gp * S[0] + r * A.grav[0], gp * S[1] + r * A.grav[1], gp * S[2] + r * A.grav[2]};
+        const double gp = Fin ? 0.0 : -A.G * psi[x];
+        // chemical-potential model: the whole force (body force included) comes recomputed in Fin
+        const double F[3] = {Fin ? Fin[x] : gp * S[0] + r * A.grav[0], Fin ? Fin[N + x] : gp * S[1] + r * A.grav[1],
+                             Fin ? Fin[2 * N + x] : gp * S[2] + r * A.grav[2]};
         // lt = (I - K)^T lambda: the adjoint of the direct dependence on p
         double lt[19];
         for (int i = 0; i < Q; ++i) lt[i] = lam1[i * N + x];
@@ -324,6 +333,184 @@ __global__ void k_psi_T(AdjDev A, const double* __restrict__ psi, const double* 
             dphi[w] += rwb * rave[y];
             qbar[y] = rwb * A.phi[w] / den[y];
         }
+    }
+}
+
+// ---- chemical-potential model (D2Q9): forward fields of the recomputed state and the transposes of
+// the force (eq. 9), the potential (eq. 12 with the Peng-Robinson mu of eq. 11), and the two solid
+// layers of eq. 15.  Fourth-order central differences: d/dx v = sum_m c_m v(x + m), m = -2..2,
+// c = (1, -8, 0, 8, -1) / 12; d2/dx2 v = sum_m d_m v(x + m), d = (-1, 16, -30, 16, -1) / 12.
+__device__ inline double cdc(int m) { return m == -2 ? 1.0 / 12.0 : m == -1 ? -8.0 / 12.0 : m == 1 ? 8.0 / 12.0 : m == 2 ? -1.0 / 12.0 : 0.0; }
+__device__ inline double cdd(int m) { return (m == -2 || m == 2) ? -1.0 / 12.0 : (m == -1 || m == 1) ? 16.0 / 12.0 : -30.0 / 12.0; }
+
+// node x + m e_k (k = 0: x axis, 1: y axis), periodic
+__device__ inline int64_t axn(const GridDev& g, int64_t x, int k, int m) {
+    const int cx = int(x % g.nx), cy = int(x / g.nx);
+    return k == 0 ? int64_t(cy) * g.nx + wrap1(cx + m, g.nx) : int64_t(wrap1(cy + m, g.ny)) * g.nx + cx;
+}
+
+__global__ void k_cpa_layer(AdjDev A, double* __restrict__ rho, int lay) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < A.g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        if (A.layer[x] != lay) continue;
+        double num = 0.0, den = 0.0;
+        for (int i = 1; i < 9; ++i) {
+            const int64_t y = nbr(A.g, 0, x, i, +1);
+            if (A.layer[y] == lay - 1) {
+                num += wgt<double>(0, i) * rho[y];
+                den += wgt<double>(0, i);
+            }
+        }
+        rho[x] = num / den;
+    }
+}
+
+// mu_PR of eq. 11 (without the gradient term) and its derivative
+__device__ inline double pr_mu0(const AdjDev& A, double r) {
+    const double br = A.pb * r, s2 = 1.4142135623730951;
+    return A.pRT * log(r / (1.0 - br)) - A.pclog * log((s2 - 1.0 + br) / (s2 + 1.0 - br)) + A.pRT / (1.0 - br) -
+           A.paal * r / (1.0 + 2.0 * br - br * br);
+}
+__device__ inline double pr_dmu0(const AdjDev& A, double r) {
+    const double br = A.pb * r, om = 1.0 - br, D = 1.0 + 2.0 * br - br * br;
+    return A.pRT / (r * om) + A.pRT * A.pb / (om * om) - A.paal / D - A.paal * (1.0 + br * br) / (D * D);
+}
+
+// the assigned potential of layer-2 node t: eq. 15 mean of its wall-node neighbours' values
+__device__ inline double l2_den(const AdjDev& A, int64_t t) {
+    double den = 0.0;
+    for (int i = 1; i < 9; ++i)
+        if (A.layer[nbr(A.g, 0, t, i, +1)] == 1) den += wgt<double>(0, i);
+    return den;
+}
+
+__global__ void k_cpa_mu(AdjDev A, const double* __restrict__ rho, double* __restrict__ mu) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < A.g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int lay = A.layer[x];
+        double m = 0.0;
+        if (lay == 0) {
+            double lap = 0.0;
+            for (int k = 0; k < 2; ++k)
+                for (int d = -2; d <= 2; ++d) lap += cdd(d) * rho[axn(A.g, x, k, d)];
+            m = A.k2 * pr_mu0(A, rho[x]) - A.kappa * lap;
+        } else if (lay == 1) {
+            m = A.phi[-A.tag[x] - 2];
+        } else if (lay == 2) {
+            double num = 0.0;
+            for (int i = 1; i < 9; ++i) {
+                const int64_t s = nbr(A.g, 0, x, i, +1);
+                if (A.layer[s] == 1) num += wgt<double>(0, i) * A.phi[-A.tag[s] - 2];
+            }
+            m = num / l2_den(A, x);
+        }
+        mu[x] = m;
+    }
+}
+
+__global__ void k_cpa_force(AdjDev A, const double* __restrict__ rho, const double* __restrict__ mu, double* __restrict__ F) {
+    const int64_t N = A.g.N;
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x) {
+        if (A.layer[x] != 0) continue;
+        for (int k = 0; k < 3; ++k) {
+            double f = rho[x] * A.grav[k];
+            if (k < 2) {
+                double gm = 0.0, gr = 0.0;
+                for (int d = -2; d <= 2; ++d) {
+                    if (d == 0) continue;
+                    const int64_t y = axn(A.g, x, k, d);
+                    gm += cdc(d) * mu[y];
+                    gr += cdc(d) * rho[y];
+                }
+                f += -rho[x] * gm + gr / 3.0;
+            }
+            F[k * N + x] = f;
+        }
+    }
+}
+
+// F-bar -> mu-bar and rho-bar on every node of the stencils (fluid and both layers), gathered from
+// the fluid nodes x = y - m e_k whose force reads y; the body force's rho dependence is taken by the
+// transposed collision
+__global__ void k_cpa_force_T(AdjDev A, const double* __restrict__ rho, const double* __restrict__ mu,
+                              const double* __restrict__ Fbar, double* __restrict__ mub, double* __restrict__ rhob) {
+    const int64_t N = A.g.N;
+    for (int64_t y = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; y < N; y += int64_t(gridDim.x) * blockDim.x) {
+        double mb = 0.0, rb = 0.0;
+        if (A.layer[y] <= 2) {
+            for (int k = 0; k < 2; ++k)
+                for (int d = -2; d <= 2; ++d) {
+                    if (d == 0) continue;
+                    const int64_t x = axn(A.g, y, k, -d);
+                    if (A.layer[x] != 0) continue;
+                    const double fb = Fbar[k * N + x];
+                    mb -= fb * rho[x] * cdc(d);
+                    rb += fb * cdc(d) / 3.0;
+                }
+            if (A.layer[y] == 0)
+                for (int k = 0; k < 2; ++k) {
+                    double gm = 0.0;
+                    for (int d = -2; d <= 2; ++d)
+                        if (d != 0) gm += cdc(d) * mu[axn(A.g, y, k, d)];
+                    rb -= Fbar[k * N + y] * gm;
+                }
+        }
+        mub[y] = mb;
+        rhob[y] = rb;
+    }
+}
+
+// mu-bar -> rho-bar (eq. 12 on fluid nodes: the Peng-Robinson slope and the transposed Laplacian)
+// and -> the assigned potentials of the wall nodes (their own mu and the layer-2 means)
+__global__ void k_cpa_mu_T(AdjDev A, const double* __restrict__ rho, const double* __restrict__ mub, double* __restrict__ rhob,
+                           double* __restrict__ dmus) {
+    for (int64_t z = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; z < A.g.N; z += int64_t(gridDim.x) * blockDim.x) {
+        const int lay = A.layer[z];
+        if (lay > 2) continue;
+        double add = 0.0;
+        for (int k = 0; k < 2; ++k)
+            for (int d = -2; d <= 2; ++d) {
+                const int64_t x = axn(A.g, z, k, -d);
+                if (A.layer[x] == 0) add -= A.kappa * cdd(d) * mub[x];
+            }
+        if (lay == 0) add += mub[z] * A.k2 * pr_dmu0(A, rho[z]);
+        rhob[z] += add;
+        if (lay == 1) {
+            double g = mub[z];
+            for (int i = 1; i < 9; ++i) {
+                const int64_t t = nbr(A.g, 0, z, i, +1);
+                if (A.layer[t] == 2) g += mub[t] * wgt<double>(0, i) / l2_den(A, t);
+            }
+            dmus[-A.tag[z] - 2] += g;
+        }
+    }
+}
+
+// layer 2 -> layer 1 (eq. 15: rho(t) = sum w rho(s) / den over t's wall-node neighbours s)
+__global__ void k_cpa_l2_T(AdjDev A, double* __restrict__ rhob) {
+    for (int64_t s = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; s < A.g.N; s += int64_t(gridDim.x) * blockDim.x) {
+        if (A.layer[s] != 1) continue;
+        double add = 0.0;
+        for (int i = 1; i < 9; ++i) {
+            const int64_t t = nbr(A.g, 0, s, i, +1);
+            if (A.layer[t] == 2) add += rhob[t] * wgt<double>(0, i) / l2_den(A, t);
+        }
+        rhob[s] += add;
+    }
+}
+
+// hand the fluid rho-bar and the wall nodes' rho-bar / den (layer 1 -> fluid through eq. 15) to the
+// transposed density sum
+__global__ void k_cpa_prep(AdjDev A, const double* __restrict__ rhob, double* __restrict__ rbar, double* __restrict__ qbar) {
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < A.g.N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int lay = A.layer[x];
+        rbar[x] = lay == 0 ? rhob[x] : 0.0;
+        double q = 0.0;
+        if (lay == 1) {
+            double den = 0.0;
+            for (int i = 1; i < 9; ++i)
+                if (A.layer[nbr(A.g, 0, x, i, +1)] == 0) den += wgt<double>(0, i);
+            q = rhob[x] / den;
+        }
+        qbar[x] = q;
     }
 }
 
@@ -521,6 +708,14 @@ AdjDev make_dev(const mcb_ctx* c) {
     const double rate[9] = {1.0, c->p.s_e, c->p.s_eps, 1.0, c->p.s_q, 1.0, c->p.s_q, sn, sn};
     const double norm[9] = {9.0, 36.0, 36.0, 6.0, 12.0, 6.0, 12.0, 4.0, 4.0};
     for (int k = 0; k < 9; ++k) A.msc[k] = rate[k] / norm[k];
+    A.cp = c->p.model == MCB_MODEL_CHEMPOT ? 1 : 0;
+    A.layer = reinterpret_cast<const int8_t*>(c->lat + c->L.cp_layer);
+    A.k2 = c->p.cp_k * c->p.cp_k;
+    A.kappa = c->p.cp_kappa;
+    A.pRT = c->p.eos_R * c->p.eos_T;
+    A.pb = c->p.eos_b;
+    A.paal = A.cp ? pr_aalpha(c->p.eos_a, c->p.eos_b, c->p.eos_R, c->p.eos_T, c->p.pr_omega) : 0.0;
+    A.pclog = A.paal / (2.0 * std::sqrt(2.0) * c->p.eos_b);
     return A;
 }
 
@@ -534,9 +729,26 @@ hipError_t adj_step_t(mcb_ctx* c, const AdjWork& w, const void* gt, const void* 
     const RC* Fv = static_cast<const RC*>(fv);
     hipLaunchKernelGGL((k_recompute<S, RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt), rec, Fv, pull,
                        w.rho0, w.p, w.rho);
-    hipLaunchKernelGGL(k_psi, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.dpsi, w.rave, w.den);
-    hipLaunchKernelGGL(k_collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar, w.Fv);
-    hipLaunchKernelGGL(k_psi_T, dim3(G), dim3(256), 0, c->stream, A, w.psi, w.dpsi, w.rave, w.den, w.Fbar, w.rbar, w.qbar, w.dphi);
+    if (!A.cp) hipLaunchKernelGGL(k_psi, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.dpsi, w.rave, w.den);
+    if (A.cp) {
+        // chemical-potential model: layer densities, mu and F of the recomputed state, then the
+        // transposed collision, force, potential and layers (mu in psi, mu-bar in dpsi, rho-bar in rave)
+        hipLaunchKernelGGL(k_cpa_layer, dim3(G), dim3(256), 0, c->stream, A, w.rho, 1);
+        hipLaunchKernelGGL(k_cpa_layer, dim3(G), dim3(256), 0, c->stream, A, w.rho, 2);
+        hipLaunchKernelGGL(k_cpa_mu, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi);
+        hipLaunchKernelGGL(k_cpa_force, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.Fv);
+        hipLaunchKernelGGL(k_collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar,
+                           w.Fv, w.Fv);
+        hipLaunchKernelGGL(k_cpa_force_T, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.Fbar, w.dpsi, w.rave);
+        hipLaunchKernelGGL(k_cpa_mu_T, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.dpsi, w.rave, w.dphi);
+        hipLaunchKernelGGL(k_cpa_l2_T, dim3(G), dim3(256), 0, c->stream, A, w.rave);
+        hipLaunchKernelGGL(k_cpa_prep, dim3(G), dim3(256), 0, c->stream, A, w.rave, w.rbar, w.qbar);
+    } else {
+        hipLaunchKernelGGL(k_collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar, w.Fv,
+                           nullptr);
+        hipLaunchKernelGGL(k_psi_T, dim3(G), dim3(256), 0, c->stream, A, w.psi, w.dpsi, w.rave, w.den, w.Fbar, w.rbar, w.qbar,
+                           w.dphi);
+    }
     if (pull) {
         hipLaunchKernelGGL(k_rho_T, dim3(G), dim3(256), 0, c->stream, A, w.rbar, w.qbar, w.pbar);
         hipLaunchKernelGGL((k_stream_T<RC>), dim3(G), dim3(256), 0, c->stream, A, rec, w.pbar, lam0, lamR0);

@@ -567,7 +567,6 @@ mcb_status mcb_adj_required_bytes(mcb_ctx* c, int64_t nsteps, int64_t k, int64_t
     if (!c || !bytes) return MCB_EINVAL;
     if (c->stage < 4) return fail(c, MCB_ESTATE, "links not built");
     if (nsteps < 0 || k < 1) return fail(c, MCB_EINVAL, "need nsteps >= 0 and k >= 1");
-    if (c->p.model != MCB_MODEL_PSEUDO) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the pseudopotential model only");
     *bytes = adj_plan(c, nsteps, k).bytes;
     return MCB_OK;
 }
@@ -588,7 +587,6 @@ mcb_status mcb_adj_forward(mcb_ctx* c, const double* rho0, int64_t nsteps, int64
     if (!rho0 || !prm || !value) return fail(c, MCB_EINVAL, "missing argument");
     if (nsteps < 0 || k < 1) return fail(c, MCB_EINVAL, "need nsteps >= 0 and k >= 1");
     if (kind < MCB_LOSS_COM_X || kind > MCB_LOSS_TOTAL_MASS) return fail(c, MCB_EINVAL, "unknown loss");
-    if (c->p.model != MCB_MODEL_PSEUDO) return fail(c, MCB_ENOTSUP, "reverse mode differentiates the pseudopotential model only");
     if (kind == MCB_LOSS_WETTED_LENGTH && !(prm[1] > 0.0)) return fail(c, MCB_EINVAL, "wetted length needs delta > 0");
     const AdjPlan a = adj_plan(c, nsteps, k);
     if (!c->adj || c->adj_bytes < a.bytes) return fail(c, MCB_ESIZE, "reverse-mode arena needs %lld bytes", (long long)a.bytes);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 
@@ -91,6 +92,23 @@ int64_t storage_bytes(int precision);
 int64_t state_bytes(int precision, int Q, int64_t N);
 int64_t plane_bytes_off(int precision, int i, int64_t N);
 int64_t compute_bytes(int precision);
+
+// Peng-Robinson critical temperature (alpha = 1): x = b rho_c is the real root of
+// x^3 + x^2 + x - 1/3 = 0 (d2p/drho2 = 0 on the curve dp/drho = 0), then
+// R T_c b / a = (1 - x)^2 (2x + 2x^2) / (1 + 2x - x^2)^2
+inline double pr_tc(double a, double b, double R) {
+    const double r2 = std::sqrt(2.0);
+    const double x = (std::cbrt(8.0 + 6.0 * r2) + std::cbrt(8.0 - 6.0 * r2) - 1.0) / 3.0;
+    const double q = 1.0 + 2.0 * x - x * x;
+    return a / (b * R) * (1.0 - x) * (1.0 - x) * 2.0 * x * (1.0 + x) / (q * q);
+}
+
+// a alpha(T) of the Peng-Robinson EOS (Sec. 2.2) with acentric factor omega
+inline double pr_aalpha(double a, double b, double R, double T, double omega) {
+    const double m = 0.37464 + 1.54226 * omega - 0.26992 * omega * omega;
+    const double s = 1.0 + m * (1.0 - std::sqrt(T / pr_tc(a, b, R)));
+    return a * s * s;
+}
 
 }  // namespace mcb
 

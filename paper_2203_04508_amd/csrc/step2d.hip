@@ -747,15 +747,6 @@ inline unsigned cp_grid(int64_t n) {
     return unsigned(b < 1 ? 1 : b);
 }
 
-// Peng-Robinson critical temperature (alpha = 1): x = b rho_c is the real root of
-// x^3 + x^2 + x - 1/3 = 0 (d2p/drho2 = 0 on the curve dp/drho = 0), then
-// R T_c b / a = (1 - x)^2 (2x + 2x^2) / (1 + 2x - x^2)^2
-double pr_tc(double a, double b, double R) {
-    const double r2 = std::sqrt(2.0);
-    const double x = (std::cbrt(8.0 + 6.0 * r2) + std::cbrt(8.0 - 6.0 * r2) - 1.0) / 3.0;
-    const double q = 1.0 + 2.0 * x - x * x;
-    return a / (b * R) * (1.0 - x) * (1.0 - x) * 2.0 * x * (1.0 + x) / (q * q);
-}
 
 template <class S, class C>
 hipError_t launch_cp(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {

@@ -124,6 +124,51 @@ def test_adjoint_other_collisions_forces_and_schemes(mcb, name, opts, _, kind):
     lat.close()
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("name,opts", [("chempot", {}), ("chempot-mrt-gravity", dict(collision="mrt", gravity=(0.0, -2e-5)))],
+                         ids=["chempot", "chempot-mrt-gravity"])
+def test_adjoint_chempot_wall_potential(mcb, name, opts, kind):
+    """The chemical-potential model: the gradient with respect to every wall node's assigned chemical
+    potential against the oracle's dual numbers (20 steps, checkpoint every 7)."""
+    from oracle import thermo
+
+    banner(f"adjoint vs oracle duals, {name}, loss {kind}")
+    _, Tc = thermo.critical_point_pr()
+    T = 0.8 * Tc
+    rv, rl = W.PR_MAXWELL[0.80]
+    dims, shapes, _ = small_case()
+    rho0 = W.drop_field(dims, 2, [((16.0, 11.0), 6.0)], rv, rl, 6.0)
+    prm = (rv, 1.0) if kind == 0 else ((rv + rl) / 2, 0.1 * (rl - rv))
+    P = oracle.make_params(2, *dims, tau=0.8, T=0.05)
+    solid = oracle.classify(P, shapes)
+    node, d, cls, q = oracle.links(P, shapes, solid)
+    walls = oracle.wall_nodes(P, solid)
+    rng = np.random.default_rng(400 + kind)
+    mu_s = W.CP_K ** 2 * W.MU_PR_COEX[0.80] + rng.uniform(-0.01, 0.01, len(walls))
+    dirs = rng.standard_normal((4, len(walls)))
+    ds = oracle.DualSim(P, solid, node, d, q)
+    ds.set_chempot(T, k=W.CP_K, kappa=W.CP_KAPPA)
+    ds.set_phi(np.ones(len(walls)))
+    ds.set_mu_wall(mu_s, dirs)
+    if opts.get("collision") == "mrt":
+        ds.set_mrt()
+    if "gravity" in opts:
+        ds.set_gravity(opts["gravity"])
+    ds.init_eq(rho0)
+    ds.step(20)
+    L_o, dL_o = ds.loss(kind, prm)
+    lat = mcb.Lattice(2, dims, 0.8, T, model="chempot", cp_k=W.CP_K, cp_kappa=W.CP_KAPPA, **opts)
+    lat.set_geometry(shapes)
+    lat.set_wettability(mu_s)
+    L_g = lat.adj_forward(rho0, 20, 7, kind, prm)
+    assert abs(L_g - L_o) <= 1e-12 * max(1.0, abs(L_o)), (L_g, L_o)
+    dL_g = dirs @ lat.adj_backward(1.0)
+    scale = max(np.abs(dL_o).max(), 1e-300)
+    assert np.abs(dL_o).max() > 0.0
+    assert np.abs(dL_g - dL_o).max() <= 1e-8 * scale + 1e-14, (dL_g, dL_o)
+    lat.close()
+
+
 def test_state_is_restored_after_backward(mcb):
     banner("forward + backward leave the state as a plain run's")
     dims, shapes, rho0 = small_case()
