@@ -483,7 +483,9 @@ hipError_t geom_fill(mcb_ctx* c) {
 }
 
 hipError_t wall_factors(mcb_ctx* c) {
-    if (c->n_wall <= 0) return hipSuccess;
+    // chemical-potential model: the solid layers' chemical potential follows the assigned values
+    const hipError_t e = cp_wall_mu(c);
+    if (e != hipSuccess || c->n_wall <= 0) return e;
     const uint8_t* solid = reinterpret_cast<const uint8_t*>(c->lat + c->L.solid);
     const int32_t* wn = reinterpret_cast<const int32_t*>(c->lk + c->L.wl_node);
     const double* phi = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);

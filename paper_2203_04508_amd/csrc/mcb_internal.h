@@ -160,6 +160,7 @@ hipError_t geom_count(mcb_ctx* c);                // block sums + scan, totals a
 hipError_t geom_fill(mcb_ctx* c);                 // tags, boundary-node / wall tables, q, class
 hipError_t geom_reclass(mcb_ctx* c);              // class from the current q (after an override)
 hipError_t wall_factors(mcb_ctx* c);              // phi / (eq. 15 weight of the fluid neighbours) per wall node
+hipError_t cp_wall_mu(mcb_ctx* c);                // chemical-potential model: mu of the solid layers from the assigned values
 
 // step2d.hip / step3d.hip: one time step from the state (fcur, rcur) to (fnext, rnext), where r are
 // the boundary records of the state (pull = false: collision of fcur in place of the pull)

@@ -609,15 +609,24 @@ template <class S, class C>
 __global__ __launch_bounds__(256) void k_cp_layer(ArgsCP<S, C> p, const int32_t* __restrict__ list, int64_t n, int lay) {
     const int nx = p.a.nx, ny = p.a.ny;
     for (int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; j < n; j += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t x = list[j];
-        const int cx = int(x % nx), cy = int(x / nx);
-        C num = C(0), den = C(0);
+        const uint32_t x = uint32_t(list[j]);  // N < 2^31
+        const int cx = int(x % uint32_t(nx)), cy = int(x / uint32_t(nx));
+        // every neighbour's layer and density are loaded before any is used (one round trip), the
+        // terms of the other layers are dropped by selection, so the sum keeps the direction order
+        int8_t ly[8];
+        C rv[8];
+#pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const int64_t y = int64_t(wrap1(cy + kEy[i], ny)) * nx + wrap1(cx + kEx[i], nx);
-            if (p.layer[y] == lay - 1) {
-                num += w9<C>(i) * p.rho[y];
-                den += w9<C>(i);
-            }
+            const uint32_t y = uint32_t(wrap1(cy + kEy[i], ny)) * uint32_t(nx) + uint32_t(wrap1(cx + kEx[i], nx));
+            ly[i - 1] = p.layer[y];
+            rv[i - 1] = p.rho[y];
+        }
+        C num = C(0), den = C(0);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const bool in = ly[i - 1] == lay - 1;
+            num += in ? w9<C>(i) * rv[i - 1] : C(0);
+            den += in ? w9<C>(i) : C(0);
         }
         p.rho[x] = num / den;
     }
@@ -648,47 +657,88 @@ __device__ __forceinline__ C cd2(C m2, C m1, C c, C p1, C p2) {
     return (C(16) * (p1 + m1) - (p2 + m2) - C(30) * c) * C(1.0 / 12.0);
 }
 
-// chemical potential: eq. 12 on fluid nodes (Peng-Robinson mu of eq. 11), the assigned value on
-// wall nodes, on the second layer the eq. 15 mean of its wall-node neighbours' assigned values
+// rows of one lane in the chemical-potential pass
+constexpr int CP_MU_ROWS = 4;
+
+__device__ __forceinline__ int wrapm(int v, int n) {
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// chemical potential on the fluid nodes: eq. 12 with the Peng-Robinson mu of eq. 11 (the solid
+// layers' values depend on the assigned ones alone and are written when those are set:
+// k_cp_mu_solid).  A lane takes CP_MU_ROWS rows of one column (the workgroup 256 columns of rows
+// blockIdx.y * CP_MU_ROWS ...): the column's densities over those rows and two more on either side
+// serve every y stencil, and all the loads of the lane are issued before any is used.
 template <class S, class C>
 __global__ __launch_bounds__(256) void k_cp_mu(ArgsCP<S, C> p) {
+    constexpr int R = CP_MU_ROWS;
     const int nx = p.a.nx, ny = p.a.ny;
     const C s2 = C(1.4142135623730951);
-    const int cx = blockIdx.x * 256 + threadIdx.x, cy = blockIdx.y;
+    const int cx = blockIdx.x * 256 + threadIdx.x, cy0 = blockIdx.y * R;
     if (cx >= nx) return;
-    const int64_t x = int64_t(cy) * nx + cx;
-    const int lay = p.layer[x];
-    const Cross k = cross_of(cx, cy, nx, ny);
-    auto at = [&](const C* v, int dx, int dy) { return v[k.row[dy + 2] + k.col[dx + 2]]; };
-    // the stencil's loads first, independent of the node's kind, so that they are all in flight at once
-    const C r = p.rho[x];
-    const C xm2 = at(p.rho, -2, 0), xm1 = at(p.rho, -1, 0), xp1 = at(p.rho, 1, 0), xp2 = at(p.rho, 2, 0);
-    const C ym2 = at(p.rho, 0, -2), ym1 = at(p.rho, 0, -1), yp1 = at(p.rho, 0, 1), yp2 = at(p.rho, 0, 2);
-    C m = C(0);
-    if (lay == 0) {
-        const C br = p.b * r;
-        if (!(r > C(0)) || !(br < C(1))) atomicOr(&p.a.flags[FLAG_DOMAIN], 1);
-        const C iq = rcp(C(1) - br);
-        const C m0 = p.RT * log(r * iq) - p.c_log * log((s2 - C(1) + br) * rcp(s2 + C(1) - br)) +
-                     p.RT * iq - p.aal * r * rcp(C(1) + C(2) * br - br * br);
-        C lap = C(0);
-        lap += cd2(xm2, xm1, r, xp1, xp2);
-        lap += cd2(ym2, ym1, r, yp1, yp2);
-        m = p.k2 * m0 - p.kappa * lap;
-    } else if (lay == 1) {
-        m = C(p.mus[-p.a.tag[x] - 2]);
-    } else if (lay == 2) {
-        C num = C(0), den = C(0);
-        for (int i = 1; i < 9; ++i) {
-            const int64_t y = int64_t(wrap1(cy + kEy[i], ny)) * nx + wrap1(cx + kEx[i], nx);
-            if (p.layer[y] == 1) {
-                num += w9<C>(i) * C(p.mus[-p.a.tag[y] - 2]);
-                den += w9<C>(i);
-            }
-        }
-        m = num / den;
+    uint32_t col[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) col[d] = uint32_t(wrap1(cx + d - 2, nx));
+    C cv[R + 4];  // column cx, rows cy0 - 2 .. cy0 + R + 1 (periodic)
+#pragma unroll
+    for (int j = 0; j < R + 4; ++j) cv[j] = p.rho[uint32_t(wrapm(cy0 - 2 + j, ny)) * uint32_t(nx) + col[2]];
+    uint32_t rowb[R];
+    bool fluid[R];
+    C xv[R][4];  // per row: columns cx - 2, cx - 1, cx + 1, cx + 2
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        rowb[j] = uint32_t(cy0 + j < ny ? cy0 + j : cy0) * uint32_t(nx);
+        fluid[j] = (p.layer[rowb[j] + col[2]] == 0) & (cy0 + j < ny);  // rows past the lattice: never stored
+        xv[j][0] = p.rho[rowb[j] + col[0]];
+        xv[j][1] = p.rho[rowb[j] + col[1]];
+        xv[j][2] = p.rho[rowb[j] + col[3]];
+        xv[j][3] = p.rho[rowb[j] + col[4]];
     }
-    p.mu[x] = m;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const C r = cv[j + 2];
+        const C rf = fluid[j] ? r : C(1);  // a harmless stand-in density where nothing is stored
+        const C br = p.b * rf;
+        if (fluid[j] && (!(rf > C(0)) || !(br < C(1)))) atomicOr(&p.a.flags[FLAG_DOMAIN], 1);
+        const C iq = rcp(C(1) - br);
+        const C m0 = p.RT * log(rf * iq) - p.c_log * log((s2 - C(1) + br) * rcp(s2 + C(1) - br)) +
+                     p.RT * iq - p.aal * rf * rcp(C(1) + C(2) * br - br * br);
+        C lap = C(0);
+        lap += cd2(xv[j][0], xv[j][1], r, xv[j][2], xv[j][3]);
+        lap += cd2(cv[j], cv[j + 1], r, cv[j + 3], cv[j + 4]);
+        if (fluid[j]) p.mu[rowb[j] + cx] = p.k2 * m0 - p.kappa * lap;
+    }
+}
+
+// chemical potential of the solid nodes: the assigned value on the wall nodes (the first solid
+// layer), on the second layer the eq. 15 mean of its wall-node neighbours' assigned values, zero
+// deeper; fluid nodes are left to k_cp_mu
+template <class C>
+__global__ __launch_bounds__(256) void k_cp_mu_solid(int nx, int ny, const int8_t* __restrict__ layer,
+                                                     const int32_t* __restrict__ tag, const double* __restrict__ mus,
+                                                     C* __restrict__ mu) {
+    const int64_t N = int64_t(nx) * ny;
+    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x) {
+        const int lay = layer[x];
+        if (lay == 0) continue;
+        C m = C(0);
+        if (lay == 1) {
+            m = C(mus[-tag[x] - 2]);
+        } else if (lay == 2) {
+            const int cx = int(x % nx), cy = int(x / nx);
+            C num = C(0), den = C(0);
+            for (int i = 1; i < 9; ++i) {
+                const int64_t y = int64_t(wrap1(cy + kEy[i], ny)) * nx + wrap1(cx + kEx[i], nx);
+                if (layer[y] == 1) {
+                    num += w9<C>(i) * C(mus[-tag[y] - 2]);
+                    den += w9<C>(i);
+                }
+            }
+            m = num / den;
+        }
+        mu[x] = m;
+    }
 }
 
 // pull, eq. 9 force from the fields, collision, store (solid nodes store zeros), boundary record
@@ -801,7 +851,8 @@ hipError_t launch_cp(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext
     if (c->n_l2 > 0)
         hipLaunchKernelGGL((k_cp_layer<S, C>), dim3(cp_grid(c->n_l2)), blk, 0, c->stream, p,
                            reinterpret_cast<const int32_t*>(c->lat + c->L.cp_l2), c->n_l2, 2);
-    hipLaunchKernelGGL((k_cp_mu<S, C>), grid, blk, 0, c->stream, p);
+    hipLaunchKernelGGL((k_cp_mu<S, C>), dim3(grid.x, unsigned((c->p.ny + CP_MU_ROWS - 1) / CP_MU_ROWS)), blk, 0,
+                       c->stream, p);
     const bool mrt = c->p.collision == MCB_COLL_MRT;
     if (pull && mrt)
         hipLaunchKernelGGL((k_cp_step<S, C, true, true>), grid, blk, 0, c->stream, p);
@@ -815,6 +866,21 @@ hipError_t launch_cp(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext
 }
 
 }  // namespace
+
+hipError_t cp_wall_mu(mcb_ctx* c) {
+    if (c->p.model != MCB_MODEL_CHEMPOT) return hipSuccess;
+    const int8_t* layer = reinterpret_cast<const int8_t*>(c->lat + c->L.cp_layer);
+    const int32_t* tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
+    const double* mus = reinterpret_cast<const double*>(c->lk + c->L.wl_phi);
+    const dim3 grid(cp_grid(c->g.N)), blk(256);
+    if (c->p.precision == MCB_F64)
+        hipLaunchKernelGGL(k_cp_mu_solid<double>, grid, blk, 0, c->stream, c->p.nx, c->p.ny, layer, tag, mus,
+                           reinterpret_cast<double*>(c->lat + c->L.cp_mu));
+    else
+        hipLaunchKernelGGL(k_cp_mu_solid<float>, grid, blk, 0, c->stream, c->p.nx, c->p.ny, layer, tag, mus,
+                           reinterpret_cast<float*>(c->lat + c->L.cp_mu));
+    return hipGetLastError();
+}
 
 hipError_t step2d(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
     if (c->p.model == MCB_MODEL_CHEMPOT) {

@@ -141,8 +141,9 @@ def drop_field(dims, dim, drops, rho_v, rho_l, W):
     return rho_v + excess
 
 
-def _rsa(rng, n, dims, dim, rlo, rhi, max_tries=2_000_000):
-    """Random sequential addition of n non-overlapping balls (periodic minimum image)."""
+def _rsa(rng, n, dims, dim, rlo, rhi, max_tries=2_000_000, gap=0.0):
+    """Random sequential addition of n balls (periodic minimum image) whose surfaces are more than
+    gap apart (gap 0: non-overlapping, possibly nearly touching)."""
     cs = np.zeros((0, dim))
     rs = np.zeros(0)
     L = np.array(dims[:dim], np.float64)
@@ -155,7 +156,7 @@ def _rsa(rng, n, dims, dim, rlo, rhi, max_tries=2_000_000):
         r = rng.uniform(rlo, rhi)
         if len(rs):
             d = _min_image(cs - c, L)
-            if np.any(np.sqrt((d**2).sum(1)) <= rs + r):
+            if np.any(np.sqrt((d**2).sum(1)) <= rs + r + gap):
                 continue
         cs = np.vstack([cs, c])
         rs = np.append(rs, r)
@@ -177,7 +178,17 @@ def _drops(rng, n, dims, dim, rlo, rhi):
 PHI_RANGE = (0.85, 1.15)
 
 
-def make(name: str) -> Workload:
+# smallest gap between the balls of c1 / c2 when they carry the chemical-potential model: its
+# fourth-order stencils reach two nodes into the solid (two solid layers), and the gaps of a
+# fraction of a lattice unit that random sequential addition leaves between nearly touching balls
+# hold fluid nodes whose stencils span both walls; there the step ends in a domain error within a
+# thousand steps (the pseudopotential's nearest-neighbour force runs on the same cusps)
+CP_MIN_GAP = 4.0
+
+
+def make(name: str, min_gap: float = 0.0) -> Workload:
+    """Workload by name; min_gap > 0 keeps the balls of c1 / c2 that far apart (the same recipe,
+    so with other draws: the balls, drops and factors differ from those of min_gap = 0)."""
     name = name.lower()
     if name == "c0":
         R, rd = 12.3, 10.0
@@ -190,14 +201,15 @@ def make(name: str) -> Workload:
         seed = 1 if name == "c1" else 2
         n = 1024 * scale
         rng = np.random.Generator(np.random.PCG64(seed))
-        cs, rs = _rsa(rng, 300 * scale * scale, (n, n, 1), 2, 8.0, 24.0)
+        cs, rs = _rsa(rng, 300 * scale * scale, (n, n, 1), 2, 8.0, 24.0, gap=min_gap)
         shapes = np.array([ball(c, r, g) for g, (c, r) in enumerate(zip(cs, rs))], np.int64)
         drops = _drops(rng, 40 * scale * scale, (n, n, 1), 2, 15.0, 40.0)
         phi = rng.uniform(*PHI_RANGE, len(rs))
         # 0.7 T_c and tau = 1: with single-relaxation-time collision the pseudopotential runs at
         # 0.6 or 0.65 T_c (density ratio ~700 / ~250) end in psi domain errors within a few
         # thousand steps on these geometries; 0.7 T_c (ratio ~65, the c0 temperature) stays stable
-        return Workload(name, 2, (n, n, 1), 1.0, 0.70, shapes, drops, phi, 10000 if name == "c1" else 5000)
+        return Workload(name, 2, (n, n, 1), 1.0, 0.70, shapes, drops, phi, 10000 if name == "c1" else 5000,
+                        extra={"min_gap": min_gap} if min_gap > 0 else {})
     if name == "c3":
         rng = np.random.Generator(np.random.PCG64(3))
         top = 10.35
