@@ -158,7 +158,8 @@ def cpu_baseline(wl, budget_s=12.0, single_s=4.0, bc_mode="present", collision="
         "unit": "MLUPS",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{steps} steps of workload {wl.name} ({'x'.join(map(str, wl.dims[:wl.dim]))}) after set-up, FP64",
+        "sample": f"{steps} steps of workload {wl.name} ({'x'.join(map(str, wl.dims[:wl.dim]))}) after set-up, FP64"
+                  + (f", {model} model, {collision}" if model != "pseudo" or collision != "bgk" else ""),
         "cpu_model": _cpu_model(),
         "single_thread_value": wl.N * s1 / e1 / 1e6,
         "single_thread_sample": f"{s1} steps, 1 thread",
@@ -248,7 +249,7 @@ def main():
             "model": args.model,
             "rho_ref": rho_ref,
             "links": nl, "boundary_nodes": nb, "wall_nodes": nw,
-            "T_over_Tc": wl.T_over_Tc, "tau": wl.tau,
+            "T_over_Tc": 0.8 if args.model == "chempot" else wl.T_over_Tc, "tau": wl.tau,
         },
         "roofline": {
             "bound": "hbm",
