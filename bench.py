@@ -4,7 +4,8 @@ A step is one pass of the whole hot path over the lattice: the fused kernel that
 populations, applies the curved-boundary links (eqs. 16-18), computes the pseudopotential force and
 collides. Inputs are resident in HBM before the timed region starts. Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--bc-mode present] [--collision bgk] [--model pseudo] [--no-cpu] [--no-adjoint]
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--precision f32s] [--bc-mode present]
+                    [--collision bgk] [--model pseudo] [--gravity 0,0] [--no-cpu] [--no-adjoint]
 
 Default: the 4096^2 D2Q9 workload (4800 circles, 640 drops) with shifted-FP32 storage, its 5000
 steps, as the throughput and HBM-roofline figures are quoted on it; the oracle is timed on a
@@ -34,21 +35,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def setup_gpu(wl, precision, rho_ref, bc_mode="present", collision="bgk", model="pseudo"):
+def setup_gpu(wl, precision, rho_ref, bc_mode="present", collision="bgk", model="pseudo", gravity=(0.0, 0.0, 0.0)):
     from paper_2203_04508_amd import mcb
     from paper_2203_04508_amd import workloads as W
 
     if model == "chempot":
         # the paper's chemical-potential model on the same geometry: Peng-Robinson at 0.8 T_c
         lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, 0.8 * W.PR_TC, precision=precision, rho_ref=rho_ref,
-                          bc_mode=bc_mode, collision=collision, model="chempot", cp_k=W.CP_K, cp_kappa=W.CP_KAPPA)
+                          bc_mode=bc_mode, collision=collision, gravity=gravity[:wl.dim], model="chempot",
+                          cp_k=W.CP_K, cp_kappa=W.CP_KAPPA)
         nl, nb, nw = lat.set_geometry(wl.shapes)
         rho0, mu_s, _ = W.chempot_inputs(wl, lat.wall_nodes())
         lat.set_wettability(mu_s)
         lat.init_equilibrium(rho0)
         return lat, (nl, nb, nw)
     lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision, rho_ref=rho_ref, bc_mode=bc_mode,
-                      collision=collision)
+                      collision=collision, gravity=gravity[:wl.dim])
     nl, nb, nw = lat.set_geometry(wl.shapes)
     lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
     lat.init_equilibrium(wl.rho0())
@@ -118,7 +120,8 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(wl, budget_s=12.0, single_s=4.0, bc_mode="present", collision="bgk", model="pseudo"):
+def cpu_baseline(wl, budget_s=12.0, single_s=4.0, bc_mode="present", collision="bgk", model="pseudo",
+                 gravity=(0.0, 0.0)):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload (same boundary
     scheme and collision): all threads OpenMP gives it, then one thread."""
     from oracle import oracle
@@ -129,6 +132,8 @@ def cpu_baseline(wl, budget_s=12.0, single_s=4.0, bc_mode="present", collision="
     sim.set_bc_mode({"present": 0, "ibc": 1, "mibc": 2, "hbbc": 3}[bc_mode])
     if collision == "mrt":
         sim.set_mrt()
+    if any(g != 0.0 for g in gravity):
+        sim.set_gravity(tuple(gravity))
     if model == "chempot":
         sim.set_chempot(0.8 * W.PR_TC, k=W.CP_K, kappa=W.CP_KAPPA)
         rho0, mu_s, _ = W.chempot_inputs(wl, oracle.wall_nodes(P, solid))
@@ -159,7 +164,8 @@ def cpu_baseline(wl, budget_s=12.0, single_s=4.0, bc_mode="present", collision="
         "cores": threads,
         "kind": "oracle",
         "sample": f"{steps} steps of workload {wl.name} ({'x'.join(map(str, wl.dims[:wl.dim]))}) after set-up, FP64"
-                  + (f", {model} model, {collision}" if model != "pseudo" or collision != "bgk" else ""),
+                  + (f", {model} model, {collision}" if model != "pseudo" or collision != "bgk" else "")
+                  + (f", gravity {tuple(gravity)}" if any(g != 0.0 for g in gravity) else ""),
         "cpu_model": _cpu_model(),
         "single_thread_value": wl.N * s1 / e1 / 1e6,
         "single_thread_sample": f"{s1} steps, 1 thread",
@@ -176,13 +182,14 @@ def main():
     ap.add_argument("--bc-mode", default="present", choices=["present", "ibc", "mibc", "hbbc"])
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"])
     ap.add_argument("--model", default="pseudo", choices=["pseudo", "chempot"])
+    ap.add_argument("--gravity", default="0,0,0", help="body-force acceleration gx,gy[,gz] (lattice units)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the domain-decomposed "
-              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the step would shard by "
+              "domain decomposition with a two-node halo, which is not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -195,7 +202,9 @@ def main():
     steps = args.steps if args.steps is not None else wl.steps
     rho_ref = (W.PR_MAXWELL[0.80][0] if args.model == "chempot" else wl.rho_v) if args.precision != "f64" else 0.0
     log(f"[bench] workload {wl.name} dims {wl.dims[:wl.dim]} precision {args.precision}: set-up")
-    lat, (nl, nb, nw) = setup_gpu(wl, args.precision, rho_ref, args.bc_mode, args.collision, args.model)
+    grav = tuple(float(v) for v in args.gravity.split(",")) + (0.0, 0.0, 0.0)
+    grav = grav[:3]
+    lat, (nl, nb, nw) = setup_gpu(wl, args.precision, rho_ref, args.bc_mode, args.collision, args.model, grav)
     M0 = lat.mass().M
     log(f"[bench] links {nl} boundary nodes {nb} wall nodes {nw}; warmup {args.warmup}")
     lat.step(args.warmup)
@@ -211,6 +220,15 @@ def main():
     lat.timing(False)
     rep = lat.mass()
     drift = (rep.M - M0) / M0
+    # the monitors of the step (mass / momentum / eq. 18 total; the largest speed), host-synchronous
+    # calls timed by the wall clock, result copy included
+    monitor = {}
+    for name, call in (("mass", lat.mass), ("max_speed", lat.max_speed)):
+        call()
+        t1 = time.perf_counter()
+        for _ in range(20):
+            call()
+        monitor[name + "_ms_per_call"] = (time.perf_counter() - t1) / 20 * 1e3
 
     from paper_2203_04508_amd.traffic import kernel_digest
 
@@ -250,6 +268,7 @@ def main():
             "rho_ref": rho_ref,
             "links": nl, "boundary_nodes": nb, "wall_nodes": nw,
             "T_over_Tc": 0.8 if args.model == "chempot" else wl.T_over_Tc, "tau": wl.tau,
+            "gravity": list(grav[:wl.dim]),
         },
         "roofline": {
             "bound": "hbm",
@@ -266,13 +285,15 @@ def main():
         },
         "mass_drift": drift,
         "mass_drift_steps": args.warmup + steps,
+        "monitor": monitor,
     }
     if not args.no_adjoint:
         log("[bench] forward + reverse mode (c3)")
         out["fwd_adjoint"] = fwd_adjoint(args.precision)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, bc_mode=args.bc_mode, collision=args.collision, model=args.model)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, bc_mode=args.bc_mode, collision=args.collision, model=args.model,
+                                           gravity=grav[:wl.dim])
     print(json.dumps(out), flush=True)
 
 

@@ -46,29 +46,35 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// pass 1: fixed grid of MON_BLOCKS workgroups, fixed node assignment -> deterministic partials
-template <class S, class C>
-__global__ __launch_bounds__(256) void k_mon_partial(GridDev g, int L, const S* __restrict__ f, const int32_t* __restrict__ tag,
+// pass 1: fixed grid of MON_BLOCKS workgroups, fixed node assignment -> deterministic partials.
+// A lane loads a node's tag and all Q populations together and selects by the tag (solid nodes
+// add nothing), so one memory round trip serves the node; the sums keep the direction order.
+template <class S, class C, int Q>
+__global__ __launch_bounds__(256) void k_mon_partial(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
                                                      double rho_ref, const C* __restrict__ rec, int rec_stride,
                                                      int64_t nb, double* __restrict__ partials) {
+    constexpr int L = Q == 9 ? 0 : 1;
     double acc[MON_FIELDS] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += stride) {
-        if (tag[x] < 0) continue;
+        const bool fl = tag[x] >= 0;
+        double v[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = double(ldp<S, C>(f, i, g.N, x));
         double m = 0, jx = 0, jy = 0, jz = 0;
-        for (int i = 0; i < g.Q; ++i) {
-            const double v = double(ldp<S, C>(f, i, g.N, x));
-            m += v;
-            jx += v * c_ex[L][i];
-            jy += v * c_ey[L][i];
-            jz += v * c_ez[L][i];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            m += v[i];
+            jx += v[i] * c_ex[L][i];
+            jy += v[i] * c_ey[L][i];
+            jz += v[i] * c_ez[L][i];
         }
         m += rho_ref;
-        acc[0] += m;
-        acc[1] += jx;
-        acc[2] += jy;
-        acc[3] += jz;
-        if (!isfinite(m) || !isfinite(jx) || !isfinite(jy) || !isfinite(jz)) acc[5] += 1.0;
+        acc[0] += fl ? m : 0.0;
+        acc[1] += fl ? jx : 0.0;
+        acc[2] += fl ? jy : 0.0;
+        acc[3] += fl ? jz : 0.0;
+        if (fl && (!isfinite(m) || !isfinite(jx) || !isfinite(jy) || !isfinite(jz))) acc[5] += 1.0;
     }
     // eq. 18 corrections that the last step applied, from the boundary records of the state
     const int ds = rec_stride - 1;
@@ -229,9 +235,14 @@ template <class S, class C>
 hipError_t monitor_t(mcb_ctx* c, const void* fcur, const void* rcur) {
     const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
     double* partials = reinterpret_cast<double*>(c->lat + c->L.partials);
-    hipLaunchKernelGGL((k_mon_partial<S, C>), dim3(MON_BLOCKS), dim3(256), 0, c->stream, c->g, c->g.dim == 2 ? 0 : 1,
-                       static_cast<const S*>(fcur), reinterpret_cast<const int32_t*>(c->lat + c->L.tag), rr,
-                       static_cast<const C*>(rcur), int(c->L.rec_stride), c->n_bnodes > 0 ? c->n_bnodes : 0, partials);
+    const int32_t* tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
+    const int64_t nb = c->n_bnodes > 0 ? c->n_bnodes : 0;
+    if (c->g.dim == 2)
+        hipLaunchKernelGGL((k_mon_partial<S, C, 9>), dim3(MON_BLOCKS), dim3(256), 0, c->stream, c->g,
+                           static_cast<const S*>(fcur), tag, rr, static_cast<const C*>(rcur), int(c->L.rec_stride), nb, partials);
+    else
+        hipLaunchKernelGGL((k_mon_partial<S, C, 19>), dim3(MON_BLOCKS), dim3(256), 0, c->stream, c->g,
+                           static_cast<const S*>(fcur), tag, rr, static_cast<const C*>(rcur), int(c->L.rec_stride), nb, partials);
     hipLaunchKernelGGL(k_mon_final, dim3(1), dim3(256), 0, c->stream, partials, MON_BLOCKS,
                        reinterpret_cast<double*>(c->lat + c->L.result));
     return hipGetLastError();
