@@ -45,11 +45,32 @@ __device__ inline double wforce(int L, int i) {
     return i < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
 }
 
-__device__ inline int64_t nbr(const GridDev& g, int L, int64_t x, int i, int sign) {
-    const int cx = int(x % g.nx), cy = int((x / g.nx) % g.ny), cz = int(x / (int64_t(g.nx) * g.ny));
-    return wrap1(cx + sign * c_ex[L][i], g.nx) +
-           int64_t(g.nx) * (wrap1(cy + sign * c_ey[L][i], g.ny) + int64_t(g.ny) * wrap1(cz + sign * c_ez[L][i], g.nz));
+// a node's lattice position (32-bit arithmetic: N < 2^31) and its periodic neighbours
+struct Pos {
+    int x, y, z;
+};
+__device__ inline Pos pos_of(const GridDev& g, int64_t x) {
+    const uint32_t u = uint32_t(x), nx = uint32_t(g.nx), nxy = nx * uint32_t(g.ny);
+    const uint32_t z = u / nxy, r = u - z * nxy, y = r / nx;
+    return {int(r - y * nx), int(y), int(z)};
 }
+__device__ inline int64_t nbr_at(const GridDev& g, int L, const Pos& p, int i, int sign) {
+    return int64_t(wrap1(p.x + sign * c_ex[L][i], g.nx)) +
+           int64_t(g.nx) * (wrap1(p.y + sign * c_ey[L][i], g.ny) + int64_t(g.ny) * wrap1(p.z + sign * c_ez[L][i], g.nz));
+}
+__device__ inline int64_t nbr(const GridDev& g, int L, int64_t x, int i, int sign) { return nbr_at(g, L, pos_of(g, x), i, sign); }
+
+// opposite direction, a compile-time constant inside unrolled loops (D2Q9 pairs 1-3, 2-4, 5-7, 6-8;
+// D3Q19 pairs 2k-1, 2k)
+template <int L>
+__host__ __device__ constexpr int opp(int i) {
+    return L == 0 ? (i == 0 ? 0 : (i < 5 ? (i + 1) % 4 + 1 : (i - 3) % 4 + 5)) : (i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1));
+}
+static_assert(opp<0>(1) == 3 && opp<0>(2) == 4 && opp<0>(3) == 1 && opp<0>(4) == 2 && opp<0>(5) == 7 &&
+                  opp<0>(6) == 8 && opp<0>(7) == 5 && opp<0>(8) == 6 && opp<0>(0) == 0,
+              "D2Q9 opposites");
+static_assert(opp<1>(1) == 2 && opp<1>(2) == 1 && opp<1>(17) == 18 && opp<1>(18) == 17 && opp<1>(0) == 0,
+              "D3Q19 opposites");
 
 struct AdjDev {
     GridDev g;
@@ -120,60 +141,72 @@ __device__ inline double ldf<double>(const double* g, const AdjDev& A, int i, in
 }
 
 // ---- 1: pre-collision populations p and density of time t+1 (recomputed from (g, R) of time t);
-// pull = 0: p = f^eq(rho0, 0), the first collision's input
-template <class S, class RC>
-__global__ void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __restrict__ la, const RC* __restrict__ Fv,
+// pull = 0: p = f^eq(rho0, 0), the first collision's input.  Q is a template parameter so that
+// every direction loop unrolls and the per-node arrays live in registers.
+template <class S, class RC, int Q>
+__global__ __launch_bounds__(256) void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __restrict__ la, const RC* __restrict__ Fv,
                             int pull, const double* __restrict__ rho0, double* __restrict__ p, double* __restrict__ rho) {
-    const int Q = A.g.Q;
+    constexpr int L = Q == 9 ? 0 : 1;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < A.g.N; x += int64_t(gridDim.x) * blockDim.x) {
         const int tg = A.tag[x];
         if (tg < 0) continue;
-        double v[19];
+        double v[Q];
         if (!pull) {
-            for (int i = 0; i < Q; ++i) v[i] = wgt<double>(A.L, i) * rho0[x];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) v[i] = wgt<double>(L, i) * rho0[x];
         } else {
-            for (int i = 0; i < Q; ++i) v[i] = ldf<S>(gt, A, i, nbr(A.g, A.L, x, i, -1));
+            const Pos ps = pos_of(A.g, x);
+            double pl[Q];  // the pulled values (the links replace some entries of v below)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) pl[i] = ldf<S>(gt, A, i, nbr_at(A.g, L, ps, i, -1));
+#pragma unroll
+            for (int i = 0; i < Q; ++i) v[i] = pl[i];
             const uint32_t m = link_bits(A, x, tg);
-            double dm = 0.0;
-            // forcing terms of time t: rho and rho u + F from the node's own populations
-            double r0 = 0.0, m0[3] = {0, 0, 0}, F0[3] = {0, 0, 0};
             if (m) {
+                double fo[Q];  // the node's own populations
+#pragma unroll
+                for (int i = 0; i < Q; ++i) fo[i] = ldf<S>(gt, A, i, x);
+                // forcing terms of time t: rho and rho u + F from the node's own populations
+                double r0 = 0.0, m0[3] = {0, 0, 0}, F0[3] = {0, 0, 0};
+#pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    const double fi = ldf<S>(gt, A, i, x);
-                    r0 += fi;
-                    m0[0] += fi * c_ex[A.L][i];
-                    m0[1] += fi * c_ey[A.L][i];
-                    m0[2] += fi * c_ez[A.L][i];
+                    r0 += fo[i];
+                    m0[0] += fo[i] * c_ex[L][i];
+                    m0[1] += fo[i] * c_ey[L][i];
+                    m0[2] += fo[i] * c_ez[L][i];
                 }
                 const int64_t b = bidx(A, tg);
                 // F = rho du from the forcing terms at the head of the boundary record
                 for (int k = 0; k < A.g.dim; ++k) F0[k] = double(Fv[b * A.fs]) * double(Fv[b * A.fs + 1 + k]);
                 for (int k = 0; k < 3; ++k) m0[k] -= F0[k];
+                double dm = 0.0;
+#pragma unroll
+                for (int j = 1; j < Q; ++j) {
+                    if (!((m >> (j - 1)) & 1u)) continue;
+                    const int64_t sl = link_slot(A, tg, m, j);
+                    const double a = double(la[sl]);
+                    // R_j = E_j(rho, m + F) - E_j(rho, m), E the equilibrium in momentum form
+                    const double w = wgt<double>(L, j);
+                    const double e[3] = {double(c_ex[L][j]), double(c_ey[L][j]), double(c_ez[L][j])};
+                    const double m1[3] = {m0[0] + F0[0], m0[1] + F0[1], m0[2] + F0[2]};
+                    const double em0 = e[0] * m0[0] + e[1] * m0[1] + e[2] * m0[2];
+                    const double em1 = e[0] * m1[0] + e[1] * m1[1] + e[2] * m1[2];
+                    const double mm0 = m0[0] * m0[0] + m0[1] * m0[1] + m0[2] * m0[2];
+                    const double mm1 = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
+                    const double Fj = w * (3.0 * (em1 - em0) + (4.5 * (em1 * em1 - em0 * em0) - 1.5 * (mm1 - mm0)) / r0);
+                    const double fj = fo[j];
+                    // x2 = x - e_j: its value is the one pulled into direction j
+                    const double o = a < 0.0 ? fo[opp<L>(j)] : (A.tag[nbr_at(A.g, L, ps, j, -1)] >= 0 ? pl[j] : 0.0);
+                    const double c1 = fabs(a), c2 = 1.0 - c1;
+                    const double B = c1 * fj + c2 * (o + A.kF * Fj);
+                    v[opp<L>(j)] = B;
+                    dm += fj - B;
+                }
+                v[0] += A.k18 * dm;
             }
-            for (int j = 1; j < Q; ++j) {
-                if (!((m >> (j - 1)) & 1u)) continue;
-                const int64_t sl = link_slot(A, tg, m, j);
-                const double a = double(la[sl]);
-                // R_j = E_j(rho, m + F) - E_j(rho, m), E the equilibrium in momentum form
-                const double w = wgt<double>(A.L, j);
-                const double e[3] = {double(c_ex[A.L][j]), double(c_ey[A.L][j]), double(c_ez[A.L][j])};
-                const double m1[3] = {m0[0] + F0[0], m0[1] + F0[1], m0[2] + F0[2]};
-                const double em0 = e[0] * m0[0] + e[1] * m0[1] + e[2] * m0[2];
-                const double em1 = e[0] * m1[0] + e[1] * m1[1] + e[2] * m1[2];
-                const double mm0 = m0[0] * m0[0] + m0[1] * m0[1] + m0[2] * m0[2];
-                const double mm1 = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
-                const double Fj = w * (3.0 * (em1 - em0) + (4.5 * (em1 * em1 - em0 * em0) - 1.5 * (mm1 - mm0)) / r0);
-                const double fj = ldf<S>(gt, A, j, x);
-                const double o = a < 0.0 ? ldf<S>(gt, A, c_opp[A.L][j], x)
-                                         : (A.tag[nbr(A.g, A.L, x, j, -1)] >= 0 ? ldf<S>(gt, A, j, nbr(A.g, A.L, x, j, -1)) : 0.0);
-                const double c1 = fabs(a), c2 = 1.0 - c1;
-                const double B = c1 * fj + c2 * (o + A.kF * Fj);
-                v[c_opp[A.L][j]] = B;
-                dm += fj - B;
-            }
-            v[0] += A.k18 * dm;
         }
         double r = 0.0;
+#pragma unroll
         for (int i = 0; i < Q; ++i) {
             p[i * A.g.N + x] = v[i];
             r += v[i];
@@ -183,21 +216,31 @@ __global__ void k_recompute(AdjDev A, const S* __restrict__ gt, const RC* __rest
 }
 
 // ---- 2: psi, d psi / d rho; wall nodes also keep rho_ave and the weight sum of eq. 15
-__global__ void k_psi(AdjDev A, const double* __restrict__ rho, double* __restrict__ psi, double* __restrict__ dpsi,
-                      double* __restrict__ rave, double* __restrict__ den) {
+template <int Q>
+__global__ __launch_bounds__(256) void k_psi(AdjDev A, const double* __restrict__ rho, double* __restrict__ psi,
+                                             double* __restrict__ dpsi, double* __restrict__ rave, double* __restrict__ den) {
+    constexpr int L = Q == 9 ? 0 : 1;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < A.g.N; x += int64_t(gridDim.x) * blockDim.x) {
         const int tg = A.tag[x];
         double s = 0.0, ds = 0.0;
         if (tg >= 0) {
             psi_d(A, rho[x], &s, &ds);
         } else if (tg <= -2) {
+            // every neighbour's tag and density at once; the solid ones are dropped by selection
+            const Pos ps = pos_of(A.g, x);
+            int ty[Q];
+            double ry[Q];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int64_t y = nbr_at(A.g, L, ps, i, +1);
+                ty[i] = A.tag[y];
+                ry[i] = rho[y];
+            }
             double num = 0.0, dn = 0.0;
-            for (int i = 1; i < A.g.Q; ++i) {
-                const int64_t y = nbr(A.g, A.L, x, i, +1);
-                if (A.tag[y] >= 0) {
-                    num += wgt<double>(A.L, i) * rho[y];
-                    dn += wgt<double>(A.L, i);
-                }
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                num += ty[i] >= 0 ? wgt<double>(L, i) * ry[i] : 0.0;
+                dn += ty[i] >= 0 ? wgt<double>(L, i) : 0.0;
             }
             const double ra = num / dn;
             psi_d(A, A.phi[-tg - 2] * ra, &s, &ds);
@@ -211,26 +254,38 @@ __global__ void k_psi(AdjDev A, const double* __restrict__ rho, double* __restri
 
 // ---- 3: transposed collision.  lam1 = adjoint of g'(t+1), lamR1 = adjoint of R(t+1) (per link
 // slot).  Gives pbar = adjoint of p through the direct and (rho, j) dependences, and Fbar.
-__global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double* __restrict__ rho,
+template <int Q>
+__global__ __launch_bounds__(256) void k_collide_T(AdjDev A, const double* __restrict__ p, const double* __restrict__ rho,
                             const double* __restrict__ psi, const double* __restrict__ lam1,
                             const double* __restrict__ lamR1, double* __restrict__ pbar, double* __restrict__ Fbar,
                             double* __restrict__ Fv, const double* __restrict__ Fin) {
-    const int Q = A.g.Q, L = A.L;
+    constexpr int L = Q == 9 ? 0 : 1;
     const int64_t N = A.g.N;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x) {
         const int tg = A.tag[x];
         if (tg < 0) continue;
         const double r = rho[x];
-        double j[3] = {0, 0, 0}, S[3] = {0, 0, 0};
+        double pv[Q], la[Q];
+#pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double v = p[i * N + x];
-            j[0] += v * c_ex[L][i];
-            j[1] += v * c_ey[L][i];
-            j[2] += v * c_ez[L][i];
+            pv[i] = p[i * N + x];
+            la[i] = lam1[i * N + x];
+        }
+        double j[3] = {0, 0, 0}, S[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            j[0] += pv[i] * c_ex[L][i];
+            j[1] += pv[i] * c_ey[L][i];
+            j[2] += pv[i] * c_ez[L][i];
         }
         if (!Fin) {
+            const Pos ps = pos_of(A.g, x);
+            double pn[Q];
+#pragma unroll
+            for (int k = 1; k < Q; ++k) pn[k] = psi[nbr_at(A.g, L, ps, k, +1)];
+#pragma unroll
             for (int k = 1; k < Q; ++k) {
-                const double w = wforce(L, k) * psi[nbr(A.g, L, x, k, +1)];
+                const double w = wforce(L, k) * pn[k];
                 S[0] += w * c_ex[L][k];
                 S[1] += w * c_ey[L][k];
                 S[2] += w * c_ez[L][k];
@@ -241,42 +296,55 @@ __global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double
         const double F[3] = {Fin ? Fin[x] : gp * S[0] + r * A.grav[0], Fin ? Fin[N + x] : gp * S[1] + r * A.grav[1],
                              Fin ? Fin[2 * N + x] : gp * S[2] + r * A.grav[2]};
         // lt = (I - K)^T lambda: the adjoint of the direct dependence on p
-        double lt[19];
-        for (int i = 0; i < Q; ++i) lt[i] = lam1[i * N + x];
-        if (A.mrt) {
-            double mu[9];
-            for (int k = 0; k < 9; ++k) {
-                double v = 0.0;
-                for (int i = 0; i < 9; ++i) v += kM2[k][i] * lt[i];
-                mu[k] = A.msc[k] * v;
+        double lt[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lt[i] = la[i];
+        bool bgk = true;
+        if constexpr (Q == 9) {
+            if (A.mrt) {
+                bgk = false;
+                double mu[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) v += kM2[k][i] * lt[i];
+                    mu[k] = A.msc[k] * v;
+                }
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) v += kM2[k][i] * mu[k];
+                    lt[i] -= v;
+                }
             }
-            for (int i = 0; i < 9; ++i) {
-                double v = 0.0;
-                for (int k = 0; k < 9; ++k) v += kM2[k][i] * mu[k];
-                lt[i] -= v;
-            }
-        } else {
+        }
+        if (bgk) {
+#pragma unroll
             for (int i = 0; i < Q; ++i) lt[i] *= 1.0 - 1.0 / A.tau;
         }
         const double m1[3] = {j[0] + F[0], j[1] + F[1], j[2] + F[2]};
         const double mm0 = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
         const double mm1 = m1[0] * m1[0] + m1[1] * m1[1] + m1[2] * m1[2];
         const uint32_t msk = link_bits(A, x, tg);
+        double rr[Q];  // adjoint of the forcing term on each link (0 without a link)
+        rr[0] = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) rr[i] = ((msk >> (i - 1)) & 1u) ? lamR1[link_slot(A, tg, msk, i)] : 0.0;
         double rb = 0.0, jb[3] = {0, 0, 0}, Fb[3] = {0, 0, 0};
         const double ir = 1.0 / r, ir2 = ir * ir;
+#pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double ab = lam1[i * N + x];
-            double rr = 0.0;
-            if (i >= 1 && ((msk >> (i - 1)) & 1u)) rr = lamR1[link_slot(A, tg, msk, i)];
-            const double al = ab + rr;   // on E_i(rho, j + F)
-            const double be = -lt[i] - rr;  // on E_i(rho, j): (K - I)^T lambda
-            (void)ab;
+            const double al = la[i] + rr[i];  // on E_i(rho, j + F)
+            const double be = -lt[i] - rr[i];  // on E_i(rho, j): (K - I)^T lambda
             const double w = wgt<double>(L, i);
             const double e[3] = {double(c_ex[L][i]), double(c_ey[L][i]), double(c_ez[L][i])};
             const double em0 = e[0] * j[0] + e[1] * j[1] + e[2] * j[2];
             const double em1 = e[0] * m1[0] + e[1] * m1[1] + e[2] * m1[2];
             // d E / d rho and d E / d m at (rho, m)
             rb += al * w * (1.0 - (4.5 * em1 * em1 - 1.5 * mm1) * ir2) + be * w * (1.0 - (4.5 * em0 * em0 - 1.5 * mm0) * ir2);
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const double d1 = al * w * (3.0 * e[k] + (9.0 * em1 * e[k] - 3.0 * m1[k]) * ir);
                 const double d0 = be * w * (3.0 * e[k] + (9.0 * em0 * e[k] - 3.0 * j[k]) * ir);
@@ -286,6 +354,7 @@ __global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double
         }
         // the body force depends on rho: F = ... + rho g
         rb += Fb[0] * A.grav[0] + Fb[1] * A.grav[1] + Fb[2] * A.grav[2];
+#pragma unroll
         for (int i = 0; i < Q; ++i)
             pbar[i * N + x] = lt[i] + rb + c_ex[L][i] * jb[0] + c_ey[L][i] * jb[1] + c_ez[L][i] * jb[2];
         for (int k = 0; k < 3; ++k) {
@@ -298,32 +367,50 @@ __global__ void k_collide_T(AdjDev A, const double* __restrict__ p, const double
 // ---- 4: transposed force stencil and psi.  Fluid y: rbar = psi'(rho) psibar; wall s:
 // rho_w-bar = psi'(rho_w) psibar, dphi += rho_w-bar rho_ave, qbar = rho_w-bar phi / den (to be
 // spread over the fluid neighbours with their lattice weights).
-__global__ void k_psi_T(AdjDev A, const double* __restrict__ psi, const double* __restrict__ dpsi,
-                        const double* __restrict__ rave, const double* __restrict__ den, const double* __restrict__ Fbar,
-                        double* __restrict__ rbar, double* __restrict__ qbar, double* __restrict__ dphi) {
-    const int Q = A.g.Q, L = A.L;
+template <int Q>
+__global__ __launch_bounds__(256) void k_psi_T(AdjDev A, const double* __restrict__ psi, const double* __restrict__ dpsi,
+                                               const double* __restrict__ rave, const double* __restrict__ den,
+                                               const double* __restrict__ Fbar, double* __restrict__ rbar,
+                                               double* __restrict__ qbar, double* __restrict__ dphi) {
+    constexpr int L = Q == 9 ? 0 : 1;
     const int64_t N = A.g.N;
     for (int64_t y = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; y < N; y += int64_t(gridDim.x) * blockDim.x) {
         const int tg = A.tag[y];
         if (tg == -1) continue;
+        const Pos ps = pos_of(A.g, y);
         double pb = 0.0;
         if (tg >= 0) {
             // own force: F(y) = -G psi(y) S(y)
+            double pn[Q];
+#pragma unroll
+            for (int k = 1; k < Q; ++k) pn[k] = psi[nbr_at(A.g, L, ps, k, +1)];
             double S[3] = {0, 0, 0};
+#pragma unroll
             for (int k = 1; k < Q; ++k) {
-                const double w = wforce(L, k) * psi[nbr(A.g, L, y, k, +1)];
+                const double w = wforce(L, k) * pn[k];
                 S[0] += w * c_ex[L][k];
                 S[1] += w * c_ey[L][k];
                 S[2] += w * c_ez[L][k];
             }
             pb += -A.G * (Fbar[y] * S[0] + Fbar[N + y] * S[1] + Fbar[2 * N + y] * S[2]);
         }
-        // the fluid neighbours x = y - e_k whose force uses psi(y) = psi(x + e_k)
+        // the fluid neighbours x = y - e_k whose force uses psi(y) = psi(x + e_k): every neighbour's
+        // tag, psi and force adjoint at once, the non-fluid ones dropped by selection
+        int tx[Q];
+        double px[Q], fx[Q][3];
+#pragma unroll
         for (int k = 1; k < Q; ++k) {
-            const int64_t x = nbr(A.g, L, y, k, -1);
-            if (A.tag[x] < 0) continue;
-            const double fe = Fbar[x] * c_ex[L][k] + Fbar[N + x] * c_ey[L][k] + Fbar[2 * N + x] * c_ez[L][k];
-            pb += -A.G * psi[x] * wforce(L, k) * fe;
+            const int64_t x = nbr_at(A.g, L, ps, k, -1);
+            tx[k] = A.tag[x];
+            px[k] = psi[x];
+            fx[k][0] = Fbar[x];
+            fx[k][1] = Fbar[N + x];
+            fx[k][2] = Fbar[2 * N + x];
+        }
+#pragma unroll
+        for (int k = 1; k < Q; ++k) {
+            const double fe = fx[k][0] * c_ex[L][k] + fx[k][1] * c_ey[L][k] + fx[k][2] * c_ez[L][k];
+            pb += tx[k] >= 0 ? -A.G * px[k] * wforce(L, k) * fe : 0.0;
         }
         if (tg >= 0) {
             rbar[y] = dpsi[y] * pb;
@@ -515,17 +602,28 @@ __global__ void k_cpa_prep(AdjDev A, const double* __restrict__ rhob, double* __
 }
 
 // ---- 5: density adjoint into pbar (rho = sum_i p_i)
-__global__ void k_rho_T(AdjDev A, const double* __restrict__ rbar, const double* __restrict__ qbar, double* __restrict__ pbar) {
-    const int Q = A.g.Q, L = A.L;
+template <int Q>
+__global__ __launch_bounds__(256) void k_rho_T(AdjDev A, const double* __restrict__ rbar, const double* __restrict__ qbar,
+                                               double* __restrict__ pbar) {
+    constexpr int L = Q == 9 ? 0 : 1;
     const int64_t N = A.g.N;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < N; x += int64_t(gridDim.x) * blockDim.x) {
         if (A.tag[x] < 0) continue;
-        double rb = rbar[x];
-        // wall nodes s = x - e_k average rho(x) = rho(s + e_k) with weight w_k
+        const Pos ps = pos_of(A.g, x);
+        // wall nodes s = x - e_k average rho(x) = rho(s + e_k) with weight w_k: every neighbour's tag
+        // and value at once, the other nodes dropped by selection
+        int ts[Q];
+        double qs[Q];
+#pragma unroll
         for (int k = 1; k < Q; ++k) {
-            const int64_t s = nbr(A.g, L, x, k, -1);
-            if (A.tag[s] <= -2) rb += wgt<double>(L, k) * qbar[s];
+            const int64_t s = nbr_at(A.g, L, ps, k, -1);
+            ts[k] = A.tag[s];
+            qs[k] = qbar[s];
         }
+        double rb = rbar[x];
+#pragma unroll
+        for (int k = 1; k < Q; ++k) rb += ts[k] <= -2 ? wgt<double>(L, k) * qs[k] : 0.0;
+#pragma unroll
         for (int i = 0; i < Q; ++i) pbar[i * N + x] += rb;
     }
 }
@@ -537,44 +635,56 @@ __global__ void k_rho_T(AdjDev A, const double* __restrict__ rbar, const double*
 //   eq. 16 of the link (y + e_i, i) as o = f_i(x - e_i): c2 Bbar_i(y + e_i);
 //   eq. 17 of the link (y, opp i) as o = f_i(y): c2 Bbar_opp(i)(y);
 // and R_j(y) by its own link only: c3 Bbar_j(y).
-template <class RC>
-__global__ void k_stream_T(AdjDev A, const RC* __restrict__ rec, const double* __restrict__ pbar, double* __restrict__ lam0,
-                           double* __restrict__ lamR0) {
+template <class RC, int Q>
+__global__ __launch_bounds__(256) void k_stream_T(AdjDev A, const RC* __restrict__ rec, const double* __restrict__ pbar,
+                                                  double* __restrict__ lam0, double* __restrict__ lamR0) {
     // rec: the link coefficients a per slot
-    const int Q = A.g.Q, L = A.L;
+    constexpr int L = Q == 9 ? 0 : 1;
     const int64_t N = A.g.N;
     for (int64_t y = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; y < N; y += int64_t(gridDim.x) * blockDim.x) {
         const int tg = A.tag[y];
         if (tg < 0) {
+#pragma unroll
             for (int i = 0; i < Q; ++i) lam0[i * N + y] = 0.0;
             continue;
         }
         const uint32_t m = link_bits(A, y, tg);
-        const double pb0 = pbar[y], pz = A.k18 * pb0;  // eq. 18 carries the adjoint of p_0 (if applied)
-        for (int i = 0; i < Q; ++i) {
-            double acc = 0.0;
-            if (i == 0) {
-                acc = pb0;
-            } else if ((m >> (i - 1)) & 1u) {
+        const Pos ps = pos_of(A.g, y);
+        // the node's own adjoints and, per direction, the neighbour y + e_i's tag and adjoint, all at once
+        double pby[Q], pxi[Q];
+        int64_t xs[Q];
+        int txs[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) pby[i] = pbar[i * N + y];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            xs[i] = nbr_at(A.g, L, ps, i, +1);
+            txs[i] = A.tag[xs[i]];
+            pxi[i] = pbar[i * N + xs[i]];
+        }
+        const double pb0 = pby[0], pz = A.k18 * pb0;  // eq. 18 carries the adjoint of p_0 (if applied)
+        lam0[y] = pb0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            double acc;
+            if ((m >> (i - 1)) & 1u) {
                 const int64_t sl = link_slot(A, tg, m, i);
                 const double c1 = fabs(double(rec[sl]));
-                const double Bb = pbar[c_opp[L][i] * N + y] - pz;
+                const double Bb = pby[opp<L>(i)] - pz;
                 acc = c1 * Bb + pz;
                 lamR0[sl] = A.kF * (1.0 - c1) * Bb;
             } else {
-                const int64_t x = nbr(A.g, L, y, i, +1);
-                acc = pbar[i * N + x];
-                const int tx = A.tag[x];
-                const uint32_t mx = link_bits(A, x, tx);
+                acc = pxi[i];
+                const uint32_t mx = link_bits(A, xs[i], txs[i]);
                 if ((mx >> (i - 1)) & 1u) {
-                    const double ax = double(rec[link_slot(A, tx, mx, i)]);
-                    if (ax > 0.0) acc += (1.0 - ax) * (pbar[c_opp[L][i] * N + x] - A.k18 * pbar[x]);
+                    const double ax = double(rec[link_slot(A, txs[i], mx, i)]);
+                    if (ax > 0.0) acc += (1.0 - ax) * (pbar[opp<L>(i) * N + xs[i]] - A.k18 * pbar[xs[i]]);
                 }
             }
-            const int io = c_opp[L][i];
-            if (i >= 1 && ((m >> (io - 1)) & 1u)) {
+            const int io = opp<L>(i);
+            if ((m >> (io - 1)) & 1u) {
                 const double ao = double(rec[link_slot(A, tg, m, io)]);
-                if (ao < 0.0) acc += (1.0 + ao) * (pbar[i * N + y] - pz);
+                if (ao < 0.0) acc += (1.0 + ao) * (pby[i] - pz);
             }
             lam0[i * N + y] = acc;
         }
@@ -727,9 +837,16 @@ hipError_t adj_step_t(mcb_ctx* c, const AdjWork& w, const void* gt, const void* 
     const RC* rec = reinterpret_cast<const RC*>(c->lk + c->L.lk_a);
     // boundary records of time t: rho and du = F / rho lead each record
     const RC* Fv = static_cast<const RC*>(fv);
-    hipLaunchKernelGGL((k_recompute<S, RC>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt), rec, Fv, pull,
-                       w.rho0, w.p, w.rho);
-    if (!A.cp) hipLaunchKernelGGL(k_psi, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.dpsi, w.rave, w.den);
+    if (c->g.dim == 2)
+        hipLaunchKernelGGL((k_recompute<S, RC, 9>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt), rec, Fv,
+                           pull, w.rho0, w.p, w.rho);
+    else
+        hipLaunchKernelGGL((k_recompute<S, RC, 19>), dim3(G), dim3(256), 0, c->stream, A, static_cast<const S*>(gt), rec, Fv,
+                           pull, w.rho0, w.p, w.rho);
+    const auto collide_T = c->g.dim == 2 ? k_collide_T<9> : k_collide_T<19>;
+    const bool d2 = c->g.dim == 2;
+    if (!A.cp)
+        hipLaunchKernelGGL(d2 ? k_psi<9> : k_psi<19>, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.dpsi, w.rave, w.den);
     if (A.cp) {
         // chemical-potential model: layer densities, mu and F of the recomputed state, then the
         // transposed collision, force, potential and layers (mu in psi, mu-bar in dpsi, rho-bar in rave)
@@ -737,21 +854,22 @@ hipError_t adj_step_t(mcb_ctx* c, const AdjWork& w, const void* gt, const void* 
         hipLaunchKernelGGL(k_cpa_layer, dim3(G), dim3(256), 0, c->stream, A, w.rho, 2);
         hipLaunchKernelGGL(k_cpa_mu, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi);
         hipLaunchKernelGGL(k_cpa_force, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.Fv);
-        hipLaunchKernelGGL(k_collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar,
+        hipLaunchKernelGGL(collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar,
                            w.Fv, w.Fv);
         hipLaunchKernelGGL(k_cpa_force_T, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.psi, w.Fbar, w.dpsi, w.rave);
         hipLaunchKernelGGL(k_cpa_mu_T, dim3(G), dim3(256), 0, c->stream, A, w.rho, w.dpsi, w.rave, w.dphi);
         hipLaunchKernelGGL(k_cpa_l2_T, dim3(G), dim3(256), 0, c->stream, A, w.rave);
         hipLaunchKernelGGL(k_cpa_prep, dim3(G), dim3(256), 0, c->stream, A, w.rave, w.rbar, w.qbar);
     } else {
-        hipLaunchKernelGGL(k_collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar, w.Fv,
+        hipLaunchKernelGGL(collide_T, dim3(G), dim3(256), 0, c->stream, A, w.p, w.rho, w.psi, lam1, lamR1, w.pbar, w.Fbar, w.Fv,
                            nullptr);
-        hipLaunchKernelGGL(k_psi_T, dim3(G), dim3(256), 0, c->stream, A, w.psi, w.dpsi, w.rave, w.den, w.Fbar, w.rbar, w.qbar,
-                           w.dphi);
+        hipLaunchKernelGGL(d2 ? k_psi_T<9> : k_psi_T<19>, dim3(G), dim3(256), 0, c->stream, A, w.psi, w.dpsi, w.rave, w.den,
+                           w.Fbar, w.rbar, w.qbar, w.dphi);
     }
     if (pull) {
-        hipLaunchKernelGGL(k_rho_T, dim3(G), dim3(256), 0, c->stream, A, w.rbar, w.qbar, w.pbar);
-        hipLaunchKernelGGL((k_stream_T<RC>), dim3(G), dim3(256), 0, c->stream, A, rec, w.pbar, lam0, lamR0);
+        hipLaunchKernelGGL(d2 ? k_rho_T<9> : k_rho_T<19>, dim3(G), dim3(256), 0, c->stream, A, w.rbar, w.qbar, w.pbar);
+        const auto stream_T = d2 ? k_stream_T<RC, 9> : k_stream_T<RC, 19>;
+        hipLaunchKernelGGL(stream_T, dim3(G), dim3(256), 0, c->stream, A, rec, w.pbar, lam0, lamR0);
     }
     return hipGetLastError();
 }
