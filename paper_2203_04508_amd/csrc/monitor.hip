@@ -12,10 +12,12 @@ __device__ inline C wgt(int L, int i) {
     return i == 0 ? C(1.0 / 3.0) : (i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0));
 }
 
+// periodic neighbour x + sign e_i (32-bit position arithmetic: N < 2^31)
 __device__ inline int64_t nb_index(const GridDev& g, int L, int64_t x, int i, int sign) {
-    const int cx = int(x % g.nx), cy = int((x / g.nx) % g.ny), cz = int(x / (int64_t(g.nx) * g.ny));
-    return wrap1(cx + sign * c_ex[L][i], g.nx) +
-           int64_t(g.nx) * (wrap1(cy + sign * c_ey[L][i], g.ny) + int64_t(g.ny) * wrap1(cz + sign * c_ez[L][i], g.nz));
+    const uint32_t u = uint32_t(x), nx = uint32_t(g.nx), nxy = nx * uint32_t(g.ny);
+    const uint32_t cz = u / nxy, r = u - cz * nxy, cy = r / nx, cx = r - cy * nx;
+    return int64_t(wrap1(int(cx) + sign * c_ex[L][i], g.nx)) +
+           int64_t(g.nx) * (wrap1(int(cy) + sign * c_ey[L][i], g.ny) + int64_t(g.ny) * wrap1(int(cz) + sign * c_ez[L][i], g.nz));
 }
 
 // f(x, 0) = f^eq(rho, u) - w_i rho_ref on fluid nodes (eq. 14), zero elsewhere
@@ -109,54 +111,75 @@ __global__ __launch_bounds__(256) void k_mon_final(const double* __restrict__ pa
     }
 }
 
-// ---- moments: rho, psi (fluid and wall nodes), then v = (j - F / 2) / rho
-template <class S, class C>
-__global__ void k_rho_out(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag, double rho_ref,
-                          double* __restrict__ rho) {
+// ---- moments: rho, psi (fluid and wall nodes), then v = (j - F / 2) / rho.  Q is a template
+// parameter (unrolled direction loops); each lane loads all it needs before using any.
+template <class S, class C, int Q>
+__global__ __launch_bounds__(256) void k_rho_out(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
+                                                 double rho_ref, double* __restrict__ rho) {
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
-        if (tag[x] < 0) { rho[x] = 0.0; continue; }
+        const bool fl = tag[x] >= 0;
+        double v[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = double(ldp<S, C>(f, i, g.N, x));
         double s = 0;
-        for (int i = 0; i < g.Q; ++i) s += double(ldp<S, C>(f, i, g.N, x));
-        rho[x] = s + rho_ref;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) s += v[i];
+        rho[x] = fl ? s + rho_ref : 0.0;
     }
 }
 
-__global__ void k_psi_out(GridDev g, int L, const int32_t* __restrict__ tag, const double* __restrict__ rho,
-                          const double* __restrict__ phi, Eos<double> eos, int32_t* flags, double* __restrict__ psi) {
+template <int Q>
+__global__ __launch_bounds__(256) void k_psi_out(GridDev g, const int32_t* __restrict__ tag, const double* __restrict__ rho,
+                                                 const double* __restrict__ phi, Eos<double> eos, int32_t* flags,
+                                                 double* __restrict__ psi) {
+    constexpr int L = Q == 9 ? 0 : 1;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
         const int tg = tag[x];
         if (tg >= 0) { psi[x] = psi_of(rho[x], eos, flags); continue; }
         if (tg == -1) { psi[x] = 0.0; continue; }
-        double num = 0, den = 0;
-        for (int i = 1; i < g.Q; ++i) {
+        // wall node: every neighbour's tag and density at once, the solid ones dropped by selection
+        int ty[Q];
+        double ry[Q];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
             const int64_t y = nb_index(g, L, x, i, +1);
-            if (tag[y] >= 0) {
-                num += wgt<double>(L, i) * rho[y];
-                den += wgt<double>(L, i);
-            }
+            ty[i] = tag[y];
+            ry[i] = rho[y];
+        }
+        double num = 0, den = 0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            num += ty[i] >= 0 ? wgt<double>(L, i) * ry[i] : 0.0;
+            den += ty[i] >= 0 ? wgt<double>(L, i) : 0.0;
         }
         psi[x] = psi_of(phi[-tg - 2] * (num / den), eos, flags);
     }
 }
 
-template <class S, class C>
-__global__ void k_vel_out(GridDev g, int L, const S* __restrict__ f, const int32_t* __restrict__ tag,
-                          const double* __restrict__ rho, const double* __restrict__ psi, double G, double gx, double gy,
-                          double gz, double* __restrict__ v) {
+template <class S, class C, int Q>
+__global__ __launch_bounds__(256) void k_vel_out(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
+                                                 const double* __restrict__ rho, const double* __restrict__ psi, double G,
+                                                 double gx, double gy, double gz, double* __restrict__ v) {
+    constexpr int L = Q == 9 ? 0 : 1;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
         if (tag[x] < 0) {
             for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = 0.0;
             continue;
         }
+        double fv[Q], pv[Q];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            fv[i] = double(ldp<S, C>(f, i, g.N, x));
+            pv[i] = psi[nb_index(g, L, x, i, +1)];
+        }
         double j[3] = {0, 0, 0}, s[3] = {0, 0, 0};
-        for (int i = 1; i < g.Q; ++i) {
-            const double fi = double(ldp<S, C>(f, i, g.N, x));
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
             const double ws = (L == 0) ? (i < 5 ? 1.0 / 3.0 : 1.0 / 12.0) : (i < 7 ? 1.0 / 6.0 : 1.0 / 12.0);
-            const double py = psi[nb_index(g, L, x, i, +1)];
             const int e[3] = {c_ex[L][i], c_ey[L][i], c_ez[L][i]};
             for (int k = 0; k < 3; ++k) {
-                j[k] += fi * e[k];
-                s[k] += ws * py * e[k];
+                j[k] += fv[i] * e[k];
+                s[k] += ws * pv[i] * e[k];
             }
         }
         const double gk[3] = {gx, gy, gz};
@@ -302,24 +325,26 @@ __global__ __launch_bounds__(256) void k_speed_final(const double* __restrict__ 
 template <class S, class C>
 hipError_t moments_dev(mcb_ctx* c, const void* fcur) {
     const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
-    const int L = c->g.dim == 2 ? 0 : 1;
     double* sr = reinterpret_cast<double*>(c->lat + c->L.scratch);
     double* sp = sr + c->g.N;
     double* sv = sp + c->g.N;
     const int32_t* tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
     Eos<double> eos{c->p.eos_R * c->p.eos_T, c->p.eos_a, c->p.eos_b / 4.0, 2.0 / c->p.G};
-    hipLaunchKernelGGL((k_rho_out<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, rr, sr);
+    const bool d2 = c->g.dim == 2;
+    const auto rho_out = d2 ? k_rho_out<S, C, 9> : k_rho_out<S, C, 19>;
+    hipLaunchKernelGGL(rho_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, rr, sr);
     if (c->p.model == MCB_MODEL_CHEMPOT) {
         hipLaunchKernelGGL((k_vel_cp<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag,
                            sr, reinterpret_cast<const C*>(c->lat + c->L.cp_rho), reinterpret_cast<const C*>(c->lat + c->L.cp_mu),
                            c->p.gravity[0], c->p.gravity[1], sv);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_psi_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, L, tag, sr,
+    hipLaunchKernelGGL(d2 ? k_psi_out<9> : k_psi_out<19>, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, tag, sr,
                        reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos,
                        reinterpret_cast<int32_t*>(c->lat + c->L.flags), sp);
-    hipLaunchKernelGGL((k_vel_out<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, L, static_cast<const S*>(fcur),
-                       tag, sr, sp, c->p.G, c->p.gravity[0], c->p.gravity[1], c->p.gravity[2], sv);
+    const auto vel_out = d2 ? k_vel_out<S, C, 9> : k_vel_out<S, C, 19>;
+    hipLaunchKernelGGL(vel_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, sr, sp,
+                       c->p.G, c->p.gravity[0], c->p.gravity[1], c->p.gravity[2], sv);
     return hipGetLastError();
 }
 

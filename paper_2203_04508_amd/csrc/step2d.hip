@@ -500,7 +500,8 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
         H = 64;
         while (H > 8 && int64_t(a.nsx) * ((a.ny + H - 1) / H) < 8192) H >>= 1;
     } else {
-        static int occ[4] = {0, 0, 0, 0};
+        // a context runs one storage type and one strip width, so four slots cover its variants
+        int* occ = c->occ;
         const int cap = pull ? (mrt ? resident_blocks(c, k_step2d<S, C, W, OUT, true, true>, W, &occ[3])
                                     : resident_blocks(c, k_step2d<S, C, W, OUT, true, false>, W, &occ[1]))
                              : (mrt ? resident_blocks(c, k_step2d<S, C, W, OUT, false, true>, W, &occ[2])

@@ -540,7 +540,7 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, const void* rcur, void* f
     // measured faster here than deep segments or a single resident round; the ring of four extra
     // density planes per segment costs one value per node each
     constexpr bool PF = sizeof(C) == 4;
-    static int occ[2] = {0, 0};
+    int* occ = c->occ + 4;  // slots 4, 5 (a context runs one storage type)
     const int cap = pull ? resident_blocks(c, k_step3d<S, C, true, PF>, NT, &occ[1])
                          : resident_blocks(c, k_step3d<S, C, false, PF>, NT, &occ[0]);
     const int64_t tiles = int64_t(a.ntx) * a.nty;
