@@ -5,7 +5,9 @@ factors and the 200 drops, whose Python set-up would dominate the test), against
 every node.
 
 Bars: FP64 1e-12 relative after one step; shifted FP32 (the benchmarked storage) 3e-6 (2-D) and
-2e-6 (3-D) per step, relative error per direction plane as in the other parity tests.
+2e-6 (3-D) per step, relative error per direction plane as in the other parity tests. The
+chemical-potential model with MRT runs on c2's recipe with the circles kept 4 apart (as the
+benchmark runs it), FP32 within 2e-5 per step.
 """
 import sys
 
@@ -91,5 +93,52 @@ def test_benchmark_size_parity(mcb, name, tol32):
     lat.step(1)
     e2 = rel_err(lat.get_f(), sim.get_f(), fluid)
     assert e2 < 3 * tol32, e2
+    lat.close()
+    sim.close()
+
+
+@pytest.mark.timeout(900)
+def test_benchmark_size_parity_chempot(mcb):
+    """The chemical-potential model with MRT at the benchmark size (c2's recipe with the circles at
+    least 4 apart, as bench.py runs it): FP64 1e-12 after one step, shifted FP32 2e-5 per step."""
+    banner("full-size parity c2 chemical potential + MRT: oracle set-up")
+    wl = W.make("c2", min_gap=W.CP_MIN_GAP)
+    T = 0.8 * W.PR_TC
+    P = oracle.make_params(2, *wl.dims, tau=wl.tau, T=0.05)
+    solid = oracle.classify(P, wl.shapes)
+    node, d, cls, q = oracle.links(P, wl.shapes, solid)
+    rho0, mu_s, rv = W.chempot_inputs(wl, oracle.wall_nodes(P, solid))
+    fluid = solid == 0
+    sim = oracle.Sim(P, solid, node, d, q)
+    sim.set_chempot(T, k=W.CP_K, kappa=W.CP_KAPPA)
+    sim.set_mrt()
+    sim.set_mu_wall(mu_s)
+    sim.init_eq(rho0)
+    f_init = sim.get_f()
+    sim.step(1)
+    f_one = sim.get_f()
+    opts = dict(model="chempot", cp_k=W.CP_K, cp_kappa=W.CP_KAPPA, collision="mrt")
+    banner("full-size parity c2 chemical potential + MRT: FP64, 1 step")
+    lat = mcb.Lattice(2, wl.dims, wl.tau, T, precision="f64", **opts)
+    assert lat.set_geometry(wl.shapes)[0] == len(node)
+    lat.set_wettability(mu_s)
+    lat.init_equilibrium(rho0)
+    assert rel_err(lat.get_f(), f_init, fluid) < 1e-13
+    lat.step(1)
+    e = rel_err(lat.get_f(), f_one, fluid)
+    assert e < 1e-12, e
+    lat.close()
+    banner("full-size parity c2 chemical potential + MRT: shifted FP32, 2 steps")
+    lat = mcb.Lattice(2, wl.dims, wl.tau, T, precision="f32s", rho_ref=rv, **opts)
+    lat.set_geometry(wl.shapes)
+    lat.set_wettability(mu_s)
+    lat.init_equilibrium(rho0)
+    lat.step(1)
+    e1 = rel_err(lat.get_f(), f_one, fluid)
+    assert e1 < 2 * 2e-5, e1
+    sim.step(1)
+    lat.step(1)
+    e2 = rel_err(lat.get_f(), sim.get_f(), fluid)
+    assert e2 < 3 * 2e-5, e2
     lat.close()
     sim.close()
