@@ -66,3 +66,15 @@ def test_drop_profile_and_chempot_inputs():
     mu_coex = W.CP_K ** 2 * W.MU_PR_COEX[0.80]
     assert mu_s.shape == (len(walls),) and len(walls) > 0
     assert np.allclose(mu_s, mu_coex * W.phi_for_walls(wl, walls), rtol=0, atol=0)
+
+
+def test_stored_thermodynamic_constants_match_the_eos():
+    """The Carnahan-Starling critical temperature and Maxwell densities the workloads store, recomputed
+    from the EOS (critical point from p' = p'' = 0; equal areas)."""
+    from oracle import thermo
+
+    rc, Tc = thermo.critical_point()
+    assert abs(W.CS_TC / Tc - 1) < 1e-13
+    for tr, (rv, rl) in W.MAXWELL.items():
+        v, l = thermo.maxwell(tr * Tc)
+        assert abs(rv / v - 1) < 1e-9 and abs(rl / l - 1) < 1e-9, (tr, rv, v, rl, l)
