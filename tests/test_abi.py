@@ -22,7 +22,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.skip("libmcb.so not built (run __graft_entry__.build())")
+        pytest.skip("libmcb.so not built (python paper_2203_04508_amd/build.py)")
     return C.CDLL(LIB)
 
 
