@@ -194,6 +194,10 @@ def main():
 
     import torch
     from paper_2203_04508_amd import workloads as W
+    from paper_2203_04508_amd import build as hipbuild, mcb as _mcb
+
+    if not os.path.exists(_mcb.LIB_PATH):
+        hipbuild.build()  # nothing built yet: compile the library (the loader itself never falls back)
 
     # the chemical-potential model runs on the same recipe with the balls kept apart (its stencils
     # reach two nodes into the solid; nearly touching balls end it in a domain error)
