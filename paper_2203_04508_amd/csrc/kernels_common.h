@@ -82,6 +82,9 @@ __device__ inline __amdgpu_buffer_rsrc_t make_res(const void* p, uint64_t bytes)
 // caller discards, whereas a store must be dropped for certain.
 template <class S>
 struct Buf;
+// cache policy of a buffer store that streams: non-temporal, so the lattice being written does not
+// push out of L2 the lines that neighbouring workgroups are about to read
+constexpr int CPOL_NT = 2;
 template <>
 struct Buf<double> {
     static __device__ inline double ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
@@ -94,6 +97,10 @@ struct Buf<double> {
     static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    }
+    static __device__ inline void st_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, CPOL_NT);
     }
 };
 template <>
@@ -108,6 +115,9 @@ struct Buf<float> {
     static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
     }
+    static __device__ inline void st_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, CPOL_NT);
+    }
 };
 template <>
 struct Buf<__half> {
@@ -120,6 +130,9 @@ struct Buf<__half> {
     static __device__ inline float round(float v) { return __half2float(__float2half_rn(v)); }
     static __device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v)), r, off, 0, 0);
+    }
+    static __device__ inline void st_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v)), r, off, 0, CPOL_NT);
     }
 };
 __device__ inline int32_t ld_i32(__amdgpu_buffer_rsrc_t r, uint32_t off) {

@@ -447,9 +447,9 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
                 if (kMixed<S> && i == 0)
-                    Buf<float>::st(M.fb, xst == OOB ? OOB : xst * 2u, coll ? out[0] : C(0));
+                    Buf<float>::st_nt(M.fb, xst == OOB ? OOB : xst * 2u, coll ? out[0] : C(0));
                 else
-                    Buf<S>::st(M.fb, sat_add(xst, uint32_t(i + (kMixed<S> ? 1 : 0)) * M.ns), coll ? out[i] : C(0));
+                    Buf<S>::st_nt(M.fb, sat_add(xst, uint32_t(i + (kMixed<S> ? 1 : 0)) * M.ns), coll ? out[i] : C(0));
             }
             // boundary record of time t+1: the forcing terms, the populations as stored, the eq. 18
             // correction
