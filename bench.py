@@ -247,7 +247,8 @@ def main():
     if os.path.exists(tfile) and args.model == "pseudo" and args.collision == "bgk":
         tj = json.load(open(tfile))
         if tj.get("kernel_digest") == kernel_digest(wl.dim):
-            traffic = tj.get("bytes_per_launch")
+            # the bytes of one whole step, like `achieved` (the 3-D step is two launches)
+            traffic = tj.get("bytes_per_step", tj.get("bytes_per_launch"))
 
     out = {
         "metric": METRIC,
