@@ -63,6 +63,21 @@ __device__ inline void stp(S* __restrict__ f, int i, int64_t N, int64_t x, C v) 
     }
     st<S, C>(f, plane_off<S>(i, N) + x, v);
 }
+// the same store, non-temporal (streaming): the lattice being written does not evict from L2 the
+// lines other workgroups read next
+template <class S, class C>
+__device__ inline void stp_nt(S* __restrict__ f, int i, int64_t N, int64_t x, C v) {
+    if constexpr (kMixed<S>) {
+        if (i == 0) {
+            __builtin_nontemporal_store(float(v), reinterpret_cast<float*>(f) + x);
+            return;
+        }
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, __float2half_rn(float(v))),
+                                    reinterpret_cast<unsigned short*>(f) + plane_off<S>(i, N) + x);
+    } else {
+        __builtin_nontemporal_store(S(v), f + plane_off<S>(i, N) + x);
+    }
+}
 
 // ---------------------------------------------------------------- bounds-checked buffer access
 // Raw buffer instructions address from a scalar 128-bit resource plus a 32-bit per-lane byte

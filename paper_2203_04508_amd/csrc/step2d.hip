@@ -772,7 +772,7 @@ __global__ __launch_bounds__(256) void k_cp_step(ArgsCP<S, C> p) {
         C rho, dux, duy, sx2, sy2, duu15;
         collide9<S, C, MRT>(a, coll, f, rs, coll ? Fx : C(0), coll ? Fy : C(0), out, rho, dux, duy, sx2, sy2, duu15);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) stp<S, C>(a.fb, i, N, x, coll ? out[i] : C(0));
+        for (int i = 0; i < 9; ++i) stp_nt<S, C>(a.fb, i, N, x, coll ? out[i] : C(0));
         if (coll && tg > 0) {
             C rv[REC2];
             rv[0] = rho;
