@@ -244,7 +244,8 @@ def main():
     # when they were taken on the kernel as it is now
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{wl.name}_{args.precision}.json")
-    if os.path.exists(tfile) and args.model == "pseudo" and args.collision == "bgk":
+    measured_cfg = args.model == "pseudo" and args.collision == "bgk" and args.bc_mode == "present" and not any(grav)
+    if os.path.exists(tfile) and measured_cfg:  # the counters were taken on this configuration only
         tj = json.load(open(tfile))
         if tj.get("kernel_digest") == kernel_digest(wl.dim):
             # the bytes of one whole step, like `achieved` (the 3-D step is two launches)
