@@ -8,6 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcb.so")
+CEILING = os.path.join(HERE, "mcb_ceiling")  # standalone copy / plain-pull bandwidth probe
 SOURCES = ["api.hip", "geometry.hip", "step2d.hip", "step3d.hip", "monitor.hip", "adjoint.hip"]
 ARCH = os.environ.get("MCB_OFFLOAD_ARCH", "gfx950")
 
@@ -37,6 +38,11 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    cmd = [hipcc, *[f for f in FLAGS if f not in ("-shared", "-fPIC")], os.path.join(CSRC, "ceiling.hip"), "-o", CEILING + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(CEILING + ".tmp", CEILING)
     return LIB
 
 
