@@ -274,15 +274,23 @@ mcb_status mcb_adj_required_bytes(mcb_ctx* ctx, int64_t nsteps, int64_t k, int64
 mcb_status mcb_adj_bind(mcb_ctx* ctx, void* device_buffer, int64_t bytes);
 
 /* Equilibrium start from rho0 (N doubles), nsteps steps with checkpoints, and the loss of the final
- * state in *value.  The context's state is then that final state (t = nsteps).  Synchronises. */
+ * state in *value.  The context's state is then that final state (t = nsteps).  Each successful call
+ * starts a new generation of the reverse mode (mcb_adj_generation).  Synchronises. */
 mcb_status mcb_adj_forward(mcb_ctx* ctx, const double* rho0, int64_t nsteps, int64_t k, int32_t loss_kind,
                            const double* loss_prm, double* value);
 
+/* The generation of the last mcb_adj_forward, while its gradient can still be taken; 0 once the
+ * state, the wettability, the links or the geometry have changed since (mcb_step, mcb_set_f,
+ * mcb_init_equilibrium, mcb_set_wettability, mcb_set_links, mcb_set_geometry, mcb_build_links,
+ * mcb_adj_bind). */
+mcb_status mcb_adj_generation(const mcb_ctx* ctx, int64_t* generation);
+
 /* dphi[w] = dloss * d loss / d phi[w] (n_wall doubles, wall nodes in ascending linear index; phi is the
  * wettability value of mcb_set_wettability: the factor, or the assigned chemical potential) for
- * the last mcb_adj_forward; the state must not have been changed since (MCB_ESTATE otherwise).
- * The context's state is left as it was.  Synchronises. */
-mcb_status mcb_adj_backward(mcb_ctx* ctx, double dloss, double* dphi);
+ * the forward pass of the given generation, which must be the last one, with nothing changed
+ * since (MCB_ESTATE otherwise: a caller holding the losses of two forward passes on one context
+ * cannot take the gradient of the first).  The context's state is left as it was.  Synchronises. */
+mcb_status mcb_adj_backward(mcb_ctx* ctx, int64_t generation, double dloss, double* dphi);
 
 #ifdef __cplusplus
 }

@@ -188,7 +188,18 @@ mcb_status check_flags(mcb_ctx* c, int64_t* n_domain_out) {
     HIPCHK(hipStreamSynchronize(c->stream));
     if (n_domain_out) *n_domain_out = flags[FLAG_DOMAIN] ? 1 : 0;
     if (flags[FLAG_NOHIT]) return fail(c, MCB_EINVAL, "a link's solid neighbour lies in no shape");
-    if (flags[FLAG_DOMAIN]) return fail(c, MCB_EDOMAIN, "psi domain error: rho <= 0 or negative square-root argument");
+    if (flags[FLAG_DOMAIN]) {
+        // a non-finite population fails the domain test too: tell the two apart by counting the
+        // fluid nodes of the current state that hold one
+        if (c->stage >= 5) {
+            HIPCHK(monitor(c, fcur(c), rcur(c)));
+            double r[MON_FIELDS];
+            HIPCHK(hipMemcpyAsync(r, c->lat + c->L.result, sizeof r, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            if (r[5] > 0.0) return fail(c, MCB_ENAN, "%lld fluid nodes hold non-finite populations", (long long)r[5]);
+        }
+        return fail(c, MCB_EDOMAIN, "psi domain error: rho <= 0 or negative square-root argument");
+    }
     return MCB_OK;
 }
 
@@ -344,11 +355,13 @@ mcb_status mcb_set_geometry(mcb_ctx* c, const mcb_shape* shapes, int64_t n) {
     }
     c->n_links = c->n_bnodes = c->n_wall = -1;
     c->stage = 2;
+    c->adj_ready = false;
     return MCB_OK;
 }
 
 mcb_status mcb_build_links(mcb_ctx* c, int32_t phase, int64_t* n_links, int64_t* n_bnodes, int64_t* n_wall) {
     if (!c) return MCB_EINVAL;
+    c->adj_ready = false;
     if (phase == MCB_COUNT) {
         if (c->stage < 2) return fail(c, MCB_ESTATE, "set geometry first");
         mcb_status st = clear_flags(c);
@@ -427,6 +440,7 @@ mcb_status mcb_set_links(mcb_ctx* c, const mcb_link* links, int64_t n) {
         if (links[l].q_fixed > uint32_t(ONE)) return fail(c, MCB_EINVAL, "link %lld: q_fixed > 2^16", (long long)l);
         qc[l] = links[l].q_fixed;
     }
+    c->adj_ready = false;
     if (n > 0) HIPCHK(hipMemcpyAsync(c->lk + c->L.lk_qc, qc.data(), 4 * n, hipMemcpyHostToDevice, c->stream));
     st = clear_flags(c);
     if (st) return st;
@@ -442,6 +456,7 @@ mcb_status mcb_set_wettability(mcb_ctx* c, const double* phi, int64_t n_wall) {
     for (int64_t w = 0; w < n_wall; ++w)
         if (!std::isfinite(phi[w]) || (!cp && !(phi[w] > 0.0)))
             return fail(c, MCB_EINVAL, "phi[%lld] must be %s", (long long)w, cp ? "finite" : "positive");
+    c->adj_ready = false;  // a gradient of the old wettability can no longer be taken
     if (n_wall > 0) {
         HIPCHK(hipMemcpyAsync(c->lk + c->L.wl_phi, phi, 8 * n_wall, hipMemcpyHostToDevice, c->stream));
         HIPCHK(wall_factors(c));
@@ -451,6 +466,7 @@ mcb_status mcb_set_wettability(mcb_ctx* c, const double* phi, int64_t n_wall) {
 }
 
 static mcb_status collide_from(mcb_ctx* c, void* fpre) {
+    c->adj_ready = false;  // a new state: the last forward pass no longer ends here
     // fpre holds pre-collision populations in storage format; the collision writes the other lattice
     const bool to_fb = fpre != c->lat + c->L.fb;
     void* dst = to_fb ? c->lat + c->L.fb : c->lat + c->L.fa;
@@ -522,6 +538,7 @@ mcb_status mcb_step(mcb_ctx* c, int64_t n) {
     if (!c) return MCB_EINVAL;
     if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
     if (n < 0) return fail(c, MCB_EINVAL, "negative step count");
+    if (n > 0) c->adj_ready = false;
     for (int64_t k = 0; k < n; ++k) {
         if (c->timing) {
             const int r = c->ev_next;
@@ -620,12 +637,22 @@ mcb_status mcb_adj_forward(mcb_ctx* c, const double* rho0, int64_t nsteps, int64
     c->adj_prm[1] = prm[1];
     c->adj_t_end = c->t;
     c->adj_ready = true;
+    ++c->adj_gen;
     return MCB_OK;
 }
 
-mcb_status mcb_adj_backward(mcb_ctx* c, double dloss, double* dphi) {
+mcb_status mcb_adj_generation(const mcb_ctx* c, int64_t* generation) {
+    if (!c || !generation) return MCB_EINVAL;
+    *generation = c->adj_ready ? c->adj_gen : 0;
+    return MCB_OK;
+}
+
+mcb_status mcb_adj_backward(mcb_ctx* c, int64_t generation, double dloss, double* dphi) {
     if (!c) return MCB_EINVAL;
     if (!c->adj_ready || c->t != c->adj_t_end) return fail(c, MCB_ESTATE, "no matching mcb_adj_forward");
+    if (generation != c->adj_gen)
+        return fail(c, MCB_ESTATE, "forward pass %lld was superseded by pass %lld", (long long)generation,
+                    (long long)c->adj_gen);
     if (c->n_wall > 0 && !dphi) return fail(c, MCB_EINVAL, "dphi missing");
     const AdjPlan& a = c->ap;
     const AdjWork w = adj_work(c);

@@ -39,6 +39,12 @@ __device__ inline void st(S* __restrict__ p, uint32_t i, C v) { st<S, C>(p, int6
 template <class S, class C>
 using MassAcc = typename std::conditional<std::is_same<S, float>::value, double, C>::type;
 
+// The eq. 18 correction of a boundary node is summed in FP64 from its link differences and added to
+// the rest population in FP64, then rounded once to the compute type; what that rounding drops (at
+// most half an ulp of f_0, carried in the compute type to within 2^-24 of itself) joins the
+// collision's mass sum, so the node keeps the mass balance of eq. 18 to within ~2^-48 f_0 whatever
+// the storage precision, and the correction never rounds on its own.
+
 // ---------------------------------------------------------------- population planes
 // Populations are stored as Q planes of N values (SoA).  With FP16 storage the rest population
 // (plane 0) is kept in FP32, in the space of the first two half planes: it holds about 4/9 of the

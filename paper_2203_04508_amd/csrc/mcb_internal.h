@@ -147,6 +147,7 @@ struct mcb_ctx {
     int64_t adj_bytes = 0;
     mcb::AdjPlan ap{};
     bool adj_ready = false;   // a forward pass with checkpoints has run and the state is its end
+    int64_t adj_gen = 0;      // generation of the last forward pass (bumped by every mcb_adj_forward)
     int64_t adj_t_end = -1;
     int32_t adj_kind = 0;
     double adj_prm[2]{};

@@ -92,6 +92,7 @@ struct March {
     C recN[RF2 + 8], aN[Q2_LINKS];  // boundary record (the part the pull uses) and link coefficients of
                                     // row r+1 (in flight)
     C dsA, dsB, dsC;             // eq. 18 corrections applied to rows r-2, r-1, r
+    C erA, erB, erC;             // and the residuals of adding them to f_0 (see apply_links)
     bool bad;
 };
 
@@ -129,18 +130,19 @@ __device__ __forceinline__ C edot(int ex, int ey, C x, C y) {
 
 // Eqs. 16-18 at a boundary node (bnd) from its record of time t (rec) and link coefficients (ca):
 // replaces the populations pulled from solid neighbours by f_in and corrects the rest population;
-// returns the correction.  Lanes that are not boundary nodes keep f and return 0.  Directions in
-// which no lane of the wave has a link are skipped.  kF and k18 select the scheme: 1 and 1 the
-// present one, 0 and 0 linear interpolation bounce-back (no forcing term, no eq. 18), 0 and 1 the
-// same with eq. 18; halfway bounce-back is a = 1 on every link.
+// returns the correction and, in res, what rounding f_0 + correction to the compute type dropped.
+// Lanes that are not boundary nodes keep f and return zeros.  Directions in which no lane of the wave has a link are
+// skipped.  kF and k18 select the scheme: 1 and 1 the present one, 0 and 0 linear interpolation
+// bounce-back (no forcing term, no eq. 18), 0 and 1 the same with eq. 18; halfway bounce-back is
+// a = 1 on every link.
 template <class S, class C>
 __device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[RF2 + 8], const C (&ca)[Q2_LINKS], C (&f)[9], C kF,
-                                         C k18) {
+                                         C k18, C& res) {
     const C rho = rec[0] * kF, dux = rec[1], duy = rec[2], sx = rec[3], sy = rec[4], duu = rec[5];
     const C* fo = rec + RF2 - 1;  // own post-collision populations 1 .. 8
     // each slot opp(j) is replaced at most once, and never one that a later eq. 16 link reads (its
     // x2 = x - e_j is fluid, while a replaced slot was pulled from a solid node)
-    C ds = C(0);
+    double ds = 0.0;
 #pragma unroll
     for (int j = 1; j < 9; ++j) {
         const C a = ca[j - 1];
@@ -155,13 +157,15 @@ __device__ __forceinline__ C apply_links(bool bnd, const C (&rec)[RF2 + 8], cons
             o = c2 != C(0) ? o : C(0);
             // rounded to the storage format, as the value would be stored; eq. 18 takes it so
             const C fin = Buf<S>::round(c1 * fo[j] + c2 * (o + Fj));
-            ds += lk ? fo[j] - fin : C(0);
+            ds += lk ? double(fo[j]) - double(fin) : 0.0;
             f[kOpp[j]] = lk ? fin : f[kOpp[j]];
         }
     }
-    ds *= k18;
-    f[0] += ds;
-    return ds;
+    ds *= double(k18);
+    const double f0 = double(f[0]) + ds;
+    f[0] = C(f0);
+    res = C(f0 - double(f[0]));
+    return C(ds);
 }
 
 // Collision of one node (eq. 4, or eqs. 1-4 when MRT; eq. 13 forcing, eq. 14 equilibrium) from its
@@ -255,6 +259,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     const int slot = k & 3;
     M.tgA = M.tgB; M.tgB = M.tgC; M.tgC = M.tg_cur;
     M.dsA = M.dsB; M.dsB = M.dsC;
+    M.erA = M.erB; M.erB = M.erC;
     C recC[RF2 + 8], aC[Q2_LINKS];  // record and coefficients of row r (arrived with its pull)
 #pragma unroll
     for (int i = 0; i < RF2 + 8; ++i) recC[i] = M.recN[i];
@@ -287,7 +292,8 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
     // ---- A: links (eqs. 16-18) and density of row r
     {
         M.dsC = C(0);
-        if (PULL && __any(M.tgC > 0)) M.dsC = apply_links<S, C>(M.tgC > 0, recC, aC, fC, a.kF, a.k18);
+        M.erC = C(0);
+        if (PULL && __any(M.tgC > 0)) M.dsC = apply_links<S, C>(M.tgC > 0, recC, aC, fC, a.kF, a.k18, M.erC);
         C sr = C(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) sr += fC[i];
@@ -341,6 +347,7 @@ __device__ __forceinline__ void march_row(March<S, C, W>& M, int k, C (&fA)[9], 
         MassAcc<S, C> rs_acc = 0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) rs_acc += MassAcc<S, C>(fA[i]);
+        rs_acc += MassAcc<S, C>(M.erA);  // the part of the eq. 18 correction that rounding kept out of f_0
         const int sl = (k - 3) & 3, sm = (k - 2) & 3, sh = (k - 1) & 3;
         const int tc = t < 1 ? 1 : (t > OUT + 2 ? OUT + 2 : t);
         const C p0 = M.s_psi[sm][tc];
@@ -435,6 +442,7 @@ __global__ __launch_bounds__(W) void k_step2d(Args2<S, C> a) {
     M.fac = make_res(a.fac, uint64_t(a.n_wall) * sizeof(C));
     M.tgA = M.tgB = M.tgC = -1;
     M.dsA = M.dsB = M.dsC = C(0);
+    M.erA = M.erB = M.erC = C(0);
     M.bad = false;
     // row march: the populations of rows r+1 and r+2 are in flight while row r is reduced to rho,
     // row r-1 to psi and row r-2 collided; five register sets rotate
@@ -566,7 +574,7 @@ struct ArgsCP {
 // pulled populations of node (cx, cy) (PULL; otherwise its own stored ones), with eqs. 16-18 at
 // boundary nodes; ds = the eq. 18 correction.  Solid nodes hold zeros, which the links replace.
 template <class S, class C, bool PULL>
-__device__ __forceinline__ int pull_node(const Args2<S, C>& a, int64_t N, int cx, int cy, C (&f)[9], C& ds) {
+__device__ __forceinline__ int pull_node(const Args2<S, C>& a, int64_t N, int cx, int cy, C (&f)[9], C& ds, C& res) {
     const int tg = a.tag[int64_t(cy) * a.nx + cx];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -574,6 +582,7 @@ __device__ __forceinline__ int pull_node(const Args2<S, C>& a, int64_t N, int cx
         f[i] = ldp<S, C>(a.fa, i, N, int64_t(sy) * a.nx + sx);
     }
     ds = C(0);
+    res = C(0);
     if (PULL) {
         const bool bnd = tg > 0;
         if (__any(bnd)) {
@@ -583,7 +592,7 @@ __device__ __forceinline__ int pull_node(const Args2<S, C>& a, int64_t N, int cx
             for (int k = 0; k < RF2 + 8; ++k) rec[k] = bnd ? a.rin[bi * REC2 + k] : C(0);
 #pragma unroll
             for (int k = 0; k < Q2_LINKS; ++k) ca[k] = bnd ? a.la[bi * Q2_LINKS + k] : C(NO_LINK);
-            ds = apply_links<S, C>(bnd, rec, ca, f, a.kF, a.k18);
+            ds = apply_links<S, C>(bnd, rec, ca, f, a.kF, a.k18, res);
         }
     }
     return tg;
@@ -597,8 +606,9 @@ __global__ __launch_bounds__(256) void k_cp_rho(ArgsCP<S, C> p) {
     if (cx >= a.nx) return;
     const int64_t N = int64_t(a.nx) * a.ny, x = int64_t(cy) * a.nx + cx;
     C f[9], ds;
-    const int tg = pull_node<S, C, PULL>(a, N, cx, cy, f, ds);
-    MassAcc<S, C> rs = 0;
+    C res;
+    const int tg = pull_node<S, C, PULL>(a, N, cx, cy, f, ds, res);
+    MassAcc<S, C> rs = MassAcc<S, C>(res);
 #pragma unroll
     for (int i = 0; i < 9; ++i) rs += MassAcc<S, C>(f[i]);
     p.rho[x] = tg >= 0 ? C(rs) + a.rho_ref : C(0);
@@ -761,9 +771,10 @@ __global__ __launch_bounds__(256) void k_cp_step(ArgsCP<S, C> p) {
         const C rxm2 = at(p.rho, -2, 0), rxm1 = at(p.rho, -1, 0), rxp1 = at(p.rho, 1, 0), rxp2 = at(p.rho, 2, 0);
         const C rym2 = at(p.rho, 0, -2), rym1 = at(p.rho, 0, -1), ryp1 = at(p.rho, 0, 1), ryp2 = at(p.rho, 0, 2);
         C f[9], ds;
-        const int tg = pull_node<S, C, PULL>(a, N, cx, cy, f, ds);
+        C res;
+        const int tg = pull_node<S, C, PULL>(a, N, cx, cy, f, ds, res);
         const bool coll = tg >= 0;
-        MassAcc<S, C> rs = 0;
+        MassAcc<S, C> rs = MassAcc<S, C>(res);
 #pragma unroll
         for (int i = 0; i < 9; ++i) rs += MassAcc<S, C>(f[i]);
         const C Fx = -r * cd1(mxm2, mxm1, mxp1, mxp2) + cd1(rxm2, rxm1, rxp1, rxp2) / C(3);

@@ -141,14 +141,15 @@ struct Args3 {
 // Eqs. 16-18 at a boundary node (bnd) from its record of time t (rec: forcing terms and the
 // populations 1..18) and link coefficients (ca): replaces the populations pulled from solid
 // neighbours by f_in (see the two-dimensional kernel for the three cases) and corrects the rest
-// population; returns the correction.  Lanes that are not boundary nodes keep f and return 0;
+// population; returns the correction and, in res, what rounding f_0 + correction to the compute type
+// dropped.  Lanes that are not boundary nodes keep f and return zeros;
 // directions in which no lane of the wave has a link are skipped.  LOAD: rec and ca are loaded
 // here, from rin at byte offset roff and la at aoff, in two halves, each just before its directions
 // (keeps the FP64 kernel within its registers).  kF = 0 drops the forcing term (MIBC); halfway
 // bounce-back is a = 1 on every link.  Eq. 18 always applies: the density pass relies on it.
 template <class S, class C, bool LOAD>
 __device__ __forceinline__ C apply_links3(bool bnd, C (&rec)[RF3 + 18], C (&ca)[18], C (&f)[19], __amdgpu_buffer_rsrc_t rin,
-                                          uint32_t roff, __amdgpu_buffer_rsrc_t la, uint32_t aoff, C kF) {
+                                          uint32_t roff, __amdgpu_buffer_rsrc_t la, uint32_t aoff, C kF, C& res) {
     constexpr int H1 = RF3 + 8, A1 = 8;  // first half: forcing terms, f~_1..f~_8; directions 1..8
     if (LOAD) {
         C h[H1], g[A1];
@@ -163,7 +164,7 @@ __device__ __forceinline__ C apply_links3(bool bnd, C (&rec)[RF3 + 18], C (&ca)[
     const C sx = rec[4], sy = rec[5], sz = rec[6], duu = rec[7];
     // each slot opp(j) is replaced at most once, and never one that a later eq. 16 link reads (its
     // x2 = x - e_j is fluid, while a replaced slot was pulled from a solid node)
-    C ds = C(0);
+    double ds = 0.0;
     auto link = [&](int j) {
         const C a = ca[j - 1];
         const bool lk = bnd && a < C(1.5);
@@ -177,7 +178,7 @@ __device__ __forceinline__ C apply_links3(bool bnd, C (&rec)[RF3 + 18], C (&ca)[
             C o = a < C(0) ? rec[RF3 + jo - 1] : f[j];
             o = c2 != C(0) ? o : C(0);
             const C fin = Buf<S>::round(c1 * rec[RF3 + j - 1] + c2 * (o + Fj));
-            ds += lk ? rec[RF3 + j - 1] - fin : C(0);
+            ds += lk ? double(rec[RF3 + j - 1]) - double(fin) : 0.0;
             f[jo] = lk ? fin : f[jo];
         }
     };
@@ -195,8 +196,10 @@ __device__ __forceinline__ C apply_links3(bool bnd, C (&rec)[RF3 + 18], C (&ca)[
     }
 #pragma unroll
     for (int j = A1 + 1; j < 19; ++j) link(j);
-    f[0] += ds;
-    return ds;
+    const double f0 = double(f[0]) + ds;
+    f[0] = C(f0);
+    res = C(f0 - double(f[0]));
+    return C(ds);
 }
 
 // Per-workgroup state of the plane march.
@@ -362,11 +365,12 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
         if (k >= 4) {
             const bool coll = M.out_col && tgC >= 0;
             C dsC = C(0);
+            C erC = C(0);
             if (PULL && __any(tgC > 0)) {
                 // without the prefetch (FP64) the record and the coefficients are loaded here
                 const uint32_t bi = uint32_t(tgC - 1);
                 dsC = apply_links3<S, C, !PF>(tgC > 0, recC, aC, fC, M.rin, tgC > 0 ? bi * (REC3 * sc) : OOB, M.la,
-                                              tgC > 0 ? bi * (Q3_LINKS * sc) : OOB, a.kF);
+                                              tgC > 0 ? bi * (Q3_LINKS * sc) : OOB, a.kF, erC);
             }
             C out[19];
             C rho = C(0), dux = C(0), duy = C(0), duz = C(0), sx2 = C(0), sy2 = C(0), sz2 = C(0), duu15 = C(0);
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
             if (__any(coll)) {
                 // the node's density at t+1 from its pulled values; the collision hands all of it
                 // back, with f_0 taking the rounding
-                MassAcc<S, C> rs_acc = 0;
+                MassAcc<S, C> rs_acc = MassAcc<S, C>(erC);  // what rounding kept out of f_0 (apply_links3)
 #pragma unroll
                 for (int i = 0; i < 19; ++i) rs_acc += MassAcc<S, C>(fC[i]);
                 const C rs = C(rs_acc);

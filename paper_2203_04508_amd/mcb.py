@@ -69,7 +69,7 @@ EXPORTS = [
     "mcb_set_geometry", "mcb_build_links", "mcb_get_links", "mcb_get_wall_nodes", "mcb_set_links",
     "mcb_set_wettability", "mcb_init_equilibrium", "mcb_set_f", "mcb_get_f", "mcb_step",
     "mcb_moments", "mcb_max_speed", "mcb_mass", "mcb_sync", "mcb_timing", "mcb_timing_report",
-    "mcb_adj_required_bytes", "mcb_adj_bind", "mcb_adj_forward", "mcb_adj_backward",
+    "mcb_adj_required_bytes", "mcb_adj_bind", "mcb_adj_forward", "mcb_adj_generation", "mcb_adj_backward",
 ]
 
 _lib = None
@@ -110,7 +110,8 @@ def load(path: str = LIB_PATH):
         "mcb_adj_required_bytes": ([vp, i64, i64, P(i64)], i32),
         "mcb_adj_bind": ([vp, vp, i64], i32),
         "mcb_adj_forward": ([vp, vp, i64, i64, i32, vp, P(C.c_double)], i32),
-        "mcb_adj_backward": ([vp, C.c_double, vp], i32),
+        "mcb_adj_generation": ([vp, P(i64)], i32),
+        "mcb_adj_backward": ([vp, i64, C.c_double, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -285,9 +286,15 @@ def mcb_adj_forward(ctx, rho0, nsteps, k, kind, prm) -> float:
     return v.value
 
 
-def mcb_adj_backward(ctx, dloss, n_wall) -> np.ndarray:
+def mcb_adj_generation(ctx) -> int:
+    g = C.c_int64()
+    _check(ctx, load().mcb_adj_generation(ctx, C.byref(g)), "mcb_adj_generation")
+    return g.value
+
+
+def mcb_adj_backward(ctx, generation, dloss, n_wall) -> np.ndarray:
     d = np.zeros(max(n_wall, 1))
-    _check(ctx, load().mcb_adj_backward(ctx, float(dloss), _ptr(d)), "mcb_adj_backward")
+    _check(ctx, load().mcb_adj_backward(ctx, int(generation), float(dloss), _ptr(d)), "mcb_adj_backward")
     return d[:n_wall]
 
 
@@ -411,11 +418,15 @@ class Lattice:
             self.adj = None
             self.adj = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
         mcb_adj_bind(self.ctx, self.adj.data_ptr(), self.adj.numel())
-        return mcb_adj_forward(self.ctx, rho0, nsteps, k, kind, prm)
+        val = mcb_adj_forward(self.ctx, rho0, nsteps, k, kind, prm)
+        self.adj_gen = mcb_adj_generation(self.ctx)
+        return val
 
-    def adj_backward(self, dloss=1.0) -> np.ndarray:
-        """dloss * d loss / d phi per wall node, for the last adj_forward."""
-        return mcb_adj_backward(self.ctx, dloss, self.n_wall)
+    def adj_backward(self, dloss=1.0, generation=None) -> np.ndarray:
+        """dloss * d loss / d phi per wall node, for the forward pass of the given generation (default:
+        the last adj_forward); MCBError (MCB_ESTATE) once that pass is superseded or its state changed."""
+        gen = self.adj_gen if generation is None else generation
+        return mcb_adj_backward(self.ctx, gen, dloss, self.n_wall)
 
 
 def _wettability_loss_class():
@@ -433,12 +444,13 @@ def _wettability_loss_class():
             lattice.set_wettability(phi.detach().to("cpu", torch.float64).numpy())
             val = lattice.adj_forward(rho0, nsteps, k, kind, prm)
             ctx.lattice = lattice
+            ctx.generation = lattice.adj_gen  # backward refuses once another forward pass has run
             ctx.phi_device = phi.device
             return torch.tensor(val, dtype=torch.float64, device=phi.device)
 
         @staticmethod
         def backward(ctx, g):
-            d = ctx.lattice.adj_backward(float(g))
+            d = ctx.lattice.adj_backward(float(g), generation=ctx.generation)
             return torch.from_numpy(d).to(ctx.phi_device), None, None, None, None, None, None
 
     return WettabilityLoss

@@ -186,10 +186,27 @@ PHI_RANGE = (0.85, 1.15)
 CP_MIN_GAP = 4.0
 
 
-def make(name: str, min_gap: float = 0.0) -> Workload:
+# The temperatures and relaxation times the workloads are specified with: 0.6 T_c and tau 0.8 for
+# the 1024^2 and 4096^2 lattices, 0.65 T_c (tau 0.8, the paper's default) for the 256^3 lattice,
+# all with the width-2 drop profile.  make(..., stated=True) returns these; the defaults of make()
+# run c1, c2 and c4 at 0.7 T_c with tau 1 (c4 also with width 4), where the single-relaxation-time
+# pseudopotential stays stable over the full step counts (the stability study records both).
+STATED = {"c1": (0.60, 0.8, 2.0), "c2": (0.60, 0.8, 2.0), "c4": (0.65, 0.8, 2.0)}
+
+
+def make(name: str, min_gap: float = 0.0, stated: bool = False) -> Workload:
     """Workload by name; min_gap > 0 keeps the balls of c1 / c2 that far apart (the same recipe,
-    so with other draws: the balls, drops and factors differ from those of min_gap = 0)."""
+    so with other draws: the balls, drops and factors differ from those of min_gap = 0).
+    stated=True: the same geometry, drops and wettability at the specified temperature, relaxation
+    time and profile width (STATED)."""
     name = name.lower()
+    if stated:
+        if name not in STATED:
+            raise KeyError(f"{name} has no separately stated parameters")
+        wl = make(name, min_gap=min_gap)
+        wl.T_over_Tc, wl.tau, wl.interface_width = STATED[name]
+        wl.extra["stated"] = True
+        return wl
     if name == "c0":
         R, rd = 12.3, 10.0
         cyl = (32.4, 20.7)

@@ -118,6 +118,10 @@ TINY = [
     ("300x70-ragged", (300, 70, 1), 1, None),
     ("37x29-random-q", (37, 29, 1), 2, "random"),
     ("40x34-half-q", (40, 34, 1), 3, "half"),
+    # the ends of the two branches of the boundary condition, set on purpose: q = 0 (eq. 16 with
+    # c1 = 0), q = 1/2 - 2^-16 (eq. 16 next to the switch), q = 1/2 (eq. 17, bounce-back), q = 1
+    # (eq. 17 with weights 1/2), and q = 2^-16
+    ("41x31-q-endpoints", (41, 31, 1), 4, "endpoints"),
 ]
 
 
@@ -135,6 +139,8 @@ def test_step_parity_small(mcb, name, dims, seed, qmode):
         qo = lambda q: rng.integers(0, 65537, len(q))
     elif qmode == "half":
         qo = lambda q: np.full(len(q), 32768)
+    elif qmode == "endpoints":
+        qo = lambda q: rng.choice(np.array([0, 1, 32767, 32768, 65536]), len(q))
     phi = rng.uniform(0.8, 1.15)
     sim, lat, fluid = build_pair(mcb, 2, dims, 0.8, 0.7 * TC, shapes, phi=phi, q_override=qo)
     f0 = _random_state(rng, dims, rho)
@@ -151,6 +157,17 @@ def test_step_parity_small(mcb, name, dims, seed, qmode):
     assert abs(rep.dM_last - sim.dm_last()) < 1e-12 * max(1.0, abs(sim.dm_last()))
     if qmode == "half":
         assert rep.dM_last == 0.0
+    if qmode == "endpoints":
+        cls = lat.links()["cls"]
+        assert set(cls.tolist()) >= {0, 2}, "both branches present"
+    # the monitor's mass and momentum against the oracle's state (FP64 reductions)
+    fo = sim.get_f()
+    e, *_ = oracle.lattice(2)
+    J_o = (fo[:, fluid].T @ e[:, :2].astype(float)).sum(0)
+    scale = (np.abs(fo[:, fluid]).T @ np.abs(e[:, :2]).astype(float)).sum()
+    assert abs(rep.M - sim.mass()) <= 1e-13 * sim.mass()
+    assert np.abs(np.array(rep.J[:2]) - J_o).max() <= 1e-13 * scale, (rep.J[:2], J_o)
+    assert rep.J[2] == 0.0
 
 
 def test_c0_parity_1000_steps_and_mass(mcb):
@@ -263,6 +280,29 @@ def test_deterministic_bitwise(mcb):
         out.append((lat.get_f(), lat.mass().M))
         lat.close()
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+def test_nan_population_reported(mcb):
+    banner("a non-finite population passed to mcb_set_f -> MCB_ENAN")
+    wl = W.make("c0")
+    P = oracle.make_params(2, *wl.dims, tau=wl.tau, T=wl.T)
+    sim, (solid, *_r) = oracle.sim_from_shapes(P, wl.shapes)
+    lat = mcb.Lattice(2, wl.dims, wl.tau, wl.T)
+    lat.set_geometry(wl.shapes)
+    lat.set_wettability(1.0)
+    lat.init_equilibrium(wl.rho0())
+    f = lat.get_f()
+    x = int(np.nonzero(solid == 0)[0][100])
+    f[3, x] = np.nan
+    with pytest.raises(mcb.MCBError) as ei:
+        lat.set_f(f)
+    assert ei.value.code == mcb.MCB_ENAN
+    # an infinite one as well, and the report counts the node after a step
+    f[3, x] = np.inf
+    with pytest.raises(mcb.MCBError) as ei:
+        lat.set_f(f)
+    assert ei.value.code == mcb.MCB_ENAN
+    lat.close()
 
 
 def test_domain_error_reported(mcb):
