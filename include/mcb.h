@@ -235,6 +235,19 @@ mcb_status mcb_max_speed(mcb_ctx* ctx, double* vmax, int64_t* node);
 /* FP64 mass / momentum / Delta M report (deterministic two-pass reduction). */
 mcb_status mcb_mass(mcb_ctx* ctx, mcb_mass_report* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the report of mcb_mass, computed by the same kernels in
+ * the same order (bit-identical results), with the reduction's partial sums and result slots kept
+ * in a static device array of the library instead of the context's lattice arena.  Allocates
+ * nothing.  The array holds 65,600 bytes (1024 x 8 partial sums and 8 result slots, a fixed grid
+ * whatever the lattice size; MCB_ESIZE if the reduction ever needed more) on each device the
+ * library runs on, until the process ends.  Every call on one device shares that device's array:
+ * calls that overlap on one device (several host threads, or several streams) race and must be
+ * serialised by the caller; each call writes every entry it reads, so nothing needs clearing.  The
+ * current device must be the one the context's buffers were bound on (MCB_ESTATE otherwise).
+ * Synchronises. */
+mcb_status mcb_mass_static(mcb_ctx* ctx, mcb_mass_report* out);
+
 /* Waits for the stream and reports device-detected faults. */
 mcb_status mcb_sync(mcb_ctx* ctx);
 

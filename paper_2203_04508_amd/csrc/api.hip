@@ -3,6 +3,7 @@
 // step3d.hip and monitor.hip.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -115,6 +116,31 @@ AdjPlan adj_plan(const mcb_ctx* c, int64_t nsteps, int64_t k) {
 using namespace mcb;
 
 namespace {
+
+// Device scratch of mcb_mass_static, for callers that cannot allocate: the monitor's per-workgroup
+// FP64 partial sums followed by its result slots (65,600 bytes on each device the library runs on,
+// held until the process ends).  Host code never passes the array's name to a kernel: each device's
+// copy lives at its own address, which mcb_bind_buffers looks up once per device with that device
+// current (hipGetSymbolAddress) and keeps in scratch_addr.
+constexpr int64_t SCRATCH_DOUBLES = int64_t(MON_BLOCKS) * MON_FIELDS + MON_FIELDS;
+__device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_addr[MAX_DEVICES] = {};
+
+// the address of the current device's scratch (dev = the current device), looked up on first use
+hipError_t scratch_of(int dev, double** out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_addr[dev] = static_cast<double*>(p);
+    }
+    *out = scratch_addr[dev];
+    return hipSuccess;
+}
 
 mcb_status fail(mcb_ctx* c, mcb_status code, const char* fmt, ...) {
     if (c) {
@@ -311,6 +337,10 @@ mcb_status mcb_bind_buffers(mcb_ctx* c, const mcb_buffers* b, void* stream) {
         int dev = 0;
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        c->device = dev;
+        // the static scratch of mcb_mass_static; a failed lookup only disables that entry point
+        c->scratch = nullptr;
+        c->scratch_err = scratch_of(dev, &c->scratch);
     }
     if (c->stage < 1) c->stage = 1;
     // lattice offsets do not depend on the counts; refresh the link offsets if counts are known
@@ -762,6 +792,43 @@ mcb_status mcb_mass(mcb_ctx* c, mcb_mass_report* out) {
     out->n_domain = nd;
     if (st) return st;
     if (out->n_nan > 0) return fail(c, MCB_ENAN, "%lld fluid nodes hold non-finite populations", (long long)out->n_nan);
+    return MCB_OK;
+}
+
+mcb_status mcb_mass_static(mcb_ctx* c, mcb_mass_report* out) {
+    if (!c) return MCB_EINVAL;
+    if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
+    if (!out) return fail(c, MCB_EINVAL, "report missing");
+    if (!c->scratch)
+        return c->device < 0 ? fail(c, MCB_ESTATE, "no device scratch: bind buffers first")
+                             : fail(c, MCB_EHIP, "device scratch not found: %s", hipGetErrorString(c->scratch_err));
+    const int64_t need = int64_t(MON_BLOCKS) * MON_FIELDS + MON_FIELDS;  // the monitor's fixed grid
+    if (need > SCRATCH_DOUBLES)
+        return fail(c, MCB_ESIZE, "the reduction needs %lld doubles of scratch, the static array holds %lld", (long long)need,
+                    (long long)SCRATCH_DOUBLES);
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != c->device) return fail(c, MCB_ESTATE, "device %d is current, the context's buffers are on device %d", cur, c->device);
+    // every entry of the partials and the result is written before it is read: nothing to clear
+    double* part = c->scratch;
+    double* res = c->scratch + int64_t(MON_BLOCKS) * MON_FIELDS;
+    HIPCHK(monitor(c, fcur(c), rcur(c), part, res));
+    double r[MON_FIELDS];
+    HIPCHK(hipMemcpyAsync(r, res, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    int32_t flags[FLAG_COUNT];
+    HIPCHK(hipMemcpyAsync(flags, c->lat + c->L.flags, sizeof flags, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::memset(out, 0, sizeof *out);
+    out->M = r[0];
+    out->J[0] = r[1];
+    out->J[1] = r[2];
+    out->J[2] = r[3];
+    out->dM_last = c->t > 0 ? r[4] : 0.0;
+    out->n_nan = int64_t(r[5]);
+    out->n_domain = flags[FLAG_DOMAIN] ? 1 : 0;
+    out->t = c->t;
+    if (out->n_nan > 0) return fail(c, MCB_ENAN, "%lld fluid nodes hold non-finite populations", (long long)out->n_nan);
+    if (flags[FLAG_DOMAIN]) return fail(c, MCB_EDOMAIN, "psi domain error: rho <= 0 or negative square-root argument");
     return MCB_OK;
 }
 

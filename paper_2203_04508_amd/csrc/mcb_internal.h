@@ -116,6 +116,9 @@ struct mcb_ctx {
     mcb_params p{};
     mcb::GridDev g{};
     hipStream_t stream = nullptr;
+    int device = -1;      // the device current when the buffers were bound
+    double* scratch = nullptr;  // that device's static scratch (mcb_mass_static), found at bind time
+    hipError_t scratch_err = hipSuccess;
     int n_cu = 0;         // compute units of the device (sizes the step grids to whole rounds)
     char* lat = nullptr;
     int64_t lat_bytes = 0;
@@ -176,7 +179,9 @@ hipError_t adj_step(mcb_ctx* c, const AdjWork& w, const void* gt, const void* re
 hipError_t adj_loss(mcb_ctx* c, const AdjWork& w, const void* g, int kind, const double* prm, double dloss, double* lam);
 
 // monitor.hip
-hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur);
+// partials (MON_BLOCKS x MON_FIELDS doubles) and result (MON_FIELDS doubles): null = the context's
+// lattice arena
+hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur, double* partials = nullptr, double* result = nullptr);
 hipError_t moments_out(mcb_ctx* c, const void* fcur, double* rho, double* v);
 hipError_t max_speed(mcb_ctx* c, const void* fcur);  // result slots MON_SPEED, MON_SPEED + 1
 hipError_t convert_plane_in(mcb_ctx* c, const double* src, void* dst_plane, int dir);

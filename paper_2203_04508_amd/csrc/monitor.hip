@@ -255,9 +255,8 @@ hipError_t init_feq_t(mcb_ctx* c, const double* rho, const double* u, void* fout
 }
 
 template <class S, class C>
-hipError_t monitor_t(mcb_ctx* c, const void* fcur, const void* rcur) {
+hipError_t monitor_t(mcb_ctx* c, const void* fcur, const void* rcur, double* partials, double* result) {
     const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
-    double* partials = reinterpret_cast<double*>(c->lat + c->L.partials);
     const int32_t* tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
     const int64_t nb = c->n_bnodes > 0 ? c->n_bnodes : 0;
     if (c->g.dim == 2)
@@ -266,8 +265,7 @@ hipError_t monitor_t(mcb_ctx* c, const void* fcur, const void* rcur) {
     else
         hipLaunchKernelGGL((k_mon_partial<S, C, 19>), dim3(MON_BLOCKS), dim3(256), 0, c->stream, c->g,
                            static_cast<const S*>(fcur), tag, rr, static_cast<const C*>(rcur), int(c->L.rec_stride), nb, partials);
-    hipLaunchKernelGGL(k_mon_final, dim3(1), dim3(256), 0, c->stream, partials, MON_BLOCKS,
-                       reinterpret_cast<double*>(c->lat + c->L.result));
+    hipLaunchKernelGGL(k_mon_final, dim3(1), dim3(256), 0, c->stream, partials, MON_BLOCKS, result);
     return hipGetLastError();
 }
 
@@ -388,11 +386,13 @@ hipError_t init_feq(mcb_ctx* c, const double* rho, const double* u, void* fout) 
     }
 }
 
-hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur) {
+hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur, double* partials, double* result) {
+    if (!partials) partials = reinterpret_cast<double*>(c->lat + c->L.partials);
+    if (!result) result = reinterpret_cast<double*>(c->lat + c->L.result);
     switch (c->p.precision) {
-        case MCB_F64: return monitor_t<double, double>(c, fcur, rcur);
-        case MCB_F32S: return monitor_t<float, float>(c, fcur, rcur);
-        default: return monitor_t<__half, float>(c, fcur, rcur);
+        case MCB_F64: return monitor_t<double, double>(c, fcur, rcur, partials, result);
+        case MCB_F32S: return monitor_t<float, float>(c, fcur, rcur, partials, result);
+        default: return monitor_t<__half, float>(c, fcur, rcur, partials, result);
     }
 }
 

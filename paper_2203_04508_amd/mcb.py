@@ -68,7 +68,7 @@ EXPORTS = [
     "mcb_create", "mcb_destroy", "mcb_last_error", "mcb_required_sizes", "mcb_bind_buffers",
     "mcb_set_geometry", "mcb_build_links", "mcb_get_links", "mcb_get_wall_nodes", "mcb_set_links",
     "mcb_set_wettability", "mcb_init_equilibrium", "mcb_set_f", "mcb_get_f", "mcb_step",
-    "mcb_moments", "mcb_max_speed", "mcb_mass", "mcb_sync", "mcb_timing", "mcb_timing_report",
+    "mcb_moments", "mcb_max_speed", "mcb_mass", "mcb_mass_static", "mcb_sync", "mcb_timing", "mcb_timing_report",
     "mcb_adj_required_bytes", "mcb_adj_bind", "mcb_adj_forward", "mcb_adj_generation", "mcb_adj_backward",
 ]
 
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
         "mcb_moments": ([vp, vp, vp], i32),
         "mcb_max_speed": ([vp, vp, vp], i32),
         "mcb_mass": ([vp, P(mcb_mass_report)], i32),
+        "mcb_mass_static": ([vp, P(mcb_mass_report)], i32),
         "mcb_sync": ([vp], i32),
         "mcb_timing": ([vp, i32], i32),
         "mcb_timing_report": ([vp, P(C.c_double), P(i64)], i32),
@@ -239,6 +240,12 @@ def mcb_max_speed(ctx):
 def mcb_mass(ctx) -> mcb_mass_report:
     r = mcb_mass_report()
     _check(ctx, load().mcb_mass(ctx, C.byref(r)), "mcb_mass")
+    return r
+
+
+def mcb_mass_static(ctx) -> mcb_mass_report:
+    r = mcb_mass_report()
+    _check(ctx, load().mcb_mass_static(ctx, C.byref(r)), "mcb_mass_static")
     return r
 
 
@@ -397,6 +404,9 @@ class Lattice:
 
     def mass(self):
         return mcb_mass(self.ctx)
+
+    def mass_static(self):
+        return mcb_mass_static(self.ctx)
 
     def max_speed(self):
         return mcb_max_speed(self.ctx)
