@@ -127,7 +127,8 @@ struct mcb_ctx {
     int64_t n_shapes = 0, n_links = -1, n_bnodes = -1, n_wall = -1;
     int64_t n_l2 = 0;  // chemical-potential model: nodes of the second solid layer
     int64_t cap_shapes = 0;
-    int occ[6] = {0, 0, 0, 0, 0, 0};  // resident workgroups per CU of the step kernel variants (0: not yet queried)
+    int occ[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // resident workgroups per CU of the step kernel variants and of
+                                            // the largest-speed pass (0: not yet queried)
     int stage = 0;        // 0 created, 1 bound, 2 geometry set, 3 counted, 4 links filled, 5 state set
     bool swapped = false; // current post-collision state lives in fb instead of fa
     int64_t t = 0;

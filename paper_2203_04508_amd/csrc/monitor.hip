@@ -111,6 +111,63 @@ __global__ __launch_bounds__(256) void k_mon_final(const double* __restrict__ pa
     }
 }
 
+// ---- per-node moment arithmetic, shared by the moment output and the one-pass largest speed, so
+// that the two give bit-identical velocities
+// density of a fluid node from its populations (stored format, shifted by w_i rho_ref)
+template <int Q>
+__device__ __forceinline__ double node_rho(const double (&v)[Q], double rho_ref) {
+    double s = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s += v[i];
+    return s + rho_ref;
+}
+
+// eq. 15: the density of a wall node, phi times the weighted mean density of its fluid neighbours
+// (neighbour i: tag ty[i], density ry[i])
+template <int Q>
+__device__ __forceinline__ double wall_rho(const int (&ty)[Q], const double (&ry)[Q], double phi) {
+    constexpr int L = Q == 9 ? 0 : 1;
+    double num = 0, den = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        num += ty[i] >= 0 ? wgt<double>(L, i) * ry[i] : 0.0;
+        den += ty[i] >= 0 ? wgt<double>(L, i) : 0.0;
+    }
+    return phi * (num / den);
+}
+
+// momentum j = sum_i f_i e_i of a node
+template <int Q>
+__device__ __forceinline__ void node_j(const double (&fv)[Q], double (&j)[3]) {
+    constexpr int L = Q == 9 ? 0 : 1;
+    j[0] = j[1] = j[2] = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int e[3] = {c_ex[L][i], c_ey[L][i], c_ez[L][i]};
+        for (int k = 0; k < 3; ++k) j[k] += fv[i] * e[k];
+    }
+}
+
+// v = (j - F / 2) / rho, F = -G psi(x) sum_i w^_i psi(x + e_i) e_i + rho g (pv[i] = psi(x + e_i))
+template <int Q>
+__device__ __forceinline__ void node_v(const double (&j)[3], const double (&pv)[Q], double psi_x, double rho_x, double G,
+                                       const double (&gk)[3], int dim, double (&v)[3]) {
+    constexpr int L = Q == 9 ? 0 : 1;
+    double s[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const double ws = (L == 0) ? (i < 5 ? 1.0 / 3.0 : 1.0 / 12.0) : (i < 7 ? 1.0 / 6.0 : 1.0 / 12.0);
+        const int e[3] = {c_ex[L][i], c_ey[L][i], c_ez[L][i]};
+        for (int k = 0; k < 3; ++k) s[k] += ws * pv[i] * e[k];
+    }
+    v[0] = v[1] = v[2] = 0.0;
+    const double ir = 1.0 / rho_x;
+    for (int k = 0; k < dim; ++k) {
+        const double F = -G * psi_x * s[k] + rho_x * gk[k];
+        v[k] = (j[k] - 0.5 * F) * ir;
+    }
+}
+
 // ---- moments: rho, psi (fluid and wall nodes), then v = (j - F / 2) / rho.  Q is a template
 // parameter (unrolled direction loops); each lane loads all it needs before using any.
 template <class S, class C, int Q>
@@ -121,10 +178,7 @@ __global__ __launch_bounds__(256) void k_rho_out(GridDev g, const S* __restrict_
         double v[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) v[i] = double(ldp<S, C>(f, i, g.N, x));
-        double s = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) s += v[i];
-        rho[x] = fl ? s + rho_ref : 0.0;
+        rho[x] = fl ? node_rho<Q>(v, rho_ref) : 0.0;
     }
 }
 
@@ -146,13 +200,7 @@ __global__ __launch_bounds__(256) void k_psi_out(GridDev g, const int32_t* __res
             ty[i] = tag[y];
             ry[i] = rho[y];
         }
-        double num = 0, den = 0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            num += ty[i] >= 0 ? wgt<double>(L, i) * ry[i] : 0.0;
-            den += ty[i] >= 0 ? wgt<double>(L, i) : 0.0;
-        }
-        psi[x] = psi_of(phi[-tg - 2] * (num / den), eos, flags);
+        psi[x] = psi_of(wall_rho<Q>(ty, ry, phi[-tg - 2]), eos, flags);
     }
 }
 
@@ -167,26 +215,17 @@ __global__ __launch_bounds__(256) void k_vel_out(GridDev g, const S* __restrict_
             continue;
         }
         double fv[Q], pv[Q];
+        fv[0] = pv[0] = 0.0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             fv[i] = double(ldp<S, C>(f, i, g.N, x));
             pv[i] = psi[nb_index(g, L, x, i, +1)];
         }
-        double j[3] = {0, 0, 0}, s[3] = {0, 0, 0};
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const double ws = (L == 0) ? (i < 5 ? 1.0 / 3.0 : 1.0 / 12.0) : (i < 7 ? 1.0 / 6.0 : 1.0 / 12.0);
-            const int e[3] = {c_ex[L][i], c_ey[L][i], c_ez[L][i]};
-            for (int k = 0; k < 3; ++k) {
-                j[k] += fv[i] * e[k];
-                s[k] += ws * pv[i] * e[k];
-            }
-        }
+        double j[3], vv[3];
+        node_j<Q>(fv, j);
         const double gk[3] = {gx, gy, gz};
-        for (int k = 0; k < g.dim; ++k) {
-            const double F = -G * psi[x] * s[k] + rho[x] * gk[k];
-            v[k * g.N + x] = (j[k] - 0.5 * F) / rho[x];
-        }
+        node_v<Q>(j, pv, psi[x], rho[x], G, gk, g.dim, vv);
+        for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = vv[k];
     }
 }
 
@@ -318,6 +357,136 @@ __global__ __launch_bounds__(256) void k_speed_final(const double* __restrict__ 
     }
 }
 
+// ---- the largest speed of a two-dimensional state in one pass.  A workgroup of SW lanes marches
+// a strip of SC = NC SW columns (each lane NC columns, SW apart; two halo columns on each side, so
+// SC - 4 output columns) along a segment of rows.  Iteration k loads row r = y0 - 2 + k
+// (populations and tags; issued one iteration earlier), puts its density and tags in a 3-row LDS
+// ring, computes psi of row r - 1 (eq. 15 at wall nodes, from the ring) into a second ring, and
+// the velocity of row r - 2 from its own momentum and density (kept in registers) and the psi
+// ring.  Each workgroup leaves its largest speed and that node in part.
+constexpr int SW = 256, NC = 1, SC = NC * SW, SO = SC - 4;
+
+template <class S, class C>
+__global__ __launch_bounds__(SW) void k_speed2d(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
+                                                double rho_ref, const double* __restrict__ phi, Eos<double> eos, double G,
+                                                double gx, double gy, int Dy, int nbx, int32_t* flags,
+                                                double* __restrict__ part) {
+    __shared__ double s_rho[3][SC];
+    __shared__ int s_tag[3][SC];
+    __shared__ double s_psi[3][SC];
+    const int t = threadIdx.x;
+    const int bx = int(blockIdx.x) % nbx, by = int(blockIdx.x) / nbx;
+    const int x0 = bx * SO, y0 = by * Dy;
+    const int Dv = min(Dy, g.ny - y0), iters = Dv + 4;
+    const double gk[3] = {gx, gy, 0.0};
+    int xc[NC];    // the lane's columns (strip positions c = t + h SW)
+    bool out[NC];  // output columns
+#pragma unroll
+    for (int h = 0; h < NC; ++h) {
+        const int c = t + h * SW, xr = x0 - 2 + c;
+        xc[h] = wrap1(xr < 0 ? xr : xr % g.nx, g.nx);
+        out[h] = c >= 2 && c < SO + 2 && xr < g.nx;
+    }
+    auto rowof = [&](int k) { int r = (y0 - 2 + k) % g.ny; return r < 0 ? r + g.ny : r; };
+    // loads of the next row in flight
+    C fr[NC][9];
+    int tgr[NC];
+    auto issue = [&](int k) {
+        const int64_t xrow = int64_t(rowof(k)) * g.nx;
+#pragma unroll
+        for (int h = 0; h < NC; ++h) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fr[h][i] = ldp<S, C>(f, i, g.N, xrow + xc[h]);
+            tgr[h] = tag[xrow + xc[h]];
+        }
+    };
+    issue(0);
+    double rA[NC] = {}, rB[NC] = {}, rC[NC] = {};   // density of rows r - 2, r - 1, r (own columns)
+    int tA[NC], tB[NC], tC[NC];                     // their tags
+    double jA[NC][3] = {}, jB[NC][3] = {}, jC[NC][3] = {};  // their momentum
+#pragma unroll
+    for (int h = 0; h < NC; ++h) tA[h] = tB[h] = tC[h] = -1;
+    double best = -1.0, at = -1.0;
+    for (int k = 0; k < iters; ++k) {
+        const int s0 = k % 3, s1 = (k + 2) % 3, s2 = (k + 1) % 3;  // ring slots of rows r, r - 1, r - 2
+        // ---- row r: density and momentum; its tags and densities to the ring
+#pragma unroll
+        for (int h = 0; h < NC; ++h) {
+            double fv[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fv[i] = double(fr[h][i]);
+            const int tg = tgr[h];
+            rA[h] = rB[h];
+            rB[h] = rC[h];
+            tA[h] = tB[h];
+            tB[h] = tC[h];
+            for (int q = 0; q < 3; ++q) {
+                jA[h][q] = jB[h][q];
+                jB[h][q] = jC[h][q];
+            }
+            rC[h] = tg >= 0 ? node_rho<9>(fv, rho_ref) : 0.0;
+            tC[h] = tg;
+            node_j<9>(fv, jC[h]);
+            s_rho[s0][t + h * SW] = rC[h];
+            s_tag[s0][t + h * SW] = tg;
+        }
+        if (k + 1 < iters) issue(k + 1);
+        __syncthreads();
+        // ---- psi of row r - 1 (its neighbours' densities are in the ring from k >= 2)
+        if (k >= 2) {
+#pragma unroll
+            for (int h = 0; h < NC; ++h) {
+                const int c = t + h * SW;
+                if (c < 1 || c >= SC - 1) continue;
+                const int tg = s_tag[s1][c];
+                // the density psi is taken of: the node's own (fluid), eq. 15's (wall); other solid
+                // nodes have psi = 0
+                double re = s_rho[s1][c];
+                if (tg < -1) {
+                    int ty[9];
+                    double ry[9];
+                    ty[0] = -1;
+                    ry[0] = 0.0;
+#pragma unroll
+                    for (int i = 1; i < 9; ++i) {
+                        const int sl = c_ey[0][i] > 0 ? s0 : (c_ey[0][i] < 0 ? s2 : s1);  // row r - 1 + e_y
+                        ty[i] = s_tag[sl][c + c_ex[0][i]];
+                        ry[i] = s_rho[sl][c + c_ex[0][i]];
+                    }
+                    re = wall_rho<9>(ty, ry, phi[-tg - 2]);
+                }
+                s_psi[s1][c] = tg == -1 ? 0.0 : psi_of(re, eos, flags);
+            }
+        }
+        __syncthreads();
+        // ---- velocity and speed of row r - 2 (psi of rows r - 3 .. r - 1 in the ring)
+        if (k >= 4) {
+            const int p0 = s2, pm = s0, pp = s1;  // psi ring slots of rows r - 2, r - 3, r - 1
+#pragma unroll
+            for (int h = 0; h < NC; ++h) {
+                if (!out[h] || tA[h] < 0) continue;
+                const int c = t + h * SW;
+                double pv[9];
+                pv[0] = 0.0;
+#pragma unroll
+                for (int i = 1; i < 9; ++i) {
+                    const int sl = c_ey[0][i] > 0 ? pp : (c_ey[0][i] < 0 ? pm : p0);
+                    pv[i] = s_psi[sl][c + c_ex[0][i]];
+                }
+                double v[3];
+                node_v<9>(jA[h], pv, s_psi[p0][c], rA[h], G, gk, 2, v);
+                const double sp = sqrt(v[0] * v[0] + v[1] * v[1]);
+                speed_pick(best, at, sp, double(int64_t(rowof(k - 2)) * g.nx + xc[h]));
+            }
+        }
+    }
+    speed_block(best, at);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = best;
+        part[2 * blockIdx.x + 1] = at;
+    }
+}
+
 // rho, psi and the physical velocity of the state into the scratch arena: rho at scratch, psi
 // after it, v (dim planes) after that
 template <class S, class C>
@@ -348,10 +517,28 @@ hipError_t moments_dev(mcb_ctx* c, const void* fcur) {
 
 template <class S, class C>
 hipError_t max_speed_t(mcb_ctx* c, const void* fcur) {
+    double* part = reinterpret_cast<double*>(c->lat + c->L.partials);
+    if (c->g.dim == 2 && c->p.model != MCB_MODEL_CHEMPOT) {
+        // one pass, one resident round of workgroups (at most the partials' capacity)
+        const int nbx = (c->g.nx + SO - 1) / SO;
+        const int cap = resident_blocks(c, k_speed2d<S, C>, SW, &c->occ[6]);
+        const int want = std::max(1, std::min(cap, MON_BLOCKS * MON_FIELDS / 2) / nbx);
+        int nseg = std::min(c->g.ny, want);
+        const int Dy = (c->g.ny + nseg - 1) / nseg;
+        nseg = (c->g.ny + Dy - 1) / Dy;
+        const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
+        Eos<double> eos{c->p.eos_R * c->p.eos_T, c->p.eos_a, c->p.eos_b / 4.0, 2.0 / c->p.G};
+        hipLaunchKernelGGL((k_speed2d<S, C>), dim3(nbx * nseg), dim3(SW), 0, c->stream, c->g, static_cast<const S*>(fcur),
+                           reinterpret_cast<const int32_t*>(c->lat + c->L.tag), rr,
+                           reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos, c->p.G, c->p.gravity[0],
+                           c->p.gravity[1], Dy, nbx, reinterpret_cast<int32_t*>(c->lat + c->L.flags), part);
+        hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(256), 0, c->stream, part, nbx * nseg,
+                           reinterpret_cast<double*>(c->lat + c->L.result) + MON_SPEED);
+        return hipGetLastError();
+    }
     hipError_t e = moments_dev<S, C>(c, fcur);
     if (e != hipSuccess) return e;
     const double* sv = reinterpret_cast<const double*>(c->lat + c->L.scratch) + 2 * c->g.N;
-    double* part = reinterpret_cast<double*>(c->lat + c->L.partials);
     hipLaunchKernelGGL(k_speed_partial, dim3(MON_BLOCKS), dim3(256), 0, c->stream, c->g,
                        reinterpret_cast<const int32_t*>(c->lat + c->L.tag), sv, part);
     hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(256), 0, c->stream, part, MON_BLOCKS,

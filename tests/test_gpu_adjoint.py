@@ -4,8 +4,13 @@ that share nothing with it:
     map, obtained without any transposition): FP64 adjoint within 1e-8 relative;
   * central finite differences of the GPU forward map on the 512^2 rough-wall workload (2000
     steps, a checkpoint every 100): 1e-4 relative on 20 seeded wall nodes;
+  * on that workload itself, the oracle's dual numbers along twenty seeded directions over the
+    full run (stored by tests/golden/make_c3_duals.py): 1e-8 relative;
   * dM/dphi = 0: eq. 18 conserves the mass for any wettability.
 """
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -264,6 +269,33 @@ def test_c3_gradient_against_central_differences(mcb):
     gm = lat.adj_backward(1.0)
     assert np.abs(gm).max() < 1e-12 * M, np.abs(gm).max()
     lat.close()
+
+
+def test_c3_gradient_against_oracle_duals(mcb):
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c3_oracle_duals.json")))
+    banner(f"c3 (512^2 rough wall, {ref['steps']} steps, k = 100): adjoint vs the oracle's dual numbers along "
+           f"{ref['n_directions']} directions")
+    wl = W.make("c3")
+    assert ref["steps"] == wl.steps and ref["loss_kind"] == 0
+    lat = mcb.Lattice(2, wl.dims, wl.tau, wl.T)
+    lat.set_geometry(wl.shapes)
+    walls = lat.wall_nodes()
+    # the directions are indexed by the wall-node list the oracle used
+    assert len(walls) == ref["n_wall"]
+    assert hashlib.sha256(np.ascontiguousarray(walls, np.int64).tobytes()).hexdigest() == ref["wall_sha256"]
+    lat.set_wettability(W.phi_for_walls(wl, walls))
+    L = lat.adj_forward(wl.rho0(), wl.steps, 100, 0, tuple(ref["loss_prm"]))
+    g = lat.adj_backward(1.0)
+    lat.close()
+    dirs = np.random.Generator(np.random.PCG64(ref["direction_seed"])).standard_normal((ref["n_directions"], len(walls)))
+    dL = dirs @ g
+    want = np.asarray(ref["derivatives"])
+    scale = np.abs(want).max()
+    err = np.abs(dL - want).max() / scale
+    print(f"  loss GPU {L:.15e} oracle {ref['loss']:.15e}; directional derivatives: worst {err:.2e} of the largest "
+          f"({scale:.3e})", flush=True)
+    assert abs(L - ref["loss"]) <= 1e-10 * abs(ref["loss"]), (L, ref["loss"])
+    assert scale > 0 and err <= 1e-8, (dL, want)
 
 
 def test_shifted_fp32_gradient_close_to_fp64(mcb):
