@@ -4,8 +4,9 @@
                                              [--precisions f64,f32s] [--out profiles/stability_stated]
 
 Each run starts from the workload's equilibrium state at the stated parameters (0.6 T_c and tau 0.8
-on 1024^2 and 4096^2, 0.65 T_c and tau 0.8 on 256^3, width-2 drops) and steps for the workload's
-full count, synchronising every 100 steps.  A run that ends in a psi domain error (a density past
+on 1024^2 and 4096^2, 0.65 T_c and tau 0.8 on 256^3, width-2 drops; --tau and --widths vary the
+relaxation time and the drop profile) and steps for the workload's full count, synchronising every
+100 steps.  A run that ends in a psi domain error (a density past
 the real branch of the pseudopotential: the large-density-ratio instability) or a non-finite
 population is recorded with the window in which it failed.  The multiple-relaxation-time collision
 (eqs. 1-3 with the paper's rates) is tried as the stable route on the two-dimensional lattices; it
@@ -23,12 +24,14 @@ import time
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def run_one(mcb, W, name, collision, precision, steps=None, check=100, stated=True, width=None):
+def run_one(mcb, W, name, collision, precision, steps=None, check=100, stated=True, width=None, tau=None):
     import torch
 
     wl = W.make(name, stated=stated)
     if width is not None:
         wl.interface_width = width
+    if tau is not None:
+        wl.tau = tau
     n = steps if steps is not None else wl.steps
     lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision,
                       rho_ref=wl.rho_v if precision != "f64" else 0.0, collision=collision)
@@ -76,6 +79,7 @@ def main():
     ap.add_argument("--precisions", default="f64,f32s")
     ap.add_argument("--steps", type=int, default=None, help="override the workloads' step counts")
     ap.add_argument("--widths", default="2", help="drop profile widths to run (the stated one is 2)")
+    ap.add_argument("--tau", type=float, default=None, help="relaxation time instead of the stated 0.8")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "stability_stated"))
     args = ap.parse_args()
     sys.path.insert(0, ROOT)
@@ -91,7 +95,7 @@ def main():
                 continue
             for prec, width in [(p, float(w)) for w in args.widths.split(",") for p in args.precisions.split(",")]:
                 print(f"[stability] {name} {coll} {prec} width {width:g}", flush=True)
-                r = run_one(mcb, W, name, coll, prec, steps=args.steps, width=width)
+                r = run_one(mcb, W, name, coll, prec, steps=args.steps, width=width, tau=args.tau)
                 print(f"[stability]   {r['status']} after {r['steps_done']} steps "
                       f"({r['seconds']:.1f} s)", flush=True)
                 rows.append(r)

@@ -222,9 +222,10 @@ def make(name: str, min_gap: float = 0.0, stated: bool = False) -> Workload:
         shapes = np.array([ball(c, r, g) for g, (c, r) in enumerate(zip(cs, rs))], np.int64)
         drops = _drops(rng, 40 * scale * scale, (n, n, 1), 2, 15.0, 40.0)
         phi = rng.uniform(*PHI_RANGE, len(rs))
-        # 0.7 T_c and tau = 1: with single-relaxation-time collision the pseudopotential runs at
-        # 0.6 or 0.65 T_c (density ratio ~700 / ~250) end in psi domain errors within a few
-        # thousand steps on these geometries; 0.7 T_c (ratio ~65, the c0 temperature) stays stable
+        # 0.7 T_c and tau = 1: at 0.6 T_c with tau 0.8 both lattices end in psi domain errors within
+        # 80 steps (BGK or MRT); with tau 1 the 1024^2 one runs 10^4 steps with BGK but not with
+        # MRT, and the 4096^2 one ends between steps 1800 and 4900; 0.7 T_c (ratio ~65, the c0
+        # temperature) keeps every collision and boundary scheme stable
         return Workload(name, 2, (n, n, 1), 1.0, 0.70, shapes, drops, phi, 10000 if name == "c1" else 5000,
                         extra={"min_gap": min_gap} if min_gap > 0 else {})
     if name == "c3":
