@@ -112,7 +112,9 @@ typedef struct {
     int32_t bc_mode;        /* MCB_BC_PRESENT, MCB_BC_IBC, MCB_BC_MIBC, MCB_BC_HBBC */
     double rho_ref;         /* shift of the stored populations (ignored for MCB_F64) */
     int32_t collision;      /* MCB_COLL_BGK (0, the default of a zeroed struct) or MCB_COLL_MRT */
-    int32_t reserved;       /* 0 */
+    int32_t track_dm;       /* nonzero: every mcb_step also adds the step's eq. 18 total (Delta M of
+                               Sec. 3.2) to an FP64 sum on the device, reported as dM_cum (two small
+                               extra launches per step); 0: dM_cum is reported as NaN */
     double s_e, s_eps, s_q; /* MRT rates of the energy, energy-square and heat-flux moments, each in
                                (0, 2) for MCB_COLL_MRT (the paper's: 1.64, 1.54, 1.7); ignored for BGK */
     double gravity[3];      /* uniform body acceleration g (lattice units): the force of eq. 13 and of
@@ -161,6 +163,8 @@ typedef struct {
     int64_t n_nan;   /* fluid nodes with a non-finite population */
     int64_t n_domain;/* psi domain errors since the state was set */
     int64_t t;       /* steps taken since the state was set */
+    double dM_cum;   /* sum of dM_last over the mcb_step steps since the state was set (Sec. 3.2),
+                        summed in FP64 in a fixed order; NaN unless params.track_dm */
 } mcb_mass_report;
 
 /* ---- context ---------------------------------------------------------------------------- */

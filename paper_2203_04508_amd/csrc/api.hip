@@ -38,6 +38,7 @@ Layout make_layout(const mcb_params& p, int64_t n_shapes, int64_t n_links, int64
     L.tag = take(4 * N);
     L.nmask = take(p.dim == 3 ? 4 * N : 0);  // 3-D: link bits of each boundary node (bit j-1: x + e_j solid)
     L.rho3 = take(p.dim == 3 ? cb * N : 0);  // 3-D: density pass output of the step (compute type)
+    L.dm = take(8 * (DM_BLOCKS + 1));         // track_dm: per-workgroup partials, then the running sum
     const bool cp = p.model == MCB_MODEL_CHEMPOT;
     L.cp_rho = take(cp ? cb * N : 0);        // chemical-potential model: density and chemical potential
     L.cp_mu = take(cp ? cb * N : 0);         // fields of the step (compute type), solid layer of each node
@@ -497,6 +498,8 @@ mcb_status mcb_set_wettability(mcb_ctx* c, const double* phi, int64_t n_wall) {
 
 static mcb_status collide_from(mcb_ctx* c, void* fpre) {
     c->adj_ready = false;  // a new state: the last forward pass no longer ends here
+    // the running Delta M sum starts again with the state
+    HIPCHK(hipMemsetAsync(c->lat + c->L.dm + 8 * DM_BLOCKS, 0, 8, c->stream));
     // fpre holds pre-collision populations in storage format; the collision writes the other lattice
     const bool to_fb = fpre != c->lat + c->L.fb;
     void* dst = to_fb ? c->lat + c->L.fb : c->lat + c->L.fa;
@@ -584,6 +587,7 @@ mcb_status mcb_step(mcb_ctx* c, int64_t n) {
         }
         c->swapped = !c->swapped;
         ++c->t;
+        if (c->p.track_dm) HIPCHK(dm_accumulate(c, rcur(c)));
     }
     return MCB_OK;
 }
@@ -771,6 +775,9 @@ mcb_status mcb_max_speed(mcb_ctx* c, double* vmax, int64_t* node) {
     return check_flags(c, nullptr);
 }
 
+// the running Delta M sum of track_dm (NaN when not tracked), as last copied to the host
+static double dm_total(const mcb_ctx* c) { return c->p.track_dm ? c->dm_host : std::nan(""); }
+
 mcb_status mcb_mass(mcb_ctx* c, mcb_mass_report* out) {
     if (!c) return MCB_EINVAL;
     if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
@@ -778,6 +785,7 @@ mcb_status mcb_mass(mcb_ctx* c, mcb_mass_report* out) {
     HIPCHK(monitor(c, fcur(c), rcur(c)));
     double r[MON_FIELDS];
     HIPCHK(hipMemcpyAsync(r, c->lat + c->L.result, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&c->dm_host, c->lat + c->L.dm + 8 * DM_BLOCKS, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     std::memset(out, 0, sizeof *out);
     out->M = r[0];
@@ -787,6 +795,7 @@ mcb_status mcb_mass(mcb_ctx* c, mcb_mass_report* out) {
     out->dM_last = c->t > 0 ? r[4] : 0.0;
     out->n_nan = int64_t(r[5]);
     out->t = c->t;
+    out->dM_cum = dm_total(c);
     int64_t nd = 0;
     mcb_status st = check_flags(c, &nd);
     out->n_domain = nd;
@@ -817,6 +826,7 @@ mcb_status mcb_mass_static(mcb_ctx* c, mcb_mass_report* out) {
     HIPCHK(hipMemcpyAsync(r, res, sizeof r, hipMemcpyDeviceToHost, c->stream));
     int32_t flags[FLAG_COUNT];
     HIPCHK(hipMemcpyAsync(flags, c->lat + c->L.flags, sizeof flags, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&c->dm_host, c->lat + c->L.dm + 8 * DM_BLOCKS, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     std::memset(out, 0, sizeof *out);
     out->M = r[0];
@@ -827,6 +837,7 @@ mcb_status mcb_mass_static(mcb_ctx* c, mcb_mass_report* out) {
     out->n_nan = int64_t(r[5]);
     out->n_domain = flags[FLAG_DOMAIN] ? 1 : 0;
     out->t = c->t;
+    out->dM_cum = dm_total(c);
     if (out->n_nan > 0) return fail(c, MCB_ENAN, "%lld fluid nodes hold non-finite populations", (long long)out->n_nan);
     if (flags[FLAG_DOMAIN]) return fail(c, MCB_EDOMAIN, "psi domain error: rho <= 0 or negative square-root argument");
     return MCB_OK;

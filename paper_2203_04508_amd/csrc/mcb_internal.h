@@ -36,6 +36,7 @@ constexpr int SCAN_BLOCK = 256;           // geometry scan granularity
 constexpr int MON_BLOCKS = 1024;          // monitor partial sums
 constexpr int MON_FIELDS = 8;             // M, Jx, Jy, Jz, dM, n_nan, then the max-speed pair
 constexpr int MON_SPEED = 6;              // result slots of the largest speed and its node
+constexpr int DM_BLOCKS = 256;            // workgroups of the per-step Delta M sum (track_dm)
 constexpr int MAX_BANDS = 8;
 
 // sticky device fault flags
@@ -64,7 +65,7 @@ struct GridDev {
 // Byte offsets of the sub-buffers carved out of the two caller-owned arenas.
 struct Layout {
     // lattice arena
-    int64_t fa, fb, tag, nmask, rho3, cp_rho, cp_mu, cp_layer, cp_l2, cp_l2n, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
+    int64_t fa, fb, tag, nmask, rho3, dm, cp_rho, cp_mu, cp_layer, cp_l2, cp_l2n, solid, scratch, blocksums, flags, partials, result, shapes, lattice_bytes;
     // links arena
     int64_t bn_node, bn_mask, bn_link0, lk_qc, lk_a, rec[2], wl_node, wl_phi, wl_fac, links_bytes;
     int64_t rec_slots;   // link-coefficient slots: Q2_LINKS / Q3_LINKS per boundary node
@@ -132,7 +133,7 @@ struct mcb_ctx {
     int stage = 0;        // 0 created, 1 bound, 2 geometry set, 3 counted, 4 links filled, 5 state set
     bool swapped = false; // current post-collision state lives in fb instead of fa
     int64_t t = 0;
-    double dm_cum = 0.0;
+    double dm_host = 0.0;  // track_dm: host copy of the running Delta M sum, read by the mass reports
     int n_bands = 0;
     mcb_shape bands[mcb::MAX_BANDS]{};
     mcb::Layout L{};
@@ -185,6 +186,9 @@ hipError_t adj_loss(mcb_ctx* c, const AdjWork& w, const void* g, int kind, const
 hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur, double* partials = nullptr, double* result = nullptr);
 hipError_t moments_out(mcb_ctx* c, const void* fcur, double* rho, double* v);
 hipError_t max_speed(mcb_ctx* c, const void* fcur);  // result slots MON_SPEED, MON_SPEED + 1
+// track_dm: adds the eq. 18 total held in the records rcur (the step that wrote them) to the FP64
+// sum at L.dm[DM_BLOCKS] (per-workgroup partials first, then one workgroup in a fixed order)
+hipError_t dm_accumulate(mcb_ctx* c, const void* rcur);
 hipError_t convert_plane_in(mcb_ctx* c, const double* src, void* dst_plane, int dir);
 hipError_t convert_plane_out(mcb_ctx* c, const void* src_plane, double* dst, int dir);
 

@@ -487,6 +487,31 @@ __global__ __launch_bounds__(SW) void k_speed2d(GridDev g, const S* __restrict__
     }
 }
 
+// ---- track_dm: the eq. 18 total of the step just taken (the correction slot, last of each
+// boundary record), added to a running FP64 sum.  Pass 1: DM_BLOCKS workgroups, each the records
+// b = blockIdx.x * 256 + threadIdx.x + k * DM_BLOCKS * 256; pass 2: one workgroup sums the partials
+// in a fixed order and adds the total to the running sum.  Deterministic.
+template <class C>
+__global__ __launch_bounds__(256) void k_dm_partial(const C* __restrict__ rec, int rec_stride, int64_t nb,
+                                                    double* __restrict__ part) {
+    double acc = 0.0;
+    for (int64_t b = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; b < nb; b += int64_t(gridDim.x) * blockDim.x)
+        acc += double(rec[b * rec_stride + rec_stride - 1]);
+    __shared__ double red[4];
+    const double s = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_dm_final(double* __restrict__ part) {
+    __shared__ double red[4];
+    const double s = wave_sum(threadIdx.x < DM_BLOCKS ? part[threadIdx.x] : 0.0);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[DM_BLOCKS] += ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 // rho, psi and the physical velocity of the state into the scratch arena: rho at scratch, psi
 // after it, v (dim planes) after that
 template <class S, class C>
@@ -581,6 +606,21 @@ hipError_t monitor(mcb_ctx* c, const void* fcur, const void* rcur, double* parti
         case MCB_F32S: return monitor_t<float, float>(c, fcur, rcur, partials, result);
         default: return monitor_t<__half, float>(c, fcur, rcur, partials, result);
     }
+}
+
+hipError_t dm_accumulate(mcb_ctx* c, const void* rcur) {
+    static_assert(DM_BLOCKS == 256, "one lane per partial in the final pass");
+    double* part = reinterpret_cast<double*>(c->lat + c->L.dm);
+    const int64_t nb = c->n_bnodes > 0 ? c->n_bnodes : 0;
+    const int stride = int(c->L.rec_stride);
+    if (c->p.precision == MCB_F64)
+        hipLaunchKernelGGL(k_dm_partial<double>, dim3(DM_BLOCKS), dim3(256), 0, c->stream, static_cast<const double*>(rcur),
+                           stride, nb, part);
+    else
+        hipLaunchKernelGGL(k_dm_partial<float>, dim3(DM_BLOCKS), dim3(256), 0, c->stream, static_cast<const float*>(rcur),
+                           stride, nb, part);
+    hipLaunchKernelGGL(k_dm_final, dim3(1), dim3(256), 0, c->stream, part);
+    return hipGetLastError();
 }
 
 hipError_t max_speed(mcb_ctx* c, const void* fcur) {

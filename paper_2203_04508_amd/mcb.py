@@ -34,7 +34,7 @@ class mcb_params(C.Structure):
                 ("tau", C.c_double), ("G", C.c_double),
                 ("eos_a", C.c_double), ("eos_b", C.c_double), ("eos_R", C.c_double), ("eos_T", C.c_double),
                 ("precision", C.c_int32), ("bc_mode", C.c_int32), ("rho_ref", C.c_double),
-                ("collision", C.c_int32), ("reserved", C.c_int32),
+                ("collision", C.c_int32), ("track_dm", C.c_int32),
                 ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double), ("gravity", C.c_double * 3),
                 ("model", C.c_int32), ("reserved2", C.c_int32), ("pr_omega", C.c_double),
                 ("cp_k", C.c_double), ("cp_kappa", C.c_double)]
@@ -61,7 +61,7 @@ class mcb_buffers(C.Structure):
 
 class mcb_mass_report(C.Structure):
     _fields_ = [("M", C.c_double), ("J", C.c_double * 3), ("dM_last", C.c_double),
-                ("n_nan", C.c_int64), ("n_domain", C.c_int64), ("t", C.c_int64)]
+                ("n_nan", C.c_int64), ("n_domain", C.c_int64), ("t", C.c_int64), ("dM_cum", C.c_double)]
 
 
 EXPORTS = [
@@ -311,10 +311,12 @@ class Lattice:
 
     def __init__(self, dim, dims, tau, T, precision="f64", rho_ref=0.0, G=-1.0, a=None, b=None, R=1.0,
                  device="cuda:0", stream=None, bc_mode="present", collision="bgk", mrt_rates=MRT_RATES_PAPER,
-                 gravity=(0.0, 0.0, 0.0), model="pseudo", cp_k=1.0, cp_kappa=0.0, pr_omega=PR_PAPER["omega"]):
+                 gravity=(0.0, 0.0, 0.0), model="pseudo", cp_k=1.0, cp_kappa=0.0, pr_omega=PR_PAPER["omega"],
+                 track_dm=False):
         """model "pseudo": pseudopotential with the Carnahan-Starling EOS (a, b default 1, 4);
         model "chempot": the chemical-potential model with the Peng-Robinson EOS (a, b default to the
-        paper's 2/49, 2/21), mesh scaling cp_k and gradient coefficient cp_kappa."""
+        paper's 2/49, 2/21), mesh scaling cp_k and gradient coefficient cp_kappa.  track_dm: sum each
+        step's eq. 18 total into the mass report's dM_cum."""
         import torch
 
         self.torch = torch
@@ -328,7 +330,7 @@ class Lattice:
         self.params = mcb_params(dim, dims[0], dims[1], nz, tau, G, a, b, R, T,
                                  PRECISIONS[precision] if isinstance(precision, str) else precision,
                                  BC_MODES[bc_mode] if isinstance(bc_mode, str) else bc_mode, rho_ref,
-                                 {"bgk": MCB_COLL_BGK, "mrt": MCB_COLL_MRT}[collision], 0, *mrt_rates,
+                                 {"bgk": MCB_COLL_BGK, "mrt": MCB_COLL_MRT}[collision], 1 if track_dm else 0, *mrt_rates,
                                  (C.c_double * 3)(*(list(gravity) + [0.0] * (3 - len(gravity)))),
                                  MCB_MODEL_CHEMPOT if cp else MCB_MODEL_PSEUDO, 0, pr_omega, cp_k, cp_kappa)
         self.dim = dim

@@ -316,3 +316,50 @@ def test_domain_error_reported(mcb):
         lat.step(20)
         lat.sync()
     assert ei.value.code == mcb.MCB_EDOMAIN
+
+
+@pytest.mark.parametrize("dim,dims", [(2, (37, 29, 1)), (3, (13, 11, 9))], ids=["2d-37x29", "3d-13x11x9"])
+def test_dm_cum_is_the_sum_of_the_steps_corrections(mcb, dim, dims):
+    """track_dm: dM_cum equals the oracle's eq. 18 totals summed over the steps (Sec. 3.2), restarts
+    with a new state, and is NaN when not tracked."""
+    banner(f"running Delta M sum {dims}")
+    rng = np.random.default_rng(77 + dim)
+    shapes = W.random_links_case(rng, dims, dim, 3, 2.0 if dim == 2 else 1.5, 6.0 if dim == 2 else 3.5)
+    rv, rl = W.MAXWELL[0.7]
+    drops = [(tuple(rng.uniform(0, n) for n in dims[:dim]), rng.uniform(3, 6)) for _ in range(2)]
+    rho = W.drop_field(dims, dim, drops, rv, rl, 2.0)
+    P = oracle.make_params(dim, *dims, tau=0.8, T=0.7 * TC)
+    solid = oracle.classify(P, shapes)
+    node, d, cls, q = oracle.links(P, shapes, solid)
+    walls = oracle.wall_nodes(P, solid)
+    phi = rng.uniform(0.85, 1.15, len(walls))
+    sim = oracle.Sim(P, solid, node, d, q)
+    sim.set_phi(phi)
+    lat = mcb.Lattice(dim, dims, 0.8, 0.7 * TC, track_dm=True)
+    plain = mcb.Lattice(dim, dims, 0.8, 0.7 * TC)
+    for L in (lat, plain):
+        L.set_geometry(shapes)
+        L.set_wettability(phi)
+        L.init_equilibrium(rho)
+    sim.init_eq(rho)
+    assert lat.mass().dM_cum == 0.0 and np.isnan(plain.mass().dM_cum)
+    total, scale = 0.0, 0.0
+    for k in range(25):
+        sim.step(1)
+        lat.step(1)
+        total += sim.dm_last()
+        scale += abs(sim.dm_last())
+    rep = lat.mass()
+    assert scale > 0.0
+    assert abs(rep.dM_cum - total) <= 1e-12 * scale, (rep.dM_cum, total)
+    plain.step(3)
+    assert np.isnan(plain.mass().dM_cum)
+    # a new state starts the sum again
+    lat.init_equilibrium(rho)
+    assert lat.mass().dM_cum == 0.0
+    lat.step(1)
+    rep = lat.mass()
+    assert abs(rep.dM_cum - rep.dM_last) <= 1e-13 * max(abs(rep.dM_last), 1e-300), (rep.dM_cum, rep.dM_last)
+    lat.close()
+    plain.close()
+    sim.close()
