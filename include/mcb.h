@@ -66,8 +66,7 @@ enum {
  * (Secs. 1 and 4).  All four coincide at q = 1/2. */
 enum {
     MCB_BC_PRESENT = 0, /* eqs. 16-18: interpolation with the forcing term, plus mass modification */
-    MCB_BC_IBC = 1,     /* eqs. 16-17 without the forcing term, no eq. 18 (2-D only: MCB_ENOTSUP
-                           from mcb_create for dim 3, whose density pass relies on eq. 18) */
+    MCB_BC_IBC = 1,     /* eqs. 16-17 without the forcing term, no eq. 18 */
     MCB_BC_MIBC = 2,    /* eqs. 16-17 without the forcing term, with eq. 18 */
     MCB_BC_HBBC = 3     /* halfway bounce-back on every link (q ignored; eq. 18 terms are zero) */
 };
@@ -168,7 +167,7 @@ typedef struct {
 } mcb_mass_report;
 
 /* ---- context ---------------------------------------------------------------------------- */
-/* Validates params (MCB_EINVAL otherwise; MCB_ENOTSUP for MCB_BC_IBC, MCB_COLL_MRT or MCB_MODEL_CHEMPOT in 3-D) and creates a
+/* Validates params (MCB_EINVAL otherwise; MCB_ENOTSUP for MCB_COLL_MRT or MCB_MODEL_CHEMPOT in 3-D) and creates a
  * context; no device work. */
 mcb_status mcb_create(const mcb_params* params, mcb_ctx** out);
 void mcb_destroy(mcb_ctx* ctx);

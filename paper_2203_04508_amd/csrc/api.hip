@@ -274,7 +274,6 @@ mcb_status mcb_create(const mcb_params* params, mcb_ctx** out) {
     const char* why = nullptr;
     if (!params_ok(params, &why)) return MCB_EINVAL;
     // the 3-D density pass takes the boundary nodes' density from the eq. 18 balance
-    if (params->dim == 3 && params->bc_mode == MCB_BC_IBC) return MCB_ENOTSUP;
     // the paper gives the moment basis of D2Q9 only; the chemical-potential path is two-dimensional
     if (params->dim == 3 && (params->collision == MCB_COLL_MRT || params->model == MCB_MODEL_CHEMPOT)) return MCB_ENOTSUP;
     auto* c = new (std::nothrow) mcb_ctx();

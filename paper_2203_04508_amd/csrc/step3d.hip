@@ -15,7 +15,9 @@
 // sum -- f_in enters once and is subtracted once from f_0 -- leaving the node's own f~_j(x, t) for
 // each link j, while the slot pulled from the solid neighbour holds 0 (solid nodes store zeros).
 // So rho = sum of the pulled populations + sum over links of f~_j(x, t), the latter kept in the
-// node's boundary record by its collision.  The pass writes rho for fluid nodes, -phi/(weight of the fluid neighbours)
+// node's boundary record by its collision.  Without eq. 18 (IBC) nothing cancels: the pass forms
+// each link's f_in from the record, the link coefficients and the pulled values, as the collision
+// pass will, and adds it.  The pass writes rho for fluid nodes, -phi/(weight of the fluid neighbours)
 // for wall nodes (the eq. 15 factor; the sign marks the wall) and 0 for the other solid nodes, so
 // the collision pass needs no tags for the ring.
 //
@@ -68,11 +70,13 @@ struct RhoArgs {
     const S* fa;                 // post-collision populations of time t, SoA [19][N]
     const int32_t* tag;          // >0: boundary index + 1; 0 fluid; -1 solid; -2-w wall w
     const C* rin;                // boundary records of time t
+    const C* la;                 // link coefficients, Q3_LINKS per boundary node (IBC only)
     const C* fac;                // eq. 15 factor per wall node
     C* rho;                      // out, per node
     int32_t* flags;
     int nx, ny, nz, nbx;
     C rho_ref;
+    int ibc;                     // boundary scheme without eq. 18: links' f_in summed explicitly
 };
 
 // One lane per node, workgroups of 256 consecutive nodes of an x-row.  PULL = false sums the
@@ -93,18 +97,38 @@ __global__ __launch_bounds__(256) void k_rho3d(RhoArgs<S, C> a) {
     const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
     const int zm = zdec(z, a.nz), zp = zinc(z, a.nz);
     const int xs[3] = {xp, x, xm}, ys[3] = {yp, y, ym}, zs[3] = {zp, z, zm};  // upstream of e = -1, 0, +1
-    C rs = C(0);
+    C fv[19];
     // FP16 storage: the rest population (own node) in FP32, the others from half plane i + 1 on
-    if (kMixed<S>) rs += Buf<float>::ld(fa, on ? node * 4u : OOB);
+    if (kMixed<S>) fv[0] = Buf<float>::ld(fa, on ? node * 4u : OOB);
 #pragma unroll
     for (int i = kMixed<S> ? 1 : 0; i < 19; ++i) {
         const uint32_t src =
             PULL ? uint32_t(zs[kEz3[i] + 1]) * nxy + uint32_t(ys[kEy3[i] + 1]) * uint32_t(a.nx) + uint32_t(xs[kEx3[i] + 1]) : node;
-        rs += Buf<S>::ld(fa, on ? (uint32_t(i + (kMixed<S> ? 1 : 0)) * N + src) * s : OOB);
+        fv[i] = Buf<S>::ld(fa, on ? (uint32_t(i + (kMixed<S> ? 1 : 0)) * N + src) * s : OOB);
     }
+    C rs = C(0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) rs += fv[i];
     if (PULL && on && tg > 0) {
-        // boundary node: its own f~_j(x, t) on each link (the slot pulled from the solid node holds 0)
-        rs += a.rin[size_t(tg - 1) * REC3 + RF3 + 18];
+        const C* rec = a.rin + size_t(tg - 1) * REC3;
+        if (!a.ibc) {
+            // boundary node: its own f~_j(x, t) on each link (the slot pulled from the solid node holds 0)
+            rs += rec[RF3 + 18];
+        } else {
+            // IBC (no forcing term, no eq. 18): the f_in of each link j, which replaces the zero
+            // pulled into slot opp(j) -- eq. 16 from the value pulled from x2 into slot j, eq. 17
+            // from the node's own opposite population
+            const C* ca = a.la + size_t(tg - 1) * Q3_LINKS;
+            for (int j = 1; j < 19; ++j) {
+                const C c = ca[j - 1];
+                if (!(c < C(1.5))) continue;
+                const C c1 = c < C(0) ? -c : c, c2 = C(1) - c1;
+                const int jo = (j & 1) ? j + 1 : j - 1;
+                C o = c < C(0) ? rec[RF3 + jo - 1] : fv[j];
+                o = c2 != C(0) ? o : C(0);
+                rs += Buf<S>::round(c1 * rec[RF3 + j - 1] + c2 * o);
+            }
+        }
     }
     if (!on) return;
     C out;
@@ -133,7 +157,7 @@ struct Args3 {
     uint32_t n_bnodes;
     int nx, ny, nz, D, ntx, nty, nblocks;
     C tau_inv, G, rho_ref;
-    C kF;                        // boundary scheme: weight of the forcing term (eq. 18 always applies)
+    C kF, k18;                   // boundary scheme: weights of the forcing term and of eq. 18
     C gx, gy, gz;                // body acceleration: F = F_nonideal + rho g, so du = F / rho gains g
     Eos<C> eos;
 };
@@ -146,10 +170,10 @@ struct Args3 {
 // directions in which no lane of the wave has a link are skipped.  LOAD: rec and ca are loaded
 // here, from rin at byte offset roff and la at aoff, in two halves, each just before its directions
 // (keeps the FP64 kernel within its registers).  kF = 0 drops the forcing term (MIBC); halfway
-// bounce-back is a = 1 on every link.  Eq. 18 always applies: the density pass relies on it.
+// bounce-back is a = 1 on every link; k18 = 0 drops eq. 18 (IBC).
 template <class S, class C, bool LOAD>
 __device__ __forceinline__ C apply_links3(bool bnd, C (&rec)[RF3 + 18], C (&ca)[18], C (&f)[19], __amdgpu_buffer_rsrc_t rin,
-                                          uint32_t roff, __amdgpu_buffer_rsrc_t la, uint32_t aoff, C kF, C& res) {
+                                          uint32_t roff, __amdgpu_buffer_rsrc_t la, uint32_t aoff, C kF, C k18, C& res) {
     constexpr int H1 = RF3 + 8, A1 = 8;  // first half: forcing terms, f~_1..f~_8; directions 1..8
     if (LOAD) {
         C h[H1], g[A1];
@@ -196,6 +220,7 @@ __device__ __forceinline__ C apply_links3(bool bnd, C (&rec)[RF3 + 18], C (&ca)[
     }
 #pragma unroll
     for (int j = A1 + 1; j < 19; ++j) link(j);
+    ds *= double(k18);
     const double f0 = double(f[0]) + ds;
     f[0] = C(f0);
     res = C(f0 - double(f[0]));
@@ -370,7 +395,7 @@ __global__ __launch_bounds__(NT) void k_step3d(Args3<S, C> a) {
                 // without the prefetch (FP64) the record and the coefficients are loaded here
                 const uint32_t bi = uint32_t(tgC - 1);
                 dsC = apply_links3<S, C, !PF>(tgC > 0, recC, aC, fC, M.rin, tgC > 0 ? bi * (REC3 * sc) : OOB, M.la,
-                                              tgC > 0 ? bi * (Q3_LINKS * sc) : OOB, a.kF, erC);
+                                              tgC > 0 ? bi * (Q3_LINKS * sc) : OOB, a.kF, a.k18, erC);
             }
             C out[19];
             C rho = C(0), dux = C(0), duy = C(0), duz = C(0), sx2 = C(0), sy2 = C(0), sz2 = C(0), duu15 = C(0);
@@ -507,6 +532,8 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, const void* rcur, void* f
         r.fa = static_cast<const S*>(fcur);
         r.tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
         r.rin = static_cast<const C*>(rcur);
+        r.la = reinterpret_cast<const C*>(c->lk + c->L.lk_a);
+        r.ibc = c->p.bc_mode == MCB_BC_IBC ? 1 : 0;
         r.fac = reinterpret_cast<const C*>(c->lk + c->L.wl_fac);
         r.rho = rho;
         r.flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
@@ -557,6 +584,7 @@ hipError_t launch_step3d(mcb_ctx* c, const void* fcur, const void* rcur, void* f
     a.G = C(c->p.G);
     a.rho_ref = c->p.precision == MCB_F64 ? C(0) : C(c->p.rho_ref);
     a.kF = c->p.bc_mode == MCB_BC_PRESENT ? C(1) : C(0);
+    a.k18 = c->p.bc_mode == MCB_BC_IBC ? C(0) : C(1);
     a.gx = C(c->p.gravity[0]);
     a.gy = C(c->p.gravity[1]);
     a.gz = C(c->p.gravity[2]);

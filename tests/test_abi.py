@@ -72,16 +72,12 @@ def test_host_side_argument_checks(lib):
         with pytest.raises(mcb.MCBError) as ei:
             mcb.mcb_create(p)
         assert ei.value.code == mcb.MCB_EINVAL
-    # every boundary scheme in 2-D; IBC in 3-D is an unsupported combination
+    # every boundary scheme in 2-D and 3-D
     for mode in (mcb.MCB_BC_PRESENT, mcb.MCB_BC_IBC, mcb.MCB_BC_MIBC, mcb.MCB_BC_HBBC):
         p = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, mode, 0.0)
         mcb.mcb_destroy(mcb.mcb_create(p))
-    p3 = mcb.mcb_params(3, 16, 16, 16, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, mcb.MCB_BC_IBC, 0.0)
-    with pytest.raises(mcb.MCBError) as ei:
-        mcb.mcb_create(p3)
-    assert ei.value.code == mcb.MCB_ENOTSUP
-    p3.bc_mode = mcb.MCB_BC_MIBC
-    mcb.mcb_destroy(mcb.mcb_create(p3))
+        p3 = mcb.mcb_params(3, 16, 16, 16, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, mode, 0.0)
+        mcb.mcb_destroy(mcb.mcb_create(p3))
     # MRT: D2Q9 only, rates in (0, 2)
     pm = mcb.mcb_params(2, 64, 64, 1, 1.0, -1.0, 1.0, 4.0, 1.0, 0.066, mcb.MCB_F64, 0, 0.0, mcb.MCB_COLL_MRT, 0,
                         *mcb.MRT_RATES_PAPER)

@@ -123,6 +123,40 @@ def test_adjoint_3d_matches_dual_numbers(mcb, nsteps, k, grav, kind):
     lat.close()
 
 
+@pytest.mark.parametrize("mode", ["ibc", "mibc", "hbbc"])
+def test_adjoint_3d_schemes_match_dual_numbers(mcb, mode):
+    """D3Q19 with the comparison schemes (IBC: no eq. 18): the gradient against the oracle's dual
+    numbers run with the same scheme (1e-8)."""
+    banner(f"adjoint vs oracle duals, D3Q19 16x14x12, {mode}, 12 steps")
+    dims = (16, 14, 12)
+    shapes = np.array([W.band_y(-0.5, 2.6, 0), W.ball((8.3, 2.6, 5.7), 2.9, 0)], np.int64)
+    rho0 = W.drop_field(dims, 3, [((8.0, 7.5, 6.0), 4.0)], RV, RL, 2.0)
+    prm = LOSSES[0][1]
+    P = oracle.make_params(3, *dims, tau=0.8, T=0.7 * TC)
+    solid = oracle.classify(P, shapes)
+    node, d, cls, q = oracle.links(P, shapes, solid)
+    walls = oracle.wall_nodes(P, solid)
+    rng = np.random.default_rng(400 + len(mode))
+    phi = rng.uniform(0.9, 1.1, len(walls))
+    dirs = rng.standard_normal((4, len(walls)))
+    ds = oracle.DualSim(P, solid, node, d, q)
+    ds.set_bc_mode({"ibc": 1, "mibc": 2, "hbbc": 3}[mode])
+    ds.set_phi(phi, dirs)
+    ds.init_eq(rho0)
+    ds.step(12)
+    L_o, dL_o = ds.loss(0, prm)
+    lat = mcb.Lattice(3, dims, 0.8, 0.7 * TC, bc_mode=mode)
+    lat.set_geometry(shapes)
+    lat.set_wettability(phi)
+    L_g = lat.adj_forward(rho0, 12, 5, 0, prm)
+    assert abs(L_g - L_o) <= 1e-12 * max(1.0, abs(L_o)), (L_g, L_o)
+    dL_g = dirs @ lat.adj_backward(1.0)
+    scale = max(np.abs(dL_o).max(), 1e-300)
+    assert np.abs(dL_o).max() > 0.0
+    assert np.abs(dL_g - dL_o).max() <= 1e-8 * scale + 1e-14, (dL_g, dL_o)
+    lat.close()
+
+
 CONFIGS = [("mrt", dict(collision="mrt"), {}), ("gravity", dict(gravity=(2e-5, -4e-5)), {}),
            ("mibc", dict(bc_mode="mibc"), {}), ("ibc", dict(bc_mode="ibc"), {}), ("hbbc", dict(bc_mode="hbbc"), {}),
            ("mrt-gravity-mibc", dict(collision="mrt", gravity=(0.0, -3e-5), bc_mode="mibc"), {})]
