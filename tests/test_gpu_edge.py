@@ -82,6 +82,12 @@ def run_pair(mcb, dim, dims, shapes, seed, steps=10):
     M = lat.mass().M
     assert abs(M - sim.mass()) <= 1e-12 * abs(M0)
     assert abs(M - M0) <= 1e-12 * abs(M0)  # eq. 18 (or no wall at all) keeps the mass
+    # the largest speed (the one-pass kernel's strip wraps through a small box several times)
+    _, v, _ = sim.moments()
+    sp = np.sqrt((v ** 2).sum(0))
+    sp[~fluid] = -1.0
+    vg, ng = lat.max_speed()
+    assert abs(vg - sp.max()) <= 1e-12 * sp.max() and ng == int(np.argmax(sp)), (vg, sp.max(), ng, int(np.argmax(sp)))
     lat.close()
     return nl, nw
 
