@@ -288,7 +288,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("k_cp_rho + 2 k_cp_layer + k_cp_mu + k_cp_step (one step)" if args.model == "chempot"
+            "kernel": ("k_cp_march (one step)" if args.model == "chempot"
                        else "k_step2d" if wl.dim == 2 else "k_rho3d + k_step3d (one step)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -754,9 +754,19 @@ mcb_status mcb_timing_report(mcb_ctx* c, double* ms, int64_t* launches) {
     return MCB_OK;
 }
 
+// chemical-potential model: the velocity output takes the force from the density and chemical-
+// potential fields of the collision that made the current state; the step keeps them on chip, so
+// they are formed here again from the populations that collision took (the other buffer of the
+// pair, and its records), which no step has overwritten since
+static hipError_t cp_fields_for_output(mcb_ctx* c) {
+    if (c->p.model != MCB_MODEL_CHEMPOT) return hipSuccess;
+    return cp_fields(c, fnext(c), rnext(c), c->t > 0);
+}
+
 mcb_status mcb_moments(mcb_ctx* c, double* rho, double* v) {
     if (!c) return MCB_EINVAL;
     if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
+    HIPCHK(cp_fields_for_output(c));
     HIPCHK(moments_out(c, fcur(c), rho, v));
     return check_flags(c, nullptr);
 }
@@ -764,6 +774,7 @@ mcb_status mcb_moments(mcb_ctx* c, double* rho, double* v) {
 mcb_status mcb_max_speed(mcb_ctx* c, double* vmax, int64_t* node) {
     if (!c) return MCB_EINVAL;
     if (c->stage < 5) return fail(c, MCB_ESTATE, "no state");
+    HIPCHK(cp_fields_for_output(c));
     HIPCHK(max_speed(c, fcur(c)));
     double r[2];
     HIPCHK(hipMemcpyAsync(r, reinterpret_cast<double*>(c->lat + c->L.result) + MON_SPEED, sizeof r, hipMemcpyDeviceToHost,

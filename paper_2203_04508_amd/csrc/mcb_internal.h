@@ -23,9 +23,10 @@ constexpr int Q3_LINKS = 20;              // 3-D: and two unused ones, so every 
 // Boundary record of a boundary-fluid node, written by its collision and read by the pull of the
 // next step: the terms of its exact-difference forcing (rho, du = F / rho, s = 2u + du and
 // duu = 1.5 du.s, from which F_j of eq. 13 follows per direction), its post-collision populations
-// 1 .. Q-1 as stored, one slot (2-D: population 0 as stored; 3-D: the sum of the node's own
-// populations on its links, which the 3-D density pass adds), and the eq. 18 correction that the
-// pull of that step applied.  The pull loads only the leading RF + Q - 1 values (a loaded value
+// 1 .. Q-1 as stored, one slot (the sum of the node's own populations on its links, which the
+// density of the next step adds: the 3-D density pass and the chemical-potential march; the 2-D
+// step of the pseudopotential model keeps population 0 as stored there, which nothing reads), and
+// the eq. 18 correction that the pull of that step applied.  The pull loads only the leading RF + Q - 1 values (a loaded value
 // that is never used frees its register while the load is in flight, and the next write to it
 // must wait for the load).
 constexpr int REC2 = 16;                  // 6 + 8 + 1 + 1
@@ -189,6 +190,9 @@ hipError_t max_speed(mcb_ctx* c, const void* fcur);  // result slots MON_SPEED, 
 // track_dm: adds the eq. 18 total held in the records rcur (the step that wrote them) to the FP64
 // sum at L.dm[DM_BLOCKS] (per-workgroup partials first, then one workgroup in a fixed order)
 hipError_t dm_accumulate(mcb_ctx* c, const void* rcur);
+// chemical-potential model: the density and chemical-potential fields of the collision that made
+// the current state, from the populations fpre it collided (pulled with the records rpre when pull)
+hipError_t cp_fields(mcb_ctx* c, const void* fpre, const void* rpre, bool pull);
 hipError_t convert_plane_in(mcb_ctx* c, const double* src, void* dst_plane, int dir);
 hipError_t convert_plane_out(mcb_ctx* c, const void* src_plane, double* dst, int dir);
 

@@ -558,8 +558,10 @@ hipError_t launch_step2d(mcb_ctx* c, const void* fcur, const void* rcur, void* f
 // ---------------------------------------------------------------- chemical-potential model (2-D)
 // The paper's multiphase model (Secs. 2.2-2.3): the force needs the density and the chemical
 // potential two nodes away on each axis, and the chemical potential itself the density two nodes
-// away, so a step runs as passes over the lattice: density (pull + eqs. 16-18), the two solid
-// layers of eq. 15, the chemical potential (eq. 12), then pull + force (eq. 9) + collision.
+// away.  A step runs as one march (k_cp_march below) that keeps the fields of a few rows in LDS.
+// The pass kernels that follow compute the same fields over the whole lattice, one stage each
+// (density with eqs. 16-18, the two solid layers of eq. 15, the chemical potential of eq. 12), for
+// the velocity output, which needs them at every node.
 template <class S, class C>
 struct ArgsCP {
     Args2<S, C> a;
@@ -570,6 +572,45 @@ struct ArgsCP {
     C k2, kappa;            // eq. 12: k^2 and kappa
     C RT, b, c_log, aal;    // eq. 11: R T, b, a alpha / (2 sqrt 2 b), a alpha
 };
+
+// the populations pulled into node (cx, cy) (PULL; otherwise its own stored ones)
+template <class S, class C, bool PULL>
+__device__ __forceinline__ void pull_pops(const Args2<S, C>& a, int64_t N, int cx, int cy, C (&f)[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int sx = PULL ? wrap1(cx - kEx[i], a.nx) : cx, sy = PULL ? wrap1(cy - kEy[i], a.ny) : cy;
+        f[i] = ldp<S, C>(a.fa, i, N, int64_t(sy) * a.nx + sx);
+    }
+}
+
+// eqs. 16-18 on pulled populations f of a node with tag tg; ds = the eq. 18 correction
+template <class S, class C, bool PULL>
+__device__ __forceinline__ void pull_links(const Args2<S, C>& a, int tg, C (&f)[9], C& ds, C& res) {
+    ds = C(0);
+    res = C(0);
+    if (PULL) {
+        const bool bnd = tg > 0;
+        if (__any(bnd)) {
+            C rec[RF2 + 8], ca[Q2_LINKS];
+            const int64_t bi = bnd ? int64_t(tg >> 8) : 0;
+#pragma unroll
+            for (int k = 0; k < RF2 + 8; ++k) rec[k] = bnd ? a.rin[bi * REC2 + k] : C(0);
+#pragma unroll
+            for (int k = 0; k < Q2_LINKS; ++k) ca[k] = bnd ? a.la[bi * Q2_LINKS + k] : C(NO_LINK);
+            ds = apply_links<S, C>(bnd, rec, ca, f, a.kF, a.k18, res);
+        }
+    }
+}
+
+// eqs. 16-18 from a boundary record and link coefficients loaded beforehand (lanes that are not
+// boundary nodes ignore theirs)
+template <class S, class C, bool PULL>
+__device__ __forceinline__ void links_from(const Args2<S, C>& a, int tg, C (&f)[9], const C (&rec)[RF2 + 8],
+                                           const C (&ca)[Q2_LINKS], C& ds, C& res) {
+    ds = C(0);
+    res = C(0);
+    if (PULL && __any(tg > 0)) ds = apply_links<S, C>(tg > 0, rec, ca, f, a.kF, a.k18, res);
+}
 
 // pulled populations of node (cx, cy) (PULL; otherwise its own stored ones), with eqs. 16-18 at
 // boundary nodes; ds = the eq. 18 correction.  Solid nodes hold zeros, which the links replace.
@@ -641,21 +682,6 @@ __global__ __launch_bounds__(256) void k_cp_layer(ArgsCP<S, C> p, const int32_t*
         }
         p.rho[x] = num / den;
     }
-}
-
-// 32-bit element offsets of the periodic cross stencil around (cx, cy): rows cy - 2 .. cy + 2 (times
-// nx) and columns cx - 2 .. cx + 2 (N < 2^31)
-struct Cross {
-    uint32_t row[5], col[5];
-};
-__device__ __forceinline__ Cross cross_of(int cx, int cy, int nx, int ny) {
-    Cross k;
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-        k.row[d] = uint32_t(wrap1(cy + d - 2, ny)) * uint32_t(nx);
-        k.col[d] = uint32_t(wrap1(cx + d - 2, nx));
-    }
-    return k;
 }
 
 // fourth-order central differences along an axis from the values at offsets -2 .. +2
@@ -752,55 +778,290 @@ __global__ __launch_bounds__(256) void k_cp_mu_solid(int nx, int ny, const int8_
     }
 }
 
-// pull, eq. 9 force from the fields, collision, store (solid nodes store zeros), boundary record
-template <class S, class C, bool PULL, bool MRT>
-__global__ __launch_bounds__(256) void k_cp_step(ArgsCP<S, C> p) {
+// ---------------------------------------------------------------- chemical-potential step in one march
+// The collision of a node needs mu and rho two nodes away on each axis (eq. 9), mu of a fluid node
+// rho two nodes away (eq. 12), the second solid layer's density the first layer's around it, and
+// the first layer's the fluid densities around it (eq. 15): densities up to six nodes away.  A
+// workgroup marches a strip of W lanes -- OUT output columns on lanes 0 .. OUT - 1 (whole cache
+// lines), HC = (W - OUT) / 2 halo columns on either side -- up a segment of H rows.  LDS rings are
+// indexed by the strip position p = column - (x0 - HC).  Iteration k, row r = y0 - 6 + k:
+//   1  the density of row r from its pulled populations, with the node's solid layer and tag,
+//      into rings.  Where eq. 18 applies, the links' f_in and the correction cancel in the sum
+//      (f_in enters once and is subtracted once from f_0), leaving the node's own post-collision
+//      populations on its links, whose sum its record holds; without eq. 18 (IBC) eqs. 16-17 run;
+//   2  the first solid layer's density in row r - 1 (eq. 15: mean over the fluid neighbours);
+//   3  the second layer's in row r - 2 (mean over the first-layer neighbours);
+//   4  mu of row r - 4: eq. 12 on fluid nodes, the assigned values on the solid layers;
+//   5  the collision of row r - 6: its populations pulled again with its boundary record and link
+//      coefficients (issued one iteration earlier; the population lines were read six rows
+//      earlier, so they come from the cache), eqs. 16-18, the eq. 9 force from the rings, the
+//      collision, the store and the boundary record.
+// Each phase narrows the columns it can serve by its stencil (1, 1, 2, 2): HC >= 6 covers it.  The
+// per-node arithmetic and its order are those of the pass kernels above, which still produce the
+// fields for the velocity output (cp_fields).
+//
+// Every load runs one iteration ahead of its use, and every iteration issues the same loads and
+// stores in the same order: through buffer resources, a lane with nothing to load or store gets
+// the offset OOB (a load reads zeros, a store is dropped), the rows past the segment are loaded
+// all the same, and the collision rows before the first store at OOB.  The compiler counts the
+// memory operations in flight in issue order; one that only some paths issue makes it wait, where
+// the paths join, for every operation issued since, the prefetches of the next rows included.
+// For the same reason the loop body ends with phase 1 of the next row, and the first row's
+// phase 1 runs before the loop with every load it made waited for.
+constexpr int CP_RING = 16, CP_MRING = 8;
+
+template <class S, class C, int W, int OUT, bool PULL, bool MRT>
+__global__ __launch_bounds__(W) void k_cp_march(ArgsCP<S, C> p) {
+    constexpr int HC = (W - OUT) / 2;
+    static_assert(HC >= 6, "six halo columns on either side");
+    constexpr uint32_t s = sizeof(S), sc = sizeof(C), P0 = kMixed<S> ? 1 : 0;
     const Args2<S, C>& a = p.a;
     const int nx = a.nx, ny = a.ny;
-    const int64_t N = int64_t(nx) * ny;
-    const int cx = blockIdx.x * 256 + threadIdx.x, cy = blockIdx.y;
-    if (cx >= nx) return;
-    {
-        const int64_t x = int64_t(cy) * nx + cx;
-        // the field stencils first, so that their loads are in flight with the pull
-        const Cross k = cross_of(cx, cy, nx, ny);
-        auto at = [&](const C* v, int dx, int dy) { return v[k.row[dy + 2] + k.col[dx + 2]]; };
-        const C r = p.rho[x];
-        const C mxm2 = at(p.mu, -2, 0), mxm1 = at(p.mu, -1, 0), mxp1 = at(p.mu, 1, 0), mxp2 = at(p.mu, 2, 0);
-        const C mym2 = at(p.mu, 0, -2), mym1 = at(p.mu, 0, -1), myp1 = at(p.mu, 0, 1), myp2 = at(p.mu, 0, 2);
-        const C rxm2 = at(p.rho, -2, 0), rxm1 = at(p.rho, -1, 0), rxp1 = at(p.rho, 1, 0), rxp2 = at(p.rho, 2, 0);
-        const C rym2 = at(p.rho, 0, -2), rym1 = at(p.rho, 0, -1), ryp1 = at(p.rho, 0, 1), ryp2 = at(p.rho, 0, 2);
-        C f[9], ds;
-        C res;
-        const int tg = pull_node<S, C, PULL>(a, N, cx, cy, f, ds, res);
-        const bool coll = tg >= 0;
-        MassAcc<S, C> rs = MassAcc<S, C>(res);
+    const uint32_t n = uint32_t(nx) * uint32_t(ny);  // the lattice fits the 32-bit buffer offsets
+    const uint32_t ns = n * s, rows = uint32_t(nx) * s;
+    const int sx = int(blockIdx.x) % a.nsx, sy = int(blockIdx.x) / a.nsx;
+    const int x0 = sx * OUT, y0 = sy * a.H;
+    const int Wv = min(OUT, nx - x0), Hv = min(a.H, ny - y0);
+    const int t = threadIdx.x;
+    const int pp = t < OUT + HC ? t + HC : t - OUT - HC;  // strip position of this lane's column
+    const int cx = wrapm(x0 - HC + pp, nx);
+    const bool out_col = t < Wv;
+    __shared__ C s_rho[CP_RING][W];
+    __shared__ int8_t s_lay[CP_RING][W];
+    __shared__ int s_tag[CP_MRING][W];
+    __shared__ C s_mu[CP_MRING][W];
+    const __amdgpu_buffer_rsrc_t rfa = make_res(a.fa, uint64_t(9 + P0) * ns);
+    const __amdgpu_buffer_rsrc_t rfb = make_res(a.fb, uint64_t(9 + P0) * ns);
+    const __amdgpu_buffer_rsrc_t rtag = make_res(a.tag, uint64_t(n) * 4);
+    const __amdgpu_buffer_rsrc_t rin = make_res(a.rin, uint64_t(a.n_bnodes) * REC2 * sc);
+    const __amdgpu_buffer_rsrc_t rout = make_res(a.rout, uint64_t(a.n_bnodes) * REC2 * sc);
+    const __amdgpu_buffer_rsrc_t rla = make_res(a.la, uint64_t(a.n_bnodes) * Q2_LINKS * sc);
+    const __amdgpu_buffer_rsrc_t rmu = make_res(p.mu, uint64_t(n) * sc);
+    const uint32_t xb[3] = {uint32_t(wrap1(cx - 1, nx)) * s, uint32_t(cx) * s, uint32_t(wrap1(cx + 1, nx)) * s};
+    const C s2 = C(1.4142135623730951);
+    const int iters = Hv + 12;
+    // the sum of a boundary node's own populations on its links, which the density adds where
+    // eq. 18 applies, sits in its record (the collision below puts it there); its address comes
+    // from the node's tag, so the tags run one row further ahead than the pulls
+    const bool link_sum = PULL && a.k18 != C(0);
+    bool bad = false;
+
+    // the populations arriving at row r of this lane's column (eq. 5), from x - e_i (PULL; otherwise
+    // the node's own)
+    auto pull = [&](int r, C (&f)[9]) {
+        const uint32_t r0 = uint32_t(r) * rows;
+        const uint32_t rowof[3] = {uint32_t(r == ny - 1 ? 0 : r + 1) * rows, r0,
+                                   uint32_t(r == 0 ? ny - 1 : r - 1) * rows};  // upstream row of e_y = -1, 0, +1
 #pragma unroll
-        for (int i = 0; i < 9; ++i) rs += MassAcc<S, C>(f[i]);
-        const C Fx = -r * cd1(mxm2, mxm1, mxp1, mxp2) + cd1(rxm2, rxm1, rxp1, rxp2) / C(3);
-        const C Fy = -r * cd1(mym2, mym1, myp1, myp2) + cd1(rym2, rym1, ryp1, ryp2) / C(3);
-        C out[9];
-        C rho, dux, duy, sx2, sy2, duu15;
-        collide9<S, C, MRT>(a, coll, f, rs, coll ? Fx : C(0), coll ? Fy : C(0), out, rho, dux, duy, sx2, sy2, duu15);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) stp_nt<S, C>(a.fb, i, N, x, coll ? out[i] : C(0));
-        if (coll && tg > 0) {
-            C rv[REC2];
-            rv[0] = rho;
-            rv[1] = dux;
-            rv[2] = duy;
-            rv[3] = sx2;
-            rv[4] = sy2;
-            rv[5] = duu15;
-#pragma unroll
-            for (int i = 1; i < 9; ++i) rv[RF2 + i - 1] = out[i];
-            rv[RF2 + 8] = kMixed<S> ? out[0] : Buf<S>::round(out[0]);
-            rv[RF2 + 9] = ds;
-            C* dst = a.rout + int64_t(tg >> 8) * REC2;
-#pragma unroll
-            for (int k = 0; k < REC2; ++k) dst[k] = rv[k];
+        for (int i = 0; i < 9; ++i) {
+            if (kMixed<S> && i == 0) {
+                f[0] = Buf<float>::ld(rfa, xb[1] * 2u, r0 * 2u);  // FP16 storage: the rest population in FP32
+                continue;
+            }
+            const uint32_t vo = PULL ? xb[1 - kEx[i]] : xb[1];
+            const uint32_t so = uint32_t(i + P0) * ns + (PULL ? rowof[kEy[i] + 1] : r0);
+            f[i] = Buf<S>::ld(rfa, vo, so);
         }
+    };
+    auto tag_at = [&](int r) { return ld_i32(rtag, uint32_t(cx) * 4u, uint32_t(r) * uint32_t(nx) * 4u); };
+    auto lsum_of = [&](int tg) {
+        return Buf<C>::ld(rin, link_sum && tg > 0 ? uint32_t(tg >> 8) * (REC2 * sc) + (RF2 + 8) * sc : OOB);
+    };
+
+    // loads one iteration ahead: the density row's pull, layer and link sum, the tag of the row
+    // after it; the collision row's pull, record and coefficients; the assigned chemical potential
+    // of the next mu row's solid nodes
+    C fD[9], fR[9], recR[RF2 + 8], aR[Q2_LINKS];
+    int tgD, tgA, tgR;
+    int8_t lyD;
+    C slD, muN = C(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fR[i] = C(0);
+#pragma unroll
+    for (int i = 0; i < RF2 + 8; ++i) recR[i] = C(0);
+#pragma unroll
+    for (int i = 0; i < Q2_LINKS; ++i) aR[i] = C(0);
+
+    // ---- 1: the density of row y0 - 6 + j from the loads above, into ring slot j
+    auto density = [&](int j) {
+        MassAcc<S, C> rs;
+        if (!PULL || a.k18 != C(0)) {
+            rs = MassAcc<S, C>(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) rs += MassAcc<S, C>(fD[i]);
+            if (PULL) rs += MassAcc<S, C>(slD);  // zero off the boundary
+        } else {
+            C ds, res;
+            pull_links<S, C, PULL>(a, tgD, fD, ds, res);
+            rs = MassAcc<S, C>(res);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) rs += MassAcc<S, C>(fD[i]);
+        }
+        s_rho[j % CP_RING][pp] = tgD >= 0 ? C(rs) + a.rho_ref : C(0);
+        s_lay[j % CP_RING][pp] = lyD;
+        s_tag[j % CP_MRING][pp] = tgD;
+    };
+    {
+        const int rf = wrapm(y0 - 6, ny);
+        pull(rf, fD);
+        tgD = tag_at(rf);
+        lyD = p.layer[int64_t(rf) * nx + cx];
+        tgA = tag_at(wrapm(y0 - 5, ny));
+        slD = lsum_of(tgD);
+        density(0);
+        asm volatile("" ::"v"(tgA));  // waited for here: nothing from before the loop is in flight in it
     }
+
+    for (int k = 0; k < iters; ++k) {
+        const int r = wrapm(y0 - 6 + k, ny);
+        auto slot = [&](int d) { return (k - d + 16 * CP_RING) % CP_RING; };  // ring slot of row r - d
+        auto mslot = [&](int d) { return (k - d + 16 * CP_MRING) % CP_MRING; };
+        // the next density row r + 1: its pull, layer and link sum; the tag of row r + 2
+        {
+            const int r1 = r == ny - 1 ? 0 : r + 1;
+            pull(r1, fD);
+            lyD = p.layer[int64_t(r1) * nx + cx];
+            tgD = tgA;
+            slD = lsum_of(tgD);
+            tgA = tag_at(r1 == ny - 1 ? 0 : r1 + 1);
+        }
+        __syncthreads();
+        // ---- 2: first solid layer of row r - 1 (eq. 15 over the fluid neighbours)
+        if (k >= 1 && pp >= 1 && pp < W - 1 && s_lay[slot(1)][pp] == 1) {
+            C num = C(0), den = C(0);
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const int sl = slot(1 - kEy[i]);  // row r - 1 + e_y
+                const bool in = s_lay[sl][pp + kEx[i]] == 0;
+                const C v = s_rho[sl][pp + kEx[i]];
+                num += in ? w9<C>(i) * v : C(0);
+                den += in ? w9<C>(i) : C(0);
+            }
+            s_rho[slot(1)][pp] = num / den;
+        }
+        __syncthreads();
+        // ---- 3: second solid layer of row r - 2 (over the first-layer neighbours)
+        if (k >= 3 && pp >= 2 && pp < W - 2 && s_lay[slot(2)][pp] == 2) {
+            C num = C(0), den = C(0);
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const int sl = slot(2 - kEy[i]);
+                const bool in = s_lay[sl][pp + kEx[i]] == 1;
+                const C v = s_rho[sl][pp + kEx[i]];
+                num += in ? w9<C>(i) * v : C(0);
+                den += in ? w9<C>(i) : C(0);
+            }
+            s_rho[slot(2)][pp] = num / den;
+        }
+        __syncthreads();
+        // ---- 4: chemical potential of row r - 4 (eq. 12 with the Peng-Robinson mu of eq. 11 on
+        // fluid nodes; the solid layers keep their assigned values)
+        if (k >= 6 && pp >= 4 && pp < W - 4) {
+            const int lay = s_lay[slot(4)][pp];
+            C m;
+            if (lay == 0) {
+                const C rc = s_rho[slot(4)][pp];
+                const C br = p.b * rc;
+                if (!(rc > C(0)) || !(br < C(1))) bad = true;
+                const C rf = rc > C(0) && br < C(1) ? rc : C(1);  // a harmless stand-in past the domain
+                const C brf = p.b * rf;
+                const C iq = rcp(C(1) - brf);
+                const C m0 = p.RT * log(rf * iq) - p.c_log * log((s2 - C(1) + brf) * rcp(s2 + C(1) - brf)) +
+                             p.RT * iq - p.aal * rf * rcp(C(1) + C(2) * brf - brf * brf);
+                C lap = C(0);
+                lap += cd2(s_rho[slot(4)][pp - 2], s_rho[slot(4)][pp - 1], rc, s_rho[slot(4)][pp + 1], s_rho[slot(4)][pp + 2]);
+                lap += cd2(s_rho[slot(6)][pp], s_rho[slot(5)][pp], rc, s_rho[slot(3)][pp], s_rho[slot(2)][pp]);
+                m = p.k2 * m0 - p.kappa * lap;
+            } else {
+                m = muN;  // loaded where the same test held (below, one iteration earlier)
+            }
+            s_mu[mslot(4)][pp] = m;
+        }
+        // the assigned potential of the solid nodes of row r - 3 (their layers are in the ring); a
+        // lane at OOB may read any word, which the test above never takes
+        {
+            const bool want = k + 1 >= 6 && pp >= 4 && pp < W - 4 && s_lay[slot(3)][pp] != 0;
+            muN = Buf<C>::ld(rmu, want ? uint32_t(cx) * sc : OOB, uint32_t(wrapm(r - 3, ny)) * uint32_t(nx) * sc);
+        }
+        __syncthreads();
+        // ---- 5: collision of row r - 6 (pulled again, issued one iteration earlier)
+        {
+            C out[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) out[i] = C(0);
+            C rv[REC2];
+#pragma unroll
+            for (int i = 0; i < REC2; ++i) rv[i] = C(0);
+            uint32_t xst = OOB, ro = OOB;
+            if (k >= 12) {
+                const int rc6 = wrapm(r - 6, ny);
+                auto R = [&](int dx, int dy) { return s_rho[slot(6 - dy)][pp + dx]; };
+                auto U = [&](int dx, int dy) { return s_mu[mslot(6 - dy)][pp + dx]; };
+                C ds, res;
+                const int tg = tgR;
+                C f[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[i] = fR[i];
+                links_from<S, C, PULL>(a, tg, f, recR, aR, ds, res);
+                const bool coll = out_col && tg >= 0;
+                MassAcc<S, C> rs = MassAcc<S, C>(res);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) rs += MassAcc<S, C>(f[i]);
+                C Fx = C(0), Fy = C(0);
+                if (out_col) {
+                    const C rr = R(0, 0);
+                    Fx = -rr * cd1(U(-2, 0), U(-1, 0), U(1, 0), U(2, 0)) + cd1(R(-2, 0), R(-1, 0), R(1, 0), R(2, 0)) / C(3);
+                    Fy = -rr * cd1(U(0, -2), U(0, -1), U(0, 1), U(0, 2)) + cd1(R(0, -2), R(0, -1), R(0, 1), R(0, 2)) / C(3);
+                }
+                C o[9];
+                C rho, dux, duy, sx2, sy2, duu15;
+                collide9<S, C, MRT>(a, coll, f, rs, coll ? Fx : C(0), coll ? Fy : C(0), o, rho, dux, duy, sx2, sy2, duu15);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) out[i] = coll ? o[i] : C(0);
+                xst = out_col ? uint32_t(rc6) * rows + xb[1] : OOB;
+                ro = coll && tg > 0 ? uint32_t(tg >> 8) * (REC2 * sc) : OOB;
+                rv[0] = rho;
+                rv[1] = dux;
+                rv[2] = duy;
+                rv[3] = sx2;
+                rv[4] = sy2;
+                rv[5] = duu15;
+#pragma unroll
+                for (int i = 1; i < 9; ++i) rv[RF2 + i - 1] = out[i];
+                // the populations on the node's links (tag bits 0 .. 7), summed in the order the
+                // density of the next step would sum them from the slots above
+                C sl = C(0);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) sl += ((tg >> j) & 1) ? out[j + 1] : C(0);
+                rv[RF2 + 8] = sl;
+                rv[RF2 + 9] = ds;
+            }
+            // every output column stores, solid nodes included (zeros)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                if (kMixed<S> && i == 0)
+                    Buf<float>::st_nt(rfb, xst == OOB ? OOB : xst * 2u, out[0]);
+                else
+                    Buf<S>::st_nt(rfb, sat_add(xst, uint32_t(i + P0) * ns), out[i]);
+            }
+            st_vec(rout, ro, rv);
+        }
+        // the collision row of the next iteration, r - 5: its tag from the ring (row r - 5 was the
+        // density row five iterations ago; before the first collision row the slot may hold what
+        // nothing wrote, so the tag is taken as solid there), its pull, record and coefficients
+        {
+            tgR = k + 1 >= 12 ? s_tag[(k + 3) % CP_MRING][pp] : -1;
+            pull(wrapm(r - 5, ny), fR);
+            if (PULL) {
+                const bool bnd = tgR > 0;
+                const uint32_t bo = uint32_t(tgR >> 8);
+                ld_vec(rin, bnd ? bo * (REC2 * sc) : OOB, recR);
+                ld_vec(rla, bnd ? bo * (Q2_LINKS * sc) : OOB, aR);
+            }
+        }
+        density(k + 1);  // row r + 1 (the last iteration's is never read)
+    }
+    if (bad) atomicOr(&a.flags[FLAG_DOMAIN], 1);
 }
 
 inline unsigned cp_grid(int64_t n) {
@@ -810,8 +1071,9 @@ inline unsigned cp_grid(int64_t n) {
 }
 
 
+// the arguments of the chemical-potential kernels for one step from fcur / rcur to fnext / rnext
 template <class S, class C>
-hipError_t launch_cp(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
+ArgsCP<S, C> cp_args(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext) {
     ArgsCP<S, C> p;
     Args2<S, C>& a = p.a;
     a.fa = static_cast<const S*>(fcur);
@@ -852,6 +1114,15 @@ hipError_t launch_cp(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext
     p.b = C(c->p.eos_b);
     p.c_log = C(aal / (2.0 * std::sqrt(2.0) * c->p.eos_b));
     p.aal = C(aal);
+    return p;
+}
+
+// The density and chemical-potential fields of a collision from the populations fpre (pulled with
+// eqs. 16-18 from the records rpre when pull) into the context's field buffers: the pass kernels.
+// The march keeps the fields in LDS; the velocity output asks for them through cp_fields.
+template <class S, class C>
+hipError_t cp_fields_t(mcb_ctx* c, const void* fpre, const void* rpre, bool pull) {
+    ArgsCP<S, C> p = cp_args<S, C>(c, fpre, rpre, nullptr, nullptr);
     const dim3 grid(unsigned((c->p.nx + 255) / 256), unsigned(c->p.ny)), blk(256);
     if (pull)
         hipLaunchKernelGGL((k_cp_rho<S, C, true>), grid, blk, 0, c->stream, p);
@@ -865,19 +1136,55 @@ hipError_t launch_cp(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext
                            reinterpret_cast<const int32_t*>(c->lat + c->L.cp_l2), c->n_l2, 2);
     hipLaunchKernelGGL((k_cp_mu<S, C>), dim3(grid.x, unsigned((c->p.ny + CP_MU_ROWS - 1) / CP_MU_ROWS)), blk, 0,
                        c->stream, p);
-    const bool mrt = c->p.collision == MCB_COLL_MRT;
-    if (pull && mrt)
-        hipLaunchKernelGGL((k_cp_step<S, C, true, true>), grid, blk, 0, c->stream, p);
-    else if (pull)
-        hipLaunchKernelGGL((k_cp_step<S, C, true, false>), grid, blk, 0, c->stream, p);
-    else if (mrt)
-        hipLaunchKernelGGL((k_cp_step<S, C, false, true>), grid, blk, 0, c->stream, p);
-    else
-        hipLaunchKernelGGL((k_cp_step<S, C, false, false>), grid, blk, 0, c->stream, p);
     return hipGetLastError();
 }
 
+template <class S, class C, int W, int OUT>
+hipError_t launch_cp_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
+    ArgsCP<S, C> p = cp_args<S, C>(c, fcur, rcur, fnext, rnext);
+    Args2<S, C>& a = p.a;
+    const bool mrt = c->p.collision == MCB_COLL_MRT;
+    a.nsx = (a.nx + OUT - 1) / OUT;
+    // segment height: the whole grid resident at once (the twelve halo rows of a segment are then
+    // spread over as few segments as the device allows), at least 32 rows
+    int* occ = c->occ;  // slots 0, 1 (the pseudopotential step's; a context runs one model)
+    const int cap = mrt ? resident_blocks(c, k_cp_march<S, C, W, OUT, true, true>, W, &occ[1])
+                        : resident_blocks(c, k_cp_march<S, C, W, OUT, true, false>, W, &occ[0]);
+    const int per = cap / a.nsx > 0 ? cap / a.nsx : 1;
+    int H = (a.ny + per - 1) / per;
+    if (H < 32) H = 32;
+    a.H = H;
+    a.nblocks = a.nsx * ((a.ny + H - 1) / H);
+    const dim3 grid(unsigned(a.nblocks)), blk(W);
+    if (pull && mrt)
+        hipLaunchKernelGGL((k_cp_march<S, C, W, OUT, true, true>), grid, blk, 0, c->stream, p);
+    else if (pull)
+        hipLaunchKernelGGL((k_cp_march<S, C, W, OUT, true, false>), grid, blk, 0, c->stream, p);
+    else if (mrt)
+        hipLaunchKernelGGL((k_cp_march<S, C, W, OUT, false, true>), grid, blk, 0, c->stream, p);
+    else
+        hipLaunchKernelGGL((k_cp_march<S, C, W, OUT, false, false>), grid, blk, 0, c->stream, p);
+    return hipGetLastError();
+}
+
+template <class S, class C>
+hipError_t launch_cp(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext, void* rnext, bool pull) {
+    // as for the pseudopotential step: one-wave strips keep small lattices busy, large lattices take
+    // strips of whole cache lines (224 FP32 / FP64 columns, 192 FP16) with 16 halo columns a side
+    if (c->g.N <= (int64_t(1) << 21)) return launch_cp_w<S, C, 64, 52>(c, fcur, rcur, fnext, rnext, pull);
+    if (sizeof(S) == 2) return launch_cp_w<S, C, 256, 192>(c, fcur, rcur, fnext, rnext, pull);
+    return launch_cp_w<S, C, 256, 224>(c, fcur, rcur, fnext, rnext, pull);
+}
+
 }  // namespace
+
+hipError_t cp_fields(mcb_ctx* c, const void* fpre, const void* rpre, bool pull) {
+    switch (c->p.precision) {
+        case MCB_F64: return cp_fields_t<double, double>(c, fpre, rpre, pull);
+        case MCB_F32S: return cp_fields_t<float, float>(c, fpre, rpre, pull);
+        default: return cp_fields_t<__half, float>(c, fpre, rpre, pull);
+    }
+}
 
 hipError_t cp_wall_mu(mcb_ctx* c) {
     if (c->p.model != MCB_MODEL_CHEMPOT) return hipSuccess;
