@@ -253,8 +253,9 @@ def main():
     # measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), used only
     # when they were taken on the kernel as it is now
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{wl.name}_{args.precision}.json")
-    measured_cfg = args.model == "pseudo" and args.collision == "bgk" and args.bc_mode == "present" and not any(grav)
+    from paper_2203_04508_amd.traffic import out_name
+    tfile = os.path.join(ROOT, "profiles", out_name(wl.name, args.precision, args.model, args.collision) + ".json")
+    measured_cfg = args.bc_mode == "present" and not any(grav)
     if os.path.exists(tfile) and measured_cfg:  # the counters were taken on this configuration only
         tj = json.load(open(tfile))
         if tj.get("kernel_digest") == kernel_digest(wl.dim):

@@ -5,7 +5,9 @@ Two phases:
 ``python -m paper_2203_04508_amd.traffic run --workload c2 --precision f32s --steps 5``
     sets up the workload, runs a few steps, then copies a 1 GiB torch tensor (a plain device copy
     of known size: 1 GiB read, 1 GiB written).  Run it under rocprofv3 once with
-    ``--pmc FETCH_SIZE`` and once with ``--pmc WRITE_SIZE``.
+    ``--pmc FETCH_SIZE`` and once with ``--pmc WRITE_SIZE``.  ``--model chempot --collision mrt``
+    takes the chemical-potential step of the same geometry instead (Peng-Robinson at 0.8 T_c, the
+    balls four nodes apart, as the benchmark runs it).
 
 ``python -m paper_2203_04508_amd.traffic summarize --fetch-db A.db --write-db B.db --workload c2 --precision f32s``
     reads both databases, scales each counter of the step kernel by (known copy bytes / what the
@@ -35,18 +37,36 @@ def kernel_digest(dim: int) -> str:
     return h.hexdigest()[:16]
 
 
+def out_name(workload, precision, model="pseudo", collision="bgk"):
+    """profiles/ base name of a measured configuration (the pseudopotential one with BGK keeps the
+    short name)."""
+    tail = "" if model == "pseudo" and collision == "bgk" else f"_{model}_{collision}"
+    return f"traffic_{workload}_{precision}{tail}"
+
+
 def run(args):
     import torch
 
     sys.path.insert(0, ROOT)
     from paper_2203_04508_amd import mcb, workloads as W
 
-    wl = W.make(args.workload)
-    rr = wl.rho_v if args.precision != "f64" else 0.0
-    lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=args.precision, rho_ref=rr)
-    lat.set_geometry(wl.shapes)
-    lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
-    lat.init_equilibrium(wl.rho0())
+    if args.model == "chempot":
+        wl = W.make(args.workload, min_gap=W.CP_MIN_GAP)
+        rr = W.PR_MAXWELL[0.80][0] if args.precision != "f64" else 0.0
+        lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, 0.8 * W.PR_TC, precision=args.precision, rho_ref=rr,
+                          collision=args.collision, model="chempot", cp_k=W.CP_K, cp_kappa=W.CP_KAPPA)
+        lat.set_geometry(wl.shapes)
+        rho0, mu_s, _ = W.chempot_inputs(wl, lat.wall_nodes())
+        lat.set_wettability(mu_s)
+        lat.init_equilibrium(rho0)
+    else:
+        wl = W.make(args.workload)
+        rr = wl.rho_v if args.precision != "f64" else 0.0
+        lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=args.precision, rho_ref=rr,
+                          collision=args.collision)
+        lat.set_geometry(wl.shapes)
+        lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
+        lat.init_equilibrium(wl.rho0())
     lat.step(args.steps)
     torch.cuda.synchronize()
     x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -78,8 +98,9 @@ def _largest(rows, match):
 
 def _pull_kernel(name):
     """The per-step kernels of the pulling step (not the collision that starts a run), by name:
-    k_step2d<S, C, W, OUT, PULL>, k_step3d<S, C, PULL, PF>, k_rho3d<S, C, PULL>."""
-    for k, idx in (("k_step2d<", 4), ("k_step3d<", 2), ("k_rho3d<", 2)):
+    k_step2d<S, C, W, OUT, PULL>, k_step3d<S, C, PULL, PF>, k_rho3d<S, C, PULL>,
+    k_cp_march<S, C, W, OUT, PULL>."""
+    for k, idx in (("k_step2d<", 4), ("k_step3d<", 2), ("k_rho3d<", 2), ("k_cp_march<", 4)):
         if k in name:
             args = name.split(k, 1)[1].split(">", 1)[0].split(",")
             return len(args) > idx and args[idx].strip() == "true"
@@ -87,7 +108,7 @@ def _pull_kernel(name):
 
 
 def _short(name):
-    for k in ("k_step2d", "k_step3d", "k_rho3d"):
+    for k in ("k_step2d", "k_step3d", "k_rho3d", "k_cp_march"):
         if k in name:
             return k
     return name
@@ -97,7 +118,8 @@ def summarize(args):
     sys.path.insert(0, ROOT)
     from paper_2203_04508_amd import workloads as W
 
-    out = {"workload": args.workload, "precision": args.precision, "copy_bytes": COPY_BYTES,
+    out = {"workload": args.workload, "precision": args.precision, "model": args.model,
+           "collision": args.collision, "copy_bytes": COPY_BYTES,
            "kernel_digest": kernel_digest(W.make(args.workload).dim), "kernels": {}}
     lines = []
     # the device copy of COPY_BYTES is the largest copy dispatch of the run
@@ -122,15 +144,15 @@ def summarize(args):
         kk["bytes_per_launch"] = kk.get("read_bytes_per_launch", 0.0) + kk.get("write_bytes_per_launch", 0.0)
         step += kk["bytes_per_launch"]
     # the step kernel proper (the collision pass in three dimensions) is the one bench.py reports
-    main = out["kernels"].get("k_step2d") or out["kernels"].get("k_step3d")
+    main = out["kernels"].get("k_step2d") or out["kernels"].get("k_step3d") or out["kernels"].get("k_cp_march")
     out["bytes_per_launch"] = main["bytes_per_launch"] if main else None
     out["bytes_per_step"] = step
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    base = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{args.precision}")
+    base = os.path.join(ROOT, "profiles", out_name(args.workload, args.precision, args.model, args.collision))
     json.dump(out, open(base + ".json", "w"), indent=1)
     with open(base + ".txt", "w") as fh:
-        fh.write(f"HBM traffic of the step kernels, workload {args.workload}, storage {args.precision} "
-                 f"(kernel sources {out['kernel_digest']})\n")
+        fh.write(f"HBM traffic of the step kernels, workload {args.workload}, storage {args.precision}, "
+                 f"{args.model} model, {args.collision} (kernel sources {out['kernel_digest']})\n")
         fh.write(f"commands: {args.commands}\n" if args.commands else "")
         fh.write("\n".join(lines) + "\n")
         for k, kk in out["kernels"].items():
@@ -152,6 +174,9 @@ def main():
     s.add_argument("--workload", default="c2")
     s.add_argument("--precision", default="f32s")
     s.add_argument("--commands", default="")
+    for q in (r, s):
+        q.add_argument("--model", default="pseudo", choices=("pseudo", "chempot"))
+        q.add_argument("--collision", default="bgk", choices=("bgk", "mrt"))
     a = ap.parse_args()
     run(a) if a.cmd == "run" else summarize(a)
 

@@ -394,6 +394,6 @@ def test_wettability_loss_autograd(mcb):
     lat.set_wettability(phi.detach().numpy())
     ref = lat.adj_forward(rho0, 40, 9, 0, (RV, 1.0))
     gref = lat.adj_backward(1.0)
-    assert float(loss) == ref
+    assert float(loss.detach()) == ref
     assert np.array_equal(phi.grad.numpy(), gref)
     lat.close()
