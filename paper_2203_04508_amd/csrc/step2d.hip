@@ -989,10 +989,7 @@ __global__ __launch_bounds__(W) void k_cp_march(ArgsCP<S, C> p) {
             C out[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) out[i] = C(0);
-            C rv[REC2];
-#pragma unroll
-            for (int i = 0; i < REC2; ++i) rv[i] = C(0);
-            uint32_t xst = OOB, ro = OOB;
+            uint32_t xst = OOB;
             if (k >= 12) {
                 const int rc6 = wrapm(r - 6, ny);
                 auto R = [&](int dx, int dy) { return s_rho[slot(6 - dy)][pp + dx]; };
@@ -1019,22 +1016,27 @@ __global__ __launch_bounds__(W) void k_cp_march(ArgsCP<S, C> p) {
 #pragma unroll
                 for (int i = 0; i < 9; ++i) out[i] = coll ? o[i] : C(0);
                 xst = out_col ? uint32_t(rc6) * rows + xb[1] : OOB;
-                ro = coll && tg > 0 ? uint32_t(tg >> 8) * (REC2 * sc) : OOB;
-                rv[0] = rho;
-                rv[1] = dux;
-                rv[2] = duy;
-                rv[3] = sx2;
-                rv[4] = sy2;
-                rv[5] = duu15;
+                // the boundary record, by the waves that hold a boundary node (its stores follow
+                // every load that a later wait is for, so they may be skipped)
+                if (__any(coll && tg > 0)) {
+                    C rv[REC2];
+                    rv[0] = rho;
+                    rv[1] = dux;
+                    rv[2] = duy;
+                    rv[3] = sx2;
+                    rv[4] = sy2;
+                    rv[5] = duu15;
 #pragma unroll
-                for (int i = 1; i < 9; ++i) rv[RF2 + i - 1] = out[i];
-                // the populations on the node's links (tag bits 0 .. 7), summed in the order the
-                // density of the next step would sum them from the slots above
-                C sl = C(0);
+                    for (int i = 1; i < 9; ++i) rv[RF2 + i - 1] = out[i];
+                    // the populations on the node's links (tag bits 0 .. 7), summed in the order
+                    // the density of the next step would sum them from the slots above
+                    C sl = C(0);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) sl += ((tg >> j) & 1) ? out[j + 1] : C(0);
-                rv[RF2 + 8] = sl;
-                rv[RF2 + 9] = ds;
+                    for (int j = 0; j < 8; ++j) sl += ((tg >> j) & 1) ? out[j + 1] : C(0);
+                    rv[RF2 + 8] = sl;
+                    rv[RF2 + 9] = ds;
+                    st_vec(rout, coll && tg > 0 ? uint32_t(tg >> 8) * (REC2 * sc) : OOB, rv);
+                }
             }
             // every output column stores, solid nodes included (zeros)
 #pragma unroll
@@ -1044,7 +1046,6 @@ __global__ __launch_bounds__(W) void k_cp_march(ArgsCP<S, C> p) {
                 else
                     Buf<S>::st_nt(rfb, sat_add(xst, uint32_t(i + P0) * ns), out[i]);
             }
-            st_vec(rout, ro, rv);
         }
         // the collision row of the next iteration, r - 5: its tag from the ring (row r - 5 was the
         // density row five iterations ago; before the first collision row the slot may hold what
