@@ -82,7 +82,9 @@ def random_state(rng, rho_field):
 
 CASES = [("300x70-ragged", (300, 70, 1), 61, None, "bgk", "present"),
          ("37x29-random-q", (37, 29, 1), 62, "random", "bgk", "present"),
-         ("300x70-mrt-mibc", (300, 70, 1), 63, None, "mrt", "mibc")]
+         ("300x70-mrt-mibc", (300, 70, 1), 63, None, "mrt", "mibc"),
+         ("300x70-ibc", (300, 70, 1), 66, None, "bgk", "ibc"),
+         ("37x29-mrt-hbbc-random-q", (37, 29, 1), 67, "random", "mrt", "hbbc")]
 
 
 @pytest.mark.parametrize("name,dims,seed,qmode,coll,mode", CASES, ids=[c[0] for c in CASES])
@@ -115,6 +117,33 @@ def test_chempot_step_parity_small(mcb, name, dims, seed, qmode, coll, mode):
     vg, ng = lat.max_speed()
     assert abs(vg - s.max()) <= 1e-10 * s.max()
     lat.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mode", ["ibc", "hbbc"])
+def test_chempot_wide_strip_schemes(mcb, mode):
+    """Above 2^21 nodes the step runs in four-wave strips; there the density row of a boundary node
+    without eq. 18 (IBC) forms each link's f_in itself, and halfway bounce-back puts a = 1 on every
+    link.  FP64, three steps from a drop field on random circles against the oracle, 1e-12 per step."""
+    banner(f"chemical-potential wide-strip parity, {mode}")
+    rng = np.random.default_rng(71 if mode == "ibc" else 72)
+    dims = (1536, 1400, 1)
+    shapes = W.random_links_case(rng, dims, 2, dims[0] * dims[1] // 900, 2.0, 6.0)
+    drops = [((rng.uniform(0, dims[0]), rng.uniform(0, dims[1])), rng.uniform(8, 20)) for _ in range(40)]
+    rho = W.drop_field(dims, 2, drops, RV, RL, 6.0)
+    sim, lat, fluid = build_pair(mcb, dims, 0.8, shapes, MU_COEX * rng.uniform(0.9, 1.1), bc_mode=mode)
+    sim.init_eq(rho)
+    lat.init_equilibrium(rho)
+    assert rel_err(lat.get_f(), sim.get_f(), fluid) < 1e-13
+    for k in range(1, 4):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < 1e-12 * k, (k, e)
+    rep = lat.mass()
+    assert abs(rep.dM_last - sim.dm_last()) < 1e-12 * max(1.0, abs(sim.dm_last()))
+    lat.close()
+    sim.close()
 
 
 def test_chempot_wall_potential_changed_mid_run(mcb):
