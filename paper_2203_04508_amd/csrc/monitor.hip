@@ -363,14 +363,18 @@ __global__ __launch_bounds__(256) void k_speed_final(const double* __restrict__ 
 // (populations and tags; issued one iteration earlier), puts its density and tags in a 3-row LDS
 // ring, computes psi of row r - 1 (eq. 15 at wall nodes, from the ring) into a second ring, and
 // the velocity of row r - 2 from its own momentum and density (kept in registers) and the psi
-// ring.  Each workgroup leaves its largest speed and that node in part.
+// ring.  Each workgroup leaves its largest speed and that node in part.  The loads go through
+// buffer resources and every iteration issues them, the rows past the segment included, and the
+// eq. 15 factor of a wall node is loaded with its row's densities, one iteration before its psi:
+// the compiler counts loads in flight in issue order, so a load that only some iterations issue,
+// or one issued just before its use, makes it wait for the next row's loads as well.
 constexpr int SW = 256, NC = 1, SC = NC * SW, SO = SC - 4;
 
 template <class S, class C>
 __global__ __launch_bounds__(SW) void k_speed2d(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
-                                                double rho_ref, const double* __restrict__ phi, Eos<double> eos, double G,
-                                                double gx, double gy, int Dy, int nbx, int32_t* flags,
-                                                double* __restrict__ part) {
+                                                double rho_ref, const double* __restrict__ phi, uint32_t n_wall,
+                                                Eos<double> eos, double G, double gx, double gy, int Dy, int nbx,
+                                                int32_t* flags, double* __restrict__ part) {
     __shared__ double s_rho[3][SC];
     __shared__ int s_tag[3][SC];
     __shared__ double s_psi[3][SC];
@@ -388,19 +392,31 @@ __global__ __launch_bounds__(SW) void k_speed2d(GridDev g, const S* __restrict__
         out[h] = c >= 2 && c < SO + 2 && xr < g.nx;
     }
     auto rowof = [&](int k) { int r = (y0 - 2 + k) % g.ny; return r < 0 ? r + g.ny : r; };
+    constexpr uint32_t s = sizeof(S), P0 = kMixed<S> ? 1 : 0;
+    const uint32_t n = uint32_t(g.N);  // the lattice fits the 32-bit buffer offsets
+    const __amdgpu_buffer_rsrc_t rf = make_res(f, uint64_t(9 + P0) * n * s);
+    const __amdgpu_buffer_rsrc_t rt = make_res(tag, uint64_t(n) * 4);
+    const __amdgpu_buffer_rsrc_t rp = make_res(phi, uint64_t(n_wall) * 8);
     // loads of the next row in flight
     C fr[NC][9];
     int tgr[NC];
     auto issue = [&](int k) {
-        const int64_t xrow = int64_t(rowof(k)) * g.nx;
+        const uint32_t xrow = uint32_t(rowof(k)) * uint32_t(g.nx);
 #pragma unroll
         for (int h = 0; h < NC; ++h) {
+            const uint32_t x = xrow + uint32_t(xc[h]);
+            tgr[h] = ld_i32(rt, x * 4u);  // first: a copy of it that waits does not wait for the populations
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fr[h][i] = ldp<S, C>(f, i, g.N, xrow + xc[h]);
-            tgr[h] = tag[xrow + xc[h]];
+            for (int i = 0; i < 9; ++i)
+                fr[h][i] = kMixed<S> && i == 0 ? C(Buf<float>::ld(rf, x * 4u))  // FP16 storage: population 0 in FP32
+                                               : C(Buf<S>::ld(rf, x * s, uint32_t(i + P0) * n * s));
         }
     };
     issue(0);
+    // eq. 15 factors of the wall nodes of rows r - 1 and r in the lane's own column, which is the
+    // column whose psi the lane computes (one column per lane)
+    static_assert(NC == 1, "psi of the lane's own column");
+    double phB[NC] = {}, phC[NC] = {};
     double rA[NC] = {}, rB[NC] = {}, rC[NC] = {};   // density of rows r - 2, r - 1, r (own columns)
     int tA[NC], tB[NC], tC[NC];                     // their tags
     double jA[NC][3] = {}, jB[NC][3] = {}, jC[NC][3] = {};  // their momentum
@@ -429,8 +445,10 @@ __global__ __launch_bounds__(SW) void k_speed2d(GridDev g, const S* __restrict__
             node_j<9>(fv, jC[h]);
             s_rho[s0][t + h * SW] = rC[h];
             s_tag[s0][t + h * SW] = tg;
+            phB[h] = phC[h];
+            phC[h] = Buf<double>::ld(rp, tg < -1 ? uint32_t(-tg - 2) * 8u : OOB);
         }
-        if (k + 1 < iters) issue(k + 1);
+        issue(k + 1);  // past the segment: a row nothing uses
         __syncthreads();
         // ---- psi of row r - 1 (its neighbours' densities are in the ring from k >= 2)
         if (k >= 2) {
@@ -453,7 +471,7 @@ __global__ __launch_bounds__(SW) void k_speed2d(GridDev g, const S* __restrict__
                         ty[i] = s_tag[sl][c + c_ex[0][i]];
                         ry[i] = s_rho[sl][c + c_ex[0][i]];
                     }
-                    re = wall_rho<9>(ty, ry, phi[-tg - 2]);
+                    re = wall_rho<9>(ty, ry, phB[h]);  // the lane's own node: c = t (NC = 1)
                 }
                 s_psi[s1][c] = tg == -1 ? 0.0 : psi_of(re, eos, flags);
             }
@@ -555,7 +573,8 @@ hipError_t max_speed_t(mcb_ctx* c, const void* fcur) {
         Eos<double> eos{c->p.eos_R * c->p.eos_T, c->p.eos_a, c->p.eos_b / 4.0, 2.0 / c->p.G};
         hipLaunchKernelGGL((k_speed2d<S, C>), dim3(nbx * nseg), dim3(SW), 0, c->stream, c->g, static_cast<const S*>(fcur),
                            reinterpret_cast<const int32_t*>(c->lat + c->L.tag), rr,
-                           reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos, c->p.G, c->p.gravity[0],
+                           reinterpret_cast<const double*>(c->lk + c->L.wl_phi), uint32_t(c->n_wall > 0 ? c->n_wall : 0),
+                           eos, c->p.G, c->p.gravity[0],
                            c->p.gravity[1], Dy, nbx, reinterpret_cast<int32_t*>(c->lat + c->L.flags), part);
         hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(256), 0, c->stream, part, nbx * nseg,
                            reinterpret_cast<double*>(c->lat + c->L.result) + MON_SPEED);
