@@ -204,14 +204,43 @@ __global__ __launch_bounds__(256) void k_psi_out(GridDev g, const int32_t* __res
     }
 }
 
-template <class S, class C, int Q>
+// largest |v| over the fluid nodes and the smallest node index attaining it; fixed grid and fixed
+// combination order, so the result does not depend on timing
+__device__ inline void speed_pick(double& best, double& at, double b, double i) {
+    if (b > best || (b == best && i >= 0.0 && (at < 0.0 || i < at))) {
+        best = b;
+        at = i;
+    }
+}
+
+__device__ inline void speed_block(double& best, double& at) {
+    for (int d = 32; d >= 1; d >>= 1) speed_pick(best, at, __shfl_xor(best, d, 64), __shfl_xor(at, d, 64));
+    __shared__ double sb[4], sa[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        sb[wv] = best;
+        sa[wv] = at;
+    }
+    __syncthreads();
+    best = sb[0];
+    at = sa[0];
+    for (int w = 1; w < 4; ++w) speed_pick(best, at, sb[w], sa[w]);
+}
+
+// the physical velocity of every node (SPEED = false: into v, zeros on solid nodes), or only the
+// largest speed over the fluid nodes and its node (SPEED = true: one (speed, node) pair per
+// workgroup into part, for k_speed_final; the same arithmetic, so the same value as the largest
+// speed of the stored field, without storing it)
+template <class S, class C, int Q, bool SPEED>
 __global__ __launch_bounds__(256) void k_vel_out(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
                                                  const double* __restrict__ rho, const double* __restrict__ psi, double G,
                                                  double gx, double gy, double gz, double* __restrict__ v) {
     constexpr int L = Q == 9 ? 0 : 1;
+    double best = -1.0, at = -1.0;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
         if (tag[x] < 0) {
-            for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = 0.0;
+            if (!SPEED)
+                for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = 0.0;
             continue;
         }
         double fv[Q], pv[Q];
@@ -225,19 +254,37 @@ __global__ __launch_bounds__(256) void k_vel_out(GridDev g, const S* __restrict_
         node_j<Q>(fv, j);
         const double gk[3] = {gx, gy, gz};
         node_v<Q>(j, pv, psi[x], rho[x], G, gk, g.dim, vv);
-        for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = vv[k];
+        if (SPEED) {
+            double s2 = 0.0;
+            for (int k = 0; k < g.dim; ++k) s2 += vv[k] * vv[k];
+            speed_pick(best, at, sqrt(s2), double(x));
+        } else {
+            for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = vv[k];
+        }
+    }
+    if (SPEED) {
+        speed_block(best, at);
+        if (threadIdx.x == 0) {
+            v[2 * blockIdx.x] = best;
+            v[2 * blockIdx.x + 1] = at;
+        }
     }
 }
 
 // chemical-potential model: v = (j - F / 2) / rho with F = -rho grad mu + grad(rho) / 3 + rho g from
-// the density and chemical-potential fields of the last collision (fourth-order differences)
-template <class S, class C>
-__global__ void k_vel_cp(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag, const double* __restrict__ rho,
-                         const C* __restrict__ fr, const C* __restrict__ fm, double gx, double gy, double* __restrict__ v) {
+// the density and chemical-potential fields of the last collision (fourth-order differences);
+// SPEED as for k_vel_out
+template <class S, class C, bool SPEED>
+__global__ __launch_bounds__(256) void k_vel_cp(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
+                                                const double* __restrict__ rho, const C* __restrict__ fr,
+                                                const C* __restrict__ fm, double gx, double gy, double* __restrict__ v) {
+    double vbest = -1.0, vat = -1.0;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
         if (tag[x] < 0) {
-            v[x] = 0.0;
-            v[g.N + x] = 0.0;
+            if (!SPEED) {
+                v[x] = 0.0;
+                v[g.N + x] = 0.0;
+            }
             continue;
         }
         double jx = 0, jy = 0;
@@ -256,8 +303,23 @@ __global__ void k_vel_cp(GridDev g, const S* __restrict__ f, const int32_t* __re
                           d1(at(fr, -2, 0), at(fr, -1, 0), at(fr, 1, 0), at(fr, 2, 0)) / 3.0 + r * gx;
         const double Fy = -r * d1(at(fm, 0, -2), at(fm, 0, -1), at(fm, 0, 1), at(fm, 0, 2)) +
                           d1(at(fr, 0, -2), at(fr, 0, -1), at(fr, 0, 1), at(fr, 0, 2)) / 3.0 + r * gy;
-        v[x] = (jx - 0.5 * Fx) / rho[x];
-        v[g.N + x] = (jy - 0.5 * Fy) / rho[x];
+        const double vx = (jx - 0.5 * Fx) / rho[x], vy = (jy - 0.5 * Fy) / rho[x];
+        if (SPEED) {
+            double s2 = 0.0;
+            s2 += vx * vx;
+            s2 += vy * vy;
+            speed_pick(vbest, vat, sqrt(s2), double(x));
+        } else {
+            v[x] = vx;
+            v[g.N + x] = vy;
+        }
+    }
+    if (SPEED) {
+        speed_block(vbest, vat);
+        if (threadIdx.x == 0) {
+            v[2 * blockIdx.x] = vbest;
+            v[2 * blockIdx.x + 1] = vat;
+        }
     }
 }
 
@@ -306,45 +368,6 @@ hipError_t monitor_t(mcb_ctx* c, const void* fcur, const void* rcur, double* par
                            static_cast<const S*>(fcur), tag, rr, static_cast<const C*>(rcur), int(c->L.rec_stride), nb, partials);
     hipLaunchKernelGGL(k_mon_final, dim3(1), dim3(256), 0, c->stream, partials, MON_BLOCKS, result);
     return hipGetLastError();
-}
-
-// largest |v| over the fluid nodes and the smallest node index attaining it; fixed grid and fixed
-// combination order, so the result does not depend on timing
-__device__ inline void speed_pick(double& best, double& at, double b, double i) {
-    if (b > best || (b == best && i >= 0.0 && (at < 0.0 || i < at))) {
-        best = b;
-        at = i;
-    }
-}
-
-__device__ inline void speed_block(double& best, double& at) {
-    for (int d = 32; d >= 1; d >>= 1) speed_pick(best, at, __shfl_xor(best, d, 64), __shfl_xor(at, d, 64));
-    __shared__ double sb[4], sa[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) {
-        sb[wv] = best;
-        sa[wv] = at;
-    }
-    __syncthreads();
-    best = sb[0];
-    at = sa[0];
-    for (int w = 1; w < 4; ++w) speed_pick(best, at, sb[w], sa[w]);
-}
-
-__global__ __launch_bounds__(256) void k_speed_partial(GridDev g, const int32_t* __restrict__ tag, const double* __restrict__ v,
-                                                       double* __restrict__ part) {
-    double best = -1.0, at = -1.0;
-    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
-        if (tag[x] < 0) continue;
-        double s2 = 0.0;
-        for (int k = 0; k < g.dim; ++k) s2 += v[k * g.N + x] * v[k * g.N + x];
-        speed_pick(best, at, sqrt(s2), double(x));
-    }
-    speed_block(best, at);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = best;
-        part[2 * blockIdx.x + 1] = at;
-    }
 }
 
 __global__ __launch_bounds__(256) void k_speed_final(const double* __restrict__ part, int nparts, double* __restrict__ out) {
@@ -532,8 +555,10 @@ __global__ __launch_bounds__(256) void k_dm_final(double* __restrict__ part) {
 
 // rho, psi and the physical velocity of the state into the scratch arena: rho at scratch, psi
 // after it, v (dim planes) after that
+// part == nullptr: rho, psi and v into the scratch arena; otherwise the velocity kernel leaves
+// MON_BLOCKS (largest speed, node) pairs in part instead of v
 template <class S, class C>
-hipError_t moments_dev(mcb_ctx* c, const void* fcur) {
+hipError_t moments_dev(mcb_ctx* c, const void* fcur, double* part = nullptr) {
     const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
     double* sr = reinterpret_cast<double*>(c->lat + c->L.scratch);
     double* sp = sr + c->g.N;
@@ -544,17 +569,21 @@ hipError_t moments_dev(mcb_ctx* c, const void* fcur) {
     const auto rho_out = d2 ? k_rho_out<S, C, 9> : k_rho_out<S, C, 19>;
     hipLaunchKernelGGL(rho_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, rr, sr);
     if (c->p.model == MCB_MODEL_CHEMPOT) {
-        hipLaunchKernelGGL((k_vel_cp<S, C>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag,
-                           sr, reinterpret_cast<const C*>(c->lat + c->L.cp_rho), reinterpret_cast<const C*>(c->lat + c->L.cp_mu),
-                           c->p.gravity[0], c->p.gravity[1], sv);
+        const auto vel_cp = part ? k_vel_cp<S, C, true> : k_vel_cp<S, C, false>;
+        hipLaunchKernelGGL(vel_cp, dim3(part ? MON_BLOCKS : grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
+                           static_cast<const S*>(fcur), tag, sr, reinterpret_cast<const C*>(c->lat + c->L.cp_rho),
+                           reinterpret_cast<const C*>(c->lat + c->L.cp_mu), c->p.gravity[0], c->p.gravity[1],
+                           part ? part : sv);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(d2 ? k_psi_out<9> : k_psi_out<19>, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, tag, sr,
                        reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos,
                        reinterpret_cast<int32_t*>(c->lat + c->L.flags), sp);
-    const auto vel_out = d2 ? k_vel_out<S, C, 9> : k_vel_out<S, C, 19>;
-    hipLaunchKernelGGL(vel_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, sr, sp,
-                       c->p.G, c->p.gravity[0], c->p.gravity[1], c->p.gravity[2], sv);
+    const auto vel_out = d2 ? (part ? k_vel_out<S, C, 9, true> : k_vel_out<S, C, 9, false>)
+                            : (part ? k_vel_out<S, C, 19, true> : k_vel_out<S, C, 19, false>);
+    hipLaunchKernelGGL(vel_out, dim3(part ? MON_BLOCKS : grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
+                       static_cast<const S*>(fcur), tag, sr, sp, c->p.G, c->p.gravity[0], c->p.gravity[1], c->p.gravity[2],
+                       part ? part : sv);
     return hipGetLastError();
 }
 
@@ -580,11 +609,9 @@ hipError_t max_speed_t(mcb_ctx* c, const void* fcur) {
                            reinterpret_cast<double*>(c->lat + c->L.result) + MON_SPEED);
         return hipGetLastError();
     }
-    hipError_t e = moments_dev<S, C>(c, fcur);
+    // the moment kernels with the velocity kernel reducing the speed instead of storing v
+    hipError_t e = moments_dev<S, C>(c, fcur, part);
     if (e != hipSuccess) return e;
-    const double* sv = reinterpret_cast<const double*>(c->lat + c->L.scratch) + 2 * c->g.N;
-    hipLaunchKernelGGL(k_speed_partial, dim3(MON_BLOCKS), dim3(256), 0, c->stream, c->g,
-                       reinterpret_cast<const int32_t*>(c->lat + c->L.tag), sv, part);
     hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(256), 0, c->stream, part, MON_BLOCKS,
                        reinterpret_cast<double*>(c->lat + c->L.result) + MON_SPEED);
     return hipGetLastError();
