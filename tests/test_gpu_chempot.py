@@ -233,6 +233,29 @@ def test_chempot_c1_fp32(mcb, prec, tol):
     lat.close()
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,tol", [("f32s", 2e-5), ("f16s", 3e-3)])
+def test_chempot_wide_strip_storage(mcb, prec, tol):
+    """The four-wave strips (above 2^21 nodes) with shifted FP32 and FP16 storage (FP16 keeps
+    population 0 in FP32): 1536x1400 random circles, MRT, three steps against the FP64 oracle."""
+    banner(f"chemical-potential wide-strip parity, {prec}")
+    rng = np.random.default_rng(73)
+    dims = (1536, 1400, 1)
+    shapes = W.random_links_case(rng, dims, 2, dims[0] * dims[1] // 900, 2.0, 6.0)
+    drops = [((rng.uniform(0, dims[0]), rng.uniform(0, dims[1])), rng.uniform(8, 20)) for _ in range(40)]
+    rho = W.drop_field(dims, 2, drops, RV, RL, 6.0)
+    sim, lat, fluid = build_pair(mcb, dims, 1.0, shapes, MU_COEX, precision=prec, rho_ref=RV, collision="mrt")
+    sim.init_eq(rho)
+    lat.init_equilibrium(rho)
+    for k in range(1, 4):
+        sim.step(1)
+        lat.step(1)
+        e = rel_err(lat.get_f(), sim.get_f(), fluid)
+        assert e < tol * (k + 1), (k, e)
+    lat.close()
+    sim.close()
+
+
 def test_chempot_unsupported(mcb):
     banner("chemical-potential model in 3-D: MCB_ENOTSUP")
     with pytest.raises(mcb.MCBError) as ei:
