@@ -1053,7 +1053,9 @@ __global__ __launch_bounds__(W) void k_cp_march(ArgsCP<S, C> p) {
         {
             tgR = k + 1 >= 12 ? s_tag[(k + 3) % CP_MRING][pp] : -1;
             pull(wrapm(r - 5, ny), fR);
-            if (PULL) {
+            // only waves that hold a boundary node in that row load them (16-byte loads cost
+            // address cycles even at OOB); elsewhere the registers keep values nothing reads
+            if (PULL && __any(tgR > 0)) {
                 const bool bnd = tgR > 0;
                 const uint32_t bo = uint32_t(tgR >> 8);
                 ld_vec(rin, bnd ? bo * (REC2 * sc) : OOB, recR);
