@@ -147,8 +147,9 @@ def summarize(args):
     main = out["kernels"].get("k_step2d") or out["kernels"].get("k_step3d") or out["kernels"].get("k_cp_march")
     out["bytes_per_launch"] = main["bytes_per_launch"] if main else None
     out["bytes_per_step"] = step
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    base = os.path.join(ROOT, "profiles", out_name(args.workload, args.precision, args.model, args.collision))
+    out_dir = args.out_dir or os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+    base = os.path.join(out_dir, out_name(args.workload, args.precision, args.model, args.collision))
     json.dump(out, open(base + ".json", "w"), indent=1)
     with open(base + ".txt", "w") as fh:
         fh.write(f"HBM traffic of the step kernels, workload {args.workload}, storage {args.precision}, "
@@ -174,6 +175,7 @@ def main():
     s.add_argument("--workload", default="c2")
     s.add_argument("--precision", default="f32s")
     s.add_argument("--commands", default="")
+    s.add_argument("--out-dir", default="", help="where the summary goes (default: profiles/)")
     for q in (r, s):
         q.add_argument("--model", default="pseudo", choices=("pseudo", "chempot"))
         q.add_argument("--collision", default="bgk", choices=("bgk", "mrt"))
