@@ -808,10 +808,15 @@ __global__ __launch_bounds__(256) void k_cp_mu_solid(int nx, int ny, const int8_
 // the paths join, for every operation issued since, the prefetches of the next rows included.
 // For the same reason the loop body ends with phase 1 of the next row, and the first row's
 // phase 1 runs before the loop with every load it made waited for.
-constexpr int CP_RING = 16, CP_MRING = 8;
+// Ring depths (rows): the densities of rows r - 8 .. r + 1 are in use at once (phase 5 reads
+// r - 8 while a wave ahead writes r + 1 in the next row's phase 1), the tags of r - 5 and r + 1,
+// the chemical potentials of r - 8 .. r - 4 (phase 4 writes the next one after every read of the
+// oldest).  25.5 KB of LDS per 256-lane workgroup in FP32, so the VGPRs decide the occupancy.
+constexpr int CP_RING = 10, CP_TRING = 8, CP_MRING = 5;
 
+// FP32 arithmetic with MRT fits 96 VGPRs without spilling: five waves per SIMD (BGK would spill)
 template <class S, class C, int W, int OUT, bool PULL, bool MRT>
-__global__ __launch_bounds__(W) void k_cp_march(ArgsCP<S, C> p) {
+__global__ __launch_bounds__(W, (sizeof(C) == 4 && MRT) ? 5 : 2) void k_cp_march(ArgsCP<S, C> p) {
     constexpr int HC = (W - OUT) / 2;
     static_assert(HC >= 6, "six halo columns on either side");
     constexpr uint32_t s = sizeof(S), sc = sizeof(C), P0 = kMixed<S> ? 1 : 0;
@@ -828,7 +833,7 @@ __global__ __launch_bounds__(W) void k_cp_march(ArgsCP<S, C> p) {
     const bool out_col = t < Wv;
     __shared__ C s_rho[CP_RING][W];
     __shared__ int8_t s_lay[CP_RING][W];
-    __shared__ int s_tag[CP_MRING][W];
+    __shared__ int s_tag[CP_TRING][W];
     __shared__ C s_mu[CP_MRING][W];
     const __amdgpu_buffer_rsrc_t rfa = make_res(a.fa, uint64_t(9 + P0) * ns);
     const __amdgpu_buffer_rsrc_t rfb = make_res(a.fb, uint64_t(9 + P0) * ns);
@@ -899,7 +904,7 @@ __global__ __launch_bounds__(W) void k_cp_march(ArgsCP<S, C> p) {
         }
         s_rho[j % CP_RING][pp] = tgD >= 0 ? C(rs) + a.rho_ref : C(0);
         s_lay[j % CP_RING][pp] = lyD;
-        s_tag[j % CP_MRING][pp] = tgD;
+        s_tag[j % CP_TRING][pp] = tgD;
     };
     {
         const int rf = wrapm(y0 - 6, ny);
@@ -1051,7 +1056,7 @@ __global__ __launch_bounds__(W) void k_cp_march(ArgsCP<S, C> p) {
         // density row five iterations ago; before the first collision row the slot may hold what
         // nothing wrote, so the tag is taken as solid there), its pull, record and coefficients
         {
-            tgR = k + 1 >= 12 ? s_tag[(k + 3) % CP_MRING][pp] : -1;
+            tgR = k + 1 >= 12 ? s_tag[(k + 3) % CP_TRING][pp] : -1;
             pull(wrapm(r - 5, ny), fR);
             // only waves that hold a boundary node in that row load them (16-byte loads cost
             // address cycles even at OOB); elsewhere the registers keep values nothing reads
