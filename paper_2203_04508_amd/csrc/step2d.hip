@@ -814,9 +814,10 @@ __global__ __launch_bounds__(256) void k_cp_mu_solid(int nx, int ny, const int8_
 // oldest).  25.5 KB of LDS per 256-lane workgroup in FP32, so the VGPRs decide the occupancy.
 constexpr int CP_RING = 10, CP_TRING = 8, CP_MRING = 5;
 
-// FP32 arithmetic with MRT fits 96 VGPRs without spilling: five waves per SIMD (BGK would spill)
+// Waves per SIMD: FP32 arithmetic with MRT fits 96 VGPRs without spilling, five waves (BGK would
+// spill); FP64 fits 168 with a 20-28 byte spill, three waves instead of two (measured faster)
 template <class S, class C, int W, int OUT, bool PULL, bool MRT>
-__global__ __launch_bounds__(W, (sizeof(C) == 4 && MRT) ? 5 : 2) void k_cp_march(ArgsCP<S, C> p) {
+__global__ __launch_bounds__(W, (sizeof(C) == 4 && MRT) ? 5 : (sizeof(C) == 8 ? 3 : 2)) void k_cp_march(ArgsCP<S, C> p) {
     constexpr int HC = (W - OUT) / 2;
     static_assert(HC >= 6, "six halo columns on either side");
     constexpr uint32_t s = sizeof(S), sc = sizeof(C), P0 = kMixed<S> ? 1 : 0;
