@@ -273,10 +273,11 @@ __global__ __launch_bounds__(256) void k_vel_out(GridDev g, const S* __restrict_
 
 // chemical-potential model: v = (j - F / 2) / rho with F = -rho grad mu + grad(rho) / 3 + rho g from
 // the density and chemical-potential fields of the last collision (fourth-order differences);
-// SPEED as for k_vel_out
+// SPEED as for k_vel_out.  rho is the density k_rho_out wrote; SPEED forms it itself from the node's
+// populations, as k_rho_out does, so the density pass is not needed for the largest speed
 template <class S, class C, bool SPEED>
 __global__ __launch_bounds__(256) void k_vel_cp(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
-                                                const double* __restrict__ rho, const C* __restrict__ fr,
+                                                const double* __restrict__ rho, double rho_ref, const C* __restrict__ fr,
                                                 const C* __restrict__ fm, double gx, double gy, double* __restrict__ v) {
     double vbest = -1.0, vat = -1.0;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
@@ -287,12 +288,15 @@ __global__ __launch_bounds__(256) void k_vel_cp(GridDev g, const S* __restrict__
             }
             continue;
         }
+        double fv[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fv[i] = (SPEED || i > 0) ? double(ldp<S, C>(f, i, g.N, x)) : 0.0;
         double jx = 0, jy = 0;
         for (int i = 1; i < 9; ++i) {
-            const double fi = double(ldp<S, C>(f, i, g.N, x));
-            jx += fi * c_ex[0][i];
-            jy += fi * c_ey[0][i];
+            jx += fv[i] * c_ex[0][i];
+            jy += fv[i] * c_ey[0][i];
         }
+        const double rx = SPEED ? node_rho<9>(fv, rho_ref) : rho[x];
         const int cx = int(x % g.nx), cy = int(x / g.nx);
         auto at = [&](const C* a, int dx, int dy) {
             return double(a[int64_t(wrap1(cy + dy, g.ny)) * g.nx + wrap1(cx + dx, g.nx)]);
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(256) void k_vel_cp(GridDev g, const S* __restrict__
                           d1(at(fr, -2, 0), at(fr, -1, 0), at(fr, 1, 0), at(fr, 2, 0)) / 3.0 + r * gx;
         const double Fy = -r * d1(at(fm, 0, -2), at(fm, 0, -1), at(fm, 0, 1), at(fm, 0, 2)) +
                           d1(at(fr, 0, -2), at(fr, 0, -1), at(fr, 0, 1), at(fr, 0, 2)) / 3.0 + r * gy;
-        const double vx = (jx - 0.5 * Fx) / rho[x], vy = (jy - 0.5 * Fy) / rho[x];
+        const double vx = (jx - 0.5 * Fx) / rx, vy = (jy - 0.5 * Fy) / rx;
         if (SPEED) {
             double s2 = 0.0;
             s2 += vx * vx;
@@ -566,12 +570,14 @@ hipError_t moments_dev(mcb_ctx* c, const void* fcur, double* part = nullptr) {
     const int32_t* tag = reinterpret_cast<const int32_t*>(c->lat + c->L.tag);
     Eos<double> eos{c->p.eos_R * c->p.eos_T, c->p.eos_a, c->p.eos_b / 4.0, 2.0 / c->p.G};
     const bool d2 = c->g.dim == 2;
+    const bool cp = c->p.model == MCB_MODEL_CHEMPOT;
     const auto rho_out = d2 ? k_rho_out<S, C, 9> : k_rho_out<S, C, 19>;
-    hipLaunchKernelGGL(rho_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, rr, sr);
-    if (c->p.model == MCB_MODEL_CHEMPOT) {
+    if (!(cp && part))  // the chemical-potential speed forms each node's density itself
+        hipLaunchKernelGGL(rho_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, rr, sr);
+    if (cp) {
         const auto vel_cp = part ? k_vel_cp<S, C, true> : k_vel_cp<S, C, false>;
         hipLaunchKernelGGL(vel_cp, dim3(part ? MON_BLOCKS : grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
-                           static_cast<const S*>(fcur), tag, sr, reinterpret_cast<const C*>(c->lat + c->L.cp_rho),
+                           static_cast<const S*>(fcur), tag, sr, rr, reinterpret_cast<const C*>(c->lat + c->L.cp_rho),
                            reinterpret_cast<const C*>(c->lat + c->L.cp_mu), c->p.gravity[0], c->p.gravity[1],
                            part ? part : sv);
         return hipGetLastError();
