@@ -182,16 +182,33 @@ __global__ __launch_bounds__(256) void k_rho_out(GridDev g, const S* __restrict_
     }
 }
 
-template <int Q>
-__global__ __launch_bounds__(256) void k_psi_out(GridDev g, const int32_t* __restrict__ tag, const double* __restrict__ rho,
-                                                 const double* __restrict__ phi, Eos<double> eos, int32_t* flags,
-                                                 double* __restrict__ psi) {
-    constexpr int L = Q == 9 ? 0 : 1;
+// rho and psi in one pass: psi(rho) on fluid nodes, zero on solid ones (wall nodes too, until
+// k_psi_wall gives them eq. 15's psi once every density is written)
+template <class S, class C, int Q>
+__global__ __launch_bounds__(256) void k_rho_psi_out(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
+                                                     double rho_ref, Eos<double> eos, int32_t* flags,
+                                                     double* __restrict__ rho, double* __restrict__ psi) {
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
-        const int tg = tag[x];
-        if (tg >= 0) { psi[x] = psi_of(rho[x], eos, flags); continue; }
-        if (tg == -1) { psi[x] = 0.0; continue; }
-        // wall node: every neighbour's tag and density at once, the solid ones dropped by selection
+        const bool fl = tag[x] >= 0;
+        double v[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = double(ldp<S, C>(f, i, g.N, x));
+        const double r = fl ? node_rho<Q>(v, rho_ref) : 0.0;
+        rho[x] = r;
+        psi[x] = fl ? psi_of(r, eos, flags) : 0.0;
+    }
+}
+
+// psi of the wall nodes (solid nodes with a fluid neighbour, listed in wl_node): eq. 15's density
+// from the neighbours' tags and densities, the solid ones dropped by selection
+template <int Q>
+__global__ __launch_bounds__(256) void k_psi_wall(GridDev g, int64_t nw, const int32_t* __restrict__ wl_node,
+                                                  const int32_t* __restrict__ tag, const double* __restrict__ rho,
+                                                  const double* __restrict__ phi, Eos<double> eos, int32_t* flags,
+                                                  double* __restrict__ psi) {
+    constexpr int L = Q == 9 ? 0 : 1;
+    for (int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; w < nw; w += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t x = wl_node[w];
         int ty[Q];
         double ry[Q];
 #pragma unroll
@@ -200,7 +217,7 @@ __global__ __launch_bounds__(256) void k_psi_out(GridDev g, const int32_t* __res
             ty[i] = tag[y];
             ry[i] = rho[y];
         }
-        psi[x] = psi_of(wall_rho<Q>(ty, ry, phi[-tg - 2]), eos, flags);
+        psi[x] = psi_of(wall_rho<Q>(ty, ry, phi[w]), eos, flags);
     }
 }
 
@@ -571,10 +588,10 @@ hipError_t moments_dev(mcb_ctx* c, const void* fcur, double* part = nullptr) {
     Eos<double> eos{c->p.eos_R * c->p.eos_T, c->p.eos_a, c->p.eos_b / 4.0, 2.0 / c->p.G};
     const bool d2 = c->g.dim == 2;
     const bool cp = c->p.model == MCB_MODEL_CHEMPOT;
-    const auto rho_out = d2 ? k_rho_out<S, C, 9> : k_rho_out<S, C, 19>;
-    if (!(cp && part))  // the chemical-potential speed forms each node's density itself
-        hipLaunchKernelGGL(rho_out, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, static_cast<const S*>(fcur), tag, rr, sr);
     if (cp) {
+        if (!part)  // the chemical-potential speed forms each node's density itself
+            hipLaunchKernelGGL((k_rho_out<S, C, 9>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
+                               static_cast<const S*>(fcur), tag, rr, sr);
         const auto vel_cp = part ? k_vel_cp<S, C, true> : k_vel_cp<S, C, false>;
         hipLaunchKernelGGL(vel_cp, dim3(part ? MON_BLOCKS : grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
                            static_cast<const S*>(fcur), tag, sr, rr, reinterpret_cast<const C*>(c->lat + c->L.cp_rho),
@@ -582,9 +599,13 @@ hipError_t moments_dev(mcb_ctx* c, const void* fcur, double* part = nullptr) {
                            part ? part : sv);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(d2 ? k_psi_out<9> : k_psi_out<19>, dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g, tag, sr,
-                       reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos,
-                       reinterpret_cast<int32_t*>(c->lat + c->L.flags), sp);
+    int32_t* flags = reinterpret_cast<int32_t*>(c->lat + c->L.flags);
+    hipLaunchKernelGGL((d2 ? k_rho_psi_out<S, C, 9> : k_rho_psi_out<S, C, 19>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream,
+                       c->g, static_cast<const S*>(fcur), tag, rr, eos, flags, sr, sp);
+    if (c->n_wall > 0)
+        hipLaunchKernelGGL(d2 ? k_psi_wall<9> : k_psi_wall<19>, dim3(grid_for(c->n_wall)), dim3(256), 0, c->stream, c->g,
+                           c->n_wall, reinterpret_cast<const int32_t*>(c->lk + c->L.wl_node), tag, sr,
+                           reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos, flags, sp);
     const auto vel_out = d2 ? (part ? k_vel_out<S, C, 9, true> : k_vel_out<S, C, 9, false>)
                             : (part ? k_vel_out<S, C, 19, true> : k_vel_out<S, C, 19, false>);
     hipLaunchKernelGGL(vel_out, dim3(part ? MON_BLOCKS : grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
