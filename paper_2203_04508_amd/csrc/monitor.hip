@@ -221,6 +221,22 @@ __global__ __launch_bounds__(256) void k_psi_wall(GridDev g, int64_t nw, const i
     }
 }
 
+// the nodes of a lane in a grid-stride loop.  Workgroups are dealt to the eight XCDs in turn; with
+// slabs (a grid of a multiple of 8) each XCD sweeps a contiguous eighth of the lattice instead of
+// every eighth row-piece of it, so the rows of neighbours that nodes share are fetched into one L2
+// rather than into several
+struct Sweep {
+    int64_t x0, xe, xs;
+};
+
+__device__ inline Sweep sweep(int64_t N, bool slabs) {
+    if (!slabs || gridDim.x % 8 != 0)
+        return {blockIdx.x * int64_t(blockDim.x) + threadIdx.x, N, int64_t(gridDim.x) * blockDim.x};
+    const int64_t slab = (N + 7) / 8, k = blockIdx.x % 8;
+    return {k * slab + (blockIdx.x / 8) * int64_t(blockDim.x) + threadIdx.x, min(N, (k + 1) * slab),
+            int64_t(gridDim.x / 8) * blockDim.x};
+}
+
 // largest |v| over the fluid nodes and the smallest node index attaining it; fixed grid and fixed
 // combination order, so the result does not depend on timing
 __device__ inline void speed_pick(double& best, double& at, double b, double i) {
@@ -254,7 +270,8 @@ __global__ __launch_bounds__(256) void k_vel_out(GridDev g, const S* __restrict_
                                                  double gx, double gy, double gz, double* __restrict__ v) {
     constexpr int L = Q == 9 ? 0 : 1;
     double best = -1.0, at = -1.0;
-    for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
+    const Sweep sw = sweep(g.N, SPEED);
+    for (int64_t x = sw.x0; x < sw.xe; x += sw.xs) {
         if (tag[x] < 0) {
             if (!SPEED)
                 for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = 0.0;
@@ -574,10 +591,15 @@ __global__ __launch_bounds__(256) void k_dm_final(double* __restrict__ part) {
     if (threadIdx.x == 0) part[DM_BLOCKS] += ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// workgroups of the velocity kernels in speed mode (a multiple of the eight XCDs): one (speed,
+// node) pair each in the partials
+constexpr int SPEED_BLOCKS = 2048;
+static_assert(SPEED_BLOCKS % 8 == 0 && SPEED_BLOCKS <= MON_BLOCKS * MON_FIELDS / 2, "speed partials");
+
 // rho, psi and the physical velocity of the state into the scratch arena: rho at scratch, psi
 // after it, v (dim planes) after that
 // part == nullptr: rho, psi and v into the scratch arena; otherwise the velocity kernel leaves
-// MON_BLOCKS (largest speed, node) pairs in part instead of v
+// SPEED_BLOCKS (largest speed, node) pairs in part instead of v
 template <class S, class C>
 hipError_t moments_dev(mcb_ctx* c, const void* fcur, double* part = nullptr) {
     const double rr = c->p.precision == MCB_F64 ? 0.0 : c->p.rho_ref;
@@ -593,7 +615,7 @@ hipError_t moments_dev(mcb_ctx* c, const void* fcur, double* part = nullptr) {
             hipLaunchKernelGGL((k_rho_out<S, C, 9>), dim3(grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
                                static_cast<const S*>(fcur), tag, rr, sr);
         const auto vel_cp = part ? k_vel_cp<S, C, true> : k_vel_cp<S, C, false>;
-        hipLaunchKernelGGL(vel_cp, dim3(part ? MON_BLOCKS : grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
+        hipLaunchKernelGGL(vel_cp, dim3(part ? SPEED_BLOCKS : grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
                            static_cast<const S*>(fcur), tag, sr, rr, reinterpret_cast<const C*>(c->lat + c->L.cp_rho),
                            reinterpret_cast<const C*>(c->lat + c->L.cp_mu), c->p.gravity[0], c->p.gravity[1],
                            part ? part : sv);
@@ -608,7 +630,7 @@ hipError_t moments_dev(mcb_ctx* c, const void* fcur, double* part = nullptr) {
                            reinterpret_cast<const double*>(c->lk + c->L.wl_phi), eos, flags, sp);
     const auto vel_out = d2 ? (part ? k_vel_out<S, C, 9, true> : k_vel_out<S, C, 9, false>)
                             : (part ? k_vel_out<S, C, 19, true> : k_vel_out<S, C, 19, false>);
-    hipLaunchKernelGGL(vel_out, dim3(part ? MON_BLOCKS : grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
+    hipLaunchKernelGGL(vel_out, dim3(part ? SPEED_BLOCKS : grid_for(c->g.N)), dim3(256), 0, c->stream, c->g,
                        static_cast<const S*>(fcur), tag, sr, sp, c->p.G, c->p.gravity[0], c->p.gravity[1], c->p.gravity[2],
                        part ? part : sv);
     return hipGetLastError();
@@ -639,7 +661,7 @@ hipError_t max_speed_t(mcb_ctx* c, const void* fcur) {
     // the moment kernels with the velocity kernel reducing the speed instead of storing v
     hipError_t e = moments_dev<S, C>(c, fcur, part);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(256), 0, c->stream, part, MON_BLOCKS,
+    hipLaunchKernelGGL(k_speed_final, dim3(1), dim3(256), 0, c->stream, part, SPEED_BLOCKS,
                        reinterpret_cast<double*>(c->lat + c->L.result) + MON_SPEED);
     return hipGetLastError();
 }

@@ -156,3 +156,39 @@ def test_max_speed_c1_fp32(mcb):
     s[~fluid] = -1.0
     assert vg == s.max() and ng == int(np.argmax(s))
     lat.close()
+
+
+SWEEP_CASES = [("97x81x73-f64", (97, 81, 73), "f64", 30), ("c4-f32s", None, "f32s", 20)]
+
+
+@pytest.mark.parametrize("name,dims,prec,steps", SWEEP_CASES, ids=[c[0] for c in SWEEP_CASES])
+def test_max_speed_3d_equals_velocity_output(mcb, name, dims, prec, steps):
+    """Lattices on which every speed-mode workgroup sweeps several nodes, N not a multiple of 8
+    (97 x 81 x 73) and the 256^3 workload: the reduction returns exactly the largest speed of the
+    GPU's own velocity field and the smallest node attaining it."""
+    banner(f"largest speed vs velocity output {name}, {steps} steps")
+    if dims is None:
+        wl = W.make("c4")
+        lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=prec, rho_ref=wl.rho_v)
+        lat.set_geometry(wl.shapes)
+        lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
+        lat.init_equilibrium(wl.rho0())
+    else:
+        rng = np.random.default_rng(97)
+        shapes = W.random_links_case(rng, dims, 3, 12, 2.5, 6.0)
+        rv, rl = W.MAXWELL[0.7]
+        drops = [(tuple(rng.uniform(0, n) for n in dims), rng.uniform(5, 9)) for _ in range(4)]
+        lat = mcb.Lattice(3, dims, 0.8, 0.7 * TC, precision=prec, gravity=(1e-5, -2e-5, 3e-5))
+        lat.set_geometry(shapes)
+        lat.set_wettability(rng.uniform(0.85, 1.15, len(lat.wall_nodes())))
+        lat.init_equilibrium(W.drop_field(dims, 3, drops, rv, rl, 4.0))
+    lat.step(steps)
+    vg, ng = lat.max_speed()
+    rho, v = lat.moments()
+    s = np.sqrt((v ** 2).sum(0))
+    s[rho == 0.0] = -1.0  # solid nodes (the moment output holds zero density there)
+    assert np.isfinite(vg) and vg > 0.0
+    assert vg == s.max() and ng == int(np.argmax(s)), (vg, s.max(), ng, int(np.argmax(s)))
+    # a second call on the same state gives the same pair
+    assert lat.max_speed() == (vg, ng)
+    lat.close()
