@@ -12,12 +12,18 @@ __device__ inline C wgt(int L, int i) {
     return i == 0 ? C(1.0 / 3.0) : (i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0));
 }
 
-// periodic neighbour x + sign e_i (32-bit position arithmetic: N < 2^31)
-__device__ inline int64_t nb_index(const GridDev& g, int L, int64_t x, int i, int sign) {
-    const uint32_t u = uint32_t(x), nx = uint32_t(g.nx), nxy = nx * uint32_t(g.ny);
+// the periodic neighbours x + e_i of node u in every direction, from per-axis offsets formed once
+// (32-bit position arithmetic: N < 2^31; the direction tables fold to constants once unrolled)
+template <int Q>
+__device__ inline void nb_all(const GridDev& g, uint32_t u, uint32_t (&y)[Q]) {
+    constexpr int L = Q == 9 ? 0 : 1;
+    const uint32_t nx = uint32_t(g.nx), ny = uint32_t(g.ny), nz = uint32_t(g.nz), nxy = nx * ny;
     const uint32_t cz = u / nxy, r = u - cz * nxy, cy = r / nx, cx = r - cy * nx;
-    return int64_t(wrap1(int(cx) + sign * c_ex[L][i], g.nx)) +
-           int64_t(g.nx) * (wrap1(int(cy) + sign * c_ey[L][i], g.ny) + int64_t(g.ny) * wrap1(int(cz) + sign * c_ez[L][i], g.nz));
+    const uint32_t xo[3] = {cx == 0 ? nx - 1 : cx - 1, cx, cx + 1 == nx ? 0 : cx + 1};
+    const uint32_t yo[3] = {(cy == 0 ? ny - 1 : cy - 1) * nx, cy * nx, (cy + 1 == ny ? 0 : cy + 1) * nx};
+    const uint32_t zo[3] = {(cz == 0 ? nz - 1 : cz - 1) * nxy, cz * nxy, (cz + 1 == nz ? 0 : cz + 1) * nxy};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) y[i] = xo[c_ex[L][i] + 1] + yo[c_ey[L][i] + 1] + zo[c_ez[L][i] + 1];
 }
 
 // f(x, 0) = f^eq(rho, u) - w_i rho_ref on fluid nodes (eq. 14), zero elsewhere
@@ -206,16 +212,16 @@ __global__ __launch_bounds__(256) void k_psi_wall(GridDev g, int64_t nw, const i
                                                   const int32_t* __restrict__ tag, const double* __restrict__ rho,
                                                   const double* __restrict__ phi, Eos<double> eos, int32_t* flags,
                                                   double* __restrict__ psi) {
-    constexpr int L = Q == 9 ? 0 : 1;
     for (int64_t w = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; w < nw; w += int64_t(gridDim.x) * blockDim.x) {
         const int64_t x = wl_node[w];
+        uint32_t nb[Q];
+        nb_all<Q>(g, uint32_t(x), nb);
         int ty[Q];
         double ry[Q];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const int64_t y = nb_index(g, L, x, i, +1);
-            ty[i] = tag[y];
-            ry[i] = rho[y];
+            ty[i] = tag[nb[i]];
+            ry[i] = rho[nb[i]];
         }
         psi[x] = psi_of(wall_rho<Q>(ty, ry, phi[w]), eos, flags);
     }
@@ -268,21 +274,20 @@ template <class S, class C, int Q, bool SPEED>
 __global__ __launch_bounds__(256) void k_vel_out(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
                                                  const double* __restrict__ rho, const double* __restrict__ psi, double G,
                                                  double gx, double gy, double gz, double* __restrict__ v) {
-    constexpr int L = Q == 9 ? 0 : 1;
     double best = -1.0, at = -1.0;
     const Sweep sw = sweep(g.N, SPEED);
     for (int64_t x = sw.x0; x < sw.xe; x += sw.xs) {
-        if (tag[x] < 0) {
-            if (!SPEED)
-                for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = 0.0;
-            continue;
-        }
+        // every load of the node at once, the tag among them (every address is in the lattice);
+        // solid nodes evaluate too and are dropped by selection, so one memory round trip per node
+        const bool fl = tag[x] >= 0;
+        uint32_t nb[Q];
+        nb_all<Q>(g, uint32_t(x), nb);
         double fv[Q], pv[Q];
         fv[0] = pv[0] = 0.0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             fv[i] = double(ldp<S, C>(f, i, g.N, x));
-            pv[i] = psi[nb_index(g, L, x, i, +1)];
+            pv[i] = psi[nb[i]];
         }
         double j[3], vv[3];
         node_j<Q>(fv, j);
@@ -291,9 +296,9 @@ __global__ __launch_bounds__(256) void k_vel_out(GridDev g, const S* __restrict_
         if (SPEED) {
             double s2 = 0.0;
             for (int k = 0; k < g.dim; ++k) s2 += vv[k] * vv[k];
-            speed_pick(best, at, sqrt(s2), double(x));
+            speed_pick(best, at, fl ? sqrt(s2) : -1.0, fl ? double(x) : -1.0);
         } else {
-            for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = vv[k];
+            for (int k = 0; k < g.dim; ++k) v[k * g.N + x] = fl ? vv[k] : 0.0;
         }
     }
     if (SPEED) {
@@ -315,13 +320,7 @@ __global__ __launch_bounds__(256) void k_vel_cp(GridDev g, const S* __restrict__
                                                 const C* __restrict__ fm, double gx, double gy, double* __restrict__ v) {
     double vbest = -1.0, vat = -1.0;
     for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < g.N; x += int64_t(gridDim.x) * blockDim.x) {
-        if (tag[x] < 0) {
-            if (!SPEED) {
-                v[x] = 0.0;
-                v[g.N + x] = 0.0;
-            }
-            continue;
-        }
+        const bool fl = tag[x] >= 0;  // solid nodes evaluate too and are dropped by selection
         double fv[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) fv[i] = (SPEED || i > 0) ? double(ldp<S, C>(f, i, g.N, x)) : 0.0;
@@ -346,10 +345,10 @@ __global__ __launch_bounds__(256) void k_vel_cp(GridDev g, const S* __restrict__
             double s2 = 0.0;
             s2 += vx * vx;
             s2 += vy * vy;
-            speed_pick(vbest, vat, sqrt(s2), double(x));
+            speed_pick(vbest, vat, fl ? sqrt(s2) : -1.0, fl ? double(x) : -1.0);
         } else {
-            v[x] = vx;
-            v[g.N + x] = vy;
+            v[x] = fl ? vx : 0.0;
+            v[g.N + x] = fl ? vy : 0.0;
         }
     }
     if (SPEED) {
