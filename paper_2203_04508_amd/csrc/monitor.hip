@@ -176,6 +176,7 @@ __device__ __forceinline__ void node_v(const double (&j)[3], const double (&pv)[
 
 // ---- moments: rho, psi (fluid and wall nodes), then v = (j - F / 2) / rho.  Q is a template
 // parameter (unrolled direction loops); each lane loads all it needs before using any.
+// k_rho_out: the density alone (the chemical-potential model's velocity needs no psi)
 template <class S, class C, int Q>
 __global__ __launch_bounds__(256) void k_rho_out(GridDev g, const S* __restrict__ f, const int32_t* __restrict__ tag,
                                                  double rho_ref, double* __restrict__ rho) {
