@@ -25,10 +25,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2203_04508_amd.roofline import HBM_PEAK_GBS, STORAGE_BYTES, algorithmic_bytes, layout_bytes  # noqa: E402
+
 METRIC = "MLUPS & % HBM roofline per step; fwd+adjoint MLUPS; relative mass drift"
-HBM_PEAK_GBS = 8000.0
 DTYPES = {"f64": "f64", "f32s": "f32", "f16s": "f32"}
-STORAGE_BYTES = {"f64": 8, "f32s": 4, "f16s": 2}
 
 
 def log(msg):
@@ -55,28 +55,6 @@ def setup_gpu(wl, precision, rho_ref, bc_mode="present", collision="bgk", model=
     lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
     lat.init_equilibrium(wl.rho0())
     return lat, (nl, nb, nw)
-
-
-def algorithmic_bytes(wl, precision, nl):
-    """Bytes the method must move per step (the roofline's numerator): each node's populations read
-    once and written once (2 Q s, s the bytes of a stored population) plus one byte of node tag,
-    and about 20 bytes per fluid-solid link (its index, direction and class, q, the incoming value
-    and the eq. 18 term)."""
-    s = STORAGE_BYTES[precision]
-    return wl.N * (2 * wl.Q * s + 1) + 20 * nl
-
-
-def implementation_bytes(wl, precision, nb):
-    """The bytes this implementation's data layout moves at least, once each: populations (FP16
-    storage keeps population 0 in FP32), the 4-byte node tag, and each boundary node's record read
-    and written once plus its link coefficients (halo re-reads and partial lines not counted)."""
-    from paper_2203_04508_amd import mcb
-
-    s = STORAGE_BYTES[precision]
-    cb = 8 if precision == "f64" else 4
-    rec, nlk = (mcb.REC2, mcb.Q2_LINKS) if wl.dim == 2 else (mcb.REC3, mcb.Q3_LINKS)
-    planes = wl.Q + 1 if precision == "f16s" else wl.Q  # FP16 storage keeps population 0 in FP32
-    return wl.N * (2 * planes * s + 4) + nb * (2 * rec + nlk) * cb
 
 
 def fwd_adjoint(precision):
@@ -246,7 +224,7 @@ def main():
     from paper_2203_04508_amd.traffic import kernel_digest
 
     alg = algorithmic_bytes(wl, args.precision, nl)
-    impl = implementation_bytes(wl, args.precision, nb)
+    impl = layout_bytes(wl, args.precision, nb)
     # one kernel launch per step; HIP events on the library's stream bracket each launch
     fused_ms = ms / max(1, launches)
     achieved = alg / (fused_ms * 1e-3) / 1e9

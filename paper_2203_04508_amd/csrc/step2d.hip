@@ -501,8 +501,11 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
     a.ny = c->p.ny;
     a.nsx = (a.nx + OUT - 1) / OUT;
     // segment height: long segments amortise the four halo rows; short ones fill the chip.  Wide
-    // strips: as many segments as the device holds at once (all workgroups resident together);
-    // one-wave strips (small lattices): enough workgroups to fill the chip several times over.
+    // strips: as many segments as the device holds in a number of resident rounds -- four with
+    // FP32 storage (the shorter segments' extra halo rows cost less than the march loses when every
+    // workgroup moves in step with the others), one with FP16 storage, whose arithmetic is the limit
+    // and grows with the halo rows, and with FP64; one-wave strips (small lattices): enough
+    // workgroups to fill the chip several times over.
     int H;
     if (W == 64) {
         H = 64;
@@ -514,7 +517,8 @@ hipError_t launch_w(mcb_ctx* c, const void* fcur, const void* rcur, void* fnext,
                                     : resident_blocks(c, k_step2d<S, C, W, OUT, true, false>, W, &occ[1]))
                              : (mrt ? resident_blocks(c, k_step2d<S, C, W, OUT, false, true>, W, &occ[2])
                                     : resident_blocks(c, k_step2d<S, C, W, OUT, false, false>, W, &occ[0]));
-        const int per = cap / a.nsx > 0 ? cap / a.nsx : 1;  // segments per strip
+        const int rounds = sizeof(S) == 4 ? 4 : 1;
+        const int per = rounds * cap / a.nsx > 0 ? rounds * cap / a.nsx : 1;  // segments per strip
         H = (a.ny + per - 1) / per;
         if (H < 16) H = 16;
     }

@@ -1,6 +1,6 @@
 """Precision study of the step on one workload: the same initial state run with FP64 storage (the
 GPU baseline) and with shifted FP32 and FP16 storage, reporting per storage format the step time,
-throughput and algorithmic HBM rate, the relative mass drift, and the density error against the
+throughput and HBM rate (of the method's bytes, and of the layout's), the relative mass drift, and the density error against the
 FP64 run, L2(rho - rho_FP64) / L2(rho_FP64) over the lattice (solid nodes hold 0 in both).
 
     python -m paper_2203_04508_amd.study --workload c2 --steps 5000 [--out profiles/precision_c2.json]
@@ -15,30 +15,16 @@ import time
 
 import numpy as np
 
+from paper_2203_04508_amd.roofline import HBM_PEAK_GBS, algorithmic_bytes, layout_bytes
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HBM_PEAK_GBS = 8000.0
-STORAGE_BYTES = {"f64": 8, "f32s": 4, "f16s": 2}
-
-
-def algorithmic_bytes(wl, precision, nb):
-    """Populations read and written once and the 4-byte tag per node; boundary records read and
-    written once and the link coefficients read per boundary node."""
-    from paper_2203_04508_amd import mcb
-
-    s = STORAGE_BYTES[precision]
-    cb = 8 if precision == "f64" else 4
-    rec, nlk = (mcb.REC2, mcb.Q2_LINKS) if wl.dim == 2 else (mcb.REC3, mcb.Q3_LINKS)
-    planes = wl.Q + 1 if precision == "f16s" else wl.Q  # FP16 storage keeps population 0 in FP32
-    return wl.N * (2 * planes * s + 4) + nb * (2 * rec + nlk) * cb
-
-
 def run_one(wl, precision, steps, rho0):
     import torch
     from paper_2203_04508_amd import mcb, workloads as W
 
     rr = wl.rho_v if precision != "f64" else 0.0
     lat = mcb.Lattice(wl.dim, wl.dims, wl.tau, wl.T, precision=precision, rho_ref=rr)
-    _, nb, _ = lat.set_geometry(wl.shapes)
+    nl, nb, _ = lat.set_geometry(wl.shapes)
     lat.set_wettability(W.phi_for_walls(wl, lat.wall_nodes()))
     lat.init_equilibrium(rho0)
     M0 = lat.mass().M
@@ -54,7 +40,8 @@ def run_one(wl, precision, steps, rho0):
     rho, _ = lat.moments()
     lat.close()
     step_ms = ms / max(1, launches)
-    alg = algorithmic_bytes(wl, precision, nb)
+    alg = algorithmic_bytes(wl, precision, nl)
+    lay = layout_bytes(wl, precision, nb)
     return {
         "precision": precision,
         "steps": steps,
@@ -63,6 +50,7 @@ def run_one(wl, precision, steps, rho0):
         "wall_mlups": wl.N * steps / el / 1e6,
         "algorithmic_gbs": alg / (step_ms * 1e-3) / 1e9,
         "hbm_frac": alg / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "layout_frac": lay / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "mass_drift": (rep.M - M0) / M0,
     }, rho
 
