@@ -220,8 +220,9 @@ def test_c1_full_size_one_step_parity(mcb):
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32s", 3e-6), ("f16s", 3e-3)])
 def test_wide_strip_path_parity(mcb, prec, tol):
-    """Lattices above 2^21 nodes take the cache-line-aligned wide strips (224 or 448 output
-    columns, ragged last strip); one oracle-checked run of three steps."""
+    """Lattices above 2^21 nodes take the cache-line-aligned wide strips (224 output columns, 192
+    with FP16 storage; ragged last strip) and, with FP32 storage, 16-row segments with a ragged last
+    one of 6 rows; one oracle-checked run of three steps."""
     banner(f"wide-strip path, 2100x1030, {prec}")
     dims = (2100, 1030, 1)
     rng = np.random.default_rng(77)
