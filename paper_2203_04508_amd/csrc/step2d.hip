@@ -829,7 +829,13 @@ __global__ __launch_bounds__(W, (sizeof(C) == 4 && MRT) ? 5 : (sizeof(C) == 8 ? 
     const int nx = a.nx, ny = a.ny;
     const uint32_t n = uint32_t(nx) * uint32_t(ny);  // the lattice fits the 32-bit buffer offsets
     const uint32_t ns = n * s, rows = uint32_t(nx) * s;
-    const int sx = int(blockIdx.x) % a.nsx, sy = int(blockIdx.x) / a.nsx;
+    // XCD-aware order, as in the pseudopotential step: each XCD takes a contiguous run of strips and
+    // segments, so the strip-edge lines that neighbouring workgroups both read stay in one L2
+    const int bid = blockIdx.x;
+    const int per = a.nblocks >> 3, rem = a.nblocks & 7;
+    const int xcd = bid & 7, k8 = bid >> 3;
+    const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k8;
+    const int sx = logical % a.nsx, sy = logical / a.nsx;
     const int x0 = sx * OUT, y0 = sy * a.H;
     const int Wv = min(OUT, nx - x0), Hv = min(a.H, ny - y0);
     const int t = threadIdx.x;
